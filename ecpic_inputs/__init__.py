@@ -1,0 +1,198 @@
+"""Seeded synthetic inputs for the r-z PIC/MCC workloads.
+
+This module holds configuration data and random initial conditions only: it
+contains none of the method's arithmetic (no mapping, field, push, deposit or
+collision code).  Both the CPU oracle and the HIP library consume what it
+produces: particle positions in physical (r, z) coordinates and velocities in
+m/s; each side converts positions to its own logical coordinates.
+
+The workloads stand in for the paper's Testbench-B discharge (Sec. 2.1: a
+cylindrical argon CCP, 3 cm gap, VHF drive, a few Pa), whose geometry files,
+cross-section data and measurements are not available.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+
+# CODATA 2018 (exact SI values where defined)
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+EPS0 = 8.8541878128e-12
+MU0 = 1.25663706212e-6
+KB = 1.380649e-23
+AMU = 1.66053906660e-27
+M_AR = 39.948 * AMU
+C_LIGHT = 299792458.0
+CHI01 = 2.404825557695773  # first zero of J0 (tabulated constant)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nr: int
+    nz: int
+    R: float
+    L: float
+    xi_a: float = 2.0
+    dt: float = 1e-11
+    drive_amp: tuple = ()
+    drive_freq: tuple = ()
+    drive_phase: tuple = ()
+    n0: float = 1e15
+    profile: str = "uniform"  # "uniform" or "j0sin"
+    ppc: int = 16  # macro-particles per cell per species
+    Te_eV: float = 3.0
+    Ti_eV: float = 0.026
+    steps: int = 10
+    tol: float = 1e-10
+    pressure_pa: float = 0.0  # 0 = no collisions
+    T_gas: float = 300.0
+    eps_max_ev: float = 1000.0
+    seed: int = 1
+
+    @property
+    def n_per_species(self) -> int:
+        return self.ppc * self.nr * self.nz
+
+    @property
+    def n_gas(self) -> float:
+        return self.pressure_pa / (KB * self.T_gas)
+
+    def grid_params(self) -> dict:
+        return dict(nr=self.nr, nz=self.nz, R=self.R, L=self.L, xi_a=self.xi_a,
+                    dt=self.dt, eps=EPS0, mu=MU0,
+                    drive_amp=tuple(self.drive_amp), drive_freq=tuple(self.drive_freq),
+                    drive_phase=tuple(self.drive_phase) if self.drive_phase
+                    else tuple(0.0 for _ in self.drive_amp))
+
+    def mcc_params(self) -> Optional[dict]:
+        if self.pressure_pa <= 0:
+            return None
+        return dict(n_gas=self.n_gas, T_gas=self.T_gas, m_gas=M_AR,
+                    eps_max_ev=self.eps_max_ev, seed=self.seed,
+                    electron_sid=0, ion_sid=1)
+
+
+WORKLOADS: Dict[str, Workload] = {
+    # 32x32 cylinder, two Maxwellian species, zero fields, no drive, no MCC
+    "c1": Workload("c1", 32, 32, 0.02, 0.02, n0=1e15, ppc=16, steps=10, tol=1e-10, seed=1),
+    # VHF CCP slab, 256x128, 100 MHz 200 V, J0*sin density, MCC
+    "c2": Workload("c2", 256, 128, 0.15, 0.03, n0=1e16, profile="j0sin", ppc=64,
+                   drive_amp=(200.0,), drive_freq=(100e6,), steps=2000, tol=1e-10,
+                   pressure_pa=5.0, seed=2),
+    # mixed-precision scale-up, 512x256, 128 ppc
+    "c3": Workload("c3", 512, 256, 0.25, 0.03, n0=1e16, profile="j0sin", ppc=128,
+                   drive_amp=(200.0,), drive_freq=(100e6,), steps=5, tol=1e-10,
+                   pressure_pa=5.0, seed=3),
+    # largest single-GPU case, 1024x512, dual frequency
+    "c5": Workload("c5", 1024, 512, 0.3, 0.03, n0=1e16, profile="j0sin", ppc=256,
+                   drive_amp=(200.0, 200.0), drive_freq=(60e6, 13.56e6), steps=1000,
+                   tol=1e-10, pressure_pa=5.0, seed=5),
+}
+
+
+def workload(name: str, **over) -> Workload:
+    w = dataclasses.replace(WORKLOADS[name])
+    for k, v in over.items():
+        setattr(w, k, v)
+    return w
+
+
+def _j0(x: np.ndarray) -> np.ndarray:
+    from scipy.special import j0
+    return j0(x)
+
+
+def _total_particles_phys(w: Workload) -> float:
+    """Physical number of electrons in the domain (integral of the density)."""
+    if w.profile == "uniform":
+        return w.n0 * math.pi * w.R ** 2 * w.L
+    from scipy.integrate import quad
+    from scipy.special import j0
+    k = 2.405 / w.R
+    ir, _ = quad(lambda r: max(j0(k * r), 0.0) * 2 * math.pi * r, 0.0, w.R, limit=200)
+    iz = 2.0 * w.L / math.pi
+    return w.n0 * ir * iz
+
+
+def _positions(w: Workload, n: int, rng: np.random.Generator):
+    """n positions, uniform in volume (r = R sqrt(U)), shaped by the profile."""
+    if w.profile == "uniform":
+        r = w.R * np.sqrt(rng.random(n))
+        z = w.L * rng.random(n)
+        return r, z
+    k = 2.405 / w.R
+    rs: List[np.ndarray] = []
+    zs: List[np.ndarray] = []
+    got = 0
+    while got < n:
+        m = int((n - got) * 2.2) + 1024
+        r = w.R * np.sqrt(rng.random(m))
+        z = w.L * rng.random(m)
+        dens = np.clip(_j0(k * r), 0.0, None) * np.sin(math.pi * z / w.L)
+        keep = rng.random(m) < dens
+        rs.append(r[keep])
+        zs.append(z[keep])
+        got += int(keep.sum())
+    return np.concatenate(rs)[:n], np.concatenate(zs)[:n]
+
+
+def _interior(x: np.ndarray, hi: float) -> np.ndarray:
+    """Keep loaded positions strictly inside (0, hi): a draw of exactly 0 is
+    moved to the smallest positive double."""
+    return np.clip(x, np.nextafter(0.0, 1.0), np.nextafter(hi, 0.0))
+
+
+def make_particles(w: Workload, seed: Optional[int] = None, n: Optional[int] = None):
+    """Electrons and Ar+ ions, pair-loaded (each ion at its electron's
+    position, so the initial node charge is zero), Maxwellian velocities.
+
+    Returns a list of two dicts (electrons, ions) with keys
+    q, m, w, r, z, vr, vt, vz, uid.
+    """
+    seed = w.seed if seed is None else seed
+    n = w.n_per_species if n is None else n
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r, z = _positions(w, n, rng)
+    r = _interior(r, w.R)
+    z = _interior(z, w.L)
+    weight = _total_particles_phys(w) / n
+    out = []
+    for q, m, T in ((-QE, ME, w.Te_eV), (QE, M_AR, w.Ti_eV)):
+        sig = math.sqrt(T * QE / m)
+        v = rng.standard_normal((3, n)) * sig
+        out.append(dict(q=q, m=m, w=weight, r=r.copy(), z=z.copy(),
+                        vr=v[0].copy(), vt=v[1].copy(), vz=v[2].copy(),
+                        uid=np.arange(n, dtype=np.uint64)))
+    return out
+
+
+def cold_mode_particles(w: Workload, n: int, v0: float, seed: int = 7):
+    """Cold electrons on a quiet (stratified) start with velocity v0 grad(psi),
+    psi = J0(chi01 r / R) sin(pi z / L), plus immobile ions at the same
+    positions.  Used for the cold-plasma oscillation check."""
+    from scipy.special import j1
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m_side = int(round(math.sqrt(n)))
+    n = m_side * m_side
+    a = (np.arange(m_side) + 0.5) / m_side
+    ur, uz = np.meshgrid(a, a, indexing="ij")
+    ur = ur.ravel() + (rng.random(n) - 0.5) * 1e-9
+    uz = uz.ravel() + (rng.random(n) - 0.5) * 1e-9
+    r = w.R * np.sqrt(ur)
+    z = w.L * uz
+    k = CHI01 / w.R
+    kz = math.pi / w.L
+    # grad psi = (-k J1(k r) sin(kz z), kz J0(k r) cos(kz z))
+    vr = v0 * (-k * j1(k * r) * np.sin(kz * z))
+    vz = v0 * (kz * _j0(k * r) * np.cos(kz * z))
+    weight = w.n0 * math.pi * w.R ** 2 * w.L / n
+    e = dict(q=-QE, m=ME, w=weight, r=r, z=z, vr=vr, vt=np.zeros(n), vz=vz,
+             uid=np.arange(n, dtype=np.uint64))
+    i = dict(q=QE, m=M_AR, w=weight, r=r.copy(), z=z.copy(), vr=np.zeros(n),
+             vt=np.zeros(n), vz=np.zeros(n), uid=np.arange(n, dtype=np.uint64))
+    return [e, i]
