@@ -1,0 +1,238 @@
+/*
+ * ecpic.h -- C ABI of the MI355X (gfx950) hot path of the implicit,
+ * energy- and charge-conserving electromagnetic PIC/MCC method on an
+ * axisymmetric r-z grid (Eremin et al., "Modeling of very high frequency
+ * large-electrode capacitively coupled plasmas with a fully electromagnetic
+ * particle-in-cell code", Sec. 2.1).
+ *
+ * Conventions
+ *  - Every call returns ecpic_status (0 = ECPIC_OK, negative = error).  No
+ *    exception or abort crosses the ABI; ecpic_last_error(ctx) gives a
+ *    NUL-terminated message owned by the context, valid until the next call.
+ *  - All work is enqueued on the HIP stream given to ecpic_create.  Calls that
+ *    return host scalars (field_iterate, step, diagnostics, read_particles'
+ *    count) synchronise that stream; the others are asynchronous.
+ *  - Array pointers marked (device) are device memory owned by the caller;
+ *    the library reads or writes them during the call (stream-ordered) and
+ *    keeps no reference.  The library owns its internal state (particle SoA,
+ *    field and solver arrays) and frees it in ecpic_destroy.
+ *  - A context is not thread-safe; calls on one context must be serialised.
+ *  - Layouts (row-major, FP64):
+ *      ur[i][j], 0<=i<nr, 0<=j<=nz : voltage of r-edge (i+1/2, j)      [V]
+ *      uz[i][j], 0<=i<=nr, 0<=j<nz : voltage of z-edge (i, j+1/2)      [V]
+ *      h [i][j], 0<=i<nr, 0<=j<nz  : H_theta at the cell centre        [A/m]
+ *      Ir, Iz as ur, uz            : current through the dual faces    [A]
+ *      node arrays [nr+1][nz+1]    : charge per node                   [C]
+ *    Logical positions xi in [0,nr], eta in [0,nz] are in cell units.
+ */
+#ifndef ECPIC_H
+#define ECPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ECPIC_OK = 0,
+  ECPIC_EINVAL = -1,    /* invalid argument, shape or descriptor            */
+  ECPIC_ENOMEM = -2,    /* device allocation failed                         */
+  ECPIC_EHIP = -3,      /* HIP runtime error (message in ecpic_last_error)  */
+  ECPIC_ENOTCONV = -4,  /* Picard iteration did not reach the tolerance     */
+  ECPIC_EPUSH = -5,     /* a particle push failed (sub-step cap / no solve) */
+  ECPIC_ECAPACITY = -6, /* species capacity exceeded by ionisation          */
+  ECPIC_ERANGE = -7,    /* a particle exceeded the null-collision bound     */
+  ECPIC_ENOTIMPL = -8   /* not available in this build                      */
+} ecpic_status;
+
+typedef enum {
+  ECPIC_FP64 = 0,  /* FP64 particle state and push                          */
+  ECPIC_MIXED = 1  /* int32 cell + FP32 offsets/velocities, FP32 push; FP64
+                      current accumulation, field solve, residual, energies */
+} ecpic_precision;
+
+/* Grid, field constants and drive (Sec. 2.1: separable map r(xi), z(eta);
+ * TM fields E_r, E_z, H_theta; PEC walls).  SI units. */
+typedef struct {
+  int32_t nr, nz;         /* cells in r and z                                */
+  double R, L;            /* cylinder radius and height [m]                  */
+  double xi_axis;         /* map parameter: r ~ sqrt(xi) below it, 0=uniform */
+  double dt;              /* time step [s]                                   */
+  double eps, mu;         /* permittivity, permeability of the gap           */
+  int32_t n_drive;        /* harmonics on the drive gap edge (0..2)          */
+  int32_t reserved;
+  double drive_amp[2];    /* V(t) = sum amp sin(2 pi freq t + phase) [V]     */
+  double drive_freq[2];
+  double drive_phase[2];
+} ecpic_grid_desc;
+
+typedef struct {
+  double q, m;            /* charge [C], mass [kg]                           */
+  double weight;          /* physical particles per macro-particle           */
+  int64_t capacity;       /* maximum macro-particles held                    */
+  int32_t mobile;         /* 0: frozen (not pushed, no current)              */
+  int32_t reserved;
+} ecpic_species_desc;
+
+/* Null-collision Monte Carlo (Sec. 2.1) with synthetic argon cross-sections:
+ * e-Ar elastic, one excitation (11.5 eV), ionisation (15.76 eV); Ar+-Ar
+ * charge exchange.  Random numbers: Philox4x64-10, key (seed, species id),
+ * counter (particle id, step, block, 0). */
+typedef struct {
+  int32_t enabled;
+  int32_t electron_sid, ion_sid;
+  int32_t reserved;
+  double n_gas, t_gas;    /* neutral density [m^-3] and temperature [K]      */
+  double m_gas;           /* neutral mass [kg]                               */
+  double eps_max_ev;      /* energy bound of the null-collision rate [eV]    */
+  uint64_t seed;
+} ecpic_mcc_desc;
+
+typedef struct {
+  double tol;             /* energy-norm relative update tolerance           */
+  int32_t max_iter;       /* Picard iterations allowed (1..64)               */
+  int32_t fixed_iter;     /* >0: exactly this many iterations (parity mode)  */
+  int32_t sort_every;     /* counting sort by cell every k steps (0 = never) */
+  int32_t use_nn;         /* 1: learned initial guess (see ecpic_nn_*)       */
+} ecpic_step_opts;
+
+typedef struct {
+  int32_t iters, converged;
+  int32_t used_nn, nn_fallback;
+  double residual[64];
+  double ke[4];           /* kinetic energy per species at t^{n+1} [J]       */
+  double we, wb;          /* electric and magnetic field energy [J]          */
+  double w_particles;     /* work done on particles by the field [J]         */
+  double w_field_io;      /* field-side energy exchange with the current [J] */
+  double w_drive;         /* energy injected by the drive gap [J]            */
+  double w_absorbed;      /* kinetic energy lost to the walls [J]            */
+  double w_coll;          /* kinetic energy lost in collisions [J]           */
+  int64_t n_alive[4];
+  int64_t n_absorbed[4];
+  int64_t n_coll[4];
+  int64_t n_ionized;
+  int64_t n_substeps, n_crossings, n_errors, n_over_range;
+  double t;               /* time after the step [s]                         */
+  int64_t step;           /* step counter after the step                     */
+} ecpic_step_stats;
+
+typedef struct ecpic_ctx ecpic_ctx;
+
+/* Create a context for the grid (Sec. 2.1 mesh and TM field model) and
+ * factorise the H_theta system.  hip_stream: a hipStream_t (NULL = default
+ * stream).  Fields start at zero, t = 0, step = 0.  EINVAL on bad shapes or
+ * non-positive constants, ENOMEM/EHIP on device failures. */
+ecpic_status ecpic_create(const ecpic_grid_desc* grid, ecpic_precision prec, void* hip_stream,
+                          ecpic_ctx** out);
+ecpic_status ecpic_destroy(ecpic_ctx* ctx);
+
+/* Add a species with room for desc->capacity macro-particles (device memory
+ * allocated here).  Up to 4 species.  *sid receives its index. */
+ecpic_status ecpic_add_species(ecpic_ctx* ctx, const ecpic_species_desc* desc, int32_t* sid);
+
+/* Replace the particles of a species.  r, z: physical positions [m] inside
+ * (0,R]x(0,L); vr, vt, vz [m/s]; uid: identifiers (RNG counters).  All
+ * (device), length n <= capacity.  Positions are mapped to logical (xi, eta)
+ * on the device.  EINVAL if n exceeds the capacity. */
+ecpic_status ecpic_load_particles(ecpic_ctx* ctx, int32_t sid, const double* r, const double* z,
+                                  const double* vr, const double* vt, const double* vz,
+                                  const uint64_t* uid, int64_t n);
+
+/* Copy the live particles of a species, in storage order, as FP64 logical
+ * positions and velocities (device outputs of length cap).  *n_out receives
+ * the count (synchronises).  EINVAL if cap is too small. */
+ecpic_status ecpic_read_particles(ecpic_ctx* ctx, int32_t sid, double* xi, double* eta,
+                                  double* vr, double* vt, double* vz, uint64_t* uid, int64_t cap,
+                                  int64_t* n_out);
+
+/* Set the field state: u at t^n (ur, uz, h) and u at t^{n-1} for the
+ * extrapolated guess (NULL: same as t^n), plus the clock.  (device) */
+ecpic_status ecpic_set_fields(ecpic_ctx* ctx, const double* ur, const double* uz, const double* h,
+                              const double* ur_prev, const double* uz_prev, double t, int64_t step);
+ecpic_status ecpic_get_fields(ecpic_ctx* ctx, double* ur, double* uz, double* h);
+
+/* Set the frozen half-step field u^{n+1/2} used by ecpic_push_deposit. (device) */
+ecpic_status ecpic_set_half_field(ecpic_ctx* ctx, const double* ur_half, const double* uz_half);
+
+/* One pass of the implicit push (Eq. (4), mid-point centring, each orbit
+ * split at every cell-face crossing) and charge-conserving deposit (Eq. (3),
+ * spline order 1) of every mobile species in the current half-step field.
+ * commit=0: particle state is read only and the currents I are recomputed;
+ * commit=1: state written, wall absorption applied.  Ir, Iz: optional
+ * (device) outputs receiving a copy of the currents.  EPUSH if a particle
+ * failed (state left as far as it got). */
+ecpic_status ecpic_push_deposit(ecpic_ctx* ctx, int32_t commit, double* Ir, double* Iz);
+
+/* Stateless Crank-Nicolson solve of the TM equations (Eq. (2), mid-point
+ * centring) from (ur0, uz0, h0) at time t with currents (Ir, Iz), writing the
+ * fields at t+dt.  H_theta is the unknown; the drive gap edge takes
+ * V(t+dt).  All arrays (device). */
+ecpic_status ecpic_field_solve(ecpic_ctx* ctx, const double* ur0, const double* uz0,
+                               const double* h0, const double* Ir, const double* Iz, double t,
+                               double* ur1, double* uz1, double* h1);
+
+/* One field iterate of the Picard loop: solve with the currents of the last
+ * push_deposit, store u^{n+1,(k+1)}, h^{n+1,(k+1)} and the next half-step
+ * field, and return r_k = |u^(k+1)-u^(k)|_E / |u^(k+1)|_E (synchronises). */
+ecpic_status ecpic_field_iterate(ecpic_ctx* ctx, double* rel_update);
+
+/* Null-collision Monte Carlo on the current velocities (Sec. 2.1), at the
+ * given step index (RNG counter).  ECAPACITY if ionisation overflowed. */
+ecpic_status ecpic_collide(ecpic_ctx* ctx, const ecpic_mcc_desc* mcc, int64_t step);
+
+/* Collision model used by ecpic_step (NULL or enabled=0 turns MCC off). */
+ecpic_status ecpic_set_mcc(ecpic_ctx* ctx, const ecpic_mcc_desc* mcc);
+
+/* One implicit step: extrapolated (or learned) guess, Picard iterations of
+ * push_deposit + field_iterate until r_k <= tol (or fixed_iter passes),
+ * commit of the particles pushed in the accepted half-step field, MCC,
+ * optional sort, field shift.  ENOTCONV leaves state and fields untouched.
+ * stats may be NULL. */
+ecpic_status ecpic_step(ecpic_ctx* ctx, const ecpic_step_opts* opts, ecpic_step_stats* stats);
+
+/* Counting sort of every species by cell, dropping absorbed particles. */
+ecpic_status ecpic_sort(ecpic_ctx* ctx);
+
+/* Node charge of all species with logical bilinear weights into q (device,
+ * [nr+1][nz+1]); wall charge absorbed so far into bot[nr+1], top[nr+1],
+ * side[nz+1] (device, each optional). */
+ecpic_status ecpic_node_charge(ecpic_ctx* ctx, double* q, double* bot, double* top, double* side);
+
+/* Energies and counts of the current state (synchronises). */
+ecpic_status ecpic_diagnostics(ecpic_ctx* ctx, ecpic_step_stats* stats);
+
+/* Learned initial guess: a 4-layer 3x3 convolutional network (6 -> 32 -> 32
+ * -> 32 -> 3 channels) on the packed (nr+1)x(nz+1) canvas of (ur, uz, h) at
+ * t^n and their change since t^{n-1}, predicting the correction to the
+ * extrapolated u^{n+1} guess.  BF16 weights and activations, FP32
+ * accumulation.  Weight layout (host or device per the call):
+ *   per layer l: W_l[cout][cin][3][3] then b_l[cout], layers concatenated;
+ *   norm[9] = input scales (6) and output scales (3).
+ * ecpic_nn_param_count returns the number of weights+biases. */
+int64_t ecpic_nn_param_count(void);
+/* Install BF16 weights (device, param_count uint16 bf16 bit patterns) and the
+ * normalisation (host, 9 floats) used by ecpic_step when use_nn=1. */
+ecpic_status ecpic_nn_set_weights(ecpic_ctx* ctx, const uint16_t* w_bf16, const float* norm);
+/* Forward pass on a batch of canvases x (device, [batch][6][nr+1][nz+1]
+ * bf16 bits) into y (device, [batch][3][nr+1][nz+1] FP32). */
+ecpic_status ecpic_nn_forward(ecpic_ctx* ctx, const uint16_t* w_bf16, const uint16_t* x,
+                              float* y, int32_t batch);
+/* Loss and gradient: mean squared error over the canvas against target t
+ * (device FP32, like y), gradient of all weights and biases into dw (device
+ * FP32, param_count), loss into *loss (synchronises). */
+ecpic_status ecpic_nn_grad(ecpic_ctx* ctx, const uint16_t* w_bf16, const uint16_t* x,
+                           const float* t, int32_t batch, float* dw, float* loss);
+/* One Adam step (beta 0.9/0.999, eps 1e-8) on FP32 master weights w (device),
+ * moments m, v (device), from gradient dw; refreshes the BF16 copy. */
+ecpic_status ecpic_nn_adam(ecpic_ctx* ctx, float* w, float* m, float* v, const float* dw,
+                           uint16_t* w_bf16, float lr, int32_t t);
+
+const char* ecpic_last_error(const ecpic_ctx* ctx);
+const char* ecpic_status_string(ecpic_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -911,13 +911,15 @@ int og_collide(og_ctx* c, og_species* sp, int32_t nsp, const og_mcc* m, int64_t 
   if (!m || !m->enabled) return 0;
   const double dt = c->g.dt;
   int rc = 0;
-  for (int sid = 0; sid < nsp; ++sid) {
+  int64_t nstart[8];
+  for (int sid = 0; sid < nsp && sid < 8; ++sid) nstart[sid] = sp[sid].n;
+  for (int sid = 0; sid < nsp && sid < 8; ++sid) {
     og_species* s = &sp[sid];
     const int role = (sid == m->electron_sid) ? 1 : (sid == m->ion_sid ? 2 : 0);
     if (!role || !s->mobile) continue;
     const double numax = og_nu_max(m, role, s->m);
     const double pnull = 1.0 - exp(-numax * dt);
-    const int64_t n0 = s->n; /* particles born this step do not collide */
+    const int64_t n0 = nstart[sid]; /* particles born this step do not collide */
     for (int64_t k = 0; k < n0; ++k) {
       draws_t D;
       get_draws(m->seed, sid, s->uid[k], step, 1, &D);
