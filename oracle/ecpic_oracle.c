@@ -520,7 +520,7 @@ static int solve_free(const pctx* P, int i, int j, const pst* p, double dtau,
       *xb = solve_xi_mid(c, p->xi, vr, dtau);
       *eb = p->eta + 0.5 * dtau * vz / c->dz;
       vb[0] = vr; vb[1] = vt; vb[2] = vz;
-      return 1;
+      return (*xb >= 0.0) ? 1 : 0;
     }
   }
   return 0;
@@ -563,7 +563,7 @@ static int solve_cross(const pctx* P, int i, int j, const pst* p, int d, double 
   const double xd = (d == 0) ? p->xi : p->eta;
   const double xbar_d = 0.5 * (xd + f);
   const double Jd = (d == 0) ? 1.0 / inv_jr(c, xbar_d) : c->dz;
-  const double D = (f - xd) * Jd;
+  const double D = (f == xd) ? 0.0 : (f - xd) * Jd; /* J_r is infinite on the axis */
   if (D == 0.0) {
     /* already on the face: leaving through it now if moving outward */
     const double v0d = (d == 0) ? p->vr : p->vz;

@@ -1,0 +1,333 @@
+"""MI355X (gfx950) hot path of the implicit energy- and charge-conserving EM
+PIC/MCC method on an r-z grid: ctypes binding of ``libecpic.so``.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``csrc/``.  PyTorch supplies device memory and the stream.  Importing this
+package never falls back to another implementation; when the library is
+missing, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libecpic.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "ecpic.h")
+
+ECPIC_FP64, ECPIC_MIXED = 0, 1
+STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "EPUSH",
+          -6: "ECAPACITY", -7: "ERANGE", -8: "ENOTIMPL"}
+
+
+class EcpicError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("R", C.c_double), ("L", C.c_double),
+                ("xi_axis", C.c_double), ("dt", C.c_double), ("eps", C.c_double),
+                ("mu", C.c_double), ("n_drive", C.c_int32), ("reserved", C.c_int32),
+                ("drive_amp", C.c_double * 2), ("drive_freq", C.c_double * 2),
+                ("drive_phase", C.c_double * 2)]
+
+
+class SpeciesDesc(C.Structure):
+    _fields_ = [("q", C.c_double), ("m", C.c_double), ("weight", C.c_double),
+                ("capacity", C.c_int64), ("mobile", C.c_int32), ("reserved", C.c_int32)]
+
+
+class MccDesc(C.Structure):
+    _fields_ = [("enabled", C.c_int32), ("electron_sid", C.c_int32), ("ion_sid", C.c_int32),
+                ("reserved", C.c_int32), ("n_gas", C.c_double), ("t_gas", C.c_double),
+                ("m_gas", C.c_double), ("eps_max_ev", C.c_double), ("seed", C.c_uint64)]
+
+
+class StepOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("fixed_iter", C.c_int32),
+                ("sort_every", C.c_int32), ("use_nn", C.c_int32)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("used_nn", C.c_int32),
+                ("nn_fallback", C.c_int32), ("residual", C.c_double * 64), ("ke", C.c_double * 4),
+                ("we", C.c_double), ("wb", C.c_double), ("w_particles", C.c_double),
+                ("w_field_io", C.c_double), ("w_drive", C.c_double), ("w_absorbed", C.c_double),
+                ("w_coll", C.c_double), ("n_alive", C.c_int64 * 4), ("n_absorbed", C.c_int64 * 4),
+                ("n_coll", C.c_int64 * 4), ("n_ionized", C.c_int64), ("n_substeps", C.c_int64),
+                ("n_crossings", C.c_int64), ("n_errors", C.c_int64), ("n_over_range", C.c_int64),
+                ("t", C.c_double), ("step", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if hasattr(v, "__len__") else v
+        d["residual"] = d["residual"][: self.iters]
+        return d
+
+
+_lib = None
+_vp, _dp, _fp = C.c_void_p, C.c_void_p, C.c_void_p
+
+
+def lib() -> C.CDLL:
+    """Load libecpic.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        sig = {
+            "ecpic_create": ([C.POINTER(GridDesc), C.c_int, _vp, C.POINTER(_vp)], st),
+            "ecpic_destroy": ([_vp], st),
+            "ecpic_add_species": ([_vp, C.POINTER(SpeciesDesc), C.POINTER(C.c_int32)], st),
+            "ecpic_load_particles": ([_vp, C.c_int32] + [_dp] * 6 + [C.c_int64], st),
+            "ecpic_read_particles": ([_vp, C.c_int32] + [_dp] * 6 + [C.c_int64,
+                                                                      C.POINTER(C.c_int64)], st),
+            "ecpic_set_fields": ([_vp] + [_dp] * 5 + [C.c_double, C.c_int64], st),
+            "ecpic_get_fields": ([_vp, _dp, _dp, _dp], st),
+            "ecpic_set_half_field": ([_vp, _dp, _dp], st),
+            "ecpic_push_deposit": ([_vp, C.c_int32, _dp, _dp], st),
+            "ecpic_field_solve": ([_vp] + [_dp] * 5 + [C.c_double] + [_dp] * 3, st),
+            "ecpic_field_iterate": ([_vp, C.POINTER(C.c_double)], st),
+            "ecpic_collide": ([_vp, C.POINTER(MccDesc), C.c_int64], st),
+            "ecpic_set_mcc": ([_vp, C.POINTER(MccDesc)], st),
+            "ecpic_step": ([_vp, C.POINTER(StepOpts), C.POINTER(StepStats)], st),
+            "ecpic_sort": ([_vp], st),
+            "ecpic_node_charge": ([_vp, _dp, _dp, _dp, _dp], st),
+            "ecpic_diagnostics": ([_vp, C.POINTER(StepStats)], st),
+            "ecpic_nn_param_count": ([], C.c_int64),
+            "ecpic_nn_set_weights": ([_vp, _vp, C.POINTER(C.c_float)], st),
+            "ecpic_nn_forward": ([_vp, _vp, _vp, _vp, C.c_int32], st),
+            "ecpic_nn_grad": ([_vp, _vp, _vp, _vp, C.c_int32, _vp, C.POINTER(C.c_float)], st),
+            "ecpic_nn_adam": ([_vp, _vp, _vp, _vp, _vp, _vp, C.c_float, C.c_int32], st),
+            "ecpic_last_error": ([_vp], C.c_char_p),
+            "ecpic_status_string": ([C.c_int], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list:
+    """Names of the entry points declared in include/ecpic.h."""
+    import re
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)  # drop comments
+    return sorted(set(re.findall(r"\b(ecpic_[a-z0-9_]+)\s*\(", txt)))
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+class Context:
+    """One grid + its species on the current HIP device and torch stream."""
+
+    def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
+                 drive_phase=(), precision: str = "fp64", device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.nr, self.nz = nr, nz
+        self.precision = precision
+        g = GridDesc()
+        g.nr, g.nz, g.R, g.L, g.xi_axis, g.dt, g.eps, g.mu = nr, nz, R, L, xi_a, dt, eps, mu
+        g.n_drive = len(drive_amp)
+        for k in range(len(drive_amp)):
+            g.drive_amp[k] = drive_amp[k]
+            g.drive_freq[k] = drive_freq[k]
+            g.drive_phase[k] = drive_phase[k] if k < len(drive_phase) else 0.0
+        self.desc = g
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = _vp()
+        self.L = lib()
+        self._check(self.L.ecpic_create(C.byref(g), ECPIC_MIXED if precision == "mixed"
+                                        else ECPIC_FP64, _vp(stream), C.byref(h)), None)
+        self.h = h
+        self.caps: Dict[int, int] = {}
+
+    def _check(self, rc: int, h=None):
+        if rc != 0:
+            msg = self.L.ecpic_last_error(h if h is not None else getattr(self, "h", None))
+            raise EcpicError(rc, (msg or b"").decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.torch.cuda.synchronize()
+            self.L.ecpic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tensors --
+    def _dev(self, a, dtype=None):
+        t = self.torch
+        if isinstance(a, np.ndarray):
+            a = t.from_numpy(np.ascontiguousarray(a))
+        return a.to(self.device, dtype=dtype).contiguous()
+
+    def zeros_r(self):
+        return self.torch.zeros(self.nr * (self.nz + 1), dtype=self.torch.float64,
+                                device=self.device)
+
+    def zeros_z(self):
+        return self.torch.zeros((self.nr + 1) * self.nz, dtype=self.torch.float64,
+                                device=self.device)
+
+    def zeros_h(self):
+        return self.torch.zeros(self.nr * self.nz, dtype=self.torch.float64, device=self.device)
+
+    # -- species --
+    def add_species(self, q, m, weight, capacity, mobile=True) -> int:
+        d = SpeciesDesc(q, m, weight, int(capacity), int(bool(mobile)), 0)
+        sid = C.c_int32()
+        self._check(self.L.ecpic_add_species(self.h, C.byref(d), C.byref(sid)), self.h)
+        self.caps[sid.value] = int(capacity)
+        return sid.value
+
+    def load_particles(self, sid: int, r, z, vr, vt, vz, uid):
+        f64 = self.torch.float64
+        arrs = [self._dev(a, f64) for a in (r, z, vr, vt, vz)]
+        u = uid if not isinstance(uid, np.ndarray) else uid.astype(np.int64)
+        u = self._dev(u, self.torch.int64)
+        self._keep = (arrs, u)
+        self._check(self.L.ecpic_load_particles(self.h, sid, *[_ptr(a) for a in arrs], _ptr(u),
+                                                len(arrs[0])), self.h)
+
+    def read_particles(self, sid: int) -> dict:
+        t = self.torch
+        cap = self.caps[sid]
+        outs = [t.empty(cap, dtype=t.float64, device=self.device) for _ in range(5)]
+        uid = t.empty(cap, dtype=t.int64, device=self.device)
+        n = C.c_int64()
+        self._check(self.L.ecpic_read_particles(self.h, sid, *[_ptr(o) for o in outs], _ptr(uid),
+                                                cap, C.byref(n)), self.h)
+        n = n.value
+        names = ("xi", "eta", "vr", "vt", "vz")
+        d = {k: o[:n].cpu().numpy() for k, o in zip(names, outs)}
+        d["uid"] = uid[:n].cpu().numpy().astype(np.uint64)
+        return d
+
+    # -- fields --
+    def set_fields(self, ur, uz, h, ur_prev=None, uz_prev=None, t=0.0, step=0):
+        f = self.torch.float64
+        ts = [self._dev(a, f) if a is not None else None for a in (ur, uz, h, ur_prev, uz_prev)]
+        self._check(self.L.ecpic_set_fields(self.h, *[_ptr(a) for a in ts], float(t), int(step)),
+                    self.h)
+        self.torch.cuda.synchronize()
+
+    def get_fields(self):
+        ur, uz, h = self.zeros_r(), self.zeros_z(), self.zeros_h()
+        self._check(self.L.ecpic_get_fields(self.h, _ptr(ur), _ptr(uz), _ptr(h)), self.h)
+        self.torch.cuda.synchronize()
+        return ur.cpu().numpy(), uz.cpu().numpy(), h.cpu().numpy()
+
+    def set_half_field(self, ur_h, uz_h):
+        f = self.torch.float64
+        a, b = self._dev(ur_h, f), self._dev(uz_h, f)
+        self._check(self.L.ecpic_set_half_field(self.h, _ptr(a), _ptr(b)), self.h)
+        self.torch.cuda.synchronize()
+
+    def push_deposit(self, commit=False):
+        Ir, Iz = self.zeros_r(), self.zeros_z()
+        self._check(self.L.ecpic_push_deposit(self.h, int(commit), _ptr(Ir), _ptr(Iz)), self.h)
+        self.torch.cuda.synchronize()
+        return Ir.cpu().numpy(), Iz.cpu().numpy()
+
+    def field_solve(self, ur0, uz0, h0, Ir, Iz, t):
+        f = self.torch.float64
+        ins = [self._dev(a, f) for a in (ur0, uz0, h0, Ir, Iz)]
+        ur1, uz1, h1 = self.zeros_r(), self.zeros_z(), self.zeros_h()
+        self._check(self.L.ecpic_field_solve(self.h, *[_ptr(a) for a in ins], float(t),
+                                             _ptr(ur1), _ptr(uz1), _ptr(h1)), self.h)
+        self.torch.cuda.synchronize()
+        return ur1.cpu().numpy(), uz1.cpu().numpy(), h1.cpu().numpy()
+
+    def field_iterate(self) -> float:
+        r = C.c_double()
+        self._check(self.L.ecpic_field_iterate(self.h, C.byref(r)), self.h)
+        return r.value
+
+    # -- collisions, step --
+    @staticmethod
+    def mcc_desc(mcc: Optional[dict]) -> MccDesc:
+        if not mcc:
+            return MccDesc()
+        return MccDesc(1, mcc.get("electron_sid", 0), mcc.get("ion_sid", 1), 0, mcc["n_gas"],
+                       mcc["T_gas"], mcc["m_gas"], mcc["eps_max_ev"], mcc["seed"])
+
+    def set_mcc(self, mcc: Optional[dict]):
+        d = self.mcc_desc(mcc)
+        self._check(self.L.ecpic_set_mcc(self.h, C.byref(d)), self.h)
+
+    def collide(self, mcc: dict, step: int):
+        d = self.mcc_desc(mcc)
+        self._check(self.L.ecpic_collide(self.h, C.byref(d), int(step)), self.h)
+
+    def step(self, tol=1e-10, max_iter=50, fixed_iter=0, sort_every=0, use_nn=False,
+             stats=True, check=True):
+        o = StepOpts(tol, max_iter, fixed_iter, sort_every, int(use_nn))
+        if stats:
+            s = StepStats()
+            rc = self.L.ecpic_step(self.h, C.byref(o), C.byref(s))
+            d = s.as_dict()
+        else:
+            rc = self.L.ecpic_step(self.h, C.byref(o), None)
+            d = {}
+        d["rc"] = rc
+        if check and rc != 0:
+            self._check(rc, self.h)
+        return d
+
+    def sort(self):
+        self._check(self.L.ecpic_sort(self.h), self.h)
+
+    def node_charge(self):
+        t = self.torch
+        q = t.zeros((self.nr + 1) * (self.nz + 1), dtype=t.float64, device=self.device)
+        b = t.zeros(self.nr + 1, dtype=t.float64, device=self.device)
+        tp = t.zeros(self.nr + 1, dtype=t.float64, device=self.device)
+        sd = t.zeros(self.nz + 1, dtype=t.float64, device=self.device)
+        self._check(self.L.ecpic_node_charge(self.h, _ptr(q), _ptr(b), _ptr(tp), _ptr(sd)), self.h)
+        t.cuda.synchronize()
+        return q.cpu().numpy(), b.cpu().numpy(), tp.cpu().numpy(), sd.cpu().numpy()
+
+    def diagnostics(self) -> dict:
+        s = StepStats()
+        self._check(self.L.ecpic_diagnostics(self.h, C.byref(s)), self.h)
+        return s.as_dict()
+
+
+def context_from_workload(w, precision="fp64", device="cuda", **over) -> Context:
+    p = w.grid_params()
+    p.update(over)
+    return Context(precision=precision, device=device, **p)
+
+
+def load_workload_species(ctx: Context, parts, extra_cap: float = 0.0, mobile=(True, True)):
+    sids = []
+    for k, d in enumerate(parts):
+        n = len(d["r"])
+        cap = int(n * (1.0 + extra_cap)) + 256
+        sid = ctx.add_species(d["q"], d["m"], d["w"], cap, mobile[k] if k < len(mobile) else True)
+        ctx.load_particles(sid, d["r"], d["z"], d["vr"], d["vt"], d["vz"], d["uid"])
+        sids.append(sid)
+    return sids

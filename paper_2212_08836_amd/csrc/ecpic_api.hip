@@ -1,0 +1,717 @@
+// ecpic_api.hip -- host runtime behind the C ABI of include/ecpic.h: context
+// and species management, the Picard driver of the implicit step (Sec. 2.1:
+// the coupled field/orbit system is solved by Picard iteration), and the
+// setup of the separable H_theta solver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ecpic_internal.h"
+
+using namespace ecpic;
+
+struct ecpic_ctx {
+  Ctx c;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kKB = 1.380649e-23;  // Boltzmann constant [J/K]
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      c.err = std::string(#expr) + ": " + hipGetErrorString(e_);                  \
+      return ECPIC_EHIP;                                                          \
+    }                                                                             \
+  } while (0)
+
+ecpic_status fail(Ctx& c, ecpic_status s, const std::string& msg) {
+  c.err = msg;
+  return s;
+}
+
+double drive(const ecpic_grid_desc& g, double t) {
+  double v = 0.0;
+  for (int k = 0; k < g.n_drive && k < 2; ++k)
+    v += g.drive_amp[k] * std::sin(2.0 * kPi * g.drive_freq[k] * t + g.drive_phase[k]);
+  return v;
+}
+
+double r_of_xi(const MapP& m, double xi) {
+  if (xi < m.xi_a) return 2.0 * m.s * std::sqrt(xi * m.xi_a);
+  return m.s * (xi + m.xi_a);
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+  return hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+hipError_t alloc_species_buf(Ctx& c, SpecDev& d, int64_t cap) {
+  hipError_t e;
+  const size_t n = (size_t)std::max<int64_t>(cap, 1);
+  std::memset(&d, 0, sizeof(d));
+  if (c.prec == ECPIC_FP64) {
+    if ((e = dalloc(&d.xi, n)) != hipSuccess) return e;
+    if ((e = dalloc(&d.eta, n)) != hipSuccess) return e;
+    if ((e = dalloc(&d.vr, n)) != hipSuccess) return e;
+    if ((e = dalloc(&d.vt, n)) != hipSuccess) return e;
+    if ((e = dalloc(&d.vz, n)) != hipSuccess) return e;
+  } else {
+    if ((e = dalloc(&d.cell, n)) != hipSuccess) return e;
+    if ((e = dalloc(&d.fa, n)) != hipSuccess) return e;
+    if ((e = dalloc(&d.fb, n)) != hipSuccess) return e;
+    if ((e = dalloc(&d.fvr, n)) != hipSuccess) return e;
+    if ((e = dalloc(&d.fvt, n)) != hipSuccess) return e;
+    if ((e = dalloc(&d.fvz, n)) != hipSuccess) return e;
+  }
+  return dalloc(&d.uid, n);
+}
+
+void free_species_buf(SpecDev& d) {
+  (void)hipFree(d.xi);
+  (void)hipFree(d.eta);
+  (void)hipFree(d.vr);
+  (void)hipFree(d.vt);
+  (void)hipFree(d.vz);
+  (void)hipFree(d.cell);
+  (void)hipFree(d.fa);
+  (void)hipFree(d.fb);
+  (void)hipFree(d.fvr);
+  (void)hipFree(d.fvt);
+  (void)hipFree(d.fvz);
+  (void)hipFree(d.uid);
+}
+
+SpecDev view(Species& s) {
+  SpecDev d = s.d[s.cur];
+  d.n = s.n;
+  d.cap = s.desc.capacity;
+  d.q = s.desc.q;
+  d.m = s.desc.m;
+  d.w = s.desc.weight;
+  d.mobile = s.desc.mobile;
+  return d;
+}
+
+int64_t n_edges_r(const Ctx& c) { return (int64_t)c.g.nr * (c.g.nz + 1); }
+int64_t n_edges_z(const Ctx& c) { return (int64_t)(c.g.nr + 1) * c.g.nz; }
+int64_t n_cells(const Ctx& c) { return (int64_t)c.g.nr * c.g.nz; }
+
+// Geometry and separable-solver tables (host FP64), uploaded once.
+hipError_t setup_solver(Ctx& c) {
+  const int nr = c.g.nr, nz = c.g.nz;
+  const MapP& m = c.m;
+  const double dt = c.g.dt, eps = c.g.eps, mu = c.g.mu;
+  std::vector<double> rn(nr + 1), rh(nr), ell(nr), area(nr), azs(nr), wr(nr), wz(nr);
+  for (int i = 0; i <= nr; ++i) rn[i] = r_of_xi(m, i);
+  rn[nr] = c.g.R;
+  for (int i = 0; i < nr; ++i) {
+    rh[i] = r_of_xi(m, i + 0.5);
+    ell[i] = rn[i + 1] - rn[i];
+    area[i] = ell[i] * m.dz;
+    const double rm = i > 0 ? rh[i - 1] : 0.0;
+    azs[i] = kPi * (rh[i] * rh[i] - rm * rm);
+    wr[i] = eps * 2.0 * kPi * rh[i] * m.dz / ell[i];
+    wz[i] = eps * azs[i] / m.dz;
+  }
+  // tridiagonal radial part T and the z-coupling weights G
+  std::vector<double> Td(nr), To(nr, 0.0), G(nr);
+  for (int i = 0; i < nr; ++i) {
+    const double mi = 2.0 * kPi * rh[i];
+    const double Dz = 2.0 * wz[i] / dt;
+    Td[i] = mi * 2.0 * mu * area[i] / dt + mi * mi / Dz;
+    if (i + 1 < nr) {
+      const double Dz1 = 2.0 * wz[i + 1] / dt;
+      Td[i] += mi * mi / Dz1;
+    }
+    if (i > 0) To[i] = -(2.0 * kPi * rh[i - 1]) * mi / Dz;
+    const double Dr = 2.0 * wr[i] / dt;
+    G[i] = mi * mi / Dr;
+  }
+  // orthonormal DCT-II diagonalising the Neumann second difference
+  std::vector<double> Q((size_t)nz * nz), Qt((size_t)nz * nz);
+  for (int k = 0; k < nz; ++k) {
+    const double a = (k == 0) ? std::sqrt(1.0 / nz) : std::sqrt(2.0 / nz);
+    for (int j = 0; j < nz; ++j) {
+      const double v = a * std::cos(kPi * k * (2.0 * j + 1.0) / (2.0 * nz));
+      Q[(size_t)k * nz + j] = v;
+      Qt[(size_t)j * nz + k] = v;
+    }
+  }
+  std::vector<double> lo((size_t)nz * nr, 0.0), inv((size_t)nz * nr);
+  for (int k = 0; k < nz; ++k) {
+    const double lam = 2.0 - 2.0 * std::cos(kPi * k / nz);
+    double cp = Td[0] + lam * G[0];
+    inv[(size_t)k * nr] = 1.0 / cp;
+    for (int i = 1; i < nr; ++i) {
+      const double l = To[i] / cp;
+      cp = Td[i] + lam * G[i] - l * To[i];
+      lo[(size_t)k * nr + i] = l;
+      inv[(size_t)k * nr + i] = 1.0 / cp;
+    }
+  }
+  SolverDev& S = c.sol;
+  hipError_t e;
+  auto up = [&](double** d, const std::vector<double>& h) -> hipError_t {
+    hipError_t ee = dalloc(d, h.size());
+    if (ee != hipSuccess) return ee;
+    return hipMemcpy(*d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
+  };
+  if ((e = up(&S.rh, rh)) != hipSuccess) return e;
+  if ((e = up(&S.wr, wr)) != hipSuccess) return e;
+  if ((e = up(&S.wz, wz)) != hipSuccess) return e;
+  if ((e = up(&S.area, area)) != hipSuccess) return e;
+  if ((e = up(&S.Q, Q)) != hipSuccess) return e;
+  if ((e = up(&S.Qt, Qt)) != hipSuccess) return e;
+  if ((e = up(&S.tri_lo, lo)) != hipSuccess) return e;
+  if ((e = up(&S.tri_inv, inv)) != hipSuccess) return e;
+  if ((e = up(&S.tri_up, To)) != hipSuccess) return e;
+  if ((e = dalloc(&S.work0, (size_t)nr * nz)) != hipSuccess) return e;
+  if ((e = dalloc(&S.work1, (size_t)nr * nz)) != hipSuccess) return e;
+  if ((e = dalloc(&S.partial, 4096)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t zero(double* p, int64_t n, hipStream_t s) { return launch_zero(p, n, s); }
+
+MccDev make_mcc(Ctx& c, int sid, int64_t step) {
+  MccDev d;
+  std::memset(&d, 0, sizeof(d));
+  const ecpic_mcc_desc& M = c.mcc;
+  if (!M.enabled) return d;
+  const int role = (sid == M.electron_sid) ? 1 : (sid == M.ion_sid ? 2 : 0);
+  if (!role) return d;
+  Species& s = c.sp[sid];
+  if (!s.desc.mobile) return d;
+  d.enabled = 1;
+  d.role = role;
+  d.numax = c.numax[sid];
+  d.pnull = 1.0 - std::exp(-d.numax * c.g.dt);
+  d.n_gas = M.n_gas;
+  d.m_gas = M.m_gas;
+  d.sig_gas = std::sqrt(kKB * M.t_gas / M.m_gas);
+  d.eps_max_ev = M.eps_max_ev;
+  d.seed = M.seed;
+  d.step = step;
+  d.base_self = s.n;
+  if (role == 1 && M.ion_sid >= 0 && M.ion_sid < (int)c.sp.size()) {
+    Species& ion = c.sp[M.ion_sid];
+    d.partner = view(ion);
+    d.partner.sid = M.ion_sid;
+    d.base_partner = ion.n;
+    d.sig_ion = std::sqrt(kKB * M.t_gas / ion.desc.m);
+  }
+  return d;
+}
+
+PushArgs push_args(Ctx& c, int sid, int commit) {
+  PushArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.m = c.m;
+  a.ur = c.ur_half;
+  a.uz = c.uz_half;
+  a.urf = c.ur_half_f;
+  a.uzf = c.uz_half_f;
+  a.Ir = c.Ir;
+  a.Iz = c.Iz;
+  a.s = view(c.sp[sid]);
+  a.s.sid = sid;
+  a.commit = commit;
+  a.wall_bot = c.wall_bot;
+  a.wall_top = c.wall_top;
+  a.wall_side = c.wall_side;
+  a.tally = c.tally;
+  return a;
+}
+
+// One pass over all species; currents zeroed first.
+ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step) {
+  HIPCHK(zero(c.Ir, n_edges_r(c), c.stream));
+  HIPCHK(zero(c.Iz, n_edges_z(c), c.stream));
+  if (commit) HIPCHK(hipMemsetAsync(c.tally, 0, sizeof(Tally), c.stream));
+  // append offsets of every species are taken before any pass appends
+  std::vector<MccDev> mcc(c.sp.size());
+  for (size_t s = 0; s < c.sp.size(); ++s) {
+    std::memset(&mcc[s], 0, sizeof(MccDev));
+    if (commit && with_mcc) mcc[s] = make_mcc(c, (int)s, step);
+  }
+  for (size_t s = 0; s < c.sp.size(); ++s) {
+    if (!c.sp[s].desc.mobile || c.sp[s].n == 0) continue;
+    PushArgs a = push_args(c, (int)s, commit);
+    a.mcc = mcc[s];
+    HIPCHK(launch_push(a, c.stream));
+  }
+  return ECPIC_OK;
+}
+
+// After a commit/collision pass: fetch the tally and grow species counts.
+ecpic_status finish_tally(Ctx& c, Tally& t) {
+  HIPCHK(hipMemcpyAsync(c.tally_host, c.tally, sizeof(Tally), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  t = *c.tally_host;
+  ecpic_status rc = ECPIC_OK;
+  for (size_t s = 0; s < c.sp.size(); ++s) {
+    const int64_t add = (int64_t)t.append[s];
+    int64_t n = c.sp[s].n + add;
+    if (n > c.sp[s].desc.capacity) n = c.sp[s].desc.capacity;
+    c.sp[s].n = n;
+  }
+  if (t.n_overflow) rc = fail(c, ECPIC_ECAPACITY, "species capacity exceeded by ionisation");
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ecpic_status_string(ecpic_status s) {
+  switch (s) {
+    case ECPIC_OK: return "ok";
+    case ECPIC_EINVAL: return "invalid argument";
+    case ECPIC_ENOMEM: return "out of device memory";
+    case ECPIC_EHIP: return "HIP runtime error";
+    case ECPIC_ENOTCONV: return "Picard iteration did not converge";
+    case ECPIC_EPUSH: return "particle push failed";
+    case ECPIC_ECAPACITY: return "species capacity exceeded";
+    case ECPIC_ERANGE: return "particle beyond the null-collision bound";
+    case ECPIC_ENOTIMPL: return "not implemented";
+  }
+  return "unknown status";
+}
+
+const char* ecpic_last_error(const ecpic_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->c.err.c_str();
+}
+
+ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* stream,
+                          ecpic_ctx** out) {
+  if (!g || !out) return ECPIC_EINVAL;
+  *out = nullptr;
+  if (g->nr < 1 || g->nz < 1 || !(g->R > 0) || !(g->L > 0) || !(g->dt > 0) || !(g->eps > 0) ||
+      !(g->mu > 0) || !(g->xi_axis >= 0) || g->xi_axis > g->nr || g->n_drive < 0 ||
+      g->n_drive > 2 || (prec != ECPIC_FP64 && prec != ECPIC_MIXED) ||
+      (int64_t)g->nr * g->nz > (int64_t)1 << 28)
+    return ECPIC_EINVAL;
+  ecpic_ctx* x = new (std::nothrow) ecpic_ctx();
+  if (!x) return ECPIC_ENOMEM;
+  Ctx& c = x->c;
+  c.g = *g;
+  c.prec = prec;
+  c.stream = (hipStream_t)stream;
+  c.m.nr = g->nr;
+  c.m.nz = g->nz;
+  c.m.xi_a = g->xi_axis;
+  c.m.s = g->R / (g->nr + g->xi_axis);
+  c.m.inv_s = 1.0 / c.m.s;
+  c.m.rsqrt_xa = g->xi_axis > 0 ? 1.0 / std::sqrt(g->xi_axis) : 0.0;
+  c.m.dz = g->L / g->nz;
+  c.m.inv_dz = 1.0 / c.m.dz;
+  c.m.dt = g->dt;
+  const int64_t nur = n_edges_r(c), nuz = n_edges_z(c), nh = n_cells(c);
+  bool ok = true;
+  auto A = [&](double** p, int64_t n) { ok = ok && dalloc(p, (size_t)n) == hipSuccess; };
+  A(&c.ur, nur); A(&c.uz, nuz); A(&c.h, nh); A(&c.ur_prev, nur); A(&c.uz_prev, nuz);
+  A(&c.ur_it, nur); A(&c.uz_it, nuz); A(&c.h_it, nh);
+  A(&c.ur_nx, nur); A(&c.uz_nx, nuz); A(&c.h_nx, nh);
+  A(&c.ur_half, nur); A(&c.uz_half, nuz); A(&c.Ir, nur); A(&c.Iz, nuz);
+  A(&c.wall_bot, g->nr + 1); A(&c.wall_top, g->nr + 1); A(&c.wall_side, g->nz + 1);
+  c.ur_half_f = c.uz_half_f = nullptr;
+  if (prec == ECPIC_MIXED) {
+    ok = ok && dalloc(&c.ur_half_f, (size_t)nur) == hipSuccess;
+    ok = ok && dalloc(&c.uz_half_f, (size_t)nuz) == hipSuccess;
+  }
+  ok = ok && dalloc(&c.hist, (size_t)nh + 1) == hipSuccess;
+  ok = ok && dalloc(&c.offs, (size_t)nh + 1) == hipSuccess;
+  ok = ok && dalloc(&c.scan_part, (size_t)(nh + 1023) / 1024 + 2) == hipSuccess;
+  ok = ok && dalloc(&c.tally, 1) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c.tally_host, sizeof(Tally)) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c.red_host, 64 * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    ecpic_destroy(x);
+    return ECPIC_ENOMEM;
+  }
+  if (setup_solver(c) != hipSuccess) {
+    ecpic_destroy(x);
+    return ECPIC_EHIP;
+  }
+  double* zs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.ur_it, c.uz_it, c.h_it,
+                  c.ur_half, c.uz_half, c.Ir, c.Iz};
+  int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz};
+  for (int k = 0; k < 12; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
+  (void)launch_zero(c.wall_bot, g->nr + 1, c.stream);
+  (void)launch_zero(c.wall_top, g->nr + 1, c.stream);
+  (void)launch_zero(c.wall_side, g->nz + 1, c.stream);
+  if (hipStreamSynchronize(c.stream) != hipSuccess) {
+    ecpic_destroy(x);
+    return ECPIC_EHIP;
+  }
+  *out = x;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_destroy(ecpic_ctx* x) {
+  if (!x) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  (void)hipStreamSynchronize(c.stream);
+  for (Species& s : c.sp) {
+    free_species_buf(s.d[0]);
+    free_species_buf(s.d[1]);
+  }
+  double* fs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.ur_it, c.uz_it, c.h_it, c.ur_nx,
+                  c.uz_nx, c.h_nx, c.ur_half, c.uz_half, c.Ir, c.Iz, c.wall_bot, c.wall_top,
+                  c.wall_side, c.sol.rh, c.sol.wr, c.sol.wz, c.sol.area, c.sol.Q, c.sol.Qt,
+                  c.sol.tri_lo, c.sol.tri_inv, c.sol.tri_up, c.sol.work0, c.sol.work1,
+                  c.sol.partial};
+  for (double* p : fs) (void)hipFree(p);
+  (void)hipFree(c.ur_half_f);
+  (void)hipFree(c.uz_half_f);
+  (void)hipFree(c.hist);
+  (void)hipFree(c.offs);
+  (void)hipFree(c.scan_part);
+  (void)hipFree(c.tally);
+  (void)hipFree(c.nn_w);
+  (void)hipFree(c.nn_ws);
+  if (c.tally_host) (void)hipHostFree(c.tally_host);
+  if (c.red_host) (void)hipHostFree(c.red_host);
+  delete x;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_add_species(ecpic_ctx* x, const ecpic_species_desc* d, int32_t* sid) {
+  if (!x || !d || !sid) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  if ((int)c.sp.size() >= kMaxSpecies) return fail(c, ECPIC_EINVAL, "at most 4 species");
+  if (d->capacity < 0 || d->capacity > ((int64_t)1 << 31) - 1 || !(d->m > 0) || !(d->weight > 0))
+    return fail(c, ECPIC_EINVAL, "bad species descriptor");
+  Species s;
+  s.desc = *d;
+  if (alloc_species_buf(c, s.d[0], d->capacity) != hipSuccess ||
+      alloc_species_buf(c, s.d[1], d->capacity) != hipSuccess) {
+    free_species_buf(s.d[0]);
+    free_species_buf(s.d[1]);
+    return fail(c, ECPIC_ENOMEM, "species allocation failed");
+  }
+  s.n = 0;
+  c.sp.push_back(s);
+  *sid = (int32_t)c.sp.size() - 1;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_load_particles(ecpic_ctx* x, int32_t sid, const double* r, const double* z,
+                                  const double* vr, const double* vt, const double* vz,
+                                  const uint64_t* uid, int64_t n) {
+  if (!x) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  if (sid < 0 || sid >= (int)c.sp.size()) return fail(c, ECPIC_EINVAL, "bad species id");
+  Species& s = c.sp[sid];
+  if (n < 0 || n > s.desc.capacity) return fail(c, ECPIC_EINVAL, "n exceeds capacity");
+  if (n > 0 && (!r || !z || !vr || !vt || !vz || !uid))
+    return fail(c, ECPIC_EINVAL, "null particle array");
+  HIPCHK(launch_load(c.m, view(s), r, z, vr, vt, vz, uid, n, c.g.R, c.prec == ECPIC_MIXED,
+                     c.stream));
+  s.n = n;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_read_particles(ecpic_ctx* x, int32_t sid, double* xi, double* eta, double* vr,
+                                  double* vt, double* vz, uint64_t* uid, int64_t cap,
+                                  int64_t* n_out) {
+  if (!x || !n_out) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  if (sid < 0 || sid >= (int)c.sp.size()) return fail(c, ECPIC_EINVAL, "bad species id");
+  Species& s = c.sp[sid];
+  *n_out = 0;
+  if (s.n == 0) return ECPIC_OK;
+  const int64_t nb = (s.n + kBlock - 1) / kBlock;
+  int32_t *blk = nullptr, *part = nullptr;
+  HIPCHK(hipMalloc((void**)&blk, sizeof(int32_t) * (nb + 1)));
+  HIPCHK(hipMalloc((void**)&part, sizeof(int32_t) * ((nb + 1023) / 1024 + 2)));
+  const int mixed = c.prec == ECPIC_MIXED;
+  ecpic_status rc = ECPIC_OK;
+  hipError_t e = launch_flag_count(c.m, view(s), s.n, mixed, blk, c.stream);
+  if (e == hipSuccess) e = scan_exclusive(blk, nb, part, c.stream);
+  int32_t total = 0;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&total, blk + nb, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  if (e == hipSuccess) {
+    if (total > cap || !xi || !eta || !vr || !vt || !vz || !uid) {
+      rc = fail(c, ECPIC_EINVAL, "output capacity too small or null output");
+    } else {
+      e = launch_compact_read(c.m, view(s), s.n, mixed, blk, xi, eta, vr, vt, vz, uid, c.stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    }
+  }
+  (void)hipFree(blk);
+  (void)hipFree(part);
+  if (e != hipSuccess) return fail(c, ECPIC_EHIP, hipGetErrorString(e));
+  *n_out = total;
+  return rc;
+}
+
+ecpic_status ecpic_set_fields(ecpic_ctx* x, const double* ur, const double* uz, const double* h,
+                              const double* ur_prev, const double* uz_prev, double t,
+                              int64_t step) {
+  if (!x || !ur || !uz || !h) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  const int64_t nur = n_edges_r(c), nuz = n_edges_z(c), nh = n_cells(c);
+  HIPCHK(launch_copy(c.ur, ur, nur, c.stream));
+  HIPCHK(launch_copy(c.uz, uz, nuz, c.stream));
+  HIPCHK(launch_copy(c.h, h, nh, c.stream));
+  HIPCHK(launch_copy(c.ur_prev, ur_prev ? ur_prev : ur, nur, c.stream));
+  HIPCHK(launch_copy(c.uz_prev, uz_prev ? uz_prev : uz, nuz, c.stream));
+  c.t = t;
+  c.step = step;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_get_fields(ecpic_ctx* x, double* ur, double* uz, double* h) {
+  if (!x) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  if (ur) HIPCHK(launch_copy(ur, c.ur, n_edges_r(c), c.stream));
+  if (uz) HIPCHK(launch_copy(uz, c.uz, n_edges_z(c), c.stream));
+  if (h) HIPCHK(launch_copy(h, c.h, n_cells(c), c.stream));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_set_half_field(ecpic_ctx* x, const double* urh, const double* uzh) {
+  if (!x || !urh || !uzh) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  // half = (u0 + u1)/2 with u0 = u1 = the given field reproduces it exactly
+  HIPCHK(launch_half(c, urh, uzh, urh, uzh, c.stream));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_push_deposit(ecpic_ctx* x, int32_t commit, double* Ir, double* Iz) {
+  if (!x) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  ecpic_status rc = pass(c, commit ? 1 : 0, false, c.step);
+  if (rc != ECPIC_OK) return rc;
+  if (Ir) HIPCHK(launch_copy(Ir, c.Ir, n_edges_r(c), c.stream));
+  if (Iz) HIPCHK(launch_copy(Iz, c.Iz, n_edges_z(c), c.stream));
+  if (commit) {
+    Tally t;
+    rc = finish_tally(c, t);
+    if (rc == ECPIC_OK && t.n_errors) rc = fail(c, ECPIC_EPUSH, "particle push failed");
+  }
+  return rc;
+}
+
+ecpic_status ecpic_field_solve(ecpic_ctx* x, const double* ur0, const double* uz0, const double* h0,
+                               const double* Ir, const double* Iz, double t, double* ur1,
+                               double* uz1, double* h1) {
+  if (!x || !ur0 || !uz0 || !h0 || !Ir || !Iz || !ur1 || !uz1 || !h1) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  const double vh = 0.5 * (drive(c.g, t) + drive(c.g, t + c.g.dt));
+  HIPCHK(field_solve(c, ur0, uz0, h0, Ir, Iz, vh, drive(c.g, t + c.g.dt), ur1, uz1, h1, c.stream));
+  return ECPIC_OK;
+}
+
+static ecpic_status iterate(Ctx& c, double* r_out) {
+  const double vnext = drive(c.g, c.t + c.g.dt);
+  const double vh = 0.5 * (drive(c.g, c.t) + vnext);
+  HIPCHK(field_solve(c, c.ur, c.uz, c.h, c.Ir, c.Iz, vh, vnext, c.ur_nx, c.uz_nx, c.h_nx,
+                     c.stream));
+  double* d_red = c.sol.partial + 4000;
+  HIPCHK(launch_resid(c, c.ur_nx, c.uz_nx, c.ur_it, c.uz_it, d_red, c.stream));
+  HIPCHK(hipMemcpyAsync(c.red_host, d_red, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  std::swap(c.ur_it, c.ur_nx);
+  std::swap(c.uz_it, c.uz_nx);
+  std::swap(c.h_it, c.h_nx);
+  HIPCHK(hipStreamSynchronize(c.stream));
+  const double num = c.red_host[0], den = c.red_host[1];
+  *r_out = den > 0.0 ? std::sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_field_iterate(ecpic_ctx* x, double* rel) {
+  if (!x || !rel) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  ecpic_status rc = iterate(c, rel);
+  if (rc != ECPIC_OK) return rc;
+  HIPCHK(launch_half(c, c.ur, c.uz, c.ur_it, c.uz_it, c.stream));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_set_mcc(ecpic_ctx* x, const ecpic_mcc_desc* m) {
+  if (!x) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  if (!m || !m->enabled) {
+    std::memset(&c.mcc, 0, sizeof(c.mcc));
+    return ECPIC_OK;
+  }
+  if (m->electron_sid < 0 || m->electron_sid >= (int)c.sp.size() || m->ion_sid < 0 ||
+      m->ion_sid >= (int)c.sp.size() || !(m->n_gas >= 0) || !(m->t_gas > 0) ||
+      !(m->m_gas > 0) || !(m->eps_max_ev > 0))
+    return fail(c, ECPIC_EINVAL, "bad collision descriptor");
+  c.mcc = *m;
+  for (size_t s = 0; s < c.sp.size() && s < (size_t)kMaxSpecies; ++s) {
+    const int role = ((int)s == m->electron_sid) ? 1 : ((int)s == m->ion_sid ? 2 : 0);
+    c.numax[s] = nu_max_host(*m, role, c.sp[s].desc.m);
+  }
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_collide(ecpic_ctx* x, const ecpic_mcc_desc* m, int64_t step) {
+  if (!x || !m) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  ecpic_mcc_desc saved = c.mcc;
+  ecpic_status rc = ecpic_set_mcc(x, m);
+  if (rc != ECPIC_OK) return rc;
+  HIPCHK(hipMemsetAsync(c.tally, 0, sizeof(Tally), c.stream));
+  std::vector<MccDev> d(c.sp.size());
+  for (size_t s = 0; s < c.sp.size(); ++s) d[s] = make_mcc(c, (int)s, step);
+  for (size_t s = 0; s < c.sp.size(); ++s) {
+    if (!d[s].enabled) continue;
+    SpecDev v = view(c.sp[s]);
+    v.sid = (int)s;
+    HIPCHK(launch_collide(c.m, v, d[s], c.tally, c.prec == ECPIC_MIXED, c.stream));
+  }
+  c.mcc = saved;
+  Tally t;
+  rc = finish_tally(c, t);
+  return rc;
+}
+
+ecpic_status ecpic_sort(ecpic_ctx* x) {
+  if (!x) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  for (Species& s : c.sp) HIPCHK(launch_sort(c, s, c.stream, nullptr));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_node_charge(ecpic_ctx* x, double* q, double* bot, double* top, double* side) {
+  if (!x) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  if (q) HIPCHK(launch_node_charge(c, q, c.stream));
+  if (bot) HIPCHK(launch_copy(bot, c.wall_bot, c.g.nr + 1, c.stream));
+  if (top) HIPCHK(launch_copy(top, c.wall_top, c.g.nr + 1, c.stream));
+  if (side) HIPCHK(launch_copy(side, c.wall_side, c.g.nz + 1, c.stream));
+  return ECPIC_OK;
+}
+
+static ecpic_status diag_into(Ctx& c, ecpic_step_stats* st) {
+  double* d = c.sol.partial + 4000;
+  HIPCHK(launch_zero(d + 8, 8, c.stream));
+  for (size_t s = 0; s < c.sp.size() && s < 4; ++s)
+    HIPCHK(launch_kinetic(c.sp[s], c.prec == ECPIC_MIXED, d + 8 + s, c.stream));
+  HIPCHK(launch_field_energy(c, c.ur, c.uz, c.h, d + 2, c.stream));
+  HIPCHK(hipMemcpyAsync(c.red_host, d, 16 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  st->we = 0.5 * c.red_host[2];
+  st->wb = 0.5 * c.g.mu * c.red_host[3];
+  for (size_t s = 0; s < 4; ++s) st->ke[s] = (s < c.sp.size()) ? c.red_host[8 + s] : 0.0;
+  for (size_t s = 0; s < c.sp.size() && s < 4; ++s) st->n_alive[s] = c.sp[s].n;
+  st->t = c.t;
+  st->step = c.step;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_diagnostics(ecpic_ctx* x, ecpic_step_stats* st) {
+  if (!x || !st) return ECPIC_EINVAL;
+  std::memset(st, 0, sizeof(*st));
+  return diag_into(x->c, st);
+}
+
+ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats* st) {
+  if (!x || !o) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  ecpic_step_stats local;
+  ecpic_step_stats* S = st ? st : &local;
+  std::memset(S, 0, sizeof(*S));
+  int kmax = o->fixed_iter > 0 ? o->fixed_iter : o->max_iter;
+  if (kmax < 1 || kmax > 64) return fail(c, ECPIC_EINVAL, "iterations must be in 1..64");
+  const double vnow = drive(c.g, c.t), vnext = drive(c.g, c.t + c.g.dt);
+  HIPCHK(launch_guess_half(c, vnow, vnext, c.stream));
+  if (o->use_nn) {
+    bool used = false;
+    ecpic_status rc = nn_guess(c, &used);
+    if (rc != ECPIC_OK) return rc;
+    S->used_nn = used ? 1 : 0;
+  }
+  int k = 0;
+  bool conv = false;
+  double prev_r = INFINITY;
+  for (k = 0; k < kmax; ++k) {
+    ecpic_status rc = pass(c, 0, false, c.step);
+    if (rc != ECPIC_OK) return rc;
+    double r;
+    rc = iterate(c, &r);
+    if (rc != ECPIC_OK) return rc;
+    S->residual[k] = r;
+    if (o->fixed_iter <= 0 && r <= o->tol) {
+      conv = true;
+      ++k;
+      break;
+    }
+    prev_r = r;
+    if (k + 1 < kmax) HIPCHK(launch_half(c, c.ur, c.uz, c.ur_it, c.uz_it, c.stream));
+  }
+  (void)prev_r;
+  S->iters = k;
+  if (o->fixed_iter > 0) conv = true;
+  S->converged = conv ? 1 : 0;
+  if (!conv) return fail(c, ECPIC_ENOTCONV, "Picard iteration did not converge");
+  // commit the particles pushed in the accepted half-step field, with MCC
+  ecpic_status rc = pass(c, 1, c.mcc.enabled != 0, c.step);
+  if (rc != ECPIC_OK) return rc;
+  double* d = c.sol.partial + 4000;
+  HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir, c.Iz, d + 4, c.stream));
+  const int nr = c.g.nr, nz = c.g.nz;
+  HIPCHK(hipMemcpyAsync(c.red_host + 32, d + 4, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipMemcpyAsync(c.red_host + 33, c.h + (int64_t)(nr - 1) * nz, sizeof(double),
+                        hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipMemcpyAsync(c.red_host + 34, c.h_it + (int64_t)(nr - 1) * nz, sizeof(double),
+                        hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipMemcpyAsync(c.red_host + 35, c.Ir + (int64_t)(nr - 1) * (nz + 1), sizeof(double),
+                        hipMemcpyDeviceToHost, c.stream));
+  Tally t;
+  rc = finish_tally(c, t);  // synchronises
+  const double vh = 0.5 * (vnow + vnext);
+  const double rgap = r_of_xi(c.m, nr - 0.5);
+  S->w_field_io = c.g.dt * c.red_host[32];
+  S->w_drive = c.g.dt * (2.0 * kPi * rgap * 0.5 * (c.red_host[33] + c.red_host[34]) * vh +
+                         vh * c.red_host[35]);
+  S->w_particles = t.w_particles;
+  S->w_absorbed = t.w_absorbed;
+  S->w_coll = t.w_coll;
+  for (size_t s = 0; s < c.sp.size() && s < 4; ++s) {
+    S->n_absorbed[s] = (int64_t)t.n_absorbed[s];
+    S->n_coll[s] = (int64_t)t.n_coll[s];
+  }
+  S->n_ionized = (int64_t)t.n_ionized;
+  S->n_substeps = (int64_t)t.n_substeps;
+  S->n_crossings = (int64_t)t.n_crossings;
+  S->n_errors = (int64_t)t.n_errors;
+  S->n_over_range = (int64_t)t.n_over_range;
+  // field shift: u^{n-1} <- u^n, u^n <- u^{n+1}
+  std::swap(c.ur_prev, c.ur);
+  std::swap(c.uz_prev, c.uz);
+  std::swap(c.ur, c.ur_it);
+  std::swap(c.uz, c.uz_it);
+  std::swap(c.h, c.h_it);
+  c.t += c.g.dt;
+  c.step += 1;
+  if (o->sort_every > 0 && c.step % o->sort_every == 0) {
+    for (Species& s : c.sp) HIPCHK(launch_sort(c, s, c.stream, nullptr));
+  }
+  if (st) {
+    ecpic_status r2 = diag_into(c, S);
+    if (r2 != ECPIC_OK) return r2;
+  }
+  if (rc == ECPIC_OK && t.n_errors) rc = fail(c, ECPIC_EPUSH, "particle push failed");
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,1046 @@
+// ecpic_push.hip -- implicit mid-point particle push split at cell-face
+// crossings (Eq. (4) of Sec. 2.1 with mid-point centring), the
+// charge-conserving current deposit (Eq. (3) with spline order 1,
+// orbit-averaged per sub-step), wall absorption, and the null-collision
+// Monte Carlo step (Sec. 2.1), for gfx950.
+//
+// One thread per particle.  Particles are kept sorted by cell, so the four
+// field values a thread gathers are shared by its neighbours (L1/L2 hits) and
+// the four face currents of a sub-step are mostly the same faces for a whole
+// wavefront: the first sub-step's currents are combined by a segmented
+// wavefront reduction keyed by cell before one lane per run issues the
+// global FP64 atomics; later sub-steps (cell crossers) use direct atomics.
+//
+// The same template serves the FP64 path (T = double, positions stored as
+// global xi, eta) and the mixed path (T = float, positions stored as int32
+// cell + FP32 offsets); current increments are always formed and
+// accumulated in FP64.
+#include "ecpic_internal.h"
+
+namespace ecpic {
+
+namespace {
+
+constexpr double kQE = 1.602176634e-19;  // elementary charge [C]
+
+template <typename T>
+struct Tol;
+template <>
+struct Tol<double> {
+  static __device__ __forceinline__ double v() { return 1e-14; }
+};
+template <>
+struct Tol<float> {
+  static __device__ __forceinline__ float v() { return 4e-7f; }
+};
+
+// particle state relative to its cell: offsets a = xi - i, b = eta - j in [0,1]
+template <typename T>
+struct PState {
+  int i, j;
+  T a, b, vr, vt, vz;
+};
+
+template <typename T>
+struct Mid {
+  T a, b, vr, vt, vz;  // mid-point offsets (cell-local) and mid velocities
+};
+
+template <typename T>
+__device__ __forceinline__ T clamp01(T x) {
+  return x < T(0) ? T(0) : (x > T(1) ? T(1) : x);
+}
+
+// r and 1/J_r at cell-local offset a of radial cell i.
+template <typename T>
+__device__ __forceinline__ void map_r(const MapP& m, int i, T a, T& r, T& ijr) {
+  if (double(i) + double(a) < m.xi_a) {
+    const T xi = T(i) + a;
+    r = T(2.0 * m.s) * sqrt(xi * T(m.xi_a));
+    ijr = sqrt(xi / T(m.xi_a)) * T(m.inv_s);
+  } else {
+    r = T(m.s * (double(i) + m.xi_a)) + T(m.s) * a;
+    ijr = T(m.inv_s);
+  }
+}
+
+// Position equation of the mid-point rule in xi, solved exactly for the
+// mid offset: linear part of the map, or the square-root part as a quadratic
+// in sqrt(xi_bar) (positive root), whichever is consistent.
+template <typename T>
+__device__ __forceinline__ bool mid_a(const MapP& m, int i, T a, T vbr, T dtau, T& abar) {
+  const T al = a + T(0.5) * dtau * vbr * T(m.inv_s);
+  if (m.xi_a <= 0.0) {
+    abar = al;
+    return T(i) + al >= T(0);
+  }
+  if (T(i) + al >= T(m.xi_a)) {
+    abar = al;
+    return true;
+  }
+  const T xi = T(i) + a;
+  const T beta = T(0.5) * dtau * vbr * T(m.inv_s * m.rsqrt_xa);
+  const T y = T(0.5) * (beta + sqrt(beta * beta + T(4) * xi));
+  abar = y * y - T(i);
+  return true;
+}
+
+// Mid-point acceleration with the theta mid velocity from the angular
+// equation vb_t (1 + dtau vb_r / (2 rb)) = v_t.  F = {ur[i][j], ur[i][j+1],
+// uz[i][j], uz[i+1][j]} of the half-step field.
+template <typename T>
+__device__ __forceinline__ bool accel(const MapP& m, const T F[4], int i, T abar, T bbar, T vbr,
+                                      T vt0, T dtau, T qm, T& ar, T& az, T& vtb) {
+  T rb, ijr;
+  map_r(m, i, abar, rb, ijr);
+  const T ac = clamp01(abar), bc = clamp01(bbar);
+  const T er = ((T(1) - bc) * F[0] + bc * F[1]) * ijr;
+  const T ez = ((T(1) - ac) * F[2] + ac * F[3]) * T(m.inv_dz);
+  if (rb > T(0)) {
+    const T den = T(1) + T(0.5) * dtau * vbr / rb;
+    if (!(den > T(0))) return false;
+    vtb = vt0 / den;
+    ar = qm * er + vtb * vtb / rb;
+  } else {
+    if (vt0 != T(0)) return false;
+    vtb = T(0);
+    ar = qm * er;
+  }
+  az = qm * ez;
+  return isfinite(ar) && isfinite(az) && isfinite(vtb);
+}
+
+// Unconstrained sub-step of length dtau in the particle's cell: fixed point
+// on the mid velocities, mid positions solved exactly from them.
+template <typename T>
+__device__ bool solve_free(const MapP& m, const T F[4], const PState<T>& p, T dtau, T qm,
+                           Mid<T>& M) {
+  T vr = p.vr, vt = p.vt, vz = p.vz;
+  const T hd = T(0.5) * dtau;
+  const T idz = T(m.inv_dz);
+  for (int it = 0; it < kMaxFixed; ++it) {
+    T abar;
+    if (!mid_a(m, p.i, p.a, vr, dtau, abar)) return false;
+    const T bbar = p.b + hd * vz * idz;
+    if (!isfinite(bbar)) return false;
+    T ar, az, vtb;
+    if (!accel(m, F, p.i, abar, bbar, vr, p.vt, dtau, qm, ar, az, vtb)) return false;
+    const T nvr = p.vr + hd * ar, nvz = p.vz + hd * az, nvt = vtb;
+    const T scale = fabs(nvr) + fabs(nvt) + fabs(nvz);
+    const T d = fmax(fabs(nvr - vr), fmax(fabs(nvt - vt), fabs(nvz - vz)));
+    vr = nvr;
+    vt = nvt;
+    vz = nvz;
+    if (d <= Tol<T>::v() * scale) {
+      if (!mid_a(m, p.i, p.a, vr, dtau, M.a)) return false;
+      M.b = p.b + hd * vz * idz;
+      M.vr = vr;
+      M.vt = vt;
+      M.vz = vz;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Smallest positive root of (a/2) t^2 + v t - D = 0 in cancellation-free
+// form, or +inf.
+template <typename T>
+__device__ __forceinline__ T smallest_pos_root(T a, T v, T D) {
+  const T A = T(0.5) * a, B = v, C = -D;
+  T best = T(INFINITY);
+  if (A == T(0)) {
+    if (B != T(0)) {
+      const T t = -C / B;
+      if (t > T(0)) best = t;
+    }
+    return best;
+  }
+  const T disc = B * B - T(4) * A * C;
+  if (disc < T(0)) return best;
+  const T sq = sqrt(disc);
+  const T q = T(-0.5) * (B + (B >= T(0) ? sq : -sq));
+  if (q != T(0)) {
+    const T t1 = q / A, t2 = C / q;
+    if (t1 > T(0) && t1 < best) best = t1;
+    if (t2 > T(0) && t2 < best) best = t2;
+  }
+  return best;
+}
+
+// Sub-step that ends exactly on the local face f (0 or 1) of axis d (0: xi,
+// 1: eta): the crossed coordinate's mid value is (x + f)/2 and the length
+// solves the position equation as a quadratic given the mid acceleration.
+template <typename T>
+__device__ bool solve_cross(const MapP& m, const T F[4], const PState<T>& p, int d, T f, T dmax,
+                            T dt0, const Mid<T>& M0, T qm, T& dtau_out, Mid<T>& M, bool& capped) {
+  const T xd = d == 0 ? p.a : p.b;
+  const T xbar = T(0.5) * (xd + f);
+  T Jd;
+  if (d == 0) {
+    T rb, ijr;
+    map_r(m, p.i, xbar, rb, ijr);
+    Jd = T(1) / ijr;
+  } else {
+    Jd = T(m.dz);
+  }
+  const T D = (f == xd) ? T(0) : (f - xd) * Jd;
+  const T v0d = d == 0 ? p.vr : p.vz;
+  capped = false;
+  if (D == T(0)) {
+    if (f == T(0) ? (v0d < T(0)) : (v0d > T(0))) {
+      dtau_out = T(0);
+      M.a = p.a;
+      M.b = p.b;
+      M.vr = p.vr;
+      M.vt = p.vt;
+      M.vz = p.vz;
+      return true;
+    }
+  }
+  T vr = M0.vr, vt = M0.vt, vz = M0.vz;
+  T dtau = dt0;
+  const T idz = T(m.inv_dz);
+  for (int it = 0; it < kMaxFixed; ++it) {
+    T abar, bbar;
+    if (d == 0) {
+      abar = xbar;
+      bbar = p.b + T(0.5) * dtau * vz * idz;
+    } else {
+      bbar = xbar;
+      if (!mid_a(m, p.i, p.a, vr, dtau, abar)) return false;
+    }
+    if (!isfinite(bbar)) return false;
+    T ar, az, vtb;
+    if (!accel(m, F, p.i, abar, bbar, vr, p.vt, dtau, qm, ar, az, vtb)) return false;
+    T nd = smallest_pos_root(d == 0 ? ar : az, v0d, D);
+    bool cap = false;
+    if (!(nd <= dmax)) {
+      nd = dmax;
+      cap = true;
+    }
+    const T nvr = p.vr + T(0.5) * nd * ar, nvz = p.vz + T(0.5) * nd * az, nvt = vtb;
+    const T scale = fabs(nvr) + fabs(nvt) + fabs(nvz);
+    const T dv = fmax(fabs(nvr - vr), fmax(fabs(nvt - vt), fabs(nvz - vz)));
+    const T ddt = fabs(nd - dtau);
+    vr = nvr;
+    vt = nvt;
+    vz = nvz;
+    dtau = nd;
+    if (dv <= Tol<T>::v() * scale && ddt <= Tol<T>::v() * dmax) {
+      capped = cap;
+      dtau_out = dtau;
+      if (d == 0) {
+        M.a = xbar;
+        M.b = p.b + T(0.5) * dtau * vz * idz;
+      } else {
+        M.b = xbar;
+        if (!mid_a(m, p.i, p.a, vr, dtau, M.a)) return false;
+      }
+      M.vr = vr;
+      M.vt = vt;
+      M.vz = vz;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Face currents of one straight logical sub-step inside cell (i, j):
+// Eq. (3) with m = 1 integrated along the sub-step.
+struct Dep {
+  double r0, r1, z0, z1;  // ur[i][j], ur[i][j+1], uz[i][j], uz[i+1][j] increments
+};
+
+__device__ __forceinline__ Dep make_dep(double a0, double b0, double a1, double b1, double c) {
+  const double dx = a1 - a0, de = b1 - b0;
+  const double xm = 0.5 * (a0 + a1), em = 0.5 * (b0 + b1);
+  Dep d;
+  d.r0 = c * dx * (1.0 - em);
+  d.r1 = c * dx * em;
+  d.z0 = c * de * (1.0 - xm);
+  d.z1 = c * de * xm;
+  return d;
+}
+
+__device__ __forceinline__ void atomic_dep(double* Ir, double* Iz, int nz, int i, int j,
+                                           const Dep& d) {
+  double* pr = Ir + (size_t)i * (nz + 1) + j;
+  unsafeAtomicAdd(pr, d.r0);
+  unsafeAtomicAdd(pr + 1, d.r1);
+  unsafeAtomicAdd(Iz + (size_t)i * nz + j, d.z0);
+  unsafeAtomicAdd(Iz + (size_t)(i + 1) * nz + j, d.z1);
+}
+
+enum { kAlive = 0, kAbsorbed = 1, kError = 2 };
+
+struct PushOut {
+  int status;
+  int wall;           // 1 bottom, 2 top, 3 side
+  int nsub, ncross;
+  bool have_first;    // first sub-step deposit held for the wave reduction
+  int fi, fj;         // its cell
+  Dep first;
+  double work;        // sum of q w E.dx over sub-steps (in units of J)
+};
+
+template <typename T>
+__device__ __forceinline__ void load_field(const MapP& m, const T* __restrict__ ur,
+                                           const T* __restrict__ uz, int i, int j, T F[4]) {
+  const T* pr = ur + (size_t)i * (m.nz + 1) + j;
+  F[0] = pr[0];
+  F[1] = pr[1];
+  F[2] = uz[(size_t)i * m.nz + j];
+  F[3] = uz[(size_t)(i + 1) * m.nz + j];
+}
+
+// Push one particle over dt.  The first sub-step's deposit is returned in
+// `out.first` (for the caller's wavefront reduction); later ones go to
+// global atomics directly.
+template <typename T>
+__device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* __restrict__ uz,
+                              double* Ir, double* Iz, PState<T>& p, T qm, double qw_dt,
+                              bool want_work, PushOut& out) {
+  out.status = kAlive;
+  out.wall = 0;
+  out.nsub = 0;
+  out.ncross = 0;
+  out.have_first = false;
+  out.work = 0.0;
+  const int nr = m.nr, nz = m.nz;
+  T tau = T(m.dt);
+  while (tau > T(0)) {
+    if (out.nsub >= kMaxSub) {
+      out.status = kError;
+      return;
+    }
+    out.nsub++;
+    // on a face, the cell the motion goes to
+    if (p.a == T(1) && p.vr >= T(0) && p.i < nr - 1) {
+      p.i += 1;
+      p.a = T(0);
+    } else if (p.a == T(0) && p.vr < T(0) && p.i > 0) {
+      p.i -= 1;
+      p.a = T(1);
+    }
+    if (p.b == T(1) && p.vz >= T(0) && p.j < nz - 1) {
+      p.j += 1;
+      p.b = T(0);
+    } else if (p.b == T(0) && p.vz < T(0) && p.j > 0) {
+      p.j -= 1;
+      p.b = T(1);
+    }
+    T F[4];
+    load_field(m, ur, uz, p.i, p.j, F);
+    T dtry = tau;
+    Mid<T> M;
+    bool ok = false;
+    for (int h = 0; h <= kMaxHalve; ++h) {
+      ok = solve_free(m, F, p, dtry, qm, M);
+      if (ok) break;
+      dtry *= T(0.5);
+    }
+    if (!ok) {
+      out.status = kError;
+      return;
+    }
+    const T ea = T(2) * M.a - p.a, eb = T(2) * M.b - p.b;
+    const bool in_x = ea >= T(0) && ea <= T(1);
+    const bool in_e = eb >= T(0) && eb <= T(1);
+    PState<T> q;
+    q.i = p.i;
+    q.j = p.j;
+    T used;
+    int cd = -1;
+    T cf = T(0);
+    if (in_x && in_e) {
+      q.a = ea;
+      q.b = eb;
+      q.vr = T(2) * M.vr - p.vr;
+      q.vt = T(2) * M.vt - p.vt;
+      q.vz = T(2) * M.vz - p.vz;
+      used = dtry;
+    } else {
+      T best_t = T(0);
+      Mid<T> BM;
+      for (int d = 0; d < 2; ++d) {
+        T f, xd, xe;
+        if (d == 0) {
+          if (in_x) continue;
+          f = ea < T(0) ? T(0) : T(1);
+          xd = p.a;
+          xe = ea;
+        } else {
+          if (in_e) continue;
+          f = eb < T(0) ? T(0) : T(1);
+          xd = p.b;
+          xe = eb;
+        }
+        const T t0 = dtry * (f - xd) / (xe - xd);
+        T tt;
+        Mid<T> CM;
+        bool cap;
+        if (!solve_cross(m, F, p, d, f, dtry, t0, M, qm, tt, CM, cap)) continue;
+        if (cd < 0 || tt < best_t - T(1e-15 * m.dt)) {
+          best_t = tt;
+          cd = d;
+          cf = f;
+          BM = CM;
+        }
+      }
+      if (cd < 0) {
+        out.status = kError;
+        return;
+      }
+      out.ncross++;
+      q.vr = T(2) * BM.vr - p.vr;
+      q.vt = T(2) * BM.vt - p.vt;
+      q.vz = T(2) * BM.vz - p.vz;
+      if (cd == 0) {
+        q.a = cf;
+        q.b = clamp01(T(2) * BM.b - p.b);
+      } else {
+        q.b = cf;
+        q.a = clamp01(T(2) * BM.a - p.a);
+      }
+      used = best_t;
+    }
+    const Dep dp = make_dep(double(p.a), double(p.b), double(q.a), double(q.b), qw_dt);
+    if (want_work) {
+      out.work += m.dt * (dp.r0 * double(F[0]) + dp.r1 * double(F[1]) + dp.z0 * double(F[2]) +
+                          dp.z1 * double(F[3]));
+    }
+    if (!out.have_first && out.nsub == 1) {
+      out.have_first = true;
+      out.fi = p.i;
+      out.fj = p.j;
+      out.first = dp;
+    } else {
+      atomic_dep(Ir, Iz, nz, p.i, p.j, dp);
+    }
+    p = q;
+    tau -= used;
+    if (cd == 0 && cf == T(1) && p.i == nr - 1) {
+      out.status = kAbsorbed;
+      out.wall = 3;
+      return;
+    }
+    if (cd == 1 && cf == T(0) && p.j == 0) {
+      out.status = kAbsorbed;
+      out.wall = 1;
+      return;
+    }
+    if (cd == 1 && cf == T(1) && p.j == nz - 1) {
+      out.status = kAbsorbed;
+      out.wall = 2;
+      return;
+    }
+    if (cd == 0 && cf == T(0) && p.i == 0) p.vr = -p.vr;  // axis: mirror
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront segmented reduction of the first sub-step deposits (keyed by
+// cell) and one atomic per run of equal keys.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double shfl_up_d(double v, int off) {
+  return __shfl_up(v, off, 64);
+}
+
+__device__ void wave_deposit(double* Ir, double* Iz, int nz, int key, int i, int j, Dep d) {
+  const int lane = threadIdx.x & 63;
+  const int prev_key = __shfl_up(key, 1, 64);
+  const bool head = (lane == 0) || (prev_key != key);
+  // start lane of my run: inclusive max-scan of head ? lane : 0
+  int start = head ? lane : 0;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(start, off, 64);
+    if (lane >= off && o > start) start = o;
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double r0 = shfl_up_d(d.r0, off), r1 = shfl_up_d(d.r1, off);
+    const double z0 = shfl_up_d(d.z0, off), z1 = shfl_up_d(d.z1, off);
+    if (lane - off >= start) {
+      d.r0 += r0;
+      d.r1 += r1;
+      d.z0 += z0;
+      d.z1 += z1;
+    }
+  }
+  const int next_key = __shfl_down(key, 1, 64);
+  const bool tail = (lane == 63) || (next_key != key);
+  if (tail && key >= 0) atomic_dep(Ir, Iz, nz, i, j, d);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11) and the null-collision step
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B97F4A7C15ull;
+      k1 += 0xBB67AE8584CAA73Bull;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t y0 = hi1 ^ c[1] ^ k0, y2 = hi0 ^ c[3] ^ k1;
+    c[0] = y0;
+    c[1] = lo1;
+    c[2] = y2;
+    c[3] = lo0;
+  }
+}
+
+__device__ __forceinline__ void draws(uint64_t seed, int sid, uint64_t uid, int64_t step, int blk,
+                                      double u[4]) {
+  uint64_t c[4] = {uid, (uint64_t)step, (uint64_t)blk, 0ull};
+  philox(c, seed, (uint64_t)sid);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) u[k] = double(c[k] >> 11) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ uint64_t child_uid(uint64_t parent, int64_t step) {
+  // SplitMix64 finaliser of a Weyl-shifted parent id, top bit set
+  uint64_t z = parent + 0x9E3779B97F4A7C15ull * (uint64_t)(step + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return (z ^ (z >> 31)) | 0x8000000000000000ull;
+}
+
+// synthetic argon cross-sections [m^2]
+__host__ __device__ __forceinline__ void xsec(double e, double& el, double& ex, double& iz) {
+  el = 1.0e-19;
+  ex = (e > 11.5) ? 1.0e-20 * (1.0 - 11.5 / e) : 0.0;
+  if (e > 15.76) {
+    const double x = e / 15.76;
+    iz = 8.0e-20 * log(x) / x;
+  } else {
+    iz = 0.0;
+  }
+}
+
+__device__ __forceinline__ void iso(double u1, double u2, double d[3]) {
+  const double ct = 1.0 - 2.0 * u1;
+  const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+  const double ph = 2.0 * M_PI * u2;
+  d[0] = st * cos(ph);
+  d[1] = st * sin(ph);
+  d[2] = ct;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_slot(const SpecDev& s, const MapP& m, int64_t k, int i, int j,
+                                           T a, T b, double vr, double vt, double vz,
+                                           uint64_t uid);
+
+template <>
+__device__ __forceinline__ void store_slot<double>(const SpecDev& s, const MapP& m, int64_t k,
+                                                   int i, int j, double a, double b, double vr,
+                                                   double vt, double vz, uint64_t uid) {
+  s.xi[k] = double(i) + a;
+  s.eta[k] = double(j) + b;
+  s.vr[k] = vr;
+  s.vt[k] = vt;
+  s.vz[k] = vz;
+  s.uid[k] = uid;
+}
+
+template <>
+__device__ __forceinline__ void store_slot<float>(const SpecDev& s, const MapP& m, int64_t k, int i,
+                                                  int j, float a, float b, double vr, double vt,
+                                                  double vz, uint64_t uid) {
+  s.cell[k] = i * m.nz + j;
+  s.fa[k] = a;
+  s.fb[k] = b;
+  s.fvr[k] = float(vr);
+  s.fvt[k] = float(vt);
+  s.fvz[k] = float(vz);
+  s.uid[k] = uid;
+}
+
+struct CollOut {
+  double dke;    // kinetic energy lost (J)
+  int coll;      // 1 if a real collision happened
+  int ionized;
+  int over;
+  int overflow;
+};
+
+// Null-collision Monte Carlo for one particle with velocity (vr, vt, vz),
+// updated in place.  Ionisation appends an electron to the own species and
+// an ion to the partner species at the parent's position.
+template <typename T>
+__device__ CollOut collide_one(const MccDev& c, const SpecDev& s, const MapP& m, int sid,
+                               uint64_t uid, int i, int j, T a, T b, double& vr, double& vt,
+                               double& vz, Tally* tally) {
+  CollOut o = {0.0, 0, 0, 0, 0};
+  double u[4];
+  draws(c.seed, sid, uid, c.step, 0, u);
+  if (!(u[0] < c.pnull)) return o;
+  const double v2 = vr * vr + vt * vt + vz * vz;
+  const double v = sqrt(v2);
+  const double ke0 = 0.5 * s.m * s.w * v2;
+  if (c.role == 1) {
+    const double e = 0.5 * s.m * v2 / kQE;
+    if (e > c.eps_max_ev) o.over = 1;
+    double sel, sex, siz;
+    xsec(e, sel, sex, siz);
+    const double nel = c.n_gas * sel * v, nex = c.n_gas * sex * v, niz = c.n_gas * siz * v;
+    const double x = u[1] * c.numax;
+    double d[3];
+    iso(u[2], u[3], d);
+    if (x < nel) {
+      const double cosx = (v > 0.0) ? (d[0] * vr + d[1] * vt + d[2] * vz) / v : 1.0;
+      const double e1 = e * (1.0 - 2.0 * s.m / c.m_gas * (1.0 - cosx));
+      const double v1 = sqrt(2.0 * e1 * kQE / s.m);
+      vr = v1 * d[0];
+      vt = v1 * d[1];
+      vz = v1 * d[2];
+      o.dke = ke0 - 0.5 * s.m * s.w * v1 * v1;
+      o.coll = 1;
+    } else if (x < nel + nex) {
+      const double e1 = e - 11.5;
+      const double v1 = sqrt(2.0 * e1 * kQE / s.m);
+      vr = v1 * d[0];
+      vt = v1 * d[1];
+      vz = v1 * d[2];
+      o.dke = ke0 - 0.5 * s.m * s.w * v1 * v1;
+      o.coll = 1;
+    } else if (x < nel + nex + niz) {
+      double w1[4], w2[4];
+      draws(c.seed, sid, uid, c.step, 1, w1);
+      draws(c.seed, sid, uid, c.step, 2, w2);
+      const double er = e - 15.76;
+      const double e1 = w1[0] * er, e2 = er - e1;
+      const double v1 = sqrt(2.0 * e1 * kQE / s.m), v2n = sqrt(2.0 * e2 * kQE / s.m);
+      double d2[3];
+      iso(w1[1], w1[2], d2);
+      const double sg = c.sig_ion;
+      const double ra = sqrt(-2.0 * log(1.0 - w1[3])), rb = sqrt(-2.0 * log(1.0 - w2[1]));
+      const double ivr = sg * ra * cos(2.0 * M_PI * w2[0]);
+      const double ivt = sg * ra * sin(2.0 * M_PI * w2[0]);
+      const double ivz = sg * rb * cos(2.0 * M_PI * w2[2]);
+      const uint64_t nu = child_uid(uid, c.step);
+      vr = v1 * d[0];
+      vt = v1 * d[1];
+      vz = v1 * d[2];
+      const unsigned long long ke = atomicAdd(&tally->append[sid], 1ull);
+      const unsigned long long ki = atomicAdd(&tally->append[c.partner.sid], 1ull);
+      const int64_t se = c.base_self + (int64_t)ke, si = c.base_partner + (int64_t)ki;
+      if (se >= s.cap || si >= c.partner.cap) {
+        o.overflow = 1;
+      } else {
+        store_slot<T>(s, m, se, i, j, a, b, v2n * d2[0], v2n * d2[1], v2n * d2[2], nu);
+        store_slot<T>(c.partner, m, si, i, j, a, b, ivr, ivt, ivz, nu);
+        o.ionized = 1;
+        o.coll = 1;
+        o.dke = ke0 - 0.5 * s.m * s.w * (v1 * v1 + v2n * v2n) -
+                0.5 * c.partner.m * c.partner.w * (ivr * ivr + ivt * ivt + ivz * ivz);
+      }
+    }
+  } else if (c.role == 2) {
+    double w1[4];
+    draws(c.seed, sid, uid, c.step, 1, w1);
+    const double sg = c.sig_gas;
+    const double ra = sqrt(-2.0 * log(1.0 - u[1])), rb = sqrt(-2.0 * log(1.0 - u[3]));
+    const double nvr = sg * ra * cos(2.0 * M_PI * u[2]);
+    const double nvt = sg * ra * sin(2.0 * M_PI * u[2]);
+    const double nvz = sg * rb * cos(2.0 * M_PI * w1[0]);
+    const double gr = vr - nvr, gt = vt - nvt, gz = vz - nvz;
+    const double g = sqrt(gr * gr + gt * gt + gz * gz);
+    const double nu = c.n_gas * 5.0e-19 * g;
+    if (nu > c.numax) o.over = 1;
+    if (w1[1] * c.numax < nu) {
+      vr = nvr;
+      vt = nvt;
+      vz = nvz;
+      o.dke = ke0 - 0.5 * s.m * s.w * (nvr * nvr + nvt * nvt + nvz * nvz);
+      o.coll = 1;
+    }
+  }
+  return o;
+}
+
+// block-wide sum of a double into *dst (one atomic per block)
+__device__ void block_sum_atomic(double v, double* dst) {
+  __shared__ double red[kBlock / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < kBlock / 64; ++k) s += red[k];
+    if (s != 0.0) unsafeAtomicAdd(dst, s);
+  }
+  __syncthreads();
+}
+
+__device__ void block_count_atomic(unsigned v, unsigned long long* dst) {
+  __shared__ unsigned redc[kBlock / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) redc[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int k = 0; k < kBlock / 64; ++k) s += redc[k];
+    if (s) atomicAdd(dst, s);
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ bool load_particle(const SpecDev& s, const MapP& m, int64_t k,
+                                              PState<T>& p);
+
+template <>
+__device__ __forceinline__ bool load_particle<double>(const SpecDev& s, const MapP& m, int64_t k,
+                                                      PState<double>& p) {
+  const double xi = s.xi[k], eta = s.eta[k];
+  p.vr = s.vr[k];
+  p.vt = s.vt[k];
+  p.vz = s.vz[k];
+  if (!(xi >= 0.0)) return false;
+  int i = int(floor(xi)), j = int(floor(eta));
+  i = i < 0 ? 0 : (i > m.nr - 1 ? m.nr - 1 : i);
+  j = j < 0 ? 0 : (j > m.nz - 1 ? m.nz - 1 : j);
+  p.i = i;
+  p.j = j;
+  p.a = xi - double(i);
+  p.b = eta - double(j);
+  return true;
+}
+
+template <>
+__device__ __forceinline__ bool load_particle<float>(const SpecDev& s, const MapP& m, int64_t k,
+                                                     PState<float>& p) {
+  const int c = s.cell[k];
+  p.a = s.fa[k];
+  p.b = s.fb[k];
+  p.vr = s.fvr[k];
+  p.vt = s.fvt[k];
+  p.vz = s.fvz[k];
+  if (c < 0) return false;
+  p.i = c / m.nz;
+  p.j = c - p.i * m.nz;
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_particle(const SpecDev& s, const MapP& m, int64_t k,
+                                               const PState<T>& p);
+template <>
+__device__ __forceinline__ void store_particle<double>(const SpecDev& s, const MapP& m, int64_t k,
+                                                       const PState<double>& p) {
+  s.xi[k] = double(p.i) + p.a;
+  s.eta[k] = double(p.j) + p.b;
+  s.vr[k] = p.vr;
+  s.vt[k] = p.vt;
+  s.vz[k] = p.vz;
+}
+template <>
+__device__ __forceinline__ void store_particle<float>(const SpecDev& s, const MapP& m, int64_t k,
+                                                      const PState<float>& p) {
+  s.cell[k] = p.i * m.nz + p.j;
+  s.fa[k] = p.a;
+  s.fb[k] = p.b;
+  s.fvr[k] = p.vr;
+  s.fvt[k] = p.vt;
+  s.fvz[k] = p.vz;
+}
+
+template <typename T>
+__device__ __forceinline__ void kill_particle(const SpecDev& s, int64_t k);
+template <>
+__device__ __forceinline__ void kill_particle<double>(const SpecDev& s, int64_t k) {
+  s.xi[k] = -1.0;
+}
+template <>
+__device__ __forceinline__ void kill_particle<float>(const SpecDev& s, int64_t k) {
+  s.cell[k] = -1;
+}
+
+template <typename T>
+struct FieldPtr;
+template <>
+struct FieldPtr<double> {
+  static __device__ __forceinline__ const double* r(const PushArgs& a) { return a.ur; }
+  static __device__ __forceinline__ const double* z(const PushArgs& a) { return a.uz; }
+};
+template <>
+struct FieldPtr<float> {
+  static __device__ __forceinline__ const float* r(const PushArgs& a) { return a.urf; }
+  static __device__ __forceinline__ const float* z(const PushArgs& a) { return a.uzf; }
+};
+
+template <typename T, bool COMMIT>
+__global__ void __launch_bounds__(kBlock) k_push(PushArgs A) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const MapP& m = A.m;
+  const SpecDev& s = A.s;
+  PState<T> p;
+  bool alive = false;
+  if (k < s.n) alive = load_particle<T>(s, m, k, p);
+  const T qm = T(s.q / s.m);
+  const double qw = s.q * s.w;
+  const double qw_dt = qw / m.dt;
+  PushOut o;
+  o.have_first = false;
+  o.status = kAlive;
+  o.nsub = 0;
+  o.ncross = 0;
+  o.work = 0.0;
+  o.wall = 0;
+  if (alive) {
+    push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, p, qm, qw_dt, COMMIT, o);
+  }
+  // first sub-step deposits: segmented wavefront reduction by cell
+  {
+    const int key = o.have_first ? o.fi * m.nz + o.fj : -1;
+    Dep d = o.have_first ? o.first : Dep{0.0, 0.0, 0.0, 0.0};
+    wave_deposit(A.Ir, A.Iz, m.nz, key, o.fi, o.fj, d);
+  }
+  if (!COMMIT) return;
+  double dke_abs = 0.0, dke_coll = 0.0;
+  unsigned absorbed = 0, coll = 0, ion = 0, err = 0, over = 0, ovf = 0;
+  if (alive) {
+    if (o.status == kError) err = 1;
+    if (o.status == kAbsorbed) {
+      kill_particle<T>(s, k);
+      absorbed = 1;
+      dke_abs = 0.5 * s.m * s.w *
+                (double(p.vr) * p.vr + double(p.vt) * p.vt + double(p.vz) * p.vz);
+      const int nr = m.nr, nz = m.nz;
+      if (o.wall == 1 || o.wall == 2) {
+        double* w = o.wall == 1 ? A.wall_bot : A.wall_top;
+        unsafeAtomicAdd(&w[p.i], qw * (1.0 - double(p.a)));
+        unsafeAtomicAdd(&w[p.i + 1], qw * double(p.a));
+      } else {
+        unsafeAtomicAdd(&A.wall_side[p.j], qw * (1.0 - double(p.b)));
+        unsafeAtomicAdd(&A.wall_side[p.j + 1], qw * double(p.b));
+      }
+      (void)nr;
+      (void)nz;
+    } else {
+      double vr = p.vr, vt = p.vt, vz = p.vz;
+      if (A.mcc.enabled) {
+        const CollOut co =
+            collide_one<T>(A.mcc, s, m, s.sid, s.uid[k], p.i, p.j, p.a, p.b, vr, vt, vz, A.tally);
+        dke_coll = co.dke;
+        coll = co.coll;
+        ion = co.ionized;
+        over = co.over;
+        ovf = co.overflow;
+        p.vr = T(vr);
+        p.vt = T(vt);
+        p.vz = T(vz);
+      }
+      store_particle<T>(s, m, k, p);
+    }
+  }
+  block_sum_atomic(o.work, &A.tally->w_particles);
+  block_sum_atomic(dke_abs, &A.tally->w_absorbed);
+  block_sum_atomic(dke_coll, &A.tally->w_coll);
+  block_count_atomic(absorbed, &A.tally->n_absorbed[s.sid]);
+  block_count_atomic(coll, &A.tally->n_coll[s.sid]);
+  block_count_atomic(ion, &A.tally->n_ionized);
+  block_count_atomic(err, &A.tally->n_errors);
+  block_count_atomic(over, &A.tally->n_over_range);
+  block_count_atomic(ovf, &A.tally->n_overflow);
+  block_count_atomic(unsigned(o.nsub), &A.tally->n_substeps);
+  block_count_atomic(unsigned(o.ncross), &A.tally->n_crossings);
+}
+
+// standalone collision pass over the live particles
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_collide(MapP m, SpecDev s, MccDev c, Tally* tally) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  PState<T> p;
+  bool alive = false;
+  if (k < c.base_self) alive = load_particle<T>(s, m, k, p);
+  double dke = 0.0;
+  unsigned coll = 0, ion = 0, over = 0, ovf = 0;
+  if (alive) {
+    double vr = p.vr, vt = p.vt, vz = p.vz;
+    const CollOut co = collide_one<T>(c, s, m, s.sid, s.uid[k], p.i, p.j, p.a, p.b, vr, vt, vz, tally);
+    dke = co.dke;
+    coll = co.coll;
+    ion = co.ionized;
+    over = co.over;
+    ovf = co.overflow;
+    if (co.coll) {
+      p.vr = T(vr);
+      p.vt = T(vt);
+      p.vz = T(vz);
+      store_particle<T>(s, m, k, p);
+    }
+  }
+  block_sum_atomic(dke, &tally->w_coll);
+  block_count_atomic(coll, &tally->n_coll[s.sid]);
+  block_count_atomic(ion, &tally->n_ionized);
+  block_count_atomic(over, &tally->n_over_range);
+  block_count_atomic(ovf, &tally->n_overflow);
+}
+
+// physical (r, z) -> logical state
+__device__ __forceinline__ double xi_of_r(const MapP& m, double r) {
+  if (m.xi_a > 0.0 && r < 2.0 * m.s * m.xi_a) return r * r / (4.0 * m.s * m.s * m.xi_a);
+  return r * m.inv_s - m.xi_a;
+}
+
+__global__ void k_load(MapP m, SpecDev s, const double* r, const double* z, const double* vr,
+                       const double* vt, const double* vz, const uint64_t* uid, int64_t n,
+                       int mixed) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  double xi = xi_of_r(m, r[k]);
+  double eta = z[k] * m.inv_dz;
+  xi = fmin(fmax(xi, 0.0), double(m.nr));
+  eta = fmin(fmax(eta, 0.0), double(m.nz));
+  if (!mixed) {
+    s.xi[k] = xi;
+    s.eta[k] = eta;
+    s.vr[k] = vr[k];
+    s.vt[k] = vt[k];
+    s.vz[k] = vz[k];
+  } else {
+    int i = int(floor(xi)), j = int(floor(eta));
+    i = i > m.nr - 1 ? m.nr - 1 : i;
+    j = j > m.nz - 1 ? m.nz - 1 : j;
+    s.cell[k] = i * m.nz + j;
+    s.fa[k] = float(xi - i);
+    s.fb[k] = float(eta - j);
+    s.fvr[k] = float(vr[k]);
+    s.fvt[k] = float(vt[k]);
+    s.fvz[k] = float(vz[k]);
+  }
+  s.uid[k] = uid[k];
+}
+
+// stable compaction of live particles into FP64 outputs
+__global__ void k_flag_count(MapP m, SpecDev s, int64_t n, int mixed, int32_t* blk) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool alive = false;
+  if (k < n) alive = mixed ? (s.cell[k] >= 0) : (s.xi[k] >= 0.0);
+  const int c = __syncthreads_count(alive);
+  if (threadIdx.x == 0) blk[blockIdx.x] = c;
+}
+
+__global__ void k_compact_read(MapP m, SpecDev s, int64_t n, int mixed, const int32_t* blk_off,
+                               double* xi, double* eta, double* vr, double* vt, double* vz,
+                               uint64_t* uid) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool alive = false;
+  if (k < n) alive = mixed ? (s.cell[k] >= 0) : (s.xi[k] >= 0.0);
+  __shared__ int wsum[kBlock / 64];
+  const uint64_t bal = __ballot(alive);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int before = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) wsum[w] = __popcll(bal);
+  __syncthreads();
+  int off = blk_off[blockIdx.x];
+  for (int q = 0; q < w; ++q) off += wsum[q];
+  if (!alive) return;
+  const int64_t d = off + before;
+  if (!mixed) {
+    xi[d] = s.xi[k];
+    eta[d] = s.eta[k];
+    vr[d] = s.vr[k];
+    vt[d] = s.vt[k];
+    vz[d] = s.vz[k];
+  } else {
+    const int c = s.cell[k];
+    const int i = c / m.nz, j = c - (c / m.nz) * m.nz;
+    xi[d] = double(i) + double(s.fa[k]);
+    eta[d] = double(j) + double(s.fb[k]);
+    vr[d] = s.fvr[k];
+    vt[d] = s.fvt[k];
+    vz[d] = s.fvz[k];
+  }
+  uid[d] = s.uid[k];
+}
+
+}  // namespace
+
+// nu_max = 1.05 n_g max_{eps <= eps_max} sigma_tot(eps) v(eps) on a 2e5-point
+// energy grid (electrons), or 1.05 n_g sigma_cx g(eps_max) (ions)
+double nu_max_host(const ecpic_mcc_desc& c, int role, double mp) {
+  if (role == 1) {
+    double best = 0.0;
+    const int K = 200000;
+    for (int k = 1; k <= K; ++k) {
+      const double e = c.eps_max_ev * (double)k / (double)K;
+      double a, b, d;
+      xsec(e, a, b, d);
+      const double f = (a + b + d) * sqrt(2.0 * e * kQE / mp);
+      if (f > best) best = f;
+    }
+    return 1.05 * c.n_gas * best;
+  }
+  if (role == 2) return 1.05 * c.n_gas * 5.0e-19 * sqrt(2.0 * c.eps_max_ev * kQE / mp);
+  return 0.0;
+}
+
+hipError_t launch_push(const PushArgs& a, hipStream_t st) {
+  if (a.s.n <= 0) return hipSuccess;
+  const int64_t nb = (a.s.n + kBlock - 1) / kBlock;
+  const bool mixed = (a.s.cell != nullptr);
+  if (!mixed) {
+    if (a.commit)
+      hipLaunchKernelGGL((k_push<double, true>), dim3(nb), dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_push<double, false>), dim3(nb), dim3(kBlock), 0, st, a);
+  } else {
+    if (a.commit)
+      hipLaunchKernelGGL((k_push<float, true>), dim3(nb), dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_push<float, false>), dim3(nb), dim3(kBlock), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_collide(const MapP& m, const SpecDev& s, const MccDev& c, Tally* tally, int mixed,
+                          hipStream_t st) {
+  if (c.base_self <= 0) return hipSuccess;
+  const int64_t nb = (c.base_self + kBlock - 1) / kBlock;
+  if (mixed)
+    hipLaunchKernelGGL((k_collide<float>), dim3(nb), dim3(kBlock), 0, st, m, s, c, tally);
+  else
+    hipLaunchKernelGGL((k_collide<double>), dim3(nb), dim3(kBlock), 0, st, m, s, c, tally);
+  return hipGetLastError();
+}
+
+hipError_t launch_load(const MapP& m, const SpecDev& s, const double* r, const double* z,
+                       const double* vr, const double* vt, const double* vz, const uint64_t* uid,
+                       int64_t n, double R, int mixed, hipStream_t st) {
+  (void)R;
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_load, dim3(nb), dim3(kBlock), 0, st, m, s, r, z, vr, vt, vz, uid, n, mixed);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_count(const MapP& m, const SpecDev& s, int64_t n, int mixed, int32_t* blk,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kBlock), 0, st, m, s, n, mixed, blk);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_read(const MapP& m, const SpecDev& s, int64_t n, int mixed,
+                               const int32_t* blk_off, double* xi, double* eta, double* vr,
+                               double* vt, double* vz, uint64_t* uid, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_compact_read, dim3(nb), dim3(kBlock), 0, st, m, s, n, mixed, blk_off, xi,
+                     eta, vr, vt, vz, uid);
+  return hipGetLastError();
+}
+
+}  // namespace ecpic

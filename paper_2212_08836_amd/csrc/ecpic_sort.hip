@@ -1,0 +1,267 @@
+// ecpic_sort.hip -- counting sort of particles by cell (the fine sorting the
+// paper's GPU parallelisation builds on, Sec. 2.1) with compaction of
+// absorbed particles, an exclusive scan, and particle-side reductions.
+#include "ecpic_internal.h"
+
+namespace ecpic {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanChunk = kScanThreads * kScanPer;  // 1024 elements per block
+
+// block-local exclusive scan; block totals to part[blockIdx.x]
+__global__ void __launch_bounds__(kScanThreads) k_scan_local(int32_t* data, int64_t n,
+                                                             int32_t* part) {
+  __shared__ int32_t wsum[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+  int32_t v[kScanPer];
+  int32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    v[q] = (base + q < n) ? data[base + q] : 0;
+    s += v[q];
+  }
+  // inclusive scan of the per-thread sums across the wavefront
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t inc = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t o = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += o;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int32_t wbase = 0;
+  for (int q = 0; q < w; ++q) wbase += wsum[q];
+  int32_t run = wbase + inc - s;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    if (base + q < n) data[base + q] = run;
+    run += v[q];
+  }
+  if (threadIdx.x == kScanThreads - 1) part[blockIdx.x] = run;
+}
+
+// single block: exclusive scan of the block totals; grand total to data[n]
+__global__ void __launch_bounds__(1024) k_scan_part(int32_t* part, int64_t nb, int32_t* data,
+                                                    int64_t n) {
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t carry_s;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+    const int64_t k = b0 + threadIdx.x;
+    const int32_t x = (k < nb) ? part[k] : 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t inc = x;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t o = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += o;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int32_t wbase = 0;
+    for (int q = 0; q < w; ++q) wbase += wsum[q];
+    const int32_t carry = carry_s;
+    if (k < nb) part[k] = carry + wbase + inc - x;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry_s = carry + wbase + inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) data[n] = carry_s;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_add(int32_t* data, int64_t n,
+                                                           const int32_t* part) {
+  const int32_t add = part[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  for (int q = threadIdx.x; q < kScanChunk; q += kScanThreads) {
+    if (base + q < n) data[base + q] += add;
+  }
+}
+
+__device__ __forceinline__ int cell_key(const MapP& m, const SpecDev& s, int64_t k, bool mixed) {
+  if (mixed) return s.cell[k];
+  const double xi = s.xi[k];
+  if (!(xi >= 0.0)) return -1;
+  int i = int(floor(xi)), j = int(floor(s.eta[k]));
+  i = i < 0 ? 0 : (i > m.nr - 1 ? m.nr - 1 : i);
+  j = j < 0 ? 0 : (j > m.nz - 1 ? m.nz - 1 : j);
+  return i * m.nz + j;
+}
+
+__global__ void k_hist(MapP m, SpecDev s, int64_t n, int mixed, int32_t* hist) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const int c = cell_key(m, s, k, mixed != 0);
+  if (c >= 0) atomicAdd(&hist[c], 1);
+}
+
+__global__ void k_scatter(MapP m, SpecDev src, SpecDev dst, int64_t n, int mixed, int32_t* offs) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const int c = cell_key(m, src, k, mixed != 0);
+  if (c < 0) return;
+  const int64_t d = atomicAdd(&offs[c], 1);
+  if (!mixed) {
+    dst.xi[d] = src.xi[k];
+    dst.eta[d] = src.eta[k];
+    dst.vr[d] = src.vr[k];
+    dst.vt[d] = src.vt[k];
+    dst.vz[d] = src.vz[k];
+  } else {
+    dst.cell[d] = c;
+    dst.fa[d] = src.fa[k];
+    dst.fb[d] = src.fb[k];
+    dst.fvr[d] = src.fvr[k];
+    dst.fvt[d] = src.fvt[k];
+    dst.fvz[d] = src.fvz[k];
+  }
+  dst.uid[d] = src.uid[k];
+}
+
+__global__ void k_kinetic(SpecDev s, int64_t n, int mixed, double* out) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double e = 0.0;
+  if (k < n) {
+    if (!mixed) {
+      if (s.xi[k] >= 0.0) e = s.vr[k] * s.vr[k] + s.vt[k] * s.vt[k] + s.vz[k] * s.vz[k];
+    } else if (s.cell[k] >= 0) {
+      const double a = s.fvr[k], b = s.fvt[k], c = s.fvz[k];
+      e = a * a + b * b + c * c;
+    }
+  }
+  __shared__ double red[kBlock / 64];
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_down(e, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) t += red[q];
+    if (t != 0.0) unsafeAtomicAdd(out, 0.5 * s.m * s.w * t);
+  }
+}
+
+__global__ void k_node_charge(MapP m, SpecDev s, int64_t n, int mixed, double* q) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  int i, j;
+  double a, b;
+  if (!mixed) {
+    const double xi = s.xi[k];
+    if (!(xi >= 0.0)) return;
+    i = int(floor(xi));
+    j = int(floor(s.eta[k]));
+    i = i < 0 ? 0 : (i > m.nr - 1 ? m.nr - 1 : i);
+    j = j < 0 ? 0 : (j > m.nz - 1 ? m.nz - 1 : j);
+    a = xi - i;
+    b = s.eta[k] - j;
+  } else {
+    const int c = s.cell[k];
+    if (c < 0) return;
+    i = c / m.nz;
+    j = c - i * m.nz;
+    a = s.fa[k];
+    b = s.fb[k];
+  }
+  const double qw = s.q * s.w;
+  const int nz1 = m.nz + 1;
+  unsafeAtomicAdd(&q[(size_t)i * nz1 + j], qw * (1 - a) * (1 - b));
+  unsafeAtomicAdd(&q[(size_t)(i + 1) * nz1 + j], qw * a * (1 - b));
+  unsafeAtomicAdd(&q[(size_t)i * nz1 + j + 1], qw * (1 - a) * b);
+  unsafeAtomicAdd(&q[(size_t)(i + 1) * nz1 + j + 1], qw * a * b);
+}
+
+__global__ void k_zero(double* p, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) p[k] = 0.0;
+}
+
+__global__ void k_zero_i(int32_t* p, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) p[k] = 0;
+}
+
+__global__ void k_copy(double* d, const double* s, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) d[k] = s[k];
+}
+
+inline int64_t nblk(int64_t n) { return (n + kBlock - 1) / kBlock; }
+
+}  // namespace
+
+hipError_t scan_exclusive(int32_t* data, int64_t n, int32_t* part, hipStream_t st) {
+  const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanThreads), 0, st, data, n, part);
+  }
+  hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(1024), 0, st, part, nb, data, n);
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanThreads), 0, st, data, n, part);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t st, int64_t* n_alive_host) {
+  const int64_t ncell = (int64_t)c.g.nr * c.g.nz;
+  const int mixed = c.prec == ECPIC_MIXED;
+  SpecDev& src = sp.d[sp.cur];
+  SpecDev& dst = sp.d[1 - sp.cur];
+  hipLaunchKernelGGL(k_zero_i, dim3(nblk(ncell + 1)), dim3(kBlock), 0, st, c.hist, ncell + 1);
+  if (sp.n > 0)
+    hipLaunchKernelGGL(k_hist, dim3(nblk(sp.n)), dim3(kBlock), 0, st, c.m, src, sp.n, mixed,
+                       c.hist);
+  hipError_t e = scan_exclusive(c.hist, ncell, c.scan_part, st);
+  if (e != hipSuccess) return e;
+  int32_t total = 0;
+  e = hipMemcpyAsync(&total, c.hist + ncell, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  if (sp.n > 0)
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(sp.n)), dim3(kBlock), 0, st, c.m, src, dst, sp.n,
+                       mixed, c.hist);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  sp.cur = 1 - sp.cur;
+  sp.n = total;
+  sp.d[sp.cur].n = total;
+  if (n_alive_host) *n_alive_host = total;
+  return hipSuccess;
+}
+
+hipError_t launch_kinetic(const Species& sp, int mixed, double* out, hipStream_t st) {
+  if (sp.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kinetic, dim3(nblk(sp.n)), dim3(kBlock), 0, st, sp.d[sp.cur], sp.n, mixed,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_charge(const Ctx& c, double* q, hipStream_t st) {
+  const int64_t nn = (int64_t)(c.g.nr + 1) * (c.g.nz + 1);
+  hipLaunchKernelGGL(k_zero, dim3(nblk(nn)), dim3(kBlock), 0, st, q, nn);
+  const int mixed = c.prec == ECPIC_MIXED;
+  for (const Species& sp : c.sp) {
+    if (sp.n <= 0) continue;
+    hipLaunchKernelGGL(k_node_charge, dim3(nblk(sp.n)), dim3(kBlock), 0, st, c.m, sp.d[sp.cur],
+                       sp.n, mixed, q);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(nblk(n)), dim3(kBlock), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(double* d, const double* s, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(nblk(n)), dim3(kBlock), 0, st, d, s, n);
+  return hipGetLastError();
+}
+
+}  // namespace ecpic

@@ -1,0 +1,272 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar: 1e-12 relative, norm-wise per array (max |a-b| / max |b|), with
+positions in cell units and velocities relative to the largest speed; the
+Picard iteration count is pinned to the oracle's in each step so that both
+sides run the same iterates.  Particles are compared keyed by species and id.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import ecpic_inputs as E
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    den = np.abs(b).max()
+    if den == 0:
+        return np.abs(a).max()
+    return np.abs(a - b).max() / den
+
+
+def _by_uid(d):
+    o = np.argsort(d["uid"], kind="stable")
+    return {k: v[o] for k, v in d.items()}
+
+
+def _cmp_species(gpu, ora, what=""):
+    g, o = _by_uid(gpu), _by_uid(ora)
+    assert len(g["uid"]) == len(o["uid"]), f"{what}: count {len(g['uid'])} vs {len(o['uid'])}"
+    assert np.array_equal(g["uid"], o["uid"]), what
+    if len(o["uid"]) == 0:
+        return 0.0
+    worst = 0.0
+    for k in ("xi", "eta"):
+        worst = max(worst, np.abs(g[k] - o[k]).max() / max(np.abs(o[k]).max(), 1.0))
+    vmax = max(np.abs(o[k]).max() for k in ("vr", "vt", "vz"))
+    for k in ("vr", "vt", "vz"):
+        worst = max(worst, np.abs(g[k] - o[k]).max() / vmax)
+    return worst
+
+
+def _make_pair(w, og, P, parts, precision="fp64", extra_cap=0.3, mobile=(True, True)):
+    g = og.grid_from_workload(w)
+    sp = []
+    for k, d in enumerate(parts):
+        n = len(d["r"])
+        sp.append(g.species(d, cap=int(n * (1 + extra_cap)) + 256, role=k + 1,
+                            mobile=mobile[k]))
+    ctx = P.context_from_workload(w, precision=precision)
+    P.load_workload_species(ctx, parts, extra_cap=extra_cap, mobile=mobile)
+    return g, sp, ctx
+
+
+def test_load_read_roundtrip(og, torch_cuda):
+    import paper_2212_08836_amd as P
+    w = E.workload("c1")
+    parts = E.make_particles(w)
+    g, sp, ctx = _make_pair(w, og, P, parts)
+    for k in range(2):
+        d = ctx.read_particles(k)
+        assert _cmp_species(d, sp[k].view(), "load") < 1e-14
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 2.0), (37, 29, 2.0), (70, 130, 0.0)])
+def test_field_solve_parity(og, torch_cuda, shape):
+    import paper_2212_08836_amd as P
+    nr, nz, xa = shape
+    _flush(f"field_solve parity {shape}")
+    w = E.Workload("f", nr, nz, 0.05, 0.03, xi_a=xa, dt=2e-11, drive_amp=(150.0,),
+                   drive_freq=(90e6,), drive_phase=(0.4,))
+    g = og.grid_from_workload(w)
+    ctx = P.context_from_workload(w)
+    rng = np.random.default_rng(nr * 1000 + nz)
+    ur0 = rng.standard_normal(nr * (nz + 1)) * 20
+    uz0 = rng.standard_normal((nr + 1) * nz) * 20
+    ur0.reshape(nr, nz + 1)[:, [0, -1]] = 0
+    uz0.reshape(nr + 1, nz)[-1] = 0
+    h0 = rng.standard_normal(nr * nz) * 0.1
+    Ir = rng.standard_normal(nr * (nz + 1)) * 1e-2
+    Iz = rng.standard_normal((nr + 1) * nz) * 1e-2
+    t = 3.3e-9
+    a = ctx.field_solve(ur0, uz0, h0, Ir, Iz, t)
+    b = g.field_solve(ur0, uz0, h0, Ir, Iz, t)
+    for x, y in zip(a, b):
+        assert _rel(x, y) < TOL
+
+
+def test_push_deposit_parity_c1(og, torch_cuda):
+    # one pass in a strong random half-step field, uncommitted then committed
+    import paper_2212_08836_amd as P
+    _flush("push_deposit parity c1")
+    w = E.workload("c1", dt=4e-11)
+    parts = E.make_particles(w)
+    for d in parts[:1]:  # hot electrons: many crossings and some wall hits
+        d["vr"] *= 4
+        d["vz"] *= 4
+    g, sp, ctx = _make_pair(w, og, P, parts)
+    rng = np.random.default_rng(3)
+    nr, nz = w.nr, w.nz
+    urh = rng.standard_normal(nr * (nz + 1)) * 2.0
+    uzh = rng.standard_normal((nr + 1) * nz) * 2.0
+    urh.reshape(nr, nz + 1)[:, [0, -1]] = 0
+    uzh.reshape(nr + 1, nz)[-1] = 0
+    ctx.set_half_field(urh, uzh)
+    Ir_g, Iz_g = ctx.push_deposit(commit=False)
+    Ir_o, Iz_o = g.zeros_r(), g.zeros_z()
+    stats = []
+    for s in sp:
+        _, _, rc, st = g.push_deposit(s, urh, uzh, commit=False, Ir=Ir_o, Iz=Iz_o)
+        stats.append(st)
+        assert rc == 0
+    assert sum(s["n_crossings"] for s in stats) > 500
+    assert _rel(Ir_g, Ir_o) < TOL and _rel(Iz_g, Iz_o) < TOL
+    # committed pass: end states, absorption and wall charge
+    Ir_g, Iz_g = ctx.push_deposit(commit=True)
+    ost = og.State(g)
+    for s in sp:
+        g.push_deposit(s, urh, uzh, commit=True, state=ost)
+    for k in range(2):
+        assert _cmp_species(ctx.read_particles(k), sp[k].view(), f"species {k}") < TOL
+    q, bot, top, side = ctx.node_charge()
+    assert _rel(bot, ost.wall_bot) < TOL and _rel(top, ost.wall_top) < TOL
+    assert _rel(side, ost.wall_side) < TOL
+
+
+def _step_parity(og, P, w, parts, nsteps, mcc=None, sort_every=0, mobile=(True, True)):
+    g, sp, ctx = _make_pair(w, og, P, parts, mobile=mobile)
+    st = og.State(g)
+    if mcc:
+        ctx.set_mcc(mcc)
+    worst = 0.0
+    for n in range(nsteps):
+        d_o = g.step(st, sp, mcc=mcc, tol=w.tol)
+        assert d_o["rc"] == 0
+        d_g = ctx.step(fixed_iter=d_o["iters"], sort_every=sort_every)
+        assert d_g["iters"] == d_o["iters"]
+        # same iterates: residual history agrees
+        for a, b in zip(d_g["residual"], d_o["residual"]):
+            assert abs(a - b) <= 1e-9 * b + 1e-13
+        ur, uz, h = ctx.get_fields()
+        errs = [_rel(ur, st.ur), _rel(uz, st.uz), _rel(h, st.h)]
+        for k in range(len(sp)):
+            errs.append(_cmp_species(ctx.read_particles(k), sp[k].view(), f"step {n} sp {k}"))
+        worst = max(worst, max(errs))
+        _flush(f"  step {n}: iters {d_o['iters']} worst rel {max(errs):.2e} "
+               f"coll {d_o['n_coll'][:2]} ion {d_o['n_ionized']}")
+        assert max(errs) < TOL, (n, errs)
+        assert d_g["n_ionized"] == d_o["n_ionized"]
+        assert d_g["n_coll"][:2] == d_o["n_coll"][:2]
+        assert d_g["w_drive"] == pytest.approx(d_o["w_drive"], rel=1e-9, abs=1e-30)
+    return worst
+
+
+def test_step_parity_c1(og, torch_cuda):
+    import paper_2212_08836_amd as P
+    _flush("step parity c1 (10 steps)")
+    w = E.workload("c1")
+    _step_parity(og, P, w, E.make_particles(w), w.steps)
+
+
+def test_step_parity_driven_collisional(og, torch_cuda):
+    # the c2 physics (drive, J0 sin profile, MCC) on a reduced grid; high
+    # pressure so that every process occurs, with a sort every 3 steps
+    import paper_2212_08836_amd as P
+    _flush("step parity driven + MCC")
+    w = E.Workload("c2s", 48, 24, 0.03, 0.012, n0=1e16, profile="j0sin", ppc=12,
+                   drive_amp=(200.0,), drive_freq=(100e6,), pressure_pa=60.0, seed=12,
+                   dt=1e-11, tol=1e-10)
+    parts = E.make_particles(w)
+    parts[0]["vr"] *= 3.0  # hotter electrons: ionisation within a few steps
+    parts[0]["vt"] *= 3.0
+    parts[0]["vz"] *= 3.0
+    mcc = w.mcc_params()
+    _step_parity(og, P, w, parts, 8, mcc=mcc, sort_every=3)
+
+
+def test_collide_parity(og, torch_cuda):
+    import paper_2212_08836_amd as P
+    _flush("collide parity")
+    w = E.Workload("mc", 16, 16, 0.02, 0.02, n0=1e16, ppc=64, Te_eV=30.0, Ti_eV=0.5,
+                   pressure_pa=300.0, seed=4)
+    parts = E.make_particles(w)
+    g, sp, ctx = _make_pair(w, og, P, parts, extra_cap=1.0)
+    mcc = w.mcc_params()
+    for step in (5, 6):
+        d_o = g.collide(sp, mcc, step)
+        ctx.collide(mcc, step)
+        assert d_o["n_ionized"] > 0 and d_o["n_coll"][1] > 0
+        for k in range(2):
+            assert _cmp_species(ctx.read_particles(k), sp[k].view(), f"collide sp {k}") < TOL
+
+
+def test_sort_keeps_particles_and_orders_cells(og, torch_cuda):
+    import paper_2212_08836_amd as P
+    w = E.workload("c1")
+    parts = E.make_particles(w)
+    g, sp, ctx = _make_pair(w, og, P, parts)
+    before = [ctx.read_particles(k) for k in range(2)]
+    ctx.sort()
+    for k in range(2):
+        d = ctx.read_particles(k)
+        cell = np.minimum(np.floor(d["xi"]).astype(int), w.nr - 1) * w.nz + \
+            np.minimum(np.floor(d["eta"]).astype(int), w.nz - 1)
+        assert np.all(np.diff(cell) >= 0)
+        assert _cmp_species(d, before[k], "sort") == 0.0
+
+
+def test_c2_full_size_sampled(og, torch_cuda):
+    # c2 at full size (256 x 128, 4.2M particles) in the configuration the
+    # bench times: one committed pass in a strong half-step field; sampled
+    # particles re-pushed one by one by the oracle, and exact charge
+    # continity of the whole deposit checked on the GPU's own outputs.
+    import paper_2212_08836_amd as P
+    _flush("c2 full size sampled")
+    w = E.workload("c2")
+    parts = E.make_particles(w)
+    ctx = P.context_from_workload(w)
+    P.load_workload_species(ctx, parts)
+    ctx.sort()
+    g = og.grid_from_workload(w)
+    nr, nz = w.nr, w.nz
+    rng = np.random.default_rng(9)
+    urh = rng.standard_normal(nr * (nz + 1)) * 3.0
+    uzh = rng.standard_normal((nr + 1) * nz) * 3.0
+    urh.reshape(nr, nz + 1)[:, [0, -1]] = 0
+    urh.reshape(nr, nz + 1)[nr - 1, 0] = 100.0
+    uzh.reshape(nr + 1, nz)[-1] = 0
+    ctx.set_half_field(urh, uzh)
+    before = [ctx.read_particles(k) for k in range(2)]
+    q0, _, _, _ = ctx.node_charge()
+    Ir, Iz = ctx.push_deposit(commit=True)
+    q1, bot, top, side = ctx.node_charge()
+    after = [ctx.read_particles(k) for k in range(2)]
+    # continuity: Delta Q + dt div I = 0 at every node (walls with their charge)
+    dq = (q1 - q0).reshape(nr + 1, nz + 1)
+    dq[:, 0] += bot
+    dq[:, -1] += top
+    dq[-1, :] += side
+    div = g.div(Ir, Iz).reshape(nr + 1, nz + 1)
+    qscale = abs(parts[0]["q"] * parts[0]["w"]) * w.ppc
+    assert np.abs(dq + w.dt * div).max() < 1e-11 * qscale
+    # sampled particles: the oracle pushes each alone in the same field
+    for k in range(2):
+        b, a = _by_uid(before[k]), _by_uid(after[k])
+        idx = rng.choice(len(b["uid"]), 3000, replace=False)
+        s = og.Species(parts[k]["q"], parts[k]["m"], parts[k]["w"], b["xi"][idx], b["eta"][idx],
+                       b["vr"][idx], b["vt"][idx], b["vz"][idx], b["uid"][idx])
+        g.push_deposit(s, urh, uzh, commit=True, state=og.State(g))
+        ov = s.view()
+        keep = np.isin(a["uid"], ov["uid"])
+        gv = {kk: v[keep] for kk, v in a.items()}
+        assert _cmp_species(gv, ov, f"c2 sample sp {k}") < TOL
