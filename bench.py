@@ -1,0 +1,148 @@
+"""Benchmark of the implicit EM PIC/MCC hot path on one MI355X.
+
+Workload: the 256 x 128 VHF CCP slab (R = 0.15 m, L = 3 cm, 100 MHz / 200 V
+drive on the bottom electrode, J0(2.405 r/R) sin(pi z/L) density of 1e16
+m^-3, 64 macro-particles per cell per species = 4,194,304 particles,
+null-collision MCC in 5 Pa argon, dt = 1e-11 s, Picard tolerance 1e-10),
+plain FP64 path.  A step is one implicit step: guess, Picard iterations of
+push+deposit and field solve, commit with absorption and MCC, and the
+counting sort every 16 steps.  Synthetic seeded inputs, resident in HBM
+before the timed region.
+
+Prints one JSON line.  `value` = particle-pushes per second counted over the
+Picard iterations (N_alive x iterations summed over the timed steps, divided
+by the wall time of the whole steps).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def cpu_baseline(w, parts, mcc, steps=1):
+    """The FP64 oracle, single-threaded, on the same workload: one step of the
+    full particle set on the full grid (bounded to ~10-30 s)."""
+    import oracle as og
+    g = og.grid_from_workload(w)
+    sp = og.species_from_workload(g, parts, extra_cap=0.05)
+    st = og.State(g)
+    t0 = time.perf_counter()
+    pushes = 0
+    iters = []
+    for _ in range(steps):
+        n_alive = sum(s.n for s in sp)
+        d = g.step(st, sp, mcc=mcc, tol=w.tol)
+        pushes += n_alive * d["iters"]
+        iters.append(d["iters"])
+    dt = time.perf_counter() - t0
+    return {"value": pushes / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+            "s_per_step": dt / steps,
+            "sample": f"{steps} implicit step(s) of the full workload "
+                      f"({sum(len(p['r']) for p in parts)} particles, 256x128 grid, MCC), "
+                      f"Picard iterations {iters}, single-threaded C oracle"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--sort-every", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import ecpic_inputs as E
+    import paper_2212_08836_amd as P
+
+    torch.cuda.set_device(0)
+    w = E.workload("c2")
+    parts = E.make_particles(w)
+    n0 = sum(len(p["r"]) for p in parts)
+    ctx = P.context_from_workload(w, precision=args.precision)
+    P.load_workload_species(ctx, parts, extra_cap=0.25)
+    ctx.sort()
+    mcc = w.mcc_params()
+    ctx.set_mcc(mcc)
+    print(f"# bench: c2 256x128, {n0} particles, {args.precision}, warmup {args.warmup}, "
+          f"steps {args.steps}", file=sys.stderr, flush=True)
+    for k in range(args.warmup):
+        ctx.step(tol=w.tol, sort_every=args.sort_every, stats=False)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last_print = t0
+    for k in range(args.steps):
+        ctx.step(tol=w.tol, sort_every=args.sort_every, stats=False)
+        now = time.perf_counter()
+        if now - last_print > 20:
+            print(f"# step {k}", file=sys.stderr, flush=True)
+            last_print = now
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    elapsed = t1 - t0
+    # Picard iterations: one push launch per mobile species per iteration
+    push = prof["push"]
+    n_push_passes = push["launches"] / 2
+    pushes = push["particles"]
+    value = pushes / elapsed
+    avg_launch_ms = push["ms"] / push["launches"]
+    bytes_per_launch = push["bytes"] / push["launches"]
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    diag = ctx.diagnostics()
+    out = {
+        "metric": "particle-pushes/s per Picard iteration (and s per implicit step)",
+        "value": value,
+        "unit": "particle-pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "s_per_step": elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "VHF CCP slab 256x128 (R 0.15 m, L 3 cm), 4.19M particles, "
+                               "100 MHz 200 V, MCC 5 Pa",
+                   "particles": n0, "grid": [w.nr, w.nz], "dt": w.dt, "tol": w.tol,
+                   "precision": args.precision, "sort_every": args.sort_every,
+                   "parallelism": "single GPU"},
+        "picard_iterations_per_step": n_push_passes / args.steps,
+        "particles_alive_end": diag["n_alive"][:2],
+        "kernel_ms": {k: (v["ms"] / v["launches"] if v["launches"] else None)
+                      for k, v in prof.items()},
+        "roofline": {"bound": "hbm", "kernel": "k_push (Picard iteration pass, one species)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms},
+    }
+    if not args.no_cpu:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, parts, mcc)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -229,6 +229,28 @@ ecpic_status ecpic_nn_grad(ecpic_ctx* ctx, const uint16_t* w_bf16, const uint16_
 ecpic_status ecpic_nn_adam(ecpic_ctx* ctx, float* w, float* m, float* v, const float* dw,
                            uint16_t* w_bf16, float lr, int32_t t);
 
+/* Kernel timing with HIP events recorded on the context stream around every
+ * launch of the hot kernels (one record per launch), for measurement. */
+typedef enum {
+  ECPIC_K_PUSH = 0,    /* push + deposit in a Picard iteration (one species) */
+  ECPIC_K_COMMIT = 1,  /* committing push + absorption + MCC (one species)   */
+  ECPIC_K_FIELD = 2,   /* one field solve (rhs, DCTs, Thomas, recovery)      */
+  ECPIC_K_SORT = 3,    /* counting sort of one species                       */
+  ECPIC_K_COUNT = 4
+} ecpic_kernel_kind;
+
+typedef struct {
+  int64_t launches[ECPIC_K_COUNT];
+  double ms[ECPIC_K_COUNT];           /* summed event-measured durations    */
+  double bytes[ECPIC_K_COUNT];        /* summed algorithmic HBM bytes       */
+  int64_t particles[ECPIC_K_COUNT];   /* summed particles processed         */
+} ecpic_profile;
+
+/* Turn timing on (1) or off (0); turning it on clears the totals. */
+ecpic_status ecpic_set_profiling(ecpic_ctx* ctx, int32_t on);
+/* Totals since profiling was turned on (synchronises). */
+ecpic_status ecpic_get_profile(ecpic_ctx* ctx, ecpic_profile* out);
+
 const char* ecpic_last_error(const ecpic_ctx* ctx);
 const char* ecpic_status_string(ecpic_status s);
 

@@ -72,6 +72,18 @@ class StepStats(C.Structure):
         return d
 
 
+KERNEL_KINDS = ("push", "commit", "field", "sort")
+
+
+class Profile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 4), ("ms", C.c_double * 4), ("bytes", C.c_double * 4),
+                ("particles", C.c_int64 * 4)]
+
+    def as_dict(self) -> dict:
+        return {k: dict(launches=self.launches[i], ms=self.ms[i], bytes=self.bytes[i],
+                        particles=self.particles[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+
 _lib = None
 _vp, _dp, _fp = C.c_void_p, C.c_void_p, C.c_void_p
 
@@ -108,6 +120,8 @@ def lib() -> C.CDLL:
             "ecpic_nn_forward": ([_vp, _vp, _vp, _vp, C.c_int32], st),
             "ecpic_nn_grad": ([_vp, _vp, _vp, _vp, C.c_int32, _vp, C.POINTER(C.c_float)], st),
             "ecpic_nn_adam": ([_vp, _vp, _vp, _vp, _vp, _vp, C.c_float, C.c_int32], st),
+            "ecpic_set_profiling": ([_vp, C.c_int32], st),
+            "ecpic_get_profile": ([_vp, C.POINTER(Profile)], st),
             "ecpic_last_error": ([_vp], C.c_char_p),
             "ecpic_status_string": ([C.c_int], C.c_char_p),
         }
@@ -309,6 +323,14 @@ class Context:
         self._check(self.L.ecpic_node_charge(self.h, _ptr(q), _ptr(b), _ptr(tp), _ptr(sd)), self.h)
         t.cuda.synchronize()
         return q.cpu().numpy(), b.cpu().numpy(), tp.cpu().numpy(), sd.cpu().numpy()
+
+    def set_profiling(self, on: bool):
+        self._check(self.L.ecpic_set_profiling(self.h, int(bool(on))), self.h)
+
+    def profile(self) -> dict:
+        p = Profile()
+        self._check(self.L.ecpic_get_profile(self.h, C.byref(p)), self.h)
+        return p.as_dict()
 
     def diagnostics(self) -> dict:
         s = StepStats()

@@ -184,6 +184,58 @@ hipError_t setup_solver(Ctx& c) {
 
 hipError_t zero(double* p, int64_t n, hipStream_t s) { return launch_zero(p, n, s); }
 
+// -- event timing: a start/stop pair around a launch, resolved after a sync --
+hipEvent_t get_event(Ctx& c) {
+  if (c.ev_pool.empty()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = c.ev_pool.back();
+  c.ev_pool.pop_back();
+  return e;
+}
+
+struct Timed {
+  Ctx& c;
+  hipEvent_t a = nullptr;
+  int kind;
+  double bytes;
+  int64_t particles;
+  Timed(Ctx& cc, int k, double b, int64_t n) : c(cc), kind(k), bytes(b), particles(n) {
+    if (c.prof_on) {
+      a = get_event(c);
+      if (a) (void)hipEventRecord(a, c.stream);
+    }
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = get_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c.stream);
+    c.pending.push_back({a, b, kind, bytes, particles});
+  }
+};
+
+// after the stream has been synchronised: fold finished pairs into totals
+void collect(Ctx& c) {
+  for (auto& p : c.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c.prof.launches[p.kind] += 1;
+      c.prof.ms[p.kind] += ms;
+      c.prof.bytes[p.kind] += p.bytes;
+      c.prof.particles[p.kind] += p.particles;
+    }
+    c.ev_pool.push_back(p.a);
+    c.ev_pool.push_back(p.b);
+  }
+  c.pending.clear();
+}
+
+// algorithmic bytes per particle of a push pass: the state read once
+double state_bytes(const Ctx& c) { return c.prec == ECPIC_FP64 ? 40.0 : 24.0; }
+
 MccDev make_mcc(Ctx& c, int sid, int64_t step) {
   MccDev d;
   std::memset(&d, 0, sizeof(d));
@@ -249,6 +301,9 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step) {
     if (!c.sp[s].desc.mobile || c.sp[s].n == 0) continue;
     PushArgs a = push_args(c, (int)s, commit);
     a.mcc = mcc[s];
+    // commit: state + id read, state written
+    const double per = commit ? 2.0 * state_bytes(c) + 8.0 : state_bytes(c);
+    Timed tm(c, commit ? ECPIC_K_COMMIT : ECPIC_K_PUSH, per * (double)c.sp[s].n, c.sp[s].n);
     HIPCHK(launch_push(a, c.stream));
   }
   return ECPIC_OK;
@@ -259,6 +314,7 @@ ecpic_status finish_tally(Ctx& c, Tally& t) {
   HIPCHK(hipMemcpyAsync(c.tally_host, c.tally, sizeof(Tally), hipMemcpyDeviceToHost, c.stream));
   HIPCHK(hipStreamSynchronize(c.stream));
   t = *c.tally_host;
+  collect(c);
   ecpic_status rc = ECPIC_OK;
   for (size_t s = 0; s < c.sp.size(); ++s) {
     const int64_t add = (int64_t)t.append[s];
@@ -382,6 +438,8 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
   (void)hipFree(c.tally);
   (void)hipFree(c.nn_w);
   (void)hipFree(c.nn_ws);
+  collect(c);
+  for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
   if (c.tally_host) (void)hipHostFree(c.tally_host);
   if (c.red_host) (void)hipHostFree(c.red_host);
   delete x;
@@ -403,6 +461,16 @@ ecpic_status ecpic_add_species(ecpic_ctx* x, const ecpic_species_desc* d, int32_
     return fail(c, ECPIC_ENOMEM, "species allocation failed");
   }
   s.n = 0;
+  // both sort buffers carry the species constants, so every kernel that is
+  // handed a buffer descriptor sees the charge, mass and weight
+  for (SpecDev& b : s.d) {
+    b.cap = d->capacity;
+    b.q = d->q;
+    b.m = d->m;
+    b.w = d->weight;
+    b.mobile = d->mobile;
+    b.sid = (int32_t)c.sp.size();
+  }
   c.sp.push_back(s);
   *sid = (int32_t)c.sp.size() - 1;
   return ECPIC_OK;
@@ -521,8 +589,13 @@ ecpic_status ecpic_field_solve(ecpic_ctx* x, const double* ur0, const double* uz
 static ecpic_status iterate(Ctx& c, double* r_out) {
   const double vnext = drive(c.g, c.t + c.g.dt);
   const double vh = 0.5 * (drive(c.g, c.t) + vnext);
-  HIPCHK(field_solve(c, c.ur, c.uz, c.h, c.Ir, c.Iz, vh, vnext, c.ur_nx, c.uz_nx, c.h_nx,
-                     c.stream));
+  {
+    // field arrays: u0, I, h0 read, u1, h1 written (FP64)
+    const double fb = 8.0 * (3.0 * (n_edges_r(c) + n_edges_z(c)) + 2.0 * n_cells(c));
+    Timed tm(c, ECPIC_K_FIELD, fb, 0);
+    HIPCHK(field_solve(c, c.ur, c.uz, c.h, c.Ir, c.Iz, vh, vnext, c.ur_nx, c.uz_nx, c.h_nx,
+                       c.stream));
+  }
   double* d_red = c.sol.partial + 4000;
   HIPCHK(launch_resid(c, c.ur_nx, c.uz_nx, c.ur_it, c.uz_it, d_red, c.stream));
   HIPCHK(hipMemcpyAsync(c.red_host, d_red, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
@@ -530,6 +603,7 @@ static ecpic_status iterate(Ctx& c, double* r_out) {
   std::swap(c.uz_it, c.uz_nx);
   std::swap(c.h_it, c.h_nx);
   HIPCHK(hipStreamSynchronize(c.stream));
+  collect(c);
   const double num = c.red_host[0], den = c.red_host[1];
   *r_out = den > 0.0 ? std::sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
   return ECPIC_OK;
@@ -615,6 +689,25 @@ static ecpic_status diag_into(Ctx& c, ecpic_step_stats* st) {
   for (size_t s = 0; s < c.sp.size() && s < 4; ++s) st->n_alive[s] = c.sp[s].n;
   st->t = c.t;
   st->step = c.step;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_set_profiling(ecpic_ctx* x, int32_t on) {
+  if (!x) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  HIPCHK(hipStreamSynchronize(c.stream));
+  collect(c);
+  c.prof_on = on != 0;
+  std::memset(&c.prof, 0, sizeof(c.prof));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_get_profile(ecpic_ctx* x, ecpic_profile* out) {
+  if (!x || !out) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  HIPCHK(hipStreamSynchronize(c.stream));
+  collect(c);
+  *out = c.prof;
   return ECPIC_OK;
 }
 
@@ -704,7 +797,15 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
   c.t += c.g.dt;
   c.step += 1;
   if (o->sort_every > 0 && c.step % o->sort_every == 0) {
-    for (Species& s : c.sp) HIPCHK(launch_sort(c, s, c.stream, nullptr));
+    for (Species& s : c.sp) {
+      const int64_t n0 = s.n;
+      {
+        Timed tm(c, ECPIC_K_SORT, (2.0 * (state_bytes(c) + 8.0) + 16.0) * (double)n0, n0);
+        HIPCHK(launch_sort(c, s, c.stream, nullptr));
+      }
+      HIPCHK(hipStreamSynchronize(c.stream));
+      collect(c);
+    }
   }
   if (st) {
     ecpic_status r2 = diag_into(c, S);

@@ -134,6 +134,17 @@ struct Ctx {
   bool nn_ready = false;
   void* nn_ws = nullptr;           // activation workspace
   size_t nn_ws_bytes = 0;
+  // event timing of the hot kernels
+  bool prof_on = false;
+  ecpic_profile prof{};
+  struct Pending {
+    hipEvent_t a, b;
+    int kind;
+    double bytes;
+    int64_t particles;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_pool;
 };
 
 // ---- launchers (stream-ordered, no synchronisation) ----

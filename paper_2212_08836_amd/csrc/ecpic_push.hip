@@ -67,22 +67,30 @@ __device__ __forceinline__ void map_r(const MapP& m, int i, T a, T& r, T& ijr) {
 // Position equation of the mid-point rule in xi, solved exactly for the
 // mid offset: linear part of the map, or the square-root part as a quadratic
 // in sqrt(xi_bar) (positive root), whichever is consistent.
+//
+// Written as a value-returning function with one exit: an earlier form that
+// wrote the result through a reference from several early-return branches was
+// compiled (hipcc, gfx950) so that, in wavefronts where some lanes took the
+// linear branch and others the square-root branch, square-root lanes received
+// the linear value.  The single-exit form is exact in that situation.
+template <typename T>
+__device__ __forceinline__ T mid_a_val(const MapP& m, int i, T a, T vbr, T dtau) {
+  const T al = a + T(0.5) * dtau * vbr * T(m.inv_s);
+  if (m.xi_a > 0.0 && T(i) + al < T(m.xi_a)) {
+    const T xi = T(i) + a;
+    const T beta = T(0.5) * dtau * vbr * T(m.inv_s * m.rsqrt_xa);
+    const T y = T(0.5) * (beta + sqrt(beta * beta + T(4) * xi));
+    return y * y - T(i);
+  }
+  return al;
+}
+
+// the mid position is admissible unless the uniform map (xi_a = 0) puts it
+// behind the axis
 template <typename T>
 __device__ __forceinline__ bool mid_a(const MapP& m, int i, T a, T vbr, T dtau, T& abar) {
-  const T al = a + T(0.5) * dtau * vbr * T(m.inv_s);
-  if (m.xi_a <= 0.0) {
-    abar = al;
-    return T(i) + al >= T(0);
-  }
-  if (T(i) + al >= T(m.xi_a)) {
-    abar = al;
-    return true;
-  }
-  const T xi = T(i) + a;
-  const T beta = T(0.5) * dtau * vbr * T(m.inv_s * m.rsqrt_xa);
-  const T y = T(0.5) * (beta + sqrt(beta * beta + T(4) * xi));
-  abar = y * y - T(i);
-  return true;
+  abar = mid_a_val(m, i, a, vbr, dtau);
+  return m.xi_a > 0.0 || T(i) + abar >= T(0);
 }
 
 // Mid-point acceleration with the theta mid velocity from the angular

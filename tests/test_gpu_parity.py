@@ -167,6 +167,12 @@ def _step_parity(og, P, w, parts, nsteps, mcc=None, sort_every=0, mobile=(True, 
         assert max(errs) < TOL, (n, errs)
         assert d_g["n_ionized"] == d_o["n_ionized"]
         assert d_g["n_coll"][:2] == d_o["n_coll"][:2]
+        assert d_g["n_absorbed"][:2] == d_o["n_absorbed"][:2]
+        # energy accounting (sums in a different order: 1e-10 relative)
+        for key in ("we", "wb", "w_absorbed", "w_coll", "w_particles", "w_field_io"):
+            assert d_g[key] == pytest.approx(d_o[key], rel=1e-10, abs=1e-30), key
+        for k in range(2):
+            assert d_g["ke"][k] == pytest.approx(d_o["ke"][k], rel=1e-12), "ke"
         assert d_g["w_drive"] == pytest.approx(d_o["w_drive"], rel=1e-9, abs=1e-30)
     return worst
 
