@@ -24,6 +24,13 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kKB = 1.380649e-23;  // Boltzmann constant [J/K]
+// layout of the device / pinned-host reduction buffer (doubles)
+constexpr int kOffRes = 0;                        // 2 nr residual partials
+constexpr int kOffFE = 4096;                      // 2 kRedBlocks field energy
+constexpr int kOffEx = kOffFE + 2 * kRedBlocks;   // kRedBlocks exchange
+constexpr int kOffKE = kOffEx + kRedBlocks;       // kMaxSpecies kinetic energies
+constexpr int kOffSc = kOffKE + 8;                // a few scalars
+constexpr int kPartLen = kOffSc + 16;
 
 #define HIPCHK(expr)                                                              \
   do {                                                                            \
@@ -178,7 +185,7 @@ hipError_t setup_solver(Ctx& c) {
   if ((e = up(&S.tri_up, To)) != hipSuccess) return e;
   if ((e = dalloc(&S.work0, (size_t)nr * nz)) != hipSuccess) return e;
   if ((e = dalloc(&S.work1, (size_t)nr * nz)) != hipSuccess) return e;
-  if ((e = dalloc(&S.partial, 4096)) != hipSuccess) return e;
+  if ((e = dalloc(&S.partial, kPartLen)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -287,10 +294,15 @@ PushArgs push_args(Ctx& c, int sid, int commit) {
 }
 
 // One pass over all species; currents zeroed first.
-ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step) {
-  HIPCHK(zero(c.Ir, n_edges_r(c), c.stream));
-  HIPCHK(zero(c.Iz, n_edges_z(c), c.stream));
+// One pass over all species.  Inside a step the currents were already reset
+// (by the guess kernel or the last field solve); a standalone pass resets them.
+ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool zero_currents) {
+  if (zero_currents) {
+    HIPCHK(zero(c.Ir, n_edges_r(c), c.stream));
+    HIPCHK(zero(c.Iz, n_edges_z(c), c.stream));
+  }
   if (commit) HIPCHK(hipMemsetAsync(c.tally, 0, sizeof(Tally), c.stream));
+  HIPCHK(launch_zero_i(c.qcount, kMaxSpecies, c.stream));
   // append offsets of every species are taken before any pass appends
   std::vector<MccDev> mcc(c.sp.size());
   for (size_t s = 0; s < c.sp.size(); ++s) {
@@ -304,7 +316,7 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step) {
     // commit: state + id read, state written
     const double per = commit ? 2.0 * state_bytes(c) + 8.0 : state_bytes(c);
     Timed tm(c, commit ? ECPIC_K_COMMIT : ECPIC_K_PUSH, per * (double)c.sp[s].n, c.sp[s].n);
-    HIPCHK(launch_push(a, c.stream));
+    HIPCHK(launch_push(a, c.queue, c.qcount + s, c.stream));
   }
   return ECPIC_OK;
 }
@@ -381,18 +393,23 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   A(&c.ur_it, nur); A(&c.uz_it, nuz); A(&c.h_it, nh);
   A(&c.ur_nx, nur); A(&c.uz_nx, nuz); A(&c.h_nx, nh);
   A(&c.ur_half, nur); A(&c.uz_half, nuz); A(&c.Ir, nur); A(&c.Iz, nuz);
+  A(&c.ur_half2, nur); A(&c.uz_half2, nuz);
   A(&c.wall_bot, g->nr + 1); A(&c.wall_top, g->nr + 1); A(&c.wall_side, g->nz + 1);
-  c.ur_half_f = c.uz_half_f = nullptr;
+  c.ur_half_f = c.uz_half_f = c.ur_half_f2 = c.uz_half_f2 = nullptr;
   if (prec == ECPIC_MIXED) {
     ok = ok && dalloc(&c.ur_half_f, (size_t)nur) == hipSuccess;
     ok = ok && dalloc(&c.uz_half_f, (size_t)nuz) == hipSuccess;
+    ok = ok && dalloc(&c.ur_half_f2, (size_t)nur) == hipSuccess;
+    ok = ok && dalloc(&c.uz_half_f2, (size_t)nuz) == hipSuccess;
   }
   ok = ok && dalloc(&c.hist, (size_t)nh + 1) == hipSuccess;
   ok = ok && dalloc(&c.offs, (size_t)nh + 1) == hipSuccess;
   ok = ok && dalloc(&c.scan_part, (size_t)(nh + 1023) / 1024 + 2) == hipSuccess;
   ok = ok && dalloc(&c.tally, 1) == hipSuccess;
+  ok = ok && dalloc(&c.qcount, kMaxSpecies) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.tally_host, sizeof(Tally)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.red_host, 64 * sizeof(double)) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c.part_host, kPartLen * sizeof(double)) == hipSuccess;
   if (!ok) {
     ecpic_destroy(x);
     return ECPIC_ENOMEM;
@@ -402,9 +419,9 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
     return ECPIC_EHIP;
   }
   double* zs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.ur_it, c.uz_it, c.h_it,
-                  c.ur_half, c.uz_half, c.Ir, c.Iz};
-  int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz};
-  for (int k = 0; k < 12; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
+                  c.ur_half, c.uz_half, c.Ir, c.Iz, c.ur_half2, c.uz_half2};
+  int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz};
+  for (int k = 0; k < 14; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
   (void)launch_zero(c.wall_bot, g->nr + 1, c.stream);
   (void)launch_zero(c.wall_top, g->nr + 1, c.stream);
   (void)launch_zero(c.wall_side, g->nz + 1, c.stream);
@@ -425,23 +442,29 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
     free_species_buf(s.d[1]);
   }
   double* fs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.ur_it, c.uz_it, c.h_it, c.ur_nx,
-                  c.uz_nx, c.h_nx, c.ur_half, c.uz_half, c.Ir, c.Iz, c.wall_bot, c.wall_top,
+                  c.uz_nx, c.h_nx, c.ur_half, c.uz_half, c.ur_half2, c.uz_half2, c.Ir, c.Iz,
+                  c.wall_bot, c.wall_top,
                   c.wall_side, c.sol.rh, c.sol.wr, c.sol.wz, c.sol.area, c.sol.Q, c.sol.Qt,
                   c.sol.tri_lo, c.sol.tri_inv, c.sol.tri_up, c.sol.work0, c.sol.work1,
                   c.sol.partial};
   for (double* p : fs) (void)hipFree(p);
   (void)hipFree(c.ur_half_f);
   (void)hipFree(c.uz_half_f);
+  (void)hipFree(c.ur_half_f2);
+  (void)hipFree(c.uz_half_f2);
   (void)hipFree(c.hist);
   (void)hipFree(c.offs);
   (void)hipFree(c.scan_part);
   (void)hipFree(c.tally);
+  (void)hipFree(c.queue);
+  (void)hipFree(c.qcount);
   (void)hipFree(c.nn_w);
   (void)hipFree(c.nn_ws);
   collect(c);
   for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
   if (c.tally_host) (void)hipHostFree(c.tally_host);
   if (c.red_host) (void)hipHostFree(c.red_host);
+  if (c.part_host) (void)hipHostFree(c.part_host);
   delete x;
   return ECPIC_OK;
 }
@@ -459,6 +482,17 @@ ecpic_status ecpic_add_species(ecpic_ctx* x, const ecpic_species_desc* d, int32_
     free_species_buf(s.d[0]);
     free_species_buf(s.d[1]);
     return fail(c, ECPIC_ENOMEM, "species allocation failed");
+  }
+  if (d->capacity > c.queue_cap) {
+    int32_t* q = nullptr;
+    if (dalloc(&q, (size_t)d->capacity) != hipSuccess) {
+      free_species_buf(s.d[0]);
+      free_species_buf(s.d[1]);
+      return fail(c, ECPIC_ENOMEM, "queue allocation failed");
+    }
+    (void)hipFree(c.queue);
+    c.queue = q;
+    c.queue_cap = d->capacity;
   }
   s.n = 0;
   // both sort buffers carry the species constants, so every kernel that is
@@ -564,7 +598,7 @@ ecpic_status ecpic_set_half_field(ecpic_ctx* x, const double* urh, const double*
 ecpic_status ecpic_push_deposit(ecpic_ctx* x, int32_t commit, double* Ir, double* Iz) {
   if (!x) return ECPIC_EINVAL;
   Ctx& c = x->c;
-  ecpic_status rc = pass(c, commit ? 1 : 0, false, c.step);
+  ecpic_status rc = pass(c, commit ? 1 : 0, false, c.step, true);
   if (rc != ECPIC_OK) return rc;
   if (Ir) HIPCHK(launch_copy(Ir, c.Ir, n_edges_r(c), c.stream));
   if (Iz) HIPCHK(launch_copy(Iz, c.Iz, n_edges_z(c), c.stream));
@@ -581,32 +615,75 @@ ecpic_status ecpic_field_solve(ecpic_ctx* x, const double* ur0, const double* uz
                                double* uz1, double* h1) {
   if (!x || !ur0 || !uz0 || !h0 || !Ir || !Iz || !ur1 || !uz1 || !h1) return ECPIC_EINVAL;
   Ctx& c = x->c;
-  const double vh = 0.5 * (drive(c.g, t) + drive(c.g, t + c.g.dt));
-  HIPCHK(field_solve(c, ur0, uz0, h0, Ir, Iz, vh, drive(c.g, t + c.g.dt), ur1, uz1, h1, c.stream));
+  SolveArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.ur0 = ur0;
+  a.uz0 = uz0;
+  a.h0 = h0;
+  a.Ir = const_cast<double*>(Ir);  // read only: zero_I = 0
+  a.Iz = const_cast<double*>(Iz);
+  a.vnext = drive(c.g, t + c.g.dt);
+  a.vhalf = 0.5 * (drive(c.g, t) + a.vnext);
+  a.ur1 = ur1;
+  a.uz1 = uz1;
+  a.h1 = h1;
+  HIPCHK(field_solve(c, a, c.stream));
   return ECPIC_OK;
 }
 
+// One field iterate: solve with the current I into the *_nx buffers, write
+// the next half-step field into *_half2, zero I, and return the residual
+// against the previous iterate.  The new iterate becomes *_it.
 static ecpic_status iterate(Ctx& c, double* r_out) {
-  const double vnext = drive(c.g, c.t + c.g.dt);
-  const double vh = 0.5 * (drive(c.g, c.t) + vnext);
+  const int nr = c.g.nr;
+  SolveArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.ur0 = c.ur;
+  a.uz0 = c.uz;
+  a.h0 = c.h;
+  a.Ir = c.Ir;
+  a.Iz = c.Iz;
+  a.vnext = drive(c.g, c.t + c.g.dt);
+  a.vhalf = 0.5 * (drive(c.g, c.t) + a.vnext);
+  a.ur1 = c.ur_nx;
+  a.uz1 = c.uz_nx;
+  a.h1 = c.h_nx;
+  a.ur_old = c.ur_it;
+  a.uz_old = c.uz_it;
+  a.part = c.sol.partial + kOffRes;
+  a.ur_h = c.ur_half2;
+  a.uz_h = c.uz_half2;
+  a.ur_hf = c.ur_half_f2;
+  a.uz_hf = c.uz_half_f2;
+  a.zero_I = 1;
   {
-    // field arrays: u0, I, h0 read, u1, h1 written (FP64)
-    const double fb = 8.0 * (3.0 * (n_edges_r(c) + n_edges_z(c)) + 2.0 * n_cells(c));
+    // field arrays: u0, I, u_old read, u1 and the half field written, h0 read,
+    // h1 written (FP64)
+    const double fb = 8.0 * (6.0 * (n_edges_r(c) + n_edges_z(c)) + 2.0 * n_cells(c));
     Timed tm(c, ECPIC_K_FIELD, fb, 0);
-    HIPCHK(field_solve(c, c.ur, c.uz, c.h, c.Ir, c.Iz, vh, vnext, c.ur_nx, c.uz_nx, c.h_nx,
-                       c.stream));
+    HIPCHK(field_solve(c, a, c.stream));
   }
-  double* d_red = c.sol.partial + 4000;
-  HIPCHK(launch_resid(c, c.ur_nx, c.uz_nx, c.ur_it, c.uz_it, d_red, c.stream));
-  HIPCHK(hipMemcpyAsync(c.red_host, d_red, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipMemcpyAsync(c.part_host + kOffRes, c.sol.partial + kOffRes, 2 * nr * sizeof(double),
+                        hipMemcpyDeviceToHost, c.stream));
   std::swap(c.ur_it, c.ur_nx);
   std::swap(c.uz_it, c.uz_nx);
   std::swap(c.h_it, c.h_nx);
   HIPCHK(hipStreamSynchronize(c.stream));
   collect(c);
-  const double num = c.red_host[0], den = c.red_host[1];
+  double num = 0.0, den = 0.0;
+  for (int i = 0; i < nr; ++i) {
+    num += c.part_host[kOffRes + 2 * i];
+    den += c.part_host[kOffRes + 2 * i + 1];
+  }
   *r_out = den > 0.0 ? std::sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
   return ECPIC_OK;
+}
+
+static void swap_half(Ctx& c) {
+  std::swap(c.ur_half, c.ur_half2);
+  std::swap(c.uz_half, c.uz_half2);
+  std::swap(c.ur_half_f, c.ur_half_f2);
+  std::swap(c.uz_half_f, c.uz_half_f2);
 }
 
 ecpic_status ecpic_field_iterate(ecpic_ctx* x, double* rel) {
@@ -614,7 +691,7 @@ ecpic_status ecpic_field_iterate(ecpic_ctx* x, double* rel) {
   Ctx& c = x->c;
   ecpic_status rc = iterate(c, rel);
   if (rc != ECPIC_OK) return rc;
-  HIPCHK(launch_half(c, c.ur, c.uz, c.ur_it, c.uz_it, c.stream));
+  swap_half(c);
   return ECPIC_OK;
 }
 
@@ -676,16 +753,22 @@ ecpic_status ecpic_node_charge(ecpic_ctx* x, double* q, double* bot, double* top
 }
 
 static ecpic_status diag_into(Ctx& c, ecpic_step_stats* st) {
-  double* d = c.sol.partial + 4000;
-  HIPCHK(launch_zero(d + 8, 8, c.stream));
+  double* d = c.sol.partial;
+  HIPCHK(launch_zero(d + kOffKE, 8, c.stream));
   for (size_t s = 0; s < c.sp.size() && s < 4; ++s)
-    HIPCHK(launch_kinetic(c.sp[s], c.prec == ECPIC_MIXED, d + 8 + s, c.stream));
-  HIPCHK(launch_field_energy(c, c.ur, c.uz, c.h, d + 2, c.stream));
-  HIPCHK(hipMemcpyAsync(c.red_host, d, 16 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(launch_kinetic(c.sp[s], c.prec == ECPIC_MIXED, d + kOffKE + s, c.stream));
+  HIPCHK(launch_field_energy(c, c.ur, c.uz, c.h, d + kOffFE, c.stream));
+  HIPCHK(hipMemcpyAsync(c.part_host + kOffFE, d + kOffFE, (kOffSc - kOffFE) * sizeof(double),
+                        hipMemcpyDeviceToHost, c.stream));
   HIPCHK(hipStreamSynchronize(c.stream));
-  st->we = 0.5 * c.red_host[2];
-  st->wb = 0.5 * c.g.mu * c.red_host[3];
-  for (size_t s = 0; s < 4; ++s) st->ke[s] = (s < c.sp.size()) ? c.red_host[8 + s] : 0.0;
+  double se = 0.0, sb = 0.0;
+  for (int b = 0; b < kRedBlocks; ++b) {
+    se += c.part_host[kOffFE + b];
+    sb += c.part_host[kOffFE + kRedBlocks + b];
+  }
+  st->we = 0.5 * se;
+  st->wb = 0.5 * c.g.mu * sb;
+  for (size_t s = 0; s < 4; ++s) st->ke[s] = (s < c.sp.size()) ? c.part_host[kOffKE + s] : 0.0;
   for (size_t s = 0; s < c.sp.size() && s < 4; ++s) st->n_alive[s] = c.sp[s].n;
   st->t = c.t;
   st->step = c.step;
@@ -737,7 +820,7 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
   bool conv = false;
   double prev_r = INFINITY;
   for (k = 0; k < kmax; ++k) {
-    ecpic_status rc = pass(c, 0, false, c.step);
+    ecpic_status rc = pass(c, 0, false, c.step, false);
     if (rc != ECPIC_OK) return rc;
     double r;
     rc = iterate(c, &r);
@@ -749,7 +832,9 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
       break;
     }
     prev_r = r;
-    if (k + 1 < kmax) HIPCHK(launch_half(c, c.ur, c.uz, c.ur_it, c.uz_it, c.stream));
+    // the next push uses (u^n + u^{n+1,(k+1)}) / 2; after the last pass the
+    // commit keeps the field of that pass
+    if (k + 1 < kmax) swap_half(c);
   }
   (void)prev_r;
   S->iters = k;
@@ -757,12 +842,13 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
   S->converged = conv ? 1 : 0;
   if (!conv) return fail(c, ECPIC_ENOTCONV, "Picard iteration did not converge");
   // commit the particles pushed in the accepted half-step field, with MCC
-  ecpic_status rc = pass(c, 1, c.mcc.enabled != 0, c.step);
+  ecpic_status rc = pass(c, 1, c.mcc.enabled != 0, c.step, false);
   if (rc != ECPIC_OK) return rc;
-  double* d = c.sol.partial + 4000;
-  HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir, c.Iz, d + 4, c.stream));
+  double* d = c.sol.partial;
+  HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir, c.Iz, d + kOffEx, c.stream));
   const int nr = c.g.nr, nz = c.g.nz;
-  HIPCHK(hipMemcpyAsync(c.red_host + 32, d + 4, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipMemcpyAsync(c.part_host + kOffEx, d + kOffEx, kRedBlocks * sizeof(double),
+                        hipMemcpyDeviceToHost, c.stream));
   HIPCHK(hipMemcpyAsync(c.red_host + 33, c.h + (int64_t)(nr - 1) * nz, sizeof(double),
                         hipMemcpyDeviceToHost, c.stream));
   HIPCHK(hipMemcpyAsync(c.red_host + 34, c.h_it + (int64_t)(nr - 1) * nz, sizeof(double),
@@ -773,7 +859,9 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
   rc = finish_tally(c, t);  // synchronises
   const double vh = 0.5 * (vnow + vnext);
   const double rgap = r_of_xi(c.m, nr - 0.5);
-  S->w_field_io = c.g.dt * c.red_host[32];
+  double xs = 0.0;
+  for (int b = 0; b < kRedBlocks; ++b) xs += c.part_host[kOffEx + b];
+  S->w_field_io = c.g.dt * xs;
   S->w_drive = c.g.dt * (2.0 * kPi * rgap * 0.5 * (c.red_host[33] + c.red_host[34]) * vh +
                          vh * c.red_host[35]);
   S->w_particles = t.w_particles;

@@ -2,11 +2,21 @@
 // Sec. 2.1 with mid-point centring) with H_theta as the unknown.
 //
 // Eliminating the interior edge voltages leaves an SPD system for
-// h^{n+1/2} that is T (x) I + G (x) N, where N is the Neumann second
+// h^{n+1/2} of the form T (x) I + G (x) N, where N is the Neumann second
 // difference in z (the PEC r-edges of the z walls decouple the end cells).
-// It is solved by an orthonormal DCT-II in z (dense FP64 product with a
-// precomputed matrix), one tridiagonal (Thomas) solve in r per z-mode, and the
-// inverse DCT; then the edge voltages are recovered from Ampere's law.
+// Three kernels solve it:
+//   k_rhs_dct      one block per radial row: the right-hand side of the row
+//                  into LDS, then its orthonormal DCT-II (precomputed FP64
+//                  matrix, L2-resident), written mode-major;
+//   k_tri_scan     one block per z-mode: the tridiagonal system in r with
+//                  precomputed LU factors, forward and backward substitution
+//                  done as parallel scans of affine maps (the recurrences
+//                  y_i = d_i - l_i y_{i-1}, x_i = (y_i - e_{i+1} x_{i+1}) / c_i
+//                  compose associatively);
+//   k_idct_recover one block per row: inverse DCT of rows i and i-1, the edge
+//                  voltages from Ampere's law, h^{n+1}, the next half-step
+//                  field, per-row partial sums of the Picard residual, and the
+//                  reset of the consumed currents.
 #include "ecpic_internal.h"
 
 namespace ecpic {
@@ -14,148 +24,277 @@ namespace ecpic {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kFB = 256;  // threads per block of the field kernels
 
 inline int64_t nblk(int64_t n) { return (n + kBlock - 1) / kBlock; }
 
 // rhs[i][j] = 2 pi r_{i+1/2} (2 mu A_c / dt h0 + circulation of u0 - D^-1 I)
-// with the half-step drive value on the gap edge and zero on other walls.
-__global__ void k_rhs(MapP m, const double* __restrict__ rh, const double* __restrict__ wr,
-                      const double* __restrict__ wz, const double* __restrict__ area, double mu,
-                      const double* __restrict__ ur0, const double* __restrict__ uz0,
-                      const double* __restrict__ h0, const double* __restrict__ Ir,
-                      const double* __restrict__ Iz, double vhalf, double* __restrict__ rhs) {
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+// with the half-step drive value on the gap edge and zero on other walls,
+// then hat[k][i] = sum_j Q[k][j] rhs[i][j].
+__global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restrict__ rh,
+                                                 const double* __restrict__ wr,
+                                                 const double* __restrict__ wz,
+                                                 const double* __restrict__ area, double mu,
+                                                 const double* __restrict__ ur0,
+                                                 const double* __restrict__ uz0,
+                                                 const double* __restrict__ h0,
+                                                 const double* __restrict__ Ir,
+                                                 const double* __restrict__ Iz, double vhalf,
+                                                 const double* __restrict__ Qt,
+                                                 double* __restrict__ hat) {
+  extern __shared__ double sh[];
   const int nr = m.nr, nz = m.nz;
-  if (c >= (int64_t)nr * nz) return;
-  const int i = int(c / nz), j = int(c - (int64_t)i * nz);
+  const int i = blockIdx.x;
   const double hdt = 0.5 * m.dt;
-  auto tr = [&](int jj) -> double {
-    if (jj == 0) return (i == nr - 1) ? vhalf : 0.0;
-    if (jj == nz) return 0.0;
-    const int64_t e = (int64_t)i * (nz + 1) + jj;
-    return ur0[e] - hdt * Ir[e] / wr[i];
-  };
-  auto tz = [&](int ii) -> double {
-    if (ii == nr) return 0.0;
-    const int64_t e = (int64_t)ii * nz + j;
-    return uz0[e] - hdt * Iz[e] / wz[ii];
-  };
-  const double circ = tz(i + 1) - tz(i) - tr(j + 1) + tr(j);
   const double mi = 2.0 * kPi * rh[i];
-  rhs[c] = mi * (2.0 * mu * area[i] / m.dt * h0[c] + circ);
+  const double mass = 2.0 * mu * area[i] / m.dt;
+  const double iwr = hdt / wr[i], iwz = hdt / wz[i];
+  const double iwz1 = (i + 1 < nr) ? hdt / wz[i + 1] : 0.0;
+  const double* urr = ur0 + (int64_t)i * (nz + 1);
+  const double* Irr = Ir + (int64_t)i * (nz + 1);
+  for (int j = threadIdx.x; j < nz; j += blockDim.x) {
+    // r-edges j (bottom) and j+1 (top) of cell (i, j)
+    double rb, rt;
+    if (j == 0)
+      rb = (i == nr - 1) ? vhalf : 0.0;
+    else
+      rb = urr[j] - Irr[j] * iwr;
+    if (j + 1 == nz)
+      rt = 0.0;
+    else
+      rt = urr[j + 1] - Irr[j + 1] * iwr;
+    // z-edges i (left) and i+1 (right)
+    const int64_t el = (int64_t)i * nz + j;
+    const double zl = uz0[el] - Iz[el] * iwz;
+    const double zr = (i + 1 < nr) ? uz0[el + nz] - Iz[el + nz] * iwz1 : 0.0;
+    sh[j] = mi * (mass * h0[el] + (zr - zl - rt + rb));
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+    double acc = 0.0;
+    const double* q = Qt + k;
+    for (int j = 0; j < nz; ++j) acc = fma(sh[j], q[(int64_t)j * nz], acc);
+    hat[(int64_t)k * nr + i] = acc;
+  }
 }
 
-// C[M][N] = A[M][K] B[K][N], FP64, 64x64 tiles, 16 x 16 threads x (4 x 4)
-constexpr int GT = 64, GK = 16;
-__global__ void __launch_bounds__(256) k_gemm(const double* __restrict__ A,
-                                              const double* __restrict__ B, double* __restrict__ C,
-                                              int M, int N, int K) {
-  __shared__ double As[GK][GT + 1];
-  __shared__ double Bs[GK][GT + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int row0 = blockIdx.y * GT, col0 = blockIdx.x * GT;
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += GK) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = threadIdx.x + q * 256;
-      const int r = idx / GK, cc = idx % GK;
-      As[cc][r] = (row0 + r < M && k0 + cc < K) ? A[(int64_t)(row0 + r) * K + k0 + cc] : 0.0;
-      const int rb = idx / GT, cb = idx % GT;
-      Bs[rb][cb] = (k0 + rb < K && col0 + cb < N) ? B[(int64_t)(k0 + rb) * N + col0 + cb] : 0.0;
-    }
+// (A, B) maps y -> A y + B; compose(later, earlier) = later o earlier
+struct Aff {
+  double A, B;
+};
+__device__ __forceinline__ Aff compose(Aff later, Aff earlier) {
+  return Aff{later.A * earlier.A, fma(later.A, earlier.B, later.B)};
+}
+
+// exclusive scan of per-thread affine maps in thread order (reverse = false)
+// or in reverse thread order; returns the composition of all maps before me
+__device__ Aff block_exscan(Aff v, bool reverse, Aff* sA) {
+  const int n = blockDim.x;
+  const int t = reverse ? (n - 1 - (int)threadIdx.x) : (int)threadIdx.x;
+  sA[t] = v;
+  __syncthreads();
+  for (int off = 1; off < n; off <<= 1) {
+    Aff mine = sA[t];
+    Aff other = (t >= off) ? sA[t - off] : Aff{1.0, 0.0};
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GK; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[kk][ty + 16 * q];
-        b[q] = Bs[kk][tx + 16 * q];
-      }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
-    }
+    if (t >= off) sA[t] = compose(mine, other);
     __syncthreads();
   }
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = row0 + ty + 16 * p, cc = col0 + tx + 16 * q;
-      if (r < M && cc < N) C[(int64_t)r * N + cc] = acc[p][q];
-    }
+  const Aff r = (t > 0) ? sA[t - 1] : Aff{1.0, 0.0};
+  __syncthreads();
+  return r;
 }
 
-// per z-mode k: (T + lambda_k G) x = d over i, factors precomputed
-__global__ void k_thomas(int nr, int nz, const double* __restrict__ lo,
-                         const double* __restrict__ inv, const double* __restrict__ up,
-                         double* __restrict__ x) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nz) return;
+constexpr int kMaxE = 8;  // rows per thread: nr <= kFB * kMaxE
+
+__global__ void __launch_bounds__(kFB) k_tri_scan(int nr, const double* __restrict__ lo,
+                                                  const double* __restrict__ inv,
+                                                  const double* __restrict__ up,
+                                                  double* __restrict__ hat) {
+  __shared__ Aff sA[kFB];
+  const int k = blockIdx.x;
+  double* x = hat + (int64_t)k * nr;
   const double* L = lo + (int64_t)k * nr;
   const double* Iv = inv + (int64_t)k * nr;
-  double y = x[k];
-  for (int i = 1; i < nr; ++i) {
-    const double d = x[(int64_t)i * nz + k] - L[i] * y;
-    x[(int64_t)i * nz + k] = d;
-    y = d;
+  const int E = (nr + blockDim.x - 1) / blockDim.x;
+  const int i0 = threadIdx.x * E;
+  const int i1 = min(i0 + E, nr);
+  double y[kMaxE];
+  // forward: y_i = -l_i y_{i-1} + d_i (l_0 = 0)
+  Aff f{1.0, 0.0};
+  for (int q = 0; q < E; ++q) {
+    const int i = i0 + q;
+    if (i < i1) {
+      y[q] = x[i];
+      const Aff g{i == 0 ? 0.0 : -L[i], y[q]};
+      f = compose(g, f);
+    }
   }
-  double xn = x[(int64_t)(nr - 1) * nz + k] * Iv[nr - 1];
-  x[(int64_t)(nr - 1) * nz + k] = xn;
-  for (int i = nr - 2; i >= 0; --i) {
-    const double v = (x[(int64_t)i * nz + k] - up[i + 1] * xn) * Iv[i];
-    x[(int64_t)i * nz + k] = v;
-    xn = v;
+  const Aff pf = block_exscan(f, false, sA);
+  double yp = pf.B;
+  for (int q = 0; q < E; ++q) {
+    const int i = i0 + q;
+    if (i < i1) {
+      const double a = (i == 0) ? 0.0 : -L[i];
+      yp = fma(a, yp, y[q]);
+      y[q] = yp;
+    }
+  }
+  // backward: x_i = (-inv_i e_{i+1}) x_{i+1} + inv_i y_i (e_nr = 0)
+  Aff g{1.0, 0.0};
+  for (int q = E - 1; q >= 0; --q) {
+    const int i = i0 + q;
+    if (i < i1) {
+      const double c = (i + 1 < nr) ? -Iv[i] * up[i + 1] : 0.0;
+      const Aff h{c, Iv[i] * y[q]};
+      g = compose(h, g);
+    }
+  }
+  const Aff pb = block_exscan(g, true, sA);
+  double xn = pb.B;
+  for (int q = E - 1; q >= 0; --q) {
+    const int i = i0 + q;
+    if (i < i1) {
+      const double c = (i + 1 < nr) ? -Iv[i] * up[i + 1] : 0.0;
+      xn = fma(c, xn, Iv[i] * y[q]);
+      x[i] = xn;
+    }
   }
 }
 
-// u^{1/2} = u0 + D^-1 (K h^{1/2} - I) on interior edges; n+1 values; walls.
-__global__ void k_recover(MapP m, const double* __restrict__ rh, const double* __restrict__ wr,
-                          const double* __restrict__ wz, const double* __restrict__ ur0,
-                          const double* __restrict__ uz0, const double* __restrict__ h0,
-                          const double* __restrict__ Ir, const double* __restrict__ Iz,
-                          const double* __restrict__ x, double vnext, double* __restrict__ ur1,
-                          double* __restrict__ uz1, double* __restrict__ h1) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void block_sum2(double& s0, double& s1, double* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_down(s0, off, 64);
+    s1 += __shfl_down(s1, off, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * w] = s0;
+    red[2 * w + 1] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+      a += red[2 * q];
+      b += red[2 * q + 1];
+    }
+    s0 = a;
+    s1 = b;
+  }
+}
+
+__global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
+                                                      const double* __restrict__ rh,
+                                                      const double* __restrict__ wr,
+                                                      const double* __restrict__ wz,
+                                                      const double* __restrict__ Q,
+                                                      const double* __restrict__ hat) {
+  extern __shared__ double sh[];
   const int nr = m.nr, nz = m.nz;
+  const int i = blockIdx.x;
+  double* hi = sh;           // hat[.][i]
+  double* hm = sh + nz;      // hat[.][i-1]
+  double* xi_ = sh + 2 * nz; // x[i][.]
+  double* xm = sh + 3 * nz;  // x[i-1][.]
+  __shared__ double red[2 * (kFB / 64)];
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+    hi[k] = hat[(int64_t)k * nr + i];
+    hm[k] = (i > 0) ? hat[(int64_t)k * nr + i - 1] : 0.0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nz; j += blockDim.x) {
+    double s = 0.0, t = 0.0;
+    for (int k = 0; k < nz; ++k) {
+      const double qv = Q[(int64_t)k * nz + j];
+      s = fma(hi[k], qv, s);
+      t = fma(hm[k], qv, t);
+    }
+    xi_[j] = s;
+    xm[j] = t;
+  }
+  __syncthreads();
   const double hdt = 0.5 * m.dt;
-  const int64_t nur = (int64_t)nr * (nz + 1), nuz = (int64_t)(nr + 1) * nz, nh = (int64_t)nr * nz;
-  if (t < nur) {
-    const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
-    double v;
-    if (j == 0) {
-      v = (i == nr - 1) ? vnext : 0.0;
-    } else if (j == nz) {
-      v = 0.0;
-    } else {
-      const double K = -2.0 * kPi * rh[i] * (x[(int64_t)i * nz + j] - x[(int64_t)i * nz + j - 1]);
-      const double uh = ur0[t] + hdt * (K - Ir[t]) / wr[i];
-      v = 2.0 * uh - ur0[t];
+  const double two_pi = 2.0 * kPi;
+  double s0 = 0.0, s1 = 0.0;
+  // r-edges of row i
+  {
+    const double w = wr[i], iw = hdt / w, ri = two_pi * rh[i];
+    for (int j = threadIdx.x; j <= nz; j += blockDim.x) {
+      const int64_t e = (int64_t)i * (nz + 1) + j;
+      double v;
+      if (j == 0) {
+        v = (i == nr - 1) ? a.vnext : 0.0;
+      } else if (j == nz) {
+        v = 0.0;
+      } else {
+        const double K = -ri * (xi_[j] - xi_[j - 1]);
+        const double uh = a.ur0[e] + (K - a.Ir[e]) * iw;
+        v = 2.0 * uh - a.ur0[e];
+        if (a.part) {
+          const double d = v - a.ur_old[e];
+          s0 += w * d * d;
+          s1 += w * v * v;
+        }
+      }
+      a.ur1[e] = v;
+      if (a.ur_h) {
+        const double hv = 0.5 * (a.ur0[e] + v);
+        a.ur_h[e] = hv;
+        if (a.ur_hf) a.ur_hf[e] = float(hv);
+      }
+      if (a.zero_I) a.Ir[e] = 0.0;
     }
-    ur1[t] = v;
   }
-  if (t < nuz) {
-    const int i = int(t / nz), j = int(t - (int64_t)i * nz);
-    double v = 0.0;
-    if (i < nr) {
-      double K = 2.0 * kPi * rh[i] * x[(int64_t)i * nz + j];
-      if (i > 0) K -= 2.0 * kPi * rh[i - 1] * x[(int64_t)(i - 1) * nz + j];
-      const double uh = uz0[t] + hdt * (K - Iz[t]) / wz[i];
-      v = 2.0 * uh - uz0[t];
+  // z-edges of row i (and the PEC row nr, owned by the last block)
+  {
+    const double w = wz[i], iw = hdt / w, ri = two_pi * rh[i];
+    const double rm = (i > 0) ? two_pi * rh[i - 1] : 0.0;
+    for (int j = threadIdx.x; j < nz; j += blockDim.x) {
+      const int64_t e = (int64_t)i * nz + j;
+      const double K = ri * xi_[j] - rm * xm[j];
+      const double uh = a.uz0[e] + (K - a.Iz[e]) * iw;
+      const double v = 2.0 * uh - a.uz0[e];
+      if (a.part) {
+        const double d = v - a.uz_old[e];
+        s0 += w * d * d;
+        s1 += w * v * v;
+      }
+      a.uz1[e] = v;
+      if (a.uz_h) {
+        const double hv = 0.5 * (a.uz0[e] + v);
+        a.uz_h[e] = hv;
+        if (a.uz_hf) a.uz_hf[e] = float(hv);
+      }
+      if (a.zero_I) a.Iz[e] = 0.0;
+      a.h1[e] = 2.0 * xi_[j] - a.h0[e];
+      if (i == nr - 1) {
+        const int64_t ew = (int64_t)nr * nz + j;
+        a.uz1[ew] = 0.0;
+        if (a.uz_h) {
+          const double hv = 0.5 * a.uz0[ew];
+          a.uz_h[ew] = hv;
+          if (a.uz_hf) a.uz_hf[ew] = float(hv);
+        }
+        if (a.zero_I) a.Iz[ew] = 0.0;
+      }
     }
-    uz1[t] = v;
   }
-  if (t < nh) h1[t] = 2.0 * x[t] - h0[t];
+  if (a.part) {
+    block_sum2(s0, s1, red);
+    if (threadIdx.x == 0) {
+      a.part[2 * i] = s0;
+      a.part[2 * i + 1] = s1;
+    }
+  }
 }
 
 // guess u^{n+1,(0)} = 2 u^n - u^{n-1} (walls at t^{n+1}), the half-step field
-// of the first push, and the wall values of u^n at t^n.
+// of the first push, the wall values of u^n at t^n, and zeroed currents.
 __global__ void k_guess_half(MapP m, double* ur, double* uz, const double* ur_prev,
                              const double* uz_prev, double* ur_it, double* uz_it, double* ur_h,
-                             double* uz_h, float* ur_hf, float* uz_hf, double vnow, double vnext) {
+                             double* uz_h, float* ur_hf, float* uz_hf, double* Ir, double* Iz,
+                             double vnow, double vnext) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int nr = m.nr, nz = m.nz;
   const int64_t nur = (int64_t)nr * (nz + 1), nuz = (int64_t)(nr + 1) * nz;
@@ -174,6 +313,7 @@ __global__ void k_guess_half(MapP m, double* ur, double* uz, const double* ur_pr
     const double h = 0.5 * (u0 + u1);
     ur_h[t] = h;
     if (ur_hf) ur_hf[t] = float(h);
+    Ir[t] = 0.0;
   }
   if (t < nuz) {
     const int i = int(t / nz);
@@ -189,6 +329,7 @@ __global__ void k_guess_half(MapP m, double* ur, double* uz, const double* ur_pr
     const double h = 0.5 * (u0 + u1);
     uz_h[t] = h;
     if (uz_hf) uz_hf[t] = float(h);
+    Iz[t] = 0.0;
   }
 }
 
@@ -209,62 +350,39 @@ __global__ void k_half(MapP m, const double* u0r, const double* u0z, const doubl
   }
 }
 
-constexpr int kRedBlocks = 256;
-
-// partial sums over interior edges: [0] sum w (a-b)^2, [1] sum w a^2
-// (b may be null: then [0] = sum w a^2 too)
+// partial sums over interior edges of w a^2 (weights eps A*/l): one value per
+// block, summed on the host in block order
 __global__ void __launch_bounds__(kBlock) k_norm2(MapP m, const double* __restrict__ wr,
                                                   const double* __restrict__ wz,
                                                   const double* __restrict__ ar,
                                                   const double* __restrict__ az,
-                                                  const double* __restrict__ br,
-                                                  const double* __restrict__ bz,
                                                   double* __restrict__ part) {
   const int nr = m.nr, nz = m.nz;
-  const int64_t nur = (int64_t)nr * (nz + 1), nuz = (int64_t)nr * nz;  // interior z-edges i<nr
-  double s0 = 0.0, s1 = 0.0;
+  const int64_t nur = (int64_t)nr * (nz + 1), nuz = (int64_t)nr * nz;
+  double s = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nur + nuz;
        t += (int64_t)gridDim.x * kBlock) {
-    double w, a, b;
     if (t < nur) {
       const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
       if (j == 0 || j == nz) continue;
-      w = wr[i];
-      a = ar[t];
-      b = br ? br[t] : 0.0;
+      s += wr[i] * ar[t] * ar[t];
     } else {
       const int64_t e = t - nur;
-      const int i = int(e / nz);
-      w = wz[i];
-      a = az[e];
-      b = bz ? bz[e] : 0.0;
+      s += wz[e / nz] * az[e] * az[e];
     }
-    s0 += w * (a - b) * (a - b);
-    s1 += w * a * a;
   }
-  __shared__ double r0[kBlock / 64], r1[kBlock / 64];
-  for (int off = 32; off > 0; off >>= 1) {
-    s0 += __shfl_down(s0, off, 64);
-    s1 += __shfl_down(s1, off, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    r0[threadIdx.x >> 6] = s0;
-    r1[threadIdx.x >> 6] = s1;
-  }
+  __shared__ double r0[kBlock / 64];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) r0[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
-    for (int q = 0; q < kBlock / 64; ++q) {
-      a += r0[q];
-      b += r1[q];
-    }
-    part[2 * blockIdx.x] = a;
-    part[2 * blockIdx.x + 1] = b;
+    double v = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) v += r0[q];
+    part[blockIdx.x] = v;
   }
 }
 
-// sum w_c h^2 with w_c = 2 pi r A_c (magnetic energy weight), and
-// sum over interior edges of ((a+b)/2) I (field-side exchange)
+// partial sums of 2 pi r A_c h^2 (magnetic energy weight)
 __global__ void __launch_bounds__(kBlock) k_hsum(MapP m, const double* __restrict__ rh,
                                                  const double* __restrict__ area,
                                                  const double* __restrict__ h,
@@ -281,12 +399,13 @@ __global__ void __launch_bounds__(kBlock) k_hsum(MapP m, const double* __restric
   if ((threadIdx.x & 63) == 0) r0[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0;
-    for (int q = 0; q < kBlock / 64; ++q) a += r0[q];
-    part[blockIdx.x] = a;
+    double v = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) v += r0[q];
+    part[blockIdx.x] = v;
   }
 }
 
+// partial sums over interior edges of ((a + b)/2) I (field-side exchange)
 __global__ void __launch_bounds__(kBlock) k_xsum(MapP m, const double* __restrict__ ar,
                                                  const double* __restrict__ az,
                                                  const double* __restrict__ br,
@@ -300,8 +419,7 @@ __global__ void __launch_bounds__(kBlock) k_xsum(MapP m, const double* __restric
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nur + nuz;
        t += (int64_t)gridDim.x * kBlock) {
     if (t < nur) {
-      const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
-      (void)i;
+      const int j = int(t % (nz + 1));
       if (j == 0 || j == nz) continue;
       s += 0.5 * (ar[t] + br[t]) * Ir[t];
     } else {
@@ -314,18 +432,10 @@ __global__ void __launch_bounds__(kBlock) k_xsum(MapP m, const double* __restric
   if ((threadIdx.x & 63) == 0) r0[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0;
-    for (int q = 0; q < kBlock / 64; ++q) a += r0[q];
-    part[blockIdx.x] = a;
+    double v = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) v += r0[q];
+    part[blockIdx.x] = v;
   }
-}
-
-// fixed-order final sum of `cnt` interleaved partial vectors of width w
-__global__ void k_final(const double* part, int nb, int w, double* out) {
-  if (threadIdx.x >= w) return;
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * w + threadIdx.x];
-  out[threadIdx.x] = s;
 }
 
 }  // namespace
@@ -334,7 +444,7 @@ hipError_t launch_guess_half(const Ctx& c, double vnow, double vnext, hipStream_
   const int64_t n = (int64_t)(c.g.nr + 1) * (c.g.nz + 1);
   hipLaunchKernelGGL(k_guess_half, dim3(nblk(n)), dim3(kBlock), 0, s, c.m, c.ur, c.uz, c.ur_prev,
                      c.uz_prev, c.ur_it, c.uz_it, c.ur_half, c.uz_half, c.ur_half_f, c.uz_half_f,
-                     vnow, vnext);
+                     c.Ir, c.Iz, vnow, vnext);
   return hipGetLastError();
 }
 
@@ -346,53 +456,34 @@ hipError_t launch_half(const Ctx& c, const double* u0r, const double* u0z, const
   return hipGetLastError();
 }
 
-hipError_t field_solve(const Ctx& c, const double* ur0, const double* uz0, const double* h0,
-                       const double* Ir, const double* Iz, double vhalf, double vnext,
-                       double* ur1, double* uz1, double* h1, hipStream_t s) {
+hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s) {
   const int nr = c.g.nr, nz = c.g.nz;
   const SolverDev& S = c.sol;
-  const int64_t nh = (int64_t)nr * nz;
-  hipLaunchKernelGGL(k_rhs, dim3(nblk(nh)), dim3(kBlock), 0, s, c.m, S.rh, S.wr, S.wz, S.area,
-                     c.g.mu, ur0, uz0, h0, Ir, Iz, vhalf, S.work0);
-  const dim3 gg((nz + GT - 1) / GT, (nr + GT - 1) / GT);
-  hipLaunchKernelGGL(k_gemm, gg, dim3(256), 0, s, S.work0, S.Qt, S.work1, nr, nz, nz);
-  hipLaunchKernelGGL(k_thomas, dim3((nz + 63) / 64), dim3(64), 0, s, nr, nz, S.tri_lo, S.tri_inv,
-                     S.tri_up, S.work1);
-  hipLaunchKernelGGL(k_gemm, gg, dim3(256), 0, s, S.work1, S.Q, S.work0, nr, nz, nz);
-  const int64_t n = (int64_t)(nr + 1) * (nz + 1);
-  hipLaunchKernelGGL(k_recover, dim3(nblk(n)), dim3(kBlock), 0, s, c.m, S.rh, S.wr, S.wz, ur0, uz0,
-                     h0, Ir, Iz, S.work0, vnext, ur1, uz1, h1);
-  return hipGetLastError();
-}
-
-hipError_t launch_resid(const Ctx& c, const double* anr, const double* anz, const double* bor,
-                        const double* boz, double* out2, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm2, dim3(kRedBlocks), dim3(kBlock), 0, s, c.m, c.sol.wr, c.sol.wz, anr,
-                     anz, bor, boz, c.sol.partial);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, c.sol.partial, kRedBlocks, 2, out2);
+  if (nr > kFB * kMaxE) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_rhs_dct, dim3(nr), dim3(kFB), sizeof(double) * nz, s, c.m, S.rh, S.wr,
+                     S.wz, S.area, c.g.mu, a.ur0, a.uz0, a.h0, a.Ir, a.Iz, a.vhalf, S.Qt, S.work1);
+  hipLaunchKernelGGL(k_tri_scan, dim3(nz), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv, S.tri_up,
+                     S.work1);
+  hipLaunchKernelGGL(k_idct_recover, dim3(nr), dim3(kFB), sizeof(double) * 4 * nz, s, a, c.m,
+                     S.rh, S.wr, S.wz, S.Q, S.work1);
   return hipGetLastError();
 }
 
 hipError_t launch_field_energy(const Ctx& c, const double* ur, const double* uz, const double* h,
-                               double* out2, hipStream_t s) {
-  // out2[0] = sum w u^2 (2 W_E / 1), out2[1] = sum 2 pi r A_c h^2 (2 W_B / mu)
+                               double* part, hipStream_t s) {
+  // part[0..kRed) = sum w u^2 partials, part[kRed..2 kRed) = sum 2 pi r A_c h^2
   hipLaunchKernelGGL(k_norm2, dim3(kRedBlocks), dim3(kBlock), 0, s, c.m, c.sol.wr, c.sol.wz, ur,
-                     uz, nullptr, nullptr, c.sol.partial);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, c.sol.partial, kRedBlocks, 2, out2);
+                     uz, part);
   hipLaunchKernelGGL(k_hsum, dim3(kRedBlocks), dim3(kBlock), 0, s, c.m, c.sol.rh, c.sol.area, h,
-                     c.sol.partial + 2 * kRedBlocks);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, c.sol.partial + 2 * kRedBlocks, kRedBlocks,
-                     1, out2 + 1);
+                     part + kRedBlocks);
   return hipGetLastError();
 }
 
 hipError_t launch_exchange(const Ctx& c, const double* ar, const double* az, const double* br,
-                           const double* bz, const double* Ir, const double* Iz, double* out1,
+                           const double* bz, const double* Ir, const double* Iz, double* part,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_xsum, dim3(kRedBlocks), dim3(kBlock), 0, s, c.m, ar, az, br, bz, Ir, Iz,
-                     c.sol.partial + 3 * kRedBlocks);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, c.sol.partial + 3 * kRedBlocks, kRedBlocks,
-                     1, out1);
+                     part);
   return hipGetLastError();
 }
 

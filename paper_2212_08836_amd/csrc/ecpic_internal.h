@@ -78,6 +78,23 @@ struct PushArgs {
   int32_t* hist;     // per-cell counts of the survivors (commit), or null
 };
 
+// One Crank-Nicolson field solve.  Optional outputs (null = skipped): the
+// residual partials against the previous iterate, the next half-step field,
+// and the reset of the consumed currents.
+struct SolveArgs {
+  const double *ur0, *uz0, *h0;
+  double *Ir, *Iz;
+  double vhalf, vnext;
+  double *ur1, *uz1, *h1;
+  const double *ur_old, *uz_old;
+  double* part;         // [2 * nr]: per row sum w (u1 - u_old)^2, sum w u1^2
+  double *ur_h, *uz_h;  // (u0 + u1) / 2
+  float *ur_hf, *uz_hf;
+  int32_t zero_I;
+};
+
+constexpr int kRedBlocks = 256;  // partial-sum blocks of the field reductions
+
 struct Species {
   ecpic_species_desc desc;
   SpecDev d[2];  // ping-pong buffers for the sort
@@ -115,12 +132,18 @@ struct Ctx {
   double *ur_nx, *uz_nx, *h_nx;    // u^{n+1,(k+1)} being produced
   double *ur_half, *uz_half;       // half-step field of the current push
   float *ur_half_f, *uz_half_f;    // FP32 copy (mixed path)
+  double *ur_half2, *uz_half2;     // half-step field of the next push
+  float *ur_half_f2, *uz_half_f2;
+  double* part_host;               // pinned host copy of reduction partials
   double *Ir, *Iz;                 // currents
   double *wall_bot, *wall_top, *wall_side;
   int32_t* hist;                   // per-cell counts [nr*nz + 1]
   int32_t* offs;                   // per-cell offsets [nr*nz + 1]
   int32_t* scan_part;              // scan block sums
   Tally* tally;                    // device tally
+  int32_t* queue = nullptr;        // slow-pass particle queue
+  int64_t queue_cap = 0;
+  int32_t* qcount = nullptr;       // per-species queue lengths [kMaxSpecies]
   Tally* tally_host;               // pinned host mirror
   double* red_host;                // pinned host reduction results
   SolverDev sol;
@@ -149,7 +172,9 @@ struct Ctx {
 
 // ---- launchers (stream-ordered, no synchronisation) ----
 // push
-hipError_t launch_push(const PushArgs& a, hipStream_t s);
+// fast pass over all particles of a species, then the slow pass over the
+// ones it queued (cell crossers, failed solves); qcount must be zero on entry
+hipError_t launch_push(const PushArgs& a, int32_t* queue, int32_t* qcount, hipStream_t s);
 hipError_t launch_load(const MapP& m, const SpecDev& s, const double* r, const double* z,
                        const double* vr, const double* vt, const double* vz, const uint64_t* uid,
                        int64_t n, double R, int mixed, hipStream_t st);
@@ -167,16 +192,14 @@ hipError_t launch_collide(const MapP& m, const SpecDev& s, const MccDev& c, Tall
 hipError_t launch_guess_half(const Ctx& c, double vnow, double vnext, hipStream_t s);
 hipError_t launch_half(const Ctx& c, const double* u0r, const double* u0z, const double* u1r,
                        const double* u1z, hipStream_t s);
-hipError_t field_solve(const Ctx& c, const double* ur0, const double* uz0, const double* h0,
-                       const double* Ir, const double* Iz, double vhalf, double vnext,
-                       double* ur1, double* uz1, double* h1, hipStream_t s);
-hipError_t launch_resid(const Ctx& c, const double* ur_new, const double* uz_new,
-                        const double* ur_old, const double* uz_old, double* out2, hipStream_t s);
+hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s);
+// partials: [0, kRedBlocks) sum w u^2, [kRedBlocks, 2 kRedBlocks) sum 2 pi r A h^2
 hipError_t launch_field_energy(const Ctx& c, const double* ur, const double* uz, const double* h,
-                               double* out2, hipStream_t s);
+                               double* part, hipStream_t s);
+// partials [0, kRedBlocks): sum over interior edges of ((a + b)/2) I
 hipError_t launch_exchange(const Ctx& c, const double* ur_a, const double* uz_a,
                            const double* ur_b, const double* uz_b, const double* Ir,
-                           const double* Iz, double* out1, hipStream_t s);
+                           const double* Iz, double* part, hipStream_t s);
 // null-collision bound (host): electrons (role 1) or ions (role 2)
 double nu_max_host(const ecpic_mcc_desc& mcc, int role, double m_particle);
 // learned initial guess: overwrites the guess of the iterate when a network
@@ -187,6 +210,7 @@ hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t s, int64_t* n_alive_host
 hipError_t launch_kinetic(const Species& sp, int mixed, double* out, hipStream_t s);
 hipError_t launch_node_charge(const Ctx& c, double* q, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
+hipError_t launch_zero_i(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 
 }  // namespace ecpic

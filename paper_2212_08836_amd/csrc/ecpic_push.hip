@@ -105,10 +105,13 @@ __device__ __forceinline__ bool accel(const MapP& m, const T F[4], int i, T abar
   const T er = ((T(1) - bc) * F[0] + bc * F[1]) * ijr;
   const T ez = ((T(1) - ac) * F[2] + ac * F[3]) * T(m.inv_dz);
   if (rb > T(0)) {
-    const T den = T(1) + T(0.5) * dtau * vbr / rb;
+    // vtb = vt0 / (1 + dtau vbr / (2 rb)) = vt0 rb q and vtb^2 / rb = vt0^2 rb q^2
+    // with q = 1 / (rb + dtau vbr / 2): one division
+    const T den = rb + T(0.5) * dtau * vbr;
     if (!(den > T(0))) return false;
-    vtb = vt0 / den;
-    ar = qm * er + vtb * vtb / rb;
+    const T q = T(1) / den;
+    vtb = vt0 * rb * q;
+    ar = qm * er + vtb * vt0 * q;
   } else {
     if (vt0 != T(0)) return false;
     vtb = T(0);
@@ -786,82 +789,172 @@ struct FieldPtr<float> {
   static __device__ __forceinline__ const float* z(const PushArgs& a) { return a.uzf; }
 };
 
+// per-thread tallies of a commit pass, reduced once per block
+struct Tl {
+  double work, dke_abs, dke_coll;
+  unsigned absorbed, coll, ion, err, over, ovf, nsub, ncross;
+};
+
+__device__ __forceinline__ void tl_zero(Tl& t) {
+  t.work = t.dke_abs = t.dke_coll = 0.0;
+  t.absorbed = t.coll = t.ion = t.err = t.over = t.ovf = t.nsub = t.ncross = 0;
+}
+
+__device__ void tl_flush(const Tl& t, Tally* tally, int sid) {
+  block_sum_atomic(t.work, &tally->w_particles);
+  block_sum_atomic(t.dke_abs, &tally->w_absorbed);
+  block_sum_atomic(t.dke_coll, &tally->w_coll);
+  block_count_atomic(t.absorbed, &tally->n_absorbed[sid]);
+  block_count_atomic(t.coll, &tally->n_coll[sid]);
+  block_count_atomic(t.ion, &tally->n_ionized);
+  block_count_atomic(t.err, &tally->n_errors);
+  block_count_atomic(t.over, &tally->n_over_range);
+  block_count_atomic(t.ovf, &tally->n_overflow);
+  block_count_atomic(t.nsub, &tally->n_substeps);
+  block_count_atomic(t.ncross, &tally->n_crossings);
+}
+
+// commit of one pushed particle: absorption (wall charge, energy) or state
+// write after the null-collision step
+template <typename T>
+__device__ void commit_one(const PushArgs& A, int64_t k, PState<T>& p, int status, int wall,
+                           Tl& t) {
+  const SpecDev& s = A.s;
+  const MapP& m = A.m;
+  const double qw = s.q * s.w;
+  if (status == kError) t.err += 1;
+  if (status == kAbsorbed) {
+    kill_particle<T>(s, k);
+    t.absorbed += 1;
+    t.dke_abs += 0.5 * s.m * s.w * (double(p.vr) * p.vr + double(p.vt) * p.vt + double(p.vz) * p.vz);
+    if (wall == 1 || wall == 2) {
+      double* w = wall == 1 ? A.wall_bot : A.wall_top;
+      unsafeAtomicAdd(&w[p.i], qw * (1.0 - double(p.a)));
+      unsafeAtomicAdd(&w[p.i + 1], qw * double(p.a));
+    } else {
+      unsafeAtomicAdd(&A.wall_side[p.j], qw * (1.0 - double(p.b)));
+      unsafeAtomicAdd(&A.wall_side[p.j + 1], qw * double(p.b));
+    }
+    return;
+  }
+  if (A.mcc.enabled) {
+    double vr = p.vr, vt = p.vt, vz = p.vz;
+    const CollOut co = collide_one<T>(A.mcc, s, m, s.sid, s.uid[k], p.i, p.j, p.a, p.b, vr, vt, vz,
+                                      A.tally);
+    t.dke_coll += co.dke;
+    t.coll += co.coll;
+    t.ion += co.ionized;
+    t.over += co.over;
+    t.ovf += co.overflow;
+    p.vr = T(vr);
+    p.vt = T(vt);
+    p.vz = T(vz);
+  }
+  store_particle<T>(s, m, k, p);
+}
+
+// Fast pass: every particle solves the mid-point system over the whole step
+// in its cell.  Those that stay in the closed cell are done (this is exactly
+// the first sub-step of the full algorithm); their currents are combined per
+// cell across the wavefront.  The others are queued for k_push_slow.
 template <typename T, bool COMMIT>
-__global__ void __launch_bounds__(kBlock) k_push(PushArgs A) {
+__global__ void __launch_bounds__(kBlock) k_push_fast(PushArgs A, int32_t* queue, int32_t* qcount) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const MapP& m = A.m;
   const SpecDev& s = A.s;
+  const T qm = T(s.q / s.m);
+  const double qw_dt = s.q * s.w / m.dt;
   PState<T> p;
   bool alive = false;
   if (k < s.n) alive = load_particle<T>(s, m, k, p);
-  const T qm = T(s.q / s.m);
-  const double qw = s.q * s.w;
-  const double qw_dt = qw / m.dt;
-  PushOut o;
-  o.have_first = false;
-  o.status = kAlive;
-  o.nsub = 0;
-  o.ncross = 0;
-  o.work = 0.0;
-  o.wall = 0;
+  bool slow = false;
+  int key = -1;
+  Dep dp{0.0, 0.0, 0.0, 0.0};
+  Tl t;
+  tl_zero(t);
   if (alive) {
-    push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, p, qm, qw_dt, COMMIT, o);
-  }
-  // first sub-step deposits: segmented wavefront reduction by cell
-  {
-    const int key = o.have_first ? o.fi * m.nz + o.fj : -1;
-    Dep d = o.have_first ? o.first : Dep{0.0, 0.0, 0.0, 0.0};
-    wave_deposit(A.Ir, A.Iz, m.nz, key, o.fi, o.fj, d);
-  }
-  if (!COMMIT) return;
-  double dke_abs = 0.0, dke_coll = 0.0;
-  unsigned absorbed = 0, coll = 0, ion = 0, err = 0, over = 0, ovf = 0;
-  if (alive) {
-    if (o.status == kError) err = 1;
-    if (o.status == kAbsorbed) {
-      kill_particle<T>(s, k);
-      absorbed = 1;
-      dke_abs = 0.5 * s.m * s.w *
-                (double(p.vr) * p.vr + double(p.vt) * p.vt + double(p.vz) * p.vz);
-      const int nr = m.nr, nz = m.nz;
-      if (o.wall == 1 || o.wall == 2) {
-        double* w = o.wall == 1 ? A.wall_bot : A.wall_top;
-        unsafeAtomicAdd(&w[p.i], qw * (1.0 - double(p.a)));
-        unsafeAtomicAdd(&w[p.i + 1], qw * double(p.a));
-      } else {
-        unsafeAtomicAdd(&A.wall_side[p.j], qw * (1.0 - double(p.b)));
-        unsafeAtomicAdd(&A.wall_side[p.j + 1], qw * double(p.b));
+    // on a face, the cell the motion goes to
+    if (p.a == T(1) && p.vr >= T(0) && p.i < m.nr - 1) {
+      p.i += 1;
+      p.a = T(0);
+    } else if (p.a == T(0) && p.vr < T(0) && p.i > 0) {
+      p.i -= 1;
+      p.a = T(1);
+    }
+    if (p.b == T(1) && p.vz >= T(0) && p.j < m.nz - 1) {
+      p.j += 1;
+      p.b = T(0);
+    } else if (p.b == T(0) && p.vz < T(0) && p.j > 0) {
+      p.j -= 1;
+      p.b = T(1);
+    }
+    T F[4];
+    load_field(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), p.i, p.j, F);
+    Mid<T> M;
+    slow = true;
+    if (solve_free(m, F, p, T(m.dt), qm, M)) {
+      const T ea = T(2) * M.a - p.a, eb = T(2) * M.b - p.b;
+      if (ea >= T(0) && ea <= T(1) && eb >= T(0) && eb <= T(1)) {
+        slow = false;
+        dp = make_dep(double(p.a), double(p.b), double(ea), double(eb), qw_dt);
+        key = p.i * m.nz + p.j;
+        if (COMMIT) {
+          t.work = m.dt * (dp.r0 * double(F[0]) + dp.r1 * double(F[1]) + dp.z0 * double(F[2]) +
+                           dp.z1 * double(F[3]));
+          t.nsub = 1;
+        }
+        p.a = ea;
+        p.b = eb;
+        p.vr = T(2) * M.vr - p.vr;
+        p.vt = T(2) * M.vt - p.vt;
+        p.vz = T(2) * M.vz - p.vz;
       }
-      (void)nr;
-      (void)nz;
-    } else {
-      double vr = p.vr, vt = p.vt, vz = p.vz;
-      if (A.mcc.enabled) {
-        const CollOut co =
-            collide_one<T>(A.mcc, s, m, s.sid, s.uid[k], p.i, p.j, p.a, p.b, vr, vt, vz, A.tally);
-        dke_coll = co.dke;
-        coll = co.coll;
-        ion = co.ionized;
-        over = co.over;
-        ovf = co.overflow;
-        p.vr = T(vr);
-        p.vt = T(vt);
-        p.vz = T(vz);
-      }
-      store_particle<T>(s, m, k, p);
     }
   }
-  block_sum_atomic(o.work, &A.tally->w_particles);
-  block_sum_atomic(dke_abs, &A.tally->w_absorbed);
-  block_sum_atomic(dke_coll, &A.tally->w_coll);
-  block_count_atomic(absorbed, &A.tally->n_absorbed[s.sid]);
-  block_count_atomic(coll, &A.tally->n_coll[s.sid]);
-  block_count_atomic(ion, &A.tally->n_ionized);
-  block_count_atomic(err, &A.tally->n_errors);
-  block_count_atomic(over, &A.tally->n_over_range);
-  block_count_atomic(ovf, &A.tally->n_overflow);
-  block_count_atomic(unsigned(o.nsub), &A.tally->n_substeps);
-  block_count_atomic(unsigned(o.ncross), &A.tally->n_crossings);
+  wave_deposit(A.Ir, A.Iz, m.nz, key, p.i, p.j, dp);
+  // queue the rest, one atomic per wavefront
+  const uint64_t mask = __ballot(slow);
+  if (mask) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(qcount, __popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (slow) queue[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)k;
+  }
+  if (!COMMIT) return;
+  if (alive && !slow) commit_one<T>(A, k, p, kAlive, 0, t);
+  tl_flush(t, A.tally, s.sid);
+}
+
+// Slow pass over the queued particles: the full push with splitting at every
+// face crossing (restarted from the particle's state), currents by atomics.
+template <typename T, bool COMMIT>
+__global__ void __launch_bounds__(kBlock) k_push_slow(PushArgs A, const int32_t* queue,
+                                                      const int32_t* qcount) {
+  const MapP& m = A.m;
+  const SpecDev& s = A.s;
+  const T qm = T(s.q / s.m);
+  const double qw_dt = s.q * s.w / m.dt;
+  const int64_t nq = *qcount;
+  Tl t;
+  tl_zero(t);
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nq;
+       q += (int64_t)gridDim.x * kBlock) {
+    const int64_t k = queue[q];
+    PState<T> p;
+    if (!load_particle<T>(s, m, k, p)) continue;
+    PushOut o;
+    push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, p, qm, qw_dt, COMMIT, o);
+    if (o.have_first) atomic_dep(A.Ir, A.Iz, m.nz, o.fi, o.fj, o.first);
+    if (COMMIT) {
+      t.work += o.work;
+      t.nsub += o.nsub;
+      t.ncross += o.ncross;
+      commit_one<T>(A, k, p, o.status, o.wall, t);
+    }
+  }
+  if (COMMIT) tl_flush(t, A.tally, s.sid);
 }
 
 // standalone collision pass over the live particles
@@ -994,20 +1087,27 @@ double nu_max_host(const ecpic_mcc_desc& c, int role, double mp) {
   return 0.0;
 }
 
-hipError_t launch_push(const PushArgs& a, hipStream_t st) {
+hipError_t launch_push(const PushArgs& a, int32_t* queue, int32_t* qcount, hipStream_t st) {
   if (a.s.n <= 0) return hipSuccess;
   const int64_t nb = (a.s.n + kBlock - 1) / kBlock;
+  const int64_t ns = nb < 1024 ? nb : 1024;  // grid-stride blocks of the slow pass
   const bool mixed = (a.s.cell != nullptr);
   if (!mixed) {
-    if (a.commit)
-      hipLaunchKernelGGL((k_push<double, true>), dim3(nb), dim3(kBlock), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_push<double, false>), dim3(nb), dim3(kBlock), 0, st, a);
+    if (a.commit) {
+      hipLaunchKernelGGL((k_push_fast<double, true>), dim3(nb), dim3(kBlock), 0, st, a, queue, qcount);
+      hipLaunchKernelGGL((k_push_slow<double, true>), dim3(ns), dim3(kBlock), 0, st, a, queue, qcount);
+    } else {
+      hipLaunchKernelGGL((k_push_fast<double, false>), dim3(nb), dim3(kBlock), 0, st, a, queue, qcount);
+      hipLaunchKernelGGL((k_push_slow<double, false>), dim3(ns), dim3(kBlock), 0, st, a, queue, qcount);
+    }
   } else {
-    if (a.commit)
-      hipLaunchKernelGGL((k_push<float, true>), dim3(nb), dim3(kBlock), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_push<float, false>), dim3(nb), dim3(kBlock), 0, st, a);
+    if (a.commit) {
+      hipLaunchKernelGGL((k_push_fast<float, true>), dim3(nb), dim3(kBlock), 0, st, a, queue, qcount);
+      hipLaunchKernelGGL((k_push_slow<float, true>), dim3(ns), dim3(kBlock), 0, st, a, queue, qcount);
+    } else {
+      hipLaunchKernelGGL((k_push_fast<float, false>), dim3(nb), dim3(kBlock), 0, st, a, queue, qcount);
+      hipLaunchKernelGGL((k_push_slow<float, false>), dim3(ns), dim3(kBlock), 0, st, a, queue, qcount);
+    }
   }
   return hipGetLastError();
 }

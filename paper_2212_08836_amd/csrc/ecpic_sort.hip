@@ -258,6 +258,12 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_zero_i(int32_t* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i, dim3(nblk(n)), dim3(kBlock), 0, st, p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(double* d, const double* s, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy, dim3(nblk(n)), dim3(kBlock), 0, st, d, s, n);
