@@ -232,11 +232,15 @@ ecpic_status ecpic_nn_adam(ecpic_ctx* ctx, float* w, float* m, float* v, const f
 /* Kernel timing with HIP events recorded on the context stream around every
  * launch of the hot kernels (one record per launch), for measurement. */
 typedef enum {
-  ECPIC_K_PUSH = 0,    /* push + deposit in a Picard iteration (one species) */
-  ECPIC_K_COMMIT = 1,  /* committing push + absorption + MCC (one species)   */
-  ECPIC_K_FIELD = 2,   /* one field solve (rhs, DCTs, Thomas, recovery)      */
-  ECPIC_K_SORT = 3,    /* counting sort of one species                       */
-  ECPIC_K_COUNT = 4
+  ECPIC_K_PUSH = 0,         /* in-cell push + deposit of a Picard iteration,
+                               all particles of one species                  */
+  ECPIC_K_PUSH_SLOW = 1,    /* the same pass for the particles that cross
+                               cell faces (split sub-steps)                  */
+  ECPIC_K_COMMIT = 2,       /* committing in-cell push + absorption + MCC    */
+  ECPIC_K_COMMIT_SLOW = 3,  /* committing push of the face-crossing ones     */
+  ECPIC_K_FIELD = 4,        /* one field solve (rhs+DCT, scan, iDCT+recover) */
+  ECPIC_K_SORT = 5,         /* counting sort of one species                  */
+  ECPIC_K_COUNT = 6
 } ecpic_kernel_kind;
 
 typedef struct {

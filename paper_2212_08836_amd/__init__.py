@@ -72,12 +72,12 @@ class StepStats(C.Structure):
         return d
 
 
-KERNEL_KINDS = ("push", "commit", "field", "sort")
+KERNEL_KINDS = ("push", "push_slow", "commit", "commit_slow", "field", "sort")
 
 
 class Profile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 4), ("ms", C.c_double * 4), ("bytes", C.c_double * 4),
-                ("particles", C.c_int64 * 4)]
+    _fields_ = [("launches", C.c_int64 * 6), ("ms", C.c_double * 6), ("bytes", C.c_double * 6),
+                ("particles", C.c_int64 * 6)]
 
     def as_dict(self) -> dict:
         return {k: dict(launches=self.launches[i], ms=self.ms[i], bytes=self.bytes[i],

@@ -205,21 +205,23 @@ hipEvent_t get_event(Ctx& c) {
 
 struct Timed {
   Ctx& c;
+  hipStream_t st;
   hipEvent_t a = nullptr;
   int kind;
   double bytes;
   int64_t particles;
-  Timed(Ctx& cc, int k, double b, int64_t n) : c(cc), kind(k), bytes(b), particles(n) {
+  Timed(Ctx& cc, int k, double b, int64_t n, hipStream_t s = nullptr)
+      : c(cc), st(s ? s : cc.stream), kind(k), bytes(b), particles(n) {
     if (c.prof_on) {
       a = get_event(c);
-      if (a) (void)hipEventRecord(a, c.stream);
+      if (a) (void)hipEventRecord(a, st);
     }
   }
   ~Timed() {
     if (!a) return;
     hipEvent_t b = get_event(c);
     if (!b) return;
-    (void)hipEventRecord(b, c.stream);
+    (void)hipEventRecord(b, st);
     c.pending.push_back({a, b, kind, bytes, particles});
   }
 };
@@ -301,31 +303,67 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool zero_cur
     HIPCHK(zero(c.Ir, n_edges_r(c), c.stream));
     HIPCHK(zero(c.Iz, n_edges_z(c), c.stream));
   }
-  if (commit) HIPCHK(hipMemsetAsync(c.tally, 0, sizeof(Tally), c.stream));
-  HIPCHK(launch_zero_i(c.qcount, kMaxSpecies, c.stream));
+  if (commit) HIPCHK(hipMemsetAsync(c.tally, 0, kSpread * sizeof(Tally), c.stream));
+  HIPCHK(launch_zero_i(c.qcount, kMaxSpecies * kSpread * kLineInts, c.stream));
   // append offsets of every species are taken before any pass appends
   std::vector<MccDev> mcc(c.sp.size());
   for (size_t s = 0; s < c.sp.size(); ++s) {
     std::memset(&mcc[s], 0, sizeof(MccDev));
     if (commit && with_mcc) mcc[s] = make_mcc(c, (int)s, step);
   }
+  // Each species: the fast pass on the main stream, then its slow pass on the
+  // species' own stream, so that it overlaps the next species' fast pass;
+  // the main stream waits for all slow passes before it goes on.
+  std::vector<int> joined;
   for (size_t s = 0; s < c.sp.size(); ++s) {
     if (!c.sp[s].desc.mobile || c.sp[s].n == 0) continue;
     PushArgs a = push_args(c, (int)s, commit);
     a.mcc = mcc[s];
-    // commit: state + id read, state written
-    const double per = commit ? 2.0 * state_bytes(c) + 8.0 : state_bytes(c);
-    Timed tm(c, commit ? ECPIC_K_COMMIT : ECPIC_K_PUSH, per * (double)c.sp[s].n, c.sp[s].n);
-    HIPCHK(launch_push(a, c.queue, c.qcount + s, c.stream));
+    int32_t* q = c.queue + (int64_t)s * c.queue_cap;
+    int32_t* qc = c.qcount + s * kSpread * kLineInts;
+    const int64_t seg = queue_segment(c.sp[s].n);
+    {
+      // commit: state + id read, state written; iteration: state read
+      const double per = commit ? 2.0 * state_bytes(c) + 8.0 : state_bytes(c);
+      Timed tm(c, commit ? ECPIC_K_COMMIT : ECPIC_K_PUSH, per * (double)c.sp[s].n, c.sp[s].n);
+      HIPCHK(launch_push_fast(a, q, seg, qc, c.stream));
+    }
+    HIPCHK(hipEventRecord(c.ev_fast[s], c.stream));
+    HIPCHK(hipStreamWaitEvent(c.aux[s], c.ev_fast[s], 0));
+    {
+      Timed tm(c, commit ? ECPIC_K_COMMIT_SLOW : ECPIC_K_PUSH_SLOW, 0.0, 0, c.aux[s]);
+      HIPCHK(launch_push_slow(a, q, seg, qc, c.aux[s]));
+    }
+    HIPCHK(hipEventRecord(c.ev_slow[s], c.aux[s]));
+    joined.push_back((int)s);
   }
+  for (int s : joined) HIPCHK(hipStreamWaitEvent(c.stream, c.ev_slow[s], 0));
   return ECPIC_OK;
 }
 
 // After a commit/collision pass: fetch the tally and grow species counts.
 ecpic_status finish_tally(Ctx& c, Tally& t) {
-  HIPCHK(hipMemcpyAsync(c.tally_host, c.tally, sizeof(Tally), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipMemcpyAsync(c.tally_host, c.tally, kSpread * sizeof(Tally), hipMemcpyDeviceToHost,
+                        c.stream));
   HIPCHK(hipStreamSynchronize(c.stream));
-  t = *c.tally_host;
+  t = c.tally_host[0];
+  for (int q = 1; q < kSpread; ++q) {
+    const Tally& u = c.tally_host[q];
+    t.w_absorbed += u.w_absorbed;
+    t.w_coll += u.w_coll;
+    t.w_particles += u.w_particles;
+    for (int s = 0; s < kMaxSpecies; ++s) {
+      t.n_absorbed[s] += u.n_absorbed[s];
+      t.n_coll[s] += u.n_coll[s];
+      t.append[s] += u.append[s];
+    }
+    t.n_ionized += u.n_ionized;
+    t.n_errors += u.n_errors;
+    t.n_crossings += u.n_crossings;
+    t.n_substeps += u.n_substeps;
+    t.n_over_range += u.n_over_range;
+    t.n_overflow += u.n_overflow;
+  }
   collect(c);
   ecpic_status rc = ECPIC_OK;
   for (size_t s = 0; s < c.sp.size(); ++s) {
@@ -386,6 +424,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   c.m.dz = g->L / g->nz;
   c.m.inv_dz = 1.0 / c.m.dz;
   c.m.dt = g->dt;
+  c.m.i_lin = (int)std::ceil(g->xi_axis);
   const int64_t nur = n_edges_r(c), nuz = n_edges_z(c), nh = n_cells(c);
   bool ok = true;
   auto A = [&](double** p, int64_t n) { ok = ok && dalloc(p, (size_t)n) == hipSuccess; };
@@ -405,9 +444,14 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   ok = ok && dalloc(&c.hist, (size_t)nh + 1) == hipSuccess;
   ok = ok && dalloc(&c.offs, (size_t)nh + 1) == hipSuccess;
   ok = ok && dalloc(&c.scan_part, (size_t)(nh + 1023) / 1024 + 2) == hipSuccess;
-  ok = ok && dalloc(&c.tally, 1) == hipSuccess;
-  ok = ok && dalloc(&c.qcount, kMaxSpecies) == hipSuccess;
-  ok = ok && hipHostMalloc((void**)&c.tally_host, sizeof(Tally)) == hipSuccess;
+  ok = ok && dalloc(&c.tally, kSpread) == hipSuccess;
+  ok = ok && dalloc(&c.qcount, kMaxSpecies * kSpread * kLineInts) == hipSuccess;
+  for (int s = 0; s < kMaxSpecies; ++s) {
+    ok = ok && hipStreamCreateWithFlags(&c.aux[s], hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c.ev_fast[s], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c.ev_slow[s], hipEventDisableTiming) == hipSuccess;
+  }
+  ok = ok && hipHostMalloc((void**)&c.tally_host, kSpread * sizeof(Tally)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.red_host, 64 * sizeof(double)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.part_host, kPartLen * sizeof(double)) == hipSuccess;
   if (!ok) {
@@ -462,6 +506,12 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
   (void)hipFree(c.nn_ws);
   collect(c);
   for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
+  for (int s = 0; s < kMaxSpecies; ++s) {
+    if (c.aux[s]) (void)hipStreamSynchronize(c.aux[s]);
+    if (c.aux[s]) (void)hipStreamDestroy(c.aux[s]);
+    if (c.ev_fast[s]) (void)hipEventDestroy(c.ev_fast[s]);
+    if (c.ev_slow[s]) (void)hipEventDestroy(c.ev_slow[s]);
+  }
   if (c.tally_host) (void)hipHostFree(c.tally_host);
   if (c.red_host) (void)hipHostFree(c.red_host);
   if (c.part_host) (void)hipHostFree(c.part_host);
@@ -483,16 +533,17 @@ ecpic_status ecpic_add_species(ecpic_ctx* x, const ecpic_species_desc* d, int32_
     free_species_buf(s.d[1]);
     return fail(c, ECPIC_ENOMEM, "species allocation failed");
   }
-  if (d->capacity > c.queue_cap) {
+  const int64_t qlen = kSpread * queue_segment(d->capacity);
+  if (qlen > c.queue_cap) {
     int32_t* q = nullptr;
-    if (dalloc(&q, (size_t)d->capacity) != hipSuccess) {
+    if (dalloc(&q, (size_t)qlen * kMaxSpecies) != hipSuccess) {
       free_species_buf(s.d[0]);
       free_species_buf(s.d[1]);
       return fail(c, ECPIC_ENOMEM, "queue allocation failed");
     }
     (void)hipFree(c.queue);
     c.queue = q;
-    c.queue_cap = d->capacity;
+    c.queue_cap = qlen;
   }
   s.n = 0;
   // both sort buffers carry the species constants, so every kernel that is
@@ -720,7 +771,7 @@ ecpic_status ecpic_collide(ecpic_ctx* x, const ecpic_mcc_desc* m, int64_t step) 
   ecpic_mcc_desc saved = c.mcc;
   ecpic_status rc = ecpic_set_mcc(x, m);
   if (rc != ECPIC_OK) return rc;
-  HIPCHK(hipMemsetAsync(c.tally, 0, sizeof(Tally), c.stream));
+  HIPCHK(hipMemsetAsync(c.tally, 0, kSpread * sizeof(Tally), c.stream));
   std::vector<MccDev> d(c.sp.size());
   for (size_t s = 0; s < c.sp.size(); ++s) d[s] = make_mcc(c, (int)s, step);
   for (size_t s = 0; s < c.sp.size(); ++s) {

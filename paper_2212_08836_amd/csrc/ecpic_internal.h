@@ -17,12 +17,17 @@ constexpr int kMaxSub = 64;     // sub-steps per particle per step
 constexpr int kMaxHalve = 20;   // halvings of a sub-step whose solve fails
 constexpr int kMaxFixed = 50;   // fixed-point iterations per sub-step solve
 constexpr int kBlock = 256;     // threads per block for particle kernels
+// Contended counters are spread over copies on separate cache lines: block b
+// uses copy b % kSpread (queue segments, commit tallies).
+constexpr int kSpread = 64;
+constexpr int kLineInts = 32;   // 128-byte stride between queue counters
 
 // Mesh map r(xi) (C^1 two-piece: r = 2 s sqrt(xi xi_a) below xi_a, s (xi+xi_a)
 // above) and the uniform axial map z = eta dz.
 struct MapP {
   int nr, nz;
   double xi_a, s, inv_s, rsqrt_xa, dz, inv_dz, dt;
+  int i_lin;  // first radial cell entirely in the linear part of the map
 };
 
 // One species as the kernels see it.  FP64 path: xi, eta, v*; mixed path:
@@ -140,11 +145,13 @@ struct Ctx {
   int32_t* hist;                   // per-cell counts [nr*nz + 1]
   int32_t* offs;                   // per-cell offsets [nr*nz + 1]
   int32_t* scan_part;              // scan block sums
-  Tally* tally;                    // device tally
-  int32_t* queue = nullptr;        // slow-pass particle queue
-  int64_t queue_cap = 0;
-  int32_t* qcount = nullptr;       // per-species queue lengths [kMaxSpecies]
-  Tally* tally_host;               // pinned host mirror
+  Tally* tally;                    // device tallies, kSpread copies
+  int32_t* queue = nullptr;        // slow-pass particle queues, one per species
+  int64_t queue_cap = 0;           // entries per species
+  hipStream_t aux[kMaxSpecies] = {};  // slow passes overlap the next fast pass
+  hipEvent_t ev_fast[kMaxSpecies] = {}, ev_slow[kMaxSpecies] = {};
+  int32_t* qcount = nullptr;       // queue lengths [kMaxSpecies][kSpread][kLineInts]
+  Tally* tally_host;               // pinned host mirror of the copies
   double* red_host;                // pinned host reduction results
   SolverDev sol;
   double t = 0.0;
@@ -173,8 +180,18 @@ struct Ctx {
 // ---- launchers (stream-ordered, no synchronisation) ----
 // push
 // fast pass over all particles of a species, then the slow pass over the
-// ones it queued (cell crossers, failed solves); qcount must be zero on entry
-hipError_t launch_push(const PushArgs& a, int32_t* queue, int32_t* qcount, hipStream_t s);
+// ones it queued (cell crossers, failed solves).  queue holds kSpread
+// segments of queue_seg entries; qcount (kSpread counters, kLineInts apart)
+// must be zero on entry.  tally points at kSpread copies.
+hipError_t launch_push_fast(const PushArgs& a, int32_t* queue, int64_t queue_seg,
+                            int32_t* qcount, hipStream_t s);
+hipError_t launch_push_slow(const PushArgs& a, int32_t* queue, int64_t queue_seg,
+                            int32_t* qcount, hipStream_t s);
+// entries per queue segment for n particles
+inline int64_t queue_segment(int64_t n) {
+  const int64_t nb = (n + kBlock - 1) / kBlock;
+  return ((nb + kSpread - 1) / kSpread) * kBlock;
+}
 hipError_t launch_load(const MapP& m, const SpecDev& s, const double* r, const double* z,
                        const double* vr, const double* vt, const double* vz, const uint64_t* uid,
                        int64_t n, double R, int mixed, hipStream_t st);

@@ -154,6 +154,64 @@ __device__ bool solve_free(const MapP& m, const T F[4], const PState<T>& p, T dt
   return false;
 }
 
+// The same mid-point system for a particle of a linear-map cell (i >= i_lin)
+// whose sub-step stays in its cell, solved without the general fixed point.
+// There E_r = ((1-b)F0 + b F1)/s depends on the mid offset b only, E_z on
+// the mid offset a only, and a = a0 + (dt/2s) vb_r, b = b0 + (dt/2dz) vb_z,
+// so (vb_r, vb_z) obey a 2x2 linear system:
+//   vb_z = Cz + Kz vb_r,   vb_r (1 - Kr Kz) = Cr + Kr Cz + (dt/2) cf,
+// with the centrifugal term cf = vb_t^2 / r_bar = v_t^2 r_bar / r_end^2
+// (vb_t = v_t r_bar / r_end from the angular equation, r_bar = r0 + dt vb_r / 2,
+// r_end = r0 + dt vb_r): a scalar fixed point in vb_r that converges in a few
+// steps.  Returns false when the case does not apply (the caller then runs
+// the general solve).
+template <typename T>
+__device__ __forceinline__ bool solve_fast(const MapP& m, const T F[4], const PState<T>& p, T dtau,
+                                           T qm, Mid<T>& M) {
+  const T hd = T(0.5) * dtau;
+  const T delta = hd * T(m.inv_s);  // d a_bar / d vb_r
+  const T gamma = hd * T(m.inv_dz); // d b_bar / d vb_z
+  const T alpha = qm * delta;       // d vb_r / d (weighted ur)
+  const T beta = qm * gamma;        // d vb_z / d (weighted uz)
+  const T dFr = F[1] - F[0], dFz = F[3] - F[2];
+  const T Cz = p.vz + beta * (F[2] + p.a * dFz);
+  const T Kz = beta * delta * dFz;
+  const T Cr = p.vr + alpha * (F[0] + p.b * dFr);
+  const T Kr = alpha * gamma * dFr;
+  const T den = T(1) - Kr * Kz;
+  if (!(den > T(0))) return false;
+  const T inv_den = T(1) / den;
+  const T c0 = (Cr + Kr * Cz) * inv_den;
+  const T cc = hd * inv_den;
+  const T r0 = T(m.s * (double(p.i) + m.xi_a)) + T(m.s) * p.a;
+  const T vt2 = p.vt * p.vt;
+  T vr = c0 + cc * vt2 / r0;  // centrifugal term at the start position
+  T rb = r0, re = r0;
+  for (int it = 0; it < 12; ++it) {
+    rb = r0 + hd * vr;
+    re = r0 + dtau * vr;
+    if (!(rb > T(0) && re > T(0))) return false;
+    const T ire = T(1) / re;
+    const T nvr = c0 + cc * vt2 * rb * ire * ire;
+    const T d = fabs(nvr - vr);
+    vr = nvr;
+    const T vz = Cz + Kz * vr;
+    const T scale = fabs(vr) + fabs(p.vt * rb * ire) + fabs(vz);
+    if (d <= Tol<T>::v() * scale) {
+      rb = r0 + hd * vr;
+      re = r0 + dtau * vr;
+      if (!(re > T(0))) return false;
+      M.vr = vr;
+      M.vz = vz;
+      M.vt = p.vt * rb / re;
+      M.a = p.a + delta * vr;
+      M.b = p.b + gamma * vz;
+      return true;
+    }
+  }
+  return false;
+}
+
 // Smallest positive root of (a/2) t^2 + v t - D = 0 in cancellation-free
 // form, or +inf.
 template <typename T>
@@ -858,7 +916,8 @@ __device__ void commit_one(const PushArgs& A, int64_t k, PState<T>& p, int statu
 // the first sub-step of the full algorithm); their currents are combined per
 // cell across the wavefront.  The others are queued for k_push_slow.
 template <typename T, bool COMMIT>
-__global__ void __launch_bounds__(kBlock) k_push_fast(PushArgs A, int32_t* queue, int32_t* qcount) {
+__global__ void __launch_bounds__(kBlock) k_push_fast(PushArgs A, int32_t* queue, int64_t qseg,
+                                                      int32_t* qcount) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const MapP& m = A.m;
   const SpecDev& s = A.s;
@@ -892,7 +951,7 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PushArgs A, int32_t* queue
     load_field(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), p.i, p.j, F);
     Mid<T> M;
     slow = true;
-    if (solve_free(m, F, p, T(m.dt), qm, M)) {
+    if (p.i >= m.i_lin && solve_fast(m, F, p, T(m.dt), qm, M)) {
       const T ea = T(2) * M.a - p.a, eb = T(2) * M.b - p.b;
       if (ea >= T(0) && ea <= T(1) && eb >= T(0) && eb <= T(1)) {
         slow = false;
@@ -912,36 +971,50 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PushArgs A, int32_t* queue
     }
   }
   wave_deposit(A.Ir, A.Iz, m.nz, key, p.i, p.j, dp);
-  // queue the rest, one atomic per wavefront
-  const uint64_t mask = __ballot(slow);
-  if (mask) {
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(qcount, __popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (slow) queue[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)k;
+  // queue the rest: ranks within the block from wavefront ballots, one
+  // atomic per block on the counter of this block's segment
+  {
+    __shared__ int wcnt[kBlock / 64];
+    __shared__ int bbase;
+    const uint64_t mask = __ballot(slow);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wcnt[w] = __popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int q = 0; q < kBlock / 64; ++q) tot += wcnt[q];
+      bbase = tot ? atomicAdd(qcount + (blockIdx.x % kSpread) * kLineInts, tot) : 0;
+    }
+    __syncthreads();
+    if (slow) {
+      int r = bbase + __popcll(mask & ((1ull << lane) - 1ull));
+      for (int q = 0; q < w; ++q) r += wcnt[q];
+      queue[(int64_t)(blockIdx.x % kSpread) * qseg + r] = (int32_t)k;
+    }
   }
   if (!COMMIT) return;
   if (alive && !slow) commit_one<T>(A, k, p, kAlive, 0, t);
-  tl_flush(t, A.tally, s.sid);
+  tl_flush(t, A.tally + (blockIdx.x % kSpread), s.sid);
 }
 
 // Slow pass over the queued particles: the full push with splitting at every
 // face crossing (restarted from the particle's state), currents by atomics.
 template <typename T, bool COMMIT>
+// grid (X, kSpread): blocks with blockIdx.y = g walk segment g
 __global__ void __launch_bounds__(kBlock) k_push_slow(PushArgs A, const int32_t* queue,
-                                                      const int32_t* qcount) {
+                                                      int64_t qseg, const int32_t* qcount) {
   const MapP& m = A.m;
   const SpecDev& s = A.s;
   const T qm = T(s.q / s.m);
   const double qw_dt = s.q * s.w / m.dt;
-  const int64_t nq = *qcount;
+  const int g = blockIdx.y;
+  const int64_t nq = qcount[g * kLineInts];
+  const int32_t* seg = queue + (int64_t)g * qseg;
   Tl t;
   tl_zero(t);
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nq;
        q += (int64_t)gridDim.x * kBlock) {
-    const int64_t k = queue[q];
+    const int64_t k = seg[q];
     PState<T> p;
     if (!load_particle<T>(s, m, k, p)) continue;
     PushOut o;
@@ -954,7 +1027,7 @@ __global__ void __launch_bounds__(kBlock) k_push_slow(PushArgs A, const int32_t*
       commit_one<T>(A, k, p, o.status, o.wall, t);
     }
   }
-  if (COMMIT) tl_flush(t, A.tally, s.sid);
+  if (COMMIT) tl_flush(t, A.tally + ((blockIdx.y * gridDim.x + blockIdx.x) % kSpread), s.sid);
 }
 
 // standalone collision pass over the live particles
@@ -981,11 +1054,12 @@ __global__ void __launch_bounds__(kBlock) k_collide(MapP m, SpecDev s, MccDev c,
       store_particle<T>(s, m, k, p);
     }
   }
-  block_sum_atomic(dke, &tally->w_coll);
-  block_count_atomic(coll, &tally->n_coll[s.sid]);
-  block_count_atomic(ion, &tally->n_ionized);
-  block_count_atomic(over, &tally->n_over_range);
-  block_count_atomic(ovf, &tally->n_overflow);
+  Tally* tt = tally + (blockIdx.x % kSpread);
+  block_sum_atomic(dke, &tt->w_coll);
+  block_count_atomic(coll, &tt->n_coll[s.sid]);
+  block_count_atomic(ion, &tt->n_ionized);
+  block_count_atomic(over, &tt->n_over_range);
+  block_count_atomic(ovf, &tt->n_overflow);
 }
 
 // physical (r, z) -> logical state
@@ -1087,27 +1161,44 @@ double nu_max_host(const ecpic_mcc_desc& c, int role, double mp) {
   return 0.0;
 }
 
-hipError_t launch_push(const PushArgs& a, int32_t* queue, int32_t* qcount, hipStream_t st) {
+hipError_t launch_push_fast(const PushArgs& a, int32_t* queue, int64_t qseg, int32_t* qcount,
+                            hipStream_t st) {
   if (a.s.n <= 0) return hipSuccess;
   const int64_t nb = (a.s.n + kBlock - 1) / kBlock;
-  const int64_t ns = nb < 1024 ? nb : 1024;  // grid-stride blocks of the slow pass
   const bool mixed = (a.s.cell != nullptr);
   if (!mixed) {
-    if (a.commit) {
-      hipLaunchKernelGGL((k_push_fast<double, true>), dim3(nb), dim3(kBlock), 0, st, a, queue, qcount);
-      hipLaunchKernelGGL((k_push_slow<double, true>), dim3(ns), dim3(kBlock), 0, st, a, queue, qcount);
-    } else {
-      hipLaunchKernelGGL((k_push_fast<double, false>), dim3(nb), dim3(kBlock), 0, st, a, queue, qcount);
-      hipLaunchKernelGGL((k_push_slow<double, false>), dim3(ns), dim3(kBlock), 0, st, a, queue, qcount);
-    }
+    if (a.commit)
+      hipLaunchKernelGGL((k_push_fast<double, true>), dim3(nb), dim3(kBlock), 0, st, a, queue, qseg, qcount);
+    else
+      hipLaunchKernelGGL((k_push_fast<double, false>), dim3(nb), dim3(kBlock), 0, st, a, queue, qseg, qcount);
   } else {
-    if (a.commit) {
-      hipLaunchKernelGGL((k_push_fast<float, true>), dim3(nb), dim3(kBlock), 0, st, a, queue, qcount);
-      hipLaunchKernelGGL((k_push_slow<float, true>), dim3(ns), dim3(kBlock), 0, st, a, queue, qcount);
-    } else {
-      hipLaunchKernelGGL((k_push_fast<float, false>), dim3(nb), dim3(kBlock), 0, st, a, queue, qcount);
-      hipLaunchKernelGGL((k_push_slow<float, false>), dim3(ns), dim3(kBlock), 0, st, a, queue, qcount);
-    }
+    if (a.commit)
+      hipLaunchKernelGGL((k_push_fast<float, true>), dim3(nb), dim3(kBlock), 0, st, a, queue, qseg, qcount);
+    else
+      hipLaunchKernelGGL((k_push_fast<float, false>), dim3(nb), dim3(kBlock), 0, st, a, queue, qseg, qcount);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_push_slow(const PushArgs& a, int32_t* queue, int64_t qseg, int32_t* qcount,
+                            hipStream_t st) {
+  if (a.s.n <= 0) return hipSuccess;
+  const int64_t nb = (a.s.n + kBlock - 1) / kBlock;
+  // per segment enough blocks for a few percent of the particles
+  int64_t xs = (nb / kSpread + 7) / 8;
+  xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
+  const dim3 gs((unsigned)xs, kSpread);
+  const bool mixed = (a.s.cell != nullptr);
+  if (!mixed) {
+    if (a.commit)
+      hipLaunchKernelGGL((k_push_slow<double, true>), gs, dim3(kBlock), 0, st, a, queue, qseg, qcount);
+    else
+      hipLaunchKernelGGL((k_push_slow<double, false>), gs, dim3(kBlock), 0, st, a, queue, qseg, qcount);
+  } else {
+    if (a.commit)
+      hipLaunchKernelGGL((k_push_slow<float, true>), gs, dim3(kBlock), 0, st, a, queue, qseg, qcount);
+    else
+      hipLaunchKernelGGL((k_push_slow<float, false>), gs, dim3(kBlock), 0, st, a, queue, qseg, qcount);
   }
   return hipGetLastError();
 }

@@ -92,19 +92,43 @@ __device__ __forceinline__ int cell_key(const MapP& m, const SpecDev& s, int64_t
   return i * m.nz + j;
 }
 
-__global__ void k_hist(MapP m, SpecDev s, int64_t n, int mixed, int32_t* hist) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  const int c = cell_key(m, s, k, mixed != 0);
-  if (c >= 0) atomicAdd(&hist[c], 1);
+// Runs of equal consecutive keys in a wavefront (particles are nearly sorted
+// by cell, so a wavefront holds a few long runs): the first lane of a run and
+// the run's length, and my rank in it.
+struct Run {
+  int start, len, rank;
+};
+__device__ __forceinline__ Run wave_run(int key) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1, 64);
+  const bool head = (lane == 0) || (prev != key);
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const int start = 63 - __clzll(heads & upto);
+  const uint64_t after = heads & ~upto;
+  const int end = after ? (__ffsll((unsigned long long)after) - 1) : 64;
+  return Run{start, end - start, lane - start};
 }
 
+// per-cell counts, one atomic per run of equal cells in a wavefront
+__global__ void k_hist(MapP m, SpecDev s, int64_t n, int mixed, int32_t* hist) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int c = (k < n) ? cell_key(m, s, k, mixed != 0) : -1;
+  const Run r = wave_run(c);
+  if (c >= 0 && r.rank == 0) atomicAdd(&hist[c], r.len);
+}
+
+// scatter to the cell's slots: one atomic per run, which keeps the order of
+// the run's particles
 __global__ void k_scatter(MapP m, SpecDev src, SpecDev dst, int64_t n, int mixed, int32_t* offs) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  const int c = cell_key(m, src, k, mixed != 0);
+  const int c = (k < n) ? cell_key(m, src, k, mixed != 0) : -1;
+  const Run r = wave_run(c);
+  int base = 0;
+  if (c >= 0 && r.rank == 0) base = atomicAdd(&offs[c], r.len);
+  base = __shfl(base, r.start, 64);
   if (c < 0) return;
-  const int64_t d = atomicAdd(&offs[c], 1);
+  const int64_t d = (int64_t)base + r.rank;
   if (!mixed) {
     dst.xi[d] = src.xi[k];
     dst.eta[d] = src.eta[k];
