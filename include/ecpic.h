@@ -250,8 +250,13 @@ typedef struct {
   int64_t particles[ECPIC_K_COUNT];   /* summed particles processed         */
 } ecpic_profile;
 
-/* Turn timing on (1) or off (0); turning it on clears the totals. */
-ecpic_status ecpic_set_profiling(ecpic_ctx* ctx, int32_t on);
+/* Choose the kinds to time: bit k of kind_mask enables ECPIC_K_* kind k
+ * (ECPIC_PROFILE_ALL = every kind, 0 = off).  Each timed launch costs two
+ * event records on its stream, so a narrow mask perturbs the run least.
+ * Launches of a speculative Picard iteration that turns out not to be needed
+ * are not counted.  Any call clears the totals. */
+#define ECPIC_PROFILE_ALL 0x3F
+ecpic_status ecpic_set_profiling(ecpic_ctx* ctx, int32_t kind_mask);
 /* Totals since profiling was turned on (synchronises). */
 ecpic_status ecpic_get_profile(ecpic_ctx* ctx, ecpic_profile* out);
 

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libecpic.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ecpic.h")
 
 ECPIC_FP64, ECPIC_MIXED = 0, 1
+ECPIC_OK, ECPIC_EINVAL, ECPIC_ENOMEM, ECPIC_EHIP, ECPIC_ENOTCONV = 0, -1, -2, -3, -4
+ECPIC_EPUSH, ECPIC_ECAPACITY, ECPIC_ERANGE, ECPIC_ENOTIMPL = -5, -6, -7, -8
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "EPUSH",
           -6: "ECAPACITY", -7: "ERANGE", -8: "ENOTIMPL"}
 
@@ -324,8 +326,18 @@ class Context:
         t.cuda.synchronize()
         return q.cpu().numpy(), b.cpu().numpy(), tp.cpu().numpy(), sd.cpu().numpy()
 
-    def set_profiling(self, on: bool):
-        self._check(self.L.ecpic_set_profiling(self.h, int(bool(on))), self.h)
+    def set_profiling(self, on: bool = True, kinds=None):
+        """Time launches with HIP events: every kind when `kinds` is None,
+        else only the named ones (names of KERNEL_KINDS)."""
+        if not on:
+            mask = 0
+        elif kinds is None:
+            mask = (1 << len(KERNEL_KINDS)) - 1
+        else:
+            mask = 0
+            for k in kinds:
+                mask |= 1 << KERNEL_KINDS.index(k)
+        self._check(self.L.ecpic_set_profiling(self.h, mask), self.h)
 
     def profile(self) -> dict:
         p = Profile()

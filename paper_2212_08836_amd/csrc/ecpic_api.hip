@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -194,8 +195,9 @@ hipError_t zero(double* p, int64_t n, hipStream_t s) { return launch_zero(p, n, 
 // -- event timing: a start/stop pair around a launch, resolved after a sync --
 hipEvent_t get_event(Ctx& c) {
   if (c.ev_pool.empty()) {
+    // timing only: no system-scope cache writeback at each record
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
   }
   hipEvent_t e = c.ev_pool.back();
@@ -212,7 +214,7 @@ struct Timed {
   int64_t particles;
   Timed(Ctx& cc, int k, double b, int64_t n, hipStream_t s = nullptr)
       : c(cc), st(s ? s : cc.stream), kind(k), bytes(b), particles(n) {
-    if (c.prof_on) {
+    if (c.prof_mask & (1u << k)) {
       a = get_event(c);
       if (a) (void)hipEventRecord(a, st);
     }
@@ -222,13 +224,19 @@ struct Timed {
     hipEvent_t b = get_event(c);
     if (!b) return;
     (void)hipEventRecord(b, st);
-    c.pending.push_back({a, b, kind, bytes, particles});
+    c.pending.push_back({a, b, kind, bytes, particles, c.cur_tag});
   }
 };
 
-// after the stream has been synchronised: fold finished pairs into totals
+// fold finished pairs into the totals; unfinished ones stay pending (all
+// are finished once the stream has been synchronised)
 void collect(Ctx& c) {
+  std::vector<Ctx::Pending> keep;
   for (auto& p : c.pending) {
+    if (hipEventQuery(p.b) == hipErrorNotReady) {
+      keep.push_back(p);
+      continue;
+    }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       c.prof.launches[p.kind] += 1;
@@ -239,7 +247,30 @@ void collect(Ctx& c) {
     c.ev_pool.push_back(p.a);
     c.ev_pool.push_back(p.b);
   }
-  c.pending.clear();
+  c.pending.swap(keep);
+  std::vector<hipEvent_t> still;
+  for (hipEvent_t e : c.ev_dropped) {
+    if (hipEventQuery(e) == hipErrorNotReady)
+      still.push_back(e);
+    else
+      c.ev_pool.push_back(e);
+  }
+  c.ev_dropped.swap(still);
+}
+
+// forget the timings of launches enqueued under `tag` (a speculative
+// iteration that was not needed); their events still complete normally
+void drop_tag(Ctx& c, int tag) {
+  std::vector<Ctx::Pending> keep;
+  for (auto& p : c.pending) {
+    if (p.tag == tag) {
+      c.ev_dropped.push_back(p.a);
+      c.ev_dropped.push_back(p.b);
+    } else {
+      keep.push_back(p);
+    }
+  }
+  c.pending.swap(keep);
 }
 
 // algorithmic bytes per particle of a push pass: the state read once
@@ -295,49 +326,56 @@ PushArgs push_args(Ctx& c, int sid, int commit) {
   return a;
 }
 
-// One pass over all species; currents zeroed first.
-// One pass over all species.  Inside a step the currents were already reset
-// (by the guess kernel or the last field solve); a standalone pass resets them.
-ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool zero_currents) {
-  if (zero_currents) {
+// One pass over all species, two species per launch, all on the context
+// stream.  Inside a step the currents, queue counters and tallies were
+// already reset (by the guess kernel, the last field solve and the residual
+// kernel); a standalone pass (prezeroed false) resets them itself.
+ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroed,
+                  bool guarded = false) {
+  if (!prezeroed) {
     HIPCHK(zero(c.Ir, n_edges_r(c), c.stream));
     HIPCHK(zero(c.Iz, n_edges_z(c), c.stream));
+    if (commit) HIPCHK(launch_zero_tally(c, c.stream));
+    HIPCHK(launch_zero_i(c.qcount, kMaxSpecies * kSpread * kLineInts, c.stream));
   }
-  if (commit) HIPCHK(hipMemsetAsync(c.tally, 0, kSpread * sizeof(Tally), c.stream));
-  HIPCHK(launch_zero_i(c.qcount, kMaxSpecies * kSpread * kLineInts, c.stream));
   // append offsets of every species are taken before any pass appends
   std::vector<MccDev> mcc(c.sp.size());
   for (size_t s = 0; s < c.sp.size(); ++s) {
     std::memset(&mcc[s], 0, sizeof(MccDev));
     if (commit && with_mcc) mcc[s] = make_mcc(c, (int)s, step);
   }
-  // Each species: the fast pass on the main stream, then its slow pass on the
-  // species' own stream, so that it overlaps the next species' fast pass;
-  // the main stream waits for all slow passes before it goes on.
-  std::vector<int> joined;
-  for (size_t s = 0; s < c.sp.size(); ++s) {
-    if (!c.sp[s].desc.mobile || c.sp[s].n == 0) continue;
-    PushArgs a = push_args(c, (int)s, commit);
-    a.mcc = mcc[s];
-    int32_t* q = c.queue + (int64_t)s * c.queue_cap;
-    int32_t* qc = c.qcount + s * kSpread * kLineInts;
-    const int64_t seg = queue_segment(c.sp[s].n);
-    {
+  std::vector<int> act;
+  for (size_t s = 0; s < c.sp.size(); ++s)
+    if (c.sp[s].desc.mobile && c.sp[s].n > 0) act.push_back((int)s);
+  for (size_t b = 0; b < act.size(); b += 2) {
+    PassArgs P;
+    std::memset(&P, 0, sizeof(P));
+    P.nsp = (b + 1 < act.size()) ? 2 : 1;
+    double bytes = 0.0;
+    int64_t parts = 0;
+    for (int q = 0; q < P.nsp; ++q) {
+      const int s = act[b + q];
+      PushArgs& a = P.a[q];
+      a = push_args(c, s, commit);
+      a.mcc = mcc[s];
+      a.stop = guarded ? c.stop : nullptr;
+      P.queue[q] = c.queue + (int64_t)s * c.queue_cap;
+      P.qcount[q] = c.qcount + s * kSpread * kLineInts;
+      P.qseg[q] = queue_segment(c.sp[s].n);
       // commit: state + id read, state written; iteration: state read
-      const double per = commit ? 2.0 * state_bytes(c) + 8.0 : state_bytes(c);
-      Timed tm(c, commit ? ECPIC_K_COMMIT : ECPIC_K_PUSH, per * (double)c.sp[s].n, c.sp[s].n);
-      HIPCHK(launch_push_fast(a, q, seg, qc, c.stream));
+      bytes += (commit ? 2.0 * state_bytes(c) + 8.0 : state_bytes(c)) * (double)c.sp[s].n;
+      parts += c.sp[s].n;
     }
-    HIPCHK(hipEventRecord(c.ev_fast[s], c.stream));
-    HIPCHK(hipStreamWaitEvent(c.aux[s], c.ev_fast[s], 0));
+    P.nb0 = (P.a[0].s.n + kBlock - 1) / kBlock;
     {
-      Timed tm(c, commit ? ECPIC_K_COMMIT_SLOW : ECPIC_K_PUSH_SLOW, 0.0, 0, c.aux[s]);
-      HIPCHK(launch_push_slow(a, q, seg, qc, c.aux[s]));
+      Timed tm(c, commit ? ECPIC_K_COMMIT : ECPIC_K_PUSH, bytes, parts);
+      HIPCHK(launch_push_fast(P, c.stream));
     }
-    HIPCHK(hipEventRecord(c.ev_slow[s], c.aux[s]));
-    joined.push_back((int)s);
+    {
+      Timed tm(c, commit ? ECPIC_K_COMMIT_SLOW : ECPIC_K_PUSH_SLOW, 0.0, 0);
+      HIPCHK(launch_push_slow(P, c.stream));
+    }
   }
-  for (int s : joined) HIPCHK(hipStreamWaitEvent(c.stream, c.ev_slow[s], 0));
   return ECPIC_OK;
 }
 
@@ -446,18 +484,24 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   ok = ok && dalloc(&c.scan_part, (size_t)(nh + 1023) / 1024 + 2) == hipSuccess;
   ok = ok && dalloc(&c.tally, kSpread) == hipSuccess;
   ok = ok && dalloc(&c.qcount, kMaxSpecies * kSpread * kLineInts) == hipSuccess;
-  for (int s = 0; s < kMaxSpecies; ++s) {
-    ok = ok && hipStreamCreateWithFlags(&c.aux[s], hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&c.ev_fast[s], hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&c.ev_slow[s], hipEventDisableTiming) == hipSuccess;
-  }
   ok = ok && hipHostMalloc((void**)&c.tally_host, kSpread * sizeof(Tally)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.red_host, 64 * sizeof(double)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.part_host, kPartLen * sizeof(double)) == hipSuccess;
+  ok = ok && dalloc(&c.stop, 1) == hipSuccess;
+  // written by kernels with system-scope stores and polled by the host
+  ok = ok && hipHostMalloc((void**)&c.res_host, kMaxIter * sizeof(double),
+                           hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c.fin_host, sizeof(StepFinal),
+                           hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c.sort_total_host, kMaxSpecies * sizeof(int32_t)) == hipSuccess;
+  ok = ok && hipHostGetDevicePointer((void**)&c.res_dev, c.res_host, 0) == hipSuccess;
+  ok = ok && hipHostGetDevicePointer((void**)&c.fin_dev, c.fin_host, 0) == hipSuccess;
   if (!ok) {
     ecpic_destroy(x);
     return ECPIC_ENOMEM;
   }
+  std::memset((void*)c.fin_host, 0, sizeof(StepFinal));
+  for (int k = 0; k < kMaxIter; ++k) std::memcpy(&c.res_host[k], &kResPending, sizeof(double));
   if (setup_solver(c) != hipSuccess) {
     ecpic_destroy(x);
     return ECPIC_EHIP;
@@ -466,6 +510,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
                   c.ur_half, c.uz_half, c.Ir, c.Iz, c.ur_half2, c.uz_half2};
   int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz};
   for (int k = 0; k < 14; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
+  (void)launch_zero_i(c.stop, 1, c.stream);
   (void)launch_zero(c.wall_bot, g->nr + 1, c.stream);
   (void)launch_zero(c.wall_top, g->nr + 1, c.stream);
   (void)launch_zero(c.wall_side, g->nz + 1, c.stream);
@@ -505,16 +550,19 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
   (void)hipFree(c.nn_w);
   (void)hipFree(c.nn_ws);
   collect(c);
-  for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
-  for (int s = 0; s < kMaxSpecies; ++s) {
-    if (c.aux[s]) (void)hipStreamSynchronize(c.aux[s]);
-    if (c.aux[s]) (void)hipStreamDestroy(c.aux[s]);
-    if (c.ev_fast[s]) (void)hipEventDestroy(c.ev_fast[s]);
-    if (c.ev_slow[s]) (void)hipEventDestroy(c.ev_slow[s]);
+  for (auto& p : c.pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
   }
+  for (hipEvent_t e : c.ev_dropped) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
   if (c.tally_host) (void)hipHostFree(c.tally_host);
   if (c.red_host) (void)hipHostFree(c.red_host);
   if (c.part_host) (void)hipHostFree(c.part_host);
+  (void)hipFree(c.stop);
+  if (c.res_host) (void)hipHostFree(c.res_host);
+  if (c.fin_host) (void)hipHostFree(c.fin_host);
+  if (c.sort_total_host) (void)hipHostFree(c.sort_total_host);
   delete x;
   return ECPIC_OK;
 }
@@ -649,7 +697,7 @@ ecpic_status ecpic_set_half_field(ecpic_ctx* x, const double* urh, const double*
 ecpic_status ecpic_push_deposit(ecpic_ctx* x, int32_t commit, double* Ir, double* Iz) {
   if (!x) return ECPIC_EINVAL;
   Ctx& c = x->c;
-  ecpic_status rc = pass(c, commit ? 1 : 0, false, c.step, true);
+  ecpic_status rc = pass(c, commit ? 1 : 0, false, c.step, false);
   if (rc != ECPIC_OK) return rc;
   if (Ir) HIPCHK(launch_copy(Ir, c.Ir, n_edges_r(c), c.stream));
   if (Iz) HIPCHK(launch_copy(Iz, c.Iz, n_edges_z(c), c.stream));
@@ -682,11 +730,13 @@ ecpic_status ecpic_field_solve(ecpic_ctx* x, const double* ur0, const double* uz
   return ECPIC_OK;
 }
 
-// One field iterate: solve with the current I into the *_nx buffers, write
-// the next half-step field into *_half2, zero I, and return the residual
-// against the previous iterate.  The new iterate becomes *_it.
-static ecpic_status iterate(Ctx& c, double* r_out) {
-  const int nr = c.g.nr;
+// Enqueue the field part of Picard iteration k: solve with the current I into
+// the *_nx buffers, write the next half-step field into *_half2, zero I, and
+// the residual against the previous iterate into res_host[k] (polled with
+// wait_residual); the new iterate becomes *_it.  Guarded: every kernel returns at
+// once when the stop flag is set (a speculative iteration after convergence);
+// the flag is set when the residual is <= tol.
+static ecpic_status enqueue_solve(Ctx& c, int k, double tol, bool guarded) {
   SolveArgs a;
   std::memset(&a, 0, sizeof(a));
   a.ur0 = c.ur;
@@ -707,6 +757,7 @@ static ecpic_status iterate(Ctx& c, double* r_out) {
   a.ur_hf = c.ur_half_f2;
   a.uz_hf = c.uz_half_f2;
   a.zero_I = 1;
+  a.stop = guarded ? c.stop : nullptr;
   {
     // field arrays: u0, I, u_old read, u1 and the half field written, h0 read,
     // h1 written (FP64)
@@ -714,19 +765,54 @@ static ecpic_status iterate(Ctx& c, double* r_out) {
     Timed tm(c, ECPIC_K_FIELD, fb, 0);
     HIPCHK(field_solve(c, a, c.stream));
   }
-  HIPCHK(hipMemcpyAsync(c.part_host + kOffRes, c.sol.partial + kOffRes, 2 * nr * sizeof(double),
-                        hipMemcpyDeviceToHost, c.stream));
+  static_assert(kOffRes == 0, "the residual kernel reads the partials at offset 0");
+  std::memcpy(&c.res_host[k], &kResPending, sizeof(double));
+  HIPCHK(launch_converge(c, k, tol, c.stream));
   std::swap(c.ur_it, c.ur_nx);
   std::swap(c.uz_it, c.uz_nx);
   std::swap(c.h_it, c.h_nx);
+  return ECPIC_OK;
+}
+
+// Spin until the device has stored the 8-byte word at p (a value other
+// than `pending`), checking the stream now and then so that a failed or
+// drained stream cannot leave the host waiting for ever.
+static ecpic_status wait_word(Ctx& c, const volatile uint64_t* p, uint64_t pending,
+                              uint64_t* out) {
+  for (uint64_t spin = 0;; ++spin) {
+    const uint64_t v = *p;
+    if (v != pending) {
+      *out = v;
+      std::atomic_thread_fence(std::memory_order_acquire);
+      return ECPIC_OK;
+    }
+    if ((spin & 1023) == 1023) {
+      const hipError_t e = hipStreamQuery(c.stream);
+      if (e != hipSuccess && e != hipErrorNotReady) return fail(c, ECPIC_EHIP, hipGetErrorString(e));
+      if (e == hipSuccess && *p == pending)
+        return fail(c, ECPIC_EHIP, "stream drained without the expected device result");
+    }
+  }
+}
+
+static ecpic_status wait_residual(Ctx& c, int k, double* r) {
+  uint64_t bits = 0;
+  ecpic_status rc = wait_word(c, reinterpret_cast<volatile uint64_t*>(c.res_host + k),
+                              kResPending, &bits);
+  if (rc != ECPIC_OK) return rc;
+  std::memcpy(r, &bits, sizeof(double));
+  return ECPIC_OK;
+}
+
+// One unguarded field iterate with the current I; returns the residual.
+static ecpic_status iterate(Ctx& c, double* r_out) {
+  HIPCHK(launch_zero_i(c.stop, 1, c.stream));
+  ecpic_status rc = enqueue_solve(c, 0, -1.0, false);
+  if (rc != ECPIC_OK) return rc;
+  rc = wait_residual(c, 0, r_out);
+  if (rc != ECPIC_OK) return rc;
   HIPCHK(hipStreamSynchronize(c.stream));
   collect(c);
-  double num = 0.0, den = 0.0;
-  for (int i = 0; i < nr; ++i) {
-    num += c.part_host[kOffRes + 2 * i];
-    den += c.part_host[kOffRes + 2 * i + 1];
-  }
-  *r_out = den > 0.0 ? std::sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
   return ECPIC_OK;
 }
 
@@ -771,7 +857,7 @@ ecpic_status ecpic_collide(ecpic_ctx* x, const ecpic_mcc_desc* m, int64_t step) 
   ecpic_mcc_desc saved = c.mcc;
   ecpic_status rc = ecpic_set_mcc(x, m);
   if (rc != ECPIC_OK) return rc;
-  HIPCHK(hipMemsetAsync(c.tally, 0, kSpread * sizeof(Tally), c.stream));
+  HIPCHK(launch_zero_tally(c, c.stream));
   std::vector<MccDev> d(c.sp.size());
   for (size_t s = 0; s < c.sp.size(); ++s) d[s] = make_mcc(c, (int)s, step);
   for (size_t s = 0; s < c.sp.size(); ++s) {
@@ -826,12 +912,12 @@ static ecpic_status diag_into(Ctx& c, ecpic_step_stats* st) {
   return ECPIC_OK;
 }
 
-ecpic_status ecpic_set_profiling(ecpic_ctx* x, int32_t on) {
+ecpic_status ecpic_set_profiling(ecpic_ctx* x, int32_t kind_mask) {
   if (!x) return ECPIC_EINVAL;
   Ctx& c = x->c;
   HIPCHK(hipStreamSynchronize(c.stream));
   collect(c);
-  c.prof_on = on != 0;
+  c.prof_mask = (uint32_t)kind_mask & ((1u << ECPIC_K_COUNT) - 1u);
   std::memset(&c.prof, 0, sizeof(c.prof));
   return ECPIC_OK;
 }
@@ -867,54 +953,106 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     if (rc != ECPIC_OK) return rc;
     S->used_nn = used ? 1 : 0;
   }
+  // Picard iterations, one enqueued ahead of the one being waited for: the
+  // next push starts while the host reads the residual.  If the residual
+  // meets the tolerance, the iteration enqueued ahead finds the stop flag set
+  // and does nothing, and the buffer roles are put back as they were.
+  const bool tol_mode = o->fixed_iter <= 0;
+  const double dtol = tol_mode ? o->tol : -1.0;
+  struct Roles {
+    double *ur_it, *uz_it, *h_it, *ur_nx, *uz_nx, *h_nx, *ur_half, *uz_half, *ur_half2,
+        *uz_half2;
+    float *ur_half_f, *uz_half_f, *ur_half_f2, *uz_half_f2;
+  };
+  auto save = [&](Roles& r) {
+    r = Roles{c.ur_it, c.uz_it, c.h_it, c.ur_nx, c.uz_nx, c.h_nx, c.ur_half, c.uz_half,
+              c.ur_half2, c.uz_half2, c.ur_half_f, c.uz_half_f, c.ur_half_f2, c.uz_half_f2};
+  };
+  auto restore = [&](const Roles& r) {
+    c.ur_it = r.ur_it; c.uz_it = r.uz_it; c.h_it = r.h_it;
+    c.ur_nx = r.ur_nx; c.uz_nx = r.uz_nx; c.h_nx = r.h_nx;
+    c.ur_half = r.ur_half; c.uz_half = r.uz_half;
+    c.ur_half2 = r.ur_half2; c.uz_half2 = r.uz_half2;
+    c.ur_half_f = r.ur_half_f; c.uz_half_f = r.uz_half_f;
+    c.ur_half_f2 = r.ur_half_f2; c.uz_half_f2 = r.uz_half_f2;
+  };
+  auto enqueue_iteration = [&](int k) -> ecpic_status {
+    c.cur_tag = k;
+    ecpic_status rc = pass(c, 0, false, c.step, true, true);
+    if (rc != ECPIC_OK) return rc;
+    return enqueue_solve(c, k, dtol, true);
+  };
   int k = 0;
   bool conv = false;
-  double prev_r = INFINITY;
+  {
+    ecpic_status rc = enqueue_iteration(0);
+    if (rc != ECPIC_OK) return rc;
+  }
   for (k = 0; k < kmax; ++k) {
-    ecpic_status rc = pass(c, 0, false, c.step, false);
-    if (rc != ECPIC_OK) return rc;
-    double r;
-    rc = iterate(c, &r);
-    if (rc != ECPIC_OK) return rc;
+    Roles after_k;
+    save(after_k);
+    const bool ahead = k + 1 < kmax;
+    if (ahead) {
+      // the next push uses (u^n + u^{n+1,(k+1)}) / 2
+      swap_half(c);
+      ecpic_status rc = enqueue_iteration(k + 1);
+      if (rc != ECPIC_OK) return rc;
+    }
+    double r = 0.0;
+    {
+      ecpic_status rc = wait_residual(c, k, &r);
+      if (rc != ECPIC_OK) return rc;
+    }
     S->residual[k] = r;
-    if (o->fixed_iter <= 0 && r <= o->tol) {
+    if (tol_mode && r <= o->tol) {
       conv = true;
+      if (ahead) {
+        // the commit keeps the half-step field of push k and iterate k
+        restore(after_k);
+        drop_tag(c, k + 1);
+      }
       ++k;
       break;
     }
-    prev_r = r;
-    // the next push uses (u^n + u^{n+1,(k+1)}) / 2; after the last pass the
-    // commit keeps the field of that pass
-    if (k + 1 < kmax) swap_half(c);
+    // timings of iterations that are known to be needed
+    collect(c);
   }
-  (void)prev_r;
+  c.cur_tag = -1;
   S->iters = k;
-  if (o->fixed_iter > 0) conv = true;
+  if (!tol_mode) conv = true;
   S->converged = conv ? 1 : 0;
-  if (!conv) return fail(c, ECPIC_ENOTCONV, "Picard iteration did not converge");
+  if (!conv) {
+    HIPCHK(hipStreamSynchronize(c.stream));
+    collect(c);
+    return fail(c, ECPIC_ENOTCONV, "Picard iteration did not converge");
+  }
   // commit the particles pushed in the accepted half-step field, with MCC
-  ecpic_status rc = pass(c, 1, c.mcc.enabled != 0, c.step, false);
+  ecpic_status rc = pass(c, 1, c.mcc.enabled != 0, c.step, true);
   if (rc != ECPIC_OK) return rc;
   double* d = c.sol.partial;
   HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir, c.Iz, d + kOffEx, c.stream));
-  const int nr = c.g.nr, nz = c.g.nz;
-  HIPCHK(hipMemcpyAsync(c.part_host + kOffEx, d + kOffEx, kRedBlocks * sizeof(double),
-                        hipMemcpyDeviceToHost, c.stream));
-  HIPCHK(hipMemcpyAsync(c.red_host + 33, c.h + (int64_t)(nr - 1) * nz, sizeof(double),
-                        hipMemcpyDeviceToHost, c.stream));
-  HIPCHK(hipMemcpyAsync(c.red_host + 34, c.h_it + (int64_t)(nr - 1) * nz, sizeof(double),
-                        hipMemcpyDeviceToHost, c.stream));
-  HIPCHK(hipMemcpyAsync(c.red_host + 35, c.Ir + (int64_t)(nr - 1) * (nz + 1), sizeof(double),
-                        hipMemcpyDeviceToHost, c.stream));
-  Tally t;
-  rc = finish_tally(c, t);  // synchronises
+  const uint64_t seq = ++c.fin_seq;
+  HIPCHK(launch_finalize(c, d + kOffEx, seq, c.stream));
+  {
+    uint64_t got = 0;
+    rc = wait_word(c, reinterpret_cast<volatile uint64_t*>(&c.fin_host->seq), seq - 1, &got);
+    if (rc != ECPIC_OK) return rc;
+  }
+  StepFinal fin;
+  std::memcpy(&fin, (const void*)c.fin_host, sizeof(fin));
+  collect(c);
+  const Tally& t = fin.t;
+  for (size_t s = 0; s < c.sp.size(); ++s) {
+    int64_t n = c.sp[s].n + (int64_t)t.append[s];
+    if (n > c.sp[s].desc.capacity) n = c.sp[s].desc.capacity;
+    c.sp[s].n = n;
+  }
+  if (t.n_overflow) rc = fail(c, ECPIC_ECAPACITY, "species capacity exceeded by ionisation");
   const double vh = 0.5 * (vnow + vnext);
-  const double rgap = r_of_xi(c.m, nr - 0.5);
-  double xs = 0.0;
-  for (int b = 0; b < kRedBlocks; ++b) xs += c.part_host[kOffEx + b];
-  S->w_field_io = c.g.dt * xs;
-  S->w_drive = c.g.dt * (2.0 * kPi * rgap * 0.5 * (c.red_host[33] + c.red_host[34]) * vh +
-                         vh * c.red_host[35]);
+  const double rgap = r_of_xi(c.m, c.g.nr - 0.5);
+  S->w_field_io = c.g.dt * fin.xs;
+  S->w_drive = c.g.dt * (2.0 * kPi * rgap * 0.5 * (fin.h_gap_n + fin.h_gap_1) * vh +
+                         vh * fin.ir_gap);
   S->w_particles = t.w_particles;
   S->w_absorbed = t.w_absorbed;
   S->w_coll = t.w_coll;
@@ -936,15 +1074,14 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
   c.t += c.g.dt;
   c.step += 1;
   if (o->sort_every > 0 && c.step % o->sort_every == 0) {
-    for (Species& s : c.sp) {
-      const int64_t n0 = s.n;
-      {
-        Timed tm(c, ECPIC_K_SORT, (2.0 * (state_bytes(c) + 8.0) + 16.0) * (double)n0, n0);
-        HIPCHK(launch_sort(c, s, c.stream, nullptr));
-      }
-      HIPCHK(hipStreamSynchronize(c.stream));
-      collect(c);
+    for (size_t s = 0; s < c.sp.size(); ++s) {
+      const int64_t n0 = c.sp[s].n;
+      Timed tm(c, ECPIC_K_SORT, (2.0 * (state_bytes(c) + 8.0) + 16.0) * (double)n0, n0);
+      HIPCHK(launch_sort_async(c, c.sp[s], c.sort_total_host + s, c.stream));
     }
+    HIPCHK(hipStreamSynchronize(c.stream));
+    collect(c);
+    for (size_t s = 0; s < c.sp.size(); ++s) finish_sort(c.sp[s], c.sort_total_host[s]);
   }
   if (st) {
     ecpic_status r2 = diag_into(c, S);

@@ -41,7 +41,9 @@ __global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restric
                                                  const double* __restrict__ Ir,
                                                  const double* __restrict__ Iz, double vhalf,
                                                  const double* __restrict__ Qt,
-                                                 double* __restrict__ hat) {
+                                                 double* __restrict__ hat,
+                                                 const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
   extern __shared__ double sh[];
   const int nr = m.nr, nz = m.nz;
   const int i = blockIdx.x;
@@ -110,7 +112,9 @@ constexpr int kMaxE = 8;  // rows per thread: nr <= kFB * kMaxE
 __global__ void __launch_bounds__(kFB) k_tri_scan(int nr, const double* __restrict__ lo,
                                                   const double* __restrict__ inv,
                                                   const double* __restrict__ up,
-                                                  double* __restrict__ hat) {
+                                                  double* __restrict__ hat,
+                                                  const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
   __shared__ Aff sA[kFB];
   const int k = blockIdx.x;
   double* x = hat + (int64_t)k * nr;
@@ -190,6 +194,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
                                                       const double* __restrict__ wz,
                                                       const double* __restrict__ Q,
                                                       const double* __restrict__ hat) {
+  if (a.stop && *a.stop) return;
   extern __shared__ double sh[];
   const int nr = m.nr, nz = m.nz;
   const int i = blockIdx.x;
@@ -289,15 +294,27 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
   }
 }
 
+// Clear the per-pass queue counters and tally copies (thread t of nthreads).
+__device__ __forceinline__ void clear_pass_scratch(int64_t t, int64_t nthreads, int32_t* qcount,
+                                                   Tally* tally) {
+  for (int64_t q = t; q < (int64_t)kMaxSpecies * kSpread * kLineInts; q += nthreads) qcount[q] = 0;
+  uint64_t* tw = reinterpret_cast<uint64_t*>(tally);
+  const int64_t nw = (int64_t)kSpread * (int64_t)(sizeof(Tally) / sizeof(uint64_t));
+  for (int64_t q = t; q < nw; q += nthreads) tw[q] = 0;
+}
+
 // guess u^{n+1,(0)} = 2 u^n - u^{n-1} (walls at t^{n+1}), the half-step field
 // of the first push, the wall values of u^n at t^n, and zeroed currents.
 __global__ void k_guess_half(MapP m, double* ur, double* uz, const double* ur_prev,
                              const double* uz_prev, double* ur_it, double* uz_it, double* ur_h,
                              double* uz_h, float* ur_hf, float* uz_hf, double* Ir, double* Iz,
-                             double vnow, double vnext) {
+                             double vnow, double vnext, int32_t* stop, int32_t* qcount,
+                             Tally* tally) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int nr = m.nr, nz = m.nz;
   const int64_t nur = (int64_t)nr * (nz + 1), nuz = (int64_t)(nr + 1) * nz;
+  if (t == 0) *stop = 0;
+  clear_pass_scratch(t, (int64_t)gridDim.x * blockDim.x, qcount, tally);
   if (t < nur) {
     const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
     double u0 = ur[t], u1;
@@ -438,13 +455,105 @@ __global__ void __launch_bounds__(kBlock) k_xsum(MapP m, const double* __restric
   }
 }
 
+// Residual of a Picard iterate: r = sqrt(sum w (u1 - u_old)^2 / sum w u1^2)
+// over the interior edges, from the per-row partials of the solve: the first
+// wavefront sums rows l, l + 64, ... per lane and then combines the lanes in
+// a fixed butterfly order (deterministic).  The other threads clear the pass
+// scratch for the next push.
+__global__ void __launch_bounds__(256) k_converge(const double* __restrict__ part, int nr, int k,
+                                                  double tol, int32_t* stop, double* res,
+                                                  int32_t* qcount, Tally* tally) {
+  if (*stop) return;
+  const int t = threadIdx.x;
+  if (t >= 64) {
+    clear_pass_scratch(t - 64, blockDim.x - 64, qcount, tally);
+    return;
+  }
+  double num = 0.0, den = 0.0;
+  for (int i = t; i < nr; i += 64) {
+    num += part[2 * i];
+    den += part[2 * i + 1];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    num += __shfl_xor(num, off, 64);
+    den += __shfl_xor(den, off, 64);
+  }
+  if (t != 0) return;
+  double r = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+  if (r != r) r = __longlong_as_double(0x7ff8000000000000ll);  // one quiet NaN
+  store_sys(res + k, r);
+  if (r <= tol) *stop = 1;
+}
+
+// Commit summary: tallies summed over their copies in copy order, the
+// exchange partials in block order, and the drive-gap values; the sequence
+// number is stored last, after a system-scope fence.  One thread.
+__global__ void k_finalize(const Tally* __restrict__ tally, const double* __restrict__ xpart,
+                           const double* __restrict__ hn, const double* __restrict__ h1,
+                           const double* __restrict__ Ir, int nr, int nz, uint64_t seq,
+                           StepFinal* out) {
+  if (threadIdx.x != 0) return;
+  Tally t = tally[0];
+  for (int q = 1; q < kSpread; ++q) {
+    const Tally& u = tally[q];
+    t.w_absorbed += u.w_absorbed;
+    t.w_coll += u.w_coll;
+    t.w_particles += u.w_particles;
+    for (int s = 0; s < kMaxSpecies; ++s) {
+      t.n_absorbed[s] += u.n_absorbed[s];
+      t.n_coll[s] += u.n_coll[s];
+      t.append[s] += u.append[s];
+    }
+    t.n_ionized += u.n_ionized;
+    t.n_errors += u.n_errors;
+    t.n_crossings += u.n_crossings;
+    t.n_substeps += u.n_substeps;
+    t.n_over_range += u.n_over_range;
+    t.n_overflow += u.n_overflow;
+  }
+  double xs = 0.0;
+  for (int b = 0; b < kRedBlocks; ++b) xs += xpart[b];
+  out->t = t;
+  out->xs = xs;
+  out->h_gap_n = hn[(int64_t)(nr - 1) * nz];
+  out->h_gap_1 = h1[(int64_t)(nr - 1) * nz];
+  out->ir_gap = Ir[(int64_t)(nr - 1) * (nz + 1)];
+  __threadfence_system();
+  store_sys(&out->seq, seq);
+}
+
+__global__ void k_zero_tally(Tally* tally) {
+  uint64_t* tw = reinterpret_cast<uint64_t*>(tally);
+  const int64_t nw = (int64_t)kSpread * (int64_t)(sizeof(Tally) / sizeof(uint64_t));
+  for (int64_t q = threadIdx.x; q < nw; q += blockDim.x) tw[q] = 0;
+}
+
 }  // namespace
+
+hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s) {
+  // the solve writes the residual row partials at the start of sol.partial
+  if (k < 0 || k >= kMaxIter) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, c.sol.partial, c.g.nr,
+                     k, tol, c.stop, c.res_dev, c.qcount, c.tally);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Ctx& c, const double* xpart, uint64_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, c.tally, xpart, c.h, c.h_it, c.Ir,
+                     c.g.nr, c.g.nz, seq, c.fin_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_tally(const Ctx& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_tally, dim3(1), dim3(256), 0, s, c.tally);
+  return hipGetLastError();
+}
 
 hipError_t launch_guess_half(const Ctx& c, double vnow, double vnext, hipStream_t s) {
   const int64_t n = (int64_t)(c.g.nr + 1) * (c.g.nz + 1);
   hipLaunchKernelGGL(k_guess_half, dim3(nblk(n)), dim3(kBlock), 0, s, c.m, c.ur, c.uz, c.ur_prev,
                      c.uz_prev, c.ur_it, c.uz_it, c.ur_half, c.uz_half, c.ur_half_f, c.uz_half_f,
-                     c.Ir, c.Iz, vnow, vnext);
+                     c.Ir, c.Iz, vnow, vnext, c.stop, c.qcount, c.tally);
   return hipGetLastError();
 }
 
@@ -461,9 +570,10 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s) {
   const SolverDev& S = c.sol;
   if (nr > kFB * kMaxE) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rhs_dct, dim3(nr), dim3(kFB), sizeof(double) * nz, s, c.m, S.rh, S.wr,
-                     S.wz, S.area, c.g.mu, a.ur0, a.uz0, a.h0, a.Ir, a.Iz, a.vhalf, S.Qt, S.work1);
+                     S.wz, S.area, c.g.mu, a.ur0, a.uz0, a.h0, a.Ir, a.Iz, a.vhalf, S.Qt, S.work1,
+                     a.stop);
   hipLaunchKernelGGL(k_tri_scan, dim3(nz), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv, S.tri_up,
-                     S.work1);
+                     S.work1, a.stop);
   hipLaunchKernelGGL(k_idct_recover, dim3(nr), dim3(kFB), sizeof(double) * 4 * nz, s, a, c.m,
                      S.rh, S.wr, S.wz, S.Q, S.work1);
   return hipGetLastError();

@@ -16,6 +16,7 @@ constexpr int kMaxSpecies = 4;
 constexpr int kMaxSub = 64;     // sub-steps per particle per step
 constexpr int kMaxHalve = 20;   // halvings of a sub-step whose solve fails
 constexpr int kMaxFixed = 50;   // fixed-point iterations per sub-step solve
+constexpr int kMaxIter = 64;    // Picard iterations per step
 constexpr int kBlock = 256;     // threads per block for particle kernels
 // Contended counters are spread over copies on separate cache lines: block b
 // uses copy b % kSpread (queue segments, commit tallies).
@@ -43,6 +44,15 @@ struct SpecDev {
   int32_t mobile, sid;
 };
 
+// Sentinel-free results the device leaves in host memory use 8-byte
+// system-scope stores (one access each, visible to a polling host).
+__device__ __forceinline__ void store_sys(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void store_sys(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Device-side tallies of a commit / collision pass.
 struct Tally {
   double w_absorbed, w_coll, w_particles;
@@ -51,6 +61,17 @@ struct Tally {
   unsigned long long n_coll[kMaxSpecies];
   unsigned long long n_ionized, n_errors, n_crossings, n_substeps, n_over_range, n_overflow;
   unsigned long long append[kMaxSpecies];
+};
+
+// What the host needs after a commit: the tallies summed over their copies,
+// the field-particle exchange, and the drive-gap values of the energy balance.
+struct StepFinal {
+  Tally t;
+  double xs;        // sum over interior edges of u^{1/2} . I
+  double h_gap_n;   // h^n at the drive-gap cell
+  double h_gap_1;   // h^{n+1} at the drive-gap cell
+  double ir_gap;    // I_r on the drive-gap edge
+  uint64_t seq;     // written last: the host polls it
 };
 
 // Null-collision parameters of one pass, prepared on the host.
@@ -81,6 +102,20 @@ struct PushArgs {
   Tally* tally;
   MccDev mcc;
   int32_t* hist;     // per-cell counts of the survivors (commit), or null
+  const int32_t* stop;  // when set and nonzero the pass does nothing (or null)
+};
+
+// One push pass over up to two species in one launch (slot 0 and slot 1):
+// the fast kernel gives blocks [0, nb0) to slot 0 and the rest to slot 1;
+// the slow kernel takes the slot from blockIdx.z.  Both slots share the
+// pass-wide members of a[0] (fields, currents, walls, tallies, stop, commit).
+struct PassArgs {
+  PushArgs a[2];
+  int32_t* queue[2];   // kSpread segments of qseg entries per slot
+  int32_t* qcount[2];  // kSpread counters, kLineInts apart, zero on entry
+  int64_t qseg[2];
+  int64_t nb0;         // blocks of slot 0 in the fast kernel
+  int32_t nsp;         // slots in use (1 or 2)
 };
 
 // One Crank-Nicolson field solve.  Optional outputs (null = skipped): the
@@ -96,6 +131,7 @@ struct SolveArgs {
   double *ur_h, *uz_h;  // (u0 + u1) / 2
   float *ur_hf, *uz_hf;
   int32_t zero_I;
+  const int32_t* stop;  // when set and nonzero the solve does nothing (or null)
 };
 
 constexpr int kRedBlocks = 256;  // partial-sum blocks of the field reductions
@@ -140,6 +176,16 @@ struct Ctx {
   double *ur_half2, *uz_half2;     // half-step field of the next push
   float *ur_half_f2, *uz_half_f2;
   double* part_host;               // pinned host copy of reduction partials
+  // speculative Picard iterations: a device flag set once an iterate meets
+  // the tolerance (every kernel of a later iteration then returns at once),
+  // and the residuals written by the device into pinned host memory
+  int32_t* stop = nullptr;
+  double* res_host = nullptr;      // [kMaxIter], coherent pinned, device-written
+  double* res_dev = nullptr;       // device alias of res_host
+  struct StepFinal* fin_host = nullptr;  // commit summary, coherent pinned
+  struct StepFinal* fin_dev = nullptr;   // device alias
+  uint64_t fin_seq = 0;            // sequence number of the last summary asked for
+  int32_t* sort_total_host = nullptr;    // [kMaxSpecies], pinned
   double *Ir, *Iz;                 // currents
   double *wall_bot, *wall_top, *wall_side;
   int32_t* hist;                   // per-cell counts [nr*nz + 1]
@@ -148,8 +194,6 @@ struct Ctx {
   Tally* tally;                    // device tallies, kSpread copies
   int32_t* queue = nullptr;        // slow-pass particle queues, one per species
   int64_t queue_cap = 0;           // entries per species
-  hipStream_t aux[kMaxSpecies] = {};  // slow passes overlap the next fast pass
-  hipEvent_t ev_fast[kMaxSpecies] = {}, ev_slow[kMaxSpecies] = {};
   int32_t* qcount = nullptr;       // queue lengths [kMaxSpecies][kSpread][kLineInts]
   Tally* tally_host;               // pinned host mirror of the copies
   double* red_host;                // pinned host reduction results
@@ -165,16 +209,19 @@ struct Ctx {
   void* nn_ws = nullptr;           // activation workspace
   size_t nn_ws_bytes = 0;
   // event timing of the hot kernels
-  bool prof_on = false;
+  uint32_t prof_mask = 0;          // bit k: time launches of kind k
+  int cur_tag = 0;                 // iteration whose launches are being enqueued
   ecpic_profile prof{};
   struct Pending {
     hipEvent_t a, b;
     int kind;
     double bytes;
     int64_t particles;
+    int tag;
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> ev_pool;
+  std::vector<hipEvent_t> ev_dropped;  // back to the pool at the next collect
 };
 
 // ---- launchers (stream-ordered, no synchronisation) ----
@@ -183,10 +230,8 @@ struct Ctx {
 // ones it queued (cell crossers, failed solves).  queue holds kSpread
 // segments of queue_seg entries; qcount (kSpread counters, kLineInts apart)
 // must be zero on entry.  tally points at kSpread copies.
-hipError_t launch_push_fast(const PushArgs& a, int32_t* queue, int64_t queue_seg,
-                            int32_t* qcount, hipStream_t s);
-hipError_t launch_push_slow(const PushArgs& a, int32_t* queue, int64_t queue_seg,
-                            int32_t* qcount, hipStream_t s);
+hipError_t launch_push_fast(const PassArgs& p, hipStream_t s);
+hipError_t launch_push_slow(const PassArgs& p, hipStream_t s);
 // entries per queue segment for n particles
 inline int64_t queue_segment(int64_t n) {
   const int64_t nb = (n + kBlock - 1) / kBlock;
@@ -210,6 +255,16 @@ hipError_t launch_guess_half(const Ctx& c, double vnow, double vnext, hipStream_
 hipError_t launch_half(const Ctx& c, const double* u0r, const double* u0z, const double* u1r,
                        const double* u1z, hipStream_t s);
 hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s);
+// residual of iterate k from the solve's row partials, stored to res_dev[k]
+// (host memory, polled); sets *stop when it is <= tol (tol < 0: never) and
+// clears the queue counters and tallies for the next pass.  Does nothing
+// when *stop is already set.
+hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s);
+// commit summary into fin_dev (host memory), seq written last
+hipError_t launch_finalize(const Ctx& c, const double* xpart, uint64_t seq, hipStream_t s);
+hipError_t launch_zero_tally(const Ctx& c, hipStream_t s);
+// the value a residual slot holds until the device has written it
+constexpr uint64_t kResPending = 0x7ff4dead0badf00dull;
 // partials: [0, kRedBlocks) sum w u^2, [kRedBlocks, 2 kRedBlocks) sum 2 pi r A h^2
 hipError_t launch_field_energy(const Ctx& c, const double* ur, const double* uz, const double* h,
                                double* part, hipStream_t s);
@@ -224,6 +279,12 @@ double nu_max_host(const ecpic_mcc_desc& mcc, int role, double m_particle);
 ecpic_status nn_guess(Ctx& c, bool* used);
 // sort and diagnostics
 hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t s, int64_t* n_alive_host);
+// the same without synchronising: the survivor count goes to *total_pinned
+// (pinned host memory); once the stream is synchronised, finish_sort makes
+// the sorted buffer current.  Species sorted back to back share the
+// histogram buffers and must be enqueued on one stream.
+hipError_t launch_sort_async(Ctx& c, Species& sp, int32_t* total_pinned, hipStream_t s);
+void finish_sort(Species& sp, int32_t total);
 hipError_t launch_kinetic(const Species& sp, int mixed, double* out, hipStream_t s);
 hipError_t launch_node_charge(const Ctx& c, double* q, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);

@@ -915,10 +915,17 @@ __device__ void commit_one(const PushArgs& A, int64_t k, PState<T>& p, int statu
 // in its cell.  Those that stay in the closed cell are done (this is exactly
 // the first sub-step of the full algorithm); their currents are combined per
 // cell across the wavefront.  The others are queued for k_push_slow.
+// Blocks [0, nb0) serve species slot 0 of the pass, the rest slot 1.
 template <typename T, bool COMMIT>
-__global__ void __launch_bounds__(kBlock) k_push_fast(PushArgs A, int32_t* queue, int64_t qseg,
-                                                      int32_t* qcount) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
+  if (P.a[0].stop && *P.a[0].stop) return;
+  const bool second = (int64_t)blockIdx.x >= P.nb0;
+  const PushArgs& A = second ? P.a[1] : P.a[0];
+  int32_t* queue = second ? P.queue[1] : P.queue[0];
+  int32_t* qcount = second ? P.qcount[1] : P.qcount[0];
+  const int64_t qseg = second ? P.qseg[1] : P.qseg[0];
+  const int64_t bx = second ? (int64_t)blockIdx.x - P.nb0 : (int64_t)blockIdx.x;
+  const int64_t k = bx * kBlock + threadIdx.x;
   const MapP& m = A.m;
   const SpecDev& s = A.s;
   const T qm = T(s.q / s.m);
@@ -983,13 +990,13 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PushArgs A, int32_t* queue
     if (threadIdx.x == 0) {
       int tot = 0;
       for (int q = 0; q < kBlock / 64; ++q) tot += wcnt[q];
-      bbase = tot ? atomicAdd(qcount + (blockIdx.x % kSpread) * kLineInts, tot) : 0;
+      bbase = tot ? atomicAdd(qcount + (bx % kSpread) * kLineInts, tot) : 0;
     }
     __syncthreads();
     if (slow) {
       int r = bbase + __popcll(mask & ((1ull << lane) - 1ull));
       for (int q = 0; q < w; ++q) r += wcnt[q];
-      queue[(int64_t)(blockIdx.x % kSpread) * qseg + r] = (int32_t)k;
+      queue[(bx % kSpread) * qseg + r] = (int32_t)k;
     }
   }
   if (!COMMIT) return;
@@ -999,10 +1006,16 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PushArgs A, int32_t* queue
 
 // Slow pass over the queued particles: the full push with splitting at every
 // face crossing (restarted from the particle's state), currents by atomics.
+// grid (X, kSpread, species slots): blocks with blockIdx.y = g walk segment g
+// of the queue of slot blockIdx.z
 template <typename T, bool COMMIT>
-// grid (X, kSpread): blocks with blockIdx.y = g walk segment g
-__global__ void __launch_bounds__(kBlock) k_push_slow(PushArgs A, const int32_t* queue,
-                                                      int64_t qseg, const int32_t* qcount) {
+__global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
+  if (P.a[0].stop && *P.a[0].stop) return;
+  const bool second = blockIdx.z > 0;
+  const PushArgs& A = second ? P.a[1] : P.a[0];
+  const int32_t* queue = second ? P.queue[1] : P.queue[0];
+  const int32_t* qcount = second ? P.qcount[1] : P.qcount[0];
+  const int64_t qseg = second ? P.qseg[1] : P.qseg[0];
   const MapP& m = A.m;
   const SpecDev& s = A.s;
   const T qm = T(s.q / s.m);
@@ -1161,44 +1174,46 @@ double nu_max_host(const ecpic_mcc_desc& c, int role, double mp) {
   return 0.0;
 }
 
-hipError_t launch_push_fast(const PushArgs& a, int32_t* queue, int64_t qseg, int32_t* qcount,
-                            hipStream_t st) {
-  if (a.s.n <= 0) return hipSuccess;
-  const int64_t nb = (a.s.n + kBlock - 1) / kBlock;
-  const bool mixed = (a.s.cell != nullptr);
+hipError_t launch_push_fast(const PassArgs& P, hipStream_t st) {
+  const int64_t nb = P.nb0 + (P.nsp > 1 ? (P.a[1].s.n + kBlock - 1) / kBlock : 0);
+  if (nb <= 0) return hipSuccess;
+  const bool mixed = (P.a[0].s.cell != nullptr);
+  const bool commit = P.a[0].commit != 0;
   if (!mixed) {
-    if (a.commit)
-      hipLaunchKernelGGL((k_push_fast<double, true>), dim3(nb), dim3(kBlock), 0, st, a, queue, qseg, qcount);
+    if (commit)
+      hipLaunchKernelGGL((k_push_fast<double, true>), dim3(nb), dim3(kBlock), 0, st, P);
     else
-      hipLaunchKernelGGL((k_push_fast<double, false>), dim3(nb), dim3(kBlock), 0, st, a, queue, qseg, qcount);
+      hipLaunchKernelGGL((k_push_fast<double, false>), dim3(nb), dim3(kBlock), 0, st, P);
   } else {
-    if (a.commit)
-      hipLaunchKernelGGL((k_push_fast<float, true>), dim3(nb), dim3(kBlock), 0, st, a, queue, qseg, qcount);
+    if (commit)
+      hipLaunchKernelGGL((k_push_fast<float, true>), dim3(nb), dim3(kBlock), 0, st, P);
     else
-      hipLaunchKernelGGL((k_push_fast<float, false>), dim3(nb), dim3(kBlock), 0, st, a, queue, qseg, qcount);
+      hipLaunchKernelGGL((k_push_fast<float, false>), dim3(nb), dim3(kBlock), 0, st, P);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_push_slow(const PushArgs& a, int32_t* queue, int64_t qseg, int32_t* qcount,
-                            hipStream_t st) {
-  if (a.s.n <= 0) return hipSuccess;
-  const int64_t nb = (a.s.n + kBlock - 1) / kBlock;
+hipError_t launch_push_slow(const PassArgs& P, hipStream_t st) {
+  int64_t nmax = 0;
+  for (int q = 0; q < P.nsp; ++q) nmax = P.a[q].s.n > nmax ? P.a[q].s.n : nmax;
+  if (nmax <= 0) return hipSuccess;
+  const int64_t nb = (nmax + kBlock - 1) / kBlock;
   // per segment enough blocks for a few percent of the particles
   int64_t xs = (nb / kSpread + 7) / 8;
   xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
-  const dim3 gs((unsigned)xs, kSpread);
-  const bool mixed = (a.s.cell != nullptr);
+  const dim3 gs((unsigned)xs, kSpread, (unsigned)P.nsp);
+  const bool mixed = (P.a[0].s.cell != nullptr);
+  const bool commit = P.a[0].commit != 0;
   if (!mixed) {
-    if (a.commit)
-      hipLaunchKernelGGL((k_push_slow<double, true>), gs, dim3(kBlock), 0, st, a, queue, qseg, qcount);
+    if (commit)
+      hipLaunchKernelGGL((k_push_slow<double, true>), gs, dim3(kBlock), 0, st, P);
     else
-      hipLaunchKernelGGL((k_push_slow<double, false>), gs, dim3(kBlock), 0, st, a, queue, qseg, qcount);
+      hipLaunchKernelGGL((k_push_slow<double, false>), gs, dim3(kBlock), 0, st, P);
   } else {
-    if (a.commit)
-      hipLaunchKernelGGL((k_push_slow<float, true>), gs, dim3(kBlock), 0, st, a, queue, qseg, qcount);
+    if (commit)
+      hipLaunchKernelGGL((k_push_slow<float, true>), gs, dim3(kBlock), 0, st, P);
     else
-      hipLaunchKernelGGL((k_push_slow<float, false>), gs, dim3(kBlock), 0, st, a, queue, qseg, qcount);
+      hipLaunchKernelGGL((k_push_slow<float, false>), gs, dim3(kBlock), 0, st, P);
   }
   return hipGetLastError();
 }

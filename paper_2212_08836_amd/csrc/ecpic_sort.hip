@@ -229,7 +229,7 @@ hipError_t scan_exclusive(int32_t* data, int64_t n, int32_t* part, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t st, int64_t* n_alive_host) {
+hipError_t launch_sort_async(Ctx& c, Species& sp, int32_t* total_pinned, hipStream_t st) {
   const int64_t ncell = (int64_t)c.g.nr * c.g.nz;
   const int mixed = c.prec == ECPIC_MIXED;
   SpecDev& src = sp.d[sp.cur];
@@ -240,20 +240,27 @@ hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t st, int64_t* n_alive_hos
                        c.hist);
   hipError_t e = scan_exclusive(c.hist, ncell, c.scan_part, st);
   if (e != hipSuccess) return e;
-  int32_t total = 0;
-  e = hipMemcpyAsync(&total, c.hist + ncell, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  e = hipMemcpyAsync(total_pinned, c.hist + ncell, sizeof(int32_t), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return e;
   if (sp.n > 0)
     hipLaunchKernelGGL(k_scatter, dim3(nblk(sp.n)), dim3(kBlock), 0, st, c.m, src, dst, sp.n,
                        mixed, c.hist);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+void finish_sort(Species& sp, int32_t total) {
   sp.cur = 1 - sp.cur;
   sp.n = total;
   sp.d[sp.cur].n = total;
-  if (n_alive_host) *n_alive_host = total;
+}
+
+hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t st, int64_t* n_alive_host) {
+  hipError_t e = launch_sort_async(c, sp, c.sort_total_host, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  finish_sort(sp, c.sort_total_host[0]);
+  if (n_alive_host) *n_alive_host = sp.n;
   return hipSuccess;
 }
 

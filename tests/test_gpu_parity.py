@@ -276,3 +276,57 @@ def test_c2_full_size_sampled(og, torch_cuda):
         keep = np.isin(a["uid"], ov["uid"])
         gv = {kk: v[keep] for kk, v in a.items()}
         assert _cmp_species(gv, ov, f"c2 sample sp {k}") < TOL
+
+
+def test_step_tolerance_mode_c1(og, torch_cuda):
+    # the production mode: both sides stop on their own residual; the GPU
+    # enqueues each iteration ahead of the residual it waits for, so the
+    # iteration after convergence must leave no trace (state, counts, timing)
+    import paper_2212_08836_amd as P
+    _flush("step parity c1, tolerance mode")
+    w = E.workload("c1")
+    g, sp, ctx = _make_pair(w, og, P, E.make_particles(w))
+    st = og.State(g)
+    ctx.set_profiling(True, kinds=("push", "field"))
+    iters = 0
+    for n in range(6):
+        d_o = g.step(st, sp, tol=w.tol)
+        d_g = ctx.step(tol=w.tol)
+        assert d_g["iters"] == d_o["iters"] and d_g["converged"] == 1
+        iters += d_g["iters"]
+        for a, b in zip(d_g["residual"][:d_o["iters"]], d_o["residual"][:d_o["iters"]]):
+            assert abs(a - b) <= 1e-9 * b + 1e-13
+        ur, uz, h = ctx.get_fields()
+        errs = [_rel(ur, st.ur), _rel(uz, st.uz), _rel(h, st.h)]
+        for k in range(len(sp)):
+            errs.append(_cmp_species(ctx.read_particles(k), sp[k].view(), f"step {n} sp {k}"))
+        _flush(f"  step {n}: iters {d_o['iters']} worst rel {max(errs):.2e}")
+        assert max(errs) < TOL, (n, errs)
+    prof = ctx.profile()
+    # both species go in one launch per pass
+    assert prof["push"]["launches"] == iters
+    assert prof["field"]["launches"] == iters
+
+
+def test_step_not_converged_leaves_state(og, torch_cuda):
+    import paper_2212_08836_amd as P
+    w = E.workload("c1")
+    g, sp, ctx = _make_pair(w, og, P, E.make_particles(w))
+    ctx.step(tol=w.tol)
+    ur0, uz0, h0 = ctx.get_fields()
+    parts0 = [ctx.read_particles(k) for k in range(2)]
+    d = ctx.step(tol=1e-30, max_iter=3, check=False)
+    assert d["rc"] == P.ECPIC_ENOTCONV and d["iters"] == 3 and d["converged"] == 0
+    ur1, uz1, h1 = ctx.get_fields()
+    assert np.array_equal(ur0, ur1) and np.array_equal(uz0, uz1) and np.array_equal(h0, h1)
+    for k in range(2):
+        assert _cmp_species(ctx.read_particles(k), parts0[k], "after ENOTCONV") == 0.0
+    # the context is still usable: the same step in tolerance mode matches
+    # the oracle run over the same two steps
+    st = og.State(g)
+    g.step(st, sp, tol=w.tol)
+    d_o = g.step(st, sp, tol=w.tol)
+    d_g = ctx.step(tol=w.tol)
+    assert d_g["iters"] == d_o["iters"]
+    ur, uz, h = ctx.get_fields()
+    assert max(_rel(ur, st.ur), _rel(uz, st.uz), _rel(h, st.h)) < TOL
