@@ -366,7 +366,7 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
       bytes += (commit ? 2.0 * state_bytes(c) + 8.0 : state_bytes(c)) * (double)c.sp[s].n;
       parts += c.sp[s].n;
     }
-    P.nb0 = (P.a[0].s.n + kBlock - 1) / kBlock;
+    P.nb0 = fast_blocks(P.a[0].s.n);
     {
       Timed tm(c, commit ? ECPIC_K_COMMIT : ECPIC_K_PUSH, bytes, parts);
       HIPCHK(launch_push_fast(P, c.stream));

@@ -18,6 +18,8 @@ constexpr int kMaxHalve = 20;   // halvings of a sub-step whose solve fails
 constexpr int kMaxFixed = 50;   // fixed-point iterations per sub-step solve
 constexpr int kMaxIter = 64;    // Picard iterations per step
 constexpr int kBlock = 256;     // threads per block for particle kernels
+constexpr int kPerThread = 4;   // particles per thread of the fast push
+constexpr int kPerBlock = kBlock * kPerThread;
 // Contended counters are spread over copies on separate cache lines: block b
 // uses copy b % kSpread (queue segments, commit tallies).
 constexpr int kSpread = 64;
@@ -232,11 +234,15 @@ struct Ctx {
 // must be zero on entry.  tally points at kSpread copies.
 hipError_t launch_push_fast(const PassArgs& p, hipStream_t s);
 hipError_t launch_push_slow(const PassArgs& p, hipStream_t s);
-// entries per queue segment for n particles
+// entries per queue segment for n particles: fast-pass block b queues into
+// segment b % kSpread
 inline int64_t queue_segment(int64_t n) {
-  const int64_t nb = (n + kBlock - 1) / kBlock;
-  return ((nb + kSpread - 1) / kSpread) * kBlock;
+  const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
+  return ((nb + kSpread - 1) / kSpread) * kPerBlock;
 }
+// fast-pass blocks for n particles; fast-pass dynamic LDS for nz cells in z
+int64_t fast_blocks(int64_t n);
+size_t fast_lds_bytes(int nz);
 hipError_t launch_load(const MapP& m, const SpecDev& s, const double* r, const double* z,
                        const double* vr, const double* vt, const double* vz, const uint64_t* uid,
                        int64_t n, double R, int mixed, hipStream_t st);

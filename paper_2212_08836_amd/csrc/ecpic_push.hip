@@ -800,6 +800,24 @@ __device__ __forceinline__ bool load_particle<float>(const SpecDev& s, const Map
   return true;
 }
 
+// cell key i * nz + j of particle k, or -1 if it is dead
+template <typename T>
+__device__ __forceinline__ int particle_cell(const SpecDev& s, const MapP& m, int64_t k);
+template <>
+__device__ __forceinline__ int particle_cell<double>(const SpecDev& s, const MapP& m, int64_t k) {
+  const double xi = s.xi[k], eta = s.eta[k];
+  if (!(xi >= 0.0)) return -1;
+  int i = int(floor(xi)), j = int(floor(eta));
+  i = i < 0 ? 0 : (i > m.nr - 1 ? m.nr - 1 : i);
+  j = j < 0 ? 0 : (j > m.nz - 1 ? m.nz - 1 : j);
+  return i * m.nz + j;
+}
+template <>
+__device__ __forceinline__ int particle_cell<float>(const SpecDev& s, const MapP& m, int64_t k) {
+  const int c = s.cell[k];
+  return c < 0 ? -1 : c;
+}
+
 template <typename T>
 __device__ __forceinline__ void store_particle(const SpecDev& s, const MapP& m, int64_t k,
                                                const PState<T>& p);
@@ -911,96 +929,212 @@ __device__ void commit_one(const PushArgs& A, int64_t k, PState<T>& p, int statu
   store_particle<T>(s, m, k, p);
 }
 
+// ---------------------------------------------------------------------------
+// LDS-staged current tile of a fast-pass block
+// ---------------------------------------------------------------------------
+// One DPP step of a wavefront scan on a double: the value of the lane CTRL
+// selects (row_shr:n or row_bcast:15/31) in the rows ROW_MASK enables, 0
+// elsewhere.  Needs all 64 lanes active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_take(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xF, true);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xF, true);
+  return __hiloint2double(h2, l2);
+}
+
+// inclusive wavefront scan; lane 63 ends with the sum of all 64 lanes
+__device__ __forceinline__ double wave_scan_add(double v) {
+  v += dpp_take<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_take<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_take<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_take<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_take<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_take<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// A block's currents are gathered in LDS over the cells [c_lo, c_lo + W):
+// r-edges i*(nz+1)+j of those cells and their j+1 neighbours at TR[e - er0]
+// (er0 = c_lo + c_lo / nz), z-edges i*nz+j and the (i+1) neighbours at
+// TZ[e - c_lo].  Deposits of cells outside the window go to global atomics.
+struct Tile {
+  double* TR;
+  double* TZ;
+  int c_lo, W, er0, nr_e, nz_e;
+};
+
+__host__ __device__ inline int tile_cells(int nz) { return 4 * nz + 64; }
+__host__ __device__ inline int tile_r_len(int nz) {
+  const int W = tile_cells(nz);
+  return W + W / nz + 2;
+}
+__host__ __device__ inline int tile_z_len(int nz) { return tile_cells(nz) + nz; }
+
+// Deposit of one particle per lane.  The cell of the first in-tile lane is
+// the wavefront's majority cell in sorted order: its lanes are summed with
+// DPP and added to the tile once; other in-tile lanes add with LDS atomics,
+// out-of-tile lanes with global atomics.  Called by all 64 lanes.
+__device__ __forceinline__ void tile_deposit(const Tile& t, double* Ir, double* Iz, int nz, int key,
+                                             int i, int j, const Dep& d) {
+  const bool in = key >= t.c_lo && key < t.c_lo + t.W;
+  if (key >= 0 && !in) atomic_dep(Ir, Iz, nz, i, j, d);
+  const uint64_t m_in = __ballot(in);
+  if (m_in == 0) return;
+  const int lead = __ffsll((unsigned long long)m_in) - 1;
+  const int k0 = __shfl(key, lead, 64);
+  const bool mem = in && key == k0;
+  const double r0 = wave_scan_add(mem ? d.r0 : 0.0);
+  const double r1 = wave_scan_add(mem ? d.r1 : 0.0);
+  const double z0 = wave_scan_add(mem ? d.z0 : 0.0);
+  const double z1 = wave_scan_add(mem ? d.z1 : 0.0);
+  const int lane = threadIdx.x & 63;
+  if (lane == 63) {
+    const int i0 = k0 / nz, j0 = k0 - i0 * nz;
+    const int er = i0 * (nz + 1) + j0 - t.er0;
+    const int ez = k0 - t.c_lo;
+    atomicAdd(&t.TR[er], r0);
+    atomicAdd(&t.TR[er + 1], r1);
+    atomicAdd(&t.TZ[ez], z0);
+    atomicAdd(&t.TZ[ez + nz], z1);
+  }
+  if (in && !mem) {
+    const int er = i * (nz + 1) + j - t.er0;
+    const int ez = key - t.c_lo;
+    atomicAdd(&t.TR[er], d.r0);
+    atomicAdd(&t.TR[er + 1], d.r1);
+    atomicAdd(&t.TZ[ez], d.z0);
+    atomicAdd(&t.TZ[ez + nz], d.z1);
+  }
+}
+
 // Fast pass: every particle solves the mid-point system over the whole step
 // in its cell.  Those that stay in the closed cell are done (this is exactly
-// the first sub-step of the full algorithm); their currents are combined per
-// cell across the wavefront.  The others are queued for k_push_slow.
+// the first sub-step of the full algorithm); their currents are gathered in
+// the block's LDS tile and flushed once per block.  The others are queued
+// for k_push_slow.  A block takes kPerThread particles per thread,
+// consecutive in memory (sorted by cell after a sort), strided by kBlock.
 // Blocks [0, nb0) serve species slot 0 of the pass, the rest slot 1.
+// Dynamic LDS: tile_r_len(nz) + tile_z_len(nz) doubles.
 template <typename T, bool COMMIT>
 __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   if (P.a[0].stop && *P.a[0].stop) return;
+  extern __shared__ double tile_mem[];
+  __shared__ int32_t slow_list[kPerBlock];
+  __shared__ int slow_n, gbase;
   const bool second = (int64_t)blockIdx.x >= P.nb0;
   const PushArgs& A = second ? P.a[1] : P.a[0];
   int32_t* queue = second ? P.queue[1] : P.queue[0];
   int32_t* qcount = second ? P.qcount[1] : P.qcount[0];
   const int64_t qseg = second ? P.qseg[1] : P.qseg[0];
   const int64_t bx = second ? (int64_t)blockIdx.x - P.nb0 : (int64_t)blockIdx.x;
-  const int64_t k = bx * kBlock + threadIdx.x;
+  const int64_t k_first = bx * kPerBlock;
   const MapP& m = A.m;
   const SpecDev& s = A.s;
   const T qm = T(s.q / s.m);
   const double qw_dt = s.q * s.w / m.dt;
-  PState<T> p;
-  bool alive = false;
-  if (k < s.n) alive = load_particle<T>(s, m, k, p);
-  bool slow = false;
-  int key = -1;
-  Dep dp{0.0, 0.0, 0.0, 0.0};
+  const int nz = m.nz;
+  // the tile window: one radial row of drift either side of the block's
+  // first particle's cell
+  Tile tl;
+  tl.W = tile_cells(nz);
+  tl.TR = tile_mem;
+  tl.TZ = tile_mem + tile_r_len(nz);
+  {
+    int c_first = -1;
+    if (k_first < s.n) c_first = particle_cell<T>(s, m, k_first);
+    if (c_first < 0) c_first = 0;
+    tl.c_lo = max(c_first - nz - 2, 0);
+    tl.er0 = tl.c_lo + tl.c_lo / nz;
+  }
+  const int ntile = tile_r_len(nz) + tile_z_len(nz);
+  for (int e = threadIdx.x; e < ntile; e += kBlock) tile_mem[e] = 0.0;
+  if (threadIdx.x == 0) slow_n = 0;
+  __syncthreads();
   Tl t;
   tl_zero(t);
-  if (alive) {
-    // on a face, the cell the motion goes to
-    if (p.a == T(1) && p.vr >= T(0) && p.i < m.nr - 1) {
-      p.i += 1;
-      p.a = T(0);
-    } else if (p.a == T(0) && p.vr < T(0) && p.i > 0) {
-      p.i -= 1;
-      p.a = T(1);
-    }
-    if (p.b == T(1) && p.vz >= T(0) && p.j < m.nz - 1) {
-      p.j += 1;
-      p.b = T(0);
-    } else if (p.b == T(0) && p.vz < T(0) && p.j > 0) {
-      p.j -= 1;
-      p.b = T(1);
-    }
-    T F[4];
-    load_field(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), p.i, p.j, F);
-    Mid<T> M;
-    slow = true;
-    if (p.i >= m.i_lin && solve_fast(m, F, p, T(m.dt), qm, M)) {
-      const T ea = T(2) * M.a - p.a, eb = T(2) * M.b - p.b;
-      if (ea >= T(0) && ea <= T(1) && eb >= T(0) && eb <= T(1)) {
-        slow = false;
-        dp = make_dep(double(p.a), double(p.b), double(ea), double(eb), qw_dt);
-        key = p.i * m.nz + p.j;
-        if (COMMIT) {
-          t.work = m.dt * (dp.r0 * double(F[0]) + dp.r1 * double(F[1]) + dp.z0 * double(F[2]) +
-                           dp.z1 * double(F[3]));
-          t.nsub = 1;
+  const int lane = threadIdx.x & 63;
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t k = k_first + (int64_t)r * kBlock + threadIdx.x;
+    PState<T> p;
+    bool alive = false;
+    if (k < s.n) alive = load_particle<T>(s, m, k, p);
+    bool slow = false;
+    int key = -1;
+    Dep dp{0.0, 0.0, 0.0, 0.0};
+    if (alive) {
+      // on a face, the cell the motion goes to
+      if (p.a == T(1) && p.vr >= T(0) && p.i < m.nr - 1) {
+        p.i += 1;
+        p.a = T(0);
+      } else if (p.a == T(0) && p.vr < T(0) && p.i > 0) {
+        p.i -= 1;
+        p.a = T(1);
+      }
+      if (p.b == T(1) && p.vz >= T(0) && p.j < m.nz - 1) {
+        p.j += 1;
+        p.b = T(0);
+      } else if (p.b == T(0) && p.vz < T(0) && p.j > 0) {
+        p.j -= 1;
+        p.b = T(1);
+      }
+      T F[4];
+      load_field(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), p.i, p.j, F);
+      Mid<T> M;
+      slow = true;
+      if (p.i >= m.i_lin && solve_fast(m, F, p, T(m.dt), qm, M)) {
+        const T ea = T(2) * M.a - p.a, eb = T(2) * M.b - p.b;
+        if (ea >= T(0) && ea <= T(1) && eb >= T(0) && eb <= T(1)) {
+          slow = false;
+          dp = make_dep(double(p.a), double(p.b), double(ea), double(eb), qw_dt);
+          key = p.i * nz + p.j;
+          if (COMMIT) {
+            t.work += m.dt * (dp.r0 * double(F[0]) + dp.r1 * double(F[1]) +
+                              dp.z0 * double(F[2]) + dp.z1 * double(F[3]));
+            t.nsub += 1;
+          }
+          p.a = ea;
+          p.b = eb;
+          p.vr = T(2) * M.vr - p.vr;
+          p.vt = T(2) * M.vt - p.vt;
+          p.vz = T(2) * M.vz - p.vz;
         }
-        p.a = ea;
-        p.b = eb;
-        p.vr = T(2) * M.vr - p.vr;
-        p.vt = T(2) * M.vt - p.vt;
-        p.vz = T(2) * M.vz - p.vz;
       }
     }
-  }
-  wave_deposit(A.Ir, A.Iz, m.nz, key, p.i, p.j, dp);
-  // queue the rest: ranks within the block from wavefront ballots, one
-  // atomic per block on the counter of this block's segment
-  {
-    __shared__ int wcnt[kBlock / 64];
-    __shared__ int bbase;
+    tile_deposit(tl, A.Ir, A.Iz, nz, key, p.i, p.j, dp);
+    // the block's slow list: one LDS atomic per wavefront
     const uint64_t mask = __ballot(slow);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) wcnt[w] = __popcll(mask);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int tot = 0;
-      for (int q = 0; q < kBlock / 64; ++q) tot += wcnt[q];
-      bbase = tot ? atomicAdd(qcount + (bx % kSpread) * kLineInts, tot) : 0;
+    if (mask) {
+      int wbase = 0;
+      if (lane == 0) wbase = atomicAdd(&slow_n, __popcll(mask));
+      wbase = __shfl(wbase, 0, 64);
+      if (slow) slow_list[wbase + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)k;
     }
-    __syncthreads();
-    if (slow) {
-      int r = bbase + __popcll(mask & ((1ull << lane) - 1ull));
-      for (int q = 0; q < w; ++q) r += wcnt[q];
-      queue[(bx % kSpread) * qseg + r] = (int32_t)k;
+    if (COMMIT && alive && !slow) commit_one<T>(A, k, p, kAlive, 0, t);
+  }
+  __syncthreads();
+  // flush the tile: one global atomic per touched edge
+  {
+    const int64_t ner = (int64_t)m.nr * (nz + 1), nez = (int64_t)(m.nr + 1) * nz;
+    const int lr = tile_r_len(nz), lz = tile_z_len(nz);
+    for (int e = threadIdx.x; e < lr; e += kBlock) {
+      const double v = tl.TR[e];
+      if (v != 0.0 && tl.er0 + e < ner) unsafeAtomicAdd(A.Ir + tl.er0 + e, v);
     }
+    for (int e = threadIdx.x; e < lz; e += kBlock) {
+      const double v = tl.TZ[e];
+      if (v != 0.0 && tl.c_lo + e < nez) unsafeAtomicAdd(A.Iz + tl.c_lo + e, v);
+    }
+  }
+  // queue the slow ones: one global atomic per block
+  const int ns = slow_n;
+  if (ns) {
+    const int64_t seg = bx % kSpread;
+    if (threadIdx.x == 0) gbase = atomicAdd(qcount + seg * kLineInts, ns);
+    __syncthreads();
+    for (int q = threadIdx.x; q < ns; q += kBlock) queue[seg * qseg + gbase + q] = slow_list[q];
   }
   if (!COMMIT) return;
-  if (alive && !slow) commit_one<T>(A, k, p, kAlive, 0, t);
   tl_flush(t, A.tally + (blockIdx.x % kSpread), s.sid);
 }
 
@@ -1174,21 +1308,29 @@ double nu_max_host(const ecpic_mcc_desc& c, int role, double mp) {
   return 0.0;
 }
 
+int64_t fast_blocks(int64_t n) { return (n + kPerBlock - 1) / kPerBlock; }
+
+size_t fast_lds_bytes(int nz) {
+  return sizeof(double) * (size_t)(tile_r_len(nz) + tile_z_len(nz));
+}
+
 hipError_t launch_push_fast(const PassArgs& P, hipStream_t st) {
-  const int64_t nb = P.nb0 + (P.nsp > 1 ? (P.a[1].s.n + kBlock - 1) / kBlock : 0);
+  const int64_t nb = P.nb0 + (P.nsp > 1 ? fast_blocks(P.a[1].s.n) : 0);
   if (nb <= 0) return hipSuccess;
+  const size_t lds = fast_lds_bytes(P.a[0].m.nz);
+  if (lds > 56 * 1024) return hipErrorInvalidValue;
   const bool mixed = (P.a[0].s.cell != nullptr);
   const bool commit = P.a[0].commit != 0;
   if (!mixed) {
     if (commit)
-      hipLaunchKernelGGL((k_push_fast<double, true>), dim3(nb), dim3(kBlock), 0, st, P);
+      hipLaunchKernelGGL((k_push_fast<double, true>), dim3(nb), dim3(kBlock), lds, st, P);
     else
-      hipLaunchKernelGGL((k_push_fast<double, false>), dim3(nb), dim3(kBlock), 0, st, P);
+      hipLaunchKernelGGL((k_push_fast<double, false>), dim3(nb), dim3(kBlock), lds, st, P);
   } else {
     if (commit)
-      hipLaunchKernelGGL((k_push_fast<float, true>), dim3(nb), dim3(kBlock), 0, st, P);
+      hipLaunchKernelGGL((k_push_fast<float, true>), dim3(nb), dim3(kBlock), lds, st, P);
     else
-      hipLaunchKernelGGL((k_push_fast<float, false>), dim3(nb), dim3(kBlock), 0, st, P);
+      hipLaunchKernelGGL((k_push_fast<float, false>), dim3(nb), dim3(kBlock), lds, st, P);
   }
   return hipGetLastError();
 }
