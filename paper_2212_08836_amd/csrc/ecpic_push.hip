@@ -403,11 +403,13 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
     load_field(m, ur, uz, p.i, p.j, F);
     T dtry = tau;
     Mid<T> M;
-    bool ok = false;
-    for (int h = 0; h <= kMaxHalve; ++h) {
+    // linear-map cells: the closed-form solve (the same mid point as the
+    // fixed point, to its tolerance); otherwise the fixed point, halving
+    // the sub-step while it fails
+    bool ok = p.i >= m.i_lin && solve_fast(m, F, p, dtry, qm, M);
+    for (int h = 0; !ok && h <= kMaxHalve; ++h) {
       ok = solve_free(m, F, p, dtry, qm, M);
-      if (ok) break;
-      dtry *= T(0.5);
+      if (!ok) dtry *= T(0.5);
     }
     if (!ok) {
       out.status = kError;
