@@ -44,6 +44,7 @@ struct PState {
 template <typename T>
 struct Mid {
   T a, b, vr, vt, vz;  // mid-point offsets (cell-local) and mid velocities
+  T kr, kz;            // solve_fast only: vr - v_r, vz - v_z (the kicks)
 };
 
 template <typename T>
@@ -168,44 +169,54 @@ __device__ bool solve_free(const MapP& m, const T F[4], const PState<T>& p, T dt
 template <typename T>
 __device__ __forceinline__ bool solve_fast(const MapP& m, const T F[4], const PState<T>& p, T dtau,
                                            T qm, Mid<T>& M) {
+  // Written for the kicks kr = vb_r - v_r, kz = vb_z - v_z, so that in FP32
+  // the rounding acts on the small field-driven part only:
+  //   kz = beta Ez + Kz (v_r + kr),
+  //   kr (1 - Kr Kz) = alpha Er + Kr (v_z + beta Ez + Kz v_r) + (dt/2) cf,
+  // with Er, Ez the weighted fields at the start offsets.
   const T hd = T(0.5) * dtau;
   const T delta = hd * T(m.inv_s);  // d a_bar / d vb_r
   const T gamma = hd * T(m.inv_dz); // d b_bar / d vb_z
   const T alpha = qm * delta;       // d vb_r / d (weighted ur)
   const T beta = qm * gamma;        // d vb_z / d (weighted uz)
   const T dFr = F[1] - F[0], dFz = F[3] - F[2];
-  const T Cz = p.vz + beta * (F[2] + p.a * dFz);
+  const T Ez = F[2] + p.a * dFz;
+  const T Er = F[0] + p.b * dFr;
   const T Kz = beta * delta * dFz;
-  const T Cr = p.vr + alpha * (F[0] + p.b * dFr);
   const T Kr = alpha * gamma * dFr;
   const T den = T(1) - Kr * Kz;
   if (!(den > T(0))) return false;
   const T inv_den = T(1) / den;
-  const T c0 = (Cr + Kr * Cz) * inv_den;
+  const T bz = beta * Ez;
+  const T k0 = (alpha * Er + Kr * (p.vz + bz + Kz * p.vr)) * inv_den;
   const T cc = hd * inv_den;
   const T r0 = T(m.s * (double(p.i) + m.xi_a)) + T(m.s) * p.a;
   const T vt2 = p.vt * p.vt;
-  T vr = c0 + cc * vt2 / r0;  // centrifugal term at the start position
+  T kr = k0 + cc * vt2 / r0;  // centrifugal term at the start position
   T rb = r0, re = r0;
   for (int it = 0; it < 12; ++it) {
+    const T vr = p.vr + kr;
     rb = r0 + hd * vr;
     re = r0 + dtau * vr;
     if (!(rb > T(0) && re > T(0))) return false;
     const T ire = T(1) / re;
-    const T nvr = c0 + cc * vt2 * rb * ire * ire;
-    const T d = fabs(nvr - vr);
-    vr = nvr;
-    const T vz = Cz + Kz * vr;
-    const T scale = fabs(vr) + fabs(p.vt * rb * ire) + fabs(vz);
+    const T nkr = k0 + cc * vt2 * rb * ire * ire;
+    const T d = fabs(nkr - kr);
+    kr = nkr;
+    const T kz = bz + Kz * (p.vr + kr);
+    const T scale = fabs(p.vr + kr) + fabs(p.vt * rb * ire) + fabs(p.vz + kz);
     if (d <= Tol<T>::v() * scale) {
-      rb = r0 + hd * vr;
-      re = r0 + dtau * vr;
+      const T vrb = p.vr + kr;
+      rb = r0 + hd * vrb;
+      re = r0 + dtau * vrb;
       if (!(re > T(0))) return false;
-      M.vr = vr;
-      M.vz = vz;
+      M.kr = kr;
+      M.kz = kz;
+      M.vr = vrb;
+      M.vz = p.vz + kz;
       M.vt = p.vt * rb / re;
-      M.a = p.a + delta * vr;
-      M.b = p.b + gamma * vz;
+      M.a = p.a + delta * vrb;
+      M.b = p.b + gamma * M.vz;
       return true;
     }
   }
@@ -1088,7 +1099,21 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
         const T ea = T(2) * M.a - p.a, eb = T(2) * M.b - p.b;
         if (ea >= T(0) && ea <= T(1) && eb >= T(0) && eb <= T(1)) {
           slow = false;
-          dp = make_dep(double(p.a), double(p.b), double(ea), double(eb), qw_dt);
+          if constexpr (sizeof(T) == 4) {
+            // mixed path: the current of the FP32 displacement, taken as its
+            // field-free part plus its kick part (summed in FP64) before the
+            // new offset is rounded for storage; a current that moved in
+            // steps of the stored offset's ulp, or of the mid velocity's,
+            // would stall Picard above the tolerance
+            const T delta = T(0.5) * T(m.dt) * T(m.inv_s);
+            const T gamma = T(0.5) * T(m.dt) * T(m.inv_dz);
+            const double da = double(delta * p.vr) + double(delta * M.kr);
+            const double db = double(gamma * p.vz) + double(gamma * M.kz);
+            dp = make_dep(double(p.a), double(p.b), double(p.a) + 2.0 * da,
+                          double(p.b) + 2.0 * db, qw_dt);
+          } else {
+            dp = make_dep(double(p.a), double(p.b), double(ea), double(eb), qw_dt);
+          }
           key = p.i * nz + p.j;
           if (COMMIT) {
             t.work += m.dt * (dp.r0 * double(F[0]) + dp.r1 * double(F[1]) +
@@ -1097,9 +1122,14 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
           }
           p.a = ea;
           p.b = eb;
-          p.vr = T(2) * M.vr - p.vr;
+          if constexpr (sizeof(T) == 4) {
+            p.vr = p.vr + T(2) * M.kr;
+            p.vz = p.vz + T(2) * M.kz;
+          } else {
+            p.vr = T(2) * M.vr - p.vr;
+            p.vz = T(2) * M.vz - p.vz;
+          }
           p.vt = T(2) * M.vt - p.vt;
-          p.vz = T(2) * M.vz - p.vz;
         }
       }
     }
@@ -1167,7 +1197,30 @@ __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
     PState<T> p;
     if (!load_particle<T>(s, m, k, p)) continue;
     PushOut o;
-    push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, p, qm, qw_dt, COMMIT, o);
+    if constexpr (sizeof(T) == 4) {
+      // mixed path: the few face crossers are pushed in FP64 arithmetic
+      // (in the FP64 half-step field) from their FP32 state and stored back
+      // rounded, so that their currents vary smoothly with the field
+      PState<double> pd;
+      pd.i = p.i;
+      pd.j = p.j;
+      pd.a = p.a;
+      pd.b = p.b;
+      pd.vr = p.vr;
+      pd.vt = p.vt;
+      pd.vz = p.vz;
+      push_particle<double>(m, A.ur, A.uz, A.Ir, A.Iz, pd, s.q / s.m, qw_dt, COMMIT, o);
+      p.i = pd.i;
+      p.j = pd.j;
+      p.a = T(pd.a);
+      p.b = T(pd.b);
+      p.vr = T(pd.vr);
+      p.vt = T(pd.vt);
+      p.vz = T(pd.vz);
+    } else {
+      push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, p, qm, qw_dt,
+                       COMMIT, o);
+    }
     if (o.have_first) atomic_dep(A.Ir, A.Iz, m.nz, o.fi, o.fj, o.first);
     if (COMMIT) {
       t.work += o.work;
