@@ -203,31 +203,43 @@ ecpic_status ecpic_node_charge(ecpic_ctx* ctx, double* q, double* bot, double* t
 /* Energies and counts of the current state (synchronises). */
 ecpic_status ecpic_diagnostics(ecpic_ctx* ctx, ecpic_step_stats* stats);
 
-/* Learned initial guess: a 4-layer 3x3 convolutional network (6 -> 32 -> 32
- * -> 32 -> 3 channels) on the packed (nr+1)x(nz+1) canvas of (ur, uz, h) at
- * t^n and their change since t^{n-1}, predicting the correction to the
- * extrapolated u^{n+1} guess.  BF16 weights and activations, FP32
- * accumulation.  Weight layout (host or device per the call):
- *   per layer l: W_l[cout][cin][3][3] then b_l[cout], layers concatenated;
- *   norm[9] = input scales (6) and output scales (3).
- * ecpic_nn_param_count returns the number of weights+biases. */
+/* Learned initial guess (not part of the paper: an initial guess for the
+ * Picard iteration of Sec. 2.1, which still converges to the same tolerance).
+ * A 4-layer 3x3 convolutional network, 6 -> 32 -> 32 -> 32 -> 2 channels,
+ * ReLU between layers, zero padding, on the (nr+1) x (nz+1) canvas where
+ * u_r[i][j], u_z[i][j] and h[i][j] sit at index (i, j) (zero elsewhere).
+ * Input channels: u_r, u_z, h at t^n and u_r, u_z, h at t^n minus t^{n-1},
+ * each divided by its scale.  Output channels: the corrections of the
+ * extrapolated guess 2u^n - u^{n-1} of u_r and u_z at t^{n+1}, in units of
+ * their scales, used on the interior r-edges (i < nr, 0 < j < nz) and the
+ * z-edges off the PEC wall (i < nr, j < nz).
+ * Weights: FP32 in the canonical layout, per layer W_l[cout][cin][3][3]
+ * then b_l[cout], layers concatenated (ecpic_nn_param_count floats).  The
+ * kernels round weights, inputs and activations to BF16 (nearest even) and
+ * accumulate in FP32 on the matrix cores; biases stay FP32.
+ * ecpic_nn_param_count returns the number of weights plus biases. */
 int64_t ecpic_nn_param_count(void);
-/* Install BF16 weights (device, param_count uint16 bf16 bit patterns) and the
- * normalisation (host, 9 floats) used by ecpic_step when use_nn=1. */
-ecpic_status ecpic_nn_set_weights(ecpic_ctx* ctx, const uint16_t* w_bf16, const float* norm);
-/* Forward pass on a batch of canvases x (device, [batch][6][nr+1][nz+1]
- * bf16 bits) into y (device, [batch][3][nr+1][nz+1] FP32). */
-ecpic_status ecpic_nn_forward(ecpic_ctx* ctx, const uint16_t* w_bf16, const uint16_t* x,
-                              float* y, int32_t batch);
-/* Loss and gradient: mean squared error over the canvas against target t
- * (device FP32, like y), gradient of all weights and biases into dw (device
- * FP32, param_count), loss into *loss (synchronises). */
-ecpic_status ecpic_nn_grad(ecpic_ctx* ctx, const uint16_t* w_bf16, const uint16_t* x,
-                           const float* t, int32_t batch, float* dw, float* loss);
-/* One Adam step (beta 0.9/0.999, eps 1e-8) on FP32 master weights w (device),
- * moments m, v (device), from gradient dw; refreshes the BF16 copy. */
+/* Install the network for ecpic_step with use_nn = 1: weights w (device,
+ * FP32, copied) and scales norm (host, 8 floats: 6 input, 2 output, > 0).
+ * w = NULL uninstalls it.  EINVAL on bad scales. */
+ecpic_status ecpic_nn_set_weights(ecpic_ctx* ctx, const float* w, const float* norm);
+/* Forward pass on a batch of canvases: x (device, [batch][6][nr+1][nz+1]
+ * BF16 bit patterns, already scaled) into y (device, [batch][2][nr+1][nz+1]
+ * FP32, in output-scale units).  Weights w as above (device, FP32). */
+ecpic_status ecpic_nn_forward(ecpic_ctx* ctx, const float* w, const uint16_t* x, float* y,
+                              int32_t batch);
+/* Loss and gradient for training: mean over the batch and the valid output
+ * positions of (y - t)^2, with t (device FP32, shaped like y); the gradient
+ * of the loss with respect to every weight and bias goes to dw (device,
+ * FP32, canonical layout), the loss to *loss (host, may be NULL).
+ * Synchronises. */
+ecpic_status ecpic_nn_grad(ecpic_ctx* ctx, const float* w, const uint16_t* x, const float* t,
+                           int32_t batch, float* dw, float* loss);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, step count t >= 1, learning
+ * rate lr > 0) in place on FP32 weights w with moments m, v (all device,
+ * param_count floats) from the gradient dw. */
 ecpic_status ecpic_nn_adam(ecpic_ctx* ctx, float* w, float* m, float* v, const float* dw,
-                           uint16_t* w_bf16, float lr, int32_t t);
+                           float lr, int32_t t);
 
 /* Kernel timing with HIP events recorded on the context stream around every
  * launch of the hot kernels (one record per launch), for measurement. */

@@ -121,7 +121,7 @@ def lib() -> C.CDLL:
             "ecpic_nn_set_weights": ([_vp, _vp, C.POINTER(C.c_float)], st),
             "ecpic_nn_forward": ([_vp, _vp, _vp, _vp, C.c_int32], st),
             "ecpic_nn_grad": ([_vp, _vp, _vp, _vp, C.c_int32, _vp, C.POINTER(C.c_float)], st),
-            "ecpic_nn_adam": ([_vp, _vp, _vp, _vp, _vp, _vp, C.c_float, C.c_int32], st),
+            "ecpic_nn_adam": ([_vp, _vp, _vp, _vp, _vp, C.c_float, C.c_int32], st),
             "ecpic_set_profiling": ([_vp, C.c_int32], st),
             "ecpic_get_profile": ([_vp, C.POINTER(Profile)], st),
             "ecpic_last_error": ([_vp], C.c_char_p),
@@ -343,6 +343,57 @@ class Context:
         p = Profile()
         self._check(self.L.ecpic_get_profile(self.h, C.byref(p)), self.h)
         return p.as_dict()
+
+    # ---- learned initial guess (argument marshalling only) ----
+    def nn_param_count(self) -> int:
+        return int(self.L.ecpic_nn_param_count())
+
+    def _f32(self, a):
+        t = self.torch
+        a = a if isinstance(a, t.Tensor) else t.as_tensor(np.asarray(a, dtype=np.float32))
+        return a.to(device=self.device, dtype=t.float32).contiguous()
+
+    def _bf16(self, a):
+        t = self.torch
+        a = a if isinstance(a, t.Tensor) else t.as_tensor(np.asarray(a, dtype=np.float32))
+        if a.dtype != t.bfloat16:
+            a = a.to(t.float32).to(t.bfloat16)
+        return a.to(self.device).contiguous()
+
+    def nn_set_weights(self, w, norm):
+        """Install FP32 weights (canonical layout) and the 8 scales for
+        step(use_nn=True); w=None uninstalls."""
+        if w is None:
+            self._check(self.L.ecpic_nn_set_weights(self.h, None, None), self.h)
+            return
+        wt = self._f32(w)
+        nm = (C.c_float * 8)(*[float(v) for v in norm])
+        self._check(self.L.ecpic_nn_set_weights(self.h, _ptr(wt), nm), self.h)
+        self.torch.cuda.synchronize()
+
+    def nn_forward(self, w, x):
+        """x: [batch][6][nr+1][nz+1] (scaled); returns y [batch][2][nr+1][nz+1] FP32."""
+        t = self.torch
+        wt, xb = self._f32(w), self._bf16(x)
+        b = xb.shape[0]
+        y = t.empty((b, 2, self.nr + 1, self.nz + 1), dtype=t.float32, device=self.device)
+        self._check(self.L.ecpic_nn_forward(self.h, _ptr(wt), _ptr(xb), _ptr(y), b), self.h)
+        return y
+
+    def nn_grad(self, w, x, target):
+        """Loss and FP32 gradient of the mean squared error over the valid outputs."""
+        t = self.torch
+        wt, xb, tt = self._f32(w), self._bf16(x), self._f32(target)
+        dw = t.empty(self.nn_param_count(), dtype=t.float32, device=self.device)
+        loss = C.c_float()
+        self._check(self.L.ecpic_nn_grad(self.h, _ptr(wt), _ptr(xb), _ptr(tt), xb.shape[0],
+                                         _ptr(dw), C.byref(loss)), self.h)
+        return dw, float(loss.value)
+
+    def nn_adam(self, w, m, v, dw, lr, step):
+        """In-place Adam step on device FP32 tensors w, m, v."""
+        self._check(self.L.ecpic_nn_adam(self.h, _ptr(w), _ptr(m), _ptr(v), _ptr(dw),
+                                         float(lr), int(step)), self.h)
 
     def diagnostics(self) -> dict:
         s = StepStats()

@@ -17,10 +17,6 @@
 
 using namespace ecpic;
 
-struct ecpic_ctx {
-  Ctx c;
-};
-
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -32,15 +28,6 @@ constexpr int kOffEx = kOffFE + 2 * kRedBlocks;   // kRedBlocks exchange
 constexpr int kOffKE = kOffEx + kRedBlocks;       // kMaxSpecies kinetic energies
 constexpr int kOffSc = kOffKE + 8;                // a few scalars
 constexpr int kPartLen = kOffSc + 16;
-
-#define HIPCHK(expr)                                                              \
-  do {                                                                            \
-    hipError_t e_ = (expr);                                                       \
-    if (e_ != hipSuccess) {                                                       \
-      c.err = std::string(#expr) + ": " + hipGetErrorString(e_);                  \
-      return ECPIC_EHIP;                                                          \
-    }                                                                             \
-  } while (0)
 
 ecpic_status fail(Ctx& c, ecpic_status s, const std::string& msg) {
   c.err = msg;
@@ -467,6 +454,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   bool ok = true;
   auto A = [&](double** p, int64_t n) { ok = ok && dalloc(p, (size_t)n) == hipSuccess; };
   A(&c.ur, nur); A(&c.uz, nuz); A(&c.h, nh); A(&c.ur_prev, nur); A(&c.uz_prev, nuz);
+  A(&c.h_prev, nh);
   A(&c.ur_it, nur); A(&c.uz_it, nuz); A(&c.h_it, nh);
   A(&c.ur_nx, nur); A(&c.uz_nx, nuz); A(&c.h_nx, nh);
   A(&c.ur_half, nur); A(&c.uz_half, nuz); A(&c.Ir, nur); A(&c.Iz, nuz);
@@ -507,9 +495,9 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
     return ECPIC_EHIP;
   }
   double* zs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.ur_it, c.uz_it, c.h_it,
-                  c.ur_half, c.uz_half, c.Ir, c.Iz, c.ur_half2, c.uz_half2};
-  int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz};
-  for (int k = 0; k < 14; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
+                  c.ur_half, c.uz_half, c.Ir, c.Iz, c.ur_half2, c.uz_half2, c.h_prev};
+  int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz, nh};
+  for (int k = 0; k < 15; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
   (void)launch_zero_i(c.stop, 1, c.stream);
   (void)launch_zero(c.wall_bot, g->nr + 1, c.stream);
   (void)launch_zero(c.wall_top, g->nr + 1, c.stream);
@@ -530,7 +518,8 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
     free_species_buf(s.d[0]);
     free_species_buf(s.d[1]);
   }
-  double* fs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.ur_it, c.uz_it, c.h_it, c.ur_nx,
+  double* fs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.h_prev, c.ur_it, c.uz_it, c.h_it,
+                  c.ur_nx,
                   c.uz_nx, c.h_nx, c.ur_half, c.uz_half, c.ur_half2, c.uz_half2, c.Ir, c.Iz,
                   c.wall_bot, c.wall_top,
                   c.wall_side, c.sol.rh, c.sol.wr, c.sol.wz, c.sol.area, c.sol.Q, c.sol.Qt,
@@ -549,6 +538,7 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
   (void)hipFree(c.qcount);
   (void)hipFree(c.nn_w);
   (void)hipFree(c.nn_ws);
+  (void)hipFree(c.nn_gws);
   collect(c);
   for (auto& p : c.pending) {
     (void)hipEventDestroy(p.a);
@@ -672,6 +662,7 @@ ecpic_status ecpic_set_fields(ecpic_ctx* x, const double* ur, const double* uz, 
   HIPCHK(launch_copy(c.h, h, nh, c.stream));
   HIPCHK(launch_copy(c.ur_prev, ur_prev ? ur_prev : ur, nur, c.stream));
   HIPCHK(launch_copy(c.uz_prev, uz_prev ? uz_prev : uz, nuz, c.stream));
+  HIPCHK(launch_copy(c.h_prev, h, nh, c.stream));
   c.t = t;
   c.step = step;
   return ECPIC_OK;
@@ -1070,7 +1061,13 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
   std::swap(c.uz_prev, c.uz);
   std::swap(c.ur, c.ur_it);
   std::swap(c.uz, c.uz_it);
-  std::swap(c.h, c.h_it);
+  {
+    // h^{n-1} <- h^n, h^n <- h^{n+1}; the old h^{n-1} buffer becomes scratch
+    double* old_prev = c.h_prev;
+    c.h_prev = c.h;
+    c.h = c.h_it;
+    c.h_it = old_prev;
+  }
   c.t += c.g.dt;
   c.step += 1;
   if (o->sort_every > 0 && c.step % o->sort_every == 0) {

@@ -170,7 +170,7 @@ struct Ctx {
   std::string err;
   std::vector<Species> sp;
   // fields (FP64) at t^n, t^{n-1}, the current iterate, the previous iterate
-  double *ur, *uz, *h, *ur_prev, *uz_prev;
+  double *ur, *uz, *h, *ur_prev, *uz_prev, *h_prev;
   double *ur_it, *uz_it, *h_it;    // u^{n+1,(k)}, h^{n+1,(k)}
   double *ur_nx, *uz_nx, *h_nx;    // u^{n+1,(k+1)} being produced
   double *ur_half, *uz_half;       // half-step field of the current push
@@ -205,11 +205,13 @@ struct Ctx {
   ecpic_mcc_desc mcc{};
   double numax[kMaxSpecies] = {0, 0, 0, 0};  // null-collision rate per species
   // learned guess
-  uint16_t* nn_w = nullptr;
-  float nn_norm[9] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
+  float* nn_w = nullptr;           // FP32 weights, canonical layout
+  float nn_norm[8] = {1, 1, 1, 1, 1, 1, 1, 1};  // input (6) and output (2) scales
   bool nn_ready = false;
-  void* nn_ws = nullptr;           // activation workspace
+  void* nn_ws = nullptr;           // training/batch workspace
   size_t nn_ws_bytes = 0;
+  void* nn_gws = nullptr;          // workspace of the in-step guess (one image)
+  size_t nn_gws_bytes = 0;
   // event timing of the hot kernels
   uint32_t prof_mask = 0;          // bit k: time launches of kind k
   int cur_tag = 0;                 // iteration whose launches are being enqueued
@@ -297,4 +299,19 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_i(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 
+// Record a failed HIP call in the context `c` in scope and return EHIP.
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      c.err = std::string(#expr) + ": " + hipGetErrorString(e_);                  \
+      return ECPIC_EHIP;                                                          \
+    }                                                                             \
+  } while (0)
+
 }  // namespace ecpic
+
+// the opaque handle of the C ABI
+struct ecpic_ctx {
+  ecpic::Ctx c;
+};
