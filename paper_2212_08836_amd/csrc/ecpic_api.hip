@@ -973,40 +973,62 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     if (rc != ECPIC_OK) return rc;
     return enqueue_solve(c, k, dtol, true);
   };
+  // With the learned guess, a residual that does not fall from one iterate
+  // to the next sends the step back to the extrapolated guess (the
+  // iteration is restarted; nn_fallback reports it).
+  bool nn_active = S->used_nn != 0;
   int k = 0;
   bool conv = false;
-  {
-    ecpic_status rc = enqueue_iteration(0);
-    if (rc != ECPIC_OK) return rc;
-  }
-  for (k = 0; k < kmax; ++k) {
-    Roles after_k;
-    save(after_k);
-    const bool ahead = k + 1 < kmax;
-    if (ahead) {
-      // the next push uses (u^n + u^{n+1,(k+1)}) / 2
-      swap_half(c);
-      ecpic_status rc = enqueue_iteration(k + 1);
-      if (rc != ECPIC_OK) return rc;
-    }
-    double r = 0.0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    bool restart = false;
     {
-      ecpic_status rc = wait_residual(c, k, &r);
+      ecpic_status rc = enqueue_iteration(0);
       if (rc != ECPIC_OK) return rc;
     }
-    S->residual[k] = r;
-    if (tol_mode && r <= o->tol) {
-      conv = true;
+    double prev_r = INFINITY;
+    for (k = 0; k < kmax; ++k) {
+      Roles after_k;
+      save(after_k);
+      const bool ahead = k + 1 < kmax;
       if (ahead) {
-        // the commit keeps the half-step field of push k and iterate k
-        restore(after_k);
-        drop_tag(c, k + 1);
+        // the next push uses (u^n + u^{n+1,(k+1)}) / 2
+        swap_half(c);
+        ecpic_status rc = enqueue_iteration(k + 1);
+        if (rc != ECPIC_OK) return rc;
       }
-      ++k;
-      break;
+      double r = 0.0;
+      {
+        ecpic_status rc = wait_residual(c, k, &r);
+        if (rc != ECPIC_OK) return rc;
+      }
+      S->residual[k] = r;
+      if (tol_mode && r <= o->tol) {
+        conv = true;
+        if (ahead) {
+          // the commit keeps the half-step field of push k and iterate k
+          restore(after_k);
+          drop_tag(c, k + 1);
+        }
+        ++k;
+        break;
+      }
+      // timings of iterations that are known to be needed
+      collect(c);
+      if (tol_mode && nn_active && k >= 1 && !(r < prev_r)) {
+        restart = true;
+        break;
+      }
+      prev_r = r;
     }
-    // timings of iterations that are known to be needed
+    if (!restart) break;
+    // back to the extrapolated guess: drain the iteration enqueued ahead,
+    // then start again (the guess kernel clears the stop flag, currents and
+    // pass scratch, and sets every iterate and half-step buffer it uses)
+    HIPCHK(hipStreamSynchronize(c.stream));
     collect(c);
+    S->nn_fallback = 1;
+    nn_active = false;
+    HIPCHK(launch_guess_half(c, vnow, vnext, c.stream));
   }
   c.cur_tag = -1;
   S->iters = k;
