@@ -11,7 +11,10 @@ before the timed region.
 
 Prints one JSON line.  `value` = particle-pushes per second counted over the
 Picard iterations (N_alive x iterations summed over the timed steps, divided
-by the wall time of the whole steps).
+by the wall time of the whole steps).  `mixed_nn` gives the same workload in
+the FP32-push form with the learned initial guess (trained beforehand, outside
+the timed region, on snapshots of the plain method from other seeds), its
+seconds per step and speedup over the plain FP64 path.
 """
 from __future__ import annotations
 
@@ -21,6 +24,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -64,6 +69,72 @@ def committed_traffic(precision):
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def mixed_nn_leg(E, P, w, steps, warmup, sort_every, plain_ms):
+    """The FP32 push + learned-guess form on the same workload: the network
+    is trained first (outside the timed region) by the library's kernels on
+    snapshots of the plain FP64 method from two other seeds/pressures."""
+    import torch
+    from paper_2212_08836_amd import nn_guess as G
+    t0 = time.perf_counter()
+    xs, ts = [], []
+    for seed, pr in ((102, 5.0), (103, 2.0)):
+        wt = E.workload("c2", seed=seed, pressure_pa=pr)
+        c = P.context_from_workload(wt)
+        P.load_workload_species(c, E.make_particles(wt), extra_cap=0.3)
+        c.sort()
+        c.set_mcc(wt.mcc_params())
+        for k in range(20):
+            c.step(tol=wt.tol, sort_every=sort_every, stats=False)
+        x, t = G.collect(c, 250, wt.tol, sort_every=sort_every)
+        xs.append(x)
+        ts.append(t)
+        c.close()
+    x, t = np.concatenate(xs), np.concatenate(ts)
+    del xs, ts
+    n_snap = int(x.shape[0])
+    norm = G.scales(x, t)
+    ctx = P.context_from_workload(w, precision="mixed")
+    P.load_workload_species(ctx, E.make_particles(w), extra_cap=0.25)
+    ctx.sort()
+    ctx.set_mcc(w.mcc_params())
+    xd, td = G.to_device(ctx, x, t, norm)
+    del x, t
+    wts, losses = G.train(ctx, xd, td, steps=1200, batch=8, lr=1e-3, seed=1)
+    del xd, td
+    ctx.nn_set_weights(wts, norm)
+    t_train = time.perf_counter() - t0
+    print(f"# mixed + learned guess: trained in {t_train:.1f} s, loss {losses[0]:.3f} -> "
+          f"{np.mean(losses[-50:]):.3f}", file=sys.stderr, flush=True)
+    for k in range(warmup):
+        ctx.step(tol=w.tol, sort_every=sort_every, use_nn=True, stats=False)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True, kinds=("push",))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(steps):
+        ctx.step(tol=w.tol, sort_every=sort_every, use_nn=True, stats=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    # first residual and fallbacks over a few steps with statistics
+    r0, fb = [], 0
+    for k in range(20):
+        d = ctx.step(tol=w.tol, sort_every=sort_every, use_nn=True)
+        r0.append(d["residual"][0])
+        fb += d["nn_fallback"]
+    ctx.close()
+    ms = 1e3 * el / steps
+    return {"ms_per_step": ms, "s_per_step": el / steps,
+            "particle_pushes_per_s": prof["push"]["particles"] / el,
+            "picard_iterations_per_step": prof["push"]["launches"] / steps,
+            "first_residual_mean": float(np.mean(r0)), "nn_fallbacks": fb,
+            "speedup_vs_plain": plain_ms / ms,
+            "train": {"snapshots": n_snap, "adam_steps": len(losses),
+                      "loss_first": losses[0], "loss_last50": float(np.mean(losses[-50:])),
+                      "seconds": t_train}}
 
 
 def calibrate_copy(mib):
@@ -113,6 +184,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--sort-every", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-nn", action="store_true",
+                    help="skip the FP32 push + learned-guess comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the streaming copy used to scale the HBM counters")
     args = ap.parse_args()
@@ -205,6 +278,15 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(args.precision),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms},
     }
+    # first Picard residual of the plain (extrapolated) guess, for comparison
+    r0 = []
+    for k in range(20):
+        r0.append(ctx.step(tol=w.tol, sort_every=args.sort_every)["residual"][0])
+    out["first_residual_mean"] = float(np.mean(r0))
+    if not args.no_nn and args.precision == "fp64":
+        print("# mixed precision + learned guess", file=sys.stderr, flush=True)
+        out["mixed_nn"] = mixed_nn_leg(E, P, w, args.steps, args.warmup, args.sort_every,
+                                       out["ms_per_step"])
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, parts, mcc)
