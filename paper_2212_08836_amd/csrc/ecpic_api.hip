@@ -318,12 +318,12 @@ PushArgs push_args(Ctx& c, int sid, int commit) {
 // already reset (by the guess kernel, the last field solve and the residual
 // kernel); a standalone pass (prezeroed false) resets them itself.
 ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroed,
-                  bool guarded = false) {
+                  bool guarded = false, bool deposit = true) {
   if (!prezeroed) {
     HIPCHK(zero(c.Ir, n_edges_r(c), c.stream));
     HIPCHK(zero(c.Iz, n_edges_z(c), c.stream));
     if (commit) HIPCHK(launch_zero_tally(c, c.stream));
-    HIPCHK(launch_zero_i(c.qcount, kMaxSpecies * kSpread * kLineInts, c.stream));
+    HIPCHK(launch_zero_i(c.qcount, 2 * kQCount, c.stream));
   }
   // append offsets of every species are taken before any pass appends
   std::vector<MccDev> mcc(c.sp.size());
@@ -346,7 +346,13 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
       a = push_args(c, s, commit);
       a.mcc = mcc[s];
       a.stop = guarded ? c.stop : nullptr;
+      if (!deposit) {
+        a.Ir = nullptr;
+        a.Iz = nullptr;
+      }
       P.queue[q] = c.queue + (int64_t)s * c.queue_cap;
+      P.cqueue[q] = c.queue + (int64_t)(kMaxSpecies + s) * c.queue_cap;
+      P.cqcount[q] = c.qcount + kQCount + s * kSpread * kLineInts;
       P.qcount[q] = c.qcount + s * kSpread * kLineInts;
       P.qseg[q] = queue_segment(c.sp[s].n);
       // commit: state + id read, state written; iteration: state read
@@ -356,11 +362,12 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
     P.nb0 = fast_blocks(P.a[0].s.n);
     {
       Timed tm(c, commit ? ECPIC_K_COMMIT : ECPIC_K_PUSH, bytes, parts);
-      HIPCHK(launch_push_fast(P, c.stream));
+      HIPCHK(launch_push_fast(P, deposit, c.stream));
     }
     {
       Timed tm(c, commit ? ECPIC_K_COMMIT_SLOW : ECPIC_K_PUSH_SLOW, 0.0, 0);
       HIPCHK(launch_push_slow(P, c.stream));
+      if (commit && with_mcc) HIPCHK(launch_collide_list(P, c.stream));
     }
   }
   return ECPIC_OK;
@@ -458,6 +465,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   A(&c.ur_it, nur); A(&c.uz_it, nuz); A(&c.h_it, nh);
   A(&c.ur_nx, nur); A(&c.uz_nx, nuz); A(&c.h_nx, nh);
   A(&c.ur_half, nur); A(&c.uz_half, nuz); A(&c.Ir, nur); A(&c.Iz, nuz);
+  A(&c.Ir_alt, nur); A(&c.Iz_alt, nuz);
   A(&c.ur_half2, nur); A(&c.uz_half2, nuz);
   A(&c.wall_bot, g->nr + 1); A(&c.wall_top, g->nr + 1); A(&c.wall_side, g->nz + 1);
   c.ur_half_f = c.uz_half_f = c.ur_half_f2 = c.uz_half_f2 = nullptr;
@@ -471,7 +479,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   ok = ok && dalloc(&c.offs, (size_t)nh + 1) == hipSuccess;
   ok = ok && dalloc(&c.scan_part, (size_t)(nh + 1023) / 1024 + 2) == hipSuccess;
   ok = ok && dalloc(&c.tally, kSpread) == hipSuccess;
-  ok = ok && dalloc(&c.qcount, kMaxSpecies * kSpread * kLineInts) == hipSuccess;
+  ok = ok && dalloc(&c.qcount, 2 * kQCount) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.tally_host, kSpread * sizeof(Tally)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.red_host, 64 * sizeof(double)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.part_host, kPartLen * sizeof(double)) == hipSuccess;
@@ -495,9 +503,10 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
     return ECPIC_EHIP;
   }
   double* zs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.ur_it, c.uz_it, c.h_it,
-                  c.ur_half, c.uz_half, c.Ir, c.Iz, c.ur_half2, c.uz_half2, c.h_prev};
-  int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz, nh};
-  for (int k = 0; k < 15; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
+                  c.ur_half, c.uz_half, c.Ir, c.Iz, c.ur_half2, c.uz_half2, c.h_prev,
+                  c.Ir_alt, c.Iz_alt};
+  int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz, nh, nur, nuz};
+  for (int k = 0; k < 17; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
   (void)launch_zero_i(c.stop, 1, c.stream);
   (void)launch_zero(c.wall_bot, g->nr + 1, c.stream);
   (void)launch_zero(c.wall_top, g->nr + 1, c.stream);
@@ -521,6 +530,7 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
   double* fs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.h_prev, c.ur_it, c.uz_it, c.h_it,
                   c.ur_nx,
                   c.uz_nx, c.h_nx, c.ur_half, c.uz_half, c.ur_half2, c.uz_half2, c.Ir, c.Iz,
+                  c.Ir_alt, c.Iz_alt,
                   c.wall_bot, c.wall_top,
                   c.wall_side, c.sol.rh, c.sol.wr, c.sol.wz, c.sol.area, c.sol.Q, c.sol.Qt,
                   c.sol.tri_lo, c.sol.tri_inv, c.sol.tri_up, c.sol.work0, c.sol.work1,
@@ -574,7 +584,7 @@ ecpic_status ecpic_add_species(ecpic_ctx* x, const ecpic_species_desc* d, int32_
   const int64_t qlen = kSpread * queue_segment(d->capacity);
   if (qlen > c.queue_cap) {
     int32_t* q = nullptr;
-    if (dalloc(&q, (size_t)qlen * kMaxSpecies) != hipSuccess) {
+    if (dalloc(&q, (size_t)qlen * kMaxSpecies * 2) != hipSuccess) {
       free_species_buf(s.d[0]);
       free_species_buf(s.d[1]);
       return fail(c, ECPIC_ENOMEM, "queue allocation failed");
@@ -710,7 +720,7 @@ ecpic_status ecpic_field_solve(ecpic_ctx* x, const double* ur0, const double* uz
   a.ur0 = ur0;
   a.uz0 = uz0;
   a.h0 = h0;
-  a.Ir = const_cast<double*>(Ir);  // read only: zero_I = 0
+  a.Ir = const_cast<double*>(Ir);  // read only (no clear target)
   a.Iz = const_cast<double*>(Iz);
   a.vnext = drive(c.g, t + c.g.dt);
   a.vhalf = 0.5 * (drive(c.g, t) + a.vnext);
@@ -727,7 +737,7 @@ ecpic_status ecpic_field_solve(ecpic_ctx* x, const double* ur0, const double* uz
 // wait_residual); the new iterate becomes *_it.  Guarded: every kernel returns at
 // once when the stop flag is set (a speculative iteration after convergence);
 // the flag is set when the residual is <= tol.
-static ecpic_status enqueue_solve(Ctx& c, int k, double tol, bool guarded) {
+static ecpic_status enqueue_solve(Ctx& c, int k, double tol, bool guarded, bool alternate) {
   SolveArgs a;
   std::memset(&a, 0, sizeof(a));
   a.ur0 = c.ur;
@@ -747,7 +757,10 @@ static ecpic_status enqueue_solve(Ctx& c, int k, double tol, bool guarded) {
   a.uz_h = c.uz_half2;
   a.ur_hf = c.ur_half_f2;
   a.uz_hf = c.uz_half_f2;
-  a.zero_I = 1;
+  // alternate: clear the other current pair, which the next pass deposits
+  // into, and keep these currents; otherwise clear them once read
+  a.Ir_clr = alternate ? c.Ir_alt : c.Ir;
+  a.Iz_clr = alternate ? c.Iz_alt : c.Iz;
   a.stop = guarded ? c.stop : nullptr;
   {
     // field arrays: u0, I, u_old read, u1 and the half field written, h0 read,
@@ -762,6 +775,10 @@ static ecpic_status enqueue_solve(Ctx& c, int k, double tol, bool guarded) {
   std::swap(c.ur_it, c.ur_nx);
   std::swap(c.uz_it, c.uz_nx);
   std::swap(c.h_it, c.h_nx);
+  if (alternate) {
+    std::swap(c.Ir, c.Ir_alt);
+    std::swap(c.Iz, c.Iz_alt);
+  }
   return ECPIC_OK;
 }
 
@@ -798,7 +815,7 @@ static ecpic_status wait_residual(Ctx& c, int k, double* r) {
 // One unguarded field iterate with the current I; returns the residual.
 static ecpic_status iterate(Ctx& c, double* r_out) {
   HIPCHK(launch_zero_i(c.stop, 1, c.stream));
-  ecpic_status rc = enqueue_solve(c, 0, -1.0, false);
+  ecpic_status rc = enqueue_solve(c, 0, -1.0, false, false);
   if (rc != ECPIC_OK) return rc;
   rc = wait_residual(c, 0, r_out);
   if (rc != ECPIC_OK) return rc;
@@ -954,12 +971,15 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     double *ur_it, *uz_it, *h_it, *ur_nx, *uz_nx, *h_nx, *ur_half, *uz_half, *ur_half2,
         *uz_half2;
     float *ur_half_f, *uz_half_f, *ur_half_f2, *uz_half_f2;
+    double *Ir, *Iz, *Ir_alt, *Iz_alt;
   };
   auto save = [&](Roles& r) {
     r = Roles{c.ur_it, c.uz_it, c.h_it, c.ur_nx, c.uz_nx, c.h_nx, c.ur_half, c.uz_half,
-              c.ur_half2, c.uz_half2, c.ur_half_f, c.uz_half_f, c.ur_half_f2, c.uz_half_f2};
+              c.ur_half2, c.uz_half2, c.ur_half_f, c.uz_half_f, c.ur_half_f2, c.uz_half_f2,
+              c.Ir, c.Iz, c.Ir_alt, c.Iz_alt};
   };
   auto restore = [&](const Roles& r) {
+    c.Ir = r.Ir; c.Iz = r.Iz; c.Ir_alt = r.Ir_alt; c.Iz_alt = r.Iz_alt;
     c.ur_it = r.ur_it; c.uz_it = r.uz_it; c.h_it = r.h_it;
     c.ur_nx = r.ur_nx; c.uz_nx = r.uz_nx; c.h_nx = r.h_nx;
     c.ur_half = r.ur_half; c.uz_half = r.uz_half;
@@ -971,7 +991,7 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     c.cur_tag = k;
     ecpic_status rc = pass(c, 0, false, c.step, true, true);
     if (rc != ECPIC_OK) return rc;
-    return enqueue_solve(c, k, dtol, true);
+    return enqueue_solve(c, k, dtol, true, true);
   };
   // With the learned guess, a residual that does not fall from one iterate
   // to the next sends the step back to the extrapolated guess (the
@@ -1039,13 +1059,16 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     collect(c);
     return fail(c, ECPIC_ENOTCONV, "Picard iteration did not converge");
   }
-  // commit the particles pushed in the accepted half-step field, with MCC
-  ecpic_status rc = pass(c, 1, c.mcc.enabled != 0, c.step, true);
+  // commit the particles pushed in the accepted half-step field, with MCC;
+  // its currents are, bitwise, those of the accepted push, kept in the
+  // alternate pair, so the commit deposits nothing
+  ecpic_status rc = pass(c, 1, c.mcc.enabled != 0, c.step, true, false, false);
   if (rc != ECPIC_OK) return rc;
   double* d = c.sol.partial;
-  HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir, c.Iz, d + kOffEx, c.stream));
+  HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir_alt, c.Iz_alt, d + kOffEx,
+                         c.stream));
   const uint64_t seq = ++c.fin_seq;
-  HIPCHK(launch_finalize(c, d + kOffEx, seq, c.stream));
+  HIPCHK(launch_finalize(c, d + kOffEx, c.Ir_alt, seq, c.stream));
   {
     uint64_t got = 0;
     rc = wait_word(c, reinterpret_cast<volatile uint64_t*>(&c.fin_host->seq), seq - 1, &got);

@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
         a.ur_h[e] = hv;
         if (a.ur_hf) a.ur_hf[e] = float(hv);
       }
-      if (a.zero_I) a.Ir[e] = 0.0;
+      if (a.Ir_clr) a.Ir_clr[e] = 0.0;
     }
   }
   // z-edges of row i (and the PEC row nr, owned by the last block)
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
         a.uz_h[e] = hv;
         if (a.uz_hf) a.uz_hf[e] = float(hv);
       }
-      if (a.zero_I) a.Iz[e] = 0.0;
+      if (a.Iz_clr) a.Iz_clr[e] = 0.0;
       a.h1[e] = 2.0 * xi_[j] - a.h0[e];
       if (i == nr - 1) {
         const int64_t ew = (int64_t)nr * nz + j;
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
           a.uz_h[ew] = hv;
           if (a.uz_hf) a.uz_hf[ew] = float(hv);
         }
-        if (a.zero_I) a.Iz[ew] = 0.0;
+        if (a.Iz_clr) a.Iz_clr[ew] = 0.0;
       }
     }
   }
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
 // Clear the per-pass queue counters and tally copies (thread t of nthreads).
 __device__ __forceinline__ void clear_pass_scratch(int64_t t, int64_t nthreads, int32_t* qcount,
                                                    Tally* tally) {
-  for (int64_t q = t; q < (int64_t)kMaxSpecies * kSpread * kLineInts; q += nthreads) qcount[q] = 0;
+  for (int64_t q = t; q < 2 * (int64_t)kQCount; q += nthreads) qcount[q] = 0;
   uint64_t* tw = reinterpret_cast<uint64_t*>(tally);
   const int64_t nw = (int64_t)kSpread * (int64_t)(sizeof(Tally) / sizeof(uint64_t));
   for (int64_t q = t; q < nw; q += nthreads) tw[q] = 0;
@@ -538,8 +538,9 @@ hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Ctx& c, const double* xpart, uint64_t seq, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, c.tally, xpart, c.h, c.h_it, c.Ir,
+hipError_t launch_finalize(const Ctx& c, const double* xpart, const double* Ir, uint64_t seq,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, c.tally, xpart, c.h, c.h_it, Ir,
                      c.g.nr, c.g.nz, seq, c.fin_dev);
   return hipGetLastError();
 }

@@ -24,6 +24,9 @@ constexpr int kPerBlock = kBlock * kPerThread;
 // uses copy b % kSpread (queue segments, commit tallies).
 constexpr int kSpread = 64;
 constexpr int kLineInts = 32;   // 128-byte stride between queue counters
+// queue counters of one kind: [kMaxSpecies][kSpread][kLineInts]; two kinds
+// (the slow-pass queue, then the collision list) in one allocation
+constexpr int kQCount = kMaxSpecies * kSpread * kLineInts;
 
 // Mesh map r(xi) (C^1 two-piece: r = 2 s sqrt(xi xi_a) below xi_a, s (xi+xi_a)
 // above) and the uniform axial map z = eta dz.
@@ -115,6 +118,8 @@ struct PassArgs {
   PushArgs a[2];
   int32_t* queue[2];   // kSpread segments of qseg entries per slot
   int32_t* qcount[2];  // kSpread counters, kLineInts apart, zero on entry
+  int32_t* cqueue[2];  // the same for the collision list of a commit pass
+  int32_t* cqcount[2];
   int64_t qseg[2];
   int64_t nb0;         // blocks of slot 0 in the fast kernel
   int32_t nsp;         // slots in use (1 or 2)
@@ -132,7 +137,7 @@ struct SolveArgs {
   double* part;         // [2 * nr]: per row sum w (u1 - u_old)^2, sum w u1^2
   double *ur_h, *uz_h;  // (u0 + u1) / 2
   float *ur_hf, *uz_hf;
-  int32_t zero_I;
+  double *Ir_clr, *Iz_clr;  // set to zero once read (may alias Ir, Iz), or null
   const int32_t* stop;  // when set and nonzero the solve does nothing (or null)
 };
 
@@ -188,15 +193,20 @@ struct Ctx {
   struct StepFinal* fin_dev = nullptr;   // device alias
   uint64_t fin_seq = 0;            // sequence number of the last summary asked for
   int32_t* sort_total_host = nullptr;    // [kMaxSpecies], pinned
-  double *Ir, *Iz;                 // currents
+  double *Ir, *Iz;                 // currents deposited by the current pass
+  double *Ir_alt, *Iz_alt;         // the other pair: inside a step the Picard
+                                   // iterations alternate, so that the currents
+                                   // of the accepted iterate outlive its solve
   double *wall_bot, *wall_top, *wall_side;
   int32_t* hist;                   // per-cell counts [nr*nz + 1]
   int32_t* offs;                   // per-cell offsets [nr*nz + 1]
   int32_t* scan_part;              // scan block sums
   Tally* tally;                    // device tallies, kSpread copies
-  int32_t* queue = nullptr;        // slow-pass particle queues, one per species
-  int64_t queue_cap = 0;           // entries per species
-  int32_t* qcount = nullptr;       // queue lengths [kMaxSpecies][kSpread][kLineInts]
+  int32_t* queue = nullptr;        // slow-pass particle queues, one per species,
+                                   // then as many collision lists
+  int64_t queue_cap = 0;           // entries per species and kind
+  int32_t* qcount = nullptr;       // queue lengths: 2 kQCount (slow queues, then
+                                   // collision lists)
   Tally* tally_host;               // pinned host mirror of the copies
   double* red_host;                // pinned host reduction results
   SolverDev sol;
@@ -234,8 +244,10 @@ struct Ctx {
 // ones it queued (cell crossers, failed solves).  queue holds kSpread
 // segments of queue_seg entries; qcount (kSpread counters, kLineInts apart)
 // must be zero on entry.  tally points at kSpread copies.
-hipError_t launch_push_fast(const PassArgs& p, hipStream_t s);
+hipError_t launch_push_fast(const PassArgs& p, bool deposit, hipStream_t s);
 hipError_t launch_push_slow(const PassArgs& p, hipStream_t s);
+// commit pass with MCC: the collisions of the particles the fast pass listed
+hipError_t launch_collide_list(const PassArgs& p, hipStream_t s);
 // entries per queue segment for n particles: fast-pass block b queues into
 // segment b % kSpread
 inline int64_t queue_segment(int64_t n) {
@@ -269,7 +281,8 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s);
 // when *stop is already set.
 hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s);
 // commit summary into fin_dev (host memory), seq written last
-hipError_t launch_finalize(const Ctx& c, const double* xpart, uint64_t seq, hipStream_t s);
+hipError_t launch_finalize(const Ctx& c, const double* xpart, const double* Ir, uint64_t seq,
+                           hipStream_t s);
 hipError_t launch_zero_tally(const Ctx& c, hipStream_t s);
 // the value a residual slot holds until the device has written it
 constexpr uint64_t kResPending = 0x7ff4dead0badf00dull;

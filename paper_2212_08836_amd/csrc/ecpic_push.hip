@@ -345,6 +345,7 @@ __device__ __forceinline__ Dep make_dep(double a0, double b0, double a1, double 
 
 __device__ __forceinline__ void atomic_dep(double* Ir, double* Iz, int nz, int i, int j,
                                            const Dep& d) {
+  if (!Ir) return;  // a pass that deposits nothing
   double* pr = Ir + (size_t)i * (nz + 1) + j;
   unsafeAtomicAdd(pr, d.r0);
   unsafeAtomicAdd(pr + 1, d.r1);
@@ -890,17 +891,48 @@ __device__ __forceinline__ void tl_zero(Tl& t) {
 }
 
 __device__ void tl_flush(const Tl& t, Tally* tally, int sid) {
-  block_sum_atomic(t.work, &tally->w_particles);
-  block_sum_atomic(t.dke_abs, &tally->w_absorbed);
-  block_sum_atomic(t.dke_coll, &tally->w_coll);
-  block_count_atomic(t.absorbed, &tally->n_absorbed[sid]);
-  block_count_atomic(t.coll, &tally->n_coll[sid]);
-  block_count_atomic(t.ion, &tally->n_ionized);
-  block_count_atomic(t.err, &tally->n_errors);
-  block_count_atomic(t.over, &tally->n_over_range);
-  block_count_atomic(t.ovf, &tally->n_overflow);
-  block_count_atomic(t.nsub, &tally->n_substeps);
-  block_count_atomic(t.ncross, &tally->n_crossings);
+  // wavefront sums, one barrier, then one atomic per non-zero field
+  __shared__ double red_d[kBlock / 64][3];
+  __shared__ unsigned red_u[kBlock / 64][8];
+  double d[3] = {t.work, t.dke_abs, t.dke_coll};
+  unsigned u[8] = {t.absorbed, t.coll, t.ion, t.err, t.over, t.ovf, t.nsub, t.ncross};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) d[q] += __shfl_down(d[q], off, 64);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] += __shfl_down(u[q], off, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) red_d[w][q] = d[q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red_u[w][q] = u[q];
+  }
+  __syncthreads();
+  const int f = threadIdx.x;
+  if (f < 3) {
+    double sd = 0.0;
+    for (int k = 0; k < kBlock / 64; ++k) sd += red_d[k][f];
+    double* dst = f == 0 ? &tally->w_particles : (f == 1 ? &tally->w_absorbed : &tally->w_coll);
+    if (sd != 0.0) unsafeAtomicAdd(dst, sd);
+  } else if (f < 11) {
+    unsigned long long su = 0;
+    for (int k = 0; k < kBlock / 64; ++k) su += red_u[k][f - 3];
+    unsigned long long* dst;
+    switch (f - 3) {
+      case 0: dst = &tally->n_absorbed[sid]; break;
+      case 1: dst = &tally->n_coll[sid]; break;
+      case 2: dst = &tally->n_ionized; break;
+      case 3: dst = &tally->n_errors; break;
+      case 4: dst = &tally->n_over_range; break;
+      case 5: dst = &tally->n_overflow; break;
+      case 6: dst = &tally->n_substeps; break;
+      default: dst = &tally->n_crossings; break;
+    }
+    if (su) atomicAdd(dst, su);
+  }
 }
 
 // commit of one pushed particle: absorption (wall charge, energy) or state
@@ -1021,6 +1053,18 @@ __device__ __forceinline__ void tile_deposit(const Tile& t, double* Ir, double* 
   }
 }
 
+// Commit of an in-cell particle in the fast pass: the pushed state is
+// stored; with MCC, true when the null-collision draw selects it (the same
+// draw collide_one makes first).
+template <typename T>
+__device__ __forceinline__ bool commit_store(const PushArgs& A, int64_t k, const PState<T>& p) {
+  store_particle<T>(A.s, A.m, k, p);
+  if (!A.mcc.enabled) return false;
+  double u[4];
+  draws(A.mcc.seed, A.s.sid, A.s.uid[k], A.mcc.step, 0, u);
+  return u[0] < A.mcc.pnull;
+}
+
 // Fast pass: every particle solves the mid-point system over the whole step
 // in its cell.  Those that stay in the closed cell are done (this is exactly
 // the first sub-step of the full algorithm); their currents are gathered in
@@ -1029,16 +1073,19 @@ __device__ __forceinline__ void tile_deposit(const Tile& t, double* Ir, double* 
 // consecutive in memory (sorted by cell after a sort), strided by kBlock.
 // Blocks [0, nb0) serve species slot 0 of the pass, the rest slot 1.
 // Dynamic LDS: tile_r_len(nz) + tile_z_len(nz) doubles.
-template <typename T, bool COMMIT>
+template <typename T, bool COMMIT, bool DEPOSIT>
 __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   if (P.a[0].stop && *P.a[0].stop) return;
   extern __shared__ double tile_mem[];
   __shared__ int32_t slow_list[kPerBlock];
-  __shared__ int slow_n, gbase;
+  __shared__ int32_t coll_list[COMMIT ? kPerBlock : 1];
+  __shared__ int slow_n, gbase, coll_n, cbase;
   const bool second = (int64_t)blockIdx.x >= P.nb0;
   const PushArgs& A = second ? P.a[1] : P.a[0];
   int32_t* queue = second ? P.queue[1] : P.queue[0];
   int32_t* qcount = second ? P.qcount[1] : P.qcount[0];
+  int32_t* cqueue = second ? P.cqueue[1] : P.cqueue[0];
+  int32_t* cqcount = second ? P.cqcount[1] : P.cqcount[0];
   const int64_t qseg = second ? P.qseg[1] : P.qseg[0];
   const int64_t bx = second ? (int64_t)blockIdx.x - P.nb0 : (int64_t)blockIdx.x;
   const int64_t k_first = bx * kPerBlock;
@@ -1060,9 +1107,14 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
     tl.c_lo = max(c_first - nz - 2, 0);
     tl.er0 = tl.c_lo + tl.c_lo / nz;
   }
-  const int ntile = tile_r_len(nz) + tile_z_len(nz);
-  for (int e = threadIdx.x; e < ntile; e += kBlock) tile_mem[e] = 0.0;
-  if (threadIdx.x == 0) slow_n = 0;
+  if (DEPOSIT) {
+    const int ntile = tile_r_len(nz) + tile_z_len(nz);
+    for (int e = threadIdx.x; e < ntile; e += kBlock) tile_mem[e] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    slow_n = 0;
+    coll_n = 0;
+  }
   __syncthreads();
   Tl t;
   tl_zero(t);
@@ -1133,7 +1185,7 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
         }
       }
     }
-    tile_deposit(tl, A.Ir, A.Iz, nz, key, p.i, p.j, dp);
+    if (DEPOSIT) tile_deposit(tl, A.Ir, A.Iz, nz, key, p.i, p.j, dp);
     // the block's slow list: one LDS atomic per wavefront
     const uint64_t mask = __ballot(slow);
     if (mask) {
@@ -1142,11 +1194,23 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
       wbase = __shfl(wbase, 0, 64);
       if (slow) slow_list[wbase + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)k;
     }
-    if (COMMIT && alive && !slow) commit_one<T>(A, k, p, kAlive, 0, t);
+    if (COMMIT) {
+      // in-cell particles are stored as pushed; those the null-collision
+      // draw selects go to the collision list (k_collide_list)
+      bool coll = false;
+      if (alive && !slow) coll = commit_store<T>(A, k, p);
+      const uint64_t cm = __ballot(coll);
+      if (cm) {
+        int wb = 0;
+        if (lane == 0) wb = atomicAdd(&coll_n, __popcll(cm));
+        wb = __shfl(wb, 0, 64);
+        if (coll) coll_list[wb + __popcll(cm & ((1ull << lane) - 1ull))] = (int32_t)k;
+      }
+    }
   }
   __syncthreads();
   // flush the tile: one global atomic per touched edge
-  {
+  if (DEPOSIT) {
     const int64_t ner = (int64_t)m.nr * (nz + 1), nez = (int64_t)(m.nr + 1) * nz;
     const int lr = tile_r_len(nz), lz = tile_z_len(nz);
     for (int e = threadIdx.x; e < lr; e += kBlock) {
@@ -1158,15 +1222,21 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
       if (v != 0.0 && tl.c_lo + e < nez) unsafeAtomicAdd(A.Iz + tl.c_lo + e, v);
     }
   }
-  // queue the slow ones: one global atomic per block
+  // queue the slow ones (and the colliding ones): one global atomic per block
+  const int64_t seg = bx % kSpread;
   const int ns = slow_n;
   if (ns) {
-    const int64_t seg = bx % kSpread;
     if (threadIdx.x == 0) gbase = atomicAdd(qcount + seg * kLineInts, ns);
     __syncthreads();
     for (int q = threadIdx.x; q < ns; q += kBlock) queue[seg * qseg + gbase + q] = slow_list[q];
   }
   if (!COMMIT) return;
+  const int nc = coll_n;
+  if (nc) {
+    if (threadIdx.x == 0) cbase = atomicAdd(cqcount + seg * kLineInts, nc);
+    __syncthreads();
+    for (int q = threadIdx.x; q < nc; q += kBlock) cqueue[seg * qseg + cbase + q] = coll_list[q];
+  }
   tl_flush(t, A.tally + (blockIdx.x % kSpread), s.sid);
 }
 
@@ -1230,6 +1300,44 @@ __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
     }
   }
   if (COMMIT) tl_flush(t, A.tally + ((blockIdx.y * gridDim.x + blockIdx.x) % kSpread), s.sid);
+}
+
+// Collisions of the particles a committing fast pass listed (their pushed
+// state is already stored): grid (X, kSpread, species slots), like the slow
+// pass.  Particles born here are appended beyond the pass's start counts.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
+  const bool second = blockIdx.z > 0;
+  const PushArgs& A = second ? P.a[1] : P.a[0];
+  const int32_t* queue = second ? P.cqueue[1] : P.cqueue[0];
+  const int32_t* qcount = second ? P.cqcount[1] : P.cqcount[0];
+  const int64_t qseg = second ? P.qseg[1] : P.qseg[0];
+  const MapP& m = A.m;
+  const SpecDev& s = A.s;
+  const int g = blockIdx.y;
+  const int64_t nq = qcount[g * kLineInts];
+  const int32_t* seg = queue + (int64_t)g * qseg;
+  Tl t;
+  tl_zero(t);
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nq;
+       q += (int64_t)gridDim.x * kBlock) {
+    const int64_t k = seg[q];
+    PState<T> p;
+    if (!load_particle<T>(s, m, k, p)) continue;
+    double vr = p.vr, vt = p.vt, vz = p.vz;
+    const CollOut co = collide_one<T>(A.mcc, s, m, s.sid, s.uid[k], p.i, p.j, p.a, p.b, vr, vt, vz,
+                                      A.tally);
+    t.dke_coll += co.dke;
+    t.coll += co.coll;
+    t.ion += co.ionized;
+    t.over += co.over;
+    t.ovf += co.overflow;
+    p.vr = T(vr);
+    p.vt = T(vt);
+    p.vz = T(vz);
+    store_particle<T>(s, m, k, p);
+  }
+  tl_flush(t, A.tally + ((blockIdx.y * gridDim.x + blockIdx.x) % kSpread), s.sid);
 }
 
 // standalone collision pass over the live particles
@@ -1369,24 +1477,45 @@ size_t fast_lds_bytes(int nz) {
   return sizeof(double) * (size_t)(tile_r_len(nz) + tile_z_len(nz));
 }
 
-hipError_t launch_push_fast(const PassArgs& P, hipStream_t st) {
+hipError_t launch_push_fast(const PassArgs& P, bool deposit, hipStream_t st) {
   const int64_t nb = P.nb0 + (P.nsp > 1 ? fast_blocks(P.a[1].s.n) : 0);
   if (nb <= 0) return hipSuccess;
-  const size_t lds = fast_lds_bytes(P.a[0].m.nz);
+  const size_t lds = deposit ? fast_lds_bytes(P.a[0].m.nz) : 0;
   if (lds > 56 * 1024) return hipErrorInvalidValue;
   const bool mixed = (P.a[0].s.cell != nullptr);
   const bool commit = P.a[0].commit != 0;
+  if (!commit && !deposit) return hipErrorInvalidValue;
+  const dim3 g(nb), b(kBlock);
   if (!mixed) {
-    if (commit)
-      hipLaunchKernelGGL((k_push_fast<double, true>), dim3(nb), dim3(kBlock), lds, st, P);
+    if (!commit)
+      hipLaunchKernelGGL((k_push_fast<double, false, true>), g, b, lds, st, P);
+    else if (deposit)
+      hipLaunchKernelGGL((k_push_fast<double, true, true>), g, b, lds, st, P);
     else
-      hipLaunchKernelGGL((k_push_fast<double, false>), dim3(nb), dim3(kBlock), lds, st, P);
+      hipLaunchKernelGGL((k_push_fast<double, true, false>), g, b, lds, st, P);
   } else {
-    if (commit)
-      hipLaunchKernelGGL((k_push_fast<float, true>), dim3(nb), dim3(kBlock), lds, st, P);
+    if (!commit)
+      hipLaunchKernelGGL((k_push_fast<float, false, true>), g, b, lds, st, P);
+    else if (deposit)
+      hipLaunchKernelGGL((k_push_fast<float, true, true>), g, b, lds, st, P);
     else
-      hipLaunchKernelGGL((k_push_fast<float, false>), dim3(nb), dim3(kBlock), lds, st, P);
+      hipLaunchKernelGGL((k_push_fast<float, true, false>), g, b, lds, st, P);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_collide_list(const PassArgs& P, hipStream_t st) {
+  int64_t nmax = 0;
+  for (int q = 0; q < P.nsp; ++q) nmax = P.a[q].s.n > nmax ? P.a[q].s.n : nmax;
+  if (nmax <= 0) return hipSuccess;
+  const int64_t nb = (nmax + kBlock - 1) / kBlock;
+  int64_t xs = (nb / kSpread + 15) / 16;
+  xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
+  const dim3 gs((unsigned)xs, kSpread, (unsigned)P.nsp);
+  if (P.a[0].s.cell != nullptr)
+    hipLaunchKernelGGL((k_collide_list<float>), gs, dim3(kBlock), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_collide_list<double>), gs, dim3(kBlock), 0, st, P);
   return hipGetLastError();
 }
 
