@@ -6,7 +6,7 @@ m^-3, 64 macro-particles per cell per species = 4,194,304 particles,
 null-collision MCC in 5 Pa argon, dt = 1e-11 s, Picard tolerance 1e-10),
 plain FP64 path.  A step is one implicit step: guess, Picard iterations of
 push+deposit and field solve, commit with absorption and MCC, and the
-counting sort every 4 steps.  Synthetic seeded inputs, resident in HBM
+counting sort every 16 steps.  Synthetic seeded inputs, resident in HBM
 before the timed region.
 
 Prints one JSON line.  `value` = particle-pushes per second counted over the
@@ -182,7 +182,7 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--sort-every", type=int, default=4)
+    ap.add_argument("--sort-every", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-nn", action="store_true",
                     help="skip the FP32 push + learned-guess comparison")

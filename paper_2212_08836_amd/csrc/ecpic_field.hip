@@ -485,34 +485,47 @@ __global__ void __launch_bounds__(256) k_converge(const double* __restrict__ par
   if (r <= tol) *stop = 1;
 }
 
-// Commit summary: tallies summed over their copies in copy order, the
-// exchange partials in block order, and the drive-gap values; the sequence
-// number is stored last, after a system-scope fence.  One thread.
-__global__ void k_finalize(const Tally* __restrict__ tally, const double* __restrict__ xpart,
-                           const double* __restrict__ hn, const double* __restrict__ h1,
-                           const double* __restrict__ Ir, int nr, int nz, uint64_t seq,
-                           StepFinal* out) {
-  if (threadIdx.x != 0) return;
-  Tally t = tally[0];
-  for (int q = 1; q < kSpread; ++q) {
-    const Tally& u = tally[q];
-    t.w_absorbed += u.w_absorbed;
-    t.w_coll += u.w_coll;
-    t.w_particles += u.w_particles;
-    for (int s = 0; s < kMaxSpecies; ++s) {
-      t.n_absorbed[s] += u.n_absorbed[s];
-      t.n_coll[s] += u.n_coll[s];
-      t.append[s] += u.append[s];
-    }
-    t.n_ionized += u.n_ionized;
-    t.n_errors += u.n_errors;
-    t.n_crossings += u.n_crossings;
-    t.n_substeps += u.n_substeps;
-    t.n_over_range += u.n_over_range;
-    t.n_overflow += u.n_overflow;
+// Commit summary: the tally copies and the exchange partials reduced by one
+// wavefront in a fixed butterfly order (deterministic), the drive-gap
+// values, and the sequence number stored last after a system-scope fence.
+__device__ __forceinline__ double wsum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ unsigned long long wsum_u(unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally,
+                                                 const double* __restrict__ xpart,
+                                                 const double* __restrict__ hn,
+                                                 const double* __restrict__ h1,
+                                                 const double* __restrict__ Ir, int nr, int nz,
+                                                 uint64_t seq, StepFinal* out) {
+  static_assert(kSpread == 64, "one tally copy per lane");
+  const int l = threadIdx.x;
+  const Tally& u = tally[l];
+  Tally t;
+  t.w_absorbed = wsum_d(u.w_absorbed);
+  t.w_coll = wsum_d(u.w_coll);
+  t.w_particles = wsum_d(u.w_particles);
+  t.pad = 0.0;
+  for (int s = 0; s < kMaxSpecies; ++s) {
+    t.n_absorbed[s] = wsum_u(u.n_absorbed[s]);
+    t.n_coll[s] = wsum_u(u.n_coll[s]);
+    t.append[s] = wsum_u(u.append[s]);
   }
+  t.n_ionized = wsum_u(u.n_ionized);
+  t.n_errors = wsum_u(u.n_errors);
+  t.n_crossings = wsum_u(u.n_crossings);
+  t.n_substeps = wsum_u(u.n_substeps);
+  t.n_over_range = wsum_u(u.n_over_range);
+  t.n_overflow = wsum_u(u.n_overflow);
   double xs = 0.0;
-  for (int b = 0; b < kRedBlocks; ++b) xs += xpart[b];
+  for (int b = l; b < kRedBlocks; b += 64) xs += xpart[b];
+  xs = wsum_d(xs);
+  if (l != 0) return;
   out->t = t;
   out->xs = xs;
   out->h_gap_n = hn[(int64_t)(nr - 1) * nz];
