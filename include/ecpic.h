@@ -252,7 +252,10 @@ typedef enum {
   ECPIC_K_COMMIT_SLOW = 3,  /* committing push of the face-crossing ones     */
   ECPIC_K_FIELD = 4,        /* one field solve (rhs+DCT, scan, iDCT+recover) */
   ECPIC_K_SORT = 5,         /* counting sort of one species                  */
-  ECPIC_K_COUNT = 6
+  ECPIC_K_PUSH_COMMIT = 6,  /* a Picard iteration's in-cell pass that also
+                               commits (into the other particle buffer), run
+                               when the residual trend predicts convergence */
+  ECPIC_K_COUNT = 7
 } ecpic_kernel_kind;
 
 typedef struct {
@@ -267,7 +270,7 @@ typedef struct {
  * event records on its stream, so a narrow mask perturbs the run least.
  * Launches of a speculative Picard iteration that turns out not to be needed
  * are not counted.  Any call clears the totals. */
-#define ECPIC_PROFILE_ALL 0x3F
+#define ECPIC_PROFILE_ALL 0x7F
 ecpic_status ecpic_set_profiling(ecpic_ctx* ctx, int32_t kind_mask);
 /* Totals since profiling was turned on (synchronises). */
 ecpic_status ecpic_get_profile(ecpic_ctx* ctx, ecpic_profile* out);

@@ -74,12 +74,12 @@ class StepStats(C.Structure):
         return d
 
 
-KERNEL_KINDS = ("push", "push_slow", "commit", "commit_slow", "field", "sort")
+KERNEL_KINDS = ("push", "push_slow", "commit", "commit_slow", "field", "sort", "push_commit")
 
 
 class Profile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 6), ("ms", C.c_double * 6), ("bytes", C.c_double * 6),
-                ("particles", C.c_int64 * 6)]
+    _fields_ = [("launches", C.c_int64 * 7), ("ms", C.c_double * 7), ("bytes", C.c_double * 7),
+                ("particles", C.c_int64 * 7)]
 
     def as_dict(self) -> dict:
         return {k: dict(launches=self.launches[i], ms=self.ms[i], bytes=self.bytes[i],

@@ -98,6 +98,26 @@ SpecDev view(Species& s) {
   return d;
 }
 
+// the species' other buffer, sized like the current one (a committing Picard
+// iteration writes the new state there)
+SpecDev other_view(Species& s) {
+  SpecDev d = view(s);
+  const SpecDev& o = s.d[1 - s.cur];
+  d.xi = o.xi;
+  d.eta = o.eta;
+  d.vr = o.vr;
+  d.vt = o.vt;
+  d.vz = o.vz;
+  d.cell = o.cell;
+  d.fa = o.fa;
+  d.fb = o.fb;
+  d.fvr = o.fvr;
+  d.fvt = o.fvt;
+  d.fvz = o.fvz;
+  d.uid = o.uid;
+  return d;
+}
+
 int64_t n_edges_r(const Ctx& c) { return (int64_t)c.g.nr * (c.g.nz + 1); }
 int64_t n_edges_z(const Ctx& c) { return (int64_t)(c.g.nr + 1) * c.g.nz; }
 int64_t n_cells(const Ctx& c) { return (int64_t)c.g.nr * c.g.nz; }
@@ -263,7 +283,7 @@ void drop_tag(Ctx& c, int tag) {
 // algorithmic bytes per particle of a push pass: the state read once
 double state_bytes(const Ctx& c) { return c.prec == ECPIC_FP64 ? 40.0 : 24.0; }
 
-MccDev make_mcc(Ctx& c, int sid, int64_t step) {
+MccDev make_mcc(Ctx& c, int sid, int64_t step, bool to_other = false) {
   MccDev d;
   std::memset(&d, 0, sizeof(d));
   const ecpic_mcc_desc& M = c.mcc;
@@ -285,7 +305,7 @@ MccDev make_mcc(Ctx& c, int sid, int64_t step) {
   d.base_self = s.n;
   if (role == 1 && M.ion_sid >= 0 && M.ion_sid < (int)c.sp.size()) {
     Species& ion = c.sp[M.ion_sid];
-    d.partner = view(ion);
+    d.partner = to_other ? other_view(ion) : view(ion);
     d.partner.sid = M.ion_sid;
     d.base_partner = ion.n;
     d.sig_ion = std::sqrt(kKB * M.t_gas / ion.desc.m);
@@ -305,6 +325,7 @@ PushArgs push_args(Ctx& c, int sid, int commit) {
   a.Iz = c.Iz;
   a.s = view(c.sp[sid]);
   a.s.sid = sid;
+  a.out = a.s;
   a.commit = commit;
   a.wall_bot = c.wall_bot;
   a.wall_top = c.wall_top;
@@ -317,8 +338,13 @@ PushArgs push_args(Ctx& c, int sid, int commit) {
 // stream.  Inside a step the currents, queue counters and tallies were
 // already reset (by the guess kernel, the last field solve and the residual
 // kernel); a standalone pass (prezeroed false) resets them itself.
+// A committing pass with to_other writes the new states into the species'
+// other buffers (the current ones stay as they are until the host accepts
+// it) and its wall charge into the scratch of parity `set`; its tallies go
+// to tally set `set` in any case.
 ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroed,
-                  bool guarded = false, bool deposit = true) {
+                  bool guarded = false, bool deposit = true, bool to_other = false,
+                  int set = 0) {
   if (!prezeroed) {
     HIPCHK(zero(c.Ir, n_edges_r(c), c.stream));
     HIPCHK(zero(c.Iz, n_edges_z(c), c.stream));
@@ -329,7 +355,7 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
   std::vector<MccDev> mcc(c.sp.size());
   for (size_t s = 0; s < c.sp.size(); ++s) {
     std::memset(&mcc[s], 0, sizeof(MccDev));
-    if (commit && with_mcc) mcc[s] = make_mcc(c, (int)s, step);
+    if (commit && with_mcc) mcc[s] = make_mcc(c, (int)s, step, to_other);
   }
   std::vector<int> act;
   for (size_t s = 0; s < c.sp.size(); ++s)
@@ -346,6 +372,15 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
       a = push_args(c, s, commit);
       a.mcc = mcc[s];
       a.stop = guarded ? c.stop : nullptr;
+      a.tally = tally_set(c, set);
+      if (to_other) {
+        a.out = other_view(c.sp[s]);
+        a.out.sid = s;
+        double* w = wall_scratch(c, set);
+        a.wall_bot = w;
+        a.wall_top = w + (c.g.nr + 1);
+        a.wall_side = w + 2 * (c.g.nr + 1);
+      }
       if (!deposit) {
         a.Ir = nullptr;
         a.Iz = nullptr;
@@ -356,12 +391,16 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
       P.qcount[q] = c.qcount + s * kSpread * kLineInts;
       P.qseg[q] = queue_segment(c.sp[s].n);
       // commit: state + id read, state written; iteration: state read
-      bytes += (commit ? 2.0 * state_bytes(c) + 8.0 : state_bytes(c)) * (double)c.sp[s].n;
+      // iteration: state read; commit: state and id read, state written (and
+      // the id too when written to the other buffer)
+      bytes += (commit ? 2.0 * state_bytes(c) + (to_other ? 16.0 : 8.0) : state_bytes(c)) *
+               (double)c.sp[s].n;
       parts += c.sp[s].n;
     }
     P.nb0 = fast_blocks(P.a[0].s.n);
     {
-      Timed tm(c, commit ? ECPIC_K_COMMIT : ECPIC_K_PUSH, bytes, parts);
+      const int kind = !commit ? ECPIC_K_PUSH : (to_other ? ECPIC_K_PUSH_COMMIT : ECPIC_K_COMMIT);
+      Timed tm(c, kind, bytes, parts);
       HIPCHK(launch_push_fast(P, deposit, c.stream));
     }
     {
@@ -467,7 +506,12 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   A(&c.ur_half, nur); A(&c.uz_half, nuz); A(&c.Ir, nur); A(&c.Iz, nuz);
   A(&c.Ir_alt, nur); A(&c.Iz_alt, nuz);
   A(&c.ur_half2, nur); A(&c.uz_half2, nuz);
-  A(&c.wall_bot, g->nr + 1); A(&c.wall_top, g->nr + 1); A(&c.wall_side, g->nz + 1);
+  // wall charge: bottom, top and side in one array (the layout of the
+  // committing iterations' scratch, which is added into it)
+  A(&c.wall_bot, wall_len(c));
+  c.wall_top = c.wall_bot ? c.wall_bot + (g->nr + 1) : nullptr;
+  c.wall_side = c.wall_top ? c.wall_top + (g->nr + 1) : nullptr;
+  A(&c.wall_scr, 2 * wall_len(c));
   c.ur_half_f = c.uz_half_f = c.ur_half_f2 = c.uz_half_f2 = nullptr;
   if (prec == ECPIC_MIXED) {
     ok = ok && dalloc(&c.ur_half_f, (size_t)nur) == hipSuccess;
@@ -478,7 +522,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   ok = ok && dalloc(&c.hist, (size_t)nh + 1) == hipSuccess;
   ok = ok && dalloc(&c.offs, (size_t)nh + 1) == hipSuccess;
   ok = ok && dalloc(&c.scan_part, (size_t)(nh + 1023) / 1024 + 2) == hipSuccess;
-  ok = ok && dalloc(&c.tally, kSpread) == hipSuccess;
+  ok = ok && dalloc(&c.tally, 2 * kSpread) == hipSuccess;
   ok = ok && dalloc(&c.qcount, 2 * kQCount) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.tally_host, kSpread * sizeof(Tally)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.red_host, 64 * sizeof(double)) == hipSuccess;
@@ -508,9 +552,8 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz, nh, nur, nuz};
   for (int k = 0; k < 17; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
   (void)launch_zero_i(c.stop, 1, c.stream);
-  (void)launch_zero(c.wall_bot, g->nr + 1, c.stream);
-  (void)launch_zero(c.wall_top, g->nr + 1, c.stream);
-  (void)launch_zero(c.wall_side, g->nz + 1, c.stream);
+  (void)launch_zero(c.wall_bot, wall_len(c), c.stream);
+  (void)launch_zero(c.wall_scr, 2 * wall_len(c), c.stream);
   if (hipStreamSynchronize(c.stream) != hipSuccess) {
     ecpic_destroy(x);
     return ECPIC_EHIP;
@@ -531,8 +574,7 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
                   c.ur_nx,
                   c.uz_nx, c.h_nx, c.ur_half, c.uz_half, c.ur_half2, c.uz_half2, c.Ir, c.Iz,
                   c.Ir_alt, c.Iz_alt,
-                  c.wall_bot, c.wall_top,
-                  c.wall_side, c.sol.rh, c.sol.wr, c.sol.wz, c.sol.area, c.sol.Q, c.sol.Qt,
+                  c.wall_bot, c.wall_scr, c.sol.rh, c.sol.wr, c.sol.wz, c.sol.area, c.sol.Q, c.sol.Qt,
                   c.sol.tri_lo, c.sol.tri_inv, c.sol.tri_up, c.sol.work0, c.sol.work1,
                   c.sol.partial};
   for (double* p : fs) (void)hipFree(p);
@@ -987,9 +1029,33 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     c.ur_half_f = r.ur_half_f; c.uz_half_f = r.uz_half_f;
     c.ur_half_f2 = r.ur_half_f2; c.uz_half_f2 = r.uz_half_f2;
   };
+  // A Picard iteration that is expected to be the last one also commits:
+  // its push writes the new particle states into the other buffers (and
+  // collides the particles its null-collision draws select), its tallies
+  // and wall charge go to the scratch of its parity.  If its residual meets
+  // the tolerance the host accepts it (flips the buffers); otherwise nothing
+  // of it is kept.  Expected: in fixed-iteration mode the last iteration; in
+  // tolerance mode iteration j >= 2 when r_{j-2} (r_{j-2} / r_{j-3})^2, the
+  // residual extrapolated at the observed contraction, is below tol / 10.
+  bool fuse_ok = true;
+  for (const Species& sp : c.sp)
+    if (!sp.desc.mobile) fuse_ok = false;  // an immobile species' buffer would not flip
+  bool committed[kMaxIter] = {};
+  auto expect_last = [&](int j) -> bool {
+    if (!fuse_ok) return false;
+    if (!tol_mode) return j == kmax - 1;
+    if (j < 3) return false;
+    const double a = S->residual[j - 2], b = S->residual[j - 3];
+    if (!(a > 0.0) || !(b > 0.0)) return false;
+    const double rho = a / b;
+    return rho < 1.0 && a * rho * rho <= 0.1 * o->tol;
+  };
   auto enqueue_iteration = [&](int k) -> ecpic_status {
     c.cur_tag = k;
-    ecpic_status rc = pass(c, 0, false, c.step, true, true);
+    const bool fuse = expect_last(k);
+    committed[k] = fuse;
+    ecpic_status rc = fuse ? pass(c, 1, c.mcc.enabled != 0, c.step, true, true, true, true, k & 1)
+                           : pass(c, 0, false, c.step, true, true);
     if (rc != ECPIC_OK) return rc;
     return enqueue_solve(c, k, dtol, true, true);
   };
@@ -1059,16 +1125,26 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     collect(c);
     return fail(c, ECPIC_ENOTCONV, "Picard iteration did not converge");
   }
-  // commit the particles pushed in the accepted half-step field, with MCC;
-  // its currents are, bitwise, those of the accepted push, kept in the
-  // alternate pair, so the commit deposits nothing
-  ecpic_status rc = pass(c, 1, c.mcc.enabled != 0, c.step, true, false, false);
-  if (rc != ECPIC_OK) return rc;
+  // The accepted iteration k* = k - 1 either committed already (into the
+  // other buffers, tallies in its parity's set) or the particles pushed in
+  // its half-step field are committed now, with MCC, in place (tallies in
+  // the set of parity k, cleared by its residual kernel).  Either way the
+  // commit's currents are, bitwise, those of the accepted push, kept in the
+  // alternate pair, so the commit deposits nothing.
+  const int ks = k - 1;
+  const bool fused = committed[ks];
+  const Tally* tset = tally_set(c, fused ? (ks & 1) : ((ks + 1) & 1));
+  ecpic_status rc = ECPIC_OK;
+  if (!fused) {
+    rc = pass(c, 1, c.mcc.enabled != 0, c.step, true, false, false, false, (ks + 1) & 1);
+    if (rc != ECPIC_OK) return rc;
+  }
   double* d = c.sol.partial;
   HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir_alt, c.Iz_alt, d + kOffEx,
                          c.stream));
   const uint64_t seq = ++c.fin_seq;
-  HIPCHK(launch_finalize(c, d + kOffEx, c.Ir_alt, seq, c.stream));
+  HIPCHK(launch_finalize(c, tset, d + kOffEx, c.Ir_alt, fused ? wall_scratch(c, ks & 1) : nullptr,
+                         seq, c.stream));
   {
     uint64_t got = 0;
     rc = wait_word(c, reinterpret_cast<volatile uint64_t*>(&c.fin_host->seq), seq - 1, &got);
@@ -1078,6 +1154,13 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
   std::memcpy(&fin, (const void*)c.fin_host, sizeof(fin));
   collect(c);
   const Tally& t = fin.t;
+  if (fused) {
+    // the new states are in the other buffers
+    for (Species& sp : c.sp) {
+      if (sp.n <= 0 && t.append[&sp - c.sp.data()] == 0) continue;
+      sp.cur = 1 - sp.cur;
+    }
+  }
   for (size_t s = 0; s < c.sp.size(); ++s) {
     int64_t n = c.sp[s].n + (int64_t)t.append[s];
     if (n > c.sp[s].desc.capacity) n = c.sp[s].desc.capacity;

@@ -294,13 +294,15 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
   }
 }
 
-// Clear the per-pass queue counters and tally copies (thread t of nthreads).
+// Clear the per-pass queue counters, one tally set and one wall-charge
+// scratch set (thread t of nthreads).
 __device__ __forceinline__ void clear_pass_scratch(int64_t t, int64_t nthreads, int32_t* qcount,
-                                                   Tally* tally) {
+                                                   Tally* tally, double* wscr, int64_t wlen) {
   for (int64_t q = t; q < 2 * (int64_t)kQCount; q += nthreads) qcount[q] = 0;
   uint64_t* tw = reinterpret_cast<uint64_t*>(tally);
   const int64_t nw = (int64_t)kSpread * (int64_t)(sizeof(Tally) / sizeof(uint64_t));
   for (int64_t q = t; q < nw; q += nthreads) tw[q] = 0;
+  for (int64_t q = t; q < wlen; q += nthreads) wscr[q] = 0.0;
 }
 
 // guess u^{n+1,(0)} = 2 u^n - u^{n-1} (walls at t^{n+1}), the half-step field
@@ -309,12 +311,12 @@ __global__ void k_guess_half(MapP m, double* ur, double* uz, const double* ur_pr
                              const double* uz_prev, double* ur_it, double* uz_it, double* ur_h,
                              double* uz_h, float* ur_hf, float* uz_hf, double* Ir, double* Iz,
                              double vnow, double vnext, int32_t* stop, int32_t* qcount,
-                             Tally* tally) {
+                             Tally* tally, double* wscr, int64_t wlen) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int nr = m.nr, nz = m.nz;
   const int64_t nur = (int64_t)nr * (nz + 1), nuz = (int64_t)(nr + 1) * nz;
   if (t == 0) *stop = 0;
-  clear_pass_scratch(t, (int64_t)gridDim.x * blockDim.x, qcount, tally);
+  clear_pass_scratch(t, (int64_t)gridDim.x * blockDim.x, qcount, tally, wscr, wlen);
   if (t < nur) {
     const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
     double u0 = ur[t], u1;
@@ -462,11 +464,12 @@ __global__ void __launch_bounds__(kBlock) k_xsum(MapP m, const double* __restric
 // scratch for the next push.
 __global__ void __launch_bounds__(256) k_converge(const double* __restrict__ part, int nr, int k,
                                                   double tol, int32_t* stop, double* res,
-                                                  int32_t* qcount, Tally* tally) {
+                                                  int32_t* qcount, Tally* tally, double* wscr,
+                                                  int64_t wlen) {
   if (*stop) return;
   const int t = threadIdx.x;
   if (t >= 64) {
-    clear_pass_scratch(t - 64, blockDim.x - 64, qcount, tally);
+    clear_pass_scratch(t - 64, blockDim.x - 64, qcount, tally, wscr, wlen);
     return;
   }
   double num = 0.0, den = 0.0;
@@ -502,7 +505,9 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
                                                  const double* __restrict__ hn,
                                                  const double* __restrict__ h1,
                                                  const double* __restrict__ Ir, int nr, int nz,
-                                                 uint64_t seq, StepFinal* out) {
+                                                 const double* __restrict__ wall_add,
+                                                 double* __restrict__ wall_tot, uint64_t seq,
+                                                 StepFinal* out) {
   static_assert(kSpread == 64, "one tally copy per lane");
   const int l = threadIdx.x;
   const Tally& u = tally[l];
@@ -525,6 +530,12 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
   double xs = 0.0;
   for (int b = l; b < kRedBlocks; b += 64) xs += xpart[b];
   xs = wsum_d(xs);
+  if (wall_add) {
+    // the wall charge of a committing iteration joins the totals (the three
+    // wall arrays are contiguous in both)
+    const int64_t wlen = 2 * (int64_t)(nr + 1) + nz + 1;
+    for (int64_t e = l; e < wlen; e += 64) wall_tot[e] += wall_add[e];
+  }
   if (l != 0) return;
   out->t = t;
   out->xs = xs;
@@ -546,15 +557,18 @@ __global__ void k_zero_tally(Tally* tally) {
 hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s) {
   // the solve writes the residual row partials at the start of sol.partial
   if (k < 0 || k >= kMaxIter) return hipErrorInvalidValue;
+  // the next iteration (parity k+1) gets a cleared tally set and wall scratch
+  const int np = (k + 1) & 1;
   hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, c.sol.partial, c.g.nr,
-                     k, tol, c.stop, c.res_dev, c.qcount, c.tally);
+                     k, tol, c.stop, c.res_dev, c.qcount, tally_set(c, np),
+                     wall_scratch(c, np), wall_len(c));
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Ctx& c, const double* xpart, const double* Ir, uint64_t seq,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, c.tally, xpart, c.h, c.h_it, Ir,
-                     c.g.nr, c.g.nz, seq, c.fin_dev);
+hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart, const double* Ir,
+                           const double* wall_add, uint64_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, tally, xpart, c.h, c.h_it, Ir,
+                     c.g.nr, c.g.nz, wall_add, c.wall_bot, seq, c.fin_dev);
   return hipGetLastError();
 }
 
@@ -567,7 +581,8 @@ hipError_t launch_guess_half(const Ctx& c, double vnow, double vnext, hipStream_
   const int64_t n = (int64_t)(c.g.nr + 1) * (c.g.nz + 1);
   hipLaunchKernelGGL(k_guess_half, dim3(nblk(n)), dim3(kBlock), 0, s, c.m, c.ur, c.uz, c.ur_prev,
                      c.uz_prev, c.ur_it, c.uz_it, c.ur_half, c.uz_half, c.ur_half_f, c.uz_half_f,
-                     c.Ir, c.Iz, vnow, vnext, c.stop, c.qcount, c.tally);
+                     c.Ir, c.Iz, vnow, vnext, c.stop, c.qcount, tally_set(c, 0),
+                     wall_scratch(c, 0), wall_len(c));
   return hipGetLastError();
 }
 

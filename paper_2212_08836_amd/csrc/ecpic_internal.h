@@ -100,6 +100,8 @@ struct PushArgs {
   double* Ir;
   double* Iz;
   SpecDev s;
+  SpecDev out;       // where a commit writes the new state (s itself, or the
+                     // species' other buffer); ids are copied when it differs
   int32_t commit;
   double* wall_bot;
   double* wall_top;
@@ -201,7 +203,10 @@ struct Ctx {
   int32_t* hist;                   // per-cell counts [nr*nz + 1]
   int32_t* offs;                   // per-cell offsets [nr*nz + 1]
   int32_t* scan_part;              // scan block sums
-  Tally* tally;                    // device tallies, kSpread copies
+  Tally* tally;                    // device tallies: two sets of kSpread copies,
+                                   // used by Picard iterations of either parity
+  double* wall_scr = nullptr;      // wall charge of a committing iteration, by
+                                   // parity: 2 x [bot nr+1, top nr+1, side nz+1]
   int32_t* queue = nullptr;        // slow-pass particle queues, one per species,
                                    // then as many collision lists
   int64_t queue_cap = 0;           // entries per species and kind
@@ -281,8 +286,14 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s);
 // when *stop is already set.
 hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s);
 // commit summary into fin_dev (host memory), seq written last
-hipError_t launch_finalize(const Ctx& c, const double* xpart, const double* Ir, uint64_t seq,
-                           hipStream_t s);
+// tally set (kSpread copies) and wall scratch of iterations of parity p
+inline Tally* tally_set(const Ctx& c, int p) { return c.tally + (int64_t)p * kSpread; }
+inline int64_t wall_len(const Ctx& c) { return 2 * (int64_t)(c.g.nr + 1) + c.g.nz + 1; }
+inline double* wall_scratch(const Ctx& c, int p) { return c.wall_scr + p * wall_len(c); }
+// commit summary from the tally set `tally`; when wall_add is set, that
+// wall-charge scratch is also added into the wall totals
+hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart, const double* Ir,
+                           const double* wall_add, uint64_t seq, hipStream_t s);
 hipError_t launch_zero_tally(const Ctx& c, hipStream_t s);
 // the value a residual slot holds until the device has written it
 constexpr uint64_t kResPending = 0x7ff4dead0badf00dull;

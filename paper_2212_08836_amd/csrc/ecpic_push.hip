@@ -940,9 +940,11 @@ __device__ void tl_flush(const Tl& t, Tally* tally, int sid) {
 template <typename T>
 __device__ void commit_one(const PushArgs& A, int64_t k, PState<T>& p, int status, int wall,
                            Tl& t) {
-  const SpecDev& s = A.s;
+  const SpecDev& s = A.out;
   const MapP& m = A.m;
   const double qw = s.q * s.w;
+  const uint64_t uid = A.s.uid[k];
+  if (s.uid != A.s.uid) s.uid[k] = uid;
   if (status == kError) t.err += 1;
   if (status == kAbsorbed) {
     kill_particle<T>(s, k);
@@ -960,7 +962,7 @@ __device__ void commit_one(const PushArgs& A, int64_t k, PState<T>& p, int statu
   }
   if (A.mcc.enabled) {
     double vr = p.vr, vt = p.vt, vz = p.vz;
-    const CollOut co = collide_one<T>(A.mcc, s, m, s.sid, s.uid[k], p.i, p.j, p.a, p.b, vr, vt, vz,
+    const CollOut co = collide_one<T>(A.mcc, s, m, s.sid, uid, p.i, p.j, p.a, p.b, vr, vt, vz,
                                       A.tally);
     t.dke_coll += co.dke;
     t.coll += co.coll;
@@ -1058,10 +1060,12 @@ __device__ __forceinline__ void tile_deposit(const Tile& t, double* Ir, double* 
 // draw collide_one makes first).
 template <typename T>
 __device__ __forceinline__ bool commit_store(const PushArgs& A, int64_t k, const PState<T>& p) {
-  store_particle<T>(A.s, A.m, k, p);
+  const uint64_t uid = A.s.uid[k];
+  store_particle<T>(A.out, A.m, k, p);
+  if (A.out.uid != A.s.uid) A.out.uid[k] = uid;
   if (!A.mcc.enabled) return false;
   double u[4];
-  draws(A.mcc.seed, A.s.sid, A.s.uid[k], A.mcc.step, 0, u);
+  draws(A.mcc.seed, A.s.sid, uid, A.mcc.step, 0, u);
   return u[0] < A.mcc.pnull;
 }
 
@@ -1199,6 +1203,8 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
       // draw selects go to the collision list (k_collide_list)
       bool coll = false;
       if (alive && !slow) coll = commit_store<T>(A, k, p);
+      // into the other buffer: dead slots stay dead there
+      if (k < s.n && !alive && A.out.uid != A.s.uid) kill_particle<T>(A.out, k);
       const uint64_t cm = __ballot(coll);
       if (cm) {
         int wb = 0;
@@ -1313,7 +1319,7 @@ __global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
   const int32_t* qcount = second ? P.cqcount[1] : P.cqcount[0];
   const int64_t qseg = second ? P.qseg[1] : P.qseg[0];
   const MapP& m = A.m;
-  const SpecDev& s = A.s;
+  const SpecDev& s = A.out;  // the pushed state, where the commit stored it
   const int g = blockIdx.y;
   const int64_t nq = qcount[g * kLineInts];
   const int32_t* seg = queue + (int64_t)g * qseg;
