@@ -397,7 +397,6 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
                (double)c.sp[s].n;
       parts += c.sp[s].n;
     }
-    P.nb0 = fast_blocks(P.a[0].s.n);
     {
       const int kind = !commit ? ECPIC_K_PUSH : (to_other ? ECPIC_K_PUSH_COMMIT : ECPIC_K_COMMIT);
       Timed tm(c, kind, bytes, parts);
@@ -1075,7 +1074,9 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     for (k = 0; k < kmax; ++k) {
       Roles after_k;
       save(after_k);
-      const bool ahead = k + 1 < kmax;
+      // the next iteration goes in ahead, unless this one is expected to be
+      // the last (then it is enqueued only if the residual says otherwise)
+      const bool ahead = k + 1 < kmax && !committed[k];
       if (ahead) {
         // the next push uses (u^n + u^{n+1,(k+1)}) / 2
         swap_half(c);
@@ -1105,6 +1106,11 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
         break;
       }
       prev_r = r;
+      if (!ahead && k + 1 < kmax) {
+        swap_half(c);
+        ecpic_status rc = enqueue_iteration(k + 1);
+        if (rc != ECPIC_OK) return rc;
+      }
     }
     if (!restart) break;
     // back to the extrapolated guess: drain the iteration enqueued ahead,

@@ -113,9 +113,9 @@ struct PushArgs {
 };
 
 // One push pass over up to two species in one launch (slot 0 and slot 1):
-// the fast kernel gives blocks [0, nb0) to slot 0 and the rest to slot 1;
-// the slow kernel takes the slot from blockIdx.z.  Both slots share the
-// pass-wide members of a[0] (fields, currents, walls, tallies, stop, commit).
+// the fast kernel takes the slot from blockIdx.y, the slow and collision
+// kernels from blockIdx.z.  Both slots share the pass-wide members of a[0]
+// (fields, currents, walls, tallies, stop, commit).
 struct PassArgs {
   PushArgs a[2];
   int32_t* queue[2];   // kSpread segments of qseg entries per slot
@@ -123,7 +123,6 @@ struct PassArgs {
   int32_t* cqueue[2];  // the same for the collision list of a commit pass
   int32_t* cqcount[2];
   int64_t qseg[2];
-  int64_t nb0;         // blocks of slot 0 in the fast kernel
   int32_t nsp;         // slots in use (1 or 2)
 };
 

@@ -1075,7 +1075,7 @@ __device__ __forceinline__ bool commit_store(const PushArgs& A, int64_t k, const
 // the block's LDS tile and flushed once per block.  The others are queued
 // for k_push_slow.  A block takes kPerThread particles per thread,
 // consecutive in memory (sorted by cell after a sort), strided by kBlock.
-// Blocks [0, nb0) serve species slot 0 of the pass, the rest slot 1.
+// Grid (blocks of the larger slot, slots): blockIdx.y is the species slot.
 // Dynamic LDS: tile_r_len(nz) + tile_z_len(nz) doubles.
 template <typename T, bool COMMIT, bool DEPOSIT>
 __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
@@ -1084,15 +1084,18 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   __shared__ int32_t slow_list[kPerBlock];
   __shared__ int32_t coll_list[COMMIT ? kPerBlock : 1];
   __shared__ int slow_n, gbase, coll_n, cbase;
-  const bool second = (int64_t)blockIdx.x >= P.nb0;
-  const PushArgs& A = second ? P.a[1] : P.a[0];
-  int32_t* queue = second ? P.queue[1] : P.queue[0];
-  int32_t* qcount = second ? P.qcount[1] : P.qcount[0];
-  int32_t* cqueue = second ? P.cqueue[1] : P.cqueue[0];
-  int32_t* cqcount = second ? P.cqcount[1] : P.cqcount[0];
-  const int64_t qseg = second ? P.qseg[1] : P.qseg[0];
-  const int64_t bx = second ? (int64_t)blockIdx.x - P.nb0 : (int64_t)blockIdx.x;
+  // the species slot indexes the arguments directly (a select between the
+  // slots' fields would keep both sets in scalar registers)
+  const int slot = blockIdx.y;
+  const PushArgs& A = P.a[slot];
+  const int64_t bx = blockIdx.x;
   const int64_t k_first = bx * kPerBlock;
+  if (k_first >= A.s.n) return;  // the grid covers the larger slot
+  int32_t* queue = P.queue[slot];
+  int32_t* qcount = P.qcount[slot];
+  int32_t* cqueue = P.cqueue[slot];
+  int32_t* cqcount = P.cqcount[slot];
+  const int64_t qseg = P.qseg[slot];
   const MapP& m = A.m;
   const SpecDev& s = A.s;
   const T qm = T(s.q / s.m);
@@ -1253,11 +1256,11 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
 template <typename T, bool COMMIT>
 __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
   if (P.a[0].stop && *P.a[0].stop) return;
-  const bool second = blockIdx.z > 0;
-  const PushArgs& A = second ? P.a[1] : P.a[0];
-  const int32_t* queue = second ? P.queue[1] : P.queue[0];
-  const int32_t* qcount = second ? P.qcount[1] : P.qcount[0];
-  const int64_t qseg = second ? P.qseg[1] : P.qseg[0];
+  const int slot = blockIdx.z;
+  const PushArgs& A = P.a[slot];
+  const int32_t* queue = P.queue[slot];
+  const int32_t* qcount = P.qcount[slot];
+  const int64_t qseg = P.qseg[slot];
   const MapP& m = A.m;
   const SpecDev& s = A.s;
   const T qm = T(s.q / s.m);
@@ -1313,11 +1316,11 @@ __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
 // pass.  Particles born here are appended beyond the pass's start counts.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
-  const bool second = blockIdx.z > 0;
-  const PushArgs& A = second ? P.a[1] : P.a[0];
-  const int32_t* queue = second ? P.cqueue[1] : P.cqueue[0];
-  const int32_t* qcount = second ? P.cqcount[1] : P.cqcount[0];
-  const int64_t qseg = second ? P.qseg[1] : P.qseg[0];
+  const int slot = blockIdx.z;
+  const PushArgs& A = P.a[slot];
+  const int32_t* queue = P.cqueue[slot];
+  const int32_t* qcount = P.cqcount[slot];
+  const int64_t qseg = P.qseg[slot];
   const MapP& m = A.m;
   const SpecDev& s = A.out;  // the pushed state, where the commit stored it
   const int g = blockIdx.y;
@@ -1484,14 +1487,15 @@ size_t fast_lds_bytes(int nz) {
 }
 
 hipError_t launch_push_fast(const PassArgs& P, bool deposit, hipStream_t st) {
-  const int64_t nb = P.nb0 + (P.nsp > 1 ? fast_blocks(P.a[1].s.n) : 0);
+  int64_t nb = 0;
+  for (int q = 0; q < P.nsp; ++q) nb = fast_blocks(P.a[q].s.n) > nb ? fast_blocks(P.a[q].s.n) : nb;
   if (nb <= 0) return hipSuccess;
   const size_t lds = deposit ? fast_lds_bytes(P.a[0].m.nz) : 0;
   if (lds > 56 * 1024) return hipErrorInvalidValue;
   const bool mixed = (P.a[0].s.cell != nullptr);
   const bool commit = P.a[0].commit != 0;
   if (!commit && !deposit) return hipErrorInvalidValue;
-  const dim3 g(nb), b(kBlock);
+  const dim3 g((unsigned)nb, (unsigned)P.nsp), b(kBlock);
   if (!mixed) {
     if (!commit)
       hipLaunchKernelGGL((k_push_fast<double, false, true>), g, b, lds, st, P);
