@@ -5,18 +5,19 @@
 // h^{n+1/2} of the form T (x) I + G (x) N, where N is the Neumann second
 // difference in z (the PEC r-edges of the z walls decouple the end cells).
 // Three kernels solve it:
-//   k_rhs_dct      one block per radial row: the right-hand side of the row
-//                  into LDS, then its orthonormal DCT-II (precomputed FP64
-//                  matrix, L2-resident), written mode-major;
+//   k_rhs_dct      one block per group of radial rows: the right-hand side of
+//                  the rows into LDS, then their orthonormal DCT-II
+//                  (precomputed FP64 matrix, L2-resident), written mode-major;
 //   k_tri_scan     one block per z-mode: the tridiagonal system in r with
 //                  precomputed LU factors, forward and backward substitution
 //                  done as parallel scans of affine maps (the recurrences
 //                  y_i = d_i - l_i y_{i-1}, x_i = (y_i - e_{i+1} x_{i+1}) / c_i
 //                  compose associatively);
-//   k_idct_recover one block per row: inverse DCT of rows i and i-1, the edge
-//                  voltages from Ampere's law, h^{n+1}, the next half-step
-//                  field, per-row partial sums of the Picard residual, and the
-//                  reset of the consumed currents.
+//   k_idct_recover one block per group of rows: inverse DCT of the rows and of
+//                  the row below them, the edge voltages from Ampere's law,
+//                  h^{n+1}, the next half-step field, per-block partial sums of
+//                  the Picard residual, and the reset of the consumed currents.
+// Grouping rows lets each load of the transform matrix feed several rows.
 #include "ecpic_internal.h"
 
 namespace ecpic {
@@ -25,8 +26,66 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kFB = 256;  // threads per block of the field kernels
+constexpr int kRB = 4;    // radial rows per block of the transform kernels
 
 inline int64_t nblk(int64_t n) { return (n + kBlock - 1) / kBlock; }
+inline int row_blocks(int nr) { return (nr + kRB - 1) / kRB; }
+
+// Row-blocked dense transform shared by both directions:
+//   out[r][k] = sum_j M[j][k] in[r][j]   for kRB rows of `in` (LDS, stride nz)
+// with M row-major nz x nz.  With P = kFB / nz parts (1 when nz >= kFB) the
+// thread (k, p) sums j over the p-th part; the parts land in psum[p][r][k]
+// and are added in part order (deterministic).  Independent loads of M are
+// issued ahead in groups of kUnroll.
+constexpr int kUnroll = 8;
+__host__ __device__ __forceinline__ int dct_parts(int nz) { return nz >= kFB ? 1 : kFB / nz; }
+
+template <int R>
+__device__ __forceinline__ void dense_rows(const double* __restrict__ M,
+                                           const double* __restrict__ in, int nz,
+                                           double* __restrict__ psum) {
+  const int P = dct_parts(nz);
+  for (int t = threadIdx.x; t < nz * P; t += blockDim.x) {
+    const int p = t / nz, k = t - p * nz;
+    const int j0 = p * nz / P, j1 = (p + 1) * nz / P;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    const double* q = M + k;
+    int j = j0;
+    for (; j + kUnroll <= j1; j += kUnroll) {
+      double qv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) qv[u] = q[(int64_t)(j + u) * nz];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = fma(in[r * nz + j + u], qv[u], acc[r]);
+    }
+    for (; j < j1; ++j) {
+      const double qv = q[(int64_t)j * nz];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = fma(in[r * nz + j], qv, acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) psum[(p * R + r) * nz + k] = acc[r];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void dct_rows(const double* __restrict__ Qt,
+                                         const double* __restrict__ in, int nz,
+                                         double* __restrict__ psum) {
+  dense_rows<kRB>(Qt, in, nz, psum);
+}
+
+__device__ __forceinline__ double psum_total(const double* __restrict__ psum, int nz, int r, int k,
+                                             int R = kRB) {
+  const int P = dct_parts(nz);
+  double v = psum[r * nz + k];
+  for (int p = 1; p < P; ++p) v += psum[(p * R + r) * nz + k];
+  return v;
+}
 
 // rhs[i][j] = 2 pi r_{i+1/2} (2 mu A_c / dt h0 + circulation of u0 - D^-1 I)
 // with the half-step drive value on the gap edge and zero on other walls,
@@ -44,17 +103,19 @@ __global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restric
                                                  double* __restrict__ hat,
                                                  const int32_t* __restrict__ stop) {
   if (stop && *stop) return;
-  extern __shared__ double sh[];
+  extern __shared__ double sh[];  // kRB rows of the right-hand side, then the part sums
   const int nr = m.nr, nz = m.nz;
-  const int i = blockIdx.x;
+  const int i0 = blockIdx.x * kRB;
+  const int rows = min(kRB, nr - i0);
   const double hdt = 0.5 * m.dt;
-  const double mi = 2.0 * kPi * rh[i];
-  const double mass = 2.0 * mu * area[i] / m.dt;
-  const double iwr = hdt / wr[i], iwz = hdt / wz[i];
-  const double iwz1 = (i + 1 < nr) ? hdt / wz[i + 1] : 0.0;
-  const double* urr = ur0 + (int64_t)i * (nz + 1);
-  const double* Irr = Ir + (int64_t)i * (nz + 1);
-  for (int j = threadIdx.x; j < nz; j += blockDim.x) {
+  for (int e = threadIdx.x; e < rows * nz; e += blockDim.x) {
+    const int r = e / nz, j = e - r * nz, i = i0 + r;
+    const double mi = 2.0 * kPi * rh[i];
+    const double mass = 2.0 * mu * area[i] / m.dt;
+    const double iwr = hdt / wr[i], iwz = hdt / wz[i];
+    const double iwz1 = (i + 1 < nr) ? hdt / wz[i + 1] : 0.0;
+    const double* urr = ur0 + (int64_t)i * (nz + 1);
+    const double* Irr = Ir + (int64_t)i * (nz + 1);
     // r-edges j (bottom) and j+1 (top) of cell (i, j)
     double rb, rt;
     if (j == 0)
@@ -69,14 +130,16 @@ __global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restric
     const int64_t el = (int64_t)i * nz + j;
     const double zl = uz0[el] - Iz[el] * iwz;
     const double zr = (i + 1 < nr) ? uz0[el + nz] - Iz[el + nz] * iwz1 : 0.0;
-    sh[j] = mi * (mass * h0[el] + (zr - zl - rt + rb));
+    sh[r * nz + j] = mi * (mass * h0[el] + (zr - zl - rt + rb));
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
-    double acc = 0.0;
-    const double* q = Qt + k;
-    for (int j = 0; j < nz; ++j) acc = fma(sh[j], q[(int64_t)j * nz], acc);
-    hat[(int64_t)k * nr + i] = acc;
+  // hat[k][i] = sum_j Qt[j][k] rhs[i][j]; each load of Qt feeds kRB rows,
+  // and the sum over j is cut into parts so that every thread has work
+  double* psum = sh + kRB * nz;
+  dct_rows(Qt, sh, nz, psum);
+  for (int e = threadIdx.x; e < nz * kRB; e += blockDim.x) {
+    const int k = e / kRB, r = e - k * kRB;
+    if (r < rows) hat[(int64_t)k * nr + i0 + r] = psum_total(psum, nz, r, k);
   }
 }
 
@@ -195,101 +258,99 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
                                                       const double* __restrict__ Q,
                                                       const double* __restrict__ hat) {
   if (a.stop && *a.stop) return;
+  constexpr int R1 = kRB + 1;  // rows i0 - 1 .. i0 + kRB - 1
   extern __shared__ double sh[];
   const int nr = m.nr, nz = m.nz;
-  const int i = blockIdx.x;
-  double* hi = sh;           // hat[.][i]
-  double* hm = sh + nz;      // hat[.][i-1]
-  double* xi_ = sh + 2 * nz; // x[i][.]
-  double* xm = sh + 3 * nz;  // x[i-1][.]
+  const int i0 = blockIdx.x * kRB;
+  const int rows = min(kRB, nr - i0);
+  double* hs = sh;            // hat of the R1 rows, [r][k]
+  double* xs = sh + R1 * nz;  // x of the R1 rows, [r][j]; row r is i0 - 1 + r
+  double* psum = sh + 2 * R1 * nz;
   __shared__ double red[2 * (kFB / 64)];
-  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
-    hi[k] = hat[(int64_t)k * nr + i];
-    hm[k] = (i > 0) ? hat[(int64_t)k * nr + i - 1] : 0.0;
+  for (int e = threadIdx.x; e < R1 * nz; e += blockDim.x) {
+    const int k = e / R1, r = e - k * R1, i = i0 - 1 + r;
+    hs[r * nz + k] = (i >= 0 && i < nr) ? hat[(int64_t)k * nr + i] : 0.0;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < nz; j += blockDim.x) {
-    double s = 0.0, t = 0.0;
-    for (int k = 0; k < nz; ++k) {
-      const double qv = Q[(int64_t)k * nz + j];
-      s = fma(hi[k], qv, s);
-      t = fma(hm[k], qv, t);
-    }
-    xi_[j] = s;
-    xm[j] = t;
+  dense_rows<R1>(Q, hs, nz, psum);
+  for (int e = threadIdx.x; e < R1 * nz; e += blockDim.x) {
+    const int r = e / nz, j = e - r * nz;
+    xs[e] = psum_total(psum, nz, r, j, R1);
   }
   __syncthreads();
   const double hdt = 0.5 * m.dt;
   const double two_pi = 2.0 * kPi;
   double s0 = 0.0, s1 = 0.0;
-  // r-edges of row i
-  {
-    const double w = wr[i], iw = hdt / w, ri = two_pi * rh[i];
-    for (int j = threadIdx.x; j <= nz; j += blockDim.x) {
-      const int64_t e = (int64_t)i * (nz + 1) + j;
-      double v;
-      if (j == 0) {
-        v = (i == nr - 1) ? a.vnext : 0.0;
-      } else if (j == nz) {
-        v = 0.0;
-      } else {
-        const double K = -ri * (xi_[j] - xi_[j - 1]);
-        const double uh = a.ur0[e] + (K - a.Ir[e]) * iw;
-        v = 2.0 * uh - a.ur0[e];
-        if (a.part) {
-          const double d = v - a.ur_old[e];
-          s0 += w * d * d;
-          s1 += w * v * v;
-        }
-      }
-      a.ur1[e] = v;
-      if (a.ur_h) {
-        const double hv = 0.5 * (a.ur0[e] + v);
-        a.ur_h[e] = hv;
-        if (a.ur_hf) a.ur_hf[e] = float(hv);
-      }
-      if (a.Ir_clr) a.Ir_clr[e] = 0.0;
-    }
-  }
-  // z-edges of row i (and the PEC row nr, owned by the last block)
-  {
-    const double w = wz[i], iw = hdt / w, ri = two_pi * rh[i];
-    const double rm = (i > 0) ? two_pi * rh[i - 1] : 0.0;
-    for (int j = threadIdx.x; j < nz; j += blockDim.x) {
-      const int64_t e = (int64_t)i * nz + j;
-      const double K = ri * xi_[j] - rm * xm[j];
-      const double uh = a.uz0[e] + (K - a.Iz[e]) * iw;
-      const double v = 2.0 * uh - a.uz0[e];
+  // r-edges of the rows
+  for (int e = threadIdx.x; e < rows * (nz + 1); e += blockDim.x) {
+    const int r = e / (nz + 1), j = e - r * (nz + 1), i = i0 + r;
+    const double* xi_ = xs + (r + 1) * nz;
+    const int64_t g = (int64_t)i * (nz + 1) + j;
+    double v;
+    if (j == 0) {
+      v = (i == nr - 1) ? a.vnext : 0.0;
+    } else if (j == nz) {
+      v = 0.0;
+    } else {
+      const double w = wr[i];
+      const double K = -two_pi * rh[i] * (xi_[j] - xi_[j - 1]);
+      const double uh = a.ur0[g] + (K - a.Ir[g]) * (hdt / w);
+      v = 2.0 * uh - a.ur0[g];
       if (a.part) {
-        const double d = v - a.uz_old[e];
+        const double d = v - a.ur_old[g];
         s0 += w * d * d;
         s1 += w * v * v;
       }
-      a.uz1[e] = v;
+    }
+    a.ur1[g] = v;
+    if (a.ur_h) {
+      const double hv = 0.5 * (a.ur0[g] + v);
+      a.ur_h[g] = hv;
+      if (a.ur_hf) a.ur_hf[g] = float(hv);
+    }
+    if (a.Ir_clr) a.Ir_clr[g] = 0.0;
+  }
+  // z-edges of the rows (and the PEC row nr, owned by the block of row nr - 1)
+  for (int e = threadIdx.x; e < rows * nz; e += blockDim.x) {
+    const int r = e / nz, j = e - r * nz, i = i0 + r;
+    const double* xi_ = xs + (r + 1) * nz;
+    const double* xm = xs + r * nz;
+    const double w = wz[i];
+    const double ri = two_pi * rh[i];
+    const double rm = (i > 0) ? two_pi * rh[i - 1] : 0.0;
+    const int64_t g = (int64_t)i * nz + j;
+    const double K = ri * xi_[j] - rm * xm[j];
+    const double uh = a.uz0[g] + (K - a.Iz[g]) * (hdt / w);
+    const double v = 2.0 * uh - a.uz0[g];
+    if (a.part) {
+      const double d = v - a.uz_old[g];
+      s0 += w * d * d;
+      s1 += w * v * v;
+    }
+    a.uz1[g] = v;
+    if (a.uz_h) {
+      const double hv = 0.5 * (a.uz0[g] + v);
+      a.uz_h[g] = hv;
+      if (a.uz_hf) a.uz_hf[g] = float(hv);
+    }
+    if (a.Iz_clr) a.Iz_clr[g] = 0.0;
+    a.h1[g] = 2.0 * xi_[j] - a.h0[g];
+    if (i == nr - 1) {
+      const int64_t ew = (int64_t)nr * nz + j;
+      a.uz1[ew] = 0.0;
       if (a.uz_h) {
-        const double hv = 0.5 * (a.uz0[e] + v);
-        a.uz_h[e] = hv;
-        if (a.uz_hf) a.uz_hf[e] = float(hv);
+        const double hv = 0.5 * a.uz0[ew];
+        a.uz_h[ew] = hv;
+        if (a.uz_hf) a.uz_hf[ew] = float(hv);
       }
-      if (a.Iz_clr) a.Iz_clr[e] = 0.0;
-      a.h1[e] = 2.0 * xi_[j] - a.h0[e];
-      if (i == nr - 1) {
-        const int64_t ew = (int64_t)nr * nz + j;
-        a.uz1[ew] = 0.0;
-        if (a.uz_h) {
-          const double hv = 0.5 * a.uz0[ew];
-          a.uz_h[ew] = hv;
-          if (a.uz_hf) a.uz_hf[ew] = float(hv);
-        }
-        if (a.Iz_clr) a.Iz_clr[ew] = 0.0;
-      }
+      if (a.Iz_clr) a.Iz_clr[ew] = 0.0;
     }
   }
   if (a.part) {
     block_sum2(s0, s1, red);
     if (threadIdx.x == 0) {
-      a.part[2 * i] = s0;
-      a.part[2 * i + 1] = s1;
+      a.part[2 * blockIdx.x] = s0;
+      a.part[2 * blockIdx.x + 1] = s1;
     }
   }
 }
@@ -458,11 +519,11 @@ __global__ void __launch_bounds__(kBlock) k_xsum(MapP m, const double* __restric
 }
 
 // Residual of a Picard iterate: r = sqrt(sum w (u1 - u_old)^2 / sum w u1^2)
-// over the interior edges, from the per-row partials of the solve: the first
-// wavefront sums rows l, l + 64, ... per lane and then combines the lanes in
+// over the interior edges, from the per-block partials of the solve: the first
+// wavefront sums blocks l, l + 64, ... per lane and then combines the lanes in
 // a fixed butterfly order (deterministic).  The other threads clear the pass
 // scratch for the next push.
-__global__ void __launch_bounds__(256) k_converge(const double* __restrict__ part, int nr, int k,
+__global__ void __launch_bounds__(256) k_converge(const double* __restrict__ part, int nparts, int k,
                                                   double tol, int32_t* stop, double* res,
                                                   int32_t* qcount, Tally* tally, double* wscr,
                                                   int64_t wlen) {
@@ -473,7 +534,7 @@ __global__ void __launch_bounds__(256) k_converge(const double* __restrict__ par
     return;
   }
   double num = 0.0, den = 0.0;
-  for (int i = t; i < nr; i += 64) {
+  for (int i = t; i < nparts; i += 64) {
     num += part[2 * i];
     den += part[2 * i + 1];
   }
@@ -559,7 +620,7 @@ hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s) {
   if (k < 0 || k >= kMaxIter) return hipErrorInvalidValue;
   // the next iteration (parity k+1) gets a cleared tally set and wall scratch
   const int np = (k + 1) & 1;
-  hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, c.sol.partial, c.g.nr,
+  hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, c.sol.partial, row_blocks(c.g.nr),
                      k, tol, c.stop, c.res_dev, c.qcount, tally_set(c, np),
                      wall_scratch(c, np), wall_len(c));
   return hipGetLastError();
@@ -598,12 +659,16 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s) {
   const int nr = c.g.nr, nz = c.g.nz;
   const SolverDev& S = c.sol;
   if (nr > kFB * kMaxE) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rhs_dct, dim3(nr), dim3(kFB), sizeof(double) * nz, s, c.m, S.rh, S.wr,
+  const int P = dct_parts(nz);
+  const size_t lds_rhs = sizeof(double) * (size_t)nz * (kRB + (size_t)P * kRB);
+  const size_t lds_rec = sizeof(double) * (size_t)nz * (2 * (kRB + 1) + (size_t)P * (kRB + 1));
+  if (lds_rec > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_rhs_dct, dim3(row_blocks(nr)), dim3(kFB), lds_rhs, s, c.m, S.rh, S.wr,
                      S.wz, S.area, c.g.mu, a.ur0, a.uz0, a.h0, a.Ir, a.Iz, a.vhalf, S.Qt, S.work1,
                      a.stop);
   hipLaunchKernelGGL(k_tri_scan, dim3(nz), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv, S.tri_up,
                      S.work1, a.stop);
-  hipLaunchKernelGGL(k_idct_recover, dim3(nr), dim3(kFB), sizeof(double) * 4 * nz, s, a, c.m,
+  hipLaunchKernelGGL(k_idct_recover, dim3(row_blocks(nr)), dim3(kFB), lds_rec, s, a, c.m,
                      S.rh, S.wr, S.wz, S.Q, S.work1);
   return hipGetLastError();
 }
