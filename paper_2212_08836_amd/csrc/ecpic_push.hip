@@ -47,6 +47,21 @@ struct Mid {
   T kr, kz;            // solve_fast only: vr - v_r, vz - v_z (the kicks)
 };
 
+// 1/x from the hardware reciprocal estimate refined by Newton steps
+// (y <- y + y (1 - x y)): two in FP64, one in FP32, which leaves the result
+// within an ulp or two of the rounded quotient for the positive, normal x
+// the in-cell solve passes (a fraction of the cost of an IEEE division).
+__device__ __forceinline__ double rcp_refined(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ float rcp_refined(float x) {
+  const float y = __builtin_amdgcn_rcpf(x);
+  return fmaf(y, fmaf(-x, y, 1.0f), y);
+}
+
 template <typename T>
 __device__ __forceinline__ T clamp01(T x) {
   return x < T(0) ? T(0) : (x > T(1) ? T(1) : x);
@@ -186,35 +201,43 @@ __device__ __forceinline__ bool solve_fast(const MapP& m, const T F[4], const PS
   const T Kr = alpha * gamma * dFr;
   const T den = T(1) - Kr * Kz;
   if (!(den > T(0))) return false;
-  const T inv_den = T(1) / den;
+  const T inv_den = rcp_refined(den);
   const T bz = beta * Ez;
   const T k0 = (alpha * Er + Kr * (p.vz + bz + Kz * p.vr)) * inv_den;
   const T cc = hd * inv_den;
   const T r0 = T(m.s * (double(p.i) + m.xi_a)) + T(m.s) * p.a;
+  if (!(r0 > T(0))) return false;
   const T vt2 = p.vt * p.vt;
-  T kr = k0 + cc * vt2 / r0;  // centrifugal term at the start position
-  T rb = r0, re = r0;
+  const T c2 = cc * vt2;
+  T kr = k0 + c2 * rcp_refined(r0);  // centrifugal term at the start position
+  // g(kr) = k0 + c2 rb / re^2 is a contraction with slope
+  // g' = c2 (hd - 2 dtau rb / re) / re^2; for |g'| < 1/2 the iterate g(kr)
+  // is within 2 |g'| |g(kr) - kr| of the fixed point, which is the stopping
+  // test (the bare step |g(kr) - kr| otherwise)
   for (int it = 0; it < 12; ++it) {
     const T vr = p.vr + kr;
-    rb = r0 + hd * vr;
-    re = r0 + dtau * vr;
+    const T rb = r0 + hd * vr;
+    const T re = r0 + dtau * vr;
     if (!(rb > T(0) && re > T(0))) return false;
-    const T ire = T(1) / re;
-    const T nkr = k0 + cc * vt2 * rb * ire * ire;
+    const T ire = rcp_refined(re);
+    const T g = c2 * ire * ire;
+    const T nkr = k0 + g * rb;
+    const T slope = fabs(g * (hd - T(2) * dtau * rb * ire));
     const T d = fabs(nkr - kr);
     kr = nkr;
     const T kz = bz + Kz * (p.vr + kr);
     const T scale = fabs(p.vr + kr) + fabs(p.vt * rb * ire) + fabs(p.vz + kz);
-    if (d <= Tol<T>::v() * scale) {
+    const T err = slope < T(0.5) ? T(2) * slope * d : d;
+    if (err <= Tol<T>::v() * scale) {
       const T vrb = p.vr + kr;
-      rb = r0 + hd * vrb;
-      re = r0 + dtau * vrb;
-      if (!(re > T(0))) return false;
+      const T rb1 = r0 + hd * vrb;
+      const T re1 = r0 + dtau * vrb;
+      if (!(re1 > T(0))) return false;
       M.kr = kr;
       M.kz = kz;
       M.vr = vrb;
       M.vz = p.vz + kz;
-      M.vt = p.vt * rb / re;
+      M.vt = p.vt * rb1 * rcp_refined(re1);
       M.a = p.a + delta * vrb;
       M.b = p.b + gamma * M.vz;
       return true;
@@ -523,41 +546,6 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront segmented reduction of the first sub-step deposits (keyed by
-// cell) and one atomic per run of equal keys.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double shfl_up_d(double v, int off) {
-  return __shfl_up(v, off, 64);
-}
-
-__device__ void wave_deposit(double* Ir, double* Iz, int nz, int key, int i, int j, Dep d) {
-  const int lane = threadIdx.x & 63;
-  const int prev_key = __shfl_up(key, 1, 64);
-  const bool head = (lane == 0) || (prev_key != key);
-  // start lane of my run: inclusive max-scan of head ? lane : 0
-  int start = head ? lane : 0;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int o = __shfl_up(start, off, 64);
-    if (lane >= off && o > start) start = o;
-  }
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const double r0 = shfl_up_d(d.r0, off), r1 = shfl_up_d(d.r1, off);
-    const double z0 = shfl_up_d(d.z0, off), z1 = shfl_up_d(d.z1, off);
-    if (lane - off >= start) {
-      d.r0 += r0;
-      d.r1 += r1;
-      d.z0 += z0;
-      d.z1 += z1;
-    }
-  }
-  const int next_key = __shfl_down(key, 1, 64);
-  const bool tail = (lane == 63) || (next_key != key);
-  if (tail && key >= 0) atomic_dep(Ir, Iz, nz, i, j, d);
-}
-
-// ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC'11) and the null-collision step
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void philox(uint64_t c[4], uint64_t k0, uint64_t k1) {
@@ -814,6 +802,62 @@ __device__ __forceinline__ bool load_particle<float>(const SpecDev& s, const Map
   return true;
 }
 
+// The stored record of a particle, fetched ahead of its decoding so that a
+// loop can have the next particle's loads in flight while it works on the
+// current one.
+template <typename T>
+struct Raw;
+template <>
+struct Raw<double> {
+  double xi, eta, vr, vt, vz;
+};
+template <>
+struct Raw<float> {
+  int32_t cell;
+  float a, b, vr, vt, vz;
+};
+__device__ __forceinline__ void fetch_raw(const SpecDev& s, int64_t k, Raw<double>& q) {
+  q.xi = s.xi[k];
+  q.eta = s.eta[k];
+  q.vr = s.vr[k];
+  q.vt = s.vt[k];
+  q.vz = s.vz[k];
+}
+__device__ __forceinline__ void fetch_raw(const SpecDev& s, int64_t k, Raw<float>& q) {
+  q.cell = s.cell[k];
+  q.a = s.fa[k];
+  q.b = s.fb[k];
+  q.vr = s.fvr[k];
+  q.vt = s.fvt[k];
+  q.vz = s.fvz[k];
+}
+// same decoding as load_particle
+__device__ __forceinline__ bool decode_raw(const MapP& m, const Raw<double>& q, PState<double>& p) {
+  p.vr = q.vr;
+  p.vt = q.vt;
+  p.vz = q.vz;
+  if (!(q.xi >= 0.0)) return false;
+  int i = int(floor(q.xi)), j = int(floor(q.eta));
+  i = i < 0 ? 0 : (i > m.nr - 1 ? m.nr - 1 : i);
+  j = j < 0 ? 0 : (j > m.nz - 1 ? m.nz - 1 : j);
+  p.i = i;
+  p.j = j;
+  p.a = q.xi - double(i);
+  p.b = q.eta - double(j);
+  return true;
+}
+__device__ __forceinline__ bool decode_raw(const MapP& m, const Raw<float>& q, PState<float>& p) {
+  p.a = q.a;
+  p.b = q.b;
+  p.vr = q.vr;
+  p.vt = q.vt;
+  p.vz = q.vz;
+  if (q.cell < 0) return false;
+  p.i = q.cell / m.nz;
+  p.j = q.cell - p.i * m.nz;
+  return true;
+}
+
 // cell key i * nz + j of particle k, or -1 if it is dead
 template <typename T>
 __device__ __forceinline__ int particle_cell(const SpecDev& s, const MapP& m, int64_t k);
@@ -990,17 +1034,6 @@ __device__ __forceinline__ double dpp_take(double v) {
   return __hiloint2double(h2, l2);
 }
 
-// inclusive wavefront scan; lane 63 ends with the sum of all 64 lanes
-__device__ __forceinline__ double wave_scan_add(double v) {
-  v += dpp_take<0x111, 0xF>(v);  // row_shr:1
-  v += dpp_take<0x112, 0xF>(v);  // row_shr:2
-  v += dpp_take<0x114, 0xF>(v);  // row_shr:4
-  v += dpp_take<0x118, 0xF>(v);  // row_shr:8
-  v += dpp_take<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_take<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  return v;
-}
-
 // A block's currents are gathered in LDS over the cells [c_lo, c_lo + W):
 // r-edges i*(nz+1)+j of those cells and their j+1 neighbours at TR[e - er0]
 // (er0 = c_lo + c_lo / nz), z-edges i*nz+j and the (i+1) neighbours at
@@ -1018,35 +1051,61 @@ __host__ __device__ inline int tile_r_len(int nz) {
 }
 __host__ __device__ inline int tile_z_len(int nz) { return tile_cells(nz) + nz; }
 
-// Deposit of one particle per lane.  The cell of the first in-tile lane is
-// the wavefront's majority cell in sorted order: its lanes are summed with
-// DPP and added to the tile once; other in-tile lanes add with LDS atomics,
-// out-of-tile lanes with global atomics.  Called by all 64 lanes.
+// Sum over the lanes of `mem` of the four edge increments of cell k0 (row
+// i0), added to the tile.  A transposing reduction: lane pairs swap halves of
+// their values so that each step adds fewer of them; after the two quad
+// steps lane l holds component l % 4 of its quad, and two row shifts leave
+// the row totals in lanes 12..15 of each row of 16, which add them to the
+// tile.  Called by all 64 lanes with uniform k0, i0.
+__device__ __forceinline__ void tile_group_add(const Tile& t, int nz, int k0, int i0, bool mem,
+                                               const Dep& d) {
+  const double r0 = mem ? d.r0 : 0.0, r1 = mem ? d.r1 : 0.0;
+  const double z0 = mem ? d.z0 : 0.0, z1 = mem ? d.z1 : 0.0;
+  const int lane = threadIdx.x & 63;
+  // lanes l, l^1 (quad_perm 1,0,3,2): even lanes keep the r pair, odd the z pair
+  const bool odd = lane & 1;
+  const double a0 = (odd ? z0 : r0) + dpp_take<0xB1, 0xF>(odd ? r0 : z0);
+  const double a1 = (odd ? z1 : r1) + dpp_take<0xB1, 0xF>(odd ? r1 : z1);
+  // lanes l, l^2 (quad_perm 2,3,0,1): lane l % 4 = 0, 1, 2, 3 keeps r0, z0, r1, z1
+  const bool hi = lane & 2;
+  double v = (hi ? a1 : a0) + dpp_take<0x4E, 0xF>(hi ? a0 : a1);
+  v += dpp_take<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_take<0x118, 0xF>(v);  // row_shr:8
+  if ((lane & 15) >= 12 && v != 0.0) {
+    const int er = k0 + i0 - t.er0;  // i0 * (nz + 1) + j0
+    const int ez = k0 - t.c_lo;
+    const int c = lane & 3;
+    double* dst = c == 0 ? &t.TR[er] : c == 1 ? &t.TZ[ez] : c == 2 ? &t.TR[er + 1] : &t.TZ[ez + nz];
+    atomicAdd(dst, v);
+  }
+}
+
+// Deposit of one particle per lane.  In cell-sorted order a wavefront's
+// particles fall in few cells: the lanes of the first in-tile lane's cell
+// are summed by tile_group_add, and so is the next cell's group while the
+// groups are large (one LDS atomic per lane would serialise on the shared
+// addresses); lanes left over add with LDS atomics, out-of-tile lanes with
+// global atomics.  Called by all 64 lanes.
 __device__ __forceinline__ void tile_deposit(const Tile& t, double* Ir, double* Iz, int nz, int key,
                                              int i, int j, const Dep& d) {
+  constexpr int kGroups = 3;     // at most this many summed groups
+  constexpr int kMinGroup = 8;   // smaller groups use LDS atomics
   const bool in = key >= t.c_lo && key < t.c_lo + t.W;
   if (key >= 0 && !in) atomic_dep(Ir, Iz, nz, i, j, d);
-  const uint64_t m_in = __ballot(in);
-  if (m_in == 0) return;
-  const int lead = __ffsll((unsigned long long)m_in) - 1;
-  const int k0 = __shfl(key, lead, 64);
-  const bool mem = in && key == k0;
-  const double r0 = wave_scan_add(mem ? d.r0 : 0.0);
-  const double r1 = wave_scan_add(mem ? d.r1 : 0.0);
-  const double z0 = wave_scan_add(mem ? d.z0 : 0.0);
-  const double z1 = wave_scan_add(mem ? d.z1 : 0.0);
-  const int lane = threadIdx.x & 63;
-  if (lane == 63) {
-    const int i0 = k0 / nz, j0 = k0 - i0 * nz;
-    const int er = i0 * (nz + 1) + j0 - t.er0;
-    const int ez = k0 - t.c_lo;
-    atomicAdd(&t.TR[er], r0);
-    atomicAdd(&t.TR[er + 1], r1);
-    atomicAdd(&t.TZ[ez], z0);
-    atomicAdd(&t.TZ[ez + nz], z1);
+  uint64_t pending = __ballot(in);
+  const uint64_t me = 1ull << (threadIdx.x & 63);
+  for (int g = 0; g < kGroups && pending; ++g) {
+    const int lead = __ffsll((unsigned long long)pending) - 1;
+    const int k0 = __builtin_amdgcn_readlane(key, lead);
+    const int i0 = __builtin_amdgcn_readlane(i, lead);
+    const bool mem = (pending & me) && key == k0;
+    const uint64_t mm = __ballot(mem);
+    if (__popcll(mm) < kMinGroup) break;
+    tile_group_add(t, nz, k0, i0, mem, d);
+    pending &= ~mm;
   }
-  if (in && !mem) {
-    const int er = i * (nz + 1) + j - t.er0;
+  if (pending & me) {
+    const int er = key + i - t.er0;
     const int ez = key - t.c_lo;
     atomicAdd(&t.TR[er], d.r0);
     atomicAdd(&t.TR[er + 1], d.r1);
@@ -1126,14 +1185,17 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   Tl t;
   tl_zero(t);
   const int lane = threadIdx.x & 63;
+  Raw<T> cur, nxt;
+  fetch_raw(s, min(k_first + (int64_t)threadIdx.x, s.n - 1), cur);
   for (int r = 0; r < kPerThread; ++r) {
     const int64_t k = k_first + (int64_t)r * kBlock + threadIdx.x;
     PState<T> p;
     bool alive = false;
-    if (k < s.n) alive = load_particle<T>(s, m, k, p);
+    if (k < s.n) alive = decode_raw(m, cur, p);
     bool slow = false;
     int key = -1;
     Dep dp{0.0, 0.0, 0.0, 0.0};
+    T F[4];
     if (alive) {
       // on a face, the cell the motion goes to
       if (p.a == T(1) && p.vr >= T(0) && p.i < m.nr - 1) {
@@ -1150,8 +1212,15 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
         p.j -= 1;
         p.b = T(1);
       }
-      T F[4];
       load_field(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), p.i, p.j, F);
+    }
+    // the next particle's record, issued after this one's field gather; the
+    // index is selected (the same particle again in the last round, cached)
+    // and clamped (k_first < n) rather than the load skipped, so that no
+    // branch joins the loads' results and the gather's wait leaves them in
+    // flight
+    fetch_raw(s, min(r + 1 < kPerThread ? k + kBlock : k, s.n - 1), nxt);
+    if (alive) {
       Mid<T> M;
       slow = true;
       if (p.i >= m.i_lin && solve_fast(m, F, p, T(m.dt), qm, M)) {
@@ -1216,6 +1285,7 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
         if (coll) coll_list[wb + __popcll(cm & ((1ull << lane) - 1ull))] = (int32_t)k;
       }
     }
+    cur = nxt;
   }
   __syncthreads();
   // flush the tile: one global atomic per touched edge
@@ -1251,8 +1321,12 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
 
 // Slow pass over the queued particles: the full push with splitting at every
 // face crossing (restarted from the particle's state), currents by atomics.
-// grid (X, kSpread, species slots): blocks with blockIdx.y = g walk segment g
-// of the queue of slot blockIdx.z
+// grid (kSpread, X, species slots): blocks with blockIdx.x = g walk segment g
+// of the queue of slot blockIdx.z.  Blocks are dispatched in grid order, so
+// with the segment index fastest the blocks that have work (low blockIdx.y)
+// all start first instead of queueing behind idle ones.  The first queue
+// entry is read before the segment count is known (within the segment's
+// capacity), so the two loads overlap.
 template <typename T, bool COMMIT>
 __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
   if (P.a[0].stop && *P.a[0].stop) return;
@@ -1265,14 +1339,16 @@ __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
   const SpecDev& s = A.s;
   const T qm = T(s.q / s.m);
   const double qw_dt = s.q * s.w / m.dt;
-  const int g = blockIdx.y;
-  const int64_t nq = qcount[g * kLineInts];
+  const int g = blockIdx.x;
   const int32_t* seg = queue + (int64_t)g * qseg;
+  int64_t q = (int64_t)blockIdx.y * kBlock + threadIdx.x;
+  int32_t k_next = q < qseg ? seg[q] : 0;
+  const int64_t nq = qcount[g * kLineInts];
   Tl t;
   tl_zero(t);
-  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nq;
-       q += (int64_t)gridDim.x * kBlock) {
-    const int64_t k = seg[q];
+  for (; q < nq; q += (int64_t)gridDim.y * kBlock) {
+    const int64_t k = k_next;
+    if (q + (int64_t)gridDim.y * kBlock < nq) k_next = seg[q + (int64_t)gridDim.y * kBlock];
     PState<T> p;
     if (!load_particle<T>(s, m, k, p)) continue;
     PushOut o;
@@ -1308,11 +1384,11 @@ __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
       commit_one<T>(A, k, p, o.status, o.wall, t);
     }
   }
-  if (COMMIT) tl_flush(t, A.tally + ((blockIdx.y * gridDim.x + blockIdx.x) % kSpread), s.sid);
+  if (COMMIT) tl_flush(t, A.tally + ((blockIdx.x + blockIdx.y) % kSpread), s.sid);
 }
 
 // Collisions of the particles a committing fast pass listed (their pushed
-// state is already stored): grid (X, kSpread, species slots), like the slow
+// state is already stored): grid (kSpread, X, species slots), like the slow
 // pass.  Particles born here are appended beyond the pass's start counts.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
@@ -1323,14 +1399,16 @@ __global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
   const int64_t qseg = P.qseg[slot];
   const MapP& m = A.m;
   const SpecDev& s = A.out;  // the pushed state, where the commit stored it
-  const int g = blockIdx.y;
-  const int64_t nq = qcount[g * kLineInts];
+  const int g = blockIdx.x;
   const int32_t* seg = queue + (int64_t)g * qseg;
+  int64_t q = (int64_t)blockIdx.y * kBlock + threadIdx.x;
+  int32_t k_next = q < qseg ? seg[q] : 0;
+  const int64_t nq = qcount[g * kLineInts];
   Tl t;
   tl_zero(t);
-  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nq;
-       q += (int64_t)gridDim.x * kBlock) {
-    const int64_t k = seg[q];
+  for (; q < nq; q += (int64_t)gridDim.y * kBlock) {
+    const int64_t k = k_next;
+    if (q + (int64_t)gridDim.y * kBlock < nq) k_next = seg[q + (int64_t)gridDim.y * kBlock];
     PState<T> p;
     if (!load_particle<T>(s, m, k, p)) continue;
     double vr = p.vr, vt = p.vt, vz = p.vz;
@@ -1346,7 +1424,7 @@ __global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
     p.vz = T(vz);
     store_particle<T>(s, m, k, p);
   }
-  tl_flush(t, A.tally + ((blockIdx.y * gridDim.x + blockIdx.x) % kSpread), s.sid);
+  tl_flush(t, A.tally + ((blockIdx.x + blockIdx.y) % kSpread), s.sid);
 }
 
 // standalone collision pass over the live particles
@@ -1521,7 +1599,7 @@ hipError_t launch_collide_list(const PassArgs& P, hipStream_t st) {
   const int64_t nb = (nmax + kBlock - 1) / kBlock;
   int64_t xs = (nb / kSpread + 15) / 16;
   xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
-  const dim3 gs((unsigned)xs, kSpread, (unsigned)P.nsp);
+  const dim3 gs(kSpread, (unsigned)xs, (unsigned)P.nsp);
   if (P.a[0].s.cell != nullptr)
     hipLaunchKernelGGL((k_collide_list<float>), gs, dim3(kBlock), 0, st, P);
   else
@@ -1537,7 +1615,7 @@ hipError_t launch_push_slow(const PassArgs& P, hipStream_t st) {
   // per segment enough blocks for a few percent of the particles
   int64_t xs = (nb / kSpread + 7) / 8;
   xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
-  const dim3 gs((unsigned)xs, kSpread, (unsigned)P.nsp);
+  const dim3 gs(kSpread, (unsigned)xs, (unsigned)P.nsp);
   const bool mixed = (P.a[0].s.cell != nullptr);
   const bool commit = P.a[0].commit != 0;
   if (!mixed) {
