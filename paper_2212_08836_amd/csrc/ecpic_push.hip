@@ -413,6 +413,10 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
   out.work = 0.0;
   const int nr = m.nr, nz = m.nz;
   T tau = T(m.dt);
+  // the field of the cell the particle is expected to enter, loaded while
+  // the crossing is solved (pf_i < 0: none)
+  T Fn[4];
+  int pf_i = -1, pf_j = -1;
   while (tau > T(0)) {
     if (out.nsub >= kMaxSub) {
       out.status = kError;
@@ -435,7 +439,14 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
       p.b = T(1);
     }
     T F[4];
-    load_field(m, ur, uz, p.i, p.j, F);
+    if (p.i == pf_i && p.j == pf_j) {
+      F[0] = Fn[0];
+      F[1] = Fn[1];
+      F[2] = Fn[2];
+      F[3] = Fn[3];
+    } else {
+      load_field(m, ur, uz, p.i, p.j, F);
+    }
     T dtry = tau;
     Mid<T> M;
     // linear-map cells: the closed-form solve (the same mid point as the
@@ -453,6 +464,22 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
     const T ea = T(2) * M.a - p.a, eb = T(2) * M.b - p.b;
     const bool in_x = ea >= T(0) && ea <= T(1);
     const bool in_e = eb >= T(0) && eb <= T(1);
+    // prefetch the field of the neighbour across the face the free orbit
+    // leaves by (the xi face when both are left); used only if the
+    // particle is in that cell at the next sub-step
+    pf_i = -1;
+    if (!(in_x && in_e)) {
+      int ni = p.i, nj = p.j;
+      if (!in_x)
+        ni += ea < T(0) ? -1 : 1;
+      else
+        nj += eb < T(0) ? -1 : 1;
+      if (ni >= 0 && ni < nr && nj >= 0 && nj < nz) {
+        load_field(m, ur, uz, ni, nj, Fn);
+        pf_i = ni;
+        pf_j = nj;
+      }
+    }
     PState<T> q;
     q.i = p.i;
     q.j = p.j;
@@ -467,22 +494,20 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
       q.vz = T(2) * M.vz - p.vz;
       used = dtry;
     } else {
+      // one crossing solve per lane on its own axis (the xi face first when
+      // both are left), so that lanes leaving by different axes share one
+      // pass of the solve; lanes that leave by both solve the eta face in a
+      // second pass and keep the earlier crossing (xi on a tie)
       T best_t = T(0);
       Mid<T> BM;
-      for (int d = 0; d < 2; ++d) {
-        T f, xd, xe;
-        if (d == 0) {
-          if (in_x) continue;
-          f = ea < T(0) ? T(0) : T(1);
-          xd = p.a;
-          xe = ea;
-        } else {
-          if (in_e) continue;
-          f = eb < T(0) ? T(0) : T(1);
-          xd = p.b;
-          xe = eb;
-        }
-        const T t0 = dtry * (f - xd) / (xe - xd);
+      const bool both = !in_x && !in_e;
+      for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1 && !both) break;
+        const int d = (pass == 0 && !in_x) ? 0 : 1;
+        const T e_end = d == 0 ? ea : eb;
+        const T f = e_end < T(0) ? T(0) : T(1);
+        const T xd = d == 0 ? p.a : p.b;
+        const T t0 = dtry * (f - xd) / (e_end - xd);
         T tt;
         Mid<T> CM;
         bool cap;
@@ -1321,16 +1346,17 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
 
 // Slow pass over the queued particles: the full push with splitting at every
 // face crossing (restarted from the particle's state), currents by atomics.
-// grid (kSpread, X, species slots): blocks with blockIdx.x = g walk segment g
-// of the queue of slot blockIdx.z.  Blocks are dispatched in grid order, so
-// with the segment index fastest the blocks that have work (low blockIdx.y)
-// all start first instead of queueing behind idle ones.  The first queue
+// grid (kSpread * slots, X): blocks with blockIdx.x = g + kSpread * slot walk
+// segment g of the queue of that slot.  Blocks are dispatched in grid order,
+// so with the segment and slot fastest the blocks that have work (low
+// blockIdx.y) of every species start first instead of queueing behind idle
+// ones.  The first queue
 // entry is read before the segment count is known (within the segment's
 // capacity), so the two loads overlap.
 template <typename T, bool COMMIT>
 __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
   if (P.a[0].stop && *P.a[0].stop) return;
-  const int slot = blockIdx.z;
+  const int slot = blockIdx.x / kSpread;
   const PushArgs& A = P.a[slot];
   const int32_t* queue = P.queue[slot];
   const int32_t* qcount = P.qcount[slot];
@@ -1339,7 +1365,7 @@ __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
   const SpecDev& s = A.s;
   const T qm = T(s.q / s.m);
   const double qw_dt = s.q * s.w / m.dt;
-  const int g = blockIdx.x;
+  const int g = blockIdx.x % kSpread;
   const int32_t* seg = queue + (int64_t)g * qseg;
   int64_t q = (int64_t)blockIdx.y * kBlock + threadIdx.x;
   int32_t k_next = q < qseg ? seg[q] : 0;
@@ -1388,18 +1414,17 @@ __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
 }
 
 // Collisions of the particles a committing fast pass listed (their pushed
-// state is already stored): grid (kSpread, X, species slots), like the slow
-// pass.  Particles born here are appended beyond the pass's start counts.
+// state is already stored): grid (kSpread * slots, X), like the slow pass.  Particles born here are appended beyond the pass's start counts.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
-  const int slot = blockIdx.z;
+  const int slot = blockIdx.x / kSpread;
   const PushArgs& A = P.a[slot];
   const int32_t* queue = P.cqueue[slot];
   const int32_t* qcount = P.cqcount[slot];
   const int64_t qseg = P.qseg[slot];
   const MapP& m = A.m;
   const SpecDev& s = A.out;  // the pushed state, where the commit stored it
-  const int g = blockIdx.x;
+  const int g = blockIdx.x % kSpread;
   const int32_t* seg = queue + (int64_t)g * qseg;
   int64_t q = (int64_t)blockIdx.y * kBlock + threadIdx.x;
   int32_t k_next = q < qseg ? seg[q] : 0;
@@ -1599,7 +1624,7 @@ hipError_t launch_collide_list(const PassArgs& P, hipStream_t st) {
   const int64_t nb = (nmax + kBlock - 1) / kBlock;
   int64_t xs = (nb / kSpread + 15) / 16;
   xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
-  const dim3 gs(kSpread, (unsigned)xs, (unsigned)P.nsp);
+  const dim3 gs((unsigned)(kSpread * P.nsp), (unsigned)xs, 1);
   if (P.a[0].s.cell != nullptr)
     hipLaunchKernelGGL((k_collide_list<float>), gs, dim3(kBlock), 0, st, P);
   else
@@ -1615,7 +1640,7 @@ hipError_t launch_push_slow(const PassArgs& P, hipStream_t st) {
   // per segment enough blocks for a few percent of the particles
   int64_t xs = (nb / kSpread + 7) / 8;
   xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
-  const dim3 gs(kSpread, (unsigned)xs, (unsigned)P.nsp);
+  const dim3 gs((unsigned)(kSpread * P.nsp), (unsigned)xs, 1);
   const bool mixed = (P.a[0].s.cell != nullptr);
   const bool commit = P.a[0].commit != 0;
   if (!mixed) {
