@@ -276,8 +276,8 @@ def main():
         "particles_alive_end": diag["n_alive"][:2],
         "kernel_ms": {k: (v["ms"] / v["launches"] if v["launches"] else None)
                       for k, v in prof_all.items()},
-        "roofline": {"bound": "hbm", "kernel": ("k_push_fast<double, false>" if args.precision == "fp64" else
-                                "k_push_fast<float, false>") + " (Picard iteration pass, both species)",
+        "roofline": {"bound": "hbm", "kernel": ("k_push_fast<double, false, true>" if args.precision == "fp64" else
+                                "k_push_fast<float, false, true>") + " (Picard iteration pass, both species)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(args.precision),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms},
