@@ -22,8 +22,8 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kKB = 1.380649e-23;  // Boltzmann constant [J/K]
 // layout of the device / pinned-host reduction buffer (doubles)
-constexpr int kOffRes = 0;                        // 2 per row block, residual partials
-constexpr int kOffFE = 4096;                      // 2 kRedBlocks field energy
+constexpr int kOffRes = 0;                        // 2 per solve block, residual partials
+constexpr int kOffFE = 2 * kResParts;             // 2 kRedBlocks field energy
 constexpr int kOffEx = kOffFE + 2 * kRedBlocks;   // kRedBlocks exchange
 constexpr int kOffKE = kOffEx + kRedBlocks;       // kMaxSpecies kinetic energies
 constexpr int kOffSc = kOffKE + 8;                // a few scalars

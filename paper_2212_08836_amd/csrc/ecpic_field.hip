@@ -27,63 +27,61 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kFB = 256;  // threads per block of the field kernels
 constexpr int kRB = 4;    // radial rows per block of the transform kernels
+constexpr int kCC = 32;   // output columns per block of the transform kernels
 
 inline int64_t nblk(int64_t n) { return (n + kBlock - 1) / kBlock; }
 inline int row_blocks(int nr) { return (nr + kRB - 1) / kRB; }
+inline int col_blocks(int nz) { return (nz + kCC - 1) / kCC; }
 
-// Row-blocked dense transform shared by both directions:
-//   out[r][k] = sum_j M[j][k] in[r][j]   for kRB rows of `in` (LDS, stride nz)
-// with M row-major nz x nz.  With P = kFB / nz parts (1 when nz >= kFB) the
-// thread (k, p) sums j over the p-th part; the parts land in psum[p][r][k]
-// and are added in part order (deterministic).  Independent loads of M are
-// issued ahead in groups of kUnroll.
+// Blocked dense transform shared by both directions:
+//   out[r][c] = sum_s M[s][c0 + c] in[r][s],  r < R, c < nc, s < ns,
+// for R rows of `in` (LDS, stride ns) and a chunk of nc output columns, M
+// row-major with row stride ldm.  With P = kFB / nc parts the thread (c, p)
+// sums s over the p-th part; the parts land in psum[p][r][c] and are added
+// in part order (deterministic).  A block covers kRB rows and kCC columns,
+// so the grid has enough blocks to fill the chip and each thread a short
+// chain.  Independent loads of M are issued ahead in groups of kUnroll.
 constexpr int kUnroll = 8;
-__host__ __device__ __forceinline__ int dct_parts(int nz) { return nz >= kFB ? 1 : kFB / nz; }
+__host__ __device__ __forceinline__ int chunk_parts(int nc) { return nc >= kFB ? 1 : kFB / nc; }
 
 template <int R>
-__device__ __forceinline__ void dense_rows(const double* __restrict__ M,
-                                           const double* __restrict__ in, int nz,
-                                           double* __restrict__ psum) {
-  const int P = dct_parts(nz);
-  for (int t = threadIdx.x; t < nz * P; t += blockDim.x) {
-    const int p = t / nz, k = t - p * nz;
-    const int j0 = p * nz / P, j1 = (p + 1) * nz / P;
+__device__ __forceinline__ void dense_chunk(const double* __restrict__ M, int ldm,
+                                            const double* __restrict__ in, int ns, int c0, int nc,
+                                            double* __restrict__ psum) {
+  const int P = chunk_parts(nc);
+  for (int t = threadIdx.x; t < nc * P; t += blockDim.x) {
+    const int p = t / nc, c = t - p * nc;
+    const int s0 = p * ns / P, s1 = (p + 1) * ns / P;
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    const double* q = M + k;
-    int j = j0;
-    for (; j + kUnroll <= j1; j += kUnroll) {
+    const double* q = M + c0 + c;
+    int j = s0;
+    for (; j + kUnroll <= s1; j += kUnroll) {
       double qv[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) qv[u] = q[(int64_t)(j + u) * nz];
+      for (int u = 0; u < kUnroll; ++u) qv[u] = q[(int64_t)(j + u) * ldm];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = fma(in[r * nz + j + u], qv[u], acc[r]);
+        for (int r = 0; r < R; ++r) acc[r] = fma(in[r * ns + j + u], qv[u], acc[r]);
     }
-    for (; j < j1; ++j) {
-      const double qv = q[(int64_t)j * nz];
+    for (; j < s1; ++j) {
+      const double qv = q[(int64_t)j * ldm];
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] = fma(in[r * nz + j], qv, acc[r]);
+      for (int r = 0; r < R; ++r) acc[r] = fma(in[r * ns + j], qv, acc[r]);
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) psum[(p * R + r) * nz + k] = acc[r];
+    for (int r = 0; r < R; ++r) psum[(p * R + r) * nc + c] = acc[r];
   }
   __syncthreads();
 }
 
-__device__ __forceinline__ void dct_rows(const double* __restrict__ Qt,
-                                         const double* __restrict__ in, int nz,
-                                         double* __restrict__ psum) {
-  dense_rows<kRB>(Qt, in, nz, psum);
-}
-
-__device__ __forceinline__ double psum_total(const double* __restrict__ psum, int nz, int r, int k,
-                                             int R = kRB) {
-  const int P = dct_parts(nz);
-  double v = psum[r * nz + k];
-  for (int p = 1; p < P; ++p) v += psum[(p * R + r) * nz + k];
+__device__ __forceinline__ double chunk_total(const double* __restrict__ psum, int nc, int r, int c,
+                                              int R) {
+  const int P = chunk_parts(nc);
+  double v = psum[r * nc + c];
+  for (int p = 1; p < P; ++p) v += psum[(p * R + r) * nc + c];
   return v;
 }
 
@@ -107,6 +105,8 @@ __global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restric
   const int nr = m.nr, nz = m.nz;
   const int i0 = blockIdx.x * kRB;
   const int rows = min(kRB, nr - i0);
+  const int k0 = blockIdx.y * kCC;
+  const int nk = min(kCC, nz - k0);
   const double hdt = 0.5 * m.dt;
   for (int e = threadIdx.x; e < rows * nz; e += blockDim.x) {
     const int r = e / nz, j = e - r * nz, i = i0 + r;
@@ -133,13 +133,12 @@ __global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restric
     sh[r * nz + j] = mi * (mass * h0[el] + (zr - zl - rt + rb));
   }
   __syncthreads();
-  // hat[k][i] = sum_j Qt[j][k] rhs[i][j]; each load of Qt feeds kRB rows,
-  // and the sum over j is cut into parts so that every thread has work
+  // hat[k][i] = sum_j Qt[j][k] rhs[i][j] for the block's modes k0 .. k0+nk-1
   double* psum = sh + kRB * nz;
-  dct_rows(Qt, sh, nz, psum);
-  for (int e = threadIdx.x; e < nz * kRB; e += blockDim.x) {
-    const int k = e / kRB, r = e - k * kRB;
-    if (r < rows) hat[(int64_t)k * nr + i0 + r] = psum_total(psum, nz, r, k);
+  dense_chunk<kRB>(Qt, nz, sh, nz, k0, nk, psum);
+  for (int e = threadIdx.x; e < nk * kRB; e += blockDim.x) {
+    const int kl = e / kRB, r = e - kl * kRB;
+    if (r < rows) hat[(int64_t)(k0 + kl) * nr + i0 + r] = chunk_total(psum, nk, r, kl, kRB);
   }
 }
 
@@ -263,28 +262,35 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
   const int nr = m.nr, nz = m.nz;
   const int i0 = blockIdx.x * kRB;
   const int rows = min(kRB, nr - i0);
-  double* hs = sh;            // hat of the R1 rows, [r][k]
-  double* xs = sh + R1 * nz;  // x of the R1 rows, [r][j]; row r is i0 - 1 + r
-  double* psum = sh + 2 * R1 * nz;
+  // the block's cells j0 .. j0+nj-1 need x at jlo = j0 - 1 (the r-edge
+  // below) .. j0+nj-1
+  const int j0 = blockIdx.y * kCC;
+  const int nj = min(kCC, nz - j0);
+  const int jlo = j0 > 0 ? j0 - 1 : 0;
+  const int nx = j0 + nj - jlo;
+  double* hs = sh;                 // hat of the R1 rows, [r][k]
+  double* xs = sh + R1 * nz;       // x of the R1 rows, [r][j - jlo]; row r is i0 - 1 + r
+  double* psum = xs + R1 * (kCC + 1);
   __shared__ double red[2 * (kFB / 64)];
   for (int e = threadIdx.x; e < R1 * nz; e += blockDim.x) {
     const int k = e / R1, r = e - k * R1, i = i0 - 1 + r;
     hs[r * nz + k] = (i >= 0 && i < nr) ? hat[(int64_t)k * nr + i] : 0.0;
   }
   __syncthreads();
-  dense_rows<R1>(Q, hs, nz, psum);
-  for (int e = threadIdx.x; e < R1 * nz; e += blockDim.x) {
-    const int r = e / nz, j = e - r * nz;
-    xs[e] = psum_total(psum, nz, r, j, R1);
+  dense_chunk<R1>(Q, nz, hs, nz, jlo, nx, psum);
+  for (int e = threadIdx.x; e < R1 * nx; e += blockDim.x) {
+    const int r = e / nx, c = e - r * nx;
+    xs[e] = chunk_total(psum, nx, r, c, R1);
   }
   __syncthreads();
   const double hdt = 0.5 * m.dt;
   const double two_pi = 2.0 * kPi;
   double s0 = 0.0, s1 = 0.0;
-  // r-edges of the rows
-  for (int e = threadIdx.x; e < rows * (nz + 1); e += blockDim.x) {
-    const int r = e / (nz + 1), j = e - r * (nz + 1), i = i0 + r;
-    const double* xi_ = xs + (r + 1) * nz;
+  // r-edges j0 .. j0+nj-1 of the rows, and the top-wall edge nz in the last chunk
+  const int ne = nj + (j0 + nj == nz ? 1 : 0);
+  for (int e = threadIdx.x; e < rows * ne; e += blockDim.x) {
+    const int r = e / ne, j = j0 + (e - r * ne), i = i0 + r;
+    const double* xr = xs + (r + 1) * nx - jlo;  // xr[j] = x[i][j]
     const int64_t g = (int64_t)i * (nz + 1) + j;
     double v;
     if (j == 0) {
@@ -293,7 +299,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
       v = 0.0;
     } else {
       const double w = wr[i];
-      const double K = -two_pi * rh[i] * (xi_[j] - xi_[j - 1]);
+      const double K = -two_pi * rh[i] * (xr[j] - xr[j - 1]);
       const double uh = a.ur0[g] + (K - a.Ir[g]) * (hdt / w);
       v = 2.0 * uh - a.ur0[g];
       if (a.part) {
@@ -310,16 +316,16 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
     }
     if (a.Ir_clr) a.Ir_clr[g] = 0.0;
   }
-  // z-edges of the rows (and the PEC row nr, owned by the block of row nr - 1)
-  for (int e = threadIdx.x; e < rows * nz; e += blockDim.x) {
-    const int r = e / nz, j = e - r * nz, i = i0 + r;
-    const double* xi_ = xs + (r + 1) * nz;
-    const double* xm = xs + r * nz;
+  // z-edges of the rows (and the PEC row nr, owned by the blocks of row nr - 1)
+  for (int e = threadIdx.x; e < rows * nj; e += blockDim.x) {
+    const int r = e / nj, j = j0 + (e - r * nj), i = i0 + r;
+    const double* xr = xs + (r + 1) * nx - jlo;
+    const double* xm = xs + r * nx - jlo;
     const double w = wz[i];
     const double ri = two_pi * rh[i];
     const double rm = (i > 0) ? two_pi * rh[i - 1] : 0.0;
     const int64_t g = (int64_t)i * nz + j;
-    const double K = ri * xi_[j] - rm * xm[j];
+    const double K = ri * xr[j] - rm * xm[j];
     const double uh = a.uz0[g] + (K - a.Iz[g]) * (hdt / w);
     const double v = 2.0 * uh - a.uz0[g];
     if (a.part) {
@@ -334,7 +340,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
       if (a.uz_hf) a.uz_hf[g] = float(hv);
     }
     if (a.Iz_clr) a.Iz_clr[g] = 0.0;
-    a.h1[g] = 2.0 * xi_[j] - a.h0[g];
+    a.h1[g] = 2.0 * xr[j] - a.h0[g];
     if (i == nr - 1) {
       const int64_t ew = (int64_t)nr * nz + j;
       a.uz1[ew] = 0.0;
@@ -349,8 +355,9 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
   if (a.part) {
     block_sum2(s0, s1, red);
     if (threadIdx.x == 0) {
-      a.part[2 * blockIdx.x] = s0;
-      a.part[2 * blockIdx.x + 1] = s1;
+      const int b = blockIdx.y * gridDim.x + blockIdx.x;
+      a.part[2 * b] = s0;
+      a.part[2 * b + 1] = s1;
     }
   }
 }
@@ -620,7 +627,8 @@ hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s) {
   if (k < 0 || k >= kMaxIter) return hipErrorInvalidValue;
   // the next iteration (parity k+1) gets a cleared tally set and wall scratch
   const int np = (k + 1) & 1;
-  hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, c.sol.partial, row_blocks(c.g.nr),
+  hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, c.sol.partial,
+                     row_blocks(c.g.nr) * col_blocks(c.g.nz),
                      k, tol, c.stop, c.res_dev, c.qcount, tally_set(c, np),
                      wall_scratch(c, np), wall_len(c));
   return hipGetLastError();
@@ -659,16 +667,20 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s) {
   const int nr = c.g.nr, nz = c.g.nz;
   const SolverDev& S = c.sol;
   if (nr > kFB * kMaxE) return hipErrorInvalidValue;
-  const int P = dct_parts(nz);
-  const size_t lds_rhs = sizeof(double) * (size_t)nz * (kRB + (size_t)P * kRB);
-  const size_t lds_rec = sizeof(double) * (size_t)nz * (2 * (kRB + 1) + (size_t)P * (kRB + 1));
-  if (lds_rec > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rhs_dct, dim3(row_blocks(nr)), dim3(kFB), lds_rhs, s, c.m, S.rh, S.wr,
+  const int cb = col_blocks(nz);
+  // residual partials: two per block of k_idct_recover
+  if ((int64_t)row_blocks(nr) * cb > kResParts) return hipErrorInvalidValue;
+  // part sums: P * R * nc <= kFB * R for nc < kFB (chunks have at most kCC + 1 columns)
+  const size_t lds_rhs = sizeof(double) * ((size_t)kRB * nz + (size_t)kFB * kRB);
+  const size_t lds_rec = sizeof(double) * ((size_t)(kRB + 1) * nz + (kRB + 1) * (kCC + 1) +
+                                           (size_t)kFB * (kRB + 1));
+  if (lds_rhs > 65536 || lds_rec > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_rhs_dct, dim3(row_blocks(nr), cb), dim3(kFB), lds_rhs, s, c.m, S.rh, S.wr,
                      S.wz, S.area, c.g.mu, a.ur0, a.uz0, a.h0, a.Ir, a.Iz, a.vhalf, S.Qt, S.work1,
                      a.stop);
   hipLaunchKernelGGL(k_tri_scan, dim3(nz), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv, S.tri_up,
                      S.work1, a.stop);
-  hipLaunchKernelGGL(k_idct_recover, dim3(row_blocks(nr)), dim3(kFB), lds_rec, s, a, c.m,
+  hipLaunchKernelGGL(k_idct_recover, dim3(row_blocks(nr), cb), dim3(kFB), lds_rec, s, a, c.m,
                      S.rh, S.wr, S.wz, S.Q, S.work1);
   return hipGetLastError();
 }

@@ -143,6 +143,7 @@ struct SolveArgs {
 };
 
 constexpr int kRedBlocks = 256;  // partial-sum blocks of the field reductions
+constexpr int kResParts = 8192;  // blocks of the field solve that write residual partials
 
 struct Species {
   ecpic_species_desc desc;
