@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # then WRITE_SIZE) and scaled by what the same counters read for a streaming
 # copy of known size (the --calibrate-copy mode below).  Reported only while
 # the kernel sources hash to what they were when the counters were taken.
+EVENT_EVERY = 8  # timed-region launches of the dominant kernel carrying events
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_fast_c2_{precision}_traffic.txt")
 PUSH_SOURCES = ("paper_2212_08836_amd/csrc/ecpic_push.hip",
                 "paper_2212_08836_amd/csrc/ecpic_internal.h")
@@ -110,7 +111,8 @@ def mixed_nn_leg(E, P, w, steps, warmup, sort_every, plain_ms):
     for k in range(warmup):
         ctx.step(tol=w.tol, sort_every=sort_every, use_nn=True, stats=False)
     torch.cuda.synchronize()
-    ctx.set_profiling(True, kinds=("push", "push_commit"))
+    # counts only (the first launch of a kind is the only one timed)
+    ctx.set_profiling(True, kinds=("push", "push_commit"), every=1 << 30)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for k in range(steps):
@@ -128,10 +130,10 @@ def mixed_nn_leg(E, P, w, steps, warmup, sort_every, plain_ms):
     ctx.close()
     ms = 1e3 * el / steps
     return {"ms_per_step": ms, "s_per_step": el / steps,
-            "particle_pushes_per_s": (prof["push"]["particles"] +
-                                      prof["push_commit"]["particles"]) / el,
-            "picard_iterations_per_step": (prof["push"]["launches"] +
-                                           prof["push_commit"]["launches"]) / steps,
+            "particle_pushes_per_s": (prof["push"]["call_particles"] +
+                                      prof["push_commit"]["call_particles"]) / el,
+            "picard_iterations_per_step": (prof["push"]["calls"] +
+                                           prof["push_commit"]["calls"]) / steps,
             "first_residual_mean": float(np.mean(r0)), "nn_fallbacks": fb,
             "speedup_vs_plain": plain_ms / ms,
             "train": {"snapshots": n_snap, "adam_steps": len(losses),
@@ -219,10 +221,11 @@ def main():
     for k in range(args.warmup):
         ctx.step(tol=w.tol, sort_every=args.sort_every, stats=False)
     torch.cuda.synchronize()
-    # in the timed region only the in-cell passes carry timing events (the
-    # plain one is the dominant kernel; a committing iteration's pass counts
-    # its pushes too)
-    ctx.set_profiling(True, kinds=("push", "push_commit"))
+    # in the timed region only the in-cell passes are counted (a committing
+    # iteration's pass pushes too), and only every 8th launch of each carries
+    # timing events: an event record stalls the stream for a few
+    # microseconds, so timing every launch would stretch the step
+    ctx.set_profiling(True, kinds=("push", "push_commit"), every=EVENT_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     last_print = t0
@@ -246,8 +249,8 @@ def main():
     # the particles of both species; the face crossers are redone in the
     # slow pass that follows it
     push = prof["push"]
-    n_push_passes = push["launches"] + prof["push_commit"]["launches"]
-    pushes = push["particles"] + prof["push_commit"]["particles"]
+    n_push_passes = push["calls"] + prof["push_commit"]["calls"]
+    pushes = push["call_particles"] + prof["push_commit"]["call_particles"]
     value = pushes / elapsed
     avg_launch_ms = push["ms"] / push["launches"]
     bytes_per_launch = push["bytes"] / push["launches"]

@@ -259,10 +259,13 @@ typedef enum {
 } ecpic_kernel_kind;
 
 typedef struct {
-  int64_t launches[ECPIC_K_COUNT];
-  double ms[ECPIC_K_COUNT];           /* summed event-measured durations    */
-  double bytes[ECPIC_K_COUNT];        /* summed algorithmic HBM bytes       */
-  int64_t particles[ECPIC_K_COUNT];   /* summed particles processed         */
+  int64_t launches[ECPIC_K_COUNT];    /* timed launches                     */
+  double ms[ECPIC_K_COUNT];           /* their summed event-measured times  */
+  double bytes[ECPIC_K_COUNT];        /* their summed algorithmic HBM bytes */
+  int64_t particles[ECPIC_K_COUNT];   /* their summed particles processed   */
+  int64_t calls[ECPIC_K_COUNT];       /* every launch of an enabled kind,
+                                         timed or not                       */
+  int64_t call_particles[ECPIC_K_COUNT]; /* particles of those launches     */
 } ecpic_profile;
 
 /* Choose the kinds to time: bit k of kind_mask enables ECPIC_K_* kind k
@@ -272,6 +275,11 @@ typedef struct {
  * are not counted.  Any call clears the totals. */
 #define ECPIC_PROFILE_ALL 0x7F
 ecpic_status ecpic_set_profiling(ecpic_ctx* ctx, int32_t kind_mask);
+/* Time only every `every`-th launch of each enabled kind (1, the default,
+ * times all of them); `calls` and `call_particles` still count every launch.
+ * Sampling keeps the event records from stretching a timed run.  every < 1
+ * is ECPIC_EINVAL.  Clears the totals like ecpic_set_profiling. */
+ecpic_status ecpic_set_profiling_every(ecpic_ctx* ctx, int32_t every);
 /* Totals since profiling was turned on (synchronises). */
 ecpic_status ecpic_get_profile(ecpic_ctx* ctx, ecpic_profile* out);
 

@@ -79,11 +79,14 @@ KERNEL_KINDS = ("push", "push_slow", "commit", "commit_slow", "field", "sort", "
 
 class Profile(C.Structure):
     _fields_ = [("launches", C.c_int64 * 7), ("ms", C.c_double * 7), ("bytes", C.c_double * 7),
-                ("particles", C.c_int64 * 7)]
+                ("particles", C.c_int64 * 7), ("calls", C.c_int64 * 7),
+                ("call_particles", C.c_int64 * 7)]
 
     def as_dict(self) -> dict:
         return {k: dict(launches=self.launches[i], ms=self.ms[i], bytes=self.bytes[i],
-                        particles=self.particles[i]) for i, k in enumerate(KERNEL_KINDS)}
+                        particles=self.particles[i], calls=self.calls[i],
+                        call_particles=self.call_particles[i])
+                for i, k in enumerate(KERNEL_KINDS)}
 
 
 _lib = None
@@ -123,6 +126,7 @@ def lib() -> C.CDLL:
             "ecpic_nn_grad": ([_vp, _vp, _vp, _vp, C.c_int32, _vp, C.POINTER(C.c_float)], st),
             "ecpic_nn_adam": ([_vp, _vp, _vp, _vp, _vp, C.c_float, C.c_int32], st),
             "ecpic_set_profiling": ([_vp, C.c_int32], st),
+            "ecpic_set_profiling_every": ([_vp, C.c_int32], st),
             "ecpic_get_profile": ([_vp, C.POINTER(Profile)], st),
             "ecpic_last_error": ([_vp], C.c_char_p),
             "ecpic_status_string": ([C.c_int], C.c_char_p),
@@ -326,9 +330,11 @@ class Context:
         t.cuda.synchronize()
         return q.cpu().numpy(), b.cpu().numpy(), tp.cpu().numpy(), sd.cpu().numpy()
 
-    def set_profiling(self, on: bool = True, kinds=None):
+    def set_profiling(self, on: bool = True, kinds=None, every: int = 1):
         """Time launches with HIP events: every kind when `kinds` is None,
-        else only the named ones (names of KERNEL_KINDS)."""
+        else only the named ones (names of KERNEL_KINDS); only every
+        `every`-th launch of a kind is timed, all are counted."""
+        self._check(self.L.ecpic_set_profiling_every(self.h, int(every)), self.h)
         if not on:
             mask = 0
         elif kinds is None:

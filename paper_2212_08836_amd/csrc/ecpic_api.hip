@@ -222,8 +222,11 @@ struct Timed {
   Timed(Ctx& cc, int k, double b, int64_t n, hipStream_t s = nullptr)
       : c(cc), st(s ? s : cc.stream), kind(k), bytes(b), particles(n) {
     if (c.prof_mask & (1u << k)) {
-      a = get_event(c);
-      if (a) (void)hipEventRecord(a, st);
+      c.count_pending.push_back({k, n, c.cur_tag});
+      if (c.prof_seq[k]++ % (uint64_t)c.prof_every == 0) {
+        a = get_event(c);
+        if (a) (void)hipEventRecord(a, st);
+      }
     }
   }
   ~Timed() {
@@ -238,6 +241,13 @@ struct Timed {
 // fold finished pairs into the totals; unfinished ones stay pending (all
 // are finished once the stream has been synchronised)
 void collect(Ctx& c) {
+  // launch counts: those of an iteration enqueued ahead are dropped by
+  // drop_tag before this runs if the iteration turns out not to be needed
+  for (const auto& q : c.count_pending) {
+    c.prof.calls[q.kind] += 1;
+    c.prof.call_particles[q.kind] += q.particles;
+  }
+  c.count_pending.clear();
   std::vector<Ctx::Pending> keep;
   for (auto& p : c.pending) {
     if (hipEventQuery(p.b) == hipErrorNotReady) {
@@ -268,6 +278,10 @@ void collect(Ctx& c) {
 // forget the timings of launches enqueued under `tag` (a speculative
 // iteration that was not needed); their events still complete normally
 void drop_tag(Ctx& c, int tag) {
+  std::vector<Ctx::Count> kc;
+  for (const auto& q : c.count_pending)
+    if (q.tag != tag) kc.push_back(q);
+  c.count_pending.swap(kc);
   std::vector<Ctx::Pending> keep;
   for (auto& p : c.pending) {
     if (p.tag == tag) {
@@ -968,6 +982,18 @@ ecpic_status ecpic_set_profiling(ecpic_ctx* x, int32_t kind_mask) {
   collect(c);
   c.prof_mask = (uint32_t)kind_mask & ((1u << ECPIC_K_COUNT) - 1u);
   std::memset(&c.prof, 0, sizeof(c.prof));
+  std::memset(c.prof_seq, 0, sizeof(c.prof_seq));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_set_profiling_every(ecpic_ctx* x, int32_t every) {
+  if (!x || every < 1) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  HIPCHK(hipStreamSynchronize(c.stream));
+  collect(c);
+  c.prof_every = every;
+  std::memset(&c.prof, 0, sizeof(c.prof));
+  std::memset(c.prof_seq, 0, sizeof(c.prof_seq));
   return ECPIC_OK;
 }
 

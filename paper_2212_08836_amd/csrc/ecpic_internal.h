@@ -229,6 +229,14 @@ struct Ctx {
   size_t nn_gws_bytes = 0;
   // event timing of the hot kernels
   uint32_t prof_mask = 0;          // bit k: time launches of kind k
+  int32_t prof_every = 1;          // time every prof_every-th launch of a kind
+  uint64_t prof_seq[ECPIC_K_COUNT] = {};
+  struct Count {
+    int kind;
+    int64_t particles;
+    int tag;
+  };
+  std::vector<Count> count_pending;  // launches not yet folded into the totals
   int cur_tag = 0;                 // iteration whose launches are being enqueued
   ecpic_profile prof{};
   struct Pending {

@@ -361,3 +361,30 @@ def test_step_tight_tolerance_discards_unaccepted_commits(og, torch_cuda):
     _flush(f"  iterations {iters}, committing iterations {prof['push_commit']['launches']} "
            f"for 8 steps")
     assert prof["push"]["launches"] + prof["push_commit"]["launches"] == iters
+    # every launch timed: the counts agree with the timed launches
+    for kind in ("push", "push_commit"):
+        assert prof[kind]["calls"] == prof[kind]["launches"]
+        assert prof[kind]["call_particles"] == prof[kind]["particles"]
+
+
+def test_sampled_profiling_counts_every_launch(torch_cuda):
+    # timing only every 3rd launch of a kind still counts every needed
+    # launch (speculative iterations that turn out to be skipped excluded)
+    import paper_2212_08836_amd as P
+    w = E.workload("c1")
+    ctx = P.context_from_workload(w)
+    P.load_workload_species(ctx, E.make_particles(w), extra_cap=0.2)
+    ctx.set_profiling(True, kinds=("push", "push_commit", "field"), every=3)
+    iters = 0
+    for k in range(6):
+        d = ctx.step(tol=w.tol)
+        iters += d["iters"]
+    prof = ctx.profile()
+    calls = prof["push"]["calls"] + prof["push_commit"]["calls"]
+    timed = prof["push"]["launches"] + prof["push_commit"]["launches"]
+    _flush(f"  sampled profiling: {iters} iterations, {calls} push passes counted, {timed} timed")
+    assert calls == iters and prof["field"]["calls"] == iters
+    assert 0 < timed < calls
+    assert prof["push"]["ms"] > 0.0
+    with pytest.raises(P.EcpicError):
+        ctx.set_profiling(True, every=0)
