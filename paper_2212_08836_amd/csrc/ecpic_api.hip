@@ -540,7 +540,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   ok = ok && hipHostMalloc((void**)&c.tally_host, kSpread * sizeof(Tally)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.red_host, 64 * sizeof(double)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.part_host, kPartLen * sizeof(double)) == hipSuccess;
-  ok = ok && dalloc(&c.stop, 1) == hipSuccess;
+  ok = ok && dalloc(&c.stop, 2) == hipSuccess;
   // written by kernels with system-scope stores and polled by the host
   ok = ok && hipHostMalloc((void**)&c.res_host, kMaxIter * sizeof(double),
                            hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
@@ -564,7 +564,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
                   c.Ir_alt, c.Iz_alt};
   int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz, nh, nur, nuz};
   for (int k = 0; k < 17; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
-  (void)launch_zero_i(c.stop, 1, c.stream);
+  (void)launch_zero_i(c.stop, 2, c.stream);
   (void)launch_zero(c.wall_bot, wall_len(c), c.stream);
   (void)launch_zero(c.wall_scr, 2 * wall_len(c), c.stream);
   if (hipStreamSynchronize(c.stream) != hipSuccess) {
@@ -858,6 +858,22 @@ static ecpic_status wait_word(Ctx& c, const volatile uint64_t* p, uint64_t pendi
   }
 }
 
+// Spin until the device has stored the sequence number `want` at p.
+static ecpic_status wait_seq(Ctx& c, const volatile uint64_t* p, uint64_t want) {
+  for (uint64_t spin = 0;; ++spin) {
+    if (*p == want) {
+      std::atomic_thread_fence(std::memory_order_acquire);
+      return ECPIC_OK;
+    }
+    if ((spin & 1023) == 1023) {
+      const hipError_t e = hipStreamQuery(c.stream);
+      if (e != hipSuccess && e != hipErrorNotReady) return fail(c, ECPIC_EHIP, hipGetErrorString(e));
+      if (e == hipSuccess && *p != want)
+        return fail(c, ECPIC_EHIP, "stream drained without the expected device result");
+    }
+  }
+}
+
 static ecpic_status wait_residual(Ctx& c, int k, double* r) {
   uint64_t bits = 0;
   ecpic_status rc = wait_word(c, reinterpret_cast<volatile uint64_t*>(c.res_host + k),
@@ -1075,14 +1091,31 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     const double rho = a / b;
     return rho < 1.0 && a * rho * rho <= 0.1 * o->tol;
   };
+  // sequence number of the commit summary enqueued behind a committing
+  // iteration (0: none)
+  uint64_t spec_seq[kMaxIter] = {};
   auto enqueue_iteration = [&](int k) -> ecpic_status {
     c.cur_tag = k;
     const bool fuse = expect_last(k);
     committed[k] = fuse;
+    spec_seq[k] = 0;
     ecpic_status rc = fuse ? pass(c, 1, c.mcc.enabled != 0, c.step, true, true, true, true, k & 1)
                            : pass(c, 0, false, c.step, true, true);
     if (rc != ECPIC_OK) return rc;
-    return enqueue_solve(c, k, dtol, true, true);
+    rc = enqueue_solve(c, k, dtol, true, true);
+    if (rc != ECPIC_OK) return rc;
+    if (fuse) {
+      // the commit summary goes in right behind the iteration expected to
+      // be the last, so the stream does not wait for the host to read the
+      // residual; on the device it runs only if this iteration converged
+      // (in fixed-count mode it is the last one)
+      HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir_alt, c.Iz_alt,
+                             c.sol.partial + kOffEx, c.stream));
+      spec_seq[k] = ++c.fin_seq;
+      HIPCHK(launch_finalize(c, tally_set(c, k & 1), c.sol.partial + kOffEx, c.Ir_alt,
+                             wall_scratch(c, k & 1), spec_seq[k], tol_mode ? k : -1, c.stream));
+    }
+    return ECPIC_OK;
   };
   // With the learned guess, a residual that does not fall from one iterate
   // to the next sends the step back to the extrapolated guess (the
@@ -1171,17 +1204,17 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     rc = pass(c, 1, c.mcc.enabled != 0, c.step, true, false, false, false, (ks + 1) & 1);
     if (rc != ECPIC_OK) return rc;
   }
-  double* d = c.sol.partial;
-  HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir_alt, c.Iz_alt, d + kOffEx,
-                         c.stream));
-  const uint64_t seq = ++c.fin_seq;
-  HIPCHK(launch_finalize(c, tset, d + kOffEx, c.Ir_alt, fused ? wall_scratch(c, ks & 1) : nullptr,
-                         seq, c.stream));
-  {
-    uint64_t got = 0;
-    rc = wait_word(c, reinterpret_cast<volatile uint64_t*>(&c.fin_host->seq), seq - 1, &got);
-    if (rc != ECPIC_OK) return rc;
+  uint64_t seq = fused ? spec_seq[ks] : 0;
+  if (seq == 0) {
+    double* d = c.sol.partial;
+    HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir_alt, c.Iz_alt, d + kOffEx,
+                           c.stream));
+    seq = ++c.fin_seq;
+    HIPCHK(launch_finalize(c, tset, d + kOffEx, c.Ir_alt,
+                           fused ? wall_scratch(c, ks & 1) : nullptr, seq, -1, c.stream));
   }
+  rc = wait_seq(c, reinterpret_cast<volatile uint64_t*>(&c.fin_host->seq), seq);
+  if (rc != ECPIC_OK) return rc;
   StepFinal fin;
   std::memcpy(&fin, (const void*)c.fin_host, sizeof(fin));
   collect(c);

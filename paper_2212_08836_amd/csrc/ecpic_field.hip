@@ -383,7 +383,10 @@ __global__ void k_guess_half(MapP m, double* ur, double* uz, const double* ur_pr
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int nr = m.nr, nz = m.nz;
   const int64_t nur = (int64_t)nr * (nz + 1), nuz = (int64_t)(nr + 1) * nz;
-  if (t == 0) *stop = 0;
+  if (t == 0) {
+    stop[0] = 0;
+    stop[1] = -1;
+  }
   clear_pass_scratch(t, (int64_t)gridDim.x * blockDim.x, qcount, tally, wscr, wlen);
   if (t < nur) {
     const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
@@ -553,7 +556,10 @@ __global__ void __launch_bounds__(256) k_converge(const double* __restrict__ par
   double r = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
   if (r != r) r = __longlong_as_double(0x7ff8000000000000ll);  // one quiet NaN
   store_sys(res + k, r);
-  if (r <= tol) *stop = 1;
+  if (r <= tol) {
+    stop[0] = 1;
+    stop[1] = k;  // the iteration that converged
+  }
 }
 
 // Commit summary: the tally copies and the exchange partials reduced by one
@@ -575,8 +581,12 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
                                                  const double* __restrict__ Ir, int nr, int nz,
                                                  const double* __restrict__ wall_add,
                                                  double* __restrict__ wall_tot, uint64_t seq,
-                                                 StepFinal* out) {
+                                                 StepFinal* out, const int32_t* __restrict__ conv,
+                                                 int want_k) {
   static_assert(kSpread == 64, "one tally copy per lane");
+  // enqueued ahead of the residual it depends on: only if iteration want_k
+  // is the one that converged
+  if (conv && conv[1] != want_k) return;
   const int l = threadIdx.x;
   const Tally& u = tally[l];
   Tally t;
@@ -635,9 +645,10 @@ hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart, const double* Ir,
-                           const double* wall_add, uint64_t seq, hipStream_t s) {
+                           const double* wall_add, uint64_t seq, int guard_k, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, tally, xpart, c.h, c.h_it, Ir,
-                     c.g.nr, c.g.nz, wall_add, c.wall_bot, seq, c.fin_dev);
+                     c.g.nr, c.g.nz, wall_add, c.wall_bot, seq, c.fin_dev,
+                     guard_k >= 0 ? (const int32_t*)c.stop : nullptr, guard_k);
   return hipGetLastError();
 }
 

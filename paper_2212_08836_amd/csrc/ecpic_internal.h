@@ -188,7 +188,7 @@ struct Ctx {
   // speculative Picard iterations: a device flag set once an iterate meets
   // the tolerance (every kernel of a later iteration then returns at once),
   // and the residuals written by the device into pinned host memory
-  int32_t* stop = nullptr;
+  int32_t* stop = nullptr;  // [0]: stop flag, [1]: the iteration that converged
   double* res_host = nullptr;      // [kMaxIter], coherent pinned, device-written
   double* res_dev = nullptr;       // device alias of res_host
   struct StepFinal* fin_host = nullptr;  // commit summary, coherent pinned
@@ -299,9 +299,11 @@ inline Tally* tally_set(const Ctx& c, int p) { return c.tally + (int64_t)p * kSp
 inline int64_t wall_len(const Ctx& c) { return 2 * (int64_t)(c.g.nr + 1) + c.g.nz + 1; }
 inline double* wall_scratch(const Ctx& c, int p) { return c.wall_scr + p * wall_len(c); }
 // commit summary from the tally set `tally`; when wall_add is set, that
-// wall-charge scratch is also added into the wall totals
+// wall-charge scratch is also added into the wall totals.  guard_k >= 0: the
+// kernel does nothing unless Picard iteration guard_k is the one the residual
+// kernel found converged (stop[1]), so it can be enqueued before that is known.
 hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart, const double* Ir,
-                           const double* wall_add, uint64_t seq, hipStream_t s);
+                           const double* wall_add, uint64_t seq, int guard_k, hipStream_t s);
 hipError_t launch_zero_tally(const Ctx& c, hipStream_t s);
 // the value a residual slot holds until the device has written it
 constexpr uint64_t kResPending = 0x7ff4dead0badf00dull;
