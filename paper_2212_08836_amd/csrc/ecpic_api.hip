@@ -99,7 +99,9 @@ SpecDev view(Species& s) {
 }
 
 // the species' other buffer, sized like the current one (a committing Picard
-// iteration writes the new state there)
+// iteration writes the new state there); the uid array stays the current
+// one: a commit keeps every particle in its slot, so both buffers share it
+// (a flip swaps the uid arrays along with the buffers)
 SpecDev other_view(Species& s) {
   SpecDev d = view(s);
   const SpecDev& o = s.d[1 - s.cur];
@@ -114,7 +116,6 @@ SpecDev other_view(Species& s) {
   d.fvr = o.fvr;
   d.fvt = o.fvt;
   d.fvz = o.fvz;
-  d.uid = o.uid;
   return d;
 }
 
@@ -404,11 +405,9 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
       P.cqcount[q] = c.qcount + kQCount + s * kSpread * kLineInts;
       P.qcount[q] = c.qcount + s * kSpread * kLineInts;
       P.qseg[q] = queue_segment(c.sp[s].n);
-      // commit: state + id read, state written; iteration: state read
-      // iteration: state read; commit: state and id read, state written (and
-      // the id too when written to the other buffer)
-      bytes += (commit ? 2.0 * state_bytes(c) + (to_other ? 16.0 : 8.0) : state_bytes(c)) *
-               (double)c.sp[s].n;
+      // iteration: state read; commit: state read and written, and the id
+      // read for the collision draw (both buffers share the ids)
+      bytes += (commit ? 2.0 * state_bytes(c) + 8.0 : state_bytes(c)) * (double)c.sp[s].n;
       parts += c.sp[s].n;
     }
     {
@@ -1224,6 +1223,7 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     for (Species& sp : c.sp) {
       if (sp.n <= 0 && t.append[&sp - c.sp.data()] == 0) continue;
       sp.cur = 1 - sp.cur;
+      std::swap(sp.d[0].uid, sp.d[1].uid);  // the uids stay with the state
     }
   }
   for (size_t s = 0; s < c.sp.size(); ++s) {

@@ -924,6 +924,12 @@ __device__ __forceinline__ void store_particle<float>(const SpecDev& s, const Ma
   s.fvz[k] = p.vz;
 }
 
+// whether two views of a species are the same particle buffer (the uid
+// array is shared by both buffers, the state arrays are not)
+__device__ __forceinline__ bool same_buffer(const SpecDev& a, const SpecDev& b) {
+  return a.xi == b.xi && a.cell == b.cell;
+}
+
 template <typename T>
 __device__ __forceinline__ void kill_particle(const SpecDev& s, int64_t k);
 template <>
@@ -1012,8 +1018,7 @@ __device__ void commit_one(const PushArgs& A, int64_t k, PState<T>& p, int statu
   const SpecDev& s = A.out;
   const MapP& m = A.m;
   const double qw = s.q * s.w;
-  const uint64_t uid = A.s.uid[k];
-  if (s.uid != A.s.uid) s.uid[k] = uid;
+  const uint64_t uid = A.s.uid[k];  // both buffers share the uid array
   if (status == kError) t.err += 1;
   if (status == kAbsorbed) {
     kill_particle<T>(s, k);
@@ -1144,10 +1149,9 @@ __device__ __forceinline__ void tile_deposit(const Tile& t, double* Ir, double* 
 // draw collide_one makes first).
 template <typename T>
 __device__ __forceinline__ bool commit_store(const PushArgs& A, int64_t k, const PState<T>& p) {
-  const uint64_t uid = A.s.uid[k];
   store_particle<T>(A.out, A.m, k, p);
-  if (A.out.uid != A.s.uid) A.out.uid[k] = uid;
   if (!A.mcc.enabled) return false;
+  const uint64_t uid = A.s.uid[k];  // both buffers share the uid array
   double u[4];
   draws(A.mcc.seed, A.s.sid, uid, A.mcc.step, 0, u);
   return u[0] < A.mcc.pnull;
@@ -1301,7 +1305,7 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
       bool coll = false;
       if (alive && !slow) coll = commit_store<T>(A, k, p);
       // into the other buffer: dead slots stay dead there
-      if (k < s.n && !alive && A.out.uid != A.s.uid) kill_particle<T>(A.out, k);
+      if (k < s.n && !alive && !same_buffer(A.out, A.s)) kill_particle<T>(A.out, k);
       const uint64_t cm = __ballot(coll);
       if (cm) {
         int wb = 0;
