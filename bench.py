@@ -38,6 +38,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # copy of known size (the --calibrate-copy mode below).  Reported only while
 # the kernel sources hash to what they were when the counters were taken.
 EVENT_EVERY = 8  # timed-region launches of the dominant kernel carrying events
+RUN_CHUNK = 50   # steps per library call in the timed region
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_fast_c2_{precision}_traffic.txt")
 PUSH_SOURCES = ("paper_2212_08836_amd/csrc/ecpic_push.hip",
                 "paper_2212_08836_amd/csrc/ecpic_internal.h")
@@ -108,15 +109,17 @@ def mixed_nn_leg(E, P, w, steps, warmup, sort_every, plain_ms):
     t_train = time.perf_counter() - t0
     print(f"# mixed + learned guess: trained in {t_train:.1f} s, loss {losses[0]:.3f} -> "
           f"{np.mean(losses[-50:]):.3f}", file=sys.stderr, flush=True)
-    for k in range(warmup):
-        ctx.step(tol=w.tol, sort_every=sort_every, use_nn=True, stats=False)
+    ctx.run(warmup, tol=w.tol, sort_every=sort_every, use_nn=True)
     torch.cuda.synchronize()
     # counts only (the first launch of a kind is the only one timed)
     ctx.set_profiling(True, kinds=("push", "push_commit"), every=1 << 30)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for k in range(steps):
-        ctx.step(tol=w.tol, sort_every=sort_every, use_nn=True, stats=False)
+    k = 0
+    while k < steps:
+        n = min(RUN_CHUNK, steps - k)
+        ctx.run(n, tol=w.tol, sort_every=sort_every, use_nn=True)
+        k += n
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
     prof = ctx.profile()
@@ -218,8 +221,7 @@ def main():
     ctx.set_mcc(mcc)
     print(f"# bench: c2 256x128, {n0} particles, {args.precision}, warmup {args.warmup}, "
           f"steps {args.steps}", file=sys.stderr, flush=True)
-    for k in range(args.warmup):
-        ctx.step(tol=w.tol, sort_every=args.sort_every, stats=False)
+    ctx.run(args.warmup, tol=w.tol, sort_every=args.sort_every)
     torch.cuda.synchronize()
     # in the timed region only the in-cell passes are counted (a committing
     # iteration's pass pushes too), and only every 8th launch of each carries
@@ -227,10 +229,15 @@ def main():
     # microseconds, so timing every launch would stretch the step
     ctx.set_profiling(True, kinds=("push", "push_commit"), every=EVENT_EVERY)
     torch.cuda.synchronize()
+    # the steps run inside the library (ecpic_run), in chunks so that
+    # progress can be reported
     t0 = time.perf_counter()
     last_print = t0
-    for k in range(args.steps):
-        ctx.step(tol=w.tol, sort_every=args.sort_every, stats=False)
+    k = 0
+    while k < args.steps:
+        n = min(RUN_CHUNK, args.steps - k)
+        ctx.run(n, tol=w.tol, sort_every=args.sort_every)
+        k += n
         now = time.perf_counter()
         if now - last_print > 20:
             print(f"# step {k}", file=sys.stderr, flush=True)

@@ -192,6 +192,18 @@ ecpic_status ecpic_set_mcc(ecpic_ctx* ctx, const ecpic_mcc_desc* mcc);
  * stats may be NULL. */
 ecpic_status ecpic_step(ecpic_ctx* ctx, const ecpic_step_opts* opts, ecpic_step_stats* stats);
 
+/* n_steps implicit steps with the same options, back to back in the library
+ * (Sec. 2.1 per step, as ecpic_step).  Between steps the next step's
+ * extrapolated guess is enqueued before the host reads the commit summary,
+ * so the stream does not wait for the host.  Stops at the first step that
+ * does not return ECPIC_OK and returns its status (ENOTCONV leaves that
+ * step's state and fields untouched); *done (may be NULL) receives the
+ * number of steps completed.  last (may be NULL) receives the statistics of
+ * the last step (computing them costs a few reductions).  n_steps < 0 is
+ * ECPIC_EINVAL; 0 does nothing. */
+ecpic_status ecpic_run(ecpic_ctx* ctx, const ecpic_step_opts* opts, int32_t n_steps, int32_t* done,
+                       ecpic_step_stats* last);
+
 /* Counting sort of every species by cell, dropping absorbed particles. */
 ecpic_status ecpic_sort(ecpic_ctx* ctx);
 

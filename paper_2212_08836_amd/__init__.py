@@ -117,6 +117,8 @@ def lib() -> C.CDLL:
             "ecpic_collide": ([_vp, C.POINTER(MccDesc), C.c_int64], st),
             "ecpic_set_mcc": ([_vp, C.POINTER(MccDesc)], st),
             "ecpic_step": ([_vp, C.POINTER(StepOpts), C.POINTER(StepStats)], st),
+            "ecpic_run": ([_vp, C.POINTER(StepOpts), C.c_int32, C.POINTER(C.c_int32),
+                           C.POINTER(StepStats)], st),
             "ecpic_sort": ([_vp], st),
             "ecpic_node_charge": ([_vp, _dp, _dp, _dp, _dp], st),
             "ecpic_diagnostics": ([_vp, C.POINTER(StepStats)], st),
@@ -313,6 +315,21 @@ class Context:
             rc = self.L.ecpic_step(self.h, C.byref(o), None)
             d = {}
         d["rc"] = rc
+        if check and rc != 0:
+            self._check(rc, self.h)
+        return d
+
+    def run(self, n_steps, tol=1e-10, max_iter=50, fixed_iter=0, sort_every=0, use_nn=False,
+            stats=False, check=True):
+        """n_steps implicit steps in the library (ecpic_run); returns the
+        number done and, with stats, the last step's statistics."""
+        o = StepOpts(tol, max_iter, fixed_iter, sort_every, int(use_nn))
+        done = C.c_int32(0)
+        s = StepStats() if stats else None
+        rc = self.L.ecpic_run(self.h, C.byref(o), int(n_steps), C.byref(done),
+                              C.byref(s) if stats else None)
+        d = s.as_dict() if stats else {}
+        d["rc"], d["done"] = rc, done.value
         if check and rc != 0:
             self._check(rc, self.h)
         return d

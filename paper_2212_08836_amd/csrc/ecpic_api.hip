@@ -1027,16 +1027,21 @@ ecpic_status ecpic_diagnostics(ecpic_ctx* x, ecpic_step_stats* st) {
   return diag_into(x->c, st);
 }
 
-ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats* st) {
-  if (!x || !o) return ECPIC_EINVAL;
-  Ctx& c = x->c;
+}  // extern "C"
+
+// One implicit step.  guess_ready: the previous step of a run already
+// enqueued this step's extrapolated guess.  prepare_next: a next step follows
+// at once, so its guess (fields only) is enqueued as soon as this step's
+// fields are final, before the host waits for the commit summary.
+static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats* st,
+                              bool guess_ready, bool prepare_next) {
   ecpic_step_stats local;
   ecpic_step_stats* S = st ? st : &local;
   std::memset(S, 0, sizeof(*S));
   int kmax = o->fixed_iter > 0 ? o->fixed_iter : o->max_iter;
   if (kmax < 1 || kmax > 64) return fail(c, ECPIC_EINVAL, "iterations must be in 1..64");
   const double vnow = drive(c.g, c.t), vnext = drive(c.g, c.t + c.g.dt);
-  HIPCHK(launch_guess_half(c, vnow, vnext, c.stream));
+  if (!guess_ready) HIPCHK(launch_guess_half(c, vnow, vnext, c.stream));
   if (o->use_nn) {
     bool used = false;
     ecpic_status rc = nn_guess(c, &used);
@@ -1212,6 +1217,23 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
     HIPCHK(launch_finalize(c, tset, d + kOffEx, c.Ir_alt,
                            fused ? wall_scratch(c, ks & 1) : nullptr, seq, -1, c.stream));
   }
+  // field shift: u^{n-1} <- u^n, u^n <- u^{n+1} (pointer roles only; the
+  // summary kernels above hold the pointers they read)
+  std::swap(c.ur_prev, c.ur);
+  std::swap(c.uz_prev, c.uz);
+  std::swap(c.ur, c.ur_it);
+  std::swap(c.uz, c.uz_it);
+  {
+    // h^{n-1} <- h^n, h^n <- h^{n+1}; the old h^{n-1} buffer becomes scratch
+    double* old_prev = c.h_prev;
+    c.h_prev = c.h;
+    c.h = c.h_it;
+    c.h_it = old_prev;
+  }
+  if (prepare_next) {
+    const double t1 = c.t + c.g.dt;
+    HIPCHK(launch_guess_half(c, drive(c.g, t1), drive(c.g, t1 + c.g.dt), c.stream));
+  }
   rc = wait_seq(c, reinterpret_cast<volatile uint64_t*>(&c.fin_host->seq), seq);
   if (rc != ECPIC_OK) return rc;
   StepFinal fin;
@@ -1249,18 +1271,6 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
   S->n_crossings = (int64_t)t.n_crossings;
   S->n_errors = (int64_t)t.n_errors;
   S->n_over_range = (int64_t)t.n_over_range;
-  // field shift: u^{n-1} <- u^n, u^n <- u^{n+1}
-  std::swap(c.ur_prev, c.ur);
-  std::swap(c.uz_prev, c.uz);
-  std::swap(c.ur, c.ur_it);
-  std::swap(c.uz, c.uz_it);
-  {
-    // h^{n-1} <- h^n, h^n <- h^{n+1}; the old h^{n-1} buffer becomes scratch
-    double* old_prev = c.h_prev;
-    c.h_prev = c.h;
-    c.h = c.h_it;
-    c.h_it = old_prev;
-  }
   c.t += c.g.dt;
   c.step += 1;
   if (o->sort_every > 0 && c.step % o->sort_every == 0) {
@@ -1279,6 +1289,37 @@ ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats
   }
   if (rc == ECPIC_OK && t.n_errors) rc = fail(c, ECPIC_EPUSH, "particle push failed");
   return rc;
+}
+
+extern "C" {
+
+ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats* st) {
+  if (!x || !o) return ECPIC_EINVAL;
+  return step_impl(x->c, o, st, false, false);
+}
+
+ecpic_status ecpic_run(ecpic_ctx* x, const ecpic_step_opts* o, int32_t n_steps, int32_t* done,
+                       ecpic_step_stats* last) {
+  if (done) *done = 0;
+  if (!x || !o || n_steps < 0) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  bool ready = false;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    const bool more = k + 1 < n_steps;
+    const ecpic_status rc = step_impl(c, o, more ? nullptr : last, ready, more);
+    if (rc != ECPIC_OK) {
+      if (ready || more) {
+        // a guess enqueued for a step that will not run is harmless (it
+        // writes only the iterate and half-step buffers), but let the
+        // stream settle before returning an error
+        (void)hipStreamSynchronize(c.stream);
+      }
+      return rc;
+    }
+    ready = more;
+    if (done) *done = k + 1;
+  }
+  return ECPIC_OK;
 }
 
 }  // extern "C"

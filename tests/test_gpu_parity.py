@@ -388,3 +388,29 @@ def test_sampled_profiling_counts_every_launch(torch_cuda):
     assert prof["push"]["ms"] > 0.0
     with pytest.raises(P.EcpicError):
         ctx.set_profiling(True, every=0)
+
+
+def test_run_matches_oracle_steps(og, torch_cuda):
+    # several steps in one library call (the next step's guess enqueued
+    # ahead) give the oracle's steps
+    import paper_2212_08836_amd as P
+    _flush("run of 5 steps in one call vs the oracle, c1")
+    w = E.workload("c1")
+    g, sp, ctx = _make_pair(w, og, P, E.make_particles(w))
+    st = og.State(g)
+    for n in range(5):
+        d_o = g.step(st, sp, tol=w.tol)
+    d = ctx.run(5, tol=w.tol, stats=True)
+    assert d["rc"] == 0 and d["done"] == 5
+    assert d["iters"] == d_o["iters"] and d["converged"] == 1
+    ur, uz, h = ctx.get_fields()
+    errs = [_rel(ur, st.ur), _rel(uz, st.uz), _rel(h, st.h)]
+    for k in range(len(sp)):
+        errs.append(_cmp_species(ctx.read_particles(k), sp[k].view(), f"run sp {k}"))
+    _flush(f"  after 5 steps: worst rel {max(errs):.2e}")
+    assert max(errs) < TOL
+    # a step that cannot converge stops the run and is reported
+    d = ctx.run(3, tol=1e-30, max_iter=3, check=False)
+    assert d["rc"] == P.ECPIC_ENOTCONV and d["done"] == 0
+    ur1, uz1, h1 = ctx.get_fields()
+    assert np.array_equal(ur, ur1) and np.array_equal(uz, uz1) and np.array_equal(h, h1)
