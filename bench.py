@@ -189,7 +189,7 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--sort-every", type=int, default=16)
+    ap.add_argument("--sort-every", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-nn", action="store_true",
                     help="skip the FP32 push + learned-guess comparison")
