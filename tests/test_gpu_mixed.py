@@ -135,6 +135,15 @@ def test_mixed_one_step_c2(torch_cuda):
     _one_step_compare(P, w, 20, w.mcc_params())
 
 
+def test_mixed_one_step_c3(torch_cuda):
+    # the mixed-precision workload at full size (512x256 cells, 128
+    # particles per cell per species, about 33.5M particles)
+    import paper_2212_08836_amd as P
+    _flush("mixed vs fp64, c3")
+    w = E.workload("c3")
+    _one_step_compare(P, w, 8, w.mcc_params())
+
+
 def test_mixed_deposit_conserves_charge(og, torch_cuda):
     # continuity of the mixed deposit: the currents are those of the FP32
     # displacements before the new offsets are rounded to FP32 for storage,
