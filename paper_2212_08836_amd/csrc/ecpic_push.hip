@@ -1074,7 +1074,10 @@ struct Tile {
   int c_lo, W, er0, nr_e, nz_e;
 };
 
-__host__ __device__ inline int tile_cells(int nz) { return 4 * nz + 64; }
+// the window: one radial row below the block's first cell and one above its
+// last (a block's 1024 particles span a few dozen cells at most in sorted
+// order), cells that particles drift to between sorts
+__host__ __device__ inline int tile_cells(int nz) { return 2 * nz + 64; }
 __host__ __device__ inline int tile_r_len(int nz) {
   const int W = tile_cells(nz);
   return W + W / nz + 2;
