@@ -111,3 +111,53 @@ def test_learned_guess_does_not_change_the_answer(trained):
            f"first residual {db['residual'][0]:.2e} vs {da['residual'][0]:.2e}")
     # both are within the tolerance of the one converged answer
     assert max(errs) < 1e-8
+
+
+def test_learned_guess_on_the_512x256_grid(torch_cuda):
+    # the learned guess on the 512x256 grid (R = 0.25 m, 128 particles per
+    # cell per species): trained there on snapshots of the plain method from
+    # two other seeds and pressures, compared with the extrapolated guess on
+    # held-out steps of a third run, at the same converged residual
+    import paper_2212_08836_amd as P
+    from paper_2212_08836_amd import nn_guess as G
+    xs, ts = [], []
+    for seed, pr in ((302, 5.0), (303, 2.0)):
+        w = E.workload("c3", seed=seed, pressure_pa=pr)
+        ctx = P.context_from_workload(w)
+        P.load_workload_species(ctx, E.make_particles(w), extra_cap=0.3)
+        ctx.sort()
+        ctx.set_mcc(w.mcc_params())
+        ctx.run(20, tol=w.tol, sort_every=8)
+        x, t = G.collect(ctx, 130, w.tol, sort_every=8)
+        xs.append(x)
+        ts.append(t)
+        ctx.close()
+    x, t = np.concatenate(xs), np.concatenate(ts)
+    norm = G.scales(x, t)
+    w = E.workload("c3")
+    ctx = P.context_from_workload(w)
+    P.load_workload_species(ctx, E.make_particles(w), extra_cap=0.3)
+    ctx.sort()
+    ctx.set_mcc(w.mcc_params())
+    xd, td = G.to_device(ctx, x, t, norm)
+    del x, t
+    wts, losses = G.train(ctx, xd, td, steps=800, batch=8, lr=1e-3, seed=1)
+    del xd, td
+    _flush(f"  512x256: {len(xs[0]) + len(xs[1])} snapshots, training loss {losses[0]:.3f} -> "
+           f"{np.mean(losses[-50:]):.3f}")
+    ctx.nn_set_weights(wts, norm)
+    ctx.run(20, tol=w.tol, sort_every=8)
+    res = {False: [], True: []}
+    for k in range(60):
+        use = k % 2 == 1
+        d = ctx.step(tol=w.tol, sort_every=8, use_nn=use)
+        assert d["converged"] == 1 and d["residual"][d["iters"] - 1] <= w.tol
+        res[use].append((d["iters"], d["residual"][0], d["nn_fallback"]))
+    plain, nn = np.array(res[False]), np.array(res[True])
+    _flush(f"  512x256 extrapolated guess: iterations {plain[:, 0].mean():.3f}, first residual "
+           f"mean {plain[:, 1].mean():.3e}")
+    _flush(f"  512x256 learned guess:      iterations {nn[:, 0].mean():.3f}, first residual "
+           f"mean {nn[:, 1].mean():.3e}, fallbacks {int(nn[:, 2].sum())}")
+    ctx.close()
+    assert nn[:, 1].mean() < plain[:, 1].mean()
+    assert nn[:, 0].mean() <= plain[:, 0].mean() + 0.05
