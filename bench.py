@@ -37,6 +37,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # then WRITE_SIZE) and scaled by what the same counters read for a streaming
 # copy of known size (the --calibrate-copy mode below).  Reported only while
 # the kernel sources hash to what they were when the counters were taken.
+WORKLOADS = {
+    "c2": "VHF CCP slab 256x128 (R 0.15 m, L 3 cm), 4.19M particles, 100 MHz 200 V, MCC 5 Pa",
+    "c3": "VHF CCP slab 512x256 (R 0.25 m, L 3 cm), 33.5M particles, 100 MHz 200 V, MCC 5 Pa",
+    "c5": "dual-frequency CCP 1024x512 (R 0.3 m, L 3 cm), 268M particles, 60 + 13.56 MHz "
+          "200 V each, MCC 5 Pa",
+}
 EVENT_EVERY = 8  # timed-region launches of the dominant kernel carrying events
 RUN_CHUNK = 50   # steps per library call in the timed region
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_fast_c2_{precision}_traffic.txt")
@@ -73,37 +79,45 @@ def committed_traffic(precision):
         return None
 
 
-def mixed_nn_leg(E, P, w, steps, warmup, sort_every, plain_ms):
-    """The FP32 push + learned-guess form on the same workload: the network
-    is trained first (outside the timed region) by the library's kernels on
-    snapshots of the plain FP64 method from two other seeds/pressures."""
+def mixed_nn_leg(E, P, w, parts, steps, warmup, sort_every, plain_ms, self_train=False):
+    """The FP32 push + learned-guess form on the same workload.  The network
+    is trained first (outside the timed region) by the library's kernels: on
+    snapshots of the plain FP64 method from two other seeds/pressures, or
+    (self_train, for the larger grids) on snapshots of the mixed run's own
+    first steps with the extrapolated guess."""
     import torch
     from paper_2212_08836_amd import nn_guess as G
     t0 = time.perf_counter()
-    xs, ts = [], []
-    for seed, pr in ((102, 5.0), (103, 2.0)):
-        wt = E.workload("c2", seed=seed, pressure_pa=pr)
-        c = P.context_from_workload(wt)
-        P.load_workload_species(c, E.make_particles(wt), extra_cap=0.3)
-        c.sort()
-        c.set_mcc(wt.mcc_params())
-        for k in range(20):
-            c.step(tol=wt.tol, sort_every=sort_every, stats=False)
-        x, t = G.collect(c, 250, wt.tol, sort_every=sort_every)
-        xs.append(x)
-        ts.append(t)
-        c.close()
-    x, t = np.concatenate(xs), np.concatenate(ts)
-    del xs, ts
-    n_snap = int(x.shape[0])
-    norm = G.scales(x, t)
     ctx = P.context_from_workload(w, precision="mixed")
-    P.load_workload_species(ctx, E.make_particles(w), extra_cap=0.25)
+    P.load_workload_species(ctx, parts, extra_cap=0.25)
     ctx.sort()
     ctx.set_mcc(w.mcc_params())
+    if self_train:
+        ctx.run(20, tol=w.tol, sort_every=sort_every)
+        x, t = G.collect(ctx, 125, w.tol, sort_every=sort_every)
+        adam_steps = 400
+    else:
+        xs, ts = [], []
+        for seed, pr in ((102, 5.0), (103, 2.0)):
+            wt = E.workload(w.name, seed=seed, pressure_pa=pr)
+            c = P.context_from_workload(wt)
+            P.load_workload_species(c, E.make_particles(wt), extra_cap=0.3)
+            c.sort()
+            c.set_mcc(wt.mcc_params())
+            c.run(20, tol=wt.tol, sort_every=sort_every)
+            x, t = G.collect(c, 250, wt.tol, sort_every=sort_every)
+            xs.append(x)
+            ts.append(t)
+            c.close()
+        x, t = np.concatenate(xs), np.concatenate(ts)
+        del xs, ts
+        adam_steps = 1200
+    n_snap = int(x.shape[0])
+    norm = G.scales(x, t)
+    print(f"# mixed + learned guess: {n_snap} snapshots collected", file=sys.stderr, flush=True)
     xd, td = G.to_device(ctx, x, t, norm)
     del x, t
-    wts, losses = G.train(ctx, xd, td, steps=1200, batch=8, lr=1e-3, seed=1)
+    wts, losses = G.train(ctx, xd, td, steps=adam_steps, batch=8, lr=1e-3, seed=1)
     del xd, td
     ctx.nn_set_weights(wts, norm)
     t_train = time.perf_counter() - t0
@@ -189,6 +203,9 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS),
+                    help="c2 is the measured configuration; the larger ones are reported "
+                         "on request (no oracle baseline, network trained on the run itself)")
     ap.add_argument("--sort-every", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-nn", action="store_true",
@@ -197,7 +214,7 @@ def main():
                     help="only run the streaming copy used to scale the HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
 
@@ -211,7 +228,8 @@ def main():
     import paper_2212_08836_amd as P
 
     torch.cuda.set_device(0)
-    w = E.workload("c2")
+    w = E.workload(args.workload)
+    print(f"# generating the {args.workload} particles", file=sys.stderr, flush=True)
     parts = E.make_particles(w)
     n0 = sum(len(p["r"]) for p in parts)
     ctx = P.context_from_workload(w, precision=args.precision)
@@ -219,7 +237,8 @@ def main():
     ctx.sort()
     mcc = w.mcc_params()
     ctx.set_mcc(mcc)
-    print(f"# bench: c2 256x128, {n0} particles, {args.precision}, warmup {args.warmup}, "
+    print(f"# bench: {args.workload} {w.nr}x{w.nz}, {n0} particles, {args.precision}, "
+          f"warmup {args.warmup}, "
           f"steps {args.steps}", file=sys.stderr, flush=True)
     ctx.run(args.warmup, tol=w.tol, sort_every=args.sort_every)
     torch.cuda.synchronize()
@@ -277,8 +296,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "VHF CCP slab 256x128 (R 0.15 m, L 3 cm), 4.19M particles, "
-                               "100 MHz 200 V, MCC 5 Pa",
+        "config": {"workload": WORKLOADS[args.workload],
                    "particles": n0, "grid": [w.nr, w.nz], "dt": w.dt, "tol": w.tol,
                    "precision": args.precision, "sort_every": args.sort_every,
                    "parallelism": "single GPU"},
@@ -289,7 +307,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": ("k_push_fast<double, false, true>" if args.precision == "fp64" else
                                 "k_push_fast<float, false, true>") + " (Picard iteration pass, both species)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(args.precision),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": committed_traffic(args.precision) if args.workload == "c2" else None,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms},
     }
     # first Picard residual of the plain (extrapolated) guess, for comparison
@@ -299,9 +318,9 @@ def main():
     out["first_residual_mean"] = float(np.mean(r0))
     if not args.no_nn and args.precision == "fp64":
         print("# mixed precision + learned guess", file=sys.stderr, flush=True)
-        out["mixed_nn"] = mixed_nn_leg(E, P, w, args.steps, args.warmup, args.sort_every,
-                                       out["ms_per_step"])
-    if not args.no_cpu:
+        out["mixed_nn"] = mixed_nn_leg(E, P, w, parts, args.steps, args.warmup, args.sort_every,
+                                       out["ms_per_step"], self_train=args.workload != "c2")
+    if not args.no_cpu and args.workload == "c2":
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, parts, mcc)
     print(json.dumps(out), flush=True)
