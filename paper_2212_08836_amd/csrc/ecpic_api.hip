@@ -417,8 +417,10 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
     }
     {
       Timed tm(c, commit ? ECPIC_K_COMMIT_SLOW : ECPIC_K_PUSH_SLOW, 0.0, 0);
-      HIPCHK(launch_push_slow(P, c.stream));
-      if (commit && with_mcc) HIPCHK(launch_collide_list(P, c.stream));
+      if (commit && with_mcc)
+        HIPCHK(launch_slow_collide(P, c.stream));
+      else
+        HIPCHK(launch_push_slow(P, c.stream));
     }
   }
   return ECPIC_OK;

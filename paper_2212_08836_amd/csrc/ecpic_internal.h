@@ -259,6 +259,9 @@ struct Ctx {
 // must be zero on entry.  tally points at kSpread copies.
 hipError_t launch_push_fast(const PassArgs& p, bool deposit, hipStream_t s);
 hipError_t launch_push_slow(const PassArgs& p, hipStream_t s);
+// the committing slow pass and the collisions of the listed particles, in
+// one launch
+hipError_t launch_slow_collide(const PassArgs& P, hipStream_t st);
 // commit pass with MCC: the collisions of the particles the fast pass listed
 hipError_t launch_collide_list(const PassArgs& p, hipStream_t s);
 // entries per queue segment for n particles: fast-pass block b queues into

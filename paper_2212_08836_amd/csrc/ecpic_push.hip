@@ -1361,9 +1361,9 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
 // entry is read before the segment count is known (within the segment's
 // capacity), so the two loads overlap.
 template <typename T, bool COMMIT>
-__global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
+__device__ __forceinline__ void slow_body(const PassArgs& P, int bx, int by, int ny) {
   if (P.a[0].stop && *P.a[0].stop) return;
-  const int slot = blockIdx.x / kSpread;
+  const int slot = bx / kSpread;
   const PushArgs& A = P.a[slot];
   const int32_t* queue = P.queue[slot];
   const int32_t* qcount = P.qcount[slot];
@@ -1372,16 +1372,16 @@ __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
   const SpecDev& s = A.s;
   const T qm = T(s.q / s.m);
   const double qw_dt = s.q * s.w / m.dt;
-  const int g = blockIdx.x % kSpread;
+  const int g = bx % kSpread;
   const int32_t* seg = queue + (int64_t)g * qseg;
-  int64_t q = (int64_t)blockIdx.y * kBlock + threadIdx.x;
+  int64_t q = (int64_t)by * kBlock + threadIdx.x;
   int32_t k_next = q < qseg ? seg[q] : 0;
   const int64_t nq = qcount[g * kLineInts];
   Tl t;
   tl_zero(t);
-  for (; q < nq; q += (int64_t)gridDim.y * kBlock) {
+  for (; q < nq; q += (int64_t)ny * kBlock) {
     const int64_t k = k_next;
-    if (q + (int64_t)gridDim.y * kBlock < nq) k_next = seg[q + (int64_t)gridDim.y * kBlock];
+    if (q + (int64_t)ny * kBlock < nq) k_next = seg[q + (int64_t)ny * kBlock];
     PState<T> p;
     if (!load_particle<T>(s, m, k, p)) continue;
     PushOut o;
@@ -1417,30 +1417,35 @@ __global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
       commit_one<T>(A, k, p, o.status, o.wall, t);
     }
   }
-  if (COMMIT) tl_flush(t, A.tally + ((blockIdx.x + blockIdx.y) % kSpread), s.sid);
+  if (COMMIT) tl_flush(t, A.tally + ((bx + by) % kSpread), s.sid);
+}
+
+template <typename T, bool COMMIT>
+__global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
+  slow_body<T, COMMIT>(P, blockIdx.x, blockIdx.y, gridDim.y);
 }
 
 // Collisions of the particles a committing fast pass listed (their pushed
 // state is already stored): grid (kSpread * slots, X), like the slow pass.  Particles born here are appended beyond the pass's start counts.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
-  const int slot = blockIdx.x / kSpread;
+__device__ __forceinline__ void collide_list_body(const PassArgs& P, int bx, int by, int ny) {
+  const int slot = bx / kSpread;
   const PushArgs& A = P.a[slot];
   const int32_t* queue = P.cqueue[slot];
   const int32_t* qcount = P.cqcount[slot];
   const int64_t qseg = P.qseg[slot];
   const MapP& m = A.m;
   const SpecDev& s = A.out;  // the pushed state, where the commit stored it
-  const int g = blockIdx.x % kSpread;
+  const int g = bx % kSpread;
   const int32_t* seg = queue + (int64_t)g * qseg;
-  int64_t q = (int64_t)blockIdx.y * kBlock + threadIdx.x;
+  int64_t q = (int64_t)by * kBlock + threadIdx.x;
   int32_t k_next = q < qseg ? seg[q] : 0;
   const int64_t nq = qcount[g * kLineInts];
   Tl t;
   tl_zero(t);
-  for (; q < nq; q += (int64_t)gridDim.y * kBlock) {
+  for (; q < nq; q += (int64_t)ny * kBlock) {
     const int64_t k = k_next;
-    if (q + (int64_t)gridDim.y * kBlock < nq) k_next = seg[q + (int64_t)gridDim.y * kBlock];
+    if (q + (int64_t)ny * kBlock < nq) k_next = seg[q + (int64_t)ny * kBlock];
     PState<T> p;
     if (!load_particle<T>(s, m, k, p)) continue;
     double vr = p.vr, vt = p.vt, vz = p.vz;
@@ -1456,7 +1461,24 @@ __global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
     p.vz = T(vz);
     store_particle<T>(s, m, k, p);
   }
-  tl_flush(t, A.tally + ((blockIdx.x + blockIdx.y) % kSpread), s.sid);
+  tl_flush(t, A.tally + ((bx + by) % kSpread), s.sid);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
+  collide_list_body<T>(P, blockIdx.x, blockIdx.y, gridDim.y);
+}
+
+// The committing slow pass and the collisions of the listed particles in
+// one launch (they touch different particles and are both latency-bound, so
+// running side by side hides one behind the other): blocks with
+// blockIdx.y < ny_slow take the slow role, the others the collision role.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_slow_collide(PassArgs P, int ny_slow) {
+  if ((int)blockIdx.y < ny_slow)
+    slow_body<T, true>(P, blockIdx.x, blockIdx.y, ny_slow);
+  else
+    collide_list_body<T>(P, blockIdx.x, blockIdx.y - ny_slow, gridDim.y - ny_slow);
 }
 
 // standalone collision pass over the live particles
@@ -1636,6 +1658,25 @@ hipError_t launch_collide_list(const PassArgs& P, hipStream_t st) {
     hipLaunchKernelGGL((k_collide_list<float>), gs, dim3(kBlock), 0, st, P);
   else
     hipLaunchKernelGGL((k_collide_list<double>), gs, dim3(kBlock), 0, st, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_slow_collide(const PassArgs& P, hipStream_t st) {
+  int64_t nmax = 0;
+  for (int q = 0; q < P.nsp; ++q) nmax = P.a[q].s.n > nmax ? P.a[q].s.n : nmax;
+  if (nmax <= 0) return hipSuccess;
+  if (P.a[0].commit == 0) return hipErrorInvalidValue;
+  const int64_t nb = (nmax + kBlock - 1) / kBlock;
+  // the slow pass and the collision list sized as in their own launches
+  int64_t xs = (nb / kSpread + 7) / 8;
+  xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
+  int64_t xc = (nb / kSpread + 15) / 16;
+  xc = xc < 1 ? 1 : (xc > 64 ? 64 : xc);
+  const dim3 gs((unsigned)(kSpread * P.nsp), (unsigned)(xs + xc), 1);
+  if (P.a[0].s.cell != nullptr)
+    hipLaunchKernelGGL((k_slow_collide<float>), gs, dim3(kBlock), 0, st, P, (int)xs);
+  else
+    hipLaunchKernelGGL((k_slow_collide<double>), gs, dim3(kBlock), 0, st, P, (int)xs);
   return hipGetLastError();
 }
 
