@@ -414,3 +414,36 @@ def test_run_matches_oracle_steps(og, torch_cuda):
     assert d["rc"] == P.ECPIC_ENOTCONV and d["done"] == 0
     ur1, uz1, h1 = ctx.get_fields()
     assert np.array_equal(ur, ur1) and np.array_equal(uz, uz1) and np.array_equal(h, h1)
+
+
+def test_run_driven_collisional_matches_oracle(og, torch_cuda):
+    # several steps in one call on the driven, collisional case: ionisation
+    # appends particles in most steps, and the next step's guess is enqueued
+    # before the host has read the appended counts
+    import paper_2212_08836_amd as P
+    _flush("run of 8 steps in one call vs the oracle, driven + MCC")
+    w = E.Workload("c2s", 48, 24, 0.03, 0.012, n0=1e16, profile="j0sin", ppc=12,
+                   drive_amp=(200.0,), drive_freq=(100e6,), pressure_pa=60.0, seed=12,
+                   dt=1e-11, tol=1e-10)
+    parts = E.make_particles(w)
+    parts[0]["vr"] *= 3.0
+    parts[0]["vt"] *= 3.0
+    parts[0]["vz"] *= 3.0
+    mcc = w.mcc_params()
+    g, sp, ctx = _make_pair(w, og, P, parts)
+    ctx.set_mcc(mcc)
+    st = og.State(g)
+    ion = 0
+    for n in range(8):
+        d_o = g.step(st, sp, mcc=mcc, tol=w.tol)
+        assert d_o["rc"] == 0
+        ion += d_o["n_ionized"]
+    d = ctx.run(8, tol=w.tol, sort_every=5, stats=True)
+    assert d["rc"] == 0 and d["done"] == 8 and d["iters"] == d_o["iters"]
+    ur, uz, h = ctx.get_fields()
+    errs = [_rel(ur, st.ur), _rel(uz, st.uz), _rel(h, st.h)]
+    for k in range(len(sp)):
+        errs.append(_cmp_species(ctx.read_particles(k), sp[k].view(), f"run sp {k}"))
+    _flush(f"  after 8 steps ({ion} ionisations): worst rel {max(errs):.2e}")
+    assert ion > 0
+    assert max(errs) < TOL
