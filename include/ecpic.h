@@ -129,7 +129,8 @@ ecpic_status ecpic_create(const ecpic_grid_desc* grid, ecpic_precision prec, voi
 ecpic_status ecpic_destroy(ecpic_ctx* ctx);
 
 /* Add a species with room for desc->capacity macro-particles (device memory
- * allocated here).  Up to 4 species.  *sid receives its index. */
+ * allocated here; at most 2^29 per species).  Up to 4 species.  *sid
+ * receives its index.  EINVAL for a bad descriptor or a fifth species. */
 ecpic_status ecpic_add_species(ecpic_ctx* ctx, const ecpic_species_desc* desc, int32_t* sid);
 
 /* Replace the particles of a species.  r, z: physical positions [m] inside

@@ -627,7 +627,9 @@ ecpic_status ecpic_add_species(ecpic_ctx* x, const ecpic_species_desc* d, int32_
   if (!x || !d || !sid) return ECPIC_EINVAL;
   Ctx& c = x->c;
   if ((int)c.sp.size() >= kMaxSpecies) return fail(c, ECPIC_EINVAL, "at most 4 species");
-  if (d->capacity < 0 || d->capacity > ((int64_t)1 << 31) - 1 || !(d->m > 0) || !(d->weight > 0))
+  // the kernels address particle arrays by 32-bit byte offsets: at most
+  // 2^29 slots of 8 bytes
+  if (d->capacity < 0 || d->capacity > ((int64_t)1 << 29) || !(d->m > 0) || !(d->weight > 0))
     return fail(c, ECPIC_EINVAL, "bad species descriptor");
   Species s;
   s.desc = *d;

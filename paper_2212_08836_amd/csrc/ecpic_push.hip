@@ -62,6 +62,19 @@ __device__ __forceinline__ float rcp_refined(float x) {
   return fmaf(y, fmaf(-x, y, 1.0f), y);
 }
 
+// Element access by a 32-bit byte offset from a uniform base, which the
+// loads and stores take as a scalar base plus one vector offset (no 64-bit
+// address arithmetic per array); species capacities keep every offset
+// below 4 GiB.
+template <typename V>
+__device__ __forceinline__ V& at32(V* base, uint32_t byte_off) {
+  return *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off);
+}
+template <typename V>
+__device__ __forceinline__ const V& at32(const V* base, uint32_t byte_off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 template <typename T>
 __device__ __forceinline__ T clamp01(T x) {
   return x < T(0) ? T(0) : (x > T(1) ? T(1) : x);
@@ -391,11 +404,12 @@ struct PushOut {
 template <typename T>
 __device__ __forceinline__ void load_field(const MapP& m, const T* __restrict__ ur,
                                            const T* __restrict__ uz, int i, int j, T F[4]) {
-  const T* pr = ur + (size_t)i * (m.nz + 1) + j;
-  F[0] = pr[0];
-  F[1] = pr[1];
-  F[2] = uz[(size_t)i * m.nz + j];
-  F[3] = uz[(size_t)(i + 1) * m.nz + j];
+  const uint32_t orr = (uint32_t)(i * (m.nz + 1) + j) * (uint32_t)sizeof(T);
+  const uint32_t oz = (uint32_t)(i * m.nz + j) * (uint32_t)sizeof(T);
+  F[0] = at32(ur, orr);
+  F[1] = at32(ur, orr + (uint32_t)sizeof(T));
+  F[2] = at32(uz, oz);
+  F[3] = at32(uz, oz + (uint32_t)(m.nz * (int)sizeof(T)));
 }
 
 // Push one particle over dt.  The first sub-step's deposit is returned in
@@ -842,19 +856,21 @@ struct Raw<float> {
   float a, b, vr, vt, vz;
 };
 __device__ __forceinline__ void fetch_raw(const SpecDev& s, int64_t k, Raw<double>& q) {
-  q.xi = s.xi[k];
-  q.eta = s.eta[k];
-  q.vr = s.vr[k];
-  q.vt = s.vt[k];
-  q.vz = s.vz[k];
+  const uint32_t o = (uint32_t)k * 8u;
+  q.xi = at32(s.xi, o);
+  q.eta = at32(s.eta, o);
+  q.vr = at32(s.vr, o);
+  q.vt = at32(s.vt, o);
+  q.vz = at32(s.vz, o);
 }
 __device__ __forceinline__ void fetch_raw(const SpecDev& s, int64_t k, Raw<float>& q) {
-  q.cell = s.cell[k];
-  q.a = s.fa[k];
-  q.b = s.fb[k];
-  q.vr = s.fvr[k];
-  q.vt = s.fvt[k];
-  q.vz = s.fvz[k];
+  const uint32_t o = (uint32_t)k * 4u;
+  q.cell = at32(s.cell, o);
+  q.a = at32(s.fa, o);
+  q.b = at32(s.fb, o);
+  q.vr = at32(s.fvr, o);
+  q.vt = at32(s.fvt, o);
+  q.vz = at32(s.fvz, o);
 }
 // same decoding as load_particle
 __device__ __forceinline__ bool decode_raw(const MapP& m, const Raw<double>& q, PState<double>& p) {
@@ -907,21 +923,23 @@ __device__ __forceinline__ void store_particle(const SpecDev& s, const MapP& m, 
 template <>
 __device__ __forceinline__ void store_particle<double>(const SpecDev& s, const MapP& m, int64_t k,
                                                        const PState<double>& p) {
-  s.xi[k] = double(p.i) + p.a;
-  s.eta[k] = double(p.j) + p.b;
-  s.vr[k] = p.vr;
-  s.vt[k] = p.vt;
-  s.vz[k] = p.vz;
+  const uint32_t o = (uint32_t)k * 8u;
+  at32(s.xi, o) = double(p.i) + p.a;
+  at32(s.eta, o) = double(p.j) + p.b;
+  at32(s.vr, o) = p.vr;
+  at32(s.vt, o) = p.vt;
+  at32(s.vz, o) = p.vz;
 }
 template <>
 __device__ __forceinline__ void store_particle<float>(const SpecDev& s, const MapP& m, int64_t k,
                                                       const PState<float>& p) {
-  s.cell[k] = p.i * m.nz + p.j;
-  s.fa[k] = p.a;
-  s.fb[k] = p.b;
-  s.fvr[k] = p.vr;
-  s.fvt[k] = p.vt;
-  s.fvz[k] = p.vz;
+  const uint32_t o = (uint32_t)k * 4u;
+  at32(s.cell, o) = p.i * m.nz + p.j;
+  at32(s.fa, o) = p.a;
+  at32(s.fb, o) = p.b;
+  at32(s.fvr, o) = p.vr;
+  at32(s.fvt, o) = p.vt;
+  at32(s.fvz, o) = p.vz;
 }
 
 // whether two views of a species are the same particle buffer (the uid
