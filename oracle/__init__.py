@@ -239,7 +239,7 @@ class Grid:
         return np.vectorize(lambda x: self._lib.og_jr_of_xi(self._h, float(x)))(xi)
 
     def xi_of_r(self, r):
-        return np.vectorize(lambda x: self._lib.og_xi_of_r(self._h, float(x)))(r)
+        return np.vectorize(lambda x: self._lib.og_xi_of_r(self._h, float(x)), otypes=[np.float64])(r)
 
     def drive(self, t: float) -> float:
         return self._lib.og_drive(self._h, float(t))

@@ -143,6 +143,87 @@ def test_push_deposit_parity_c1(og, torch_cuda):
     assert _rel(side, ost.wall_side) < TOL
 
 
+def _edge_particles(w):
+    """Hand-placed electrons on the c1 grid: on cell faces and corners
+    (moving out, in, along), in the square-root-map cells next to the axis
+    and at the axis itself, heading out through every wall, fast enough to
+    cross several cells in one step, and at rest.  The ions are empty."""
+    s = w.R / (w.nr + w.xi_a)
+    r_of = lambda xi: (2.0 * s * np.sqrt(xi * w.xi_a) if xi < w.xi_a else s * (xi + w.xi_a))
+    dz = w.L / w.nz
+    v = 4e6  # m/s: about 1.5 cells per 1e-11 s step radially in the linear cells
+    rows = []
+    for i, j in ((5, 7), (12, 3), (20, 28)):
+        # slow normal motion off the face: a particle exactly on a face with
+        # zero normal velocity, pushed out of both adjacent cells by their
+        # fields, has no admissible sub-step (both sides report a failed push)
+        for dv in ((v, 0, v), (-v, 0, -v), (1e3, 0, v), (v, 0, -1e3), (-1e3, v, 1e3)):
+            rows.append((r_of(i), (j + 0.5) * dz) + dv)           # on an r-face
+            rows.append((r_of(i + 0.5), j * dz) + dv)             # on a z-face
+            rows.append((r_of(i), j * dz) + dv)                   # on a corner
+    for xi in (1e-6, 0.3, 1.0, 1.7, 2.0, 2.4):                   # near the axis
+        for dv in ((-v, 0, 0.3 * v), (v, 0.5 * v, 0), (-0.2 * v, 2 * v, -v)):
+            rows.append((r_of(xi), 0.37 * w.L) + dv)
+    rows.append((r_of(w.nr - 0.1), 0.5 * w.L, 3 * v, 0, 0))      # out through the side wall
+    rows.append((r_of(9.5), 0.1 * dz, 0, 0, -3 * v))              # the bottom electrode
+    rows.append((r_of(9.5), w.L - 0.1 * dz, 0, 0, 3 * v))         # the top electrode
+    rows.append((r_of(w.nr - 0.05), 0.05 * dz, 2 * v, 0, -2 * v))  # a corner
+    rows.append((r_of(14.25), 0.5 * w.L, 4 * v, v, 4 * v))        # several cells at once
+    rows.append((r_of(14.25), 0.25 * w.L, 0, 0, 0))               # at rest
+    a = np.array(rows, dtype=np.float64)
+    base = E.make_particles(w)
+    e = dict(q=base[0]["q"], m=base[0]["m"], w=base[0]["w"], r=a[:, 0].copy(), z=a[:, 1].copy(),
+             vr=a[:, 2].copy(), vt=a[:, 3].copy(), vz=a[:, 4].copy(),
+             uid=np.arange(len(a), dtype=np.uint64))
+    empty = dict(q=base[1]["q"], m=base[1]["m"], w=base[1]["w"],
+                 **{k: np.zeros(0) for k in ("r", "z", "vr", "vt", "vz")},
+                 uid=np.zeros(0, dtype=np.uint64))
+    return [e, empty]
+
+
+def test_push_deposit_edge_cases(og, torch_cuda):
+    import paper_2212_08836_amd as P
+    _flush("push_deposit parity, edge cases")
+    w = E.workload("c1")
+    parts = _edge_particles(w)
+    g, sp, ctx = _make_pair(w, og, P, parts)
+    rng = np.random.default_rng(5)
+    nr, nz = w.nr, w.nz
+    urh = rng.standard_normal(nr * (nz + 1)) * 2.0
+    uzh = rng.standard_normal((nr + 1) * nz) * 2.0
+    urh.reshape(nr, nz + 1)[:, [0, -1]] = 0
+    uzh.reshape(nr + 1, nz)[-1] = 0
+    ctx.set_half_field(urh, uzh)
+    Ir_g, Iz_g = ctx.push_deposit(commit=False)
+    Ir_o, Iz_o = g.zeros_r(), g.zeros_z()
+    cross = 0
+    for s in sp:
+        _, _, rc, st = g.push_deposit(s, urh, uzh, commit=False, Ir=Ir_o, Iz=Iz_o)
+        assert rc == 0
+        cross += st["n_crossings"]
+    _flush(f"  {len(parts[0]['r'])} electrons, {cross} face crossings")
+    assert cross >= 20  # 27 with these particles and fields
+    assert _rel(Ir_g, Ir_o) < TOL and _rel(Iz_g, Iz_o) < TOL
+    Ir_g, Iz_g = ctx.push_deposit(commit=True)
+    ost = og.State(g)
+    for s in sp:
+        g.push_deposit(s, urh, uzh, commit=True, state=ost)
+    assert _cmp_species(ctx.read_particles(0), sp[0].view(), "edge electrons") < TOL
+    assert len(ctx.read_particles(1)["xi"]) == 0
+    q, bot, top, side = ctx.node_charge()
+    assert _rel(bot, ost.wall_bot) < TOL and _rel(top, ost.wall_top) < TOL
+    assert _rel(side, ost.wall_side) < TOL
+    assert np.abs(side).max() > 0 and np.abs(bot).max() > 0 and np.abs(top).max() > 0
+
+
+def test_step_parity_edge_cases(og, torch_cuda):
+    # whole steps with the same particles (one species empty throughout)
+    import paper_2212_08836_amd as P
+    _flush("step parity, edge cases")
+    w = E.workload("c1")
+    _step_parity(og, P, w, _edge_particles(w), 3)
+
+
 def _step_parity(og, P, w, parts, nsteps, mcc=None, sort_every=0, mobile=(True, True)):
     g, sp, ctx = _make_pair(w, og, P, parts, mobile=mobile)
     st = og.State(g)
