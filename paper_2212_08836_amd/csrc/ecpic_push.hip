@@ -391,15 +391,40 @@ __device__ __forceinline__ void atomic_dep(double* Ir, double* Iz, int nz, int i
 
 enum { kAlive = 0, kAbsorbed = 1, kError = 2 };
 
+// Sub-step deposits a push holds in registers for its caller to issue after
+// the push: those of the first two sub-steps (a third is the last one for
+// nearly every particle, and nothing is loaded after the last).
 struct PushOut {
   int status;
   int wall;           // 1 bottom, 2 top, 3 side
   int nsub, ncross;
-  bool have_first;    // first sub-step deposit held for the wave reduction
-  int fi, fj;         // its cell
-  Dep first;
+  int nheld;          // held sub-step deposits (0, 1 or 2)
+  int i0, j0, i1, j1; // their cells
+  Dep d0, d1;
   double work;        // sum of q w E.dx over sub-steps (in units of J)
 };
+
+// Issue the deposits a push held: all addresses first, then the atomics
+// back to back.
+__device__ __forceinline__ void flush_held(double* Ir, double* Iz, int nz, const PushOut& o) {
+  if (!Ir || o.nheld == 0) return;
+  const bool h1 = o.nheld > 1;
+  const int i1 = h1 ? o.i1 : o.i0, j1 = h1 ? o.j1 : o.j0;
+  double* r0 = Ir + (size_t)o.i0 * (nz + 1) + o.j0;
+  double* r1 = Ir + (size_t)i1 * (nz + 1) + j1;
+  double* z0 = Iz + (size_t)o.i0 * nz + o.j0;
+  double* z1 = Iz + (size_t)i1 * nz + j1;
+  unsafeAtomicAdd(r0, o.d0.r0);
+  unsafeAtomicAdd(r0 + 1, o.d0.r1);
+  unsafeAtomicAdd(z0, o.d0.z0);
+  unsafeAtomicAdd(z0 + nz, o.d0.z1);
+  if (h1) {
+    unsafeAtomicAdd(r1, o.d1.r0);
+    unsafeAtomicAdd(r1 + 1, o.d1.r1);
+    unsafeAtomicAdd(z1, o.d1.z0);
+    unsafeAtomicAdd(z1 + nz, o.d1.z1);
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ void load_field(const MapP& m, const T* __restrict__ ur,
@@ -412,9 +437,13 @@ __device__ __forceinline__ void load_field(const MapP& m, const T* __restrict__ 
   F[3] = at32(uz, oz + (uint32_t)(m.nz * (int)sizeof(T)));
 }
 
-// Push one particle over dt.  The first sub-step's deposit is returned in
-// `out.first` (for the caller's wavefront reduction); later ones go to
-// global atomics directly.
+// Push one particle over dt.  The deposits of the first two sub-steps are
+// returned in `out` for the caller to issue once the push is done: vector
+// loads and stores (atomics included) retire in issue order on one counter,
+// so a field load issued after an atomic that is still in flight waits for
+// that atomic (several microseconds for device-wide FP64 atomics), and
+// sub-steps that each deposited at once would each pay that round trip.
+// Later sub-steps deposit at once.
 template <typename T>
 __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* __restrict__ uz,
                               double* Ir, double* Iz, PState<T>& p, T qm, double qw_dt,
@@ -423,7 +452,7 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
   out.wall = 0;
   out.nsub = 0;
   out.ncross = 0;
-  out.have_first = false;
+  out.nheld = 0;
   out.work = 0.0;
   const int nr = m.nr, nz = m.nz;
   T tau = T(m.dt);
@@ -461,6 +490,27 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
     } else {
       load_field(m, ur, uz, p.i, p.j, F);
     }
+    // the field of the neighbour the particle is expected to enter next,
+    // guessed from free flight over the rest of the step (the linear-map
+    // scale in xi; the xi face first when both are left) and loaded now, so
+    // that the load overlaps this sub-step's solves
+    {
+      const T ea0 = p.a + tau * p.vr * T(m.inv_s), eb0 = p.b + tau * p.vz * T(m.inv_dz);
+      const bool ix0 = ea0 >= T(0) && ea0 <= T(1), ie0 = eb0 >= T(0) && eb0 <= T(1);
+      pf_i = -1;
+      if (!(ix0 && ie0)) {
+        int ni = p.i, nj = p.j;
+        if (!ix0)
+          ni += ea0 < T(0) ? -1 : 1;
+        else
+          nj += eb0 < T(0) ? -1 : 1;
+        if (ni >= 0 && ni < nr && nj >= 0 && nj < nz) {
+          load_field(m, ur, uz, ni, nj, Fn);
+          pf_i = ni;
+          pf_j = nj;
+        }
+      }
+    }
     T dtry = tau;
     Mid<T> M;
     // linear-map cells: the closed-form solve (the same mid point as the
@@ -478,17 +528,16 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
     const T ea = T(2) * M.a - p.a, eb = T(2) * M.b - p.b;
     const bool in_x = ea >= T(0) && ea <= T(1);
     const bool in_e = eb >= T(0) && eb <= T(1);
-    // prefetch the field of the neighbour across the face the free orbit
-    // leaves by (the xi face when both are left); used only if the
-    // particle is in that cell at the next sub-step
-    pf_i = -1;
+    // the neighbour across the face the solved free orbit leaves by (the xi
+    // face when both are left): loaded here unless the guess above was it;
+    // used only if the particle is in that cell at the next sub-step
     if (!(in_x && in_e)) {
       int ni = p.i, nj = p.j;
       if (!in_x)
         ni += ea < T(0) ? -1 : 1;
       else
         nj += eb < T(0) ? -1 : 1;
-      if (ni >= 0 && ni < nr && nj >= 0 && nj < nz) {
+      if (ni >= 0 && ni < nr && nj >= 0 && nj < nz && !(ni == pf_i && nj == pf_j)) {
         load_field(m, ur, uz, ni, nj, Fn);
         pf_i = ni;
         pf_j = nj;
@@ -555,11 +604,16 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
       out.work += m.dt * (dp.r0 * double(F[0]) + dp.r1 * double(F[1]) + dp.z0 * double(F[2]) +
                           dp.z1 * double(F[3]));
     }
-    if (!out.have_first && out.nsub == 1) {
-      out.have_first = true;
-      out.fi = p.i;
-      out.fj = p.j;
-      out.first = dp;
+    if (out.nheld == 0) {
+      out.i0 = p.i;
+      out.j0 = p.j;
+      out.d0 = dp;
+      out.nheld = 1;
+    } else if (out.nheld == 1) {
+      out.i1 = p.i;
+      out.j1 = p.j;
+      out.d1 = dp;
+      out.nheld = 2;
     } else {
       atomic_dep(Ir, Iz, nz, p.i, p.j, dp);
     }
@@ -983,10 +1037,12 @@ __device__ __forceinline__ void tl_zero(Tl& t) {
   t.absorbed = t.coll = t.ion = t.err = t.over = t.ovf = t.nsub = t.ncross = 0;
 }
 
+template <int kThreads = kBlock>
 __device__ void tl_flush(const Tl& t, Tally* tally, int sid) {
   // wavefront sums, one barrier, then one atomic per non-zero field
-  __shared__ double red_d[kBlock / 64][3];
-  __shared__ unsigned red_u[kBlock / 64][8];
+  constexpr int kW = kThreads / 64;
+  __shared__ double red_d[kW][3];
+  __shared__ unsigned red_u[kW][8];
   double d[3] = {t.work, t.dke_abs, t.dke_coll};
   unsigned u[8] = {t.absorbed, t.coll, t.ion, t.err, t.over, t.ovf, t.nsub, t.ncross};
 #pragma unroll
@@ -1007,12 +1063,12 @@ __device__ void tl_flush(const Tl& t, Tally* tally, int sid) {
   const int f = threadIdx.x;
   if (f < 3) {
     double sd = 0.0;
-    for (int k = 0; k < kBlock / 64; ++k) sd += red_d[k][f];
+    for (int k = 0; k < kW; ++k) sd += red_d[k][f];
     double* dst = f == 0 ? &tally->w_particles : (f == 1 ? &tally->w_absorbed : &tally->w_coll);
     if (sd != 0.0) unsafeAtomicAdd(dst, sd);
   } else if (f < 11) {
     unsigned long long su = 0;
-    for (int k = 0; k < kBlock / 64; ++k) su += red_u[k][f - 3];
+    for (int k = 0; k < kW; ++k) su += red_u[k][f - 3];
     unsigned long long* dst;
     switch (f - 3) {
       case 0: dst = &tally->n_absorbed[sid]; break;
@@ -1182,7 +1238,7 @@ __device__ __forceinline__ bool commit_store(const PushArgs& A, int64_t k, const
 // in its cell.  Those that stay in the closed cell are done (this is exactly
 // the first sub-step of the full algorithm); their currents are gathered in
 // the block's LDS tile and flushed once per block.  The others are queued
-// for k_push_slow.  A block takes kPerThread particles per thread,
+// for the slow pass.  A block takes kPerThread particles per thread,
 // consecutive in memory (sorted by cell after a sort), strided by kBlock.
 // Grid (blocks of the larger slot, slots): blockIdx.y is the species slot.
 // Dynamic LDS: tile_r_len(nz) + tile_z_len(nz) doubles.
@@ -1322,7 +1378,7 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
     }
     if (COMMIT) {
       // in-cell particles are stored as pushed; those the null-collision
-      // draw selects go to the collision list (k_collide_list)
+      // draw selects go to the collision list
       bool coll = false;
       if (alive && !slow) coll = commit_store<T>(A, k, p);
       // into the other buffer: dead slots stay dead there
@@ -1369,134 +1425,197 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   tl_flush(t, A.tally + (blockIdx.x % kSpread), s.sid);
 }
 
-// Slow pass over the queued particles: the full push with splitting at every
+// Queue passes: the slow pass over the particles the fast pass queued, the
+// collisions of the particles a committing fast pass listed, or both in one
+// launch.  A pass has roles (the slow queue or the collision list of a
+// slot); the entries of each role's kSpread segments are read as one list
+// in segment order, the lists of the roles follow each other, and
+// wavefront w takes entries [64 u, 64 u + 64) of the whole for
+// u = w, w + W, ... (W wavefronts).  Blocks are one wavefront, so the work
+// lands on the first wavefronts of the grid, spread over every XCD and
+// compute unit: the pass is latency-bound (one particle per lane, a chain of
+// dependent FP64 steps per face crossing), and a SIMD that runs two such
+// wavefronts runs each more slowly.
+static_assert(kSpread == 64, "one queue segment per lane");
+constexpr int kQThreads = 64;
+
+struct QView {
+  int excl;   // lane g: entries in segments before g
+  int total;  // entries in all segments
+};
+
+__device__ __forceinline__ QView queue_view(const int32_t* qcount) {
+  const int lane = threadIdx.x & 63;
+  const int c = qcount[lane * kLineInts];
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  QView q;
+  q.excl = incl - c;
+  q.total = __builtin_amdgcn_readlane(incl, 63);  // uniform: the role loop stays scalar
+  return q;
+}
+
+// Position in the queue buffer of list entry e < total: the last segment
+// whose exclusive prefix is <= e (empty segments before it share its
+// prefix), at offset e - prefix.  All lanes must be active.
+__device__ __forceinline__ int64_t queue_pos(const QView& q, int e, int64_t qseg) {
+  int g = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1) {
+    const int cand = g + step;
+    const int v = __shfl(q.excl, cand & 63, 64);
+    if (cand < 64 && v <= e) g = cand;
+  }
+  return (int64_t)g * qseg + (e - __shfl(q.excl, g, 64));
+}
+
+// Slow pass of one queued particle: the full push with splitting at every
 // face crossing (restarted from the particle's state), currents by atomics.
-// grid (kSpread * slots, X): blocks with blockIdx.x = g + kSpread * slot walk
-// segment g of the queue of that slot.  Blocks are dispatched in grid order,
-// so with the segment and slot fastest the blocks that have work (low
-// blockIdx.y) of every species start first instead of queueing behind idle
-// ones.  The first queue
-// entry is read before the segment count is known (within the segment's
-// capacity), so the two loads overlap.
 template <typename T, bool COMMIT>
-__device__ __forceinline__ void slow_body(const PassArgs& P, int bx, int by, int ny) {
-  if (P.a[0].stop && *P.a[0].stop) return;
-  const int slot = bx / kSpread;
-  const PushArgs& A = P.a[slot];
-  const int32_t* queue = P.queue[slot];
-  const int32_t* qcount = P.qcount[slot];
-  const int64_t qseg = P.qseg[slot];
+__device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, Tl& t) {
   const MapP& m = A.m;
   const SpecDev& s = A.s;
-  const T qm = T(s.q / s.m);
+  PState<T> p;
+  if (!load_particle<T>(s, m, k, p)) return;
   const double qw_dt = s.q * s.w / m.dt;
-  const int g = bx % kSpread;
-  const int32_t* seg = queue + (int64_t)g * qseg;
-  int64_t q = (int64_t)by * kBlock + threadIdx.x;
-  int32_t k_next = q < qseg ? seg[q] : 0;
-  const int64_t nq = qcount[g * kLineInts];
-  Tl t;
-  tl_zero(t);
-  for (; q < nq; q += (int64_t)ny * kBlock) {
-    const int64_t k = k_next;
-    if (q + (int64_t)ny * kBlock < nq) k_next = seg[q + (int64_t)ny * kBlock];
-    PState<T> p;
-    if (!load_particle<T>(s, m, k, p)) continue;
-    PushOut o;
-    if constexpr (sizeof(T) == 4) {
-      // mixed path: the few face crossers are pushed in FP64 arithmetic
-      // (in the FP64 half-step field) from their FP32 state and stored back
-      // rounded, so that their currents vary smoothly with the field
-      PState<double> pd;
-      pd.i = p.i;
-      pd.j = p.j;
-      pd.a = p.a;
-      pd.b = p.b;
-      pd.vr = p.vr;
-      pd.vt = p.vt;
-      pd.vz = p.vz;
-      push_particle<double>(m, A.ur, A.uz, A.Ir, A.Iz, pd, s.q / s.m, qw_dt, COMMIT, o);
-      p.i = pd.i;
-      p.j = pd.j;
-      p.a = T(pd.a);
-      p.b = T(pd.b);
-      p.vr = T(pd.vr);
-      p.vt = T(pd.vt);
-      p.vz = T(pd.vz);
-    } else {
-      push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, p, qm, qw_dt,
-                       COMMIT, o);
-    }
-    if (o.have_first) atomic_dep(A.Ir, A.Iz, m.nz, o.fi, o.fj, o.first);
-    if (COMMIT) {
-      t.work += o.work;
-      t.nsub += o.nsub;
-      t.ncross += o.ncross;
-      commit_one<T>(A, k, p, o.status, o.wall, t);
-    }
+  PushOut o;
+  if constexpr (sizeof(T) == 4) {
+    // mixed path: the few face crossers are pushed in FP64 arithmetic
+    // (in the FP64 half-step field) from their FP32 state and stored back
+    // rounded, so that their currents vary smoothly with the field
+    PState<double> pd;
+    pd.i = p.i;
+    pd.j = p.j;
+    pd.a = p.a;
+    pd.b = p.b;
+    pd.vr = p.vr;
+    pd.vt = p.vt;
+    pd.vz = p.vz;
+    push_particle<double>(m, A.ur, A.uz, A.Ir, A.Iz, pd, s.q / s.m, qw_dt, COMMIT, o);
+    p.i = pd.i;
+    p.j = pd.j;
+    p.a = T(pd.a);
+    p.b = T(pd.b);
+    p.vr = T(pd.vr);
+    p.vt = T(pd.vt);
+    p.vz = T(pd.vz);
+  } else {
+    push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, p, T(s.q / s.m),
+                     qw_dt, COMMIT, o);
   }
-  if (COMMIT) tl_flush(t, A.tally + ((bx + by) % kSpread), s.sid);
+  flush_held(A.Ir, A.Iz, m.nz, o);
+  if (COMMIT) {
+    t.work += o.work;
+    t.nsub += o.nsub;
+    t.ncross += o.ncross;
+    commit_one<T>(A, k, p, o.status, o.wall, t);
+  }
 }
 
-template <typename T, bool COMMIT>
-__global__ void __launch_bounds__(kBlock) k_push_slow(PassArgs P) {
-  slow_body<T, COMMIT>(P, blockIdx.x, blockIdx.y, gridDim.y);
-}
-
-// Collisions of the particles a committing fast pass listed (their pushed
-// state is already stored): grid (kSpread * slots, X), like the slow pass.  Particles born here are appended beyond the pass's start counts.
+// Collision of one listed particle (its pushed state is already stored).
+// Particles born here are appended beyond the pass's start counts.
 template <typename T>
-__device__ __forceinline__ void collide_list_body(const PassArgs& P, int bx, int by, int ny) {
-  const int slot = bx / kSpread;
-  const PushArgs& A = P.a[slot];
-  const int32_t* queue = P.cqueue[slot];
-  const int32_t* qcount = P.cqcount[slot];
-  const int64_t qseg = P.qseg[slot];
+__device__ __forceinline__ void listed_one(const PushArgs& A, int64_t k, Tl& t) {
   const MapP& m = A.m;
   const SpecDev& s = A.out;  // the pushed state, where the commit stored it
-  const int g = bx % kSpread;
-  const int32_t* seg = queue + (int64_t)g * qseg;
-  int64_t q = (int64_t)by * kBlock + threadIdx.x;
-  int32_t k_next = q < qseg ? seg[q] : 0;
-  const int64_t nq = qcount[g * kLineInts];
+  PState<T> p;
+  if (!load_particle<T>(s, m, k, p)) return;
+  double vr = p.vr, vt = p.vt, vz = p.vz;
+  const CollOut co = collide_one<T>(A.mcc, s, m, s.sid, s.uid[k], p.i, p.j, p.a, p.b, vr, vt, vz,
+                                    A.tally);
+  t.dke_coll += co.dke;
+  t.coll += co.coll;
+  t.ion += co.ionized;
+  t.over += co.over;
+  t.ovf += co.overflow;
+  p.vr = T(vr);
+  p.vt = T(vt);
+  p.vz = T(vz);
+  store_particle<T>(s, m, k, p);
+}
+
+// MODE 0: slow pass (roles: the slots' queues); 1: committing slow pass;
+// 2: collision lists; 3: committing slow pass then collision lists (2 slots
+// roles).  The slow roles do nothing once the residual has stopped the
+// iteration.  Grid: 1-D, one wavefront per block.
+enum { kQSlow = 0, kQSlowCommit = 1, kQCollide = 2, kQSlowCollide = 3 };
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kQThreads, 2) k_queue(PassArgs P) {
+  const bool stopped = P.a[0].stop && *P.a[0].stop;
+  if (MODE == kQSlow && stopped) return;
+  constexpr int kMaxRoles = MODE == kQSlowCollide ? 4 : 2;
+  const int nroles = MODE == kQSlowCollide ? 2 * P.nsp : P.nsp;
+  const int lane = threadIdx.x;
+  constexpr bool kTally = MODE != kQSlow;
+  // every role's view up front: its counter loads then precede the
+  // particle work, whose deposit atomics a later load would wait for
+  QView vw[kMaxRoles];
+#pragma unroll
+  for (int r = 0; r < kMaxRoles; ++r) {
+    vw[r].excl = 0;
+    vw[r].total = 0;
+    if (r < nroles) {
+      const int sl = r % P.nsp;
+      const bool sw = MODE == kQCollide ? false : (MODE == kQSlowCollide ? r < P.nsp : true);
+      if (!(sw && stopped)) vw[r] = queue_view(sw ? P.qcount[sl] : P.cqcount[sl]);
+    }
+  }
+  int role = 0;
+  int64_t base = 0;  // units of the roles before `role`
+  bool worked = false;
   Tl t;
   tl_zero(t);
-  for (; q < nq; q += (int64_t)ny * kBlock) {
-    const int64_t k = k_next;
-    if (q + (int64_t)ny * kBlock < nq) k_next = seg[q + (int64_t)ny * kBlock];
-    PState<T> p;
-    if (!load_particle<T>(s, m, k, p)) continue;
-    double vr = p.vr, vt = p.vt, vz = p.vz;
-    const CollOut co = collide_one<T>(A.mcc, s, m, s.sid, s.uid[k], p.i, p.j, p.a, p.b, vr, vt, vz,
-                                      A.tally);
-    t.dke_coll += co.dke;
-    t.coll += co.coll;
-    t.ion += co.ionized;
-    t.over += co.over;
-    t.ovf += co.overflow;
-    p.vr = T(vr);
-    p.vt = T(vt);
-    p.vz = T(vz);
-    store_particle<T>(s, m, k, p);
+  for (int64_t u = blockIdx.x;; u += gridDim.x) {
+    // wavefront-uniform: the role of unit u
+    QView v = vw[0];
+#pragma unroll
+    for (int r = 1; r < kMaxRoles; ++r)
+      if (role == r) v = vw[r];
+    while (role < nroles && u >= base + (v.total + 63) / 64) {
+      if (kTally && worked) {
+        const PushArgs& A = P.a[role % P.nsp];
+        tl_flush<kQThreads>(t, A.tally + (blockIdx.x % kSpread), A.s.sid);
+        tl_zero(t);
+        worked = false;
+      }
+      base += (v.total + 63) / 64;
+      ++role;
+#pragma unroll
+      for (int r = 1; r < kMaxRoles; ++r)
+        if (role == r) v = vw[r];
+    }
+    if (role >= nroles) break;
+    // uniform by construction; said so, so that the slot's arguments are
+    // read by scalar loads and kept in scalar registers
+    role = __builtin_amdgcn_readfirstlane(role);
+    const int slot = role % P.nsp;
+    const bool slow = MODE == kQCollide ? false : (MODE == kQSlowCollide ? role < P.nsp : true);
+    const int64_t e = (u - base) * 64 + lane;
+    const int64_t pos = queue_pos(v, (int)(e < v.total ? e : v.total - 1), P.qseg[slot]);
+    worked = true;
+    if (e >= v.total) continue;
+    const PushArgs& A = P.a[slot];
+    if (MODE != kQCollide && slow) {
+      slow_one<T, MODE != kQSlow>(A, P.queue[slot][pos], t);
+    } else if (MODE != kQSlow) {
+      listed_one<T>(A, P.cqueue[slot][pos], t);
+    }
   }
-  tl_flush(t, A.tally + ((bx + by) % kSpread), s.sid);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_collide_list(PassArgs P) {
-  collide_list_body<T>(P, blockIdx.x, blockIdx.y, gridDim.y);
-}
-
-// The committing slow pass and the collisions of the listed particles in
-// one launch (they touch different particles and are both latency-bound, so
-// running side by side hides one behind the other): blocks with
-// blockIdx.y < ny_slow take the slow role, the others the collision role.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_slow_collide(PassArgs P, int ny_slow) {
-  if ((int)blockIdx.y < ny_slow)
-    slow_body<T, true>(P, blockIdx.x, blockIdx.y, ny_slow);
-  else
-    collide_list_body<T>(P, blockIdx.x, blockIdx.y - ny_slow, gridDim.y - ny_slow);
+// wavefronts (one-wavefront blocks) of a queue pass over slots of at most
+// nmax particles: enough for 1/16 of them in one round (more loop); a
+// multiple of 8 XCDs
+inline unsigned queue_grid(int64_t nmax, int nsp) {
+  int64_t w = (nmax * nsp) / 1024;
+  w = w < 64 ? 64 : w;
+  w = (w + 7) / 8 * 8;
+  return (unsigned)(w > (1 << 30) ? (1 << 30) : w);
 }
 
 // standalone collision pass over the live particles
@@ -1664,62 +1783,45 @@ hipError_t launch_push_fast(const PassArgs& P, bool deposit, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_collide_list(const PassArgs& P, hipStream_t st) {
+namespace {
+int64_t max_slot_n(const PassArgs& P) {
   int64_t nmax = 0;
   for (int q = 0; q < P.nsp; ++q) nmax = P.a[q].s.n > nmax ? P.a[q].s.n : nmax;
-  if (nmax <= 0) return hipSuccess;
-  const int64_t nb = (nmax + kBlock - 1) / kBlock;
-  int64_t xs = (nb / kSpread + 15) / 16;
-  xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
-  const dim3 gs((unsigned)(kSpread * P.nsp), (unsigned)xs, 1);
+  return nmax;
+}
+
+template <int MODE>
+void launch_queue(const PassArgs& P, int64_t nmax, hipStream_t st) {
+  const dim3 gs(queue_grid(nmax, P.nsp), 1, 1);
   if (P.a[0].s.cell != nullptr)
-    hipLaunchKernelGGL((k_collide_list<float>), gs, dim3(kBlock), 0, st, P);
+    hipLaunchKernelGGL((k_queue<float, MODE>), gs, dim3(kQThreads), 0, st, P);
   else
-    hipLaunchKernelGGL((k_collide_list<double>), gs, dim3(kBlock), 0, st, P);
+    hipLaunchKernelGGL((k_queue<double, MODE>), gs, dim3(kQThreads), 0, st, P);
+}
+}  // namespace
+
+hipError_t launch_collide_list(const PassArgs& P, hipStream_t st) {
+  const int64_t nmax = max_slot_n(P);
+  if (nmax <= 0) return hipSuccess;
+  launch_queue<kQCollide>(P, nmax, st);
   return hipGetLastError();
 }
 
 hipError_t launch_slow_collide(const PassArgs& P, hipStream_t st) {
-  int64_t nmax = 0;
-  for (int q = 0; q < P.nsp; ++q) nmax = P.a[q].s.n > nmax ? P.a[q].s.n : nmax;
+  const int64_t nmax = max_slot_n(P);
   if (nmax <= 0) return hipSuccess;
   if (P.a[0].commit == 0) return hipErrorInvalidValue;
-  const int64_t nb = (nmax + kBlock - 1) / kBlock;
-  // the slow pass and the collision list sized as in their own launches
-  int64_t xs = (nb / kSpread + 7) / 8;
-  xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
-  int64_t xc = (nb / kSpread + 15) / 16;
-  xc = xc < 1 ? 1 : (xc > 64 ? 64 : xc);
-  const dim3 gs((unsigned)(kSpread * P.nsp), (unsigned)(xs + xc), 1);
-  if (P.a[0].s.cell != nullptr)
-    hipLaunchKernelGGL((k_slow_collide<float>), gs, dim3(kBlock), 0, st, P, (int)xs);
-  else
-    hipLaunchKernelGGL((k_slow_collide<double>), gs, dim3(kBlock), 0, st, P, (int)xs);
+  launch_queue<kQSlowCollide>(P, nmax, st);
   return hipGetLastError();
 }
 
 hipError_t launch_push_slow(const PassArgs& P, hipStream_t st) {
-  int64_t nmax = 0;
-  for (int q = 0; q < P.nsp; ++q) nmax = P.a[q].s.n > nmax ? P.a[q].s.n : nmax;
+  const int64_t nmax = max_slot_n(P);
   if (nmax <= 0) return hipSuccess;
-  const int64_t nb = (nmax + kBlock - 1) / kBlock;
-  // per segment enough blocks for a few percent of the particles
-  int64_t xs = (nb / kSpread + 7) / 8;
-  xs = xs < 1 ? 1 : (xs > 64 ? 64 : xs);
-  const dim3 gs((unsigned)(kSpread * P.nsp), (unsigned)xs, 1);
-  const bool mixed = (P.a[0].s.cell != nullptr);
-  const bool commit = P.a[0].commit != 0;
-  if (!mixed) {
-    if (commit)
-      hipLaunchKernelGGL((k_push_slow<double, true>), gs, dim3(kBlock), 0, st, P);
-    else
-      hipLaunchKernelGGL((k_push_slow<double, false>), gs, dim3(kBlock), 0, st, P);
-  } else {
-    if (commit)
-      hipLaunchKernelGGL((k_push_slow<float, true>), gs, dim3(kBlock), 0, st, P);
-    else
-      hipLaunchKernelGGL((k_push_slow<float, false>), gs, dim3(kBlock), 0, st, P);
-  }
+  if (P.a[0].commit != 0)
+    launch_queue<kQSlowCommit>(P, nmax, st);
+  else
+    launch_queue<kQSlow>(P, nmax, st);
   return hipGetLastError();
 }
 
