@@ -562,17 +562,20 @@ __global__ void __launch_bounds__(256) k_converge(const double* __restrict__ par
   }
 }
 
-// Commit summary: the tally copies and the exchange partials reduced by one
-// wavefront in a fixed butterfly order (deterministic), the drive-gap
-// values, and the sequence number stored last after a system-scope fence.
+// Commit summary: the tally copies summed word by word (lane f adds word f of
+// the 64 copies in copy order: independent loads, no cross-lane steps), the
+// exchange partials reduced by one wavefront in a fixed butterfly order (both
+// deterministic), the drive-gap values, and the sequence number stored last
+// after a system-scope fence.
 __device__ __forceinline__ double wsum_d(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
-__device__ __forceinline__ unsigned long long wsum_u(unsigned long long v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+
+constexpr int kTallyWords = (int)(sizeof(Tally) / sizeof(uint64_t));
+constexpr int kTallyDoubles = 4;  // w_absorbed, w_coll, w_particles, pad lead the record
+static_assert(sizeof(Tally) % sizeof(uint64_t) == 0 && kTallyWords <= 64, "one word per lane");
+static_assert(offsetof(Tally, n_absorbed) == kTallyDoubles * sizeof(double), "doubles first");
 
 __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally,
                                                  const double* __restrict__ xpart,
@@ -583,28 +586,24 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
                                                  double* __restrict__ wall_tot, uint64_t seq,
                                                  StepFinal* out, const int32_t* __restrict__ conv,
                                                  int want_k) {
-  static_assert(kSpread == 64, "one tally copy per lane");
+  static_assert(kSpread == 64, "64 tally copies");
   // enqueued ahead of the residual it depends on: only if iteration want_k
   // is the one that converged
   if (conv && conv[1] != want_k) return;
   const int l = threadIdx.x;
-  const Tally& u = tally[l];
-  Tally t;
-  t.w_absorbed = wsum_d(u.w_absorbed);
-  t.w_coll = wsum_d(u.w_coll);
-  t.w_particles = wsum_d(u.w_particles);
-  t.pad = 0.0;
-  for (int s = 0; s < kMaxSpecies; ++s) {
-    t.n_absorbed[s] = wsum_u(u.n_absorbed[s]);
-    t.n_coll[s] = wsum_u(u.n_coll[s]);
-    t.append[s] = wsum_u(u.append[s]);
+  if (l < kTallyWords) {
+    const uint64_t* w = reinterpret_cast<const uint64_t*>(tally) + l;
+    uint64_t* dst = reinterpret_cast<uint64_t*>(&out->t) + l;
+    if (l < kTallyDoubles) {
+      double acc = 0.0;
+      for (int c = 0; c < kSpread; ++c) acc += __longlong_as_double((long long)w[c * kTallyWords]);
+      *dst = (uint64_t)__double_as_longlong(acc);
+    } else {
+      uint64_t acc = 0;
+      for (int c = 0; c < kSpread; ++c) acc += w[c * kTallyWords];
+      *dst = acc;
+    }
   }
-  t.n_ionized = wsum_u(u.n_ionized);
-  t.n_errors = wsum_u(u.n_errors);
-  t.n_crossings = wsum_u(u.n_crossings);
-  t.n_substeps = wsum_u(u.n_substeps);
-  t.n_over_range = wsum_u(u.n_over_range);
-  t.n_overflow = wsum_u(u.n_overflow);
   double xs = 0.0;
   for (int b = l; b < kRedBlocks; b += 64) xs += xpart[b];
   xs = wsum_d(xs);
@@ -614,14 +613,16 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
     const int64_t wlen = 2 * (int64_t)(nr + 1) + nz + 1;
     for (int64_t e = l; e < wlen; e += 64) wall_tot[e] += wall_add[e];
   }
-  if (l != 0) return;
-  out->t = t;
-  out->xs = xs;
-  out->h_gap_n = hn[(int64_t)(nr - 1) * nz];
-  out->h_gap_1 = h1[(int64_t)(nr - 1) * nz];
-  out->ir_gap = Ir[(int64_t)(nr - 1) * (nz + 1)];
+  if (l == 0) {
+    out->xs = xs;
+    out->h_gap_n = hn[(int64_t)(nr - 1) * nz];
+    out->h_gap_1 = h1[(int64_t)(nr - 1) * nz];
+    out->ir_gap = Ir[(int64_t)(nr - 1) * (nz + 1)];
+  }
+  // every lane's stores are ordered before the sequence number
   __threadfence_system();
-  store_sys(&out->seq, seq);
+  __syncthreads();
+  if (l == 0) store_sys(&out->seq, seq);
 }
 
 __global__ void k_zero_tally(Tally* tally) {
