@@ -15,6 +15,8 @@
 // global xi, eta) and the mixed path (T = float, positions stored as int32
 // cell + FP32 offsets); current increments are always formed and
 // accumulated in FP64.
+#include <climits>
+
 #include "ecpic_internal.h"
 
 namespace ecpic {
@@ -389,42 +391,52 @@ __device__ __forceinline__ void atomic_dep(double* Ir, double* Iz, int nz, int i
   unsafeAtomicAdd(Iz + (size_t)(i + 1) * nz + j, d.z1);
 }
 
+// A block's currents are gathered in LDS over the cells [c_lo, c_lo + W):
+// r-edges i*(nz+1)+j of those cells and their j+1 neighbours at TR[e - er0]
+// (er0 = c_lo + c_lo / nz), z-edges i*nz+j and the (i+1) neighbours at
+// TZ[e - c_lo].  Deposits of cells outside the window go to global atomics.
+struct Tile {
+  double* TR;
+  double* TZ;
+  int c_lo, W, er0;
+};
+
+// the window: one radial row below the block's first cell and one above its
+// last (a block's 1024 particles span a few dozen cells at most in sorted
+// order), cells that particles drift to between sorts
+__host__ __device__ inline int tile_cells(int nz) { return 2 * nz + 64; }
+__host__ __device__ inline int tile_r_len(int nz) {
+  const int W = tile_cells(nz);
+  return W + W / nz + 2;
+}
+__host__ __device__ inline int tile_z_len(int nz) { return tile_cells(nz) + nz; }
+
+
+// Deposit of one sub-step: into the tile when its cell is in the window (LDS
+// atomics), else by global atomics.
+__device__ __forceinline__ void tile_or_global(const Tile& t, double* Ir, double* Iz, int nz,
+                                               int i, int j, const Dep& d) {
+  if (!Ir) return;  // a pass that deposits nothing
+  const int key = i * nz + j;
+  if (key >= t.c_lo && key < t.c_lo + t.W) {
+    const int er = key + i - t.er0, ez = key - t.c_lo;
+    atomicAdd(&t.TR[er], d.r0);
+    atomicAdd(&t.TR[er + 1], d.r1);
+    atomicAdd(&t.TZ[ez], d.z0);
+    atomicAdd(&t.TZ[ez + nz], d.z1);
+  } else {
+    atomic_dep(Ir, Iz, nz, i, j, d);
+  }
+}
+
 enum { kAlive = 0, kAbsorbed = 1, kError = 2 };
 
-// Sub-step deposits a push holds in registers for its caller to issue after
-// the push: those of the first two sub-steps (a third is the last one for
-// nearly every particle, and nothing is loaded after the last).
 struct PushOut {
   int status;
   int wall;           // 1 bottom, 2 top, 3 side
   int nsub, ncross;
-  int nheld;          // held sub-step deposits (0, 1 or 2)
-  int i0, j0, i1, j1; // their cells
-  Dep d0, d1;
   double work;        // sum of q w E.dx over sub-steps (in units of J)
 };
-
-// Issue the deposits a push held: all addresses first, then the atomics
-// back to back.
-__device__ __forceinline__ void flush_held(double* Ir, double* Iz, int nz, const PushOut& o) {
-  if (!Ir || o.nheld == 0) return;
-  const bool h1 = o.nheld > 1;
-  const int i1 = h1 ? o.i1 : o.i0, j1 = h1 ? o.j1 : o.j0;
-  double* r0 = Ir + (size_t)o.i0 * (nz + 1) + o.j0;
-  double* r1 = Ir + (size_t)i1 * (nz + 1) + j1;
-  double* z0 = Iz + (size_t)o.i0 * nz + o.j0;
-  double* z1 = Iz + (size_t)i1 * nz + j1;
-  unsafeAtomicAdd(r0, o.d0.r0);
-  unsafeAtomicAdd(r0 + 1, o.d0.r1);
-  unsafeAtomicAdd(z0, o.d0.z0);
-  unsafeAtomicAdd(z0 + nz, o.d0.z1);
-  if (h1) {
-    unsafeAtomicAdd(r1, o.d1.r0);
-    unsafeAtomicAdd(r1 + 1, o.d1.r1);
-    unsafeAtomicAdd(z1, o.d1.z0);
-    unsafeAtomicAdd(z1 + nz, o.d1.z1);
-  }
-}
 
 template <typename T>
 __device__ __forceinline__ void load_field(const MapP& m, const T* __restrict__ ur,
@@ -437,22 +449,20 @@ __device__ __forceinline__ void load_field(const MapP& m, const T* __restrict__ 
   F[3] = at32(uz, oz + (uint32_t)(m.nz * (int)sizeof(T)));
 }
 
-// Push one particle over dt.  The deposits of the first two sub-steps are
-// returned in `out` for the caller to issue once the push is done: vector
-// loads and stores (atomics included) retire in issue order on one counter,
-// so a field load issued after an atomic that is still in flight waits for
-// that atomic (several microseconds for device-wide FP64 atomics), and
-// sub-steps that each deposited at once would each pay that round trip.
-// Later sub-steps deposit at once.
+// Push one particle over dt, depositing each sub-step into the caller's
+// tile (cells outside its window by global atomics).  LDS atomics keep the
+// sub-step loop free of global ones: vector loads and stores (atomics
+// included) retire in issue order on one counter, so a field load issued
+// after a global atomic still in flight waits for it (microseconds for
+// device-wide FP64 atomics).
 template <typename T>
 __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* __restrict__ uz,
-                              double* Ir, double* Iz, PState<T>& p, T qm, double qw_dt,
-                              bool want_work, PushOut& out) {
+                              double* Ir, double* Iz, const Tile& tl, PState<T>& p, T qm,
+                              double qw_dt, bool want_work, PushOut& out) {
   out.status = kAlive;
   out.wall = 0;
   out.nsub = 0;
   out.ncross = 0;
-  out.nheld = 0;
   out.work = 0.0;
   const int nr = m.nr, nz = m.nz;
   T tau = T(m.dt);
@@ -604,19 +614,7 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
       out.work += m.dt * (dp.r0 * double(F[0]) + dp.r1 * double(F[1]) + dp.z0 * double(F[2]) +
                           dp.z1 * double(F[3]));
     }
-    if (out.nheld == 0) {
-      out.i0 = p.i;
-      out.j0 = p.j;
-      out.d0 = dp;
-      out.nheld = 1;
-    } else if (out.nheld == 1) {
-      out.i1 = p.i;
-      out.j1 = p.j;
-      out.d1 = dp;
-      out.nheld = 2;
-    } else {
-      atomic_dep(Ir, Iz, nz, p.i, p.j, dp);
-    }
+    tile_or_global(tl, Ir, Iz, nz, p.i, p.j, dp);
     p = q;
     tau -= used;
     if (cd == 0 && cf == T(1) && p.i == nr - 1) {
@@ -1138,26 +1136,6 @@ __device__ __forceinline__ double dpp_take(double v) {
   return __hiloint2double(h2, l2);
 }
 
-// A block's currents are gathered in LDS over the cells [c_lo, c_lo + W):
-// r-edges i*(nz+1)+j of those cells and their j+1 neighbours at TR[e - er0]
-// (er0 = c_lo + c_lo / nz), z-edges i*nz+j and the (i+1) neighbours at
-// TZ[e - c_lo].  Deposits of cells outside the window go to global atomics.
-struct Tile {
-  double* TR;
-  double* TZ;
-  int c_lo, W, er0, nr_e, nz_e;
-};
-
-// the window: one radial row below the block's first cell and one above its
-// last (a block's 1024 particles span a few dozen cells at most in sorted
-// order), cells that particles drift to between sorts
-__host__ __device__ inline int tile_cells(int nz) { return 2 * nz + 64; }
-__host__ __device__ inline int tile_r_len(int nz) {
-  const int W = tile_cells(nz);
-  return W + W / nz + 2;
-}
-__host__ __device__ inline int tile_z_len(int nz) { return tile_cells(nz) + nz; }
-
 // Sum over the lanes of `mem` of the four edge increments of cell k0 (row
 // i0), added to the tile.  A transposing reduction: lane pairs swap halves of
 // their values so that each step adds fewer of them; after the two quad
@@ -1473,14 +1451,14 @@ __device__ __forceinline__ int64_t queue_pos(const QView& q, int e, int64_t qseg
   return (int64_t)g * qseg + (e - __shfl(q.excl, g, 64));
 }
 
-// Slow pass of one queued particle: the full push with splitting at every
-// face crossing (restarted from the particle's state), currents by atomics.
+// Slow pass of one queued particle (loaded into p): the full push with
+// splitting at every face crossing (restarted from the particle's state),
+// currents into the wavefront's tile.
 template <typename T, bool COMMIT>
-__device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, Tl& t) {
+__device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, PState<T>& p,
+                                         const Tile& tl, Tl& t) {
   const MapP& m = A.m;
   const SpecDev& s = A.s;
-  PState<T> p;
-  if (!load_particle<T>(s, m, k, p)) return;
   const double qw_dt = s.q * s.w / m.dt;
   PushOut o;
   if constexpr (sizeof(T) == 4) {
@@ -1495,7 +1473,7 @@ __device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, Tl& t) {
     pd.vr = p.vr;
     pd.vt = p.vt;
     pd.vz = p.vz;
-    push_particle<double>(m, A.ur, A.uz, A.Ir, A.Iz, pd, s.q / s.m, qw_dt, COMMIT, o);
+    push_particle<double>(m, A.ur, A.uz, A.Ir, A.Iz, tl, pd, s.q / s.m, qw_dt, COMMIT, o);
     p.i = pd.i;
     p.j = pd.j;
     p.a = T(pd.a);
@@ -1504,10 +1482,9 @@ __device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, Tl& t) {
     p.vt = T(pd.vt);
     p.vz = T(pd.vz);
   } else {
-    push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, p, T(s.q / s.m),
+    push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, tl, p, T(s.q / s.m),
                      qw_dt, COMMIT, o);
   }
-  flush_held(A.Ir, A.Iz, m.nz, o);
   if (COMMIT) {
     t.work += o.work;
     t.nsub += o.nsub;
@@ -1546,6 +1523,9 @@ enum { kQSlow = 0, kQSlowCommit = 1, kQCollide = 2, kQSlowCollide = 3 };
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kQThreads, 2) k_queue(PassArgs P) {
+  // dynamic LDS (slow roles): the tile, tile_r_len(nz) + tile_z_len(nz)
+  // doubles
+  extern __shared__ double qtile[];
   const bool stopped = P.a[0].stop && *P.a[0].stop;
   if (MODE == kQSlow && stopped) return;
   constexpr int kMaxRoles = MODE == kQSlowCollide ? 4 : 2;
@@ -1598,12 +1578,52 @@ __global__ void __launch_bounds__(kQThreads, 2) k_queue(PassArgs P) {
     const int64_t e = (u - base) * 64 + lane;
     const int64_t pos = queue_pos(v, (int)(e < v.total ? e : v.total - 1), P.qseg[slot]);
     worked = true;
-    if (e >= v.total) continue;
     const PushArgs& A = P.a[slot];
     if (MODE != kQCollide && slow) {
-      slow_one<T, MODE != kQSlow>(A, P.queue[slot][pos], t);
+      // the unit's particles, then a tile over their cells: one radial row
+      // either side of the lowest (a unit holds consecutive queue entries,
+      // which come from one or two fast-pass blocks of cell-sorted
+      // particles)
+      int64_t k = 0;
+      PState<T> p;
+      bool ok = false;
+      if (e < v.total) {
+        k = P.queue[slot][pos];
+        ok = load_particle<T>(A.s, A.m, k, p);
+      }
+      const int nz = A.m.nz;
+      int c = ok ? p.i * nz + p.j : INT_MAX;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) c = min(c, __shfl_xor(c, off, 64));
+      Tile tl;
+      tl.W = tile_cells(nz);
+      tl.TR = qtile;
+      tl.TZ = qtile + tile_r_len(nz);
+      tl.c_lo = max((c == INT_MAX ? 0 : c) - nz - 2, 0);
+      tl.er0 = tl.c_lo + tl.c_lo / nz;
+      const int lr = tile_r_len(nz), lz = tile_z_len(nz);
+      // a pass without deposit (null currents) leaves the tile untouched
+      const bool dep = A.Ir != nullptr;
+      if (dep)
+        for (int q = lane; q < lr + lz; q += kQThreads) qtile[q] = 0.0;
+      __syncthreads();
+      if (ok) slow_one<T, MODE != kQSlow>(A, k, p, tl, t);
+      __syncthreads();
+      if (dep) {
+        // flush: one global atomic per touched edge
+        const int64_t ner = (int64_t)A.m.nr * (nz + 1), nez = (int64_t)(A.m.nr + 1) * nz;
+        for (int q = lane; q < lr; q += kQThreads) {
+          const double x = tl.TR[q];
+          if (x != 0.0 && tl.er0 + q < ner) unsafeAtomicAdd(A.Ir + tl.er0 + q, x);
+        }
+        for (int q = lane; q < lz; q += kQThreads) {
+          const double x = tl.TZ[q];
+          if (x != 0.0 && tl.c_lo + q < nez) unsafeAtomicAdd(A.Iz + tl.c_lo + q, x);
+        }
+      }
+      __syncthreads();
     } else if (MODE != kQSlow) {
-      listed_one<T>(A, P.cqueue[slot][pos], t);
+      if (e < v.total) listed_one<T>(A, P.cqueue[slot][pos], t);
     }
   }
 }
@@ -1793,10 +1813,11 @@ int64_t max_slot_n(const PassArgs& P) {
 template <int MODE>
 void launch_queue(const PassArgs& P, int64_t nmax, hipStream_t st) {
   const dim3 gs(queue_grid(nmax, P.nsp), 1, 1);
+  const size_t lds = MODE == kQCollide ? 0 : fast_lds_bytes(P.a[0].m.nz);
   if (P.a[0].s.cell != nullptr)
-    hipLaunchKernelGGL((k_queue<float, MODE>), gs, dim3(kQThreads), 0, st, P);
+    hipLaunchKernelGGL((k_queue<float, MODE>), gs, dim3(kQThreads), lds, st, P);
   else
-    hipLaunchKernelGGL((k_queue<double, MODE>), gs, dim3(kQThreads), 0, st, P);
+    hipLaunchKernelGGL((k_queue<double, MODE>), gs, dim3(kQThreads), lds, st, P);
 }
 }  // namespace
 
