@@ -379,6 +379,7 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
     PassArgs P;
     std::memset(&P, 0, sizeof(P));
     P.nsp = (b + 1 < act.size()) ? 2 : 1;
+    P.qcap = c.queue_cap;
     double bytes = 0.0;
     int64_t parts = 0;
     for (int q = 0; q < P.nsp; ++q) {
@@ -401,6 +402,7 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
         a.Iz = nullptr;
       }
       P.queue[q] = c.queue + (int64_t)s * c.queue_cap;
+      P.qrec[q] = c.qrec + (int64_t)s * 5 * c.queue_cap;
       P.cqueue[q] = c.queue + (int64_t)(kMaxSpecies + s) * c.queue_cap;
       P.cqcount[q] = c.qcount + kQCount + s * kSpread * kLineInts;
       P.qcount[q] = c.qcount + s * kSpread * kLineInts;
@@ -601,6 +603,7 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
   (void)hipFree(c.scan_part);
   (void)hipFree(c.tally);
   (void)hipFree(c.queue);
+  (void)hipFree(c.qrec);
   (void)hipFree(c.qcount);
   (void)hipFree(c.nn_w);
   (void)hipFree(c.nn_ws);
@@ -642,13 +645,18 @@ ecpic_status ecpic_add_species(ecpic_ctx* x, const ecpic_species_desc* d, int32_
   const int64_t qlen = kSpread * queue_segment(d->capacity);
   if (qlen > c.queue_cap) {
     int32_t* q = nullptr;
-    if (dalloc(&q, (size_t)qlen * kMaxSpecies * 2) != hipSuccess) {
+    double* r = nullptr;
+    if (dalloc(&q, (size_t)qlen * kMaxSpecies * 2) != hipSuccess ||
+        dalloc(&r, (size_t)qlen * kMaxSpecies * 5) != hipSuccess) {
+      (void)hipFree(q);
       free_species_buf(s.d[0]);
       free_species_buf(s.d[1]);
       return fail(c, ECPIC_ENOMEM, "queue allocation failed");
     }
     (void)hipFree(c.queue);
+    (void)hipFree(c.qrec);
     c.queue = q;
+    c.qrec = r;
     c.queue_cap = qlen;
   }
   s.n = 0;

@@ -123,6 +123,11 @@ struct PassArgs {
   int32_t* cqueue[2];  // the same for the collision list of a commit pass
   int32_t* cqcount[2];
   int64_t qseg[2];
+  // per slot, the particle record of every slow-queue entry at the entry's
+  // position: field f at qrec[f * qcap + position] (FP64: xi, eta, vr, vt,
+  // vz; FP32: cell, a, b, vr, vt, vz as 4-byte words)
+  double* qrec[2];
+  int64_t qcap;
   int32_t nsp;         // slots in use (1 or 2)
 };
 
@@ -210,6 +215,8 @@ struct Ctx {
   int32_t* queue = nullptr;        // slow-pass particle queues, one per species,
                                    // then as many collision lists
   int64_t queue_cap = 0;           // entries per species and kind
+  double* qrec = nullptr;          // slow-queue entry records, 5 x queue_cap
+                                   // words of 8 bytes per species
   int32_t* qcount = nullptr;       // queue lengths: 2 kQCount (slow queues, then
                                    // collision lists)
   Tally* tally_host;               // pinned host mirror of the copies

@@ -951,6 +951,47 @@ __device__ __forceinline__ bool decode_raw(const MapP& m, const Raw<float>& q, P
   return true;
 }
 
+// The record of a slow-queue entry (the particle's stored record when it was
+// queued), field f at rec[f * cap + pos].
+__device__ __forceinline__ void store_rec(double* rec, int64_t cap, int64_t pos,
+                                          const Raw<double>& r) {
+  rec[pos] = r.xi;
+  rec[cap + pos] = r.eta;
+  rec[2 * cap + pos] = r.vr;
+  rec[3 * cap + pos] = r.vt;
+  rec[4 * cap + pos] = r.vz;
+}
+__device__ __forceinline__ void load_rec(const double* rec, int64_t cap, int64_t pos,
+                                         Raw<double>& r) {
+  r.xi = rec[pos];
+  r.eta = rec[cap + pos];
+  r.vr = rec[2 * cap + pos];
+  r.vt = rec[3 * cap + pos];
+  r.vz = rec[4 * cap + pos];
+}
+__device__ __forceinline__ void store_rec(double* rec, int64_t cap, int64_t pos,
+                                          const Raw<float>& r) {
+  int32_t* ri = reinterpret_cast<int32_t*>(rec);
+  float* rf = reinterpret_cast<float*>(rec);
+  ri[pos] = r.cell;
+  rf[cap + pos] = r.a;
+  rf[2 * cap + pos] = r.b;
+  rf[3 * cap + pos] = r.vr;
+  rf[4 * cap + pos] = r.vt;
+  rf[5 * cap + pos] = r.vz;
+}
+__device__ __forceinline__ void load_rec(const double* rec, int64_t cap, int64_t pos,
+                                         Raw<float>& r) {
+  const int32_t* ri = reinterpret_cast<const int32_t*>(rec);
+  const float* rf = reinterpret_cast<const float*>(rec);
+  r.cell = ri[pos];
+  r.a = rf[cap + pos];
+  r.b = rf[2 * cap + pos];
+  r.vr = rf[3 * cap + pos];
+  r.vt = rf[4 * cap + pos];
+  r.vz = rf[5 * cap + pos];
+}
+
 // cell key i * nz + j of particle k, or -1 if it is dead
 template <typename T>
 __device__ __forceinline__ int particle_cell(const SpecDev& s, const MapP& m, int64_t k);
@@ -1391,7 +1432,18 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   if (ns) {
     if (threadIdx.x == 0) gbase = atomicAdd(qcount + seg * kLineInts, ns);
     __syncthreads();
-    for (int q = threadIdx.x; q < ns; q += kBlock) queue[seg * qseg + gbase + q] = slow_list[q];
+    // with each entry the particle's record (read by this block moments ago,
+    // so from cache), which the slow pass then reads in order instead of
+    // gathering it
+    double* rec = P.qrec[slot];
+    for (int q = threadIdx.x; q < ns; q += kBlock) {
+      const int32_t kq = slow_list[q];
+      const int64_t pos = seg * qseg + gbase + q;
+      queue[pos] = kq;
+      Raw<T> r;
+      fetch_raw(s, kq, r);
+      store_rec(rec, P.qcap, pos, r);
+    }
   }
   if (!COMMIT) return;
   const int nc = coll_n;
@@ -1589,7 +1641,9 @@ __global__ void __launch_bounds__(kQThreads, 2) k_queue(PassArgs P) {
       bool ok = false;
       if (e < v.total) {
         k = P.queue[slot][pos];
-        ok = load_particle<T>(A.s, A.m, k, p);
+        Raw<T> r;
+        load_rec(P.qrec[slot], P.qcap, pos, r);
+        ok = decode_raw(A.m, r, p);
       }
       const int nz = A.m.nz;
       int c = ok ? p.i * nz + p.j : INT_MAX;
