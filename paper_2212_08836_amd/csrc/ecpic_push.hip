@@ -951,6 +951,29 @@ __device__ __forceinline__ bool decode_raw(const MapP& m, const Raw<float>& q, P
   return true;
 }
 
+// The stored record of a decoded particle that has not moved: xi = i + a
+// exactly (a = xi - i was exact), likewise eta, and the cell key.  The face
+// step of a push start (a = 1 to the next cell's a = 0) keeps i + a.
+__device__ __forceinline__ Raw<double> raw_of(const PState<double>& p, int nz) {
+  Raw<double> r;
+  r.xi = double(p.i) + p.a;
+  r.eta = double(p.j) + p.b;
+  r.vr = p.vr;
+  r.vt = p.vt;
+  r.vz = p.vz;
+  return r;
+}
+__device__ __forceinline__ Raw<float> raw_of(const PState<float>& p, int nz) {
+  Raw<float> r;
+  r.cell = p.i * nz + p.j;
+  r.a = p.a;
+  r.b = p.b;
+  r.vr = p.vr;
+  r.vt = p.vt;
+  r.vz = p.vz;
+  return r;
+}
+
 // The record of a slow-queue entry (the particle's stored record when it was
 // queued), field f at rec[f * cap + pos].
 __device__ __forceinline__ void store_rec(double* rec, int64_t cap, int64_t pos,
@@ -1266,6 +1289,10 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   if (P.a[0].stop && *P.a[0].stop) return;
   extern __shared__ double tile_mem[];
   __shared__ int32_t slow_list[kPerBlock];
+  // the records of the block's first kStage slow particles, kept when they
+  // are queued (later ones are fetched again at the end)
+  constexpr int kStage = 64;
+  __shared__ Raw<T> slow_rec[kStage];
   __shared__ int32_t coll_list[COMMIT ? kPerBlock : 1];
   __shared__ int slow_n, gbase, coll_n, cbase;
   // the species slot indexes the arguments directly (a select between the
@@ -1393,7 +1420,11 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
       int wbase = 0;
       if (lane == 0) wbase = atomicAdd(&slow_n, __popcll(mask));
       wbase = __shfl(wbase, 0, 64);
-      if (slow) slow_list[wbase + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)k;
+      if (slow) {
+        const int qi = wbase + __popcll(mask & ((1ull << lane) - 1ull));
+        slow_list[qi] = (int32_t)k;
+        if (qi < kStage) slow_rec[qi] = raw_of(p, nz);
+      }
     }
     if (COMMIT) {
       // in-cell particles are stored as pushed; those the null-collision
@@ -1432,16 +1463,18 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   if (ns) {
     if (threadIdx.x == 0) gbase = atomicAdd(qcount + seg * kLineInts, ns);
     __syncthreads();
-    // with each entry the particle's record (read by this block moments ago,
-    // so from cache), which the slow pass then reads in order instead of
-    // gathering it
+    // with each entry the particle's record, which the slow pass then reads
+    // in order instead of gathering it
     double* rec = P.qrec[slot];
     for (int q = threadIdx.x; q < ns; q += kBlock) {
       const int32_t kq = slow_list[q];
       const int64_t pos = seg * qseg + gbase + q;
       queue[pos] = kq;
       Raw<T> r;
-      fetch_raw(s, kq, r);
+      if (q < kStage)
+        r = slow_rec[q];
+      else
+        fetch_raw(s, kq, r);
       store_rec(rec, P.qcap, pos, r);
     }
   }
