@@ -216,6 +216,50 @@ def test_push_deposit_edge_cases(og, torch_cuda):
     assert np.abs(side).max() > 0 and np.abs(bot).max() > 0 and np.abs(top).max() > 0
 
 
+@pytest.mark.parametrize("sort", [False, True])
+def test_push_deposit_many_crossers(og, torch_cuda, sort):
+    # electrons at 30x thermal speed (about 2.7 keV): about half of them leave
+    # their cell, hundreds per fast-pass block, so the slow queue's records
+    # are both staged and fetched again, and in cell order (sort) the slow
+    # pass's tile takes most deposits while in load order most go to global
+    # atomics
+    import paper_2212_08836_amd as P
+    _flush(f"push_deposit parity, fast electrons, sorted {sort}")
+    w = E.workload("c1")
+    parts = E.make_particles(w, n=4096)
+    for k in ("vr", "vt", "vz"):
+        parts[0][k] = parts[0][k] * 30.0
+    g, sp, ctx = _make_pair(w, og, P, parts)
+    if sort:
+        ctx.sort()
+    rng = np.random.default_rng(6)
+    nr, nz = w.nr, w.nz
+    urh = rng.standard_normal(nr * (nz + 1)) * 2.0
+    uzh = rng.standard_normal((nr + 1) * nz) * 2.0
+    urh.reshape(nr, nz + 1)[:, [0, -1]] = 0
+    uzh.reshape(nr + 1, nz)[-1] = 0
+    ctx.set_half_field(urh, uzh)
+    Ir_g, Iz_g = ctx.push_deposit(commit=False)
+    Ir_o, Iz_o = g.zeros_r(), g.zeros_z()
+    cross = 0
+    for s in sp:
+        _, _, rc, st = g.push_deposit(s, urh, uzh, commit=False, Ir=Ir_o, Iz=Iz_o)
+        assert rc == 0
+        cross += st["n_crossings"]
+    _flush(f"  {cross} face crossings")
+    assert cross > 2000  # 2266 with these particles and fields
+    assert _rel(Ir_g, Ir_o) < TOL and _rel(Iz_g, Iz_o) < TOL
+    Ir_g, Iz_g = ctx.push_deposit(commit=True)
+    ost = og.State(g)
+    for s in sp:
+        g.push_deposit(s, urh, uzh, commit=True, state=ost)
+    for k in range(2):
+        assert _cmp_species(ctx.read_particles(k), sp[k].view(), f"species {k}") < TOL
+    q, bot, top, side = ctx.node_charge()
+    assert _rel(bot, ost.wall_bot) < TOL and _rel(top, ost.wall_top) < TOL
+    assert _rel(side, ost.wall_side) < TOL
+
+
 def test_step_parity_edge_cases(og, torch_cuda):
     # whole steps with the same particles (one species empty throughout)
     import paper_2212_08836_amd as P
