@@ -1276,6 +1276,12 @@ __device__ __forceinline__ bool commit_store(const PushArgs& A, int64_t k, const
   return u[0] < A.mcc.pnull;
 }
 
+// Set bits of a wavefront mask in the lanes below this one.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Fast pass: every particle solves the mid-point system over the whole step
 // in its cell.  Those that stay in the closed cell are done (this is exactly
 // the first sub-step of the full algorithm); their currents are gathered in
@@ -1288,13 +1294,16 @@ template <typename T, bool COMMIT, bool DEPOSIT>
 __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   if (P.a[0].stop && *P.a[0].stop) return;
   extern __shared__ double tile_mem[];
+  // the slow and collision lists, a region of kPerWave entries per
+  // wavefront filled in order (no atomics), and the records of each
+  // wavefront's first kStageW slow particles, kept when they are queued
+  // (later ones are fetched again at the end)
+  constexpr int kWaves = kBlock / 64, kPerWave = kPerBlock / kWaves, kStageW = 16;
   __shared__ int32_t slow_list[kPerBlock];
-  // the records of the block's first kStage slow particles, kept when they
-  // are queued (later ones are fetched again at the end)
-  constexpr int kStage = 64;
-  __shared__ Raw<T> slow_rec[kStage];
+  __shared__ Raw<T> slow_rec[kWaves * kStageW];
   __shared__ int32_t coll_list[COMMIT ? kPerBlock : 1];
-  __shared__ int slow_n, gbase, coll_n, cbase;
+  __shared__ int wslow[kWaves], wcoll[kWaves], gbase, cbase;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // the species slot indexes the arguments directly (a select between the
   // slots' fields would keep both sets in scalar registers)
   const int slot = blockIdx.y;
@@ -1329,11 +1338,8 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
     const int ntile = tile_r_len(nz) + tile_z_len(nz);
     for (int e = threadIdx.x; e < ntile; e += kBlock) tile_mem[e] = 0.0;
   }
-  if (threadIdx.x == 0) {
-    slow_n = 0;
-    coll_n = 0;
-  }
   __syncthreads();
+  int wn_slow = 0, wn_coll = 0;  // this wavefront's list lengths (uniform)
   Tl t;
   tl_zero(t);
   const int lane = threadIdx.x & 63;
@@ -1414,18 +1420,14 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
       }
     }
     if (DEPOSIT) tile_deposit(tl, A.Ir, A.Iz, nz, key, p.i, p.j, dp);
-    // the block's slow list: one LDS atomic per wavefront
+    // the wavefront's slow list
     const uint64_t mask = __ballot(slow);
-    if (mask) {
-      int wbase = 0;
-      if (lane == 0) wbase = atomicAdd(&slow_n, __popcll(mask));
-      wbase = __shfl(wbase, 0, 64);
-      if (slow) {
-        const int qi = wbase + __popcll(mask & ((1ull << lane) - 1ull));
-        slow_list[qi] = (int32_t)k;
-        if (qi < kStage) slow_rec[qi] = raw_of(p, nz);
-      }
+    if (slow) {
+      const int qi = wn_slow + lanes_below(mask);
+      slow_list[wv * kPerWave + qi] = (int32_t)k;
+      if (qi < kStageW) slow_rec[wv * kStageW + qi] = raw_of(p, nz);
     }
+    wn_slow = __builtin_amdgcn_readfirstlane(wn_slow + (int)__popcll(mask));
     if (COMMIT) {
       // in-cell particles are stored as pushed; those the null-collision
       // draw selects go to the collision list
@@ -1434,14 +1436,14 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
       // into the other buffer: dead slots stay dead there
       if (k < s.n && !alive && !same_buffer(A.out, A.s)) kill_particle<T>(A.out, k);
       const uint64_t cm = __ballot(coll);
-      if (cm) {
-        int wb = 0;
-        if (lane == 0) wb = atomicAdd(&coll_n, __popcll(cm));
-        wb = __shfl(wb, 0, 64);
-        if (coll) coll_list[wb + __popcll(cm & ((1ull << lane) - 1ull))] = (int32_t)k;
-      }
+      if (coll) coll_list[wv * kPerWave + wn_coll + lanes_below(cm)] = (int32_t)k;
+      wn_coll = __builtin_amdgcn_readfirstlane(wn_coll + (int)__popcll(cm));
     }
     cur = nxt;
+  }
+  if (lane == 0) {
+    wslow[wv] = wn_slow;
+    wcoll[wv] = wn_coll;
   }
   __syncthreads();
   // flush the tile: one global atomic per touched edge
@@ -1459,7 +1461,16 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   }
   // queue the slow ones (and the colliding ones): one global atomic per block
   const int64_t seg = bx % kSpread;
-  const int ns = slow_n;
+  // list entry q of the block: wavefront w of the first whose lists end
+  // beyond q, at offset q - (entries of the wavefronts before w)
+  int spre[kWaves + 1], cpre[kWaves + 1];
+  spre[0] = cpre[0] = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    spre[w + 1] = spre[w] + wslow[w];
+    cpre[w + 1] = cpre[w] + wcoll[w];
+  }
+  const int ns = spre[kWaves];
   if (ns) {
     if (threadIdx.x == 0) gbase = atomicAdd(qcount + seg * kLineInts, ns);
     __syncthreads();
@@ -1467,23 +1478,32 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
     // in order instead of gathering it
     double* rec = P.qrec[slot];
     for (int q = threadIdx.x; q < ns; q += kBlock) {
-      const int32_t kq = slow_list[q];
+      int w = 0;
+#pragma unroll
+      for (int u = 1; u < kWaves; ++u) w += q >= spre[u] ? 1 : 0;
+      const int o = q - spre[w];
+      const int32_t kq = slow_list[w * kPerWave + o];
       const int64_t pos = seg * qseg + gbase + q;
       queue[pos] = kq;
       Raw<T> r;
-      if (q < kStage)
-        r = slow_rec[q];
+      if (o < kStageW)
+        r = slow_rec[w * kStageW + o];
       else
         fetch_raw(s, kq, r);
       store_rec(rec, P.qcap, pos, r);
     }
   }
   if (!COMMIT) return;
-  const int nc = coll_n;
+  const int nc = cpre[kWaves];
   if (nc) {
     if (threadIdx.x == 0) cbase = atomicAdd(cqcount + seg * kLineInts, nc);
     __syncthreads();
-    for (int q = threadIdx.x; q < nc; q += kBlock) cqueue[seg * qseg + cbase + q] = coll_list[q];
+    for (int q = threadIdx.x; q < nc; q += kBlock) {
+      int w = 0;
+#pragma unroll
+      for (int u = 1; u < kWaves; ++u) w += q >= cpre[u] ? 1 : 0;
+      cqueue[seg * qseg + cbase + q] = coll_list[w * kPerWave + q - cpre[w]];
+    }
   }
   tl_flush(t, A.tally + (blockIdx.x % kSpread), s.sid);
 }
