@@ -411,6 +411,24 @@ __host__ __device__ inline int tile_r_len(int nz) {
 }
 __host__ __device__ inline int tile_z_len(int nz) { return tile_cells(nz) + nz; }
 
+// The slow pass's window (per wavefront): the fast pass's where that is at
+// most kSlowW cells (one radial row either side of the unit's lowest cell);
+// for longer rows kSlowW cells from 32 below that cell, so that crossings of
+// z-faces stay in it and those of r-faces (to cells nz away) go to global
+// atomics, and the tile does not limit how many wavefronts a CU holds.
+constexpr int kSlowW = 576;
+__host__ __device__ inline int slow_cells(int nz) {
+  return tile_cells(nz) < kSlowW ? tile_cells(nz) : kSlowW;
+}
+__host__ __device__ inline int slow_r_len(int nz) {
+  const int W = slow_cells(nz);
+  return W + W / nz + 2;
+}
+__host__ __device__ inline int slow_z_len(int nz) { return slow_cells(nz) + nz; }
+__host__ __device__ inline int slow_below(int nz) {
+  return tile_cells(nz) <= kSlowW ? nz + 2 : 32;
+}
+
 
 // Deposit of one sub-step: into the tile when its cell is in the window (LDS
 // atomics), else by global atomics.
@@ -1628,7 +1646,7 @@ enum { kQSlow = 0, kQSlowCommit = 1, kQCollide = 2, kQSlowCollide = 3 };
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kQThreads, 2) k_queue(PassArgs P) {
-  // dynamic LDS (slow roles): the tile, tile_r_len(nz) + tile_z_len(nz)
+  // dynamic LDS (slow roles): the tile, slow_r_len(nz) + slow_z_len(nz)
   // doubles
   extern __shared__ double qtile[];
   const bool stopped = P.a[0].stop && *P.a[0].stop;
@@ -1685,10 +1703,9 @@ __global__ void __launch_bounds__(kQThreads, 2) k_queue(PassArgs P) {
     worked = true;
     const PushArgs& A = P.a[slot];
     if (MODE != kQCollide && slow) {
-      // the unit's particles, then a tile over their cells: one radial row
-      // either side of the lowest (a unit holds consecutive queue entries,
-      // which come from one or two fast-pass blocks of cell-sorted
-      // particles)
+      // the unit's particles, then a tile over their cells from just below
+      // the lowest (a unit holds consecutive queue entries, which come from
+      // one or two fast-pass blocks of cell-sorted particles)
       int64_t k = 0;
       PState<T> p;
       bool ok = false;
@@ -1703,12 +1720,12 @@ __global__ void __launch_bounds__(kQThreads, 2) k_queue(PassArgs P) {
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) c = min(c, __shfl_xor(c, off, 64));
       Tile tl;
-      tl.W = tile_cells(nz);
+      tl.W = slow_cells(nz);
       tl.TR = qtile;
-      tl.TZ = qtile + tile_r_len(nz);
-      tl.c_lo = max((c == INT_MAX ? 0 : c) - nz - 2, 0);
+      tl.TZ = qtile + slow_r_len(nz);
+      tl.c_lo = max((c == INT_MAX ? 0 : c) - slow_below(nz), 0);
       tl.er0 = tl.c_lo + tl.c_lo / nz;
-      const int lr = tile_r_len(nz), lz = tile_z_len(nz);
+      const int lr = slow_r_len(nz), lz = slow_z_len(nz);
       // a pass without deposit (null currents) leaves the tile untouched
       const bool dep = A.Ir != nullptr;
       if (dep)
@@ -1920,7 +1937,8 @@ int64_t max_slot_n(const PassArgs& P) {
 template <int MODE>
 void launch_queue(const PassArgs& P, int64_t nmax, hipStream_t st) {
   const dim3 gs(queue_grid(nmax, P.nsp), 1, 1);
-  const size_t lds = MODE == kQCollide ? 0 : fast_lds_bytes(P.a[0].m.nz);
+  const int nz = P.a[0].m.nz;
+  const size_t lds = MODE == kQCollide ? 0 : sizeof(double) * (size_t)(slow_r_len(nz) + slow_z_len(nz));
   if (P.a[0].s.cell != nullptr)
     hipLaunchKernelGGL((k_queue<float, MODE>), gs, dim3(kQThreads), lds, st, P);
   else

@@ -216,23 +216,13 @@ def test_push_deposit_edge_cases(og, torch_cuda):
     assert np.abs(side).max() > 0 and np.abs(bot).max() > 0 and np.abs(top).max() > 0
 
 
-@pytest.mark.parametrize("sort", [False, True])
-def test_push_deposit_many_crossers(og, torch_cuda, sort):
-    # electrons at 30x thermal speed (about 2.7 keV): about half of them leave
-    # their cell, hundreds per fast-pass block, so the slow queue's records
-    # are both staged and fetched again, and in cell order (sort) the slow
-    # pass's tile takes most deposits while in load order most go to global
-    # atomics
-    import paper_2212_08836_amd as P
-    _flush(f"push_deposit parity, fast electrons, sorted {sort}")
-    w = E.workload("c1")
-    parts = E.make_particles(w, n=4096)
-    for k in ("vr", "vt", "vz"):
-        parts[0][k] = parts[0][k] * 30.0
+def _push_deposit_case(og, P, w, parts, sort, seed=6):
+    """One push (then one committing push) of `parts` in random half-step
+    fields against the oracle; returns the oracle's face-crossing count."""
     g, sp, ctx = _make_pair(w, og, P, parts)
     if sort:
         ctx.sort()
-    rng = np.random.default_rng(6)
+    rng = np.random.default_rng(seed)
     nr, nz = w.nr, w.nz
     urh = rng.standard_normal(nr * (nz + 1)) * 2.0
     uzh = rng.standard_normal((nr + 1) * nz) * 2.0
@@ -247,7 +237,6 @@ def test_push_deposit_many_crossers(og, torch_cuda, sort):
         assert rc == 0
         cross += st["n_crossings"]
     _flush(f"  {cross} face crossings")
-    assert cross > 2000  # 2266 with these particles and fields
     assert _rel(Ir_g, Ir_o) < TOL and _rel(Iz_g, Iz_o) < TOL
     Ir_g, Iz_g = ctx.push_deposit(commit=True)
     ost = og.State(g)
@@ -258,6 +247,33 @@ def test_push_deposit_many_crossers(og, torch_cuda, sort):
     q, bot, top, side = ctx.node_charge()
     assert _rel(bot, ost.wall_bot) < TOL and _rel(top, ost.wall_top) < TOL
     assert _rel(side, ost.wall_side) < TOL
+    return cross
+
+
+@pytest.mark.parametrize("sort", [False, True])
+def test_push_deposit_many_crossers(og, torch_cuda, sort):
+    # electrons at 30x thermal speed (about 2.7 keV): about half of them leave
+    # their cell, hundreds per fast-pass block, so the slow queue's records
+    # are both staged and fetched again, and in cell order (sort) the slow
+    # pass's tile takes most deposits while in load order most go to global
+    # atomics
+    import paper_2212_08836_amd as P
+    _flush(f"push_deposit parity, fast electrons, sorted {sort}")
+    w = E.workload("c1")
+    parts = E.make_particles(w, n=4096)
+    for k in ("vr", "vt", "vz"):
+        parts[0][k] = parts[0][k] * 30.0
+    assert _push_deposit_case(og, P, w, parts, sort) > 2000  # 2266
+
+
+def test_push_deposit_long_rows(og, torch_cuda):
+    # 320 cells along z: the slow pass's tile spans part of a row only, so
+    # crossings of r-faces leave it for global atomics
+    import paper_2212_08836_amd as P
+    _flush("push_deposit parity, 12 x 320 grid")
+    w = E.Workload("long", 12, 320, 0.01, 0.03, ppc=2, Te_eV=300.0)
+    parts = E.make_particles(w)
+    assert _push_deposit_case(og, P, w, parts, sort=True) > 3000
 
 
 def test_step_parity_edge_cases(og, torch_cuda):
