@@ -1644,8 +1644,11 @@ __device__ __forceinline__ void listed_one(const PushArgs& A, int64_t k, Tl& t) 
 // iteration.  Grid: 1-D, one wavefront per block.
 enum { kQSlow = 0, kQSlowCommit = 1, kQCollide = 2, kQSlowCollide = 3 };
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kQThreads, 2) k_queue(PassArgs P) {
+// WAVES: the wavefronts per SIMD the register budget is cut for.  Two keep
+// the push in registers; three (the plain slow pass on large workloads,
+// where it is throughput-bound) spill a few and hold more wavefronts.
+template <typename T, int MODE, int WAVES>
+__global__ void __launch_bounds__(kQThreads, WAVES) k_queue(PassArgs P) {
   // dynamic LDS (slow roles): the tile, slow_r_len(nz) + slow_z_len(nz)
   // doubles
   extern __shared__ double qtile[];
@@ -1934,15 +1937,31 @@ int64_t max_slot_n(const PassArgs& P) {
   return nmax;
 }
 
-template <int MODE>
-void launch_queue(const PassArgs& P, int64_t nmax, hipStream_t st) {
+template <int MODE, int WAVES>
+void launch_queue_w(const PassArgs& P, int64_t nmax, hipStream_t st) {
   const dim3 gs(queue_grid(nmax, P.nsp), 1, 1);
   const int nz = P.a[0].m.nz;
   const size_t lds = MODE == kQCollide ? 0 : sizeof(double) * (size_t)(slow_r_len(nz) + slow_z_len(nz));
   if (P.a[0].s.cell != nullptr)
-    hipLaunchKernelGGL((k_queue<float, MODE>), gs, dim3(kQThreads), lds, st, P);
+    hipLaunchKernelGGL((k_queue<float, MODE, WAVES>), gs, dim3(kQThreads), lds, st, P);
   else
-    hipLaunchKernelGGL((k_queue<double, MODE>), gs, dim3(kQThreads), lds, st, P);
+    hipLaunchKernelGGL((k_queue<double, MODE, WAVES>), gs, dim3(kQThreads), lds, st, P);
+}
+
+// particles in a pass from which the plain slow pass takes the three-wavefront
+// build (at 4.2M its queue fits the GPU in one round and latency decides; at
+// 268M it is throughput-bound: 2.5 -> 2.2 ms per pass)
+constexpr int64_t kWideQueue = (int64_t)16 << 20;
+
+template <int MODE>
+void launch_queue(const PassArgs& P, int64_t nmax, hipStream_t st) {
+  if constexpr (MODE == kQSlow) {
+    if (nmax * P.nsp >= kWideQueue) {
+      launch_queue_w<MODE, 3>(P, nmax, st);
+      return;
+    }
+  }
+  launch_queue_w<MODE, 2>(P, nmax, st);
 }
 }  // namespace
 
