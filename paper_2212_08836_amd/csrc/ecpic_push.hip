@@ -215,25 +215,28 @@ __device__ __forceinline__ bool solve_fast(const MapP& m, const T F[4], const PS
   const T Kz = beta * delta * dFz;
   const T Kr = alpha * gamma * dFr;
   const T den = T(1) - Kr * Kz;
-  if (!(den > T(0))) return false;
+  const T r0 = T(m.s * (double(p.i) + m.xi_a)) + T(m.s) * p.a;
+  // admissibility as flags (no early exits): a failed lane computes on and
+  // is rejected at the end
+  bool ok = (den > T(0)) & (r0 > T(0));
   const T inv_den = rcp_refined(den);
   const T bz = beta * Ez;
   const T k0 = (alpha * Er + Kr * (p.vz + bz + Kz * p.vr)) * inv_den;
   const T cc = hd * inv_den;
-  const T r0 = T(m.s * (double(p.i) + m.xi_a)) + T(m.s) * p.a;
-  if (!(r0 > T(0))) return false;
   const T vt2 = p.vt * p.vt;
   const T c2 = cc * vt2;
   T kr = k0 + c2 * rcp_refined(r0);  // centrifugal term at the start position
   // g(kr) = k0 + c2 rb / re^2 is a contraction with slope
   // g' = c2 (hd - 2 dtau rb / re) / re^2; for |g'| < 1/2 the iterate g(kr)
   // is within 2 |g'| |g(kr) - kr| of the fixed point, which is the stopping
-  // test (the bare step |g(kr) - kr| otherwise)
+  // test (the bare step |g(kr) - kr| otherwise).  The outputs are formed
+  // once after the loop, from the final kr.
+  bool conv = false;
   for (int it = 0; it < 12; ++it) {
     const T vr = p.vr + kr;
     const T rb = r0 + hd * vr;
     const T re = r0 + dtau * vr;
-    if (!(rb > T(0) && re > T(0))) return false;
+    ok = ok & (rb > T(0)) & (re > T(0));
     const T ire = rcp_refined(re);
     const T g = c2 * ire * ire;
     const T nkr = k0 + g * rb;
@@ -243,22 +246,23 @@ __device__ __forceinline__ bool solve_fast(const MapP& m, const T F[4], const PS
     const T kz = bz + Kz * (p.vr + kr);
     const T scale = fabs(p.vr + kr) + fabs(p.vt * rb * ire) + fabs(p.vz + kz);
     const T err = slope < T(0.5) ? T(2) * slope * d : d;
-    if (err <= Tol<T>::v() * scale) {
-      const T vrb = p.vr + kr;
-      const T rb1 = r0 + hd * vrb;
-      const T re1 = r0 + dtau * vrb;
-      if (!(re1 > T(0))) return false;
-      M.kr = kr;
-      M.kz = kz;
-      M.vr = vrb;
-      M.vz = p.vz + kz;
-      M.vt = p.vt * rb1 * rcp_refined(re1);
-      M.a = p.a + delta * vrb;
-      M.b = p.b + gamma * M.vz;
-      return true;
+    if (!ok || err <= Tol<T>::v() * scale) {
+      conv = ok;
+      break;
     }
   }
-  return false;
+  const T vrb = p.vr + kr;
+  const T rb1 = r0 + hd * vrb;
+  const T re1 = r0 + dtau * vrb;
+  const T kz = bz + Kz * vrb;
+  M.kr = kr;
+  M.kz = kz;
+  M.vr = vrb;
+  M.vz = p.vz + kz;
+  M.vt = p.vt * rb1 * rcp_refined(re1);
+  M.a = p.a + delta * vrb;
+  M.b = p.b + gamma * M.vz;
+  return conv & (re1 > T(0));
 }
 
 // Smallest positive root of (a/2) t^2 + v t - D = 0 in cancellation-free
