@@ -951,15 +951,15 @@ __device__ __forceinline__ bool decode_raw(const MapP& m, const Raw<double>& q, 
   p.vr = q.vr;
   p.vt = q.vt;
   p.vz = q.vz;
-  if (!(q.xi >= 0.0)) return false;
-  int i = int(floor(q.xi)), j = int(floor(q.eta));
+  const bool alive = q.xi >= 0.0;
+  int i = int(floor(alive ? q.xi : 0.0)), j = int(floor(alive ? q.eta : 0.0));
   i = i < 0 ? 0 : (i > m.nr - 1 ? m.nr - 1 : i);
   j = j < 0 ? 0 : (j > m.nz - 1 ? m.nz - 1 : j);
   p.i = i;
   p.j = j;
   p.a = q.xi - double(i);
   p.b = q.eta - double(j);
-  return true;
+  return alive;
 }
 __device__ __forceinline__ bool decode_raw(const MapP& m, const Raw<float>& q, PState<float>& p) {
   p.a = q.a;
@@ -1377,21 +1377,15 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
     Dep dp{0.0, 0.0, 0.0, 0.0};
     T F[4];
     if (alive) {
-      // on a face, the cell the motion goes to
-      if (p.a == T(1) && p.vr >= T(0) && p.i < m.nr - 1) {
-        p.i += 1;
-        p.a = T(0);
-      } else if (p.a == T(0) && p.vr < T(0) && p.i > 0) {
-        p.i -= 1;
-        p.a = T(1);
-      }
-      if (p.b == T(1) && p.vz >= T(0) && p.j < m.nz - 1) {
-        p.j += 1;
-        p.b = T(0);
-      } else if (p.b == T(0) && p.vz < T(0) && p.j > 0) {
-        p.j -= 1;
-        p.b = T(1);
-      }
+      // on a face, the cell the motion goes to (selects, no branches)
+      const bool ru = (p.a == T(1)) & (p.vr >= T(0)) & (p.i < m.nr - 1);
+      const bool rd = (p.a == T(0)) & (p.vr < T(0)) & (p.i > 0);
+      const bool zu = (p.b == T(1)) & (p.vz >= T(0)) & (p.j < m.nz - 1);
+      const bool zd = (p.b == T(0)) & (p.vz < T(0)) & (p.j > 0);
+      p.i += ru ? 1 : (rd ? -1 : 0);
+      p.a = ru ? T(0) : (rd ? T(1) : p.a);
+      p.j += zu ? 1 : (zd ? -1 : 0);
+      p.b = zu ? T(0) : (zd ? T(1) : p.b);
       load_field(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), p.i, p.j, F);
     }
     // the next particle's record, issued after this one's field gather; the
