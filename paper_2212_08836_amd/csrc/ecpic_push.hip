@@ -135,21 +135,17 @@ __device__ __forceinline__ bool accel(const MapP& m, const T F[4], int i, T abar
   const T ac = clamp01(abar), bc = clamp01(bbar);
   const T er = ((T(1) - bc) * F[0] + bc * F[1]) * ijr;
   const T ez = ((T(1) - ac) * F[2] + ac * F[3]) * T(m.inv_dz);
-  if (rb > T(0)) {
-    // vtb = vt0 / (1 + dtau vbr / (2 rb)) = vt0 rb q and vtb^2 / rb = vt0^2 rb q^2
-    // with q = 1 / (rb + dtau vbr / 2): one division
-    const T den = rb + T(0.5) * dtau * vbr;
-    if (!(den > T(0))) return false;
-    const T q = T(1) / den;
-    vtb = vt0 * rb * q;
-    ar = qm * er + vtb * vt0 * q;
-  } else {
-    if (vt0 != T(0)) return false;
-    vtb = T(0);
-    ar = qm * er;
-  }
+  // vtb = vt0 / (1 + dtau vbr / (2 rb)) = vt0 rb q and vtb^2 / rb = vt0^2 rb q^2
+  // with q = 1 / (rb + dtau vbr / 2): one division; on the axis (rb = 0)
+  // only a particle without v_theta is admissible.  Selects, no branches.
+  const bool off_axis = rb > T(0);
+  const T den = rb + T(0.5) * dtau * vbr;
+  const T q = T(1) / den;
+  vtb = off_axis ? vt0 * rb * q : T(0);
+  ar = qm * er + (off_axis ? vtb * vt0 * q : T(0));
   az = qm * ez;
-  return isfinite(ar) && isfinite(az) && isfinite(vtb);
+  const bool adm = off_axis ? (den > T(0)) : (vt0 == T(0));
+  return adm & isfinite(ar) & isfinite(az) & isfinite(vtb);
 }
 
 // Unconstrained sub-step of length dtau in the particle's cell: fixed point
@@ -162,11 +158,12 @@ __device__ bool solve_free(const MapP& m, const T F[4], const PState<T>& p, T dt
   const T idz = T(m.inv_dz);
   for (int it = 0; it < kMaxFixed; ++it) {
     T abar;
-    if (!mid_a(m, p.i, p.a, vr, dtau, abar)) return false;
+    const bool oka = mid_a(m, p.i, p.a, vr, dtau, abar);
     const T bbar = p.b + hd * vz * idz;
-    if (!isfinite(bbar)) return false;
     T ar, az, vtb;
-    if (!accel(m, F, p.i, abar, bbar, vr, p.vt, dtau, qm, ar, az, vtb)) return false;
+    // admissibility as flags, one exit per iteration
+    if (!(oka & isfinite(bbar) & accel(m, F, p.i, abar, bbar, vr, p.vt, dtau, qm, ar, az, vtb)))
+      return false;
     const T nvr = p.vr + hd * ar, nvz = p.vz + hd * az, nvt = vtb;
     const T scale = fabs(nvr) + fabs(nvt) + fabs(nvz);
     const T d = fmax(fabs(nvr - vr), fmax(fabs(nvt - vt), fabs(nvz - vz)));
@@ -324,17 +321,19 @@ __device__ bool solve_cross(const MapP& m, const T F[4], const PState<T>& p, int
   T dtau = dt0;
   const T idz = T(m.inv_dz);
   for (int it = 0; it < kMaxFixed; ++it) {
+    // admissibility as flags, one exit per iteration
     T abar, bbar;
+    bool ok = true;
     if (d == 0) {
       abar = xbar;
       bbar = p.b + T(0.5) * dtau * vz * idz;
     } else {
       bbar = xbar;
-      if (!mid_a(m, p.i, p.a, vr, dtau, abar)) return false;
+      ok = mid_a(m, p.i, p.a, vr, dtau, abar);
     }
-    if (!isfinite(bbar)) return false;
     T ar, az, vtb;
-    if (!accel(m, F, p.i, abar, bbar, vr, p.vt, dtau, qm, ar, az, vtb)) return false;
+    ok = ok & isfinite(bbar) & accel(m, F, p.i, abar, bbar, vr, p.vt, dtau, qm, ar, az, vtb);
+    if (!ok) return false;
     T nd = smallest_pos_root(d == 0 ? ar : az, v0d, D);
     bool cap = false;
     if (!(nd <= dmax)) {
