@@ -341,6 +341,21 @@ def test_step_parity_driven_collisional(og, torch_cuda):
     _step_parity(og, P, w, parts, 8, mcc=mcc, sort_every=3)
 
 
+def test_step_parity_immobile_ions_collisional(og, torch_cuda):
+    # one mobile species: the passes run one slot, the commit is never fused
+    # (an immobile species' buffer would not flip), so every step ends with
+    # the separate commit pass and its collision list
+    import paper_2212_08836_amd as P
+    _flush("step parity, immobile ions, MCC")
+    w = E.Workload("c2s", 48, 24, 0.03, 0.012, n0=1e16, profile="j0sin", ppc=12,
+                   drive_amp=(200.0,), drive_freq=(100e6,), pressure_pa=60.0, seed=13,
+                   dt=1e-11, tol=1e-10)
+    parts = E.make_particles(w)
+    for k in ("vr", "vt", "vz"):
+        parts[0][k] = parts[0][k] * 3.0
+    _step_parity(og, P, w, parts, 4, mcc=w.mcc_params(), sort_every=2, mobile=(True, False))
+
+
 def test_collide_parity(og, torch_cuda):
     import paper_2212_08836_amd as P
     _flush("collide parity")
