@@ -1170,12 +1170,11 @@ __device__ void tl_flush(const Tl& t, Tally* tally, int sid) {
 // commit of one pushed particle: absorption (wall charge, energy) or state
 // write after the null-collision step
 template <typename T>
-__device__ void commit_one(const PushArgs& A, int64_t k, PState<T>& p, int status, int wall,
-                           Tl& t) {
+__device__ void commit_one(const PushArgs& A, int64_t k, uint64_t uid, PState<T>& p, int status,
+                           int wall, Tl& t) {
   const SpecDev& s = A.out;
   const MapP& m = A.m;
   const double qw = s.q * s.w;
-  const uint64_t uid = A.s.uid[k];  // both buffers share the uid array
   if (status == kError) t.err += 1;
   if (status == kAbsorbed) {
     kill_particle<T>(s, k);
@@ -1575,7 +1574,7 @@ __device__ __forceinline__ int64_t queue_pos(const QView& q, int e, int64_t qseg
 // splitting at every face crossing (restarted from the particle's state),
 // currents into the wavefront's tile.
 template <typename T, bool COMMIT>
-__device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, PState<T>& p,
+__device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, uint64_t uid, PState<T>& p,
                                          const Tile& tl, Tl& t) {
   const MapP& m = A.m;
   const SpecDev& s = A.s;
@@ -1609,7 +1608,7 @@ __device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, PState<T>
     t.work += o.work;
     t.nsub += o.nsub;
     t.ncross += o.ncross;
-    commit_one<T>(A, k, p, o.status, o.wall, t);
+    commit_one<T>(A, k, uid, p, o.status, o.wall, t);
   }
 }
 
@@ -1619,10 +1618,11 @@ template <typename T>
 __device__ __forceinline__ void listed_one(const PushArgs& A, int64_t k, Tl& t) {
   const MapP& m = A.m;
   const SpecDev& s = A.out;  // the pushed state, where the commit stored it
+  const uint64_t uid = s.uid[k];  // issued with the record's loads
   PState<T> p;
   if (!load_particle<T>(s, m, k, p)) return;
   double vr = p.vr, vt = p.vt, vz = p.vz;
-  const CollOut co = collide_one<T>(A.mcc, s, m, s.sid, s.uid[k], p.i, p.j, p.a, p.b, vr, vt, vz,
+  const CollOut co = collide_one<T>(A.mcc, s, m, s.sid, uid, p.i, p.j, p.a, p.b, vr, vt, vz,
                                     A.tally);
   t.dke_coll += co.dke;
   t.coll += co.coll;
@@ -1707,10 +1707,14 @@ __global__ void __launch_bounds__(kQThreads, WAVES) k_queue(PassArgs P) {
       // the lowest (a unit holds consecutive queue entries, which come from
       // one or two fast-pass blocks of cell-sorted particles)
       int64_t k = 0;
+      uint64_t uid = 0;
       PState<T> p;
       bool ok = false;
       if (e < v.total) {
         k = P.queue[slot][pos];
+        // a commit's id load (both buffers share the id array), issued now
+        // so that it is in flight during the push
+        if (MODE != kQSlow) uid = A.s.uid[k];
         Raw<T> r;
         load_rec(P.qrec[slot], P.qcap, pos, r);
         ok = decode_raw(A.m, r, p);
@@ -1731,7 +1735,7 @@ __global__ void __launch_bounds__(kQThreads, WAVES) k_queue(PassArgs P) {
       if (dep)
         for (int q = lane; q < lr + lz; q += kQThreads) qtile[q] = 0.0;
       __syncthreads();
-      if (ok) slow_one<T, MODE != kQSlow>(A, k, p, tl, t);
+      if (ok) slow_one<T, MODE != kQSlow>(A, k, uid, p, tl, t);
       __syncthreads();
       if (dep) {
         // flush: one global atomic per touched edge
