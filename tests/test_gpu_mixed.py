@@ -144,6 +144,15 @@ def test_mixed_one_step_c3(torch_cuda):
     _one_step_compare(P, w, 8, w.mcc_params())
 
 
+def test_mixed_one_step_long_rows(torch_cuda):
+    # 384 cells along z: the slow pass's tile spans part of a row only
+    import paper_2212_08836_amd as P
+    _flush("mixed vs fp64, 32 x 384")
+    w = E.Workload("long", 32, 384, 0.05, 0.03, n0=1e16, profile="j0sin", ppc=8,
+                   drive_amp=(200.0,), drive_freq=(100e6,), pressure_pa=5.0, seed=21)
+    _one_step_compare(P, w, 10, w.mcc_params())
+
+
 def test_mixed_deposit_conserves_charge(og, torch_cuda):
     # continuity of the mixed deposit: the currents are those of the FP32
     # displacements before the new offsets are rounded to FP32 for storage,
