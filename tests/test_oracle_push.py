@@ -199,3 +199,51 @@ def test_uncommitted_pass_leaves_state(og):
     after = sp.view()
     for k in before:
         assert np.array_equal(before[k], after[k])
+
+
+def _exb_orbit(og, dt, nsteps, B, E0, R, r0, vt0, dvr):
+    g = og.Grid(100, 4, R, 0.004, 2.0, dt, EPS0, MU0, bz_ext=B, er_ext=E0)
+    ur, uz = g.zeros_r(), g.zeros_z()
+    sp = og.Species(-QE, ME, 1.0, [g.xi_of_r(r0)], [2.0], [dvr], [vt0], [0.0], [0])
+    r = [r0]
+    for n in range(nsteps):
+        g.push_deposit(sp, ur, uz, commit=True, state=og.State(g))
+        assert sp.n == 1
+        r.append(g.r_of_xi(sp.xi[0]))
+    return np.array(r)
+
+
+def _sinusoid_frequency(s, dt):
+    # s_n = c + A cos(W n dt + p): the differences d_n obey
+    # d_{n+1} + d_{n-1} = 2 cos(W dt) d_n; least squares for cos(W dt)
+    d = np.diff(s)
+    x, y = d[1:-1], d[2:] + d[:-2]
+    c = np.dot(x, y) / (2 * np.dot(x, x))
+    return math.acos(c) / dt
+
+
+def test_exb_epicyclic_frequency_is_second_order(og):
+    # E_r = E0 r / R plus uniform B_z.  In x + i y = zeta the motion is linear:
+    # zeta'' = k zeta - i wc zeta' with k = (q/m) E0 / R, wc = q B / m, so every
+    # orbit is a sum of two circular modes exp(i w t), w^2 + wc w + k = 0, and
+    # r^2 = |zeta|^2 oscillates at the difference of the roots,
+    # W = sqrt(wc^2 - 4k), at any amplitude.  Start on the slow (E x B) rigid
+    # rotation and kick v_r: the measured frequency of r^2 converges to W at
+    # second order in dt.
+    B, E0, R = 0.02, -2.0e4, 0.1
+    q, m = -QE, ME
+    wc = q * B / m
+    k = (q / m) * E0 / R
+    W = math.sqrt(wc * wc - 4 * k)
+    w_slow = (-wc - math.copysign(W, -wc)) / 2   # the root of smaller modulus
+    assert abs(w_slow) < 0.01 * abs(wc)
+    r0 = 0.06
+    T = 2 * math.pi / W
+    errs = []
+    for dt in (T / 24, T / 48, T / 96):
+        n = int(round(4 * T / dt))
+        r = _exb_orbit(og, dt, n, B, E0, R, r0, w_slow * r0, 0.3 * abs(w_slow) * r0)
+        assert np.ptp(r) > 1e-3 * r0   # the kick excites the fast mode
+        errs.append(abs(_sinusoid_frequency(r * r, dt) / W - 1))
+    assert errs[0] < 1e-2
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
