@@ -14,8 +14,18 @@
  *    count) synchronise that stream; the others are asynchronous.
  *  - Array pointers marked (device) are device memory owned by the caller;
  *    the library reads or writes them during the call (stream-ordered) and
- *    keeps no reference.  The library owns its internal state (particle SoA,
- *    field and solver arrays) and frees it in ecpic_destroy.
+ *    keeps no reference (ecpic_bind_fields excepted).
+ *  - Device memory of the context.  ecpic_create allocates none.  All of the
+ *    context's device arrays (particle SoA of every species, fields, solver
+ *    tables, queues, scratch) live in one region: either a workspace the
+ *    caller allocates and binds (ecpic_workspace_size, then
+ *    ecpic_bind_workspace, after every ecpic_add_species; the library then
+ *    never allocates device memory for them), or, if none is bound, one
+ *    block the library allocates at the first call that needs the device
+ *    and frees in ecpic_destroy.  Species added after that first call get
+ *    allocations of their own (library-owned region only).  The training
+ *    calls ecpic_nn_forward / ecpic_nn_grad grow a batch workspace of their
+ *    own.  Pinned host words (residuals, summaries) are the library's.
  *  - A context is not thread-safe; calls on one context must be serialised.
  *  - Layouts (row-major, FP64):
  *      ur[i][j], 0<=i<nr, 0<=j<=nz : voltage of r-edge (i+1/2, j)      [V]
@@ -96,6 +106,10 @@ typedef struct {
   int32_t fixed_iter;     /* >0: exactly this many iterations (parity mode)  */
   int32_t sort_every;     /* counting sort by cell every k steps (0 = never) */
   int32_t use_nn;         /* 1: learned initial guess (see ecpic_nn_*)       */
+  int32_t check_conservation; /* 1: fill gauss_max, continuity_max, q_max of
+                             the step's statistics (one node-charge pass
+                             over the particles per step, plus one at the
+                             first checked step)                             */
 } ecpic_step_opts;
 
 typedef struct {
@@ -116,6 +130,17 @@ typedef struct {
   int64_t n_substeps, n_crossings, n_errors, n_over_range;
   double t;               /* time after the step [s]                         */
   int64_t step;           /* step counter after the step                     */
+  /* With check_conservation (Sec. 2.1: the charge-conserving current keeps
+   * Gauss's law once it holds).  Q = particle node charge (bilinear
+   * weights) plus the wall charge on the wall nodes; div = net flux out of a
+   * node's dual cell.  All in coulombs, maxima over nodes:                   */
+  double continuity_max;  /* |Q^{n+1} - Q^n + dt div I| over every node, with
+                             I the currents of the accepted iterate          */
+  double gauss_max;       /* |(G - Q_p)^{n+1} - (G - Q_p)^n| over the nodes
+                             off the conducting walls (0<=i<nr, 0<j<nz), G
+                             = div of the displacement flux eps Ad u / l,
+                             Ad the dual-face area of an edge of length l   */
+  double q_max;           /* max |Q_p^{n+1}|, the scale of the two above     */
 } ecpic_step_stats;
 
 typedef struct ecpic_ctx ecpic_ctx;
@@ -128,10 +153,43 @@ ecpic_status ecpic_create(const ecpic_grid_desc* grid, ecpic_precision prec, voi
                           ecpic_ctx** out);
 ecpic_status ecpic_destroy(ecpic_ctx* ctx);
 
-/* Add a species with room for desc->capacity macro-particles (device memory
- * allocated here; at most 2^29 per species).  Up to 4 species.  *sid
- * receives its index.  EINVAL for a bad descriptor or a fifth species. */
+/* Add a species with room for desc->capacity macro-particles (at most 2^29
+ * per species).  Up to 4 species.  *sid receives its index.  Its device
+ * buffers come with the context's region (see the conventions).  EINVAL for
+ * a bad descriptor, a fifth species, or a species added after a workspace
+ * was bound; ENOMEM if a library allocation fails. */
 ecpic_status ecpic_add_species(ecpic_ctx* ctx, const ecpic_species_desc* desc, int32_t* sid);
+
+/* Bytes of device memory the context needs for its grid and the species
+ * added so far (all particle buffers, fields, solver tables, queues and
+ * scratch), as ecpic_bind_workspace expects them.  Host only. */
+ecpic_status ecpic_workspace_size(const ecpic_ctx* ctx, size_t* bytes);
+
+/* Give the context its device memory: ws (device, 256-byte aligned, at
+ * least ecpic_workspace_size bytes) is owned by the caller, who keeps it
+ * alive until ecpic_destroy and frees it afterwards; the library carves
+ * every device array from it and allocates none of its own for them.  Must
+ * come after the last ecpic_add_species and before any call that touches the
+ * device.  The solver tables are uploaded and the state cleared here
+ * (synchronises).  EINVAL if device memory is already in use or ws is
+ * misaligned, ENOMEM if bytes is too small. */
+ecpic_status ecpic_bind_workspace(ecpic_ctx* ctx, void* ws, size_t bytes);
+
+/* Field arrays of the state in the caller's memory (device, FP64, layouts as
+ * above). */
+typedef struct {
+  double *ur, *uz, *h;                /* u at t^n                            */
+  double *ur_prev, *uz_prev, *h_prev; /* u at t^{n-1}                        */
+} ecpic_field_view;
+
+/* Keep the field state in the caller's arrays (six distinct device arrays,
+ * owned by the caller and kept alive while bound): their current contents
+ * become u^n and u^{n-1} (as ecpic_set_fields would set them, without a
+ * copy), and every committed step leaves the new u^n and u^{n-1} in the same
+ * arrays (a copy kernel per step), so the caller reads the state in place.
+ * view = NULL unbinds: the state is copied back into the library's arrays
+ * (synchronises).  EINVAL for a null or repeated array. */
+ecpic_status ecpic_bind_fields(ecpic_ctx* ctx, const ecpic_field_view* view);
 
 /* Replace the particles of a species.  r, z: physical positions [m] inside
  * (0,R]x(0,L); vr, vt, vz [m/s]; uid: identifiers (RNG counters).  All
@@ -180,7 +238,11 @@ ecpic_status ecpic_field_solve(ecpic_ctx* ctx, const double* ur0, const double* 
 ecpic_status ecpic_field_iterate(ecpic_ctx* ctx, double* rel_update);
 
 /* Null-collision Monte Carlo on the current velocities (Sec. 2.1), at the
- * given step index (RNG counter).  ECAPACITY if ionisation overflowed. */
+ * given step index (RNG counter), in place.  ECAPACITY: an ionisation whose
+ * electron-ion pair did not fit was not applied (its electron keeps its
+ * velocity; every other collision was applied).  ERANGE: the collisions
+ * were applied, and some particle's collision rate exceeded the
+ * null-collision bound (raise eps_max_ev). */
 ecpic_status ecpic_collide(ecpic_ctx* ctx, const ecpic_mcc_desc* mcc, int64_t step);
 
 /* Collision model used by ecpic_step (NULL or enabled=0 turns MCC off). */
@@ -189,8 +251,12 @@ ecpic_status ecpic_set_mcc(ecpic_ctx* ctx, const ecpic_mcc_desc* mcc);
 /* One implicit step: extrapolated (or learned) guess, Picard iterations of
  * push_deposit + field_iterate until r_k <= tol (or fixed_iter passes),
  * commit of the particles pushed in the accepted half-step field, MCC,
- * optional sort, field shift.  ENOTCONV leaves state and fields untouched.
- * stats may be NULL. */
+ * optional sort, field shift.  stats may be NULL.  A step that returns
+ * ENOTCONV, ECAPACITY (an ionisation's electron-ion pair did not fit in a
+ * species' capacity) or ERANGE (a particle's collision rate exceeded the
+ * null-collision bound, eps_max_ev) is not committed: particles, counts,
+ * fields, wall charge and clock are as before the call (stats are filled).
+ * EPUSH: committed, with n_errors particles whose push failed. */
 ecpic_status ecpic_step(ecpic_ctx* ctx, const ecpic_step_opts* opts, ecpic_step_stats* stats);
 
 /* n_steps implicit steps with the same options, back to back in the library
@@ -295,6 +361,25 @@ ecpic_status ecpic_set_profiling(ecpic_ctx* ctx, int32_t kind_mask);
 ecpic_status ecpic_set_profiling_every(ecpic_ctx* ctx, int32_t every);
 /* Totals since profiling was turned on (synchronises). */
 ecpic_status ecpic_get_profile(ecpic_ctx* ctx, ecpic_profile* out);
+
+/* Switches: kernel builds (the results are the same to the inner-solve
+ * tolerance; they exist for tuning and so that every compiled build can be
+ * compared with the CPU reference at small sizes) and a test switch. */
+typedef enum {
+  ECPIC_OPT_QUEUE_WAVES = 0, /* the plain slow pass (face crossers, Eq. (4)
+                                split at crossings): 0 = chosen by size (the
+                                build for three wavefronts per SIMD from 16M
+                                particles per pass, else two), 2 or 3 = that
+                                build always                                 */
+  ECPIC_OPT_NN_FORCE_FALLBACK = 1 /* test switch for the learned guess's
+                                fallback: k >= 1 makes a step that uses the
+                                learned guess treat residual k as not falling
+                                (the fallback to the extrapolated guess is
+                                then taken at iteration k, as for a real rise);
+                                0 = off (the default)                        */
+} ecpic_option;
+/* Set a switch.  EINVAL for an unknown option or value. */
+ecpic_status ecpic_set_option(ecpic_ctx* ctx, int32_t option, int64_t value);
 
 const char* ecpic_last_error(const ecpic_ctx* ctx);
 const char* ecpic_status_string(ecpic_status s);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libecpic.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ecpic.h")
 
 ECPIC_FP64, ECPIC_MIXED = 0, 1
+ECPIC_OPT_QUEUE_WAVES, ECPIC_OPT_NN_FORCE_FALLBACK = 0, 1
 ECPIC_OK, ECPIC_EINVAL, ECPIC_ENOMEM, ECPIC_EHIP, ECPIC_ENOTCONV = 0, -1, -2, -3, -4
 ECPIC_EPUSH, ECPIC_ECAPACITY, ECPIC_ERANGE, ECPIC_ENOTIMPL = -5, -6, -7, -8
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "EPUSH",
@@ -52,7 +53,13 @@ class MccDesc(C.Structure):
 
 class StepOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("fixed_iter", C.c_int32),
-                ("sort_every", C.c_int32), ("use_nn", C.c_int32)]
+                ("sort_every", C.c_int32), ("use_nn", C.c_int32),
+                ("check_conservation", C.c_int32)]
+
+
+class FieldView(C.Structure):
+    _fields_ = [("ur", C.c_void_p), ("uz", C.c_void_p), ("h", C.c_void_p),
+                ("ur_prev", C.c_void_p), ("uz_prev", C.c_void_p), ("h_prev", C.c_void_p)]
 
 
 class StepStats(C.Structure):
@@ -63,7 +70,8 @@ class StepStats(C.Structure):
                 ("w_coll", C.c_double), ("n_alive", C.c_int64 * 4), ("n_absorbed", C.c_int64 * 4),
                 ("n_coll", C.c_int64 * 4), ("n_ionized", C.c_int64), ("n_substeps", C.c_int64),
                 ("n_crossings", C.c_int64), ("n_errors", C.c_int64), ("n_over_range", C.c_int64),
-                ("t", C.c_double), ("step", C.c_int64)]
+                ("t", C.c_double), ("step", C.c_int64), ("continuity_max", C.c_double),
+                ("gauss_max", C.c_double), ("q_max", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -104,6 +112,9 @@ def lib() -> C.CDLL:
         sig = {
             "ecpic_create": ([C.POINTER(GridDesc), C.c_int, _vp, C.POINTER(_vp)], st),
             "ecpic_destroy": ([_vp], st),
+            "ecpic_workspace_size": ([_vp, C.POINTER(C.c_size_t)], st),
+            "ecpic_bind_workspace": ([_vp, _vp, C.c_size_t], st),
+            "ecpic_bind_fields": ([_vp, C.POINTER(FieldView)], st),
             "ecpic_add_species": ([_vp, C.POINTER(SpeciesDesc), C.POINTER(C.c_int32)], st),
             "ecpic_load_particles": ([_vp, C.c_int32] + [_dp] * 6 + [C.c_int64], st),
             "ecpic_read_particles": ([_vp, C.c_int32] + [_dp] * 6 + [C.c_int64,
@@ -128,6 +139,7 @@ def lib() -> C.CDLL:
             "ecpic_nn_grad": ([_vp, _vp, _vp, _vp, C.c_int32, _vp, C.POINTER(C.c_float)], st),
             "ecpic_nn_adam": ([_vp, _vp, _vp, _vp, _vp, C.c_float, C.c_int32], st),
             "ecpic_set_profiling": ([_vp, C.c_int32], st),
+            "ecpic_set_option": ([_vp, C.c_int32, C.c_int64], st),
             "ecpic_set_profiling_every": ([_vp, C.c_int32], st),
             "ecpic_get_profile": ([_vp, C.POINTER(Profile)], st),
             "ecpic_last_error": ([_vp], C.c_char_p),
@@ -160,6 +172,9 @@ class Context:
 
     def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
                  drive_phase=(), precision: str = "fp64", device: str = "cuda"):
+        """The context allocates no device memory until its first device call;
+        call :meth:`bind_workspace` after the last :meth:`add_species` to give
+        it a torch-allocated region instead."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -180,6 +195,8 @@ class Context:
                                         else ECPIC_FP64, _vp(stream), C.byref(h)), None)
         self.h = h
         self.caps: Dict[int, int] = {}
+        self.workspace = None
+        self._bound_fields = None
 
     def _check(self, rc: int, h=None):
         if rc != 0:
@@ -198,6 +215,40 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # -- device memory owned by torch --
+    def workspace_size(self) -> int:
+        n = C.c_size_t()
+        self._check(self.L.ecpic_workspace_size(self.h, C.byref(n)), self.h)
+        return int(n.value)
+
+    def bind_workspace(self, nbytes: Optional[int] = None):
+        """Allocate the context's whole device region as one torch tensor and
+        bind it (after the last add_species)."""
+        t = self.torch
+        n = self.workspace_size() if nbytes is None else int(nbytes)
+        ws = t.empty(n + 256, dtype=t.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        self._check(self.L.ecpic_bind_workspace(self.h, _vp(ws.data_ptr() + off), n), self.h)
+        self.workspace = ws
+        return ws
+
+    def bind_fields(self, ur, uz, h, ur_prev, uz_prev, h_prev):
+        """Keep u^n, u^{n-1} in these six torch FP64 device tensors (their
+        contents become the state); None as ur unbinds."""
+        if ur is None:
+            self._check(self.L.ecpic_bind_fields(self.h, None), self.h)
+            self._bound_fields = None
+            return
+        ts = (ur, uz, h, ur_prev, uz_prev, h_prev)
+        for a in ts:
+            assert a.is_cuda and a.dtype == self.torch.float64 and a.is_contiguous()
+        assert ur.numel() == self.nr * (self.nz + 1) == ur_prev.numel()
+        assert uz.numel() == (self.nr + 1) * self.nz == uz_prev.numel()
+        assert h.numel() == self.nr * self.nz == h_prev.numel()
+        v = FieldView(*[a.data_ptr() for a in ts])
+        self._check(self.L.ecpic_bind_fields(self.h, C.byref(v)), self.h)
+        self._bound_fields = ts
 
     # -- tensors --
     def _dev(self, a, dtype=None):
@@ -305,8 +356,8 @@ class Context:
         self._check(self.L.ecpic_collide(self.h, C.byref(d), int(step)), self.h)
 
     def step(self, tol=1e-10, max_iter=50, fixed_iter=0, sort_every=0, use_nn=False,
-             stats=True, check=True):
-        o = StepOpts(tol, max_iter, fixed_iter, sort_every, int(use_nn))
+             stats=True, check=True, conservation=False):
+        o = StepOpts(tol, max_iter, fixed_iter, sort_every, int(use_nn), int(conservation))
         if stats:
             s = StepStats()
             rc = self.L.ecpic_step(self.h, C.byref(o), C.byref(s))
@@ -320,10 +371,10 @@ class Context:
         return d
 
     def run(self, n_steps, tol=1e-10, max_iter=50, fixed_iter=0, sort_every=0, use_nn=False,
-            stats=False, check=True):
+            stats=False, check=True, conservation=False):
         """n_steps implicit steps in the library (ecpic_run); returns the
         number done and, with stats, the last step's statistics."""
-        o = StepOpts(tol, max_iter, fixed_iter, sort_every, int(use_nn))
+        o = StepOpts(tol, max_iter, fixed_iter, sort_every, int(use_nn), int(conservation))
         done = C.c_int32(0)
         s = StepStats() if stats else None
         rc = self.L.ecpic_run(self.h, C.byref(o), int(n_steps), C.byref(done),
@@ -346,6 +397,9 @@ class Context:
         self._check(self.L.ecpic_node_charge(self.h, _ptr(q), _ptr(b), _ptr(tp), _ptr(sd)), self.h)
         t.cuda.synchronize()
         return q.cpu().numpy(), b.cpu().numpy(), tp.cpu().numpy(), sd.cpu().numpy()
+
+    def set_option(self, option: int, value: int):
+        self._check(self.L.ecpic_set_option(self.h, int(option), int(value)), self.h)
 
     def set_profiling(self, on: bool = True, kinds=None, every: int = 1):
         """Time launches with HIP events: every kind when `kinds` is None,
@@ -425,17 +479,24 @@ class Context:
 
 
 def context_from_workload(w, precision="fp64", device="cuda", **over) -> Context:
+    """A context for workload w (ecpic_inputs.Workload)."""
     p = w.grid_params()
     p.update(over)
     return Context(precision=precision, device=device, **p)
 
 
-def load_workload_species(ctx: Context, parts, extra_cap: float = 0.0, mobile=(True, True)):
+def load_workload_species(ctx: Context, parts, extra_cap: float = 0.0, mobile=(True, True),
+                          workspace: bool = False):
+    """Add the species of `parts` and load them; with workspace, the
+    context's device region is one torch tensor bound before the load."""
     sids = []
     for k, d in enumerate(parts):
         n = len(d["r"])
         cap = int(n * (1.0 + extra_cap)) + 256
         sid = ctx.add_species(d["q"], d["m"], d["w"], cap, mobile[k] if k < len(mobile) else True)
-        ctx.load_particles(sid, d["r"], d["z"], d["vr"], d["vt"], d["vz"], d["uid"])
         sids.append(sid)
+    if workspace:
+        ctx.bind_workspace()
+    for sid, d in zip(sids, parts):
+        ctx.load_particles(sid, d["r"], d["z"], d["vr"], d["vt"], d["vz"], d["uid"])
     return sids

@@ -46,45 +46,133 @@ double r_of_xi(const MapP& m, double xi) {
   return m.s * (xi + m.xi_a);
 }
 
-template <typename T>
-hipError_t dalloc(T** p, size_t n) {
-  return hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
-}
-
-hipError_t alloc_species_buf(Ctx& c, SpecDev& d, int64_t cap) {
-  hipError_t e;
-  const size_t n = (size_t)std::max<int64_t>(cap, 1);
-  std::memset(&d, 0, sizeof(d));
-  if (c.prec == ECPIC_FP64) {
-    if ((e = dalloc(&d.xi, n)) != hipSuccess) return e;
-    if ((e = dalloc(&d.eta, n)) != hipSuccess) return e;
-    if ((e = dalloc(&d.vr, n)) != hipSuccess) return e;
-    if ((e = dalloc(&d.vt, n)) != hipSuccess) return e;
-    if ((e = dalloc(&d.vz, n)) != hipSuccess) return e;
-  } else {
-    if ((e = dalloc(&d.cell, n)) != hipSuccess) return e;
-    if ((e = dalloc(&d.fa, n)) != hipSuccess) return e;
-    if ((e = dalloc(&d.fb, n)) != hipSuccess) return e;
-    if ((e = dalloc(&d.fvr, n)) != hipSuccess) return e;
-    if ((e = dalloc(&d.fvt, n)) != hipSuccess) return e;
-    if ((e = dalloc(&d.fvz, n)) != hipSuccess) return e;
+// Device memory layout.  One walk over every device array computes the
+// size of the region (base null); a second assigns the arrays from a region
+// of that size.  Arrays start on 256-byte boundaries.
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  void take(T** p, size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    if (base) *p = reinterpret_cast<T*>(base + off);
+    off += std::max<size_t>(n, 1) * sizeof(T);
   }
-  return dalloc(&d.uid, n);
+};
+
+void carve_species_buf(const Ctx& c, Carver& k, SpecDev& d, int64_t cap) {
+  const size_t n = (size_t)std::max<int64_t>(cap, 1);
+  if (c.prec == ECPIC_FP64) {
+    k.take(&d.xi, n);
+    k.take(&d.eta, n);
+    k.take(&d.vr, n);
+    k.take(&d.vt, n);
+    k.take(&d.vz, n);
+  } else {
+    k.take(&d.cell, n);
+    k.take(&d.fa, n);
+    k.take(&d.fb, n);
+    k.take(&d.fvr, n);
+    k.take(&d.fvt, n);
+    k.take(&d.fvz, n);
+  }
+  k.take(&d.uid, n);
 }
 
-void free_species_buf(SpecDev& d) {
-  (void)hipFree(d.xi);
-  (void)hipFree(d.eta);
-  (void)hipFree(d.vr);
-  (void)hipFree(d.vt);
-  (void)hipFree(d.vz);
-  (void)hipFree(d.cell);
-  (void)hipFree(d.fa);
-  (void)hipFree(d.fb);
-  (void)hipFree(d.fvr);
-  (void)hipFree(d.fvt);
-  (void)hipFree(d.fvz);
-  (void)hipFree(d.uid);
+// queue entries per species and kind for a species of capacity cap
+int64_t queue_len(int64_t cap) { return kSpread * queue_segment(cap); }
+
+// int32 words of the block counts ecpic_read_particles needs at capacity cap
+int64_t read_scratch_len(int64_t cap) {
+  const int64_t nb = (cap + kBlock - 1) / kBlock;
+  return nb + 1 + (nb + 1023) / 1024 + 2;
+}
+
+void carve_queues(Ctx& c, Carver& k, int64_t max_cap, int32_t nsp) {
+  const int64_t ql = queue_len(max_cap);
+  k.take(&c.queue, (size_t)ql * nsp * 2);   // slow queues, then collision lists
+  k.take(&c.qrec, (size_t)ql * nsp * 5);    // records of slow-queue entries
+  k.take(&c.rd_scratch, (size_t)read_scratch_len(max_cap));
+  if (k.base) {
+    c.queue_cap = ql;
+    c.queue_species = nsp;
+    c.rd_scratch_len = read_scratch_len(max_cap);
+  }
+}
+
+int64_t n_edges_r(const Ctx& c) { return (int64_t)c.g.nr * (c.g.nz + 1); }
+int64_t n_edges_z(const Ctx& c) { return (int64_t)(c.g.nr + 1) * c.g.nz; }
+int64_t n_cells(const Ctx& c) { return (int64_t)c.g.nr * c.g.nz; }
+int64_t n_nodes(const Ctx& c) { return (int64_t)(c.g.nr + 1) * (c.g.nz + 1); }
+
+// Every device array of the context and of its species so far.
+void carve_all(Ctx& c, Carver& k) {
+  const int nr = c.g.nr, nz = c.g.nz;
+  const size_t nur = (size_t)n_edges_r(c), nuz = (size_t)n_edges_z(c), nh = (size_t)n_cells(c);
+  double** er[] = {&c.ur, &c.ur_prev, &c.ur_it, &c.ur_nx, &c.ur_half, &c.Ir, &c.Ir_alt,
+                   &c.ur_half2, &c.ur_spare};
+  double** ez[] = {&c.uz, &c.uz_prev, &c.uz_it, &c.uz_nx, &c.uz_half, &c.Iz, &c.Iz_alt,
+                   &c.uz_half2, &c.uz_spare};
+  for (double** p : er) k.take(p, nur);
+  for (double** p : ez) k.take(p, nuz);
+  double** eh[] = {&c.h, &c.h_prev, &c.h_it, &c.h_nx};
+  for (double** p : eh) k.take(p, nh);
+  // wall charge: bottom, top and side in one array (the layout of the
+  // committing iterations' scratch, which is added into it)
+  k.take(&c.wall_bot, (size_t)wall_len(c));
+  k.take(&c.wall_scr, 2 * (size_t)wall_len(c));
+  if (c.prec == ECPIC_MIXED) {
+    k.take(&c.ur_half_f, nur);
+    k.take(&c.uz_half_f, nuz);
+    k.take(&c.ur_half_f2, nur);
+    k.take(&c.uz_half_f2, nuz);
+  }
+  k.take(&c.hist, nh + 1);
+  k.take(&c.offs, nh + 1);
+  k.take(&c.scan_part, (nh + 1023) / 1024 + 2);
+  k.take(&c.tally, 2 * kSpread);
+  k.take(&c.qcount, 2 * kQCount);
+  k.take(&c.stop, 2);
+  SolverDev& S = c.sol;
+  k.take(&S.rh, nr);
+  k.take(&S.wr, nr);
+  k.take(&S.wz, nr);
+  k.take(&S.area, nr);
+  k.take(&S.Q, (size_t)nz * nz);
+  k.take(&S.Qt, (size_t)nz * nz);
+  k.take(&S.tri_lo, (size_t)nz * nr);
+  k.take(&S.tri_inv, (size_t)nz * nr);
+  k.take(&S.tri_up, nr);
+  k.take(&S.work0, nh);
+  k.take(&S.work1, nh);
+  k.take(&S.partial, kPartLen);
+  const size_t nn = (size_t)n_nodes(c);
+  k.take(&c.q_node, nn);
+  k.take(&c.q0, nn);
+  k.take(&c.gq0, nn);
+  k.take(&c.cons_dev, 4);
+  k.take(&c.nn_w, (size_t)ecpic_nn_param_count());
+  char* gws = nullptr;
+  k.take(&gws, nn_guess_ws_bytes(c));
+  if (k.base) {
+    c.nn_gws = gws;
+    c.nn_gws_bytes = nn_guess_ws_bytes(c);
+  }
+  int64_t max_cap = 0;
+  for (Species& s : c.sp) {
+    carve_species_buf(c, k, s.d[0], s.desc.capacity);
+    carve_species_buf(c, k, s.d[1], s.desc.capacity);
+    max_cap = std::max<int64_t>(max_cap, s.desc.capacity);
+  }
+  carve_queues(c, k, max_cap, std::max<int32_t>((int32_t)c.sp.size(), 1));
+}
+
+// a device allocation of the library's own, freed at destroy
+template <typename T>
+hipError_t owned_alloc(Ctx& c, T** p, size_t n) {
+  const hipError_t e = hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+  if (e == hipSuccess) c.owned.push_back((void*)*p);
+  return e;
 }
 
 SpecDev view(Species& s) {
@@ -118,10 +206,6 @@ SpecDev other_view(Species& s) {
   d.fvz = o.fvz;
   return d;
 }
-
-int64_t n_edges_r(const Ctx& c) { return (int64_t)c.g.nr * (c.g.nz + 1); }
-int64_t n_edges_z(const Ctx& c) { return (int64_t)(c.g.nr + 1) * c.g.nz; }
-int64_t n_cells(const Ctx& c) { return (int64_t)c.g.nr * c.g.nz; }
 
 // Geometry and separable-solver tables (host FP64), uploaded once.
 hipError_t setup_solver(Ctx& c) {
@@ -178,24 +262,21 @@ hipError_t setup_solver(Ctx& c) {
   }
   SolverDev& S = c.sol;
   hipError_t e;
-  auto up = [&](double** d, const std::vector<double>& h) -> hipError_t {
-    hipError_t ee = dalloc(d, h.size());
-    if (ee != hipSuccess) return ee;
-    return hipMemcpy(*d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
+  auto up = [&](double* d, const std::vector<double>& h) -> hipError_t {
+    return hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
+                          c.stream);
   };
-  if ((e = up(&S.rh, rh)) != hipSuccess) return e;
-  if ((e = up(&S.wr, wr)) != hipSuccess) return e;
-  if ((e = up(&S.wz, wz)) != hipSuccess) return e;
-  if ((e = up(&S.area, area)) != hipSuccess) return e;
-  if ((e = up(&S.Q, Q)) != hipSuccess) return e;
-  if ((e = up(&S.Qt, Qt)) != hipSuccess) return e;
-  if ((e = up(&S.tri_lo, lo)) != hipSuccess) return e;
-  if ((e = up(&S.tri_inv, inv)) != hipSuccess) return e;
-  if ((e = up(&S.tri_up, To)) != hipSuccess) return e;
-  if ((e = dalloc(&S.work0, (size_t)nr * nz)) != hipSuccess) return e;
-  if ((e = dalloc(&S.work1, (size_t)nr * nz)) != hipSuccess) return e;
-  if ((e = dalloc(&S.partial, kPartLen)) != hipSuccess) return e;
-  return hipSuccess;
+  if ((e = up(S.rh, rh)) != hipSuccess) return e;
+  if ((e = up(S.wr, wr)) != hipSuccess) return e;
+  if ((e = up(S.wz, wz)) != hipSuccess) return e;
+  if ((e = up(S.area, area)) != hipSuccess) return e;
+  if ((e = up(S.Q, Q)) != hipSuccess) return e;
+  if ((e = up(S.Qt, Qt)) != hipSuccess) return e;
+  if ((e = up(S.tri_lo, lo)) != hipSuccess) return e;
+  if ((e = up(S.tri_inv, inv)) != hipSuccess) return e;
+  if ((e = up(S.tri_up, To)) != hipSuccess) return e;
+  // the host vectors die here: wait for the copies
+  return hipStreamSynchronize(c.stream);
 }
 
 hipError_t zero(double* p, int64_t n, hipStream_t s) { return launch_zero(p, n, s); }
@@ -320,7 +401,9 @@ MccDev make_mcc(Ctx& c, int sid, int64_t step, bool to_other = false) {
   d.base_self = s.n;
   if (role == 1 && M.ion_sid >= 0 && M.ion_sid < (int)c.sp.size()) {
     Species& ion = c.sp[M.ion_sid];
-    d.partner = to_other ? other_view(ion) : view(ion);
+    // a committing pass into the other buffers appends ions there too,
+    // unless the ion species is immobile (its buffers never flip)
+    d.partner = (to_other && ion.desc.mobile) ? other_view(ion) : view(ion);
     d.partner.sid = M.ion_sid;
     d.base_partner = ion.n;
     d.sig_ion = std::sqrt(kKB * M.t_gas / ion.desc.m);
@@ -380,6 +463,7 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
     std::memset(&P, 0, sizeof(P));
     P.nsp = (b + 1 < act.size()) ? 2 : 1;
     P.qcap = c.queue_cap;
+    P.queue_waves = c.queue_waves;
     double bytes = 0.0;
     int64_t parts = 0;
     for (int q = 0; q < P.nsp; ++q) {
@@ -403,7 +487,7 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
       }
       P.queue[q] = c.queue + (int64_t)s * c.queue_cap;
       P.qrec[q] = c.qrec + (int64_t)s * 5 * c.queue_cap;
-      P.cqueue[q] = c.queue + (int64_t)(kMaxSpecies + s) * c.queue_cap;
+      P.cqueue[q] = c.queue + (int64_t)(c.queue_species + s) * c.queue_cap;
       P.cqcount[q] = c.qcount + kQCount + s * kSpread * kLineInts;
       P.qcount[q] = c.qcount + s * kSpread * kLineInts;
       P.qseg[q] = queue_segment(c.sp[s].n);
@@ -413,7 +497,9 @@ ecpic_status pass(Ctx& c, int commit, bool with_mcc, int64_t step, bool prezeroe
       parts += c.sp[s].n;
     }
     {
-      const int kind = !commit ? ECPIC_K_PUSH : (to_other ? ECPIC_K_PUSH_COMMIT : ECPIC_K_COMMIT);
+      // a committing Picard iteration deposits; a separate commit does not
+      const int kind = !commit ? ECPIC_K_PUSH
+                               : ((to_other && deposit) ? ECPIC_K_PUSH_COMMIT : ECPIC_K_COMMIT);
       Timed tm(c, kind, bytes, parts);
       HIPCHK(launch_push_fast(P, deposit, c.stream));
     }
@@ -465,6 +551,60 @@ ecpic_status finish_tally(Ctx& c, Tally& t) {
 
 }  // namespace
 
+namespace ecpic {
+
+// Assign every device array (from the bound workspace, or from one block of
+// the library's own), upload the solver tables and clear the state.  Done
+// once, at the first call that needs the device.
+ecpic_status materialise(Ctx& c) {
+  if (c.materialised) return ECPIC_OK;
+  Carver dry;
+  carve_all(c, dry);
+  char* base = nullptr;
+  if (c.ws) {
+    if (c.ws_bytes < dry.off)
+      return fail(c, ECPIC_ENOMEM, "workspace smaller than ecpic_workspace_size reports");
+    base = static_cast<char*>(c.ws);
+  } else {
+    if (hipMalloc(&c.own_block, dry.off) != hipSuccess) {
+      c.own_block = nullptr;
+      return fail(c, ECPIC_ENOMEM, "device allocation failed");
+    }
+    base = static_cast<char*>(c.own_block);
+  }
+  Carver k{base};
+  carve_all(c, k);
+  c.wall_top = c.wall_bot + (c.g.nr + 1);
+  c.wall_side = c.wall_top + (c.g.nr + 1);
+  HIPCHK(setup_solver(c));
+  const int64_t nur = n_edges_r(c), nuz = n_edges_z(c), nh = n_cells(c);
+  double* zs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.ur_it, c.uz_it, c.h_it,
+                  c.ur_half, c.uz_half, c.Ir, c.Iz, c.ur_half2, c.uz_half2, c.h_prev,
+                  c.Ir_alt, c.Iz_alt};
+  int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz, nh, nur, nuz};
+  for (int q = 0; q < 17; ++q) HIPCHK(launch_zero(zs[q], zn[q], c.stream));
+  HIPCHK(launch_zero_i(c.stop, 2, c.stream));
+  HIPCHK(launch_zero_i(c.qcount, 2 * kQCount, c.stream));
+  HIPCHK(launch_zero(c.wall_bot, wall_len(c), c.stream));
+  HIPCHK(launch_zero(c.wall_scr, 2 * wall_len(c), c.stream));
+  HIPCHK(launch_zero_tally(c, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  c.materialised = true;
+  return ECPIC_OK;
+}
+
+}  // namespace ecpic
+
+namespace {
+
+#define ENSURE_DEVICE(c)                          \
+  do {                                            \
+    const ecpic_status r_ = materialise(c);       \
+    if (r_ != ECPIC_OK) return r_;                \
+  } while (0)
+
+}  // namespace
+
 extern "C" {
 
 const char* ecpic_status_string(ecpic_status s) {
@@ -512,38 +652,13 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   c.m.inv_dz = 1.0 / c.m.dz;
   c.m.dt = g->dt;
   c.m.i_lin = (int)std::ceil(g->xi_axis);
-  const int64_t nur = n_edges_r(c), nuz = n_edges_z(c), nh = n_cells(c);
+  // host memory the device writes or the host reads back (pinned); device
+  // memory waits for the first use or a bound workspace
   bool ok = true;
-  auto A = [&](double** p, int64_t n) { ok = ok && dalloc(p, (size_t)n) == hipSuccess; };
-  A(&c.ur, nur); A(&c.uz, nuz); A(&c.h, nh); A(&c.ur_prev, nur); A(&c.uz_prev, nuz);
-  A(&c.h_prev, nh);
-  A(&c.ur_it, nur); A(&c.uz_it, nuz); A(&c.h_it, nh);
-  A(&c.ur_nx, nur); A(&c.uz_nx, nuz); A(&c.h_nx, nh);
-  A(&c.ur_half, nur); A(&c.uz_half, nuz); A(&c.Ir, nur); A(&c.Iz, nuz);
-  A(&c.Ir_alt, nur); A(&c.Iz_alt, nuz);
-  A(&c.ur_half2, nur); A(&c.uz_half2, nuz);
-  // wall charge: bottom, top and side in one array (the layout of the
-  // committing iterations' scratch, which is added into it)
-  A(&c.wall_bot, wall_len(c));
-  c.wall_top = c.wall_bot ? c.wall_bot + (g->nr + 1) : nullptr;
-  c.wall_side = c.wall_top ? c.wall_top + (g->nr + 1) : nullptr;
-  A(&c.wall_scr, 2 * wall_len(c));
-  c.ur_half_f = c.uz_half_f = c.ur_half_f2 = c.uz_half_f2 = nullptr;
-  if (prec == ECPIC_MIXED) {
-    ok = ok && dalloc(&c.ur_half_f, (size_t)nur) == hipSuccess;
-    ok = ok && dalloc(&c.uz_half_f, (size_t)nuz) == hipSuccess;
-    ok = ok && dalloc(&c.ur_half_f2, (size_t)nur) == hipSuccess;
-    ok = ok && dalloc(&c.uz_half_f2, (size_t)nuz) == hipSuccess;
-  }
-  ok = ok && dalloc(&c.hist, (size_t)nh + 1) == hipSuccess;
-  ok = ok && dalloc(&c.offs, (size_t)nh + 1) == hipSuccess;
-  ok = ok && dalloc(&c.scan_part, (size_t)(nh + 1023) / 1024 + 2) == hipSuccess;
-  ok = ok && dalloc(&c.tally, 2 * kSpread) == hipSuccess;
-  ok = ok && dalloc(&c.qcount, 2 * kQCount) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.tally_host, kSpread * sizeof(Tally)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.red_host, 64 * sizeof(double)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.part_host, kPartLen * sizeof(double)) == hipSuccess;
-  ok = ok && dalloc(&c.stop, 2) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c.cons_host, 4 * sizeof(unsigned long long)) == hipSuccess;
   // written by kernels with system-scope stores and polled by the host
   ok = ok && hipHostMalloc((void**)&c.res_host, kMaxIter * sizeof(double),
                            hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
@@ -558,22 +673,6 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   }
   std::memset((void*)c.fin_host, 0, sizeof(StepFinal));
   for (int k = 0; k < kMaxIter; ++k) std::memcpy(&c.res_host[k], &kResPending, sizeof(double));
-  if (setup_solver(c) != hipSuccess) {
-    ecpic_destroy(x);
-    return ECPIC_EHIP;
-  }
-  double* zs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.ur_it, c.uz_it, c.h_it,
-                  c.ur_half, c.uz_half, c.Ir, c.Iz, c.ur_half2, c.uz_half2, c.h_prev,
-                  c.Ir_alt, c.Iz_alt};
-  int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz, nh, nur, nuz};
-  for (int k = 0; k < 17; ++k) (void)launch_zero(zs[k], zn[k], c.stream);
-  (void)launch_zero_i(c.stop, 2, c.stream);
-  (void)launch_zero(c.wall_bot, wall_len(c), c.stream);
-  (void)launch_zero(c.wall_scr, 2 * wall_len(c), c.stream);
-  if (hipStreamSynchronize(c.stream) != hipSuccess) {
-    ecpic_destroy(x);
-    return ECPIC_EHIP;
-  }
   *out = x;
   return ECPIC_OK;
 }
@@ -582,32 +681,11 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
   if (!x) return ECPIC_EINVAL;
   Ctx& c = x->c;
   (void)hipStreamSynchronize(c.stream);
-  for (Species& s : c.sp) {
-    free_species_buf(s.d[0]);
-    free_species_buf(s.d[1]);
-  }
-  double* fs[] = {c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.h_prev, c.ur_it, c.uz_it, c.h_it,
-                  c.ur_nx,
-                  c.uz_nx, c.h_nx, c.ur_half, c.uz_half, c.ur_half2, c.uz_half2, c.Ir, c.Iz,
-                  c.Ir_alt, c.Iz_alt,
-                  c.wall_bot, c.wall_scr, c.sol.rh, c.sol.wr, c.sol.wz, c.sol.area, c.sol.Q, c.sol.Qt,
-                  c.sol.tri_lo, c.sol.tri_inv, c.sol.tri_up, c.sol.work0, c.sol.work1,
-                  c.sol.partial};
-  for (double* p : fs) (void)hipFree(p);
-  (void)hipFree(c.ur_half_f);
-  (void)hipFree(c.uz_half_f);
-  (void)hipFree(c.ur_half_f2);
-  (void)hipFree(c.uz_half_f2);
-  (void)hipFree(c.hist);
-  (void)hipFree(c.offs);
-  (void)hipFree(c.scan_part);
-  (void)hipFree(c.tally);
-  (void)hipFree(c.queue);
-  (void)hipFree(c.qrec);
-  (void)hipFree(c.qcount);
-  (void)hipFree(c.nn_w);
-  (void)hipFree(c.nn_ws);
-  (void)hipFree(c.nn_gws);
+  // device arrays live in the bound workspace (the caller's) or in the
+  // library's block, plus the allocations made after the first use
+  if (c.own_block) (void)hipFree(c.own_block);
+  for (void* p : c.owned) (void)hipFree(p);
+  (void)hipFree(c.nn_ws);  // training workspace (grown on demand)
   collect(c);
   for (auto& p : c.pending) {
     (void)hipEventDestroy(p.a);
@@ -618,11 +696,68 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
   if (c.tally_host) (void)hipHostFree(c.tally_host);
   if (c.red_host) (void)hipHostFree(c.red_host);
   if (c.part_host) (void)hipHostFree(c.part_host);
-  (void)hipFree(c.stop);
+  if (c.cons_host) (void)hipHostFree(c.cons_host);
   if (c.res_host) (void)hipHostFree(c.res_host);
   if (c.fin_host) (void)hipHostFree(c.fin_host);
   if (c.sort_total_host) (void)hipHostFree(c.sort_total_host);
   delete x;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_workspace_size(const ecpic_ctx* x, size_t* bytes) {
+  if (!x || !bytes) return ECPIC_EINVAL;
+  Carver dry;
+  carve_all(const_cast<Ctx&>(x->c), dry);
+  *bytes = dry.off;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_bind_workspace(ecpic_ctx* x, void* ws, size_t bytes) {
+  if (!x || !ws) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  if (c.materialised)
+    return fail(c, ECPIC_EINVAL, "device memory is in use: bind the workspace before any call "
+                                 "that touches the device");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(c, ECPIC_EINVAL, "workspace must be 256-byte aligned");
+  c.ws = ws;
+  c.ws_bytes = bytes;
+  const ecpic_status rc = materialise(c);
+  if (rc != ECPIC_OK) {
+    c.ws = nullptr;
+    c.ws_bytes = 0;
+  }
+  return rc;
+}
+
+ecpic_status ecpic_bind_fields(ecpic_ctx* x, const ecpic_field_view* v) {
+  if (!x) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  ENSURE_DEVICE(c);
+  const int64_t nur = n_edges_r(c), nuz = n_edges_z(c), nh = n_cells(c);
+  double** roles[6] = {&c.ur, &c.uz, &c.h, &c.ur_prev, &c.uz_prev, &c.h_prev};
+  const int64_t len[6] = {nur, nuz, nh, nur, nuz, nh};
+  if (v) {
+    double* p[6] = {v->ur, v->uz, v->h, v->ur_prev, v->uz_prev, v->h_prev};
+    for (int q = 0; q < 6; ++q) {
+      if (!p[q]) return fail(c, ECPIC_EINVAL, "null field array");
+      for (int r = 0; r < q; ++r)
+        if (p[r] == p[q]) return fail(c, ECPIC_EINVAL, "field arrays must be distinct");
+    }
+    if (!c.fields_bound)
+      for (int q = 0; q < 6; ++q) c.lib_fields[q] = *roles[q];
+    for (int q = 0; q < 6; ++q) *roles[q] = p[q];
+    c.fields_bound = true;
+  } else if (c.fields_bound) {
+    // the state goes back into the library's own arrays
+    for (int q = 0; q < 6; ++q) {
+      HIPCHK(launch_copy(c.lib_fields[q], *roles[q], len[q], c.stream));
+      *roles[q] = c.lib_fields[q];
+    }
+    c.fields_bound = false;
+    HIPCHK(hipStreamSynchronize(c.stream));
+  }
+  c.cons_valid = false;
   return ECPIC_OK;
 }
 
@@ -634,30 +769,36 @@ ecpic_status ecpic_add_species(ecpic_ctx* x, const ecpic_species_desc* d, int32_
   // 2^29 slots of 8 bytes
   if (d->capacity < 0 || d->capacity > ((int64_t)1 << 29) || !(d->m > 0) || !(d->weight > 0))
     return fail(c, ECPIC_EINVAL, "bad species descriptor");
+  if (c.materialised && c.ws)
+    return fail(c, ECPIC_EINVAL, "add every species before binding the workspace");
   Species s;
+  std::memset(&s.d, 0, sizeof(s.d));
   s.desc = *d;
-  if (alloc_species_buf(c, s.d[0], d->capacity) != hipSuccess ||
-      alloc_species_buf(c, s.d[1], d->capacity) != hipSuccess) {
-    free_species_buf(s.d[0]);
-    free_species_buf(s.d[1]);
-    return fail(c, ECPIC_ENOMEM, "species allocation failed");
-  }
-  const int64_t qlen = kSpread * queue_segment(d->capacity);
-  if (qlen > c.queue_cap) {
-    int32_t* q = nullptr;
-    double* r = nullptr;
-    if (dalloc(&q, (size_t)qlen * kMaxSpecies * 2) != hipSuccess ||
-        dalloc(&r, (size_t)qlen * kMaxSpecies * 5) != hipSuccess) {
-      (void)hipFree(q);
-      free_species_buf(s.d[0]);
-      free_species_buf(s.d[1]);
-      return fail(c, ECPIC_ENOMEM, "queue allocation failed");
+  if (c.materialised) {
+    // library-owned memory: the species' buffers, and larger queues when
+    // they no longer cover it
+    Carver dry;
+    carve_species_buf(c, dry, s.d[0], d->capacity);
+    char* b0 = nullptr;
+    char* b1 = nullptr;
+    if (owned_alloc(c, &b0, dry.off) != hipSuccess || owned_alloc(c, &b1, dry.off) != hipSuccess)
+      return fail(c, ECPIC_ENOMEM, "species allocation failed");
+    Carver k0{b0}, k1{b1};
+    carve_species_buf(c, k0, s.d[0], d->capacity);
+    carve_species_buf(c, k1, s.d[1], d->capacity);
+    const int32_t nsp = (int32_t)c.sp.size() + 1;
+    int64_t max_cap = d->capacity;
+    for (const Species& o : c.sp) max_cap = std::max<int64_t>(max_cap, o.desc.capacity);
+    if (queue_len(max_cap) > c.queue_cap || nsp > c.queue_species ||
+        read_scratch_len(max_cap) > c.rd_scratch_len) {
+      Carver qd;
+      carve_queues(c, qd, max_cap, kMaxSpecies);
+      char* qb = nullptr;
+      if (owned_alloc(c, &qb, qd.off) != hipSuccess)
+        return fail(c, ECPIC_ENOMEM, "queue allocation failed");
+      Carver qk{qb};
+      carve_queues(c, qk, max_cap, kMaxSpecies);
     }
-    (void)hipFree(c.queue);
-    (void)hipFree(c.qrec);
-    c.queue = q;
-    c.qrec = r;
-    c.queue_cap = qlen;
   }
   s.n = 0;
   // both sort buffers carry the species constants, so every kernel that is
@@ -680,6 +821,7 @@ ecpic_status ecpic_load_particles(ecpic_ctx* x, int32_t sid, const double* r, co
                                   const uint64_t* uid, int64_t n) {
   if (!x) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   if (sid < 0 || sid >= (int)c.sp.size()) return fail(c, ECPIC_EINVAL, "bad species id");
   Species& s = c.sp[sid];
   if (n < 0 || n > s.desc.capacity) return fail(c, ECPIC_EINVAL, "n exceeds capacity");
@@ -687,6 +829,7 @@ ecpic_status ecpic_load_particles(ecpic_ctx* x, int32_t sid, const double* r, co
     return fail(c, ECPIC_EINVAL, "null particle array");
   HIPCHK(launch_load(c.m, view(s), r, z, vr, vt, vz, uid, n, c.g.R, c.prec == ECPIC_MIXED,
                      c.stream));
+  c.cons_valid = false;
   s.n = n;
   return ECPIC_OK;
 }
@@ -696,14 +839,16 @@ ecpic_status ecpic_read_particles(ecpic_ctx* x, int32_t sid, double* xi, double*
                                   int64_t* n_out) {
   if (!x || !n_out) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   if (sid < 0 || sid >= (int)c.sp.size()) return fail(c, ECPIC_EINVAL, "bad species id");
   Species& s = c.sp[sid];
   *n_out = 0;
   if (s.n == 0) return ECPIC_OK;
   const int64_t nb = (s.n + kBlock - 1) / kBlock;
-  int32_t *blk = nullptr, *part = nullptr;
-  HIPCHK(hipMalloc((void**)&blk, sizeof(int32_t) * (nb + 1)));
-  HIPCHK(hipMalloc((void**)&part, sizeof(int32_t) * ((nb + 1023) / 1024 + 2)));
+  // block counts and their scan partials in the context's scratch
+  if (read_scratch_len(s.n) > c.rd_scratch_len) return fail(c, ECPIC_EINVAL, "read scratch");
+  int32_t* blk = c.rd_scratch;
+  int32_t* part = c.rd_scratch + nb + 1;
   const int mixed = c.prec == ECPIC_MIXED;
   ecpic_status rc = ECPIC_OK;
   hipError_t e = launch_flag_count(c.m, view(s), s.n, mixed, blk, c.stream);
@@ -720,8 +865,6 @@ ecpic_status ecpic_read_particles(ecpic_ctx* x, int32_t sid, double* xi, double*
       if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
     }
   }
-  (void)hipFree(blk);
-  (void)hipFree(part);
   if (e != hipSuccess) return fail(c, ECPIC_EHIP, hipGetErrorString(e));
   *n_out = total;
   return rc;
@@ -732,6 +875,7 @@ ecpic_status ecpic_set_fields(ecpic_ctx* x, const double* ur, const double* uz, 
                               int64_t step) {
   if (!x || !ur || !uz || !h) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   const int64_t nur = n_edges_r(c), nuz = n_edges_z(c), nh = n_cells(c);
   HIPCHK(launch_copy(c.ur, ur, nur, c.stream));
   HIPCHK(launch_copy(c.uz, uz, nuz, c.stream));
@@ -739,6 +883,7 @@ ecpic_status ecpic_set_fields(ecpic_ctx* x, const double* ur, const double* uz, 
   HIPCHK(launch_copy(c.ur_prev, ur_prev ? ur_prev : ur, nur, c.stream));
   HIPCHK(launch_copy(c.uz_prev, uz_prev ? uz_prev : uz, nuz, c.stream));
   HIPCHK(launch_copy(c.h_prev, h, nh, c.stream));
+  c.cons_valid = false;
   c.t = t;
   c.step = step;
   return ECPIC_OK;
@@ -747,6 +892,7 @@ ecpic_status ecpic_set_fields(ecpic_ctx* x, const double* ur, const double* uz, 
 ecpic_status ecpic_get_fields(ecpic_ctx* x, double* ur, double* uz, double* h) {
   if (!x) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   if (ur) HIPCHK(launch_copy(ur, c.ur, n_edges_r(c), c.stream));
   if (uz) HIPCHK(launch_copy(uz, c.uz, n_edges_z(c), c.stream));
   if (h) HIPCHK(launch_copy(h, c.h, n_cells(c), c.stream));
@@ -756,6 +902,7 @@ ecpic_status ecpic_get_fields(ecpic_ctx* x, double* ur, double* uz, double* h) {
 ecpic_status ecpic_set_half_field(ecpic_ctx* x, const double* urh, const double* uzh) {
   if (!x || !urh || !uzh) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   // half = (u0 + u1)/2 with u0 = u1 = the given field reproduces it exactly
   HIPCHK(launch_half(c, urh, uzh, urh, uzh, c.stream));
   return ECPIC_OK;
@@ -764,8 +911,10 @@ ecpic_status ecpic_set_half_field(ecpic_ctx* x, const double* urh, const double*
 ecpic_status ecpic_push_deposit(ecpic_ctx* x, int32_t commit, double* Ir, double* Iz) {
   if (!x) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   ecpic_status rc = pass(c, commit ? 1 : 0, false, c.step, false);
   if (rc != ECPIC_OK) return rc;
+  if (commit) c.cons_valid = false;
   if (Ir) HIPCHK(launch_copy(Ir, c.Ir, n_edges_r(c), c.stream));
   if (Iz) HIPCHK(launch_copy(Iz, c.Iz, n_edges_z(c), c.stream));
   if (commit) {
@@ -781,6 +930,7 @@ ecpic_status ecpic_field_solve(ecpic_ctx* x, const double* ur0, const double* uz
                                double* uz1, double* h1) {
   if (!x || !ur0 || !uz0 || !h0 || !Ir || !Iz || !ur1 || !uz1 || !h1) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   SolveArgs a;
   std::memset(&a, 0, sizeof(a));
   a.ur0 = ur0;
@@ -916,6 +1066,7 @@ static void swap_half(Ctx& c) {
 ecpic_status ecpic_field_iterate(ecpic_ctx* x, double* rel) {
   if (!x || !rel) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   ecpic_status rc = iterate(c, rel);
   if (rc != ECPIC_OK) return rc;
   swap_half(c);
@@ -944,6 +1095,7 @@ ecpic_status ecpic_set_mcc(ecpic_ctx* x, const ecpic_mcc_desc* m) {
 ecpic_status ecpic_collide(ecpic_ctx* x, const ecpic_mcc_desc* m, int64_t step) {
   if (!x || !m) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   ecpic_mcc_desc saved = c.mcc;
   ecpic_status rc = ecpic_set_mcc(x, m);
   if (rc != ECPIC_OK) return rc;
@@ -957,14 +1109,18 @@ ecpic_status ecpic_collide(ecpic_ctx* x, const ecpic_mcc_desc* m, int64_t step) 
     HIPCHK(launch_collide(c.m, v, d[s], c.tally, c.prec == ECPIC_MIXED, c.stream));
   }
   c.mcc = saved;
+  c.cons_valid = false;
   Tally t;
   rc = finish_tally(c, t);
+  if (rc == ECPIC_OK && t.n_over_range)
+    rc = fail(c, ECPIC_ERANGE, "particles beyond the null-collision bound (collisions applied)");
   return rc;
 }
 
 ecpic_status ecpic_sort(ecpic_ctx* x) {
   if (!x) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   for (Species& s : c.sp) HIPCHK(launch_sort(c, s, c.stream, nullptr));
   return ECPIC_OK;
 }
@@ -972,6 +1128,7 @@ ecpic_status ecpic_sort(ecpic_ctx* x) {
 ecpic_status ecpic_node_charge(ecpic_ctx* x, double* q, double* bot, double* top, double* side) {
   if (!x) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   if (q) HIPCHK(launch_node_charge(c, q, c.stream));
   if (bot) HIPCHK(launch_copy(bot, c.wall_bot, c.g.nr + 1, c.stream));
   if (top) HIPCHK(launch_copy(top, c.wall_top, c.g.nr + 1, c.stream));
@@ -1000,6 +1157,23 @@ static ecpic_status diag_into(Ctx& c, ecpic_step_stats* st) {
   st->t = c.t;
   st->step = c.step;
   return ECPIC_OK;
+}
+
+ecpic_status ecpic_set_option(ecpic_ctx* x, int32_t option, int64_t value) {
+  if (!x) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  switch (option) {
+    case ECPIC_OPT_QUEUE_WAVES:
+      if (value != 0 && value != 2 && value != 3)
+        return fail(c, ECPIC_EINVAL, "queue waves: 0, 2 or 3");
+      c.queue_waves = (int32_t)value;
+      return ECPIC_OK;
+    case ECPIC_OPT_NN_FORCE_FALLBACK:
+      if (value < 0 || value >= kMaxIter) return fail(c, ECPIC_EINVAL, "fallback iteration");
+      c.nn_force_fallback = (int32_t)value;
+      return ECPIC_OK;
+  }
+  return fail(c, ECPIC_EINVAL, "unknown option");
 }
 
 ecpic_status ecpic_set_profiling(ecpic_ctx* x, int32_t kind_mask) {
@@ -1035,6 +1209,7 @@ ecpic_status ecpic_get_profile(ecpic_ctx* x, ecpic_profile* out) {
 
 ecpic_status ecpic_diagnostics(ecpic_ctx* x, ecpic_step_stats* st) {
   if (!x || !st) return ECPIC_EINVAL;
+  ENSURE_DEVICE(x->c);
   std::memset(st, 0, sizeof(*st));
   return diag_into(x->c, st);
 }
@@ -1053,6 +1228,13 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   int kmax = o->fixed_iter > 0 ? o->fixed_iter : o->max_iter;
   if (kmax < 1 || kmax > 64) return fail(c, ECPIC_EINVAL, "iterations must be in 1..64");
   const double vnow = drive(c.g, c.t), vnext = drive(c.g, c.t + c.g.dt);
+  const bool check = o->check_conservation != 0 && st != nullptr;
+  if (check && !c.cons_valid) {
+    // the charge and Gauss residual of t^n, which the commit compares with
+    HIPCHK(launch_node_charge(c, c.q_node, c.stream));
+    HIPCHK(launch_conservation(c, c.ur, c.uz, c.Ir, c.Iz, true, c.stream));
+    c.cons_valid = true;
+  }
   if (!guess_ready) HIPCHK(launch_guess_half(c, vnow, vnext, c.stream));
   if (o->use_nn) {
     bool used = false;
@@ -1094,9 +1276,11 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   // of it is kept.  Expected: in fixed-iteration mode the last iteration; in
   // tolerance mode iteration j >= 2 when r_{j-2} (r_{j-2} / r_{j-3})^2, the
   // residual extrapolated at the observed contraction, is below tol / 10.
-  bool fuse_ok = true;
-  for (const Species& sp : c.sp)
-    if (!sp.desc.mobile) fuse_ok = false;  // an immobile species' buffer would not flip
+  // every commit writes the mobile species' new states into their other
+  // buffers (an immobile species is not written; ions born into it are
+  // appended to its current buffer beyond its count), so any iteration may
+  // commit
+  const bool fuse_ok = true;
   bool committed[kMaxIter] = {};
   auto expect_last = [&](int j) -> bool {
     if (!fuse_ok) return false;
@@ -1176,7 +1360,20 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
       }
       // timings of iterations that are known to be needed
       collect(c);
-      if (tol_mode && nn_active && k >= 1 && !(r < prev_r)) {
+      if (tol_mode && nn_active && k >= 1 && (!(r < prev_r) || k == c.nn_force_fallback)) {
+        if (ahead) {
+          // iteration k+1 is already on the stream and commits (fused)
+          // if it converges: then it is accepted rather than restarted
+          double r1 = 0.0;
+          ecpic_status rc = wait_residual(c, k + 1, &r1);
+          if (rc != ECPIC_OK) return rc;
+          S->residual[k + 1] = r1;
+          if (r1 <= o->tol) {
+            conv = true;
+            k += 2;
+            break;
+          }
+        }
         restart = true;
         break;
       }
@@ -1214,10 +1411,14 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   // alternate pair, so the commit deposits nothing.
   const int ks = k - 1;
   const bool fused = committed[ks];
-  const Tally* tset = tally_set(c, fused ? (ks & 1) : ((ks + 1) & 1));
+  // a separate commit (the prediction missed) also writes into the other
+  // buffers, with its wall charge in the scratch of parity ks + 1, which
+  // the residual kernel of iteration ks cleared
+  const int cset = fused ? (ks & 1) : ((ks + 1) & 1);
+  const Tally* tset = tally_set(c, cset);
   ecpic_status rc = ECPIC_OK;
   if (!fused) {
-    rc = pass(c, 1, c.mcc.enabled != 0, c.step, true, false, false, false, (ks + 1) & 1);
+    rc = pass(c, 1, c.mcc.enabled != 0, c.step, true, false, false, true, cset);
     if (rc != ECPIC_OK) return rc;
   }
   uint64_t seq = fused ? spec_seq[ks] : 0;
@@ -1226,25 +1427,39 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
     HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir_alt, c.Iz_alt, d + kOffEx,
                            c.stream));
     seq = ++c.fin_seq;
-    HIPCHK(launch_finalize(c, tset, d + kOffEx, c.Ir_alt,
-                           fused ? wall_scratch(c, ks & 1) : nullptr, seq, -1, c.stream));
+    HIPCHK(launch_finalize(c, tset, d + kOffEx, c.Ir_alt, wall_scratch(c, cset), seq, -1,
+                           c.stream));
   }
-  // field shift: u^{n-1} <- u^n, u^n <- u^{n+1} (pointer roles only; the
-  // summary kernels above hold the pointers they read)
-  std::swap(c.ur_prev, c.ur);
-  std::swap(c.uz_prev, c.uz);
-  std::swap(c.ur, c.ur_it);
-  std::swap(c.uz, c.uz_it);
-  {
+  // field shift u^{n-1} <- u^n <- u^{n+1}.  Library buffers: by pointer
+  // roles, at once (the summary kernels above hold the pointers they read),
+  // so that the next step's guess can go in before the host reads the
+  // summary; u^{n-1} moves to the spare buffer, which the guess does not
+  // write, so that a step that is not committed can be put back.  Fields
+  // bound by the caller: by copies once the commit is known to stand.
+  struct FieldRoles {
+    double *ur, *uz, *h, *ur_prev, *uz_prev, *h_prev, *ur_it, *uz_it, *h_it, *ur_spare,
+        *uz_spare;
+  };
+  const FieldRoles before{c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.h_prev,
+                          c.ur_it, c.uz_it, c.h_it, c.ur_spare, c.uz_spare};
+  const bool early_shift = !c.fields_bound;
+  if (early_shift) {
+    c.ur_prev = before.ur;
+    c.uz_prev = before.uz;
+    c.ur = before.ur_it;
+    c.uz = before.uz_it;
+    c.ur_it = before.ur_spare;
+    c.uz_it = before.uz_spare;
+    c.ur_spare = before.ur_prev;
+    c.uz_spare = before.uz_prev;
     // h^{n-1} <- h^n, h^n <- h^{n+1}; the old h^{n-1} buffer becomes scratch
-    double* old_prev = c.h_prev;
-    c.h_prev = c.h;
-    c.h = c.h_it;
-    c.h_it = old_prev;
-  }
-  if (prepare_next) {
-    const double t1 = c.t + c.g.dt;
-    HIPCHK(launch_guess_half(c, drive(c.g, t1), drive(c.g, t1 + c.g.dt), c.stream));
+    c.h_prev = before.h;
+    c.h = before.h_it;
+    c.h_it = before.h_prev;
+    if (prepare_next) {
+      const double t1 = c.t + c.g.dt;
+      HIPCHK(launch_guess_half(c, drive(c.g, t1), drive(c.g, t1 + c.g.dt), c.stream));
+    }
   }
   rc = wait_seq(c, reinterpret_cast<volatile uint64_t*>(&c.fin_host->seq), seq);
   if (rc != ECPIC_OK) return rc;
@@ -1252,20 +1467,6 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   std::memcpy(&fin, (const void*)c.fin_host, sizeof(fin));
   collect(c);
   const Tally& t = fin.t;
-  if (fused) {
-    // the new states are in the other buffers
-    for (Species& sp : c.sp) {
-      if (sp.n <= 0 && t.append[&sp - c.sp.data()] == 0) continue;
-      sp.cur = 1 - sp.cur;
-      std::swap(sp.d[0].uid, sp.d[1].uid);  // the uids stay with the state
-    }
-  }
-  for (size_t s = 0; s < c.sp.size(); ++s) {
-    int64_t n = c.sp[s].n + (int64_t)t.append[s];
-    if (n > c.sp[s].desc.capacity) n = c.sp[s].desc.capacity;
-    c.sp[s].n = n;
-  }
-  if (t.n_overflow) rc = fail(c, ECPIC_ECAPACITY, "species capacity exceeded by ionisation");
   const double vh = 0.5 * (vnow + vnext);
   const double rgap = r_of_xi(c.m, c.g.nr - 0.5);
   S->w_field_io = c.g.dt * fin.xs;
@@ -1283,8 +1484,67 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   S->n_crossings = (int64_t)t.n_crossings;
   S->n_errors = (int64_t)t.n_errors;
   S->n_over_range = (int64_t)t.n_over_range;
+  if (t.n_overflow || t.n_over_range) {
+    // not committed: the particle buffers are not flipped (the new states,
+    // and any pair that was appended, stay in the other buffers or beyond
+    // the counts), the counts, clock and fields stay as they were, and the
+    // finalize kernel left the wall charge out
+    if (early_shift) {
+      c.ur = before.ur;
+      c.uz = before.uz;
+      c.h = before.h;
+      c.ur_prev = before.ur_prev;
+      c.uz_prev = before.uz_prev;
+      c.h_prev = before.h_prev;
+      c.ur_it = before.ur_it;
+      c.uz_it = before.uz_it;
+      c.h_it = before.h_it;
+      c.ur_spare = before.ur_spare;
+      c.uz_spare = before.uz_spare;
+    }
+    HIPCHK(hipStreamSynchronize(c.stream));
+    collect(c);
+    S->t = c.t;
+    S->step = c.step;
+    for (size_t s = 0; s < c.sp.size() && s < 4; ++s) S->n_alive[s] = c.sp[s].n;
+    if (t.n_overflow)
+      return fail(c, ECPIC_ECAPACITY,
+                  "species capacity exceeded by ionisation (step not committed)");
+    return fail(c, ECPIC_ERANGE,
+                "a particle exceeded the null-collision bound eps_max (step not committed)");
+  }
+  if (!early_shift) {
+    HIPCHK(launch_shift(c, c.stream));
+    if (prepare_next) {
+      const double t1 = c.t + c.g.dt;
+      HIPCHK(launch_guess_half(c, drive(c.g, t1), drive(c.g, t1 + c.g.dt), c.stream));
+    }
+  }
+  // the new states are in the mobile species' other buffers
+  for (size_t s = 0; s < c.sp.size(); ++s) {
+    Species& sp = c.sp[s];
+    if (!sp.desc.mobile) continue;
+    if (sp.n <= 0 && t.append[s] == 0) continue;
+    sp.cur = 1 - sp.cur;
+    std::swap(sp.d[0].uid, sp.d[1].uid);  // the uids stay with the state
+  }
+  for (size_t s = 0; s < c.sp.size(); ++s) {
+    int64_t n = c.sp[s].n + (int64_t)t.append[s];
+    if (n > c.sp[s].desc.capacity) n = c.sp[s].desc.capacity;
+    c.sp[s].n = n;
+  }
   c.t += c.g.dt;
   c.step += 1;
+  if (check) {
+    // continuity and Gauss against t^n with the accepted currents
+    HIPCHK(launch_zero(reinterpret_cast<double*>(c.cons_dev), 4, c.stream));
+    HIPCHK(launch_node_charge(c, c.q_node, c.stream));
+    HIPCHK(launch_conservation(c, c.ur, c.uz, c.Ir_alt, c.Iz_alt, false, c.stream));
+    HIPCHK(hipMemcpyAsync(c.cons_host, c.cons_dev, 3 * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, c.stream));
+  } else {
+    c.cons_valid = false;
+  }
   if (o->sort_every > 0 && c.step % o->sort_every == 0) {
     for (size_t s = 0; s < c.sp.size(); ++s) {
       const int64_t n0 = c.sp[s].n;
@@ -1298,8 +1558,15 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   if (st) {
     ecpic_status r2 = diag_into(c, S);
     if (r2 != ECPIC_OK) return r2;
+    if (check) {
+      double v[3];
+      std::memcpy(v, c.cons_host, sizeof(v));
+      S->continuity_max = v[0];
+      S->gauss_max = v[1];
+      S->q_max = v[2];
+    }
   }
-  if (rc == ECPIC_OK && t.n_errors) rc = fail(c, ECPIC_EPUSH, "particle push failed");
+  if (t.n_errors) rc = fail(c, ECPIC_EPUSH, "particle push failed");
   return rc;
 }
 
@@ -1307,6 +1574,7 @@ extern "C" {
 
 ecpic_status ecpic_step(ecpic_ctx* x, const ecpic_step_opts* o, ecpic_step_stats* st) {
   if (!x || !o) return ECPIC_EINVAL;
+  ENSURE_DEVICE(x->c);
   return step_impl(x->c, o, st, false, false);
 }
 
@@ -1315,6 +1583,7 @@ ecpic_status ecpic_run(ecpic_ctx* x, const ecpic_step_opts* o, int32_t n_steps, 
   if (done) *done = 0;
   if (!x || !o || n_steps < 0) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  ENSURE_DEVICE(c);
   bool ready = false;
   for (int32_t k = 0; k < n_steps; ++k) {
     const bool more = k + 1 < n_steps;

@@ -591,6 +591,7 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
   // is the one that converged
   if (conv && conv[1] != want_k) return;
   const int l = threadIdx.x;
+  uint64_t iacc = 0;  // this lane's integer tally word
   if (l < kTallyWords) {
     const uint64_t* w = reinterpret_cast<const uint64_t*>(tally) + l;
     uint64_t* dst = reinterpret_cast<uint64_t*>(&out->t) + l;
@@ -599,15 +600,20 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
       for (int c = 0; c < kSpread; ++c) acc += __longlong_as_double((long long)w[c * kTallyWords]);
       *dst = (uint64_t)__double_as_longlong(acc);
     } else {
-      uint64_t acc = 0;
-      for (int c = 0; c < kSpread; ++c) acc += w[c * kTallyWords];
-      *dst = acc;
+      for (int c = 0; c < kSpread; ++c) iacc += w[c * kTallyWords];
+      *dst = iacc;
     }
   }
+  // a commit with an ionisation that did not fit, or a particle beyond the
+  // null-collision bound, is not accepted: its wall charge stays out of the
+  // totals
+  constexpr int kOvf = (int)(offsetof(Tally, n_overflow) / sizeof(uint64_t));
+  constexpr int kOver = (int)(offsetof(Tally, n_over_range) / sizeof(uint64_t));
+  const uint64_t rejected = __shfl(iacc, kOvf, 64) | __shfl(iacc, kOver, 64);
   double xs = 0.0;
   for (int b = l; b < kRedBlocks; b += 64) xs += xpart[b];
   xs = wsum_d(xs);
-  if (wall_add) {
+  if (wall_add && !rejected) {
     // the wall charge of a committing iteration joins the totals (the three
     // wall arrays are contiguous in both)
     const int64_t wlen = 2 * (int64_t)(nr + 1) + nz + 1;
@@ -623,6 +629,26 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
   __threadfence_system();
   __syncthreads();
   if (l == 0) store_sys(&out->seq, seq);
+}
+
+// field shift of a committed step done by copies: prev <- cur <- next
+__global__ void k_shift(int64_t nur, int64_t nuz, int64_t nh, double* ur, double* uz, double* h,
+                        double* ur_prev, double* uz_prev, double* h_prev,
+                        const double* __restrict__ ur_next, const double* __restrict__ uz_next,
+                        const double* __restrict__ h_next) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < nur) {
+    ur_prev[t] = ur[t];
+    ur[t] = ur_next[t];
+  }
+  if (t < nuz) {
+    uz_prev[t] = uz[t];
+    uz[t] = uz_next[t];
+  }
+  if (t < nh) {
+    h_prev[t] = h[t];
+    h[t] = h_next[t];
+  }
 }
 
 __global__ void k_zero_tally(Tally* tally) {
@@ -650,6 +676,14 @@ hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, tally, xpart, c.h, c.h_it, Ir,
                      c.g.nr, c.g.nz, wall_add, c.wall_bot, seq, c.fin_dev,
                      guard_k >= 0 ? (const int32_t*)c.stop : nullptr, guard_k);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(const Ctx& c, hipStream_t s) {
+  const int64_t nur = (int64_t)c.g.nr * (c.g.nz + 1), nuz = (int64_t)(c.g.nr + 1) * c.g.nz;
+  const int64_t nh = (int64_t)c.g.nr * c.g.nz;
+  hipLaunchKernelGGL(k_shift, dim3(nblk(nuz > nur ? nuz : nur)), dim3(kBlock), 0, s, nur, nuz, nh,
+                     c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.h_prev, c.ur_it, c.uz_it, c.h_it);
   return hipGetLastError();
 }
 

@@ -129,6 +129,7 @@ struct PassArgs {
   double* qrec[2];
   int64_t qcap;
   int32_t nsp;         // slots in use (1 or 2)
+  int32_t queue_waves; // build of the plain slow pass: 0 by size, else 2 or 3
 };
 
 // One Crank-Nicolson field solve.  Optional outputs (null = skipped): the
@@ -234,6 +235,36 @@ struct Ctx {
   size_t nn_ws_bytes = 0;
   void* nn_gws = nullptr;          // workspace of the in-step guess (one image)
   size_t nn_gws_bytes = 0;
+  // Device memory.  Nothing is allocated at create: at first use (or when
+  // the caller binds a workspace) every device array of the context and of
+  // the species added so far is carved from one region, the caller's bound
+  // workspace or one block the library allocates.  Species added after that
+  // (library-owned memory only) get allocations of their own.
+  bool materialised = false;
+  void* ws = nullptr;              // the caller's workspace, or null
+  size_t ws_bytes = 0;
+  void* own_block = nullptr;       // the library's block when none is bound
+  std::vector<void*> owned;        // allocations made after the first use
+  int32_t queue_species = 0;       // species slots the queues are sized for
+  int32_t queue_waves = 0;         // ECPIC_OPT_QUEUE_WAVES
+  int32_t nn_force_fallback = 0;   // ECPIC_OPT_NN_FORCE_FALLBACK
+  // the rotation of u^{n-1}, u^n, u^{n+1} takes a fourth buffer, so that a
+  // step that is not committed still has u^{n-1} after the next step's guess
+  // has been enqueued
+  double *ur_spare = nullptr, *uz_spare = nullptr;
+  // fields bound by the caller (ecpic_bind_fields): u^n and u^{n-1} live in
+  // the caller's arrays, shifted by copies at each commit
+  bool fields_bound = false;
+  double* lib_fields[6] = {};      // the library's own ur, uz, h, ur_prev, uz_prev, h_prev
+  // charge-conservation diagnostics of a committed step
+  double* q_node = nullptr;        // particle node charge [nr+1][nz+1]
+  double* q0 = nullptr;            // total node charge (with walls) at t^n
+  double* gq0 = nullptr;           // Gauss residual G - Q at t^n
+  unsigned long long* cons_dev = nullptr;   // maxima as double bit patterns
+  unsigned long long* cons_host = nullptr;  // pinned copy
+  bool cons_valid = false;         // q0, gq0 describe the current state
+  int32_t* rd_scratch = nullptr;   // block counts of ecpic_read_particles
+  int64_t rd_scratch_len = 0;
   // event timing of the hot kernels
   uint32_t prof_mask = 0;          // bit k: time launches of kind k
   int32_t prof_every = 1;          // time every prof_every-th launch of a kind
@@ -339,6 +370,17 @@ hipError_t launch_sort_async(Ctx& c, Species& sp, int32_t* total_pinned, hipStre
 void finish_sort(Species& sp, int32_t total);
 hipError_t launch_kinetic(const Species& sp, int mixed, double* out, hipStream_t s);
 hipError_t launch_node_charge(const Ctx& c, double* q, hipStream_t s);
+// charge-conservation maxima of a committed step (first: only record the
+// state at t^n); needs the particle node charge in c.q_node
+hipError_t launch_conservation(const Ctx& c, const double* ur, const double* uz, const double* Ir,
+                               const double* Iz, bool first, hipStream_t s);
+// bytes of the learned guess's one-image workspace (weights prepared in it)
+size_t nn_guess_ws_bytes(const Ctx& c);
+// assign the context's device arrays at first use (from the bound workspace
+// or one block of the library's own); ECPIC_OK when already done
+ecpic_status materialise(Ctx& c);
+// u^{n-1} <- u^n, u^n <- u^{n+1} by copies (fields bound by the caller)
+hipError_t launch_shift(const Ctx& c, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_i(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);

@@ -369,8 +369,11 @@ struct Ws {
 };
 
 // carve a workspace for nimg images out of the buffer (buf, bytes), growing
-// the allocation when needed
-ecpic_status workspace(Ctx& c, int nimg, Ws& w, void*& buf, size_t& bytes) {
+// the allocation when needed (grow = false: a buffer carved from the
+// context's device region, which must already be large enough); with
+// need_only, only the size is computed (into *need_only)
+ecpic_status workspace(const Ctx& c, int nimg, Ws& w, void*& buf, size_t& bytes,
+                       bool grow = true, size_t* need_only = nullptr) {
   const int64_t P = (int64_t)nimg * (c.g.nr + 1) * (c.g.nz + 1);
   size_t need = 0;
   auto take = [&](size_t bytes) {
@@ -391,7 +394,12 @@ ecpic_status workspace(Ctx& c, int nimg, Ws& w, void*& buf, size_t& bytes) {
   const size_t o_part = take(sizeof(float) * (size_t)kGradWaves * 9 * kCH * kCH);
   const size_t o_pdb = take(sizeof(float) * (size_t)kGradWaves * kCH);
   const size_t o_loss = take(sizeof(double) * (size_t)nblk256(P));
+  if (need_only) {
+    *need_only = need;
+    return ECPIC_OK;
+  }
   if (need > bytes) {
+    if (!grow) return ECPIC_ENOMEM;
     if (buf) {
       if (hipStreamSynchronize(c.stream) != hipSuccess) return ECPIC_EHIP;
       (void)hipFree(buf);
@@ -446,13 +454,21 @@ ecpic_status check_ctx(ecpic_ctx* x) { return x ? ECPIC_OK : ECPIC_EINVAL; }
 
 }  // namespace
 
+size_t nn_guess_ws_bytes(const Ctx& c) {
+  Ws w;
+  void* buf = nullptr;
+  size_t bytes = 0, need = 0;
+  (void)workspace(c, 1, w, buf, bytes, false, &need);
+  return need;
+}
+
 // Learned guess inside ecpic_step: called after the extrapolated guess.
 ecpic_status nn_guess(Ctx& c, bool* used) {
   *used = false;
   if (!c.nn_ready) return ECPIC_OK;
   // the guess buffer: its BF16 weights were prepared by ecpic_nn_set_weights
   Ws w;
-  ecpic_status rc = workspace(c, 1, w, c.nn_gws, c.nn_gws_bytes);
+  ecpic_status rc = workspace(c, 1, w, c.nn_gws, c.nn_gws_bytes, false);
   if (rc != ECPIC_OK) return rc;
   const int H = c.g.nr + 1, W = c.g.nz + 1;
   const int64_t hw = (int64_t)H * W;
@@ -488,11 +504,14 @@ ecpic_status ecpic_nn_set_weights(ecpic_ctx* x, const float* w, const float* nor
   if (!norm) return ECPIC_EINVAL;
   for (int k = 0; k < 8; ++k)
     if (!(norm[k] > 0.f) || !std::isfinite(norm[k])) return ECPIC_EINVAL;
+  {
+    const ecpic_status r0 = materialise(c);
+    if (r0 != ECPIC_OK) return r0;
+  }
   const int64_t n = layer_w_off(kNL);
-  if (!c.nn_w && hipMalloc(&c.nn_w, sizeof(float) * n) != hipSuccess) return ECPIC_ENOMEM;
   HIPCHK(hipMemcpyAsync(c.nn_w, w, sizeof(float) * n, hipMemcpyDeviceToDevice, c.stream));
   Ws g;
-  ecpic_status rc = workspace(c, 1, g, c.nn_gws, c.nn_gws_bytes);
+  ecpic_status rc = workspace(c, 1, g, c.nn_gws, c.nn_gws_bytes, false);
   if (rc != ECPIC_OK) return rc;
   HIPCHK(prep_weights(c.nn_w, g, c.stream));
   std::memcpy(c.nn_norm, norm, 8 * sizeof(float));
@@ -504,6 +523,10 @@ ecpic_status ecpic_nn_forward(ecpic_ctx* x, const float* wts, const uint16_t* in
                               int32_t batch) {
   if (check_ctx(x) != ECPIC_OK || !wts || !in || !y || batch < 1) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  {
+    const ecpic_status r0 = materialise(c);
+    if (r0 != ECPIC_OK) return r0;
+  }
   Ws w;
   ecpic_status rc = workspace(c, batch, w, c.nn_ws, c.nn_ws_bytes);
   if (rc != ECPIC_OK) return rc;
@@ -521,6 +544,10 @@ ecpic_status ecpic_nn_grad(ecpic_ctx* x, const float* wts, const uint16_t* in, c
                            int32_t batch, float* dw, float* loss) {
   if (check_ctx(x) != ECPIC_OK || !wts || !in || !t || !dw || batch < 1) return ECPIC_EINVAL;
   Ctx& c = x->c;
+  {
+    const ecpic_status r0 = materialise(c);
+    if (r0 != ECPIC_OK) return r0;
+  }
   Ws w;
   ecpic_status rc = workspace(c, batch, w, c.nn_ws, c.nn_ws_bytes);
   if (rc != ECPIC_OK) return rc;

@@ -745,6 +745,17 @@ __device__ __forceinline__ void store_slot<float>(const SpecDev& s, const MapP& 
   s.uid[k] = uid;
 }
 
+template <typename T>
+__device__ __forceinline__ void kill_slot(const SpecDev& s, int64_t k);
+template <>
+__device__ __forceinline__ void kill_slot<double>(const SpecDev& s, int64_t k) {
+  s.xi[k] = -1.0;
+}
+template <>
+__device__ __forceinline__ void kill_slot<float>(const SpecDev& s, int64_t k) {
+  s.cell[k] = -1;
+}
+
 struct CollOut {
   double dke;    // kinetic energy lost (J)
   int coll;      // 1 if a real collision happened
@@ -808,15 +819,20 @@ __device__ CollOut collide_one(const MccDev& c, const SpecDev& s, const MapP& m,
       const double ivt = sg * ra * sin(2.0 * M_PI * w2[0]);
       const double ivz = sg * rb * cos(2.0 * M_PI * w2[2]);
       const uint64_t nu = child_uid(uid, c.step);
-      vr = v1 * d[0];
-      vt = v1 * d[1];
-      vz = v1 * d[2];
       const unsigned long long ke = atomicAdd(&tally->append[sid], 1ull);
       const unsigned long long ki = atomicAdd(&tally->append[c.partner.sid], 1ull);
       const int64_t se = c.base_self + (int64_t)ke, si = c.base_partner + (int64_t)ki;
       if (se >= s.cap || si >= c.partner.cap) {
+        // the pair does not fit: no ionisation at all (the primary keeps
+        // its velocity), and a slot reserved within capacity is marked dead
+        // so that no unwritten slot becomes a live particle
         o.overflow = 1;
+        if (se < s.cap) kill_slot<T>(s, se);
+        if (si < c.partner.cap) kill_slot<T>(c.partner, si);
       } else {
+        vr = v1 * d[0];
+        vt = v1 * d[1];
+        vz = v1 * d[2];
         store_slot<T>(s, m, se, i, j, a, b, v2n * d2[0], v2n * d2[1], v2n * d2[2], nu);
         store_slot<T>(c.partner, m, si, i, j, a, b, ivr, ivt, ivz, nu);
         o.ionized = 1;
@@ -1086,17 +1102,6 @@ __device__ __forceinline__ bool same_buffer(const SpecDev& a, const SpecDev& b) 
 }
 
 template <typename T>
-__device__ __forceinline__ void kill_particle(const SpecDev& s, int64_t k);
-template <>
-__device__ __forceinline__ void kill_particle<double>(const SpecDev& s, int64_t k) {
-  s.xi[k] = -1.0;
-}
-template <>
-__device__ __forceinline__ void kill_particle<float>(const SpecDev& s, int64_t k) {
-  s.cell[k] = -1;
-}
-
-template <typename T>
 struct FieldPtr;
 template <>
 struct FieldPtr<double> {
@@ -1177,7 +1182,7 @@ __device__ void commit_one(const PushArgs& A, int64_t k, uint64_t uid, PState<T>
   const double qw = s.q * s.w;
   if (status == kError) t.err += 1;
   if (status == kAbsorbed) {
-    kill_particle<T>(s, k);
+    kill_slot<T>(s, k);
     t.absorbed += 1;
     t.dke_abs += 0.5 * s.m * s.w * (double(p.vr) * p.vr + double(p.vt) * p.vt + double(p.vz) * p.vz);
     if (wall == 1 || wall == 2) {
@@ -1448,7 +1453,7 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
       bool coll = false;
       if (alive && !slow) coll = commit_store<T>(A, k, p);
       // into the other buffer: dead slots stay dead there
-      if (k < s.n && !alive && !same_buffer(A.out, A.s)) kill_particle<T>(A.out, k);
+      if (k < s.n && !alive && !same_buffer(A.out, A.s)) kill_slot<T>(A.out, k);
       const uint64_t cm = __ballot(coll);
       if (coll) coll_list[wv * kPerWave + wn_coll + lanes_below(cm)] = (int32_t)k;
       wn_coll = __builtin_amdgcn_readfirstlane(wn_coll + (int)__popcll(cm));
@@ -1957,7 +1962,7 @@ constexpr int64_t kWideQueue = (int64_t)16 << 20;
 template <int MODE>
 void launch_queue(const PassArgs& P, int64_t nmax, hipStream_t st) {
   if constexpr (MODE == kQSlow) {
-    if (nmax * P.nsp >= kWideQueue) {
+    if (P.queue_waves == 3 || (P.queue_waves == 0 && nmax * P.nsp >= kWideQueue)) {
       launch_queue_w<MODE, 3>(P, nmax, st);
       return;
     }

@@ -283,6 +283,100 @@ hipError_t launch_node_charge(const Ctx& c, double* q, hipStream_t st) {
   return hipGetLastError();
 }
 
+namespace {
+
+// Charge-conservation check of a committed step (Sec. 2.1: the deposit is
+// charge-conserving, so continuity holds at every node and Gauss's law,
+// once it holds, keeps holding).  Per node (i, j) of [nr+1][nz+1]:
+//   Q   = particle charge (bilinear weights) + wall charge on wall nodes
+//   div = net flux out of the node's dual cell of a face quantity on the
+//         r-edges (f_r) and z-edges (f_z):
+//         f_r[i][j] - f_r[i-1][j] + f_z[i][j] - f_z[i][j-1] (missing terms 0)
+//   continuity  = Q^{n+1} - Q^n + dt div(I)
+//   Gauss       = div(D) - Q_particles with D the displacement flux
+//                 eps A*/l u (halved dual faces of r-edges on the z walls),
+//                 compared with its value at t^n on the nodes off the
+//                 conducting walls (0 <= i < nr, 0 < j < nz)
+// The state of t^{n+1} replaces that of t^n in q0 / gq0.  Maxima of
+// |continuity|, |Gauss change| and |Q| go to out[0..2] as the bit patterns of
+// non-negative doubles, whose integer order is their numeric order.
+__global__ void __launch_bounds__(kBlock)
+    k_conservation(MapP m, const double* __restrict__ wr, const double* __restrict__ wz,
+                   const double* __restrict__ ur, const double* __restrict__ uz,
+                   const double* __restrict__ Ir, const double* __restrict__ Iz,
+                   const double* __restrict__ qp, const double* __restrict__ wbot,
+                   const double* __restrict__ wtop, const double* __restrict__ wside,
+                   double* __restrict__ q0, double* __restrict__ gq0, int first, double dt,
+                   unsigned long long* out) {
+  const int nr = m.nr, nz = m.nz;
+  const int64_t nn = (int64_t)(nr + 1) * (nz + 1);
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double c_cont = 0.0, c_gauss = 0.0, c_q = 0.0;
+  if (t < nn) {
+    const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
+    double q = qp[t];
+    const double qpart = q;
+    if (j == 0) q += wbot[i];
+    if (j == nz) q += wtop[i];
+    if (i == nr) q += wside[j];
+    // r-edges (i, j) and (i-1, j); z-edges (i, j) and (i, j-1)
+    const int64_t er = (int64_t)i * (nz + 1) + j, erm = er - (nz + 1);
+    const int64_t ez = (int64_t)i * nz + j, ezm = ez - 1;
+    double dI = 0.0, dD = 0.0;
+    const double half = (j == 0 || j == nz) ? 0.5 : 1.0;
+    if (i < nr) {
+      dI += Ir[er];
+      dD += half * wr[i] * ur[er];
+    }
+    if (i > 0) {
+      dI -= Ir[erm];
+      dD -= half * wr[i - 1] * ur[erm];
+    }
+    if (j < nz) {
+      dI += Iz[ez];
+      if (i < nr) dD += wz[i] * uz[ez];
+    }
+    if (j > 0) {
+      dI -= Iz[ezm];
+      if (i < nr) dD -= wz[i] * uz[ezm];
+    }
+    const double gq = dD - qpart;
+    if (!first) {
+      c_cont = fabs(q - q0[t] + dt * dI);
+      if (i < nr && j > 0 && j < nz) c_gauss = fabs(gq - gq0[t]);
+    }
+    c_q = fabs(qpart);
+    q0[t] = q;
+    gq0[t] = gq;
+  }
+  double v[3] = {c_cont, c_gauss, c_q};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = fmax(v[k], __shfl_xor(v[k], off, 64));
+  __shared__ double red[kBlock / 64][3];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 3; ++k) red[w][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double x = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) x = fmax(x, red[q][threadIdx.x]);
+    if (x > 0.0) atomicMax(out + threadIdx.x, (unsigned long long)__double_as_longlong(x));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_conservation(const Ctx& c, const double* ur, const double* uz, const double* Ir,
+                               const double* Iz, bool first, hipStream_t st) {
+  const int64_t nn = (int64_t)(c.g.nr + 1) * (c.g.nz + 1);
+  hipLaunchKernelGGL(k_conservation, dim3(nblk(nn)), dim3(kBlock), 0, st, c.m, c.sol.wr,
+                     c.sol.wz, ur, uz, Ir, Iz, c.q_node, c.wall_bot, c.wall_top, c.wall_side,
+                     c.q0, c.gq0, first ? 1 : 0, c.g.dt, c.cons_dev);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero, dim3(nblk(n)), dim3(kBlock), 0, st, p, n);

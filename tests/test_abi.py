@@ -11,7 +11,8 @@ import paper_2212_08836_amd as P
 def test_header_declares_the_boundary_calls():
     names = P.header_symbols()
     for must in ("ecpic_create", "ecpic_add_species", "ecpic_push_deposit", "ecpic_field_iterate",
-                 "ecpic_collide", "ecpic_step", "ecpic_destroy", "ecpic_sort"):
+                 "ecpic_collide", "ecpic_step", "ecpic_destroy", "ecpic_sort", "ecpic_workspace_size",
+                 "ecpic_bind_workspace", "ecpic_bind_fields", "ecpic_set_option"):
         assert must in names
 
 

@@ -186,3 +186,47 @@ def test_mixed_deposit_conserves_charge(og, torch_cuda):
     # each node sees at most ~4 ppc particles per species, each off by at
     # most 2^-25 of a cell in either offset
     assert worst < 8 * 2.0 ** -25
+
+
+def _mixed_vs_oracle(og, P, w, warm_steps, mcc):
+    """From a common state (the FP64 GPU path after warm_steps), one step of
+    the mixed path and one of the CPU oracle; returns the worst field error."""
+    parts0 = E.make_particles(w)
+    qmw = [(d["q"], d["m"], d["w"]) for d in parts0]
+    caps = [int(len(d["r"]) * 1.3) + 256 for d in parts0]
+    run = P.context_from_workload(w)
+    P.load_workload_species(run, parts0, extra_cap=0.3)
+    if mcc:
+        run.set_mcc(mcc)
+    for k in range(warm_steps):
+        run.step(tol=w.tol, sort_every=4, stats=False)
+    st = run.diagnostics()
+    parts, fields = _state_of(run, w)
+    run.close()
+    mix = _fresh(P, w, "mixed", parts, fields, caps, qmw, st["t"], st["step"], mcc)
+    g = og.grid_from_workload(w)
+    sp = [g.species(dict(parts[k], q=qmw[k][0], m=qmw[k][1], w=qmw[k][2]), cap=caps[k],
+                    role=k + 1) for k in range(2)]
+    ost = og.State(g)
+    ost.ur, ost.uz, ost.h = (f.copy() for f in fields)
+    ost.ur_prev, ost.uz_prev = ost.ur.copy(), ost.uz.copy()
+    ost.t, ost.step = st["t"], st["step"]
+    d_o = g.step(ost, sp, mcc=mcc, tol=w.tol)
+    d_m = mix.step(tol=w.tol)
+    assert d_o["rc"] == 0 and d_m["converged"] == 1
+    assert d_m["residual"][d_m["iters"] - 1] <= w.tol
+    errs = [_rel(a, b) for a, b in zip(mix.get_fields(), (ost.ur, ost.uz, ost.h))]
+    _flush(f"  {w.name}: mixed vs oracle after {warm_steps} steps: field rel err "
+           f"{errs[0]:.2e} {errs[1]:.2e} {errs[2]:.2e}; iters oracle {d_o['iters']} "
+           f"mixed {d_m['iters']}")
+    mix.close()
+    return max(errs)
+
+
+def test_mixed_one_step_against_the_oracle(og, torch_cuda):
+    # the 1e-5 bar against the CPU oracle itself (not only the FP64 GPU path)
+    import paper_2212_08836_amd as P
+    _flush("mixed vs oracle, c1 and a reduced c2")
+    assert _mixed_vs_oracle(og, P, E.workload("c1"), 6, None) <= FIELD_TOL
+    w = E.workload("c2", ppc=8)
+    assert _mixed_vs_oracle(og, P, w, 10, w.mcc_params()) <= FIELD_TOL

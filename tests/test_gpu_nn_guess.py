@@ -161,3 +161,79 @@ def test_learned_guess_on_the_512x256_grid(torch_cuda):
     ctx.close()
     assert nn[:, 1].mean() < plain[:, 1].mean()
     assert nn[:, 0].mean() <= plain[:, 0].mean() + 0.05
+
+
+def test_learned_guess_far_off_still_converges_to_the_answer(trained):
+    # weights flipped in sign and scaled by 1e3: the guess is far off (first
+    # residual ~1e7); Picard still contracts (no fallback needed) and ends at
+    # the same converged answer, with the charge conserved
+    import paper_2212_08836_amd as P
+    a, b, w = _twin_states(P, trained)
+    torch = pytest.importorskip("torch")
+    _, _, wts, norm = trained
+    b.nn_set_weights(torch.as_tensor(wts).clone() * -1e3, norm)
+    da = a.step(tol=w.tol)
+    db = b.step(tol=w.tol, use_nn=True, conservation=True)
+    _flush(f"  corrupted network: fallback {db['nn_fallback']}, iterations {db['iters']} vs "
+           f"{da['iters']}, residuals {['%.1e' % r for r in db['residual']]}")
+    assert db["used_nn"] == 1 and db["converged"] == 1 and db["residual"][0] > 1e3
+    _same_answer(a, b)
+    assert db["continuity_max"] <= 1e-12 * db["q_max"]
+
+
+@pytest.mark.parametrize("at", [1, 2, 3])
+def test_learned_guess_fallback_restarts_cleanly(trained, at):
+    # the fallback path, forced from the host at iteration `at`: the step
+    # restarts from the extrapolated guess (or accepts an iteration already
+    # enqueued ahead that converged), ends at the same answer, and no
+    # speculative commit of the abandoned attempt leaves wall charge behind
+    import paper_2212_08836_amd as P
+    a, b, w = _twin_states(P, trained)
+    _, _, wts, norm = trained
+    b.nn_set_weights(wts, norm)
+    b.set_option(P.ECPIC_OPT_NN_FORCE_FALLBACK, at)
+    da = a.step(tol=w.tol)
+    db = b.step(tol=w.tol, use_nn=True, conservation=True)
+    _flush(f"  fallback forced at {at}: taken {db['nn_fallback']}, iterations {db['iters']} vs "
+           f"{da['iters']}")
+    assert db["used_nn"] == 1 and db["converged"] == 1
+    # at k <= iters - 3 the restart is taken; at iters - 2 the iteration
+    # enqueued ahead may already have converged (then it is accepted); at
+    # iters - 1 the step converges before the check
+    if at <= da["iters"] - 3:
+        assert db["nn_fallback"] == 1
+    if at == da["iters"] - 1:
+        assert db["nn_fallback"] == 0
+    _same_answer(a, b)
+    assert db["continuity_max"] <= 1e-12 * db["q_max"]
+    # two more steps: wall charge and fields stay with the plain context's
+    for n in range(2):
+        a.step(tol=w.tol)
+        b.step(tol=w.tol, use_nn=True)
+    _same_answer(a, b)
+
+
+def _twin_states(P, trained):
+    """Two FP64 contexts holding the trained context's current state."""
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    import test_gpu_mixed as T
+    w, ctx, wts, norm = trained
+    st = ctx.diagnostics()
+    parts, fields = T._state_of(ctx, w)
+    ref = E.make_particles(w)
+    qmw = [(ref[k]["q"], ref[k]["m"], ref[k]["w"]) for k in range(2)]
+    del ref
+    caps = [int(len(p["r"]) * 1.2) + 256 for p in parts]
+    a = T._fresh(P, w, "fp64", parts, fields, caps, qmw, st["t"], st["step"], w.mcc_params())
+    b = T._fresh(P, w, "fp64", parts, fields, caps, qmw, st["t"], st["step"], w.mcc_params())
+    return a, b, w
+
+
+def _same_answer(a, b):
+    fa, fb = a.get_fields(), b.get_fields()
+    errs = [np.abs(x - y).max() / np.abs(y).max() for x, y in zip(fb, fa)]
+    assert max(errs) < 1e-8, errs
+    # wall charge totals (bottom, top, side)
+    qa, qb = a.node_charge(), b.node_charge()
+    for x, y in zip(qa[1:], qb[1:]):
+        assert np.abs(x - y).max() <= 1e-6 * max(np.abs(y).max(), 1e-300)

@@ -1,7 +1,8 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
 Bar: 1e-12 relative, norm-wise per array (max |a-b| / max |b|), with
-positions in cell units and velocities relative to the largest speed; the
+positions as absolute differences in cell units and velocities relative to
+the largest speed; the
 Picard iteration count is pinned to the oracle's in each step so that both
 sides run the same iterates.  Particles are compared keyed by species and id.
 """
@@ -39,6 +40,39 @@ def _rel(a, b):
     return np.abs(a - b).max() / den
 
 
+def _currents_ok(Ig, Io, w, parts, what=""):
+    """Current parity: 1e-12 of the largest current, plus the floor the
+    oracle's positions set.  The oracle keeps global logical positions
+    (xi up to nr, eta up to nz), so each sub-step's displacement, the
+    difference of two stored positions, carries the rounding of a number of
+    that size: up to ulp(max(nr, nz)) cells, i.e. (q w / dt) ulp amperes per
+    particle.  The GPU forms displacements from cell offsets in [0, 1].  The
+    floor is that per-particle bound times the square root of the particles
+    that deposit on one edge (at most those of four cells), times 2."""
+    n_cell = 0
+    for d in parts:
+        if len(d["r"]):
+            n_cell = max(n_cell, _max_per_cell(w, d))
+    unit = sum(abs(d["q"] * d["w"]) for d in parts) / w.dt
+    floor = 2.0 * unit * np.spacing(float(max(w.nr, w.nz))) * math.sqrt(4 * max(n_cell, 1))
+    worst = 0.0
+    for a, b in zip(Ig, Io):
+        err = np.abs(a - b).max()
+        bound = 1e-12 * np.abs(b).max() + floor
+        worst = max(worst, err / bound)
+    _flush(f"  {what} currents: worst error {worst:.2f} of the bar (floor {floor:.2e} A)")
+    return worst <= 1.0
+
+
+def _max_per_cell(w, d):
+    s = w.R / (w.nr + w.xi_a)
+    r = np.asarray(d["r"])
+    xi = np.where(r < 2 * s * w.xi_a, r * r / (4 * s * s * max(w.xi_a, 1e-300)), r / s - w.xi_a)
+    i = np.clip(np.floor(xi).astype(np.int64), 0, w.nr - 1)
+    j = np.clip(np.floor(np.asarray(d["z"]) / (w.L / w.nz)).astype(np.int64), 0, w.nz - 1)
+    return int(np.bincount(i * w.nz + j, minlength=w.nr * w.nz).max())
+
+
 def _by_uid(d):
     o = np.argsort(d["uid"], kind="stable")
     return {k: v[o] for k, v in d.items()}
@@ -51,8 +85,8 @@ def _cmp_species(gpu, ora, what=""):
     if len(o["uid"]) == 0:
         return 0.0
     worst = 0.0
-    for k in ("xi", "eta"):
-        worst = max(worst, np.abs(g[k] - o[k]).max() / max(np.abs(o[k]).max(), 1.0))
+    for k in ("xi", "eta"):  # absolute, in cell units
+        worst = max(worst, np.abs(g[k] - o[k]).max())
     vmax = max(np.abs(o[k]).max() for k in ("vr", "vt", "vz"))
     for k in ("vr", "vt", "vz"):
         worst = max(worst, np.abs(g[k] - o[k]).max() / vmax)
@@ -81,7 +115,9 @@ def test_load_read_roundtrip(og, torch_cuda):
         assert _cmp_species(d, sp[k].view(), "load") < 1e-14
 
 
-@pytest.mark.parametrize("shape", [(32, 32, 2.0), (37, 29, 2.0), (70, 130, 0.0)])
+# nr > 256 gives the per-mode scan 2, 4 and 5 rows per thread
+@pytest.mark.parametrize("shape", [(32, 32, 2.0), (37, 29, 2.0), (70, 130, 0.0), (300, 16, 2.0),
+                                   (512, 8, 2.0), (1024, 8, 2.0), (1100, 12, 0.0)])
 def test_field_solve_parity(og, torch_cuda, shape):
     import paper_2212_08836_amd as P
     nr, nz, xa = shape
@@ -216,10 +252,12 @@ def test_push_deposit_edge_cases(og, torch_cuda):
     assert np.abs(side).max() > 0 and np.abs(bot).max() > 0 and np.abs(top).max() > 0
 
 
-def _push_deposit_case(og, P, w, parts, sort, seed=6):
+def _push_deposit_case(og, P, w, parts, sort, seed=6, waves=0):
     """One push (then one committing push) of `parts` in random half-step
-    fields against the oracle; returns the oracle's face-crossing count."""
+    fields against the oracle; returns the oracle's face-crossing count.
+    waves: build of the plain slow pass (0 by size, 2 or 3 forced)."""
     g, sp, ctx = _make_pair(w, og, P, parts)
+    ctx.set_option(P.ECPIC_OPT_QUEUE_WAVES, waves)
     if sort:
         ctx.sort()
     rng = np.random.default_rng(seed)
@@ -250,30 +288,31 @@ def _push_deposit_case(og, P, w, parts, sort, seed=6):
     return cross
 
 
-@pytest.mark.parametrize("sort", [False, True])
-def test_push_deposit_many_crossers(og, torch_cuda, sort):
+@pytest.mark.parametrize("sort,waves", [(False, 0), (True, 0), (False, 3), (True, 3)])
+def test_push_deposit_many_crossers(og, torch_cuda, sort, waves):
     # electrons at 30x thermal speed (about 2.7 keV): about half of them leave
     # their cell, hundreds per fast-pass block, so the slow queue's records
     # are both staged and fetched again, and in cell order (sort) the slow
     # pass's tile takes most deposits while in load order most go to global
     # atomics
     import paper_2212_08836_amd as P
-    _flush(f"push_deposit parity, fast electrons, sorted {sort}")
+    _flush(f"push_deposit parity, fast electrons, sorted {sort}, slow-pass build {waves}")
     w = E.workload("c1")
     parts = E.make_particles(w, n=4096)
     for k in ("vr", "vt", "vz"):
         parts[0][k] = parts[0][k] * 30.0
-    assert _push_deposit_case(og, P, w, parts, sort) > 2000  # 2266
+    assert _push_deposit_case(og, P, w, parts, sort, waves=waves) > 2000  # 2266
 
 
-def test_push_deposit_long_rows(og, torch_cuda):
+@pytest.mark.parametrize("waves", [0, 3])
+def test_push_deposit_long_rows(og, torch_cuda, waves):
     # 320 cells along z: the slow pass's tile spans part of a row only, so
     # crossings of r-faces leave it for global atomics
     import paper_2212_08836_amd as P
-    _flush("push_deposit parity, 12 x 320 grid")
+    _flush(f"push_deposit parity, 12 x 320 grid, slow-pass build {waves}")
     w = E.Workload("long", 12, 320, 0.01, 0.03, ppc=2, Te_eV=300.0)
     parts = E.make_particles(w)
-    assert _push_deposit_case(og, P, w, parts, sort=True) > 3000
+    assert _push_deposit_case(og, P, w, parts, sort=True, waves=waves) > 3000
 
 
 def test_step_parity_edge_cases(og, torch_cuda):
@@ -432,6 +471,99 @@ def test_c2_full_size_sampled(og, torch_cuda):
         keep = np.isin(a["uid"], ov["uid"])
         gv = {kk: v[keep] for kk, v in a.items()}
         assert _cmp_species(gv, ov, f"c2 sample sp {k}") < TOL
+
+
+def _c2_half_field(w, seed=9):
+    rng = np.random.default_rng(seed)
+    nr, nz = w.nr, w.nz
+    urh = rng.standard_normal(nr * (nz + 1)) * 3.0
+    uzh = rng.standard_normal((nr + 1) * nz) * 3.0
+    urh.reshape(nr, nz + 1)[:, [0, -1]] = 0
+    urh.reshape(nr, nz + 1)[nr - 1, 0] = 100.0
+    uzh.reshape(nr + 1, nz)[-1] = 0
+    return urh, uzh
+
+
+def test_c2_full_iteration_pass_currents(og, torch_cuda):
+    # the bench's dominant pass at full size (4.19M particles, cell-sorted,
+    # fast and slow pass): every current element against the oracle's push
+    # of every particle
+    import paper_2212_08836_amd as P
+    _flush("c2 full-size iteration pass, every current")
+    w = E.workload("c2")
+    parts = E.make_particles(w)
+    g, sp, ctx = _make_pair(w, og, P, parts, extra_cap=0.05)
+    ctx.sort()
+    urh, uzh = _c2_half_field(w)
+    ctx.set_half_field(urh, uzh)
+    Ir_g, Iz_g = ctx.push_deposit(commit=False)
+    Ir_o, Iz_o = g.zeros_r(), g.zeros_z()
+    cross = 0
+    for s in sp:
+        _, _, rc, st = g.push_deposit(s, urh, uzh, commit=False, Ir=Ir_o, Iz=Iz_o)
+        assert rc == 0
+        cross += st["n_crossings"]
+    _flush(f"  {cross} face crossings; Ir {_rel(Ir_g, Ir_o):.2e}, Iz {_rel(Iz_g, Iz_o):.2e}")
+    assert cross > 50_000
+    assert _currents_ok((Ir_g, Iz_g), (Ir_o, Iz_o), w, parts, "c2 both species")
+
+
+def test_c2_full_iteration_pass_currents_per_species(og, torch_cuda):
+    # each species alone (the other immobile): the ions' currents are four
+    # orders of magnitude below the electrons', so their parity shows the
+    # position-rounding floor of the bar on its own
+    import paper_2212_08836_amd as P
+    _flush("c2 full-size iteration pass, per species")
+    w = E.workload("c2")
+    parts = E.make_particles(w)
+    g = og.grid_from_workload(w)
+    urh, uzh = _c2_half_field(w)
+    for k in range(2):
+        mob = (k == 0, k == 1)
+        ctx = P.context_from_workload(w)
+        P.load_workload_species(ctx, parts, extra_cap=0.05, mobile=mob)
+        ctx.sort()
+        ctx.set_half_field(urh, uzh)
+        Ig = ctx.push_deposit(commit=False)
+        s = g.species(parts[k], cap=len(parts[k]["r"]) + 256, role=k + 1)
+        Io = (g.zeros_r(), g.zeros_z())
+        _, _, rc, st = g.push_deposit(s, urh, uzh, commit=False, Ir=Io[0], Iz=Io[1])
+        assert rc == 0
+        assert _currents_ok(Ig, Io, w, [parts[k]], f"c2 species {k}")
+        ctx.close()
+
+
+def test_c2_full_step_tolerance_mode(og, torch_cuda):
+    # one production step of the bench workload (100 MHz drive, 5 Pa MCC),
+    # each side stopping on its own residual; fields, every particle, the
+    # tallies, and the library's own charge-conservation check
+    import paper_2212_08836_amd as P
+    _flush("c2 full-size step, tolerance mode")
+    w = E.workload("c2")
+    parts = E.make_particles(w)
+    g, sp, ctx = _make_pair(w, og, P, parts, extra_cap=0.05)
+    mcc = w.mcc_params()
+    ctx.set_mcc(mcc)
+    st = og.State(g)
+    for n in range(2):
+        d_o = g.step(st, sp, mcc=mcc, tol=w.tol)
+        assert d_o["rc"] == 0
+        d_g = ctx.step(tol=w.tol, conservation=True)
+        assert d_g["iters"] == d_o["iters"] and d_g["converged"] == 1
+        for a, b in zip(d_g["residual"], d_o["residual"]):
+            assert abs(a - b) <= 1e-9 * b + 1e-13
+        ur, uz, h = ctx.get_fields()
+        errs = [_rel(ur, st.ur), _rel(uz, st.uz), _rel(h, st.h)]
+        for k in range(2):
+            errs.append(_cmp_species(ctx.read_particles(k), sp[k].view(), f"c2 step {n} sp {k}"))
+        assert d_g["n_ionized"] == d_o["n_ionized"]
+        assert d_g["n_coll"][:2] == d_o["n_coll"][:2]
+        assert d_g["n_absorbed"][:2] == d_o["n_absorbed"][:2]
+        _flush(f"  step {n}: iters {d_o['iters']} worst {max(errs):.2e} continuity "
+               f"{d_g['continuity_max'] / d_g['q_max']:.1e} gauss {d_g['gauss_max'] / d_g['q_max']:.1e}")
+        assert max(errs) < TOL, errs
+        assert d_g["continuity_max"] <= 1e-12 * d_g["q_max"]
+        assert d_g["gauss_max"] <= 1e-12 * d_g["q_max"]
 
 
 def test_step_tolerance_mode_c1(og, torch_cuda):
