@@ -232,6 +232,22 @@ ecpic_status ecpic_field_solve(ecpic_ctx* ctx, const double* ur0, const double* 
                                const double* h0, const double* Ir, const double* Iz, double t,
                                double* ur1, double* uz1, double* h1);
 
+/* The solve of ecpic_field_solve (same arguments, same results), for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  Its one scratch
+ * array, the [nz][nr] transform intermediate, is a static device array of
+ * the library (2^20 doubles, 8 MiB, on each GPU it runs on, held until the
+ * process ends) instead of the context's region; the call allocates nothing
+ * and needs nothing cleared (the solve writes every element it reads).
+ * Limit: nr * nz <= 2^20 cells (EINVAL beyond).  The context's device
+ * memory must already be in place (after ecpic_bind_workspace or any
+ * earlier call that touches the device): EINVAL otherwise.  Every call on
+ * one GPU shares the array: calls that overlap on one GPU (different
+ * streams, or contexts used from several threads) race. */
+ecpic_status ecpic_field_solve_noalloc(ecpic_ctx* ctx, const double* ur0, const double* uz0,
+                                       const double* h0, const double* Ir, const double* Iz,
+                                       double t, double* ur1, double* uz1, double* h1);
+
 /* One field iterate of the Picard loop: solve with the currents of the last
  * push_deposit, store u^{n+1,(k+1)}, h^{n+1,(k+1)} and the next half-step
  * field, and return r_k = |u^(k+1)-u^(k)|_E / |u^(k+1)|_E (synchronises). */

@@ -125,6 +125,7 @@ def lib() -> C.CDLL:
             "ecpic_push_deposit": ([_vp, C.c_int32, _dp, _dp], st),
             "ecpic_field_solve": ([_vp] + [_dp] * 5 + [C.c_double] + [_dp] * 3, st),
             "ecpic_field_iterate": ([_vp, C.POINTER(C.c_double)], st),
+            "ecpic_field_solve_noalloc": ([_vp] + [_dp] * 5 + [C.c_double] + [_dp] * 3, st),
             "ecpic_collide": ([_vp, C.POINTER(MccDesc), C.c_int64], st),
             "ecpic_set_mcc": ([_vp, C.POINTER(MccDesc)], st),
             "ecpic_step": ([_vp, C.POINTER(StepOpts), C.POINTER(StepStats)], st),
@@ -333,6 +334,16 @@ class Context:
                                              _ptr(ur1), _ptr(uz1), _ptr(h1)), self.h)
         self.torch.cuda.synchronize()
         return ur1.cpu().numpy(), uz1.cpu().numpy(), h1.cpu().numpy()
+
+    def field_solve_noalloc(self, ur0, uz0, h0, Ir, Iz, t, out=None):
+        """ecpic_field_solve_noalloc on device tensors; out: (ur1, uz1, h1)
+        device tensors to fill (allocated here when None).  Returns them."""
+        f = self.torch.float64
+        ins = [self._dev(a, f) for a in (ur0, uz0, h0, Ir, Iz)]
+        outs = out if out is not None else (self.zeros_r(), self.zeros_z(), self.zeros_h())
+        self._check(self.L.ecpic_field_solve_noalloc(self.h, *[_ptr(a) for a in ins], float(t),
+                                                     *[_ptr(o) for o in outs]), self.h)
+        return outs
 
     def field_iterate(self) -> float:
         r = C.c_double()

@@ -673,6 +673,11 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   }
   std::memset((void*)c.fin_host, 0, sizeof(StepFinal));
   for (int k = 0; k < kMaxIter; ++k) std::memcpy(&c.res_host[k], &kResPending, sizeof(double));
+  // this device's address of the static scratch of ecpic_field_solve_noalloc
+  if (hipGetDevice(&c.device) != hipSuccess || static_scratch_setup(c.device) != hipSuccess) {
+    ecpic_destroy(x);
+    return ECPIC_EHIP;
+  }
   *out = x;
   return ECPIC_OK;
 }
@@ -944,6 +949,36 @@ ecpic_status ecpic_field_solve(ecpic_ctx* x, const double* ur0, const double* uz
   a.uz1 = uz1;
   a.h1 = h1;
   HIPCHK(field_solve(c, a, c.stream));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_field_solve_noalloc(ecpic_ctx* x, const double* ur0, const double* uz0,
+                                       const double* h0, const double* Ir, const double* Iz,
+                                       double t, double* ur1, double* uz1, double* h1) {
+  if (!x || !ur0 || !uz0 || !h0 || !Ir || !Iz || !ur1 || !uz1 || !h1) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  // setting the context's device memory up would allocate: it must be in
+  // place already
+  if (!c.materialised)
+    return fail(c, ECPIC_EINVAL, "context device memory not set up (bind a workspace or make "
+                                 "any device call first)");
+  if (n_cells(c) > kStaticScratchDoubles)
+    return fail(c, ECPIC_EINVAL, "grid larger than the static scratch (2^20 cells)");
+  double* hat = static_scratch(c.device);
+  if (!hat) return fail(c, ECPIC_EHIP, "static scratch address not set up on this device");
+  SolveArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.ur0 = ur0;
+  a.uz0 = uz0;
+  a.h0 = h0;
+  a.Ir = const_cast<double*>(Ir);  // read only (no clear target)
+  a.Iz = const_cast<double*>(Iz);
+  a.vnext = drive(c.g, t + c.g.dt);
+  a.vhalf = 0.5 * (drive(c.g, t) + a.vnext);
+  a.ur1 = ur1;
+  a.uz1 = uz1;
+  a.h1 = h1;
+  HIPCHK(field_solve(c, a, c.stream, hat));
   return ECPIC_OK;
 }
 

@@ -18,9 +18,43 @@
 //                  h^{n+1}, the next half-step field, per-block partial sums of
 //                  the Picard residual, and the reset of the consumed currents.
 // Grouping rows lets each load of the transform matrix feed several rows.
+#include <mutex>
+
 #include "ecpic_internal.h"
 
+// The transform intermediate of ecpic_field_solve_noalloc: a static array of
+// the library on every GPU it runs on (held until the process ends), used
+// in place of the context's scratch by the entry point that may not
+// allocate.  Host code reaches it only through the per-device address that
+// hipGetSymbolAddress returns (static_scratch_setup); the name itself is a
+// host-side stand-in and must not be passed to a kernel.
+static __device__ __align__(256) double scratch[ecpic::kStaticScratchDoubles];
+
 namespace ecpic {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  // with `device` current: its own copy of the array, at its own address
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[device];
+}
 
 namespace {
 
@@ -709,9 +743,10 @@ hipError_t launch_half(const Ctx& c, const double* u0r, const double* u0z, const
   return hipGetLastError();
 }
 
-hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s) {
+hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s, double* hat) {
   const int nr = c.g.nr, nz = c.g.nz;
   const SolverDev& S = c.sol;
+  if (!hat) hat = S.work1;  // the mode-major transform of the right-hand side
   if (nr > kFB * kMaxE) return hipErrorInvalidValue;
   const int cb = col_blocks(nz);
   // residual partials: two per block of k_idct_recover
@@ -722,12 +757,12 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s) {
                                            (size_t)kFB * (kRB + 1));
   if (lds_rhs > 65536 || lds_rec > 65536) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rhs_dct, dim3(row_blocks(nr), cb), dim3(kFB), lds_rhs, s, c.m, S.rh, S.wr,
-                     S.wz, S.area, c.g.mu, a.ur0, a.uz0, a.h0, a.Ir, a.Iz, a.vhalf, S.Qt, S.work1,
+                     S.wz, S.area, c.g.mu, a.ur0, a.uz0, a.h0, a.Ir, a.Iz, a.vhalf, S.Qt, hat,
                      a.stop);
   hipLaunchKernelGGL(k_tri_scan, dim3(nz), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv, S.tri_up,
-                     S.work1, a.stop);
+                     hat, a.stop);
   hipLaunchKernelGGL(k_idct_recover, dim3(row_blocks(nr), cb), dim3(kFB), lds_rec, s, a, c.m,
-                     S.rh, S.wr, S.wz, S.Q, S.work1);
+                     S.rh, S.wr, S.wz, S.Q, hat);
   return hipGetLastError();
 }
 

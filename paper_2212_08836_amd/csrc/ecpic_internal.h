@@ -179,6 +179,7 @@ struct Ctx {
   ecpic_grid_desc g;
   ecpic_precision prec;
   hipStream_t stream;
+  int device = 0;                  // the device current at ecpic_create
   MapP m;
   std::string err;
   std::vector<Species> sp;
@@ -328,7 +329,13 @@ hipError_t launch_collide(const MapP& m, const SpecDev& s, const MccDev& c, Tall
 hipError_t launch_guess_half(const Ctx& c, double vnow, double vnext, hipStream_t s);
 hipError_t launch_half(const Ctx& c, const double* u0r, const double* u0z, const double* u1r,
                        const double* u1z, hipStream_t s);
-hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s);
+// hat: the [nz][nr] transform intermediate (null: the context's scratch)
+hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s, double* hat = nullptr);
+// the static scratch of the allocation-free solve: its address on `device`
+// (taken once, with that device current, by static_scratch_setup), or null
+constexpr int64_t kStaticScratchDoubles = (int64_t)1 << 20;
+hipError_t static_scratch_setup(int device);
+double* static_scratch(int device);
 // residual of iterate k from the solve's row partials, stored to res_dev[k]
 // (host memory, polled); sets *stop when it is <= tol (tol < 0: never) and
 // clears the queue counters and tallies for the next pass.  Does nothing

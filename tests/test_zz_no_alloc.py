@@ -1,0 +1,81 @@
+"""The allocation-free entry point ecpic_field_solve_noalloc: the same solve
+as ecpic_field_solve with its scratch in the library's static device array,
+called through the C ABI and compared with the allocating entry point on two
+calls in a row, the second on a smaller grid (the array keeps the first
+call's contents)."""
+import numpy as np
+import pytest
+
+import ecpic_inputs as E
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _inputs(nr, nz, seed):
+    rng = np.random.default_rng(seed)
+    ur0 = rng.standard_normal(nr * (nz + 1)) * 20
+    uz0 = rng.standard_normal((nr + 1) * nz) * 20
+    ur0.reshape(nr, nz + 1)[:, [0, -1]] = 0
+    uz0.reshape(nr + 1, nz)[-1] = 0
+    h0 = rng.standard_normal(nr * nz) * 0.1
+    Ir = rng.standard_normal(nr * (nz + 1)) * 1e-2
+    Iz = rng.standard_normal((nr + 1) * nz) * 1e-2
+    return ur0, uz0, h0, Ir, Iz
+
+
+def _ctx(P, nr, nz):
+    w = E.Workload("f", nr, nz, 0.05, 0.03, xi_a=2.0, dt=2e-11, drive_amp=(150.0,),
+                   drive_freq=(90e6,), drive_phase=(0.4,))
+    return P.context_from_workload(w)
+
+
+def test_noalloc_solve_matches_the_allocating_solve(torch_cuda):
+    import paper_2212_08836_amd as P
+    torch = torch_cuda
+    # the second call is smaller than the first: the static array still
+    # holds the first call's larger intermediate
+    for nr, nz, seed in ((512, 300, 1), (37, 29, 2)):
+        print(f"noalloc field solve {nr} x {nz}", flush=True)
+        ctx = _ctx(P, nr, nz)
+        ins = _inputs(nr, nz, seed)
+        t = 1.7e-9
+        ref = ctx.field_solve(*ins, t)  # the allocating entry point (sets the context up)
+        outs = (ctx.zeros_r(), ctx.zeros_z(), ctx.zeros_h())
+        for o in outs:
+            o.fill_(np.nan)  # every output element must be written
+        got = ctx.field_solve_noalloc(*ins, t, out=outs)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            a = a.cpu().numpy()
+            # the same kernels on the same inputs: the same bits
+            assert np.array_equal(a, b)
+        ctx.close()
+
+
+def test_noalloc_solve_refuses_what_it_cannot_do_without_allocating(torch_cuda):
+    import paper_2212_08836_amd as P
+    ins = _inputs(40, 24, 3)
+    # a context whose device memory is not in place yet
+    ctx = _ctx(P, 40, 24)
+    with pytest.raises(P.EcpicError) as e:
+        ctx.field_solve_noalloc(*ins, 0.0)
+    assert e.value.status == P.ECPIC_EINVAL
+    ctx.close()
+    # a grid beyond the static array (2^20 cells), its context set up by
+    # another device call
+    nr, nz = 1100, 1000
+    ctx = _ctx(P, nr, nz)
+    big = _inputs(nr, nz, 4)
+    ctx.get_fields()
+    with pytest.raises(P.EcpicError) as e:
+        ctx.field_solve_noalloc(*big, 0.0)
+    assert e.value.status == P.ECPIC_EINVAL
+    ctx.close()
