@@ -196,3 +196,49 @@ def cold_mode_particles(w: Workload, n: int, v0: float, seed: int = 7):
     i = dict(q=QE, m=M_AR, w=weight, r=r.copy(), z=z.copy(), vr=np.zeros(n),
              vt=np.zeros(n), vz=np.zeros(n), uid=np.arange(n, dtype=np.uint64))
     return [e, i]
+
+
+def make_particles_device(w: Workload, device="cuda", seed: Optional[int] = None,
+                          n: Optional[int] = None):
+    """The make_particles recipe drawn on the GPU with torch's seeded
+    generator, for the workloads too large to draw on the host (c5: 268M
+    particles): the same distributions (uniform-in-volume proposals shaped
+    by the profile by rejection, pair loading, Maxwellians, 0-based ids) from
+    another random stream.  Returns the two species as dicts of device
+    tensors (FP64; ids int64)."""
+    import torch
+    seed = w.seed if seed is None else seed
+    n = w.n_per_species if n is None else n
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    f64 = torch.float64
+    k = 2.405 / w.R
+    rs, zs, got = [], [], 0
+    while got < n:
+        m = int((n - got) * (1.0 if w.profile == "uniform" else 2.2)) + 1024
+        r = w.R * torch.sqrt(torch.rand(m, generator=gen, device=device, dtype=f64))
+        z = w.L * torch.rand(m, generator=gen, device=device, dtype=f64)
+        if w.profile != "uniform":
+            dens = torch.clamp(torch.special.bessel_j0(k * r), min=0.0) * torch.sin(math.pi * z / w.L)
+            keep = torch.rand(m, generator=gen, device=device, dtype=f64) < dens
+            r, z = r[keep], z[keep]
+            del dens, keep
+        rs.append(r)
+        zs.append(z)
+        got += int(r.numel())
+    r = torch.cat(rs)[:n].clone()
+    z = torch.cat(zs)[:n].clone()
+    del rs, zs
+    # strictly inside (0, R) x (0, L)
+    r.clamp_(min=float(np.nextafter(0.0, 1.0)), max=float(np.nextafter(w.R, 0.0)))
+    z.clamp_(min=float(np.nextafter(0.0, 1.0)), max=float(np.nextafter(w.L, 0.0)))
+    weight = _total_particles_phys(w) / n
+    out = []
+    for q, m_, T in ((-QE, ME, w.Te_eV), (QE, M_AR, w.Ti_eV)):
+        sig = math.sqrt(T * QE / m_)
+        v = torch.randn((3, n), generator=gen, device=device, dtype=f64) * sig
+        out.append(dict(q=q, m=m_, w=weight, r=r if not out else r.clone(),
+                        z=z if not out else z.clone(), vr=v[0].clone(), vt=v[1].clone(),
+                        vz=v[2].clone(), uid=torch.arange(n, device=device, dtype=torch.int64)))
+        del v
+    return out

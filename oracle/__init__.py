@@ -16,29 +16,40 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ecpic_oracle.c")
 _LIB = os.path.join(_HERE, "libecpic_oracle.so")
+# the same source with OpenMP: only for timing the CPU baseline on all cores
+_LIB_OMP = os.path.join(_HERE, "libecpic_oracle_omp.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
-                        "-Wall", "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (no FMA contraction, no fast-math), and
+    its OpenMP timing build."""
+    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out):
+            tmp = out + ".tmp"
+            subprocess.run(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
+                            "-Wall", *extra, "-o", tmp, _SRC, "-lm"], check=True)
+            os.replace(tmp, out)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        _lib = C.CDLL(_LIB)
-        _declare(_lib)
-    return _lib
+def lib(omp: bool = False):
+    """The oracle library; omp=True: the OpenMP timing build."""
+    if omp not in _libs:
+        path = _LIB_OMP if omp else _LIB
+        if not os.path.exists(path):
+            build(force=False)
+        L = C.CDLL(path)
+        _declare(L)
+        _libs[omp] = L
+    return _libs[omp]
+
+
+def threads(omp: bool = False) -> int:
+    """Threads a push pass of that build uses."""
+    return int(lib(omp).og_threads())
 
 
 class OgGrid(C.Structure):
@@ -47,7 +58,7 @@ class OgGrid(C.Structure):
                 ("n_drive", C.c_int32), ("self_b", C.c_int32),
                 ("drive_amp", C.c_double * 2), ("drive_freq", C.c_double * 2),
                 ("drive_phase", C.c_double * 2), ("bz_ext", C.c_double), ("er_ext", C.c_double),
-                ("sub_tol", C.c_double)]
+                ("sub_tol", C.c_double), ("push_only", C.c_int32), ("pad", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -130,6 +141,8 @@ def _declare(L):
     L.og_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
     L.og_child_uid.argtypes = [C.c_uint64, C.c_int64]
     L.og_child_uid.restype = C.c_uint64
+    L.og_threads.argtypes = []
+    L.og_threads.restype = C.c_int
 
 
 def _p(a: Optional[np.ndarray]):
@@ -204,8 +217,9 @@ class Grid:
     """Mesh, mapping, field operators and the factorised H_theta system."""
 
     def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
-                 drive_phase=(), self_b=False, bz_ext=0.0, er_ext=0.0, sub_tol=0.0):
-        L_ = lib()
+                 drive_phase=(), self_b=False, bz_ext=0.0, er_ext=0.0, sub_tol=0.0,
+                 omp=False, push_only=False):
+        L_ = lib(omp)
         g = OgGrid()
         g.nr, g.nz, g.R, g.L, g.xi_a, g.dt, g.eps, g.mu = nr, nz, R, L, xi_a, dt, eps, mu
         g.n_drive = len(drive_amp)
@@ -215,6 +229,7 @@ class Grid:
             g.drive_phase[k] = drive_phase[k] if k < len(drive_phase) else 0.0
         g.self_b = int(self_b)
         g.bz_ext, g.er_ext, g.sub_tol = bz_ext, er_ext, sub_tol
+        g.push_only = int(push_only)
         self.desc = g
         self.nr, self.nz, self.R, self.L, self.xi_a, self.dt = nr, nz, R, L, xi_a, dt
         self.eps, self.mu = eps, mu

@@ -7,7 +7,11 @@
  *
  * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
  * CPU-baseline timing, never by the product path.  Single-threaded, particle
- * load order, no blocking or fusion beyond what the method states.
+ * load order, no blocking or fusion beyond what the method states.  The
+ * same source built with OpenMP (a second library, used only to time the
+ * CPU baseline on all host cores) runs the particle loop of a push pass in
+ * parallel, each thread into its own current arrays, summed in thread
+ * order; everything else stays as written.
  *
  * What each part follows:
  *   mapping            Sec. 2.1 (separable r(xi), z(eta); r ~ sqrt(xi) near
@@ -27,6 +31,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OG_PI 3.14159265358979323846
 #define OG_QE 1.602176634e-19 /* elementary charge [C], CODATA 2018 */
@@ -249,7 +256,8 @@ int og_create(const og_grid* g, og_ctx** out) {
   c->wz = (double*)calloc(nr, sizeof(double));
   c->ncell = (int64_t)nr * nz;
   c->band = nz;
-  c->chol = (double*)malloc(sizeof(double) * (size_t)c->ncell * (size_t)(nz + 1));
+  c->chol = g->push_only ? (double*)malloc(sizeof(double))
+                         : (double*)malloc(sizeof(double) * (size_t)c->ncell * (size_t)(nz + 1));
   c->rhs = (double*)malloc(sizeof(double) * (size_t)c->ncell);
   c->x = (double*)malloc(sizeof(double) * (size_t)c->ncell);
   c->tr = (double*)malloc(sizeof(double) * (size_t)nr * (nz + 1));
@@ -270,7 +278,7 @@ int og_create(const og_grid* g, og_ctx** out) {
     c->wr[i] = g->eps * 2.0 * OG_PI * c->rh[i] * c->dz / c->ell[i];
     c->wz[i] = g->eps * c->azs[i] / c->dz;
   }
-  if (factorize(c) != 0) {
+  if (!g->push_only && factorize(c) != 0) {
     og_destroy(c);
     return -3;
   }
@@ -312,6 +320,7 @@ static void set_boundary(const og_ctx* c, double* ur, double* uz, double vd) {
 int og_field_solve(og_ctx* c, const double* ur0, const double* uz0, const double* h0,
                    const double* Ir, const double* Iz, double t,
                    double* ur1, double* uz1, double* h1) {
+  if (c->g.push_only) return -5;
   const int nr = c->g.nr, nz = c->g.nz;
   const double dt = c->g.dt, mu = c->g.mu;
   const double vh = 0.5 * (og_drive(c, t) + og_drive(c, t + dt));
@@ -759,10 +768,93 @@ static void tally_wall(const og_ctx* c, og_state* st, const hit_t* h, double qw)
   }
 }
 
+int og_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+#ifdef _OPENMP
+/* The push pass with the particle loop split over the threads (timing
+ * build): each thread pushes a contiguous range into its own currents and
+ * counters, which are then summed in thread order; a commit then absorbs and
+ * compacts in particle order, as the serial loop does. */
+static int push_deposit_threads(og_ctx* c, og_species* s, const pctx* P, int commit,
+                                double* Ir, double* Iz, og_state* st, og_stats* S) {
+  const int nt = omp_get_max_threads();
+  const int64_t nur = (int64_t)c->g.nr * (c->g.nz + 1), nuz = (int64_t)(c->g.nr + 1) * c->g.nz;
+  const double qw = s->q * s->w;
+  double* cur = (double*)calloc((size_t)nt * (size_t)(nur + nuz), sizeof(double));
+  og_stats* ts = (og_stats*)calloc((size_t)nt, sizeof(og_stats));
+  double* twork = (double*)calloc((size_t)nt, sizeof(double));
+  int* terr = (int*)calloc((size_t)nt, sizeof(int));
+  pst* res = commit ? (pst*)malloc(sizeof(pst) * (size_t)(s->n > 0 ? s->n : 1)) : NULL;
+  int* rcs = commit ? (int*)malloc(sizeof(int) * (size_t)(s->n > 0 ? s->n : 1)) : NULL;
+  hit_t* hits = commit ? (hit_t*)malloc(sizeof(hit_t) * (size_t)(s->n > 0 ? s->n : 1)) : NULL;
+#pragma omp parallel
+  {
+    const int t = omp_get_thread_num();
+    double* mr = cur + (int64_t)t * (nur + nuz);
+    double* mz = mr + nur;
+#pragma omp for schedule(static)
+    for (int64_t k = 0; k < s->n; ++k) {
+      pst p = {s->xi[k], s->eta[k], s->vr[k], s->vt[k], s->vz[k]};
+      hit_t hit;
+      const int rc = push_one(P, &p, qw, mr, mz, S ? &ts[t] : NULL, &twork[t], &hit);
+      if (rc == P_ERROR) terr[t]++;
+      if (commit) { res[k] = p; rcs[k] = rc; hits[k] = hit; }
+    }
+  }
+  int nerr = 0;
+  double work = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    const double* mr = cur + (int64_t)t * (nur + nuz);
+    for (int64_t e = 0; e < nur; ++e) Ir[e] += mr[e];
+    for (int64_t e = 0; e < nuz; ++e) Iz[e] += mr[nur + e];
+    nerr += terr[t];
+    work += twork[t];
+    if (S) {
+      S->n_substeps += ts[t].n_substeps;
+      S->n_crossings += ts[t].n_crossings;
+      S->n_halvings += ts[t].n_halvings;
+      S->n_errors += ts[t].n_errors;
+      S->n_capped += ts[t].n_capped;
+    }
+  }
+  if (commit) {
+    int64_t out = 0;
+    for (int64_t k = 0; k < s->n; ++k) {
+      const pst p = res[k];
+      if (rcs[k] == P_ABSORBED) {
+        tally_wall(c, st, &hits[k], qw);
+        if (S) S->w_absorbed += 0.5 * s->m * s->w * (p.vr * p.vr + p.vt * p.vt + p.vz * p.vz);
+        continue;
+      }
+      s->xi[out] = p.xi; s->eta[out] = p.eta;
+      s->vr[out] = p.vr; s->vt[out] = p.vt; s->vz[out] = p.vz;
+      s->uid[out] = s->uid[k];
+      out++;
+    }
+    if (S) S->w_particles += work;
+    s->n = out;
+  }
+  free(cur); free(ts); free(twork); free(terr); free(res); free(rcs); free(hits);
+  return -nerr;
+}
+#endif
+
 int og_push_deposit(og_ctx* c, og_species* s, const double* ur_h, const double* uz_h,
                     const double* h_h, int commit, double* Ir, double* Iz,
                     og_state* st, og_stats* S) {
   if (!s->mobile) return 0;
+#ifdef _OPENMP
+  if (omp_get_max_threads() > 1) {
+    pctx Pt = {c, ur_h, uz_h, h_h, s->q / s->m};
+    return push_deposit_threads(c, s, &Pt, commit, Ir, Iz, st, S);
+  }
+#endif
   pctx P = {c, ur_h, uz_h, h_h, s->q / s->m};
   const double qw = s->q * s->w;
   int nerr = 0;
@@ -1010,6 +1102,7 @@ int og_collide(og_ctx* c, og_species* sp, int32_t nsp, const og_mcc* m, int64_t 
 /* ------------------------------------------------------------------------ */
 int og_step(og_ctx* c, og_state* st, og_species* sp, int32_t nsp, const og_mcc* mcc,
             const og_opts* o, og_stats* S) {
+  if (c->g.push_only) return -5;
   const int nr = c->g.nr, nz = c->g.nz;
   const int64_t nur = (int64_t)nr * (nz + 1), nuz = (int64_t)(nr + 1) * nz, nh = c->ncell;
   const double dt = c->g.dt, t = st->t;

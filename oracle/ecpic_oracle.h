@@ -33,6 +33,10 @@ typedef struct {
   double bz_ext;                /* test option: uniform external B_z [T]     */
   double er_ext;                /* test option: external E_r = er_ext*r/R    */
   double sub_tol;               /* inner fixed-point tolerance (0 -> 1e-14)  */
+  int32_t push_only;            /* 1: no field solver (push passes only; the
+                                   banded factorisation is skipped, and
+                                   og_field_solve / og_step return -5)       */
+  int32_t pad;
 } og_grid;
 
 typedef struct {
@@ -87,6 +91,10 @@ typedef struct {
 } og_stats;
 
 typedef struct og_ctx og_ctx;
+
+/* Threads a push pass uses: 1, or the OpenMP thread count in the timing
+ * build (libecpic_oracle_omp.so). */
+int og_threads(void);
 
 /* Setup: derived mesh quantities and the Cholesky factor of the H_theta
  * system (Sec. 2.1, Eq. (2) with mid-point centring).  Returns 0 or <0. */

@@ -813,6 +813,8 @@ ecpic_status ecpic_add_species(ecpic_ctx* x, const ecpic_species_desc* d, int32_
     b.q = d->q;
     b.m = d->m;
     b.w = d->weight;
+    b.qm = d->q / d->m;
+    b.qw_dt = d->q * d->weight / c.g.dt;
     b.mobile = d->mobile;
     b.sid = (int32_t)c.sp.size();
   }

@@ -46,6 +46,7 @@ struct SpecDev {
   uint64_t* uid;
   int64_t n, cap;
   double q, m, w;
+  double qm, qw_dt;   // q/m and q w/dt, formed on the host
   int32_t mobile, sid;
 };
 

@@ -51,8 +51,10 @@ struct Mid {
 
 // 1/x from the hardware reciprocal estimate refined by Newton steps
 // (y <- y + y (1 - x y)): two in FP64, one in FP32, which leaves the result
-// within an ulp or two of the rounded quotient for the positive, normal x
-// the in-cell solve passes (a fraction of the cost of an IEEE division).
+// within an ulp or two of the rounded quotient for the finite, normal,
+// non-zero x the sub-step solves pass (a fraction of the cost of an IEEE
+// division); 0 gives NaN, which the callers' admissibility checks reject or
+// never select.
 __device__ __forceinline__ double rcp_refined(double x) {
   double y = __builtin_amdgcn_rcp(x);
   y = fma(y, fma(-x, y, 1.0), y);
@@ -63,6 +65,22 @@ __device__ __forceinline__ float rcp_refined(float x) {
   const float y = __builtin_amdgcn_rcpf(x);
   return fmaf(y, fmaf(-x, y, 1.0f), y);
 }
+
+// sqrt(x) from the hardware reciprocal-square-root estimate: two Newton
+// steps on 1/sqrt(x), then one on the root, which leaves it within an ulp or
+// two of the rounded root for the positive, normal x the sub-step solves
+// pass (0 gives 0, a negative x NaN); a fraction of the cost of the
+// correctly rounded sequence.
+__device__ __forceinline__ double sqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  double r = x * y;
+  r = fma(0.5 * y, fma(-r, r, x), r);
+  return x > 0.0 ? r : (x == 0.0 ? 0.0 : __builtin_nan(""));
+}
+__device__ __forceinline__ float sqrt_refined(float x) { return sqrtf(x); }
 
 // Element access by a 32-bit byte offset from a uniform base, which the
 // loads and stores take as a scalar base plus one vector offset (no 64-bit
@@ -87,8 +105,9 @@ template <typename T>
 __device__ __forceinline__ void map_r(const MapP& m, int i, T a, T& r, T& ijr) {
   if (double(i) + double(a) < m.xi_a) {
     const T xi = T(i) + a;
-    r = T(2.0 * m.s) * sqrt(xi * T(m.xi_a));
-    ijr = sqrt(xi / T(m.xi_a)) * T(m.inv_s);
+    const T sx = sqrt_refined(xi);
+    r = T(2.0 * m.s * sqrt(m.xi_a)) * sx;
+    ijr = sx * T(m.rsqrt_xa * m.inv_s);
   } else {
     r = T(m.s * (double(i) + m.xi_a)) + T(m.s) * a;
     ijr = T(m.inv_s);
@@ -110,7 +129,7 @@ __device__ __forceinline__ T mid_a_val(const MapP& m, int i, T a, T vbr, T dtau)
   if (m.xi_a > 0.0 && T(i) + al < T(m.xi_a)) {
     const T xi = T(i) + a;
     const T beta = T(0.5) * dtau * vbr * T(m.inv_s * m.rsqrt_xa);
-    const T y = T(0.5) * (beta + sqrt(beta * beta + T(4) * xi));
+    const T y = T(0.5) * (beta + sqrt_refined(beta * beta + T(4) * xi));
     return y * y - T(i);
   }
   return al;
@@ -140,7 +159,7 @@ __device__ __forceinline__ bool accel(const MapP& m, const T F[4], int i, T abar
   // only a particle without v_theta is admissible.  Selects, no branches.
   const bool off_axis = rb > T(0);
   const T den = rb + T(0.5) * dtau * vbr;
-  const T q = T(1) / den;
+  const T q = rcp_refined(den);
   vtb = off_axis ? vt0 * rb * q : T(0);
   ar = qm * er + (off_axis ? vtb * vt0 * q : T(0));
   az = qm * ez;
@@ -223,34 +242,31 @@ __device__ __forceinline__ bool solve_fast(const MapP& m, const T F[4], const PS
   const T vt2 = p.vt * p.vt;
   const T c2 = cc * vt2;
   T kr = k0 + c2 * rcp_refined(r0);  // centrifugal term at the start position
-  // g(kr) = k0 + c2 rb / re^2 is a contraction with slope
-  // g' = c2 (hd - 2 dtau rb / re) / re^2; for |g'| < 1/2 the iterate g(kr)
-  // is within 2 |g'| |g(kr) - kr| of the fixed point, which is the stopping
-  // test (the bare step |g(kr) - kr| otherwise).  The outputs are formed
-  // once after the loop, from the final kr.
+  // g(kr) = k0 + c2 rb / re^2 is a contraction (slope about (dt v_t / r)^2,
+  // tiny in a linear cell): iterate until the step |g(kr) - kr| is below the
+  // tolerance of the velocity scale, which bounds the distance to the fixed
+  // point by the step itself.  The scale is taken once, from the first
+  // estimate of the mid velocity (a fixed threshold keeps the loop to the
+  // update and one compare); admissibility is checked once, on the result.
+  const T thr = Tol<T>::v() * (fabs(p.vr + kr) + fabs(p.vt) + fabs(p.vz + bz + Kz * (p.vr + kr)));
   bool conv = false;
   for (int it = 0; it < 12; ++it) {
     const T vr = p.vr + kr;
     const T rb = r0 + hd * vr;
-    const T re = r0 + dtau * vr;
-    ok = ok & (rb > T(0)) & (re > T(0));
-    const T ire = rcp_refined(re);
-    const T g = c2 * ire * ire;
-    const T nkr = k0 + g * rb;
-    const T slope = fabs(g * (hd - T(2) * dtau * rb * ire));
+    const T ire = rcp_refined(r0 + dtau * vr);
+    const T nkr = k0 + c2 * ire * ire * rb;
     const T d = fabs(nkr - kr);
     kr = nkr;
-    const T kz = bz + Kz * (p.vr + kr);
-    const T scale = fabs(p.vr + kr) + fabs(p.vt * rb * ire) + fabs(p.vz + kz);
-    const T err = slope < T(0.5) ? T(2) * slope * d : d;
-    if (!ok || err <= Tol<T>::v() * scale) {
-      conv = ok;
+    if (d <= thr) {
+      conv = true;
       break;
     }
   }
   const T vrb = p.vr + kr;
   const T rb1 = r0 + hd * vrb;
   const T re1 = r0 + dtau * vrb;
+  ok = ok & (rb1 > T(0)) & (re1 > T(0));
+  conv = conv & ok;
   const T kz = bz + Kz * vrb;
   M.kr = kr;
   M.kz = kz;
@@ -270,17 +286,17 @@ __device__ __forceinline__ T smallest_pos_root(T a, T v, T D) {
   T best = T(INFINITY);
   if (A == T(0)) {
     if (B != T(0)) {
-      const T t = -C / B;
+      const T t = -C * rcp_refined(B);
       if (t > T(0)) best = t;
     }
     return best;
   }
   const T disc = B * B - T(4) * A * C;
   if (disc < T(0)) return best;
-  const T sq = sqrt(disc);
+  const T sq = sqrt_refined(disc);
   const T q = T(-0.5) * (B + (B >= T(0) ? sq : -sq));
   if (q != T(0)) {
-    const T t1 = q / A, t2 = C / q;
+    const T t1 = q * rcp_refined(A), t2 = C * rcp_refined(q);
     if (t1 > T(0) && t1 < best) best = t1;
     if (t2 > T(0) && t2 < best) best = t2;
   }
@@ -299,7 +315,7 @@ __device__ bool solve_cross(const MapP& m, const T F[4], const PState<T>& p, int
   if (d == 0) {
     T rb, ijr;
     map_r(m, p.i, xbar, rb, ijr);
-    Jd = T(1) / ijr;
+    Jd = rcp_refined(ijr);
   } else {
     Jd = T(m.dz);
   }
@@ -601,7 +617,7 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
         const T e_end = d == 0 ? ea : eb;
         const T f = e_end < T(0) ? T(0) : T(1);
         const T xd = d == 0 ? p.a : p.b;
-        const T t0 = dtry * (f - xd) / (e_end - xd);
+        const T t0 = dtry * (f - xd) * rcp_refined(e_end - xd);
         T tt;
         Mid<T> CM;
         bool cap;
@@ -1343,8 +1359,8 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   const int64_t qseg = P.qseg[slot];
   const MapP& m = A.m;
   const SpecDev& s = A.s;
-  const T qm = T(s.q / s.m);
-  const double qw_dt = s.q * s.w / m.dt;
+  const T qm = T(s.qm);
+  const double qw_dt = s.qw_dt;
   const int nz = m.nz;
   // the tile window: one radial row of drift either side of the block's
   // first particle's cell
@@ -1583,7 +1599,7 @@ __device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, uint64_t 
                                          const Tile& tl, Tl& t) {
   const MapP& m = A.m;
   const SpecDev& s = A.s;
-  const double qw_dt = s.q * s.w / m.dt;
+  const double qw_dt = s.qw_dt;
   PushOut o;
   if constexpr (sizeof(T) == 4) {
     // mixed path: the few face crossers are pushed in FP64 arithmetic
@@ -1597,7 +1613,7 @@ __device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, uint64_t 
     pd.vr = p.vr;
     pd.vt = p.vt;
     pd.vz = p.vz;
-    push_particle<double>(m, A.ur, A.uz, A.Ir, A.Iz, tl, pd, s.q / s.m, qw_dt, COMMIT, o);
+    push_particle<double>(m, A.ur, A.uz, A.Ir, A.Iz, tl, pd, s.qm, qw_dt, COMMIT, o);
     p.i = pd.i;
     p.j = pd.j;
     p.a = T(pd.a);
@@ -1606,7 +1622,7 @@ __device__ __forceinline__ void slow_one(const PushArgs& A, int64_t k, uint64_t 
     p.vt = T(pd.vt);
     p.vz = T(pd.vz);
   } else {
-    push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, tl, p, T(s.q / s.m),
+    push_particle<T>(m, FieldPtr<T>::r(A), FieldPtr<T>::z(A), A.Ir, A.Iz, tl, p, T(s.qm),
                      qw_dt, COMMIT, o);
   }
   if (COMMIT) {

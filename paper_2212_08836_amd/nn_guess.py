@@ -91,9 +91,9 @@ def to_device(ctx, x, t, norm):
     return xd, td
 
 
-def train(ctx, xd, td, steps=400, batch=8, lr=1e-3, seed=0, w=None):
+def train(ctx, xd, td, steps=400, batch=8, lr=1e-3, seed=0, w=None, progress=None):
     """Adam on the mean squared error; returns the FP32 weights (device) and
-    the loss history."""
+    the loss history.  progress(step, loss) is called every 100 steps."""
     torch = ctx.torch
     n = ctx.nn_param_count()
     if w is None:
@@ -109,5 +109,7 @@ def train(ctx, xd, td, steps=400, batch=8, lr=1e-3, seed=0, w=None):
                                td.index_select(0, idx).contiguous())
         ctx.nn_adam(w, m, v, dw, lr, it)
         losses.append(loss)
+        if progress is not None and it % 100 == 0:
+            progress(it, loss)
     torch.cuda.synchronize()
     return w, losses

@@ -195,3 +195,20 @@ def test_brute_force_newton_agrees_with_picard(og):
         assert abs(sp.xi[k] - P1[k, 0]) < 1e-12 and abs(sp.eta[k] - P1[k, 1]) < 1e-12
         vmax = np.abs(P1[k, 2:]).max()
         assert np.abs(np.array([sp.vr[k], sp.vt[k], sp.vz[k]]) - P1[k, 2:]).max() < 1e-11 * vmax
+
+
+def test_device_input_generator_draws_the_same_distributions():
+    # the GPU recipe (run here on the CPU device) against the host one: the
+    # same profile, weights and Maxwellians, another random stream
+    import torch
+    from scipy import stats
+    w = E.workload("c2")
+    a = E.make_particles_device(w, device="cpu", n=100_000)
+    b = E.make_particles(w, n=100_000)
+    for k in range(2):
+        assert a[k]["w"] == b[k]["w"] and a[k]["q"] == b[k]["q"]
+        for key in ("r", "z", "vr", "vt", "vz"):
+            x = a[k][key].numpy()
+            assert stats.ks_2samp(x, b[k][key]).pvalue > 1e-4, (k, key)
+        assert torch.equal(a[0]["r"], a[1]["r"])  # pair loading
+    assert float(a[0]["r"].min()) > 0 and float(a[0]["r"].max()) < w.R
