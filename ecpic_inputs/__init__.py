@@ -42,8 +42,12 @@ class Workload:
     drive_amp: tuple = ()
     drive_freq: tuple = ()
     drive_phase: tuple = ()
+    drive_t_end: float = 0.0  # > 0: the drive is a burst that ends then
     n0: float = 1e15
-    profile: str = "uniform"  # "uniform" or "j0sin"
+    profile: str = "uniform"  # "uniform", "j0sin" or "slab"
+    gap: float = 0.0  # slab: vacuum gap left at each electrode [m]
+    n_rings: int = 0  # slab: lattice rings, equally spaced in r^2
+    n_layers: int = 0  # slab: lattice layers, equally spaced in z
     ppc: int = 16  # macro-particles per cell per species
     Te_eV: float = 3.0
     Ti_eV: float = 0.026
@@ -67,7 +71,8 @@ class Workload:
                     dt=self.dt, eps=EPS0, mu=MU0,
                     drive_amp=tuple(self.drive_amp), drive_freq=tuple(self.drive_freq),
                     drive_phase=tuple(self.drive_phase) if self.drive_phase
-                    else tuple(0.0 for _ in self.drive_amp))
+                    else tuple(0.0 for _ in self.drive_amp),
+                    drive_t_end=self.drive_t_end)
 
     def mcc_params(self) -> Optional[dict]:
         if self.pressure_pa <= 0:
@@ -93,6 +98,29 @@ WORKLOADS: Dict[str, Workload] = {
                    drive_amp=(200.0, 200.0), drive_freq=(60e6, 13.56e6), steps=1000,
                    tol=1e-10, pressure_pa=5.0, seed=5),
 }
+
+
+def sawtooth_drive(amp: float, n_harm: int, freq: float):
+    """Amplitudes and frequencies of the sawtooth-like excitation
+    A sum_{n<=N} sin(2 pi n f t) / n (Sec. 3.1)."""
+    return (tuple(amp / n for n in range(1, n_harm + 1)),
+            tuple(n * freq for n in range(1, n_harm + 1)))
+
+
+_SAW_AMP, _SAW_FREQ = sawtooth_drive(1.0, 20, 106e6)
+
+# Surface-mode cavity (Sec. 3.1): a uniform 1e16 m^-3 plasma slab with
+# immobile ions and cold electrons between two 1.8 mm vacuum gaps, excited by
+# one period of the 106 MHz, 20-harmonic, 1 V sawtooth on the drive gap.
+# The ring count puts at least two rings into each cell next to the axis.
+WORKLOADS["slab_small"] = Workload(
+    "slab_small", 24, 50, 0.15, 0.03, dt=5e-11, drive_amp=_SAW_AMP, drive_freq=_SAW_FREQ,
+    drive_t_end=1.0 / 106e6, n0=1e16, profile="slab", gap=1.8e-3, n_rings=169, n_layers=44,
+    Te_eV=0.0, Ti_eV=0.0, steps=3000, tol=1e-10, seed=11)
+WORKLOADS["slab"] = Workload(
+    "slab", 64, 100, 0.15, 0.03, dt=2e-11, drive_amp=_SAW_AMP, drive_freq=_SAW_FREQ,
+    drive_t_end=1.0 / 106e6, n0=1e16, profile="slab", gap=1.8e-3, n_rings=1089, n_layers=176,
+    Te_eV=0.0, Ti_eV=0.0, steps=15000, tol=1e-10, seed=12)
 
 
 def workload(name: str, **over) -> Workload:
@@ -196,6 +224,31 @@ def cold_mode_particles(w: Workload, n: int, v0: float, seed: int = 7):
     i = dict(q=QE, m=M_AR, w=weight, r=r.copy(), z=z.copy(), vr=np.zeros(n),
              vt=np.zeros(n), vz=np.zeros(n), uid=np.arange(n, dtype=np.uint64))
     return [e, i]
+
+
+def slab_particles(w: Workload):
+    """Quiet start for the surface-mode cavity: electrons on a lattice of
+    n_rings rings equally spaced in r^2 (so equal volume per ring) times
+    n_layers layers equally spaced in z over [gap, L - gap], each with an
+    immobile ion at the same position (zero initial charge).  Velocities are
+    drawn at Te_eV / Ti_eV (zero: a cold plasma).  Returns [electrons, ions]
+    like make_particles; the ions are meant to be added with mobile = 0."""
+    rng = np.random.Generator(np.random.PCG64(w.seed))
+    u = (np.arange(w.n_rings) + 0.5) / w.n_rings
+    zl = w.gap + (w.L - 2.0 * w.gap) * (np.arange(w.n_layers) + 0.5) / w.n_layers
+    uu, zz = np.meshgrid(u, zl, indexing="ij")
+    r = w.R * np.sqrt(uu.ravel())
+    z = zz.ravel()
+    n = r.size
+    weight = w.n0 * math.pi * w.R ** 2 * (w.L - 2.0 * w.gap) / n
+    out = []
+    for q, m, T in ((-QE, ME, w.Te_eV), (QE, M_AR, w.Ti_eV)):
+        sig = math.sqrt(T * QE / m)
+        v = rng.standard_normal((3, n)) * sig
+        out.append(dict(q=q, m=m, w=weight, r=r.copy(), z=z.copy(),
+                        vr=v[0].copy(), vt=v[1].copy(), vz=v[2].copy(),
+                        uid=np.arange(n, dtype=np.uint64)))
+    return out
 
 
 def make_particles_device(w: Workload, device="cuda", seed: Optional[int] = None,

@@ -71,11 +71,12 @@ typedef struct {
   double xi_axis;         /* map parameter: r ~ sqrt(xi) below it, 0=uniform */
   double dt;              /* time step [s]                                   */
   double eps, mu;         /* permittivity, permeability of the gap           */
-  int32_t n_drive;        /* harmonics on the drive gap edge (0..2)          */
+  int32_t n_drive;        /* harmonics on the drive gap edge (0..32)         */
   int32_t reserved;
-  double drive_amp[2];    /* V(t) = sum amp sin(2 pi freq t + phase) [V]     */
-  double drive_freq[2];
-  double drive_phase[2];
+  double drive_amp[32];   /* V(t) = sum amp sin(2 pi freq t + phase) [V]     */
+  double drive_freq[32];
+  double drive_phase[32];
+  double drive_t_end;     /* > 0: V(t) = 0 from this time on (a burst)       */
 } ecpic_grid_desc;
 
 typedef struct {

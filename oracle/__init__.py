@@ -56,8 +56,9 @@ class OgGrid(C.Structure):
     _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("R", C.c_double), ("L", C.c_double),
                 ("xi_a", C.c_double), ("dt", C.c_double), ("eps", C.c_double), ("mu", C.c_double),
                 ("n_drive", C.c_int32), ("self_b", C.c_int32),
-                ("drive_amp", C.c_double * 2), ("drive_freq", C.c_double * 2),
-                ("drive_phase", C.c_double * 2), ("bz_ext", C.c_double), ("er_ext", C.c_double),
+                ("drive_amp", C.c_double * 32), ("drive_freq", C.c_double * 32),
+                ("drive_phase", C.c_double * 32), ("drive_t_end", C.c_double),
+                ("bz_ext", C.c_double), ("er_ext", C.c_double),
                 ("sub_tol", C.c_double), ("push_only", C.c_int32), ("pad", C.c_int32)]
 
 
@@ -217,8 +218,8 @@ class Grid:
     """Mesh, mapping, field operators and the factorised H_theta system."""
 
     def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
-                 drive_phase=(), self_b=False, bz_ext=0.0, er_ext=0.0, sub_tol=0.0,
-                 omp=False, push_only=False):
+                 drive_phase=(), drive_t_end=0.0, self_b=False, bz_ext=0.0, er_ext=0.0,
+                 sub_tol=0.0, omp=False, push_only=False):
         L_ = lib(omp)
         g = OgGrid()
         g.nr, g.nz, g.R, g.L, g.xi_a, g.dt, g.eps, g.mu = nr, nz, R, L, xi_a, dt, eps, mu
@@ -227,6 +228,7 @@ class Grid:
             g.drive_amp[k] = drive_amp[k]
             g.drive_freq[k] = drive_freq[k]
             g.drive_phase[k] = drive_phase[k] if k < len(drive_phase) else 0.0
+        g.drive_t_end = drive_t_end
         g.self_b = int(self_b)
         g.bz_ext, g.er_ext, g.sub_tol = bz_ext, er_ext, sub_tol
         g.push_only = int(push_only)

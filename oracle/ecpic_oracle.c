@@ -90,7 +90,8 @@ double og_xi_of_r(const og_ctx* c, double r) {
 
 double og_drive(const og_ctx* c, double t) {
   double v = 0.0;
-  for (int k = 0; k < c->g.n_drive && k < 2; ++k)
+  if (c->g.drive_t_end > 0.0 && t >= c->g.drive_t_end) return 0.0;
+  for (int k = 0; k < c->g.n_drive && k < OG_MAX_DRIVE; ++k)
     v += c->g.drive_amp[k] * sin(2.0 * OG_PI * c->g.drive_freq[k] * t + c->g.drive_phase[k]);
   return v;
 }

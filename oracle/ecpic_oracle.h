@@ -23,13 +23,17 @@
 extern "C" {
 #endif
 
+#define OG_MAX_DRIVE 32
+
 typedef struct {
   int32_t nr, nz;
   double R, L, xi_a;            /* radius, height [m]; axis map parameter   */
   double dt, eps, mu;           /* time step [s]; permittivity, permeability */
-  int32_t n_drive;              /* number of drive harmonics on the gap edge */
+  int32_t n_drive;              /* number of drive harmonics on the gap edge
+                                   (0..OG_MAX_DRIVE)                          */
   int32_t self_b;               /* test option: mu*h as B_theta on particles */
-  double drive_amp[2], drive_freq[2], drive_phase[2];
+  double drive_amp[OG_MAX_DRIVE], drive_freq[OG_MAX_DRIVE], drive_phase[OG_MAX_DRIVE];
+  double drive_t_end;           /* > 0: the drive is off from this time on    */
   double bz_ext;                /* test option: uniform external B_z [T]     */
   double er_ext;                /* test option: external E_r = er_ext*r/R    */
   double sub_tol;               /* inner fixed-point tolerance (0 -> 1e-14)  */

@@ -36,8 +36,8 @@ class GridDesc(C.Structure):
     _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("R", C.c_double), ("L", C.c_double),
                 ("xi_axis", C.c_double), ("dt", C.c_double), ("eps", C.c_double),
                 ("mu", C.c_double), ("n_drive", C.c_int32), ("reserved", C.c_int32),
-                ("drive_amp", C.c_double * 2), ("drive_freq", C.c_double * 2),
-                ("drive_phase", C.c_double * 2)]
+                ("drive_amp", C.c_double * 32), ("drive_freq", C.c_double * 32),
+                ("drive_phase", C.c_double * 32), ("drive_t_end", C.c_double)]
 
 
 class SpeciesDesc(C.Structure):
@@ -172,7 +172,7 @@ class Context:
     """One grid + its species on the current HIP device and torch stream."""
 
     def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
-                 drive_phase=(), precision: str = "fp64", device: str = "cuda"):
+                 drive_phase=(), drive_t_end=0.0, precision: str = "fp64", device: str = "cuda"):
         """The context allocates no device memory until its first device call;
         call :meth:`bind_workspace` after the last :meth:`add_species` to give
         it a torch-allocated region instead."""
@@ -188,6 +188,7 @@ class Context:
             g.drive_amp[k] = drive_amp[k]
             g.drive_freq[k] = drive_freq[k]
             g.drive_phase[k] = drive_phase[k] if k < len(drive_phase) else 0.0
+        g.drive_t_end = drive_t_end
         self.desc = g
         stream = torch.cuda.current_stream(self.device).cuda_stream
         h = _vp()

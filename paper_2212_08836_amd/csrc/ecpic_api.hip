@@ -36,7 +36,8 @@ ecpic_status fail(Ctx& c, ecpic_status s, const std::string& msg) {
 
 double drive(const ecpic_grid_desc& g, double t) {
   double v = 0.0;
-  for (int k = 0; k < g.n_drive && k < 2; ++k)
+  if (g.drive_t_end > 0.0 && t >= g.drive_t_end) return 0.0;
+  for (int k = 0; k < g.n_drive && k < 32; ++k)
     v += g.drive_amp[k] * std::sin(2.0 * kPi * g.drive_freq[k] * t + g.drive_phase[k]);
   return v;
 }
@@ -633,7 +634,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   *out = nullptr;
   if (g->nr < 1 || g->nz < 1 || !(g->R > 0) || !(g->L > 0) || !(g->dt > 0) || !(g->eps > 0) ||
       !(g->mu > 0) || !(g->xi_axis >= 0) || g->xi_axis > g->nr || g->n_drive < 0 ||
-      g->n_drive > 2 || (prec != ECPIC_FP64 && prec != ECPIC_MIXED) ||
+      g->n_drive > 32 || !(g->drive_t_end >= 0) || (prec != ECPIC_FP64 && prec != ECPIC_MIXED) ||
       (int64_t)g->nr * g->nz > (int64_t)1 << 28)
     return ECPIC_EINVAL;
   ecpic_ctx* x = new (std::nothrow) ecpic_ctx();
