@@ -59,7 +59,7 @@ class OgGrid(C.Structure):
                 ("drive_amp", C.c_double * 32), ("drive_freq", C.c_double * 32),
                 ("drive_phase", C.c_double * 32), ("drive_t_end", C.c_double),
                 ("bz_ext", C.c_double), ("er_ext", C.c_double),
-                ("sub_tol", C.c_double), ("push_only", C.c_int32), ("pad", C.c_int32)]
+                ("sub_tol", C.c_double), ("push_only", C.c_int32), ("model", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -219,7 +219,7 @@ class Grid:
 
     def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
                  drive_phase=(), drive_t_end=0.0, self_b=False, bz_ext=0.0, er_ext=0.0,
-                 sub_tol=0.0, omp=False, push_only=False):
+                 sub_tol=0.0, omp=False, push_only=False, model="em"):
         L_ = lib(omp)
         g = OgGrid()
         g.nr, g.nz, g.R, g.L, g.xi_a, g.dt, g.eps, g.mu = nr, nz, R, L, xi_a, dt, eps, mu
@@ -232,9 +232,11 @@ class Grid:
         g.self_b = int(self_b)
         g.bz_ext, g.er_ext, g.sub_tol = bz_ext, er_ext, sub_tol
         g.push_only = int(push_only)
+        g.model = {"em": 0, "es": 1}[model]
         self.desc = g
         self.nr, self.nz, self.R, self.L, self.xi_a, self.dt = nr, nz, R, L, xi_a, dt
         self.eps, self.mu = eps, mu
+        self.model = model
         h = C.c_void_p()
         rc = L_.og_create(C.byref(g), C.byref(h))
         if rc != 0:

@@ -54,8 +54,10 @@ struct og_ctx {
   double *wr;    /* eps*A*_r/ell of an interior r-edge, nr           */
   double *wz;    /* eps*A*_z/dz of a z-edge, nr                      */
   int64_t ncell; /* nr*nz                                            */
-  int32_t band;  /* Cholesky half bandwidth (= nz)                   */
-  double *chol;  /* banded lower factor, ncell*(band+1)              */
+  int64_t nunk;  /* unknowns of the factorised system: the cells     */
+                 /* (EM) or the free nodes nr*(nz-1) (ES)            */
+  int32_t band;  /* Cholesky half bandwidth (nz, or nz-1 for ES)     */
+  double *chol;  /* banded lower factor, nunk*(band+1)               */
   double *rhs, *x, *tr, *tz; /* work                                 */
 };
 
@@ -165,6 +167,8 @@ static void add_entry(og_ctx* c, int64_t a, int64_t bcol, double v) {
   LB(a, a - bcol) += v;
 }
 
+static int chol_factor(og_ctx* c);
+
 static int factorize(og_ctx* c) {
   const int nr = c->g.nr, nz = c->g.nz, b = c->band;
   const int64_t N = c->ncell;
@@ -200,6 +204,46 @@ static int factorize(og_ctx* c) {
         add_entry(c, HC(i - 1, j), HC(i, j), -mm * mi * dinv);
       }
     }
+  return chol_factor(c);
+}
+
+/* Electrostatic model (Sec. 2.2, Eq. (8)): the mapped Poisson operator on
+ * the free nodes (i, j), 0 <= i < nr, 0 < j < nz, in finite-integration
+ * form: (L phi)_n = sum over the edges e at node n of w_e (phi_n - phi_m),
+ * with w_e = eps A*_e / l_e, so that L phi is the Gauss charge of the edge
+ * voltages u = phi(start) - phi(end).  Plates, side wall and corners are
+ * Dirichlet nodes. */
+#define PN(i, j) ((int64_t)(i) * (nz - 1) + (j) - 1)
+
+static int factorize_es(og_ctx* c) {
+  const int nr = c->g.nr, nz = c->g.nz, b = c->band;
+  const int64_t N = c->nunk;
+  memset(c->chol, 0, sizeof(double) * (size_t)N * (size_t)(b + 1));
+  /* r-edges (i, j) -> (i+1, j) of the free rows j */
+  for (int i = 0; i < nr; ++i)
+    for (int j = 1; j < nz; ++j) {
+      const double w = c->wr[i];
+      add_entry(c, PN(i, j), PN(i, j), w);
+      if (i + 1 < nr) {
+        add_entry(c, PN(i + 1, j), PN(i + 1, j), w);
+        add_entry(c, PN(i, j), PN(i + 1, j), -w);
+      }
+    }
+  /* z-edges (i, j) -> (i, j+1) */
+  for (int i = 0; i < nr; ++i)
+    for (int j = 0; j < nz; ++j) {
+      const double w = c->wz[i];
+      const int lo_free = j >= 1, hi_free = j + 1 <= nz - 1;
+      if (lo_free) add_entry(c, PN(i, j), PN(i, j), w);
+      if (hi_free) add_entry(c, PN(i, j + 1), PN(i, j + 1), w);
+      if (lo_free && hi_free) add_entry(c, PN(i, j), PN(i, j + 1), -w);
+    }
+  return chol_factor(c);
+}
+
+static int chol_factor(og_ctx* c) {
+  const int b = c->band;
+  const int64_t N = c->nunk;
   /* In-place Cholesky (row-oriented), L stored in the band. */
   for (int64_t k = 0; k < N; ++k) {
     const int64_t m0 = k - b > 0 ? k - b : 0;
@@ -219,7 +263,7 @@ static int factorize(og_ctx* c) {
 
 static void chol_solve(og_ctx* c, const double* rhs, double* x) {
   const int b = c->band;
-  const int64_t N = c->ncell;
+  const int64_t N = c->nunk;
   for (int64_t k = 0; k < N; ++k) {
     double s = rhs[k];
     const int64_t p0 = k - b > 0 ? k - b : 0;
@@ -239,7 +283,8 @@ static void chol_solve(og_ctx* c, const double* rhs, double* x) {
 /* ------------------------------------------------------------------------ */
 int og_create(const og_grid* g, og_ctx** out) {
   if (!g || !out || g->nr < 1 || g->nz < 1 || !(g->R > 0) || !(g->L > 0) ||
-      !(g->dt > 0) || !(g->eps > 0) || !(g->mu > 0) || g->xi_a < 0 || g->xi_a > g->nr)
+      !(g->dt > 0) || !(g->eps > 0) || !(g->mu > 0) || g->xi_a < 0 || g->xi_a > g->nr ||
+      (g->model != OG_EM && g->model != OG_ES) || (g->model == OG_ES && g->nz < 2))
     return -1;
   og_ctx* c = (og_ctx*)calloc(1, sizeof(og_ctx));
   if (!c) return -2;
@@ -256,7 +301,8 @@ int og_create(const og_grid* g, og_ctx** out) {
   c->wr = (double*)calloc(nr, sizeof(double));
   c->wz = (double*)calloc(nr, sizeof(double));
   c->ncell = (int64_t)nr * nz;
-  c->band = nz;
+  c->nunk = g->model == OG_ES ? (int64_t)nr * (nz - 1) : c->ncell;
+  c->band = g->model == OG_ES ? nz - 1 : nz;
   c->chol = g->push_only ? (double*)malloc(sizeof(double))
                          : (double*)malloc(sizeof(double) * (size_t)c->ncell * (size_t)(nz + 1));
   c->rhs = (double*)malloc(sizeof(double) * (size_t)c->ncell);
@@ -279,7 +325,7 @@ int og_create(const og_grid* g, og_ctx** out) {
     c->wr[i] = g->eps * 2.0 * OG_PI * c->rh[i] * c->dz / c->ell[i];
     c->wz[i] = g->eps * c->azs[i] / c->dz;
   }
-  if (!g->push_only && factorize(c) != 0) {
+  if (!g->push_only && (g->model == OG_ES ? factorize_es(c) : factorize(c)) != 0) {
     og_destroy(c);
     return -3;
   }
@@ -318,10 +364,54 @@ static void set_boundary(const og_ctx* c, double* ur, double* uz, double vd) {
   ur[UR(nr - 1, 0)] = vd; /* drive gap between powered bottom plate and wall */
 }
 
+/* Electrostatic update (Sec. 2.2, Eq. (8)).  The deposit conserves charge,
+ * so the node charge after the step is Q^n - dt div I, and Poisson's
+ * equation for phi^{n+1} is the same as L (phi^{n+1} - phi^n) = -dt div I
+ * with the plate potential's change on the powered plate's nodes (the
+ * bottom nodes i < nr) and zero on the grounded ones.  Then
+ * u^{n+1} = u^n + (dphi(start) - dphi(end)) on every edge, and h = 0. */
+static void field_solve_es(og_ctx* c, const double* ur0, const double* uz0,
+                           const double* Ir, const double* Iz, double t,
+                           double* ur1, double* uz1, double* h1) {
+  const int nr = c->g.nr, nz = c->g.nz;
+  const double dt = c->g.dt;
+  const double dv = og_drive(c, t + dt) - og_drive(c, t);
+  double* b = c->rhs;
+  for (int i = 0; i < nr; ++i)
+    for (int j = 1; j < nz; ++j) {
+      double div = Ir[UR(i, j)] + Iz[UZ(i, j)] - Iz[UZ(i, j - 1)];
+      if (i > 0) div -= Ir[UR(i - 1, j)];
+      double v = -dt * div;
+      if (j == 1) v += c->wz[i] * dv; /* the powered plate below */
+      b[PN(i, j)] = v;
+    }
+  chol_solve(c, b, c->x);
+  /* dphi on every node, Dirichlet values included */
+  for (int i = 0; i < nr; ++i)
+    for (int j = 0; j <= nz; ++j) {
+      const double pa = (j == 0) ? dv : (j == nz ? 0.0 : c->x[PN(i, j)]);
+      const double pb = (i + 1 == nr) ? 0.0 : ((j == 0) ? dv : (j == nz ? 0.0 : c->x[PN(i + 1, j)]));
+      ur1[UR(i, j)] = ur0[UR(i, j)] + (pa - pb);
+    }
+  for (int i = 0; i <= nr; ++i)
+    for (int j = 0; j < nz; ++j) {
+      if (i == nr) { uz1[UZ(i, j)] = 0.0; continue; }
+      const double pa = (j == 0) ? dv : c->x[PN(i, j)];
+      const double pb = (j + 1 == nz) ? 0.0 : c->x[PN(i, j + 1)];
+      uz1[UZ(i, j)] = uz0[UZ(i, j)] + (pa - pb);
+    }
+  set_boundary(c, ur1, uz1, og_drive(c, t + dt));
+  for (int64_t k = 0; k < c->ncell; ++k) h1[k] = 0.0;
+}
+
 int og_field_solve(og_ctx* c, const double* ur0, const double* uz0, const double* h0,
                    const double* Ir, const double* Iz, double t,
                    double* ur1, double* uz1, double* h1) {
   if (c->g.push_only) return -5;
+  if (c->g.model == OG_ES) {
+    field_solve_es(c, ur0, uz0, Ir, Iz, t, ur1, uz1, h1);
+    return 0;
+  }
   const int nr = c->g.nr, nz = c->g.nz;
   const double dt = c->g.dt, mu = c->g.mu;
   const double vh = 0.5 * (og_drive(c, t) + og_drive(c, t + dt));
@@ -1180,8 +1270,20 @@ int og_step(og_ctx* c, og_state* st, og_species* sp, int32_t nsp, const og_mcc* 
       for (int j = 0; j < nz; ++j) wio += 0.5 * (st->uz[UZ(i, j)] + uz1[UZ(i, j)]) * Iz[UZ(i, j)];
     S->w_field_io = dt * wio;
     const double vh = 0.5 * (og_drive(c, t) + og_drive(c, t + dt));
-    const double hgap = 0.5 * (st->h[HC(nr - 1, 0)] + h1[HC(nr - 1, 0)]);
-    S->w_drive = dt * (2.0 * OG_PI * c->rh[nr - 1] * hgap * vh + vh * Ir[UR(nr - 1, 0)]);
+    if (c->g.model == OG_ES) {
+      /* the source's work: V^{1/2} times the charge it moves onto the
+       * powered plate's nodes (the change of their field flux plus the
+       * current leaving them into the domain), plus the gap edge's share */
+      double dq = 0.0, ip = 0.0;
+      for (int i = 0; i < nr; ++i) {
+        dq += c->wz[i] * (uz1[UZ(i, 0)] - st->uz[UZ(i, 0)]);
+        ip += Iz[UZ(i, 0)];
+      }
+      S->w_drive = vh * (dq + dt * ip) + dt * vh * Ir[UR(nr - 1, 0)];
+    } else {
+      const double hgap = 0.5 * (st->h[HC(nr - 1, 0)] + h1[HC(nr - 1, 0)]);
+      S->w_drive = dt * (2.0 * OG_PI * c->rh[nr - 1] * hgap * vh + vh * Ir[UR(nr - 1, 0)]);
+    }
   }
   if (mcc && mcc->enabled) {
     const int e = og_collide(c, sp, nsp, mcc, st->step, S);

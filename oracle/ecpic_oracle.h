@@ -40,8 +40,11 @@ typedef struct {
   int32_t push_only;            /* 1: no field solver (push passes only; the
                                    banded factorisation is skipped, and
                                    og_field_solve / og_step return -5)       */
-  int32_t pad;
+  int32_t model;                /* OG_EM (Eq. (2)) or OG_ES (Eq. (8))        */
 } og_grid;
+
+#define OG_EM 0
+#define OG_ES 1
 
 typedef struct {
   double q, m, w;               /* charge [C], mass [kg], macro weight       */
