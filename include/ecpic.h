@@ -63,6 +63,16 @@ typedef enum {
                       current accumulation, field solve, residual, energies */
 } ecpic_precision;
 
+/* Field model.  ECPIC_MODEL_EM: the TM Maxwell system (Sec. 2.1, Eq. (2)).
+ * ECPIC_MODEL_ES: the electrostatic version (Sec. 2.2, Eq. (8)): the field
+ * is the gradient of a potential that solves the mapped Poisson equation,
+ * here in its charge-conserving update form L (phi^{n+1} - phi^n) =
+ * -dt div I over the free nodes (0 <= i < nr, 0 < j < nz), with the drive
+ * voltage's change on the powered plate's nodes (the bottom nodes i < nr)
+ * and zero on the grounded top, side and corner; h stays zero.  Needs
+ * nz >= 2. */
+typedef enum { ECPIC_MODEL_EM = 0, ECPIC_MODEL_ES = 1 } ecpic_model;
+
 /* Grid, field constants and drive (Sec. 2.1: separable map r(xi), z(eta);
  * TM fields E_r, E_z, H_theta; PEC walls).  SI units. */
 typedef struct {
@@ -72,7 +82,7 @@ typedef struct {
   double dt;              /* time step [s]                                   */
   double eps, mu;         /* permittivity, permeability of the gap           */
   int32_t n_drive;        /* harmonics on the drive gap edge (0..32)         */
-  int32_t reserved;
+  int32_t model;          /* ecpic_model                                     */
   double drive_amp[32];   /* V(t) = sum amp sin(2 pi freq t + phase) [V]     */
   double drive_freq[32];
   double drive_phase[32];

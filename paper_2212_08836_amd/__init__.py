@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libecpic.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ecpic.h")
 
 ECPIC_FP64, ECPIC_MIXED = 0, 1
+ECPIC_MODEL_EM, ECPIC_MODEL_ES = 0, 1
 ECPIC_OPT_QUEUE_WAVES, ECPIC_OPT_NN_FORCE_FALLBACK = 0, 1
 ECPIC_OK, ECPIC_EINVAL, ECPIC_ENOMEM, ECPIC_EHIP, ECPIC_ENOTCONV = 0, -1, -2, -3, -4
 ECPIC_EPUSH, ECPIC_ECAPACITY, ECPIC_ERANGE, ECPIC_ENOTIMPL = -5, -6, -7, -8
@@ -35,7 +36,7 @@ class EcpicError(RuntimeError):
 class GridDesc(C.Structure):
     _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("R", C.c_double), ("L", C.c_double),
                 ("xi_axis", C.c_double), ("dt", C.c_double), ("eps", C.c_double),
-                ("mu", C.c_double), ("n_drive", C.c_int32), ("reserved", C.c_int32),
+                ("mu", C.c_double), ("n_drive", C.c_int32), ("model", C.c_int32),
                 ("drive_amp", C.c_double * 32), ("drive_freq", C.c_double * 32),
                 ("drive_phase", C.c_double * 32), ("drive_t_end", C.c_double)]
 
@@ -172,7 +173,8 @@ class Context:
     """One grid + its species on the current HIP device and torch stream."""
 
     def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
-                 drive_phase=(), drive_t_end=0.0, precision: str = "fp64", device: str = "cuda"):
+                 drive_phase=(), drive_t_end=0.0, precision: str = "fp64", device: str = "cuda",
+                 model: str = "em"):
         """The context allocates no device memory until its first device call;
         call :meth:`bind_workspace` after the last :meth:`add_species` to give
         it a torch-allocated region instead."""
@@ -189,6 +191,7 @@ class Context:
             g.drive_freq[k] = drive_freq[k]
             g.drive_phase[k] = drive_phase[k] if k < len(drive_phase) else 0.0
         g.drive_t_end = drive_t_end
+        g.model = {"em": ECPIC_MODEL_EM, "es": ECPIC_MODEL_ES}[model]
         self.desc = g
         stream = torch.cuda.current_stream(self.device).cuda_stream
         h = _vp()

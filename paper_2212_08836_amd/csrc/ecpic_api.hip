@@ -239,26 +239,55 @@ hipError_t setup_solver(Ctx& c) {
     const double Dr = 2.0 * wr[i] / dt;
     G[i] = mi * mi / Dr;
   }
-  // orthonormal DCT-II diagonalising the Neumann second difference
   std::vector<double> Q((size_t)nz * nz), Qt((size_t)nz * nz);
-  for (int k = 0; k < nz; ++k) {
-    const double a = (k == 0) ? std::sqrt(1.0 / nz) : std::sqrt(2.0 / nz);
-    for (int j = 0; j < nz; ++j) {
-      const double v = a * std::cos(kPi * k * (2.0 * j + 1.0) / (2.0 * nz));
-      Q[(size_t)k * nz + j] = v;
-      Qt[(size_t)j * nz + k] = v;
-    }
-  }
   std::vector<double> lo((size_t)nz * nr, 0.0), inv((size_t)nz * nr);
-  for (int k = 0; k < nz; ++k) {
-    const double lam = 2.0 - 2.0 * std::cos(kPi * k / nz);
-    double cp = Td[0] + lam * G[0];
-    inv[(size_t)k * nr] = 1.0 / cp;
-    for (int i = 1; i < nr; ++i) {
-      const double l = To[i] / cp;
-      cp = Td[i] + lam * G[i] - l * To[i];
-      lo[(size_t)k * nr + i] = l;
-      inv[(size_t)k * nr + i] = 1.0 / cp;
+  if (c.g.model == ECPIC_MODEL_ES) {
+    // Electrostatic model: the Poisson operator on the free nodes is
+    // W_r (x) I + diag(wz) (x) T_z with T_z the Dirichlet second difference
+    // over the nz - 1 free rows, diagonalised by the orthonormal DST-I
+    // S[j][k] = sqrt(2/nz) sin(pi (j+1)(k+1) / nz) (symmetric, its own
+    // inverse); per mode a tridiagonal system in r with the grounded side
+    // wall as the Dirichlet end.
+    const int nf = nz - 1;
+    for (int k = 0; k < nf; ++k)
+      for (int j = 0; j < nf; ++j) {
+        const double v = std::sqrt(2.0 / nz) * std::sin(kPi * (j + 1.0) * (k + 1.0) / nz);
+        Q[(size_t)k * nf + j] = v;
+        Qt[(size_t)j * nf + k] = v;
+      }
+    for (int i = 0; i < nr; ++i) To[i] = (i > 0) ? -wr[i - 1] : 0.0;
+    for (int k = 0; k < nf; ++k) {
+      const double lam = 2.0 - 2.0 * std::cos(kPi * (k + 1.0) / nz);
+      auto diag = [&](int i) { return wr[i] + (i > 0 ? wr[i - 1] : 0.0) + lam * wz[i]; };
+      double cp = diag(0);
+      inv[(size_t)k * nr] = 1.0 / cp;
+      for (int i = 1; i < nr; ++i) {
+        const double l = To[i] / cp;
+        cp = diag(i) - l * To[i];
+        lo[(size_t)k * nr + i] = l;
+        inv[(size_t)k * nr + i] = 1.0 / cp;
+      }
+    }
+  } else {
+    // orthonormal DCT-II diagonalising the Neumann second difference
+    for (int k = 0; k < nz; ++k) {
+      const double a = (k == 0) ? std::sqrt(1.0 / nz) : std::sqrt(2.0 / nz);
+      for (int j = 0; j < nz; ++j) {
+        const double v = a * std::cos(kPi * k * (2.0 * j + 1.0) / (2.0 * nz));
+        Q[(size_t)k * nz + j] = v;
+        Qt[(size_t)j * nz + k] = v;
+      }
+    }
+    for (int k = 0; k < nz; ++k) {
+      const double lam = 2.0 - 2.0 * std::cos(kPi * k / nz);
+      double cp = Td[0] + lam * G[0];
+      inv[(size_t)k * nr] = 1.0 / cp;
+      for (int i = 1; i < nr; ++i) {
+        const double l = To[i] / cp;
+        cp = Td[i] + lam * G[i] - l * To[i];
+        lo[(size_t)k * nr + i] = l;
+        inv[(size_t)k * nr + i] = 1.0 / cp;
+      }
     }
   }
   SolverDev& S = c.sol;
@@ -635,6 +664,8 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   if (g->nr < 1 || g->nz < 1 || !(g->R > 0) || !(g->L > 0) || !(g->dt > 0) || !(g->eps > 0) ||
       !(g->mu > 0) || !(g->xi_axis >= 0) || g->xi_axis > g->nr || g->n_drive < 0 ||
       g->n_drive > 32 || !(g->drive_t_end >= 0) || (prec != ECPIC_FP64 && prec != ECPIC_MIXED) ||
+      (g->model != ECPIC_MODEL_EM && g->model != ECPIC_MODEL_ES) ||
+      (g->model == ECPIC_MODEL_ES && g->nz < 2) ||
       (int64_t)g->nr * g->nz > (int64_t)1 << 28)
     return ECPIC_EINVAL;
   ecpic_ctx* x = new (std::nothrow) ecpic_ctx();
@@ -947,7 +978,8 @@ ecpic_status ecpic_field_solve(ecpic_ctx* x, const double* ur0, const double* uz
   a.Ir = const_cast<double*>(Ir);  // read only (no clear target)
   a.Iz = const_cast<double*>(Iz);
   a.vnext = drive(c.g, t + c.g.dt);
-  a.vhalf = 0.5 * (drive(c.g, t) + a.vnext);
+  a.vnow = drive(c.g, t);
+  a.vhalf = 0.5 * (a.vnow + a.vnext);
   a.ur1 = ur1;
   a.uz1 = uz1;
   a.h1 = h1;
@@ -977,7 +1009,8 @@ ecpic_status ecpic_field_solve_noalloc(ecpic_ctx* x, const double* ur0, const do
   a.Ir = const_cast<double*>(Ir);  // read only (no clear target)
   a.Iz = const_cast<double*>(Iz);
   a.vnext = drive(c.g, t + c.g.dt);
-  a.vhalf = 0.5 * (drive(c.g, t) + a.vnext);
+  a.vnow = drive(c.g, t);
+  a.vhalf = 0.5 * (a.vnow + a.vnext);
   a.ur1 = ur1;
   a.uz1 = uz1;
   a.h1 = h1;
@@ -1000,7 +1033,8 @@ static ecpic_status enqueue_solve(Ctx& c, int k, double tol, bool guarded, bool 
   a.Ir = c.Ir;
   a.Iz = c.Iz;
   a.vnext = drive(c.g, c.t + c.g.dt);
-  a.vhalf = 0.5 * (drive(c.g, c.t) + a.vnext);
+  a.vnow = drive(c.g, c.t);
+  a.vhalf = 0.5 * (a.vnow + a.vnext);
   a.ur1 = c.ur_nx;
   a.uz1 = c.uz_nx;
   a.h1 = c.h_nx;
@@ -1351,7 +1385,8 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
                              c.sol.partial + kOffEx, c.stream));
       spec_seq[k] = ++c.fin_seq;
       HIPCHK(launch_finalize(c, tally_set(c, k & 1), c.sol.partial + kOffEx, c.Ir_alt,
-                             wall_scratch(c, k & 1), spec_seq[k], tol_mode ? k : -1, c.stream));
+                             c.Iz_alt, wall_scratch(c, k & 1), spec_seq[k], tol_mode ? k : -1,
+                             c.stream));
     }
     return ECPIC_OK;
   };
@@ -1465,8 +1500,8 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
     HIPCHK(launch_exchange(c, c.ur, c.uz, c.ur_it, c.uz_it, c.Ir_alt, c.Iz_alt, d + kOffEx,
                            c.stream));
     seq = ++c.fin_seq;
-    HIPCHK(launch_finalize(c, tset, d + kOffEx, c.Ir_alt, wall_scratch(c, cset), seq, -1,
-                           c.stream));
+    HIPCHK(launch_finalize(c, tset, d + kOffEx, c.Ir_alt, c.Iz_alt, wall_scratch(c, cset), seq,
+                           -1, c.stream));
   }
   // field shift u^{n-1} <- u^n <- u^{n+1}.  Library buffers: by pointer
   // roles, at once (the summary kernels above hold the pointers they read),
@@ -1508,8 +1543,14 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   const double vh = 0.5 * (vnow + vnext);
   const double rgap = r_of_xi(c.m, c.g.nr - 0.5);
   S->w_field_io = c.g.dt * fin.xs;
-  S->w_drive = c.g.dt * (2.0 * kPi * rgap * 0.5 * (fin.h_gap_n + fin.h_gap_1) * vh +
-                         vh * fin.ir_gap);
+  if (c.g.model == ECPIC_MODEL_ES)
+    // the source's work: V^{1/2} times the charge it moves onto the powered
+    // plate (the change of the plate nodes' field flux and the current
+    // leaving them), plus the gap edge's share
+    S->w_drive = vh * (fin.qp_delta + c.g.dt * fin.iz_plate) + c.g.dt * vh * fin.ir_gap;
+  else
+    S->w_drive = c.g.dt * (2.0 * kPi * rgap * 0.5 * (fin.h_gap_n + fin.h_gap_1) * vh +
+                           vh * fin.ir_gap);
   S->w_particles = t.w_particles;
   S->w_absorbed = t.w_absorbed;
   S->w_coll = t.w_coll;

@@ -396,6 +396,159 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
   }
 }
 
+// Electrostatic model (Sec. 2.2, Eq. (8)), charge-conserving update form:
+// L dphi = -dt div I on the free nodes (i < nr, 0 < j < nz), with the
+// plate potential's step dv on the powered plate below (bottom nodes
+// i < nr) and zero on the grounded top, side wall and corner.  L is
+// W_r (x) I + diag(wz) (x) T_z (finite integration, weights eps A*/l), so
+// the same three-kernel scheme solves it with the DST-I over the nz - 1 free
+// rows in place of the DCT.
+//
+// rhs[i][j-1] = -dt (div I)(i, j) (+ wz_i dv next to the plate), then
+// hat[k][i] = sum_j S[j][k] rhs[i][j].
+__global__ void __launch_bounds__(kFB) k_es_rhs_dst(MapP m, const double* __restrict__ wz,
+                                                    const double* __restrict__ Ir,
+                                                    const double* __restrict__ Iz, double dv,
+                                                    const double* __restrict__ St,
+                                                    double* __restrict__ hat,
+                                                    const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  extern __shared__ double sh[];  // kRB rows of the right-hand side, then the part sums
+  const int nr = m.nr, nz = m.nz, nf = nz - 1;
+  const int i0 = blockIdx.x * kRB;
+  const int rows = min(kRB, nr - i0);
+  const int k0 = blockIdx.y * kCC;
+  const int nk = min(kCC, nf - k0);
+  for (int e = threadIdx.x; e < rows * nf; e += blockDim.x) {
+    const int r = e / nf, jj = e - r * nf, i = i0 + r, j = jj + 1;
+    const double* Irr = Ir + (int64_t)i * (nz + 1);
+    const double* Izr = Iz + (int64_t)i * nz;
+    double div = Irr[j] + Izr[j] - Izr[j - 1];
+    if (i > 0) div -= Irr[j - (nz + 1)];
+    double v = -m.dt * div;
+    if (j == 1) v += wz[i] * dv;
+    sh[r * nf + jj] = v;
+  }
+  __syncthreads();
+  double* psum = sh + kRB * nf;
+  dense_chunk<kRB>(St, nf, sh, nf, k0, nk, psum);
+  for (int e = threadIdx.x; e < nk * kRB; e += blockDim.x) {
+    const int kl = e / kRB, r = e - kl * kRB;
+    if (r < rows) hat[(int64_t)(k0 + kl) * nr + i0 + r] = chunk_total(psum, nk, r, kl, kRB);
+  }
+}
+
+// The inverse DST of the rows i0 .. i0+kRB (the last may be the grounded
+// wall row) over the block's nodes j0 .. j0+nj, then on the block's edges
+// u^{n+1} = u^n + dphi(start) - dphi(end), the next half-step field, the
+// residual partials, h^{n+1} = 0, and the reset of the consumed currents.
+// Edge ownership and partial layout are those of k_idct_recover.
+__global__ void __launch_bounds__(kFB) k_es_recover(SolveArgs a, MapP m,
+                                                    const double* __restrict__ wr,
+                                                    const double* __restrict__ wz,
+                                                    const double* __restrict__ S,
+                                                    const double* __restrict__ hat, double dv) {
+  if (a.stop && *a.stop) return;
+  constexpr int R1 = kRB + 1;  // rows i0 .. i0 + kRB
+  constexpr int XS = kCC + 1;  // node columns j0 .. j0 + nj
+  extern __shared__ double sh[];
+  const int nr = m.nr, nz = m.nz, nf = nz - 1;
+  const int i0 = blockIdx.x * kRB;
+  const int rows = min(kRB, nr - i0);
+  const int j0 = blockIdx.y * kCC;
+  const int nj = min(kCC, nz - j0);
+  // free rows among the block's nodes: jf_lo .. jf_hi (never empty: nz >= 2)
+  const int jf_lo = j0 > 1 ? j0 : 1;
+  const int jf_hi = (j0 + nj < nf) ? j0 + nj : nf;
+  const int nc = jf_hi - jf_lo + 1;
+  double* hs = sh;            // hat of the R1 rows, [r][k]
+  double* xs = sh + R1 * nf;  // dphi of the R1 rows, [r][j - j0]
+  double* psum = xs + R1 * XS;
+  __shared__ double red[2 * (kFB / 64)];
+  for (int e = threadIdx.x; e < R1 * nf; e += blockDim.x) {
+    const int k = e / R1, r = e - k * R1, i = i0 + r;
+    hs[r * nf + k] = (i < nr) ? hat[(int64_t)k * nr + i] : 0.0;
+  }
+  __syncthreads();
+  dense_chunk<R1>(S, nf, hs, nf, jf_lo - 1, nc, psum);
+  for (int e = threadIdx.x; e < R1 * (nj + 1); e += blockDim.x) {
+    const int r = e / (nj + 1), jn = e - r * (nj + 1), j = j0 + jn, i = i0 + r;
+    double x;
+    if (i >= nr || j == nz)
+      x = 0.0;  // grounded wall row, top plate (and the corners)
+    else if (j == 0)
+      x = dv;   // the powered plate
+    else
+      x = chunk_total(psum, nc, r, j - jf_lo, R1);
+    xs[r * XS + jn] = x;
+  }
+  __syncthreads();
+  double s0 = 0.0, s1 = 0.0;
+  const int ne = nj + (j0 + nj == nz ? 1 : 0);
+  for (int e = threadIdx.x; e < rows * ne; e += blockDim.x) {
+    const int r = e / ne, jn = e - r * ne, j = j0 + jn, i = i0 + r;
+    const int64_t g = (int64_t)i * (nz + 1) + j;
+    double v;
+    if (j == 0) {
+      v = (i == nr - 1) ? a.vnext : 0.0;
+    } else if (j == nz) {
+      v = 0.0;
+    } else {
+      v = a.ur0[g] + (xs[r * XS + jn] - xs[(r + 1) * XS + jn]);
+      if (a.part) {
+        const double w = wr[i];
+        const double d = v - a.ur_old[g];
+        s0 += w * d * d;
+        s1 += w * v * v;
+      }
+    }
+    a.ur1[g] = v;
+    if (a.ur_h) {
+      const double hv = 0.5 * (a.ur0[g] + v);
+      a.ur_h[g] = hv;
+      if (a.ur_hf) a.ur_hf[g] = float(hv);
+    }
+    if (a.Ir_clr) a.Ir_clr[g] = 0.0;
+  }
+  for (int e = threadIdx.x; e < rows * nj; e += blockDim.x) {
+    const int r = e / nj, jn = e - r * nj, j = j0 + jn, i = i0 + r;
+    const int64_t g = (int64_t)i * nz + j;
+    const double v = a.uz0[g] + (xs[r * XS + jn] - xs[r * XS + jn + 1]);
+    if (a.part) {
+      const double w = wz[i];
+      const double d = v - a.uz_old[g];
+      s0 += w * d * d;
+      s1 += w * v * v;
+    }
+    a.uz1[g] = v;
+    if (a.uz_h) {
+      const double hv = 0.5 * (a.uz0[g] + v);
+      a.uz_h[g] = hv;
+      if (a.uz_hf) a.uz_hf[g] = float(hv);
+    }
+    if (a.Iz_clr) a.Iz_clr[g] = 0.0;
+    a.h1[g] = 0.0;
+    if (i == nr - 1) {
+      const int64_t ew = (int64_t)nr * nz + j;
+      a.uz1[ew] = 0.0;
+      if (a.uz_h) {
+        const double hv = 0.5 * a.uz0[ew];
+        a.uz_h[ew] = hv;
+        if (a.uz_hf) a.uz_hf[ew] = float(hv);
+      }
+      if (a.Iz_clr) a.Iz_clr[ew] = 0.0;
+    }
+  }
+  if (a.part) {
+    block_sum2(s0, s1, red);
+    if (threadIdx.x == 0) {
+      const int b = blockIdx.y * gridDim.x + blockIdx.x;
+      a.part[2 * b] = s0;
+      a.part[2 * b + 1] = s1;
+    }
+  }
+}
+
 // Clear the per-pass queue counters, one tally set and one wall-charge
 // scratch set (thread t of nthreads).
 __device__ __forceinline__ void clear_pass_scratch(int64_t t, int64_t nthreads, int32_t* qcount,
@@ -616,6 +769,10 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
                                                  const double* __restrict__ hn,
                                                  const double* __restrict__ h1,
                                                  const double* __restrict__ Ir, int nr, int nz,
+                                                 const double* __restrict__ uzn,
+                                                 const double* __restrict__ uz1,
+                                                 const double* __restrict__ Iz,
+                                                 const double* __restrict__ wz, int es,
                                                  const double* __restrict__ wall_add,
                                                  double* __restrict__ wall_tot, uint64_t seq,
                                                  StepFinal* out, const int32_t* __restrict__ conv,
@@ -647,6 +804,18 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
   double xs = 0.0;
   for (int b = l; b < kRedBlocks; b += 64) xs += xpart[b];
   xs = wsum_d(xs);
+  double qp = 0.0, izp = 0.0;
+  if (es) {
+    // the powered plate's nodes (i, 0), i < nr: their field flux change and
+    // the current leaving them
+    for (int i = l; i < nr; i += 64) {
+      const int64_t e = (int64_t)i * nz;
+      qp += wz[i] * (uz1[e] - uzn[e]);
+      izp += Iz[e];
+    }
+    qp = wsum_d(qp);
+    izp = wsum_d(izp);
+  }
   if (wall_add && !rejected) {
     // the wall charge of a committing iteration joins the totals (the three
     // wall arrays are contiguous in both)
@@ -658,6 +827,8 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
     out->h_gap_n = hn[(int64_t)(nr - 1) * nz];
     out->h_gap_1 = h1[(int64_t)(nr - 1) * nz];
     out->ir_gap = Ir[(int64_t)(nr - 1) * (nz + 1)];
+    out->qp_delta = qp;
+    out->iz_plate = izp;
   }
   // every lane's stores are ordered before the sequence number
   __threadfence_system();
@@ -706,9 +877,11 @@ hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart, const double* Ir,
-                           const double* wall_add, uint64_t seq, int guard_k, hipStream_t s) {
+                           const double* Iz, const double* wall_add, uint64_t seq, int guard_k,
+                           hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, tally, xpart, c.h, c.h_it, Ir,
-                     c.g.nr, c.g.nz, wall_add, c.wall_bot, seq, c.fin_dev,
+                     c.g.nr, c.g.nz, c.uz, c.uz_it, Iz, c.sol.wz,
+                     c.g.model == ECPIC_MODEL_ES ? 1 : 0, wall_add, c.wall_bot, seq, c.fin_dev,
                      guard_k >= 0 ? (const int32_t*)c.stop : nullptr, guard_k);
   return hipGetLastError();
 }
@@ -751,6 +924,22 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s, double* 
   const int cb = col_blocks(nz);
   // residual partials: two per block of k_idct_recover
   if ((int64_t)row_blocks(nr) * cb > kResParts) return hipErrorInvalidValue;
+  if (c.g.model == ECPIC_MODEL_ES) {
+    const int nf = nz - 1;
+    if (nf < 1) return hipErrorInvalidValue;
+    const size_t lds_es_rhs = sizeof(double) * ((size_t)kRB * nf + (size_t)kFB * kRB);
+    const size_t lds_es_rec = sizeof(double) * ((size_t)(kRB + 1) * nf + (kRB + 1) * (kCC + 1) +
+                                                (size_t)kFB * (kRB + 1));
+    if (lds_es_rhs > 65536 || lds_es_rec > 65536) return hipErrorInvalidValue;
+    const double dv = a.vnext - a.vnow;
+    hipLaunchKernelGGL(k_es_rhs_dst, dim3(row_blocks(nr), col_blocks(nf)), dim3(kFB),
+                       lds_es_rhs, s, c.m, S.wz, a.Ir, a.Iz, dv, S.Qt, hat, a.stop);
+    hipLaunchKernelGGL(k_tri_scan, dim3(nf), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv, S.tri_up,
+                       hat, a.stop);
+    hipLaunchKernelGGL(k_es_recover, dim3(row_blocks(nr), cb), dim3(kFB), lds_es_rec, s, a, c.m,
+                       S.wr, S.wz, S.Q, hat, dv);
+    return hipGetLastError();
+  }
   // part sums: P * R * nc <= kFB * R for nc < kFB (chunks have at most kCC + 1 columns)
   const size_t lds_rhs = sizeof(double) * ((size_t)kRB * nz + (size_t)kFB * kRB);
   const size_t lds_rec = sizeof(double) * ((size_t)(kRB + 1) * nz + (kRB + 1) * (kCC + 1) +

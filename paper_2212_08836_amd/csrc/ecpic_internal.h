@@ -77,6 +77,11 @@ struct StepFinal {
   double h_gap_n;   // h^n at the drive-gap cell
   double h_gap_1;   // h^{n+1} at the drive-gap cell
   double ir_gap;    // I_r on the drive-gap edge
+  // electrostatic model: the change of the field flux leaving the powered
+  // plate's nodes, sum_i wz_i (uz^{n+1} - uz^n)[i][0], and the current
+  // leaving them, sum_i Iz[i][0] (the source's work)
+  double qp_delta;
+  double iz_plate;
   uint64_t seq;     // written last: the host polls it
 };
 
@@ -140,6 +145,7 @@ struct SolveArgs {
   const double *ur0, *uz0, *h0;
   double *Ir, *Iz;
   double vhalf, vnext;
+  double vnow;          // drive at t^n (the electrostatic model's plate step)
   double *ur1, *uz1, *h1;
   const double *ur_old, *uz_old;
   double* part;         // [2 * nr]: per row sum w (u1 - u_old)^2, sum w u1^2
@@ -352,7 +358,8 @@ inline double* wall_scratch(const Ctx& c, int p) { return c.wall_scr + p * wall_
 // kernel does nothing unless Picard iteration guard_k is the one the residual
 // kernel found converged (stop[1]), so it can be enqueued before that is known.
 hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart, const double* Ir,
-                           const double* wall_add, uint64_t seq, int guard_k, hipStream_t s);
+                           const double* Iz, const double* wall_add, uint64_t seq, int guard_k,
+                           hipStream_t s);
 hipError_t launch_zero_tally(const Ctx& c, hipStream_t s);
 // the value a residual slot holds until the device has written it
 constexpr uint64_t kResPending = 0x7ff4dead0badf00dull;

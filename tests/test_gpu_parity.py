@@ -94,14 +94,15 @@ def _cmp_species(gpu, ora, what=""):
     return worst
 
 
-def _make_pair(w, og, P, parts, precision="fp64", extra_cap=0.3, mobile=(True, True)):
-    g = og.grid_from_workload(w)
+def _make_pair(w, og, P, parts, precision="fp64", extra_cap=0.3, mobile=(True, True),
+               model="em"):
+    g = og.grid_from_workload(w, model=model)
     sp = []
     for k, d in enumerate(parts):
         n = len(d["r"])
         sp.append(g.species(d, cap=int(n * (1 + extra_cap)) + 256, role=k + 1,
                             mobile=mobile[k]))
-    ctx = P.context_from_workload(w, precision=precision)
+    ctx = P.context_from_workload(w, precision=precision, model=model)
     P.load_workload_species(ctx, parts, extra_cap=extra_cap, mobile=mobile)
     return g, sp, ctx
 
@@ -325,13 +326,13 @@ def test_step_parity_edge_cases(og, torch_cuda):
 
 
 def _step_parity(og, P, w, parts, nsteps, mcc=None, sort_every=0, mobile=(True, True),
-                 running_scale=False):
+                 running_scale=False, model="em"):
     """Steps on both sides with the oracle's iteration counts.  Fields are
     compared against their largest value in this step, or with running_scale
     in any step so far (for runs whose drive is switched off: the fields then
     fall to the plasma's response and keep the absolute rounding of the
     driven steps)."""
-    g, sp, ctx = _make_pair(w, og, P, parts, mobile=mobile)
+    g, sp, ctx = _make_pair(w, og, P, parts, mobile=mobile, model=model)
     st = og.State(g)
     if mcc:
         ctx.set_mcc(mcc)

@@ -70,12 +70,12 @@ def test_cold_slab_first_pass_currents(og, torch_cuda):
     assert _currents_ok((Irg, Izg), (Iro, Izo), w, [parts[0]], "cold slab first pass")
 
 
-def _gpu_ring(torch, P, w, c_factor):
+def _gpu_ring(torch, P, w, c_factor, model="em"):
     """Run the cavity on the GPU; the E_z edge voltages 1 mm from each plate
     after every step, gathered on the device from the bound field tensors."""
     dev = torch.device("cuda")
     f64 = torch.float64
-    ctx = P.context_from_workload(w, mu=E.MU0 / c_factor ** 2)
+    ctx = P.context_from_workload(w, mu=E.MU0 / c_factor ** 2, model=model)
     P.load_workload_species(ctx, E.slab_particles(w), mobile=(True, False))
     nr, nz = w.nr, w.nz
     ur = torch.zeros(nr * (nz + 1), dtype=f64, device=dev)
@@ -114,6 +114,8 @@ def rings(og, torch_cuda):
     for cf in (1.0, 10.0, 100.0):
         _flush(f"surface-mode cavity 64 x 100, {w.steps} steps, c* = {cf:g} c")
         out[cf] = _gpu_ring(torch_cuda, P, w, cf)
+    _flush(f"surface-mode cavity 64 x 100, {w.steps} steps, electrostatic model")
+    out["es"] = _gpu_ring(torch_cuda, P, w, 1.0, model="es")
     return w, r, out
 
 
@@ -145,6 +147,24 @@ def test_lines_follow_the_dispersion_relation(rings, cf):
             bad.append((m, fam))
         worst = max(worst, abs(got / want - 1.0))
     _flush(f"  worst relative line offset {worst:.4f}")
+    assert not bad, bad
+
+
+def test_electrostatic_model_lines_follow_eq10(rings):
+    """The same cavity with the electrostatic model (Sec. 2.2): its lines
+    sit on Eq. (10)."""
+    w, r, out = rings
+    bot, top = out["es"]
+    bad = []
+    for m, fam in _LINES:
+        k = sm.bessel_zeros(0, m)[m - 1] / w.R
+        want = sm.es_frequency(k, w.n0, w.gap, w.L / 2, fam)
+        got = _line(w, r, bot, top, m, fam)
+        _flush(f"  ES m={m} {fam:13s}: PIC {got / 2e6 / math.pi:8.2f} MHz, "
+               f"Eq.(10) {want / 2e6 / math.pi:8.2f}")
+        tol = 0.01 if m == 1 else 0.025
+        if not abs(got / want - 1.0) < tol:
+            bad.append((m, fam))
     assert not bad, bad
 
 
