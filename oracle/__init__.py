@@ -79,7 +79,8 @@ class OgState(C.Structure):
 
 
 class OgOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("fixed_iter", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("fixed_iter", C.c_int32),
+                ("solver", C.c_int32), ("krylov", C.c_int32), ("eta", C.c_double)]
 
 
 class OgMcc(C.Structure):
@@ -95,7 +96,8 @@ class OgStats(C.Structure):
                 ("w_absorbed", C.c_double), ("w_coll", C.c_double),
                 ("n_absorbed", C.c_int64 * 4), ("n_coll", C.c_int64 * 4), ("n_ionized", C.c_int64),
                 ("n_substeps", C.c_int64), ("n_crossings", C.c_int64), ("n_halvings", C.c_int64),
-                ("n_errors", C.c_int64), ("n_capped", C.c_int64), ("n_over_range", C.c_int64)]
+                ("n_errors", C.c_int64), ("n_capped", C.c_int64), ("n_over_range", C.c_int64),
+                ("newton_iters", C.c_int32), ("krylov_iters", C.c_int32)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -348,10 +350,11 @@ class Grid:
                        mobile=mobile, cap=cap, role=role)
 
     def step(self, state: State, species: List[Species], mcc: Optional[dict] = None,
-             tol=1e-10, max_iter=50, fixed_iter=0) -> dict:
+             tol=1e-10, max_iter=50, fixed_iter=0, solver="picard", krylov=10,
+             eta=1e-4) -> dict:
         arr = (OgSpecies * len(species))(*[s.struct() for s in species])
         stc = state.struct()
-        o = OgOpts(tol, max_iter, fixed_iter)
+        o = OgOpts(tol, max_iter, fixed_iter, {"picard": 0, "jfnk": 1}[solver], krylov, eta)
         m = make_mcc(mcc)
         st = OgStats()
         rc = self._lib.og_step(self._h, C.byref(stc), arr, len(species),

@@ -1189,6 +1189,160 @@ int og_collide(og_ctx* c, og_species* sp, int32_t nsp, const og_mcc* m, int64_t 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Jacobian-free Newton-Krylov solve of the same system (Sec. 2.1 names     */
+/* JFNK beside Picard).  The unknown is the edge-voltage iterate X = u^{n+1} */
+/* and the residual F(X) = X - G(X), where G is one Picard map: push every   */
+/* species in the half-step field (u^n + X)/2, deposit, and solve the field  */
+/* equations from u^n with that current.  Newton: J d = -F with J = I - G',  */
+/* J v taken by the forward difference (G(X + e v) - G(X)) / e, e =         */
+/* sqrt(eps_mach) max(|X|, |F|) / |v| in the energy norm, and solved by     */
+/* GMRES (Arnoldi with modified Gram-Schmidt in the energy inner product,   */
+/* Givens rotations), from d = 0, without restarts.  In tolerance mode the  */
+/* step X + l d is taken with l halved (at most 8 times) until |F| falls by */
+/* the factor 1 - 1e-4 l (backtracking); with a fixed count, l = 1.         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  og_ctx* c;
+  og_state* st;
+  og_species* sp;
+  int32_t nsp;
+  double *urh, *uzh, *hh, *Ir, *Iz; /* work: half field and currents */
+  int64_t evals;
+} jfnk_ctx;
+
+/* energy inner product over the interior edges (the weights of the
+ * residual norm); a vector is ur (nr*(nz+1)) followed by uz ((nr+1)*nz) */
+static double wdot(const og_ctx* c, const double* a, const double* b) {
+  const int nr = c->g.nr, nz = c->g.nz;
+  const int64_t nur = (int64_t)nr * (nz + 1);
+  double s = 0.0;
+  for (int i = 0; i < nr; ++i)
+    for (int j = 1; j < nz; ++j) s += c->wr[i] * a[UR(i, j)] * b[UR(i, j)];
+  for (int i = 0; i < nr; ++i)
+    for (int j = 0; j < nz; ++j) s += c->wz[i] * a[nur + UZ(i, j)] * b[nur + UZ(i, j)];
+  return s;
+}
+
+/* G(X): the Picard map; X and the result are [ur | uz], h into gh */
+static void picard_map(jfnk_ctx* J, const double* X, double* GX, double* gh) {
+  og_ctx* c = J->c;
+  const int nr = c->g.nr, nz = c->g.nz;
+  const int64_t nur = (int64_t)nr * (nz + 1), nuz = (int64_t)(nr + 1) * nz;
+  for (int64_t e = 0; e < nur; ++e) J->urh[e] = 0.5 * (J->st->ur[e] + X[e]);
+  for (int64_t e = 0; e < nuz; ++e) J->uzh[e] = 0.5 * (J->st->uz[e] + X[nur + e]);
+  memcpy(J->hh, J->st->h, sizeof(double) * c->ncell);
+  memset(J->Ir, 0, sizeof(double) * nur);
+  memset(J->Iz, 0, sizeof(double) * nuz);
+  for (int s = 0; s < J->nsp; ++s)
+    og_push_deposit(c, &J->sp[s], J->urh, J->uzh, J->hh, 0, J->Ir, J->Iz, NULL, NULL);
+  og_field_solve(c, J->st->ur, J->st->uz, J->st->h, J->Ir, J->Iz, J->st->t, GX, GX + nur, gh);
+  J->evals++;
+}
+
+/* Newton iterations from X (in place).  Returns 1 when converged (or the
+ * fixed count is done), 0 otherwise; GX and gh hold G(X) of the accepted X,
+ * and J->urh/uzh its half field. */
+static int jfnk_solve(jfnk_ctx* J, const og_opts* o, double* X, double* GX, double* gh,
+                      og_stats* S) {
+  og_ctx* c = J->c;
+  const int nr = c->g.nr, nz = c->g.nz;
+  const int64_t n = (int64_t)nr * (nz + 1) + (int64_t)(nr + 1) * nz;
+  const int m = o->krylov;
+  const int fixed = o->fixed_iter > 0;
+  const int nmax = fixed ? o->fixed_iter : o->max_iter;
+  double* F = (double*)malloc(sizeof(double) * n);
+  double* V = (double*)malloc(sizeof(double) * n * (m + 1));
+  double* Y = (double*)malloc(sizeof(double) * n);
+  double* GY = (double*)malloc(sizeof(double) * n);
+  double* W = (double*)malloc(sizeof(double) * n);
+  double* D = (double*)malloc(sizeof(double) * n);
+  double* hy = (double*)malloc(sizeof(double) * c->ncell);
+  double H[OG_MAX_KRYLOV + 1][OG_MAX_KRYLOV];
+  double cs[OG_MAX_KRYLOV], sn[OG_MAX_KRYLOV], g[OG_MAX_KRYLOV + 1], y[OG_MAX_KRYLOV];
+  int conv = 0;
+  if (!F || !V || !Y || !GY || !W || !D || !hy) goto out;
+  picard_map(J, X, GX, gh);
+  for (int64_t e = 0; e < n; ++e) F[e] = X[e] - GX[e];
+  double fn = sqrt(wdot(c, F, F)), gn = sqrt(wdot(c, GX, GX));
+  for (int k = 0; k < nmax; ++k) {
+    const double r = gn > 0.0 ? fn / gn : (fn > 0.0 ? INFINITY : 0.0);
+    S->residual[k] = r;
+    S->newton_iters = k + 1;
+    if (fixed ? (k == nmax - 1) : (r <= o->tol)) { conv = 1; break; }
+    if (!(fn > 0.0)) { conv = 1; break; }
+    /* GMRES on J d = -F from d = 0 */
+    const double xn = sqrt(wdot(c, X, X));
+    const double eps = 1.4901161193847656e-08 * (xn > fn ? xn : fn);
+    for (int64_t e = 0; e < n; ++e) V[e] = -F[e] / fn;
+    g[0] = fn;
+    int used = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + (int64_t)j * n;
+      for (int64_t e = 0; e < n; ++e) Y[e] = X[e] + eps * vj[e];
+      picard_map(J, Y, GY, hy);
+      for (int64_t e = 0; e < n; ++e) W[e] = vj[e] - (GY[e] - GX[e]) / eps;
+      for (int i = 0; i <= j; ++i) {
+        const double* vi = V + (int64_t)i * n;
+        H[i][j] = wdot(c, W, vi);
+        for (int64_t e = 0; e < n; ++e) W[e] -= H[i][j] * vi[e];
+      }
+      H[j + 1][j] = sqrt(wdot(c, W, W));
+      double* vn = V + (int64_t)(j + 1) * n;
+      for (int64_t e = 0; e < n; ++e) vn[e] = H[j + 1][j] > 0.0 ? W[e] / H[j + 1][j] : 0.0;
+      /* previous rotations on the new column, then its own */
+      for (int i = 0; i < j; ++i) {
+        const double a = H[i][j], b = H[i + 1][j];
+        H[i][j] = cs[i] * a + sn[i] * b;
+        H[i + 1][j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = H[j][j], b = H[j + 1][j];
+      const double d = sqrt(a * a + b * b);
+      cs[j] = d > 0.0 ? a / d : 1.0;
+      sn[j] = d > 0.0 ? b / d : 0.0;
+      H[j][j] = d;
+      H[j + 1][j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      used = j + 1;
+      S->krylov_iters++;
+      if (!fixed && fabs(g[j + 1]) <= o->eta * fn) break;
+    }
+    /* back substitution: d = sum y_i V_i */
+    for (int i = used - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int q = i + 1; q < used; ++q) s -= H[i][q] * y[q];
+      y[i] = s / H[i][i];
+    }
+    memset(D, 0, sizeof(double) * n);
+    for (int i = 0; i < used; ++i) {
+      const double* vi = V + (int64_t)i * n;
+      for (int64_t e = 0; e < n; ++e) D[e] += y[i] * vi[e];
+    }
+    /* the step, backtracking in tolerance mode; the trial's map is the next
+     * residual evaluation */
+    double lam = 1.0;
+    for (int ls = 0;; ++ls) {
+      for (int64_t e = 0; e < n; ++e) Y[e] = X[e] + lam * D[e];
+      picard_map(J, Y, GY, gh);
+      for (int64_t e = 0; e < n; ++e) W[e] = Y[e] - GY[e];
+      const double fy = sqrt(wdot(c, W, W));
+      if (fixed || ls == 8 || fy <= (1.0 - 1e-4 * lam) * fn) {
+        memcpy(X, Y, sizeof(double) * n);
+        memcpy(GX, GY, sizeof(double) * n);
+        memcpy(F, W, sizeof(double) * n);
+        fn = fy;
+        gn = sqrt(wdot(c, GX, GX));
+        break;
+      }
+      lam *= 0.5;
+    }
+  }
+out:
+  free(F); free(V); free(Y); free(GY); free(W); free(D); free(hy);
+  return conv;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One implicit step (Picard iteration of the coupled system, Sec. 2.1)      */
 /* ------------------------------------------------------------------------ */
 int og_step(og_ctx* c, og_state* st, og_species* sp, int32_t nsp, const og_mcc* mcc,
@@ -1229,6 +1383,30 @@ int og_step(og_ctx* c, og_state* st, og_species* sp, int32_t nsp, const og_mcc* 
   int kmax = o->fixed_iter > 0 ? o->fixed_iter : o->max_iter;
   if (kmax > 64) kmax = 64;
   S->converged = 0;
+  if (o->solver == OG_JFNK) {
+    if (o->krylov < 1 || o->krylov > OG_MAX_KRYLOV || c->g.self_b) { rc = -1; goto done; }
+    const int64_t nv = nur + nuz;
+    double* X = (double*)malloc(sizeof(double) * nv);
+    double* GX = (double*)malloc(sizeof(double) * nv);
+    if (!X || !GX) { free(X); free(GX); rc = -2; goto done; }
+    memcpy(X, ur1, sizeof(double) * nur);
+    memcpy(X + nur, uz1, sizeof(double) * nuz);
+    jfnk_ctx J = {c, st, sp, nsp, urh, uzh, hh, Ir, Iz, 0};
+    og_opts oo = *o;
+    oo.max_iter = kmax;
+    const int ok = jfnk_solve(&J, &oo, X, GX, h1, S);
+    /* the accepted iterate: fields G(X), particles pushed in (u^n + X)/2
+     * (left in urh, uzh by the last evaluation of G at X) */
+    memcpy(ur1, GX, sizeof(double) * nur);
+    memcpy(uz1, GX + nur, sizeof(double) * nuz);
+    free(X);
+    free(GX);
+    k = (int)J.evals;
+    S->converged = ok;
+    S->iters = k;
+    if (!ok) { rc = -4; goto done; }
+    goto accepted;
+  }
   for (k = 0; k < kmax; ++k) {
     for (int64_t e = 0; e < nur; ++e) urh[e] = 0.5 * (st->ur[e] + ur1[e]);
     for (int64_t e = 0; e < nuz; ++e) uzh[e] = 0.5 * (st->uz[e] + uz1[e]);
@@ -1250,6 +1428,7 @@ int og_step(og_ctx* c, og_state* st, og_species* sp, int32_t nsp, const og_mcc* 
   S->iters = k;
   if (o->fixed_iter > 0) S->converged = 1;
   if (!S->converged) { rc = -4; goto done; }
+accepted:
   /* commit the particles from the last push (field urh, uzh, hh) and
    * account the energy exchanged with the field on both sides */
   memset(Ir, 0, sizeof(double) * nur);

@@ -66,9 +66,20 @@ typedef struct {
 
 typedef struct {
   double tol;                   /* relative energy-norm update tolerance     */
-  int32_t max_iter;             /* Picard iterations allowed (<=64)          */
+  int32_t max_iter;             /* Picard iterations (JFNK: Newton residual
+                                   evaluations) allowed (<=64)               */
   int32_t fixed_iter;           /* >0: run exactly this many iterations      */
+  int32_t solver;               /* OG_PICARD or OG_JFNK                      */
+  int32_t krylov;               /* JFNK: GMRES iterations per Newton step
+                                   (1..OG_MAX_KRYLOV; all of them when
+                                   fixed_iter > 0)                           */
+  double eta;                   /* JFNK: GMRES stops at eta * |F| (tolerance
+                                   mode)                                     */
 } og_opts;
+
+#define OG_PICARD 0
+#define OG_JFNK 1
+#define OG_MAX_KRYLOV 32
 
 typedef struct {
   int32_t enabled;
@@ -95,6 +106,10 @@ typedef struct {
   int64_t n_ionized;
   int64_t n_substeps, n_crossings, n_halvings, n_errors, n_capped;
   int64_t n_over_range;         /* particles beyond the nu_max bound         */
+  int32_t newton_iters;         /* JFNK: Newton residual evaluations (the
+                                   residual[] entries); iters counts every
+                                   push pass of the iteration               */
+  int32_t krylov_iters;         /* JFNK: GMRES iterations in all             */
 } og_stats;
 
 typedef struct og_ctx og_ctx;
