@@ -121,7 +121,31 @@ typedef struct {
                              the step's statistics (one node-charge pass
                              over the particles per step, plus one at the
                              first checked step)                             */
+  int32_t solver;         /* ecpic_solver: the nonlinear iteration            */
+  int32_t krylov;         /* JFNK: GMRES iterations per Newton step, 1 up to
+                             the space reserved with ECPIC_OPT_JFNK_KRYLOV
+                             (all of them when fixed_iter > 0)               */
+  double eta;             /* JFNK: GMRES stops once its residual estimate is
+                             <= eta |F| (tolerance mode)                     */
 } ecpic_step_opts;
+
+/* The nonlinear iteration of the step (Sec. 2.1 names both).
+ * ECPIC_SOLVER_PICARD: u^{(k+1)} = G(u^{(k)}), where G pushes every species
+ * in (u^n + u^{(k)}) / 2, deposits, and solves the field equations.
+ * ECPIC_SOLVER_JFNK: Newton on F(u) = u - G(u): J d = -F with J = I - G',
+ * J v by the forward difference (G(u + e v) - G(u)) / e with
+ * e = 1e-6 max(|u|, |F|) / |v| in the energy norm (G carries the
+ * deposit's rounding and the 1e-14 inner-solve tolerance: a relative step of
+ * sqrt(eps_mach) leaves the Krylov directions after the first mostly
+ * noise), GMRES from
+ * d = 0 (Arnoldi by classical Gram-Schmidt applied twice, energy inner
+ * product, Givens rotations, no restart), and in tolerance mode the step
+ * u + l d with l halved at most 8 times until |F| falls by 1 - 1e-4 l.
+ * max_iter / fixed_iter count Newton residual evaluations; stats.iters
+ * counts every push pass (each evaluation of G), stats.residual holds the
+ * Newton residuals |F| / |G(u)|.  The accepted state is that of Picard:
+ * fields G(u), particles pushed in (u^n + u) / 2. */
+typedef enum { ECPIC_SOLVER_PICARD = 0, ECPIC_SOLVER_JFNK = 1 } ecpic_solver;
 
 typedef struct {
   int32_t iters, converged;
@@ -152,6 +176,9 @@ typedef struct {
                              = div of the displacement flux eps Ad u / l,
                              Ad the dual-face area of an edge of length l   */
   double q_max;           /* max |Q_p^{n+1}|, the scale of the two above     */
+  int32_t newton_iters;   /* JFNK: Newton residual evaluations (entries of
+                             residual[]); 0 for Picard                       */
+  int32_t krylov_iters;   /* JFNK: GMRES iterations over the step            */
 } ecpic_step_stats;
 
 typedef struct ecpic_ctx ecpic_ctx;
@@ -398,12 +425,19 @@ typedef enum {
                                 build for three wavefronts per SIMD from 16M
                                 particles per pass, else two), 2 or 3 = that
                                 build always                                 */
-  ECPIC_OPT_NN_FORCE_FALLBACK = 1 /* test switch for the learned guess's
+  ECPIC_OPT_NN_FORCE_FALLBACK = 1, /* test switch for the learned guess's
                                 fallback: k >= 1 makes a step that uses the
                                 learned guess treat residual k as not falling
                                 (the fallback to the extrapolated guess is
                                 then taken at iteration k, as for a real rise);
                                 0 = off (the default)                        */
+  ECPIC_OPT_JFNK_KRYLOV = 2  /* Krylov vectors reserved for the JFNK solver,
+                                0..32 (default 0: JFNK unavailable).  Adds
+                                (value + 7) field-sized vectors to the device
+                                layout, so it must be set before the device
+                                memory is set up (before ecpic_workspace_size
+                                and ecpic_bind_workspace, or the first call
+                                that touches the device); later: EINVAL      */
 } ecpic_option;
 /* Set a switch.  EINVAL for an unknown option or value. */
 ecpic_status ecpic_set_option(ecpic_ctx* ctx, int32_t option, int64_t value);

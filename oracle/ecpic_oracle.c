@@ -1195,12 +1195,18 @@ int og_collide(og_ctx* c, og_species* sp, int32_t nsp, const og_mcc* m, int64_t 
 /* species in the half-step field (u^n + X)/2, deposit, and solve the field  */
 /* equations from u^n with that current.  Newton: J d = -F with J = I - G',  */
 /* J v taken by the forward difference (G(X + e v) - G(X)) / e, e =         */
-/* sqrt(eps_mach) max(|X|, |F|) / |v| in the energy norm, and solved by     */
+/* 1e-6 max(|X|, |F|) / |v| in the energy norm (G carries the rounding of   */
+/* the deposit and the 1e-14 inner-solve tolerance, so a difference over a  */
+/* relative step of sqrt(eps_mach) is mostly noise beyond the first Krylov  */
+/* direction; 1e-6 keeps that noise near 1e-8 of |v| while G is nearly      */
+/* linear in u over such a step), and solved by                             */
 /* GMRES (Arnoldi with modified Gram-Schmidt in the energy inner product,   */
 /* Givens rotations), from d = 0, without restarts.  In tolerance mode the  */
 /* step X + l d is taken with l halved (at most 8 times) until |F| falls by */
 /* the factor 1 - 1e-4 l (backtracking); with a fixed count, l = 1.         */
 /* ------------------------------------------------------------------------ */
+#define OG_JF_DIFF 1e-6
+
 typedef struct {
   og_ctx* c;
   og_state* st;
@@ -1272,7 +1278,7 @@ static int jfnk_solve(jfnk_ctx* J, const og_opts* o, double* X, double* GX, doub
     if (!(fn > 0.0)) { conv = 1; break; }
     /* GMRES on J d = -F from d = 0 */
     const double xn = sqrt(wdot(c, X, X));
-    const double eps = 1.4901161193847656e-08 * (xn > fn ? xn : fn);
+    const double eps = OG_JF_DIFF * (xn > fn ? xn : fn);
     for (int64_t e = 0; e < n; ++e) V[e] = -F[e] / fn;
     g[0] = fn;
     int used = 0;

@@ -20,7 +20,9 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "ecpic.h")
 
 ECPIC_FP64, ECPIC_MIXED = 0, 1
 ECPIC_MODEL_EM, ECPIC_MODEL_ES = 0, 1
-ECPIC_OPT_QUEUE_WAVES, ECPIC_OPT_NN_FORCE_FALLBACK = 0, 1
+ECPIC_OPT_QUEUE_WAVES, ECPIC_OPT_NN_FORCE_FALLBACK, ECPIC_OPT_JFNK_KRYLOV = 0, 1, 2
+ECPIC_SOLVER_PICARD, ECPIC_SOLVER_JFNK = 0, 1
+_SOLVERS = {"picard": ECPIC_SOLVER_PICARD, "jfnk": ECPIC_SOLVER_JFNK}
 ECPIC_OK, ECPIC_EINVAL, ECPIC_ENOMEM, ECPIC_EHIP, ECPIC_ENOTCONV = 0, -1, -2, -3, -4
 ECPIC_EPUSH, ECPIC_ECAPACITY, ECPIC_ERANGE, ECPIC_ENOTIMPL = -5, -6, -7, -8
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "EPUSH",
@@ -55,7 +57,8 @@ class MccDesc(C.Structure):
 class StepOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("fixed_iter", C.c_int32),
                 ("sort_every", C.c_int32), ("use_nn", C.c_int32),
-                ("check_conservation", C.c_int32)]
+                ("check_conservation", C.c_int32), ("solver", C.c_int32),
+                ("krylov", C.c_int32), ("eta", C.c_double)]
 
 
 class FieldView(C.Structure):
@@ -72,7 +75,8 @@ class StepStats(C.Structure):
                 ("n_coll", C.c_int64 * 4), ("n_ionized", C.c_int64), ("n_substeps", C.c_int64),
                 ("n_crossings", C.c_int64), ("n_errors", C.c_int64), ("n_over_range", C.c_int64),
                 ("t", C.c_double), ("step", C.c_int64), ("continuity_max", C.c_double),
-                ("gauss_max", C.c_double), ("q_max", C.c_double)]
+                ("gauss_max", C.c_double), ("q_max", C.c_double),
+                ("newton_iters", C.c_int32), ("krylov_iters", C.c_int32)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -371,8 +375,10 @@ class Context:
         self._check(self.L.ecpic_collide(self.h, C.byref(d), int(step)), self.h)
 
     def step(self, tol=1e-10, max_iter=50, fixed_iter=0, sort_every=0, use_nn=False,
-             stats=True, check=True, conservation=False):
-        o = StepOpts(tol, max_iter, fixed_iter, sort_every, int(use_nn), int(conservation))
+             stats=True, check=True, conservation=False, solver="picard", krylov=10,
+             eta=1e-4):
+        o = StepOpts(tol, max_iter, fixed_iter, sort_every, int(use_nn), int(conservation),
+                     _SOLVERS[solver], krylov, eta)
         if stats:
             s = StepStats()
             rc = self.L.ecpic_step(self.h, C.byref(o), C.byref(s))
@@ -386,10 +392,12 @@ class Context:
         return d
 
     def run(self, n_steps, tol=1e-10, max_iter=50, fixed_iter=0, sort_every=0, use_nn=False,
-            stats=False, check=True, conservation=False):
+            stats=False, check=True, conservation=False, solver="picard", krylov=10,
+            eta=1e-4):
         """n_steps implicit steps in the library (ecpic_run); returns the
         number done and, with stats, the last step's statistics."""
-        o = StepOpts(tol, max_iter, fixed_iter, sort_every, int(use_nn), int(conservation))
+        o = StepOpts(tol, max_iter, fixed_iter, sort_every, int(use_nn), int(conservation),
+                     _SOLVERS[solver], krylov, eta)
         done = C.c_int32(0)
         s = StepStats() if stats else None
         rc = self.L.ecpic_run(self.h, C.byref(o), int(n_steps), C.byref(done),

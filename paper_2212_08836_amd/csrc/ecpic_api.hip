@@ -166,6 +166,10 @@ void carve_all(Ctx& c, Carver& k) {
     max_cap = std::max<int64_t>(max_cap, s.desc.capacity);
   }
   carve_queues(c, k, max_cap, std::max<int32_t>((int32_t)c.sp.size(), 1));
+  if (c.jfnk_m > 0) {
+    k.take(&c.jf_vec, (size_t)(c.jfnk_m + 7) * (nur + nuz));
+    k.take(&c.jf_part, (size_t)(kMaxKrylov + 1) * kJfBlocks);
+  }
 }
 
 // a device allocation of the library's own, freed at destroy
@@ -691,6 +695,8 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   ok = ok && hipHostMalloc((void**)&c.red_host, 64 * sizeof(double)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.part_host, kPartLen * sizeof(double)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c.cons_host, 4 * sizeof(unsigned long long)) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c.jf_host, (kMaxKrylov + 1) * kJfBlocks * sizeof(double)) ==
+                 hipSuccess;
   // written by kernels with system-scope stores and polled by the host
   ok = ok && hipHostMalloc((void**)&c.res_host, kMaxIter * sizeof(double),
                            hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
@@ -734,6 +740,7 @@ ecpic_status ecpic_destroy(ecpic_ctx* x) {
   if (c.red_host) (void)hipHostFree(c.red_host);
   if (c.part_host) (void)hipHostFree(c.part_host);
   if (c.cons_host) (void)hipHostFree(c.cons_host);
+  if (c.jf_host) (void)hipHostFree(c.jf_host);
   if (c.res_host) (void)hipHostFree(c.res_host);
   if (c.fin_host) (void)hipHostFree(c.fin_host);
   if (c.sort_total_host) (void)hipHostFree(c.sort_total_host);
@@ -1244,6 +1251,12 @@ ecpic_status ecpic_set_option(ecpic_ctx* x, int32_t option, int64_t value) {
       if (value < 0 || value >= kMaxIter) return fail(c, ECPIC_EINVAL, "fallback iteration");
       c.nn_force_fallback = (int32_t)value;
       return ECPIC_OK;
+    case ECPIC_OPT_JFNK_KRYLOV:
+      if (value < 0 || value > kMaxKrylov) return fail(c, ECPIC_EINVAL, "Krylov space: 0..32");
+      if (c.materialised)
+        return fail(c, ECPIC_EINVAL, "reserve the Krylov space before the device memory is set up");
+      c.jfnk_m = (int32_t)value;
+      return ECPIC_OK;
   }
   return fail(c, ECPIC_EINVAL, "unknown option");
 }
@@ -1292,6 +1305,184 @@ ecpic_status ecpic_diagnostics(ecpic_ctx* x, ecpic_step_stats* st) {
 // enqueued this step's extrapolated guess.  prepare_next: a next step follows
 // at once, so its guess (fields only) is enqueued as soon as this step's
 // fields are final, before the host waits for the commit summary.
+// Jacobian-free Newton-Krylov iterations of one step (ECPIC_SOLVER_JFNK;
+// the algorithm is stated with the solver enum in ecpic.h).  Starts from
+// the guess in c.ur_it / c.uz_it.  Ends with the state the Picard loop
+// leaves for a separate commit: the accepted iterate's fields in c.*_it,
+// its half-step field in c.*_half, its push's currents in c.Ir_alt /
+// c.Iz_alt, and the pass scratch of parity slot + 1 cleared by the residual
+// kernel of `slot`, the residual slot of the last evaluation (*last_slot).
+// Every evaluation is waited for: the Krylov loop needs its inner products
+// on the host.
+// relative forward-difference step of the JFNK Jacobian (see ecpic.h)
+constexpr double kJfDiff = 1e-6;
+
+static ecpic_status jfnk_iterate(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats* S,
+                                 int* last_slot, int* evals_out, bool* conv) {
+  const int64_t nur = n_edges_r(c), n = nur + n_edges_z(c);
+  const int m = o->krylov;
+  const bool fixed = o->fixed_iter > 0;
+  const int nmax = fixed ? o->fixed_iter : o->max_iter;
+  double* V = c.jf_vec;  // m + 1 Krylov vectors, then six work vectors
+  double* X = V + (int64_t)(c.jfnk_m + 1) * n;
+  double* GX = X + n;
+  double* F = GX + n;
+  double* Y = F + n;
+  double* W = Y + n;
+  double* D = W + n;
+  int slot = 0, evals = 0;
+  *conv = false;
+  auto dots = [&](const double* w, const double* Vb, int K, double* out) -> ecpic_status {
+    HIPCHK(launch_jf_dots(c, w, Vb, n, K, c.stream));
+    HIPCHK(hipMemcpyAsync(c.jf_host, c.jf_part, sizeof(double) * K * kJfBlocks,
+                          hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    for (int k = 0; k < K; ++k) {
+      double acc = 0.0;
+      for (int b = 0; b < kJfBlocks; ++b) acc += c.jf_host[(size_t)k * kJfBlocks + b];
+      out[k] = acc;
+    }
+    return ECPIC_OK;
+  };
+  auto norm = [&](const double* a, double* out) -> ecpic_status {
+    double d = 0.0;
+    const ecpic_status rc = dots(a, a, 1, &d);
+    *out = std::sqrt(std::max(d, 0.0));
+    return rc;
+  };
+  // G at Yv: the push in (u^n + Yv) / 2, the field solve from u^n; the
+  // result is left in c.ur_it / c.uz_it / c.h_it and the push's currents in
+  // c.Ir_alt / c.Iz_alt
+  auto eval = [&](double* Yv) -> ecpic_status {
+    slot = evals % kMaxIter;
+    ++evals;
+    HIPCHK(launch_half(c, c.ur, c.uz, Yv, Yv + nur, c.stream));
+    double* keep_r = c.ur_it;
+    double* keep_z = c.uz_it;
+    // the residual kernel measures the solve against the previous iterate
+    c.ur_it = Yv;
+    c.uz_it = Yv + nur;
+    ecpic_status rc = pass(c, 0, false, c.step, true, false);
+    if (rc != ECPIC_OK) {
+      c.ur_it = keep_r;
+      c.uz_it = keep_z;
+      return rc;
+    }
+    rc = enqueue_solve(c, slot, -1.0, false, true);
+    // the solve wrote a library buffer, now the iterate, and left Yv as the
+    // next target: the target role goes back to the library buffer
+    c.ur_nx = keep_r;
+    c.uz_nx = keep_z;
+    if (rc != ECPIC_OK) return rc;
+    double r = 0.0;
+    return wait_residual(c, slot, &r);
+  };
+#define JF(call)                          \
+  do {                                    \
+    const ecpic_status rc_ = (call);      \
+    if (rc_ != ECPIC_OK) return rc_;      \
+  } while (0)
+  HIPCHK(hipMemcpyAsync(X, c.ur_it, sizeof(double) * nur, hipMemcpyDeviceToDevice, c.stream));
+  HIPCHK(hipMemcpyAsync(X + nur, c.uz_it, sizeof(double) * (n - nur), hipMemcpyDeviceToDevice,
+                        c.stream));
+  JF(eval(X));
+  HIPCHK(launch_jf_sub(c, X, c.ur_it, c.uz_it, F, GX, c.stream));
+  double fn = 0.0, gn = 0.0;
+  JF(norm(F, &fn));
+  JF(norm(GX, &gn));
+  double H[kMaxKrylov + 1][kMaxKrylov];
+  double cs[kMaxKrylov], sn[kMaxKrylov], g[kMaxKrylov + 1], yv[kMaxKrylov];
+  double h1[kMaxKrylov + 1], h2[kMaxKrylov + 1];
+  for (int k = 0; k < nmax; ++k) {
+    const double r = gn > 0.0 ? fn / gn : (fn > 0.0 ? INFINITY : 0.0);
+    S->residual[k] = r;
+    S->newton_iters = k + 1;
+    if (fixed ? (k == nmax - 1) : (r <= o->tol)) {
+      *conv = true;
+      break;
+    }
+    if (!(fn > 0.0)) {
+      *conv = true;
+      break;
+    }
+    // GMRES on J d = -F from d = 0
+    double xn = 0.0;
+    JF(norm(X, &xn));
+    const double eps = kJfDiff * std::max(xn, fn);
+    HIPCHK(launch_jf_axpby(c, -1.0 / fn, F, 0.0, F, V, c.stream));
+    g[0] = fn;
+    int used = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + (int64_t)j * n;
+      HIPCHK(launch_jf_axpby(c, 1.0, X, eps, vj, Y, c.stream));
+      JF(eval(Y));
+      HIPCHK(launch_jf_jv(c, vj, c.ur_it, c.uz_it, GX, eps, W, c.stream));
+      // classical Gram-Schmidt, applied twice, in the energy inner product
+      JfCoef cf;
+      JF(dots(W, V, j + 1, h1));
+      for (int i = 0; i <= j; ++i) cf.v[i] = -h1[i];
+      HIPCHK(launch_jf_gemv(c, j + 1, V, n, cf, 1.0, W, c.stream));
+      JF(dots(W, V, j + 1, h2));
+      for (int i = 0; i <= j; ++i) cf.v[i] = -h2[i];
+      HIPCHK(launch_jf_gemv(c, j + 1, V, n, cf, 1.0, W, c.stream));
+      for (int i = 0; i <= j; ++i) H[i][j] = h1[i] + h2[i];
+      double hn = 0.0;
+      JF(norm(W, &hn));
+      H[j + 1][j] = hn;
+      HIPCHK(launch_jf_axpby(c, hn > 0.0 ? 1.0 / hn : 0.0, W, 0.0, W, V + (int64_t)(j + 1) * n,
+                             c.stream));
+      // the earlier rotations on the new column, then its own
+      for (int i = 0; i < j; ++i) {
+        const double a = H[i][j], b = H[i + 1][j];
+        H[i][j] = cs[i] * a + sn[i] * b;
+        H[i + 1][j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = H[j][j], b = H[j + 1][j];
+      const double d = std::sqrt(a * a + b * b);
+      cs[j] = d > 0.0 ? a / d : 1.0;
+      sn[j] = d > 0.0 ? b / d : 0.0;
+      H[j][j] = d;
+      H[j + 1][j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      used = j + 1;
+      S->krylov_iters++;
+      if (!fixed && std::fabs(g[j + 1]) <= o->eta * fn) break;
+    }
+    for (int i = used - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int q = i + 1; q < used; ++q) acc -= H[i][q] * yv[q];
+      yv[i] = acc / H[i][i];
+    }
+    JfCoef cd;
+    for (int i = 0; i < used; ++i) cd.v[i] = yv[i];
+    HIPCHK(launch_jf_gemv(c, used, V, n, cd, 0.0, D, c.stream));
+    // the step, backtracking in tolerance mode; the accepted trial's map is
+    // the next residual evaluation
+    double lam = 1.0;
+    for (int ls = 0;; ++ls) {
+      HIPCHK(launch_jf_axpby(c, 1.0, X, lam, D, Y, c.stream));
+      JF(eval(Y));
+      HIPCHK(launch_jf_sub(c, Y, c.ur_it, c.uz_it, W, nullptr, c.stream));
+      double fy = 0.0;
+      JF(norm(W, &fy));
+      if (fixed || ls == 8 || fy <= (1.0 - 1e-4 * lam) * fn) {
+        std::swap(X, Y);
+        std::swap(F, W);
+        HIPCHK(launch_jf_sub(c, X, c.ur_it, c.uz_it, F, GX, c.stream));
+        fn = fy;
+        JF(norm(GX, &gn));
+        break;
+      }
+      lam *= 0.5;
+    }
+  }
+#undef JF
+  *last_slot = slot;
+  *evals_out = evals;
+  return ECPIC_OK;
+}
+
 static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats* st,
                               bool guess_ready, bool prepare_next) {
   ecpic_step_stats local;
@@ -1299,6 +1490,12 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   std::memset(S, 0, sizeof(*S));
   int kmax = o->fixed_iter > 0 ? o->fixed_iter : o->max_iter;
   if (kmax < 1 || kmax > 64) return fail(c, ECPIC_EINVAL, "iterations must be in 1..64");
+  const bool jfnk = o->solver == ECPIC_SOLVER_JFNK;
+  if (o->solver != ECPIC_SOLVER_PICARD && !jfnk) return fail(c, ECPIC_EINVAL, "unknown solver");
+  if (jfnk && (c.jfnk_m < 1 || o->krylov < 1 || o->krylov > c.jfnk_m || !(o->eta >= 0.0)))
+    return fail(c, ECPIC_EINVAL,
+                "JFNK: krylov must be in 1..the space reserved with ECPIC_OPT_JFNK_KRYLOV, "
+                "eta >= 0");
   const double vnow = drive(c.g, c.t), vnext = drive(c.g, c.t + c.g.dt);
   const bool check = o->check_conservation != 0 && st != nullptr;
   if (check && !c.cons_valid) {
@@ -1396,7 +1593,15 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   bool nn_active = S->used_nn != 0;
   int k = 0;
   bool conv = false;
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  int iters_done = 0;
+  if (jfnk) {
+    int last = 0;
+    ecpic_status rc = jfnk_iterate(c, o, S, &last, &iters_done, &conv);
+    if (rc != ECPIC_OK) return rc;
+    // the common commit below takes iterate k - 1, with committed[] unset
+    k = last + 1;
+  }
+  for (int attempt = 0; attempt < 2 && !jfnk; ++attempt) {
     bool restart = false;
     {
       ecpic_status rc = enqueue_iteration(0);
@@ -1468,7 +1673,7 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
     HIPCHK(launch_guess_half(c, vnow, vnext, c.stream));
   }
   c.cur_tag = -1;
-  S->iters = k;
+  S->iters = jfnk ? iters_done : k;
   if (!tol_mode) conv = true;
   S->converged = conv ? 1 : 0;
   if (!conv) {

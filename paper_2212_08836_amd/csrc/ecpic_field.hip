@@ -836,6 +836,91 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
   if (l == 0) store_sys(&out->seq, seq);
 }
 
+// -- JFNK vector kernels (the unknown is [ur | uz]) --------------------------
+__device__ __forceinline__ double jf_weight(const MapP& m, const double* __restrict__ wr,
+                                            const double* __restrict__ wz, int64_t e) {
+  const int64_t nur = (int64_t)m.nr * (m.nz + 1);
+  if (e < nur) {
+    const int64_t i = e / (m.nz + 1);
+    const int64_t j = e - i * (m.nz + 1);
+    return (j >= 1 && j < m.nz) ? wr[i] : 0.0;
+  }
+  const int64_t i = (e - nur) / m.nz;
+  return i < m.nr ? wz[i] : 0.0;
+}
+
+__global__ void k_jf_axpby(int64_t n, double a, const double* __restrict__ x, double b,
+                           const double* __restrict__ y, double* __restrict__ z) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    z[e] = a * x[e] + b * y[e];
+}
+
+__global__ void k_jf_jv(int64_t nur, int64_t n, const double* __restrict__ v,
+                        const double* __restrict__ gr, const double* __restrict__ gz,
+                        const double* __restrict__ gx, double eps, double* __restrict__ w) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double g = e < nur ? gr[e] : gz[e - nur];
+    w[e] = v[e] - (g - gx[e]) / eps;
+  }
+}
+
+__global__ void k_jf_sub(int64_t nur, int64_t n, const double* __restrict__ y,
+                         const double* __restrict__ gr, const double* __restrict__ gz,
+                         double* __restrict__ f, double* __restrict__ gcopy) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double g = e < nur ? gr[e] : gz[e - nur];
+    f[e] = y[e] - g;
+    if (gcopy) gcopy[e] = g;
+  }
+}
+
+// one block's share of <w, V_k> for k < K: a fixed grid-stride split and a
+// fixed reduction order, so the sums do not depend on timing
+template <int KB>
+__global__ void __launch_bounds__(256) k_jf_dots(MapP m, const double* __restrict__ wr,
+                                                 const double* __restrict__ wz, int64_t n,
+                                                 const double* __restrict__ w,
+                                                 const double* __restrict__ V, int64_t ldv, int K,
+                                                 double* __restrict__ part) {
+  __shared__ double red[KB][256 / 64];
+  double acc[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) acc[k] = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double ww = jf_weight(m, wr, wz, e) * w[e];
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+      if (k < K) acc[k] = fma(ww, V[k * ldv + e], acc[k]);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[k][wv] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    double v = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) v += red[k][q];
+    part[(int64_t)k * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+__global__ void k_jf_gemv(int64_t n, int K, const double* __restrict__ V, int64_t ldv,
+                          JfCoef coef, double alpha, double* __restrict__ y) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = alpha == 0.0 ? 0.0 : alpha * y[e];
+    for (int k = 0; k < K; ++k) acc = fma(coef.v[k], V[k * ldv + e], acc);
+    y[e] = acc;
+  }
+}
+
 // field shift of a committed step done by copies: prev <- cur <- next
 __global__ void k_shift(int64_t nur, int64_t nuz, int64_t nh, double* ur, double* uz, double* h,
                         double* ur_prev, double* uz_prev, double* h_prev,
@@ -891,6 +976,59 @@ hipError_t launch_shift(const Ctx& c, hipStream_t s) {
   const int64_t nh = (int64_t)c.g.nr * c.g.nz;
   hipLaunchKernelGGL(k_shift, dim3(nblk(nuz > nur ? nuz : nur)), dim3(kBlock), 0, s, nur, nuz, nh,
                      c.ur, c.uz, c.h, c.ur_prev, c.uz_prev, c.h_prev, c.ur_it, c.uz_it, c.h_it);
+  return hipGetLastError();
+}
+
+namespace {
+int64_t jf_len(const Ctx& c) {
+  return (int64_t)c.g.nr * (c.g.nz + 1) + (int64_t)(c.g.nr + 1) * c.g.nz;
+}
+int jf_grid(int64_t n) { return (int)std::min<int64_t>(nblk(n), 4096); }
+}  // namespace
+
+hipError_t launch_jf_axpby(const Ctx& c, double a, const double* x, double b, const double* y,
+                           double* z, hipStream_t s) {
+  const int64_t n = jf_len(c);
+  hipLaunchKernelGGL(k_jf_axpby, dim3(jf_grid(n)), dim3(kBlock), 0, s, n, a, x, b, y, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_jf_jv(const Ctx& c, const double* v, const double* gr, const double* gz,
+                        const double* gx, double e, double* w, hipStream_t s) {
+  const int64_t n = jf_len(c), nur = (int64_t)c.g.nr * (c.g.nz + 1);
+  hipLaunchKernelGGL(k_jf_jv, dim3(jf_grid(n)), dim3(kBlock), 0, s, nur, n, v, gr, gz, gx, e, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_jf_sub(const Ctx& c, const double* y, const double* gr, const double* gz,
+                         double* f, double* gcopy, hipStream_t s) {
+  const int64_t n = jf_len(c), nur = (int64_t)c.g.nr * (c.g.nz + 1);
+  hipLaunchKernelGGL(k_jf_sub, dim3(jf_grid(n)), dim3(kBlock), 0, s, nur, n, y, gr, gz, f, gcopy);
+  return hipGetLastError();
+}
+
+hipError_t launch_jf_dots(const Ctx& c, const double* w, const double* V, int64_t ldv, int K,
+                          hipStream_t s) {
+  if (K < 1 || K > kMaxKrylov + 1) return hipErrorInvalidValue;
+  const int64_t n = jf_len(c);
+  if (K <= 4)
+    hipLaunchKernelGGL(k_jf_dots<4>, dim3(kJfBlocks), dim3(256), 0, s, c.m, c.sol.wr, c.sol.wz, n,
+                       w, V, ldv, K, c.jf_part);
+  else if (K <= 16)
+    hipLaunchKernelGGL(k_jf_dots<16>, dim3(kJfBlocks), dim3(256), 0, s, c.m, c.sol.wr, c.sol.wz,
+                       n, w, V, ldv, K, c.jf_part);
+  else
+    hipLaunchKernelGGL(k_jf_dots<kMaxKrylov + 1>, dim3(kJfBlocks), dim3(256), 0, s, c.m,
+                       c.sol.wr, c.sol.wz, n, w, V, ldv, K, c.jf_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_jf_gemv(const Ctx& c, int K, const double* V, int64_t ldv, const JfCoef& coef,
+                          double alpha, double* y, hipStream_t s) {
+  if (K < 0 || K > kMaxKrylov + 1) return hipErrorInvalidValue;
+  const int64_t n = jf_len(c);
+  hipLaunchKernelGGL(k_jf_gemv, dim3(jf_grid(n)), dim3(kBlock), 0, s, n, K, V, ldv, coef, alpha,
+                     y);
   return hipGetLastError();
 }
 

@@ -17,6 +17,8 @@ constexpr int kMaxSub = 64;     // sub-steps per particle per step
 constexpr int kMaxHalve = 20;   // halvings of a sub-step whose solve fails
 constexpr int kMaxFixed = 50;   // fixed-point iterations per sub-step solve
 constexpr int kMaxIter = 64;    // Picard iterations per step
+constexpr int kMaxKrylov = 32;  // JFNK: GMRES iterations per Newton step
+constexpr int kJfBlocks = 256;  // JFNK: blocks of the dot-product kernel
 constexpr int kBlock = 256;     // threads per block for particle kernels
 constexpr int kPerThread = 4;   // particles per thread of the fast push
 constexpr int kPerBlock = kBlock * kPerThread;
@@ -256,6 +258,12 @@ struct Ctx {
   int32_t queue_species = 0;       // species slots the queues are sized for
   int32_t queue_waves = 0;         // ECPIC_OPT_QUEUE_WAVES
   int32_t nn_force_fallback = 0;   // ECPIC_OPT_NN_FORCE_FALLBACK
+  // Jacobian-free Newton-Krylov: ECPIC_OPT_JFNK_KRYLOV reserves jfnk_m + 1
+  // Krylov vectors and six work vectors ([ur | uz] each) in the layout
+  int32_t jfnk_m = 0;
+  double* jf_vec = nullptr;
+  double* jf_part = nullptr;       // dot partials [kMaxKrylov + 1][kJfBlocks]
+  double* jf_host = nullptr;       // pinned copy of the partials
   // the rotation of u^{n-1}, u^n, u^{n+1} takes a fourth buffer, so that a
   // step that is not committed still has u^{n-1} after the next step's guess
   // has been enqueued
@@ -361,6 +369,26 @@ hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart
                            const double* Iz, const double* wall_add, uint64_t seq, int guard_k,
                            hipStream_t s);
 hipError_t launch_zero_tally(const Ctx& c, hipStream_t s);
+// JFNK vector kernels.  A vector is [ur (nr (nz+1)) | uz ((nr+1) nz)]; the
+// inner product weights interior edges by eps A*/l (the residual's norm).
+struct JfCoef {
+  double v[kMaxKrylov + 1];
+};
+// z = a x + b y
+hipError_t launch_jf_axpby(const Ctx& c, double a, const double* x, double b, const double* y,
+                           double* z, hipStream_t s);
+// w = v - (g - gx) / e, with g given as its two parts (library field buffers)
+hipError_t launch_jf_jv(const Ctx& c, const double* v, const double* gr, const double* gz,
+                        const double* gx, double e, double* w, hipStream_t s);
+// f = y - g and, if gcopy, gcopy = g (g as two parts)
+hipError_t launch_jf_sub(const Ctx& c, const double* y, const double* gr, const double* gz,
+                         double* f, double* gcopy, hipStream_t s);
+// partials of <w, V_k>, k < K (V_k = V + k ldv), into c.jf_part[k][block]
+hipError_t launch_jf_dots(const Ctx& c, const double* w, const double* V, int64_t ldv, int K,
+                          hipStream_t s);
+// y = alpha y + sum_k coef_k V_k, k < K
+hipError_t launch_jf_gemv(const Ctx& c, int K, const double* V, int64_t ldv, const JfCoef& coef,
+                          double alpha, double* y, hipStream_t s);
 // the value a residual slot holds until the device has written it
 constexpr uint64_t kResPending = 0x7ff4dead0badf00dull;
 // partials: [0, kRedBlocks) sum w u^2, [kRedBlocks, 2 kRedBlocks) sum 2 pi r A h^2
