@@ -108,9 +108,12 @@ def particles(E, w, device_gen):
     return E.make_particles(w)
 
 
-def new_context(E, P, w, parts, precision):
-    """A context whose device memory is one torch tensor (bound workspace)."""
-    ctx = P.context_from_workload(w, precision=precision)
+def new_context(E, P, w, parts, precision, model="em", krylov=0):
+    """A context whose device memory is one torch tensor (bound workspace);
+    krylov > 0 reserves that many JFNK Krylov vectors in it."""
+    ctx = P.context_from_workload(w, precision=precision, model=model)
+    if krylov:
+        ctx.set_option(P.ECPIC_OPT_JFNK_KRYLOV, krylov)
     P.load_workload_species(ctx, parts, extra_cap=0.25, workspace=True)
     ctx.sort()
     ctx.set_mcc(w.mcc_params())
@@ -118,14 +121,15 @@ def new_context(E, P, w, parts, precision):
 
 
 def timed_run(ctx, w, steps, warmup, period, use_nn=False, kinds=("push", "push_slow",
-                                                                  "push_commit")):
-    """Warm-up, alignment to a sort boundary, then `steps` timed steps.
+                                                                  "push_commit"), **solver):
+    """Warm-up, alignment to a sort boundary, then `steps` timed steps
+    (solver: ecpic_step options such as solver="jfnk", krylov, eta).
     Returns (elapsed seconds, profile of the timed region)."""
     import torch
-    ctx.run(warmup, tol=w.tol, sort_every=period, use_nn=use_nn)
+    ctx.run(warmup, tol=w.tol, sort_every=period, use_nn=use_nn, **solver)
     step = ctx.diagnostics()["step"]
     if step % period:
-        ctx.run(period - step % period, tol=w.tol, sort_every=period, use_nn=use_nn)
+        ctx.run(period - step % period, tol=w.tol, sort_every=period, use_nn=use_nn, **solver)
     torch.cuda.synchronize()
     ctx.set_profiling(True, kinds=kinds, every=EVENT_EVERY)
     torch.cuda.synchronize()
@@ -134,7 +138,7 @@ def timed_run(ctx, w, steps, warmup, period, use_nn=False, kinds=("push", "push_
     k = 0
     while k < steps:
         n = min(RUN_CHUNK, steps - k)
-        ctx.run(n, tol=w.tol, sort_every=period, use_nn=use_nn)
+        ctx.run(n, tol=w.tol, sort_every=period, use_nn=use_nn, **solver)
         k += n
         if time.perf_counter() - last > 20:
             log(f"step {k}")
@@ -214,6 +218,57 @@ def leg(E, P, w, parts_fn, precision, use_nn, steps, warmup, period, plain_ms, n
             "s_per_step": el / steps, "particle_pushes_per_s": pushes / el,
             "picard_iterations_per_step": iters, "first_residual_mean": r0,
             "nn_fallbacks": fb, "speedup_vs_plain": plain_ms / ms}
+
+
+def model_leg(E, P, w, parts_fn, steps, warmup, period, plain_ms):
+    """The electrostatic model (Eq. (8)) on the same workload: the particle
+    side is unchanged, the field update is the Poisson solve."""
+    ctx = new_context(E, P, w, parts_fn(), "fp64", model="es")
+    el, prof = timed_run(ctx, w, steps, warmup, period, kinds=("push", "push_commit", "field"))
+    pushes, iters = pushes_and_iters(prof, steps)
+    ctx.close()
+    ms = 1e3 * el / steps
+    f = prof["field"]
+    return {"model": "electrostatic", "ms_per_step": ms, "particle_pushes_per_s": pushes / el,
+            "picard_iterations_per_step": iters,
+            "field_solve_ms": f["ms"] / f["launches"] if f["launches"] else None,
+            "vs_em_step": plain_ms / ms}
+
+
+def jfnk_leg(E, P, w, parts_fn, steps, warmup, period, plain_ms, krylov=10, eta=1e-3):
+    """The JFNK solver on the same workload, and on a dense 32x32 plasma
+    (omega_pe dt = 3.4) where Picard does not converge."""
+    opts = dict(solver="jfnk", krylov=krylov, eta=eta)
+    ctx = new_context(E, P, w, parts_fn(), "fp64", krylov=krylov)
+    el, prof = timed_run(ctx, w, steps, warmup, period, kinds=("push", "push_commit"), **opts)
+    pushes, passes = pushes_and_iters(prof, steps)
+    ds = [ctx.step(tol=w.tol, sort_every=period, **opts) for _ in range(4)]
+    ctx.close()
+    ms = 1e3 * el / steps
+    out = {"solver": "jfnk", "krylov": krylov, "eta": eta, "ms_per_step": ms,
+           "particle_pushes_per_s": pushes / el, "push_passes_per_step": passes,
+           "newton_per_step": float(np.mean([d["newton_iters"] for d in ds])),
+           "krylov_per_step": float(np.mean([d["krylov_iters"] for d in ds])),
+           "vs_picard_step": plain_ms / ms}
+    wd = E.workload("c1", n0=1e18, dt=6e-11, tol=1e-10)
+    cd = new_context(E, P, wd, E.make_particles(wd), "fp64", krylov=20)
+    d = cd.step(tol=wd.tol, max_iter=50, check=False)
+    picard_rc = d["rc"]
+    cd.close()
+    cd = new_context(E, P, wd, E.make_particles(wd), "fp64", krylov=20)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dd = [cd.step(tol=wd.tol, max_iter=20, solver="jfnk", krylov=20, eta=1e-4)
+          for _ in range(8)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cd.close()
+    out["dense_32x32"] = {"omega_pe_dt": 3.38, "picard_status": picard_rc,
+                          "jfnk_ms_per_step": 1e3 * el / 8,
+                          "push_passes_per_step": float(np.mean([x["iters"] for x in dd])),
+                          "newton_per_step": float(np.mean([x["newton_iters"] for x in dd]))}
+    return out
 
 
 def calibrate_copy(mib):
@@ -392,6 +447,12 @@ def main():
 
         def parts_fn():
             return particles(E, w, device_gen)
+        log("leg: electrostatic model")
+        legs["es"] = model_leg(E, P, w, parts_fn, args.steps, args.warmup, period, ms)
+        torch.cuda.empty_cache()
+        log("leg: JFNK solver")
+        legs["jfnk"] = jfnk_leg(E, P, w, parts_fn, args.steps, args.warmup, period, ms)
+        torch.cuda.empty_cache()
         log("leg: mixed precision, extrapolated guess")
         legs["mixed"] = leg(E, P, w, parts_fn, "mixed", False, args.steps, args.warmup,
                             period, ms)

@@ -146,15 +146,21 @@ __global__ void k_scatter(MapP m, SpecDev src, SpecDev dst, int64_t n, int mixed
   dst.uid[d] = src.uid[k];
 }
 
+// Kinetic energy of a species: a fixed grid (kKineticBlocks) strides over
+// the particles, so that only that many blocks add their sums into one word
+// (one block per 256 particles serialised 0.5M atomic adds on it at 134M
+// particles).
+constexpr int kKineticBlocks = 2048;
+
 __global__ void k_kinetic(SpecDev s, int64_t n, int mixed, double* out) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double e = 0.0;
-  if (k < n) {
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kBlock) {
     if (!mixed) {
-      if (s.xi[k] >= 0.0) e = s.vr[k] * s.vr[k] + s.vt[k] * s.vt[k] + s.vz[k] * s.vz[k];
+      if (s.xi[k] >= 0.0) e += s.vr[k] * s.vr[k] + s.vt[k] * s.vt[k] + s.vz[k] * s.vz[k];
     } else if (s.cell[k] >= 0) {
       const double a = s.fvr[k], b = s.fvt[k], c = s.fvz[k];
-      e = a * a + b * b + c * c;
+      e += a * a + b * b + c * c;
     }
   }
   __shared__ double red[kBlock / 64];
@@ -168,34 +174,63 @@ __global__ void k_kinetic(SpecDev s, int64_t n, int mixed, double* out) {
   }
 }
 
+// Bilinear node charge.  The lanes of a wavefront that share a cell (most
+// of them, between sorts) are summed by a butterfly first, and one lane adds
+// the four sums: one round per distinct cell in the wavefront, four atomics
+// each, instead of four per particle.
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __global__ void k_node_charge(MapP m, SpecDev s, int64_t n, int mixed, double* q) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  int i, j;
-  double a, b;
-  if (!mixed) {
-    const double xi = s.xi[k];
-    if (!(xi >= 0.0)) return;
-    i = int(floor(xi));
-    j = int(floor(s.eta[k]));
-    i = i < 0 ? 0 : (i > m.nr - 1 ? m.nr - 1 : i);
-    j = j < 0 ? 0 : (j > m.nz - 1 ? m.nz - 1 : j);
-    a = xi - i;
-    b = s.eta[k] - j;
-  } else {
-    const int c = s.cell[k];
-    if (c < 0) return;
-    i = c / m.nz;
-    j = c - i * m.nz;
-    a = s.fa[k];
-    b = s.fb[k];
+  int key = -1;  // cell of a live particle
+  int i = 0, j = 0;
+  double a = 0.0, b = 0.0;
+  if (k < n) {
+    if (!mixed) {
+      const double xi = s.xi[k];
+      if (xi >= 0.0) {
+        i = int(floor(xi));
+        j = int(floor(s.eta[k]));
+        i = i < 0 ? 0 : (i > m.nr - 1 ? m.nr - 1 : i);
+        j = j < 0 ? 0 : (j > m.nz - 1 ? m.nz - 1 : j);
+        a = xi - i;
+        b = s.eta[k] - j;
+        key = i * m.nz + j;
+      }
+    } else {
+      const int c = s.cell[k];
+      if (c >= 0) {
+        i = c / m.nz;
+        j = c - i * m.nz;
+        a = s.fa[k];
+        b = s.fb[k];
+        key = c;
+      }
+    }
   }
   const double qw = s.q * s.w;
+  const double w00 = qw * (1 - a) * (1 - b), w10 = qw * a * (1 - b);
+  const double w01 = qw * (1 - a) * b, w11 = qw * a * b;
+  const int lane = (int)(threadIdx.x & 63);
   const int nz1 = m.nz + 1;
-  unsafeAtomicAdd(&q[(size_t)i * nz1 + j], qw * (1 - a) * (1 - b));
-  unsafeAtomicAdd(&q[(size_t)(i + 1) * nz1 + j], qw * a * (1 - b));
-  unsafeAtomicAdd(&q[(size_t)i * nz1 + j + 1], qw * (1 - a) * b);
-  unsafeAtomicAdd(&q[(size_t)(i + 1) * nz1 + j + 1], qw * a * b);
+  unsigned long long todo = __ballot(key >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lk = __shfl(key, leader, 64);
+    const bool mine = key == lk;
+    const double s00 = wave_sum_d(mine ? w00 : 0.0), s10 = wave_sum_d(mine ? w10 : 0.0);
+    const double s01 = wave_sum_d(mine ? w01 : 0.0), s11 = wave_sum_d(mine ? w11 : 0.0);
+    if (lane == leader) {
+      unsafeAtomicAdd(&q[(size_t)i * nz1 + j], s00);
+      unsafeAtomicAdd(&q[(size_t)(i + 1) * nz1 + j], s10);
+      unsafeAtomicAdd(&q[(size_t)i * nz1 + j + 1], s01);
+      unsafeAtomicAdd(&q[(size_t)(i + 1) * nz1 + j + 1], s11);
+    }
+    todo &= ~__ballot(mine);
+  }
 }
 
 __global__ void k_zero(double* p, int64_t n) {
@@ -266,7 +301,8 @@ hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t st, int64_t* n_alive_hos
 
 hipError_t launch_kinetic(const Species& sp, int mixed, double* out, hipStream_t st) {
   if (sp.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_kinetic, dim3(nblk(sp.n)), dim3(kBlock), 0, st, sp.d[sp.cur], sp.n, mixed,
+  hipLaunchKernelGGL(k_kinetic, dim3((unsigned)std::min<int64_t>(nblk(sp.n), kKineticBlocks)),
+                     dim3(kBlock), 0, st, sp.d[sp.cur], sp.n, mixed,
                      out);
   return hipGetLastError();
 }
