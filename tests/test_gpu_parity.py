@@ -119,7 +119,8 @@ def test_load_read_roundtrip(og, torch_cuda):
 
 # nr > 256 gives the per-mode scan 2, 4 and 5 rows per thread
 @pytest.mark.parametrize("shape", [(32, 32, 2.0), (37, 29, 2.0), (70, 130, 0.0), (300, 16, 2.0),
-                                   (512, 8, 2.0), (1024, 8, 2.0), (1100, 12, 0.0)])
+                                   (512, 8, 2.0), (1024, 8, 2.0), (1100, 12, 0.0),
+                                   (1024, 512, 2.0)])
 def test_field_solve_parity(og, torch_cuda, shape):
     import paper_2212_08836_amd as P
     nr, nz, xa = shape
@@ -139,8 +140,34 @@ def test_field_solve_parity(og, torch_cuda, shape):
     t = 3.3e-9
     a = ctx.field_solve(ur0, uz0, h0, Ir, Iz, t)
     b = g.field_solve(ur0, uz0, h0, Ir, Iz, t)
-    for x, y in zip(a, b):
-        assert _rel(x, y) < TOL
+    bar = max(TOL, _cn_condition(g, w) * 2.0 ** -53)
+    errs = [_rel(x, y) for x, y in zip(a, b)]
+    _flush(f"  errors {errs}, bar {bar:.2e}")
+    assert max(errs) < bar
+
+
+def _cn_condition(g, w):
+    """Condition number of the SPD system for h^{n+1/2}: its extreme
+    eigenvalues are those of the radial tridiagonal of the lowest and of the
+    highest axial mode (the system separates in z).  Two backward-stable
+    solves of it may differ by this times the unit roundoff; at 1024 x 512
+    with dt = 20 ps it is 1.4e5 (c dt / dz = 100), below 1e4 on the smaller
+    shapes."""
+    from scipy.linalg import eigvalsh_tridiagonal
+    t = g.tables()
+    rh, wr, wz, area = t["rh"], t["wr"], t["wz"], t["area"]
+    dt, mu = w.dt, E.MU0
+    mi = 2 * math.pi * rh
+    dzw, drw = 2 * wz / dt, 2 * wr / dt
+    diag = mi * 2 * mu * area / dt + mi * mi / dzw
+    diag[:-1] += mi[:-1] ** 2 / dzw[1:]
+    off = -(2 * math.pi * rh[:-1]) * mi[1:] / dzw[1:]
+    grad = mi * mi / drw
+    lam = 2 - 2 * math.cos(math.pi * (w.nz - 1) / w.nz)
+    lo = eigvalsh_tridiagonal(diag, off, select="i", select_range=(0, 0))[0]
+    hi = eigvalsh_tridiagonal(diag + lam * grad, off, select="i",
+                              select_range=(w.nr - 1, w.nr - 1))[0]
+    return hi / lo
 
 
 def test_push_deposit_parity_c1(og, torch_cuda):
@@ -483,6 +510,56 @@ def test_c2_full_size_sampled(og, torch_cuda):
         keep = np.isin(a["uid"], ov["uid"])
         gv = {kk: v[keep] for kk, v in a.items()}
         assert _cmp_species(gv, ov, f"c2 sample sp {k}") < TOL
+
+
+def test_c5_grid_sampled(og, torch_cuda):
+    # the c5 grid (1024 x 512) at 64 particles per cell and species (67M
+    # particles: the three-wavefront slow-pass build is chosen by size), drawn
+    # on the GPU as the bench draws c5: one committed pass, exact continuity
+    # of the whole deposit on the GPU's outputs, and 2000 sampled particles
+    # per species re-pushed by the oracle
+    import paper_2212_08836_amd as P
+    _flush("c5 grid, 67M particles, sampled")
+    w = E.workload("c5", ppc=64)
+    parts = E.make_particles_device(w, device="cuda")
+    ctx = P.context_from_workload(w)
+    P.load_workload_species(ctx, parts)
+    del parts
+    ctx.sort()
+    g = og.grid_from_workload(w, push_only=True)
+    nr, nz = w.nr, w.nz
+    urh, uzh = _c2_half_field(w, seed=15)
+    ctx.set_half_field(urh, uzh)
+    before = [ctx.read_particles(k) for k in range(2)]
+    q0, _, _, _ = ctx.node_charge()
+    Ir, Iz = ctx.push_deposit(commit=True)
+    q1, bot, top, side = ctx.node_charge()
+    after = [ctx.read_particles(k) for k in range(2)]
+    dq = (q1 - q0).reshape(nr + 1, nz + 1)
+    dq[:, 0] += bot
+    dq[:, -1] += top
+    dq[-1, :] += side
+    div = g.div(Ir, Iz).reshape(nr + 1, nz + 1)
+    # the charge of one cell's particles of one species
+    qw = E.QE * (E._total_particles_phys(w) / w.n_per_species) * w.ppc
+    err = np.abs(dq + w.dt * div).max()
+    _flush(f"  continuity {err:.3e} against {qw:.3e} (charge of one cell's particles)")
+    assert err < 1e-11 * qw
+    rng = np.random.default_rng(21)
+    for k in range(2):
+        b = before[k]
+        idx = rng.choice(len(b["uid"]), 2000, replace=False)
+        q, m = (-E.QE, E.ME) if k == 0 else (E.QE, E.M_AR)
+        s = og.Species(q, m, 1.0, b["xi"][idx], b["eta"][idx], b["vr"][idx], b["vt"][idx],
+                       b["vz"][idx], b["uid"][idx])
+        g.push_deposit(s, urh, uzh, commit=True, state=og.State(g))
+        ov = s.view()
+        a = after[k]
+        sel = np.isin(a["uid"], ov["uid"])
+        gv = _by_uid({kk: v[sel] for kk, v in a.items()})
+        worst = _cmp_species(gv, ov, f"c5 sample sp {k}")
+        _flush(f"  species {k}: sampled worst {worst:.2e}")
+        assert worst < TOL
 
 
 def _c2_half_field(w, seed=9):
