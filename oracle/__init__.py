@@ -59,7 +59,8 @@ class OgGrid(C.Structure):
                 ("drive_amp", C.c_double * 32), ("drive_freq", C.c_double * 32),
                 ("drive_phase", C.c_double * 32), ("drive_t_end", C.c_double),
                 ("bz_ext", C.c_double), ("er_ext", C.c_double),
-                ("sub_tol", C.c_double), ("push_only", C.c_int32), ("model", C.c_int32)]
+                ("sub_tol", C.c_double), ("push_only", C.c_int32), ("model", C.c_int32),
+                ("cap", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -75,7 +76,8 @@ class OgSpecies(C.Structure):
 class OgState(C.Structure):
     _fields_ = [("ur", _dp), ("uz", _dp), ("h", _dp), ("ur_prev", _dp), ("uz_prev", _dp),
                 ("wall_bot", _dp), ("wall_top", _dp), ("wall_side", _dp),
-                ("t", C.c_double), ("step", C.c_int64)]
+                ("t", C.c_double), ("step", C.c_int64), ("phi", C.c_double),
+                ("phi_prev", C.c_double), ("q_cap", C.c_double)]
 
 
 class OgOpts(C.Structure):
@@ -97,7 +99,8 @@ class OgStats(C.Structure):
                 ("n_absorbed", C.c_int64 * 4), ("n_coll", C.c_int64 * 4), ("n_ionized", C.c_int64),
                 ("n_substeps", C.c_int64), ("n_crossings", C.c_int64), ("n_halvings", C.c_int64),
                 ("n_errors", C.c_int64), ("n_capped", C.c_int64), ("n_over_range", C.c_int64),
-                ("newton_iters", C.c_int32), ("krylov_iters", C.c_int32)]
+                ("newton_iters", C.c_int32), ("krylov_iters", C.c_int32),
+                ("phi", C.c_double), ("q_cap", C.c_double), ("w_gen", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -204,10 +207,14 @@ class State:
         self.wall_side = np.zeros(nz + 1)
         self.t = 0.0
         self.step = 0
+        self.phi = 0.0       # electrode potential (blocking capacitor)
+        self.phi_prev = 0.0
+        self.q_cap = 0.0     # capacitor charge
 
     def struct(self) -> OgState:
         return OgState(_p(self.ur), _p(self.uz), _p(self.h), _p(self.ur_prev), _p(self.uz_prev),
-                       _p(self.wall_bot), _p(self.wall_top), _p(self.wall_side), self.t, self.step)
+                       _p(self.wall_bot), _p(self.wall_top), _p(self.wall_side), self.t, self.step,
+                       self.phi, self.phi_prev, self.q_cap)
 
     def copy(self) -> "State":
         s = State.__new__(State)
@@ -221,7 +228,7 @@ class Grid:
 
     def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
                  drive_phase=(), drive_t_end=0.0, self_b=False, bz_ext=0.0, er_ext=0.0,
-                 sub_tol=0.0, omp=False, push_only=False, model="em"):
+                 sub_tol=0.0, omp=False, push_only=False, model="em", cap=0.0):
         L_ = lib(omp)
         g = OgGrid()
         g.nr, g.nz, g.R, g.L, g.xi_a, g.dt, g.eps, g.mu = nr, nz, R, L, xi_a, dt, eps, mu
@@ -235,6 +242,7 @@ class Grid:
         g.bz_ext, g.er_ext, g.sub_tol = bz_ext, er_ext, sub_tol
         g.push_only = int(push_only)
         g.model = {"em": 0, "es": 1}[model]
+        g.cap = cap
         self.desc = g
         self.nr, self.nz, self.R, self.L, self.xi_a, self.dt = nr, nz, R, L, xi_a, dt
         self.eps, self.mu = eps, mu
@@ -363,6 +371,7 @@ class Grid:
             s.n = arr[k].n
         state.t = stc.t
         state.step = stc.step
+        state.phi, state.phi_prev, state.q_cap = stc.phi, stc.phi_prev, stc.q_cap
         d = st.as_dict()
         d["rc"] = rc
         return d

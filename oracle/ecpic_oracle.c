@@ -59,6 +59,8 @@ struct og_ctx {
   int32_t band;  /* Cholesky half bandwidth (nz, or nz-1 for ES)     */
   double *chol;  /* banded lower factor, nunk*(band+1)               */
   double *rhs, *x, *tr, *tz; /* work                                 */
+  int gap_set;              /* 1: the solves take the gap voltages below */
+  double gap_now, gap_next; /* gap voltage at t^n and t^{n+1}            */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -284,6 +286,7 @@ static void chol_solve(og_ctx* c, const double* rhs, double* x) {
 int og_create(const og_grid* g, og_ctx** out) {
   if (!g || !out || g->nr < 1 || g->nz < 1 || !(g->R > 0) || !(g->L > 0) ||
       !(g->dt > 0) || !(g->eps > 0) || !(g->mu > 0) || g->xi_a < 0 || g->xi_a > g->nr ||
+      !(g->cap >= 0.0) ||
       (g->model != OG_EM && g->model != OG_ES) || (g->model == OG_ES && g->nz < 2))
     return -1;
   og_ctx* c = (og_ctx*)calloc(1, sizeof(og_ctx));
@@ -375,7 +378,9 @@ static void field_solve_es(og_ctx* c, const double* ur0, const double* uz0,
                            double* ur1, double* uz1, double* h1) {
   const int nr = c->g.nr, nz = c->g.nz;
   const double dt = c->g.dt;
-  const double dv = og_drive(c, t + dt) - og_drive(c, t);
+  const double vnow = c->gap_set ? c->gap_now : og_drive(c, t);
+  const double vnext = c->gap_set ? c->gap_next : og_drive(c, t + dt);
+  const double dv = vnext - vnow;
   double* b = c->rhs;
   for (int i = 0; i < nr; ++i)
     for (int j = 1; j < nz; ++j) {
@@ -400,7 +405,7 @@ static void field_solve_es(og_ctx* c, const double* ur0, const double* uz0,
       const double pb = (j + 1 == nz) ? 0.0 : c->x[PN(i, j + 1)];
       uz1[UZ(i, j)] = uz0[UZ(i, j)] + (pa - pb);
     }
-  set_boundary(c, ur1, uz1, og_drive(c, t + dt));
+  set_boundary(c, ur1, uz1, vnext);
   for (int64_t k = 0; k < c->ncell; ++k) h1[k] = 0.0;
 }
 
@@ -414,7 +419,9 @@ int og_field_solve(og_ctx* c, const double* ur0, const double* uz0, const double
   }
   const int nr = c->g.nr, nz = c->g.nz;
   const double dt = c->g.dt, mu = c->g.mu;
-  const double vh = 0.5 * (og_drive(c, t) + og_drive(c, t + dt));
+  const double vnow = c->gap_set ? c->gap_now : og_drive(c, t);
+  const double vnext = c->gap_set ? c->gap_next : og_drive(c, t + dt);
+  const double vh = 0.5 * (vnow + vnext);
   double* tr = c->tr;
   double* tz = c->tz;
   /* u0 - D^-1 I on interior edges, the half-step value on boundary edges */
@@ -445,7 +452,7 @@ int og_field_solve(og_ctx* c, const double* ur0, const double* uz0, const double
       const double uh = uz0[UZ(i, j)] + dt * (tz[UZ(i, j)] - Iz[UZ(i, j)]) / (2.0 * c->wz[i]);
       uz1[UZ(i, j)] = 2.0 * uh - uz0[UZ(i, j)];
     }
-  set_boundary(c, ur1, uz1, og_drive(c, t + dt));
+  set_boundary(c, ur1, uz1, vnext);
   for (int64_t k = 0; k < c->ncell; ++k) h1[k] = 2.0 * c->x[k] - h0[k];
   return 0;
 }
@@ -1349,6 +1356,43 @@ out:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Blocking capacitor (Sec. 2.1, Eq. (6)): the current I_e leaving the       */
+/* powered electrode into the domain over the step, in the form the energy   */
+/* balance of the drive takes (the drive's work is dt V_gap^{1/2} I_e):       */
+/*   EM: 2 pi r_{nr-1/2} h^{n+1/2} of the gap cell + I_r of the gap edge;     */
+/*   ES: the change of the field flux leaving the plate's nodes over dt, the  */
+/*       particle current leaving them, and I_r of the gap edge.              */
+/* The electrode potential then follows from the capacitor charge:            */
+/* phi^{n+1} = V^{n+1} - (q^n + dt I_e) / C, iterated with the Picard         */
+/* iterates, and q^{n+1} = q^n + dt I_e for the accepted one.  The iteration */
+/* is converged when the field update and the potential's change (relative  */
+/* to the generator's amplitude) are both within the tolerance.              */
+/* ------------------------------------------------------------------------ */
+/* the scale of the circuit's part of the residual: the sum of the drive
+ * amplitudes (1 V when there is none) */
+static double circuit_scale(const og_ctx* c) {
+  double s = 0.0;
+  for (int k = 0; k < c->g.n_drive && k < OG_MAX_DRIVE; ++k) s += fabs(c->g.drive_amp[k]);
+  return s > 0.0 ? s : 1.0;
+}
+
+static double electrode_current(const og_ctx* c, const og_state* st, const double* uz1,
+                                const double* h1, const double* Ir, const double* Iz) {
+  const int nr = c->g.nr, nz = c->g.nz;
+  const double dt = c->g.dt;
+  if (c->g.model == OG_ES) {
+    double dq = 0.0, ip = 0.0;
+    for (int i = 0; i < nr; ++i) {
+      dq += c->wz[i] * (uz1[UZ(i, 0)] - st->uz[UZ(i, 0)]);
+      ip += Iz[UZ(i, 0)];
+    }
+    return dq / dt + ip + Ir[UR(nr - 1, 0)];
+  }
+  const double hgap = 0.5 * (st->h[HC(nr - 1, 0)] + h1[HC(nr - 1, 0)]);
+  return 2.0 * OG_PI * c->rh[nr - 1] * hgap + Ir[UR(nr - 1, 0)];
+}
+
+/* ------------------------------------------------------------------------ */
 /* One implicit step (Picard iteration of the coupled system, Sec. 2.1)      */
 /* ------------------------------------------------------------------------ */
 int og_step(og_ctx* c, og_state* st, og_species* sp, int32_t nsp, const og_mcc* mcc,
@@ -1379,18 +1423,27 @@ int og_step(og_ctx* c, og_state* st, og_species* sp, int32_t nsp, const og_mcc* 
     rc = -2;
     goto done;
   }
-  set_boundary(c, st->ur, st->uz, og_drive(c, t));
+  /* with a blocking capacitor the gap carries the electrode potential: phi^n
+   * now, its extrapolation 2 phi^n - phi^{n-1} as the first iterate */
+  const int circ = c->g.cap > 0.0;
+  double phi_it = 2.0 * st->phi - st->phi_prev, phi_used = st->phi, ie = 0.0;
+  set_boundary(c, st->ur, st->uz, circ ? st->phi : og_drive(c, t));
   /* guess: u^{n+1,(0)} = 2 u^n - u^{n-1}; boundary edges at t^{n+1} */
   for (int64_t k = 0; k < nur; ++k) ur1[k] = 2.0 * st->ur[k] - st->ur_prev[k];
   for (int64_t k = 0; k < nuz; ++k) uz1[k] = 2.0 * st->uz[k] - st->uz_prev[k];
-  set_boundary(c, ur1, uz1, og_drive(c, t + dt));
+  set_boundary(c, ur1, uz1, circ ? phi_it : og_drive(c, t + dt));
   memcpy(h1, st->h, sizeof(double) * nh);
+  c->gap_set = circ;
+  c->gap_now = st->phi;
   int k;
   int kmax = o->fixed_iter > 0 ? o->fixed_iter : o->max_iter;
   if (kmax > 64) kmax = 64;
   S->converged = 0;
   if (o->solver == OG_JFNK) {
-    if (o->krylov < 1 || o->krylov > OG_MAX_KRYLOV || c->g.self_b) { rc = -1; goto done; }
+    if (o->krylov < 1 || o->krylov > OG_MAX_KRYLOV || c->g.self_b || circ) {
+      rc = -1;
+      goto done;
+    }
     const int64_t nv = nur + nuz;
     double* X = (double*)malloc(sizeof(double) * nv);
     double* GX = (double*)malloc(sizeof(double) * nv);
@@ -1420,11 +1473,22 @@ int og_step(og_ctx* c, og_state* st, og_species* sp, int32_t nsp, const og_mcc* 
     memset(Ir, 0, sizeof(double) * nur);
     memset(Iz, 0, sizeof(double) * nuz);
     for (int s = 0; s < nsp; ++s) og_push_deposit(c, &sp[s], urh, uzh, hh, 0, Ir, Iz, NULL, NULL);
+    c->gap_next = phi_it;
     og_field_solve(c, st->ur, st->uz, st->h, Ir, Iz, t, urn, uzn, hn);
+    if (circ) {
+      ie = electrode_current(c, st, uzn, hn, Ir, Iz);
+      phi_used = phi_it;
+      phi_it = og_drive(c, t + dt) - (st->q_cap + dt * ie) / c->g.cap;
+    }
     for (int64_t e = 0; e < nur; ++e) dr_[e] = urn[e] - ur1[e];
     for (int64_t e = 0; e < nuz; ++e) dz_[e] = uzn[e] - uz1[e];
     const double num = og_energy_norm2(c, dr_, dz_), den = og_energy_norm2(c, urn, uzn);
-    const double r = (den > 0.0) ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+    double r = (den > 0.0) ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+    if (circ) {
+      /* the electrode potential's change, against the generator's amplitude */
+      const double rc_ = fabs(phi_it - phi_used) / circuit_scale(c);
+      if (rc_ > r) r = rc_;
+    }
     S->residual[k] = r;
     memcpy(ur1, urn, sizeof(double) * nur);
     memcpy(uz1, uzn, sizeof(double) * nuz);
@@ -1454,7 +1518,8 @@ accepted:
     for (int i = 0; i < nr; ++i)
       for (int j = 0; j < nz; ++j) wio += 0.5 * (st->uz[UZ(i, j)] + uz1[UZ(i, j)]) * Iz[UZ(i, j)];
     S->w_field_io = dt * wio;
-    const double vh = 0.5 * (og_drive(c, t) + og_drive(c, t + dt));
+    const double vgen = 0.5 * (og_drive(c, t) + og_drive(c, t + dt));
+    const double vh = circ ? 0.5 * (st->phi + phi_used) : vgen;
     if (c->g.model == OG_ES) {
       /* the source's work: V^{1/2} times the charge it moves onto the
        * powered plate's nodes (the change of their field flux plus the
@@ -1469,6 +1534,7 @@ accepted:
       const double hgap = 0.5 * (st->h[HC(nr - 1, 0)] + h1[HC(nr - 1, 0)]);
       S->w_drive = dt * (2.0 * OG_PI * c->rh[nr - 1] * hgap * vh + vh * Ir[UR(nr - 1, 0)]);
     }
+    if (circ) S->w_gen = dt * vgen * ie;
   }
   if (mcc && mcc->enabled) {
     const int e = og_collide(c, sp, nsp, mcc, st->step, S);
@@ -1481,10 +1547,18 @@ accepted:
   memcpy(st->h, h1, sizeof(double) * nh);
   st->t = t + dt;
   st->step += 1;
+  if (circ) {
+    st->phi_prev = st->phi;
+    st->phi = phi_used;
+    st->q_cap += dt * ie;
+  }
+  S->phi = st->phi;
+  S->q_cap = st->q_cap;
   for (int s = 0; s < nsp; ++s) S->ke[s] = og_kinetic(&sp[s]);
   S->we = og_energy_e(c, st->ur, st->uz);
   S->wb = og_energy_b(c, st->h);
 done:
+  c->gap_set = 0;
   free(ur1); free(uz1); free(h1); free(urn); free(uzn); free(hn);
   free(urh); free(uzh); free(hh); free(Ir); free(Iz); free(dr_); free(dz_);
   return rc;

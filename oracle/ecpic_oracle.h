@@ -41,6 +41,10 @@ typedef struct {
                                    banded factorisation is skipped, and
                                    og_field_solve / og_step return -5)       */
   int32_t model;                /* OG_EM (Eq. (2)) or OG_ES (Eq. (8))        */
+  double cap;                   /* > 0: the drive reaches the powered
+                                   electrode through a blocking capacitor of
+                                   this capacitance [F] (Eq. (6)); the gap
+                                   voltage is then the electrode potential   */
 } og_grid;
 
 #define OG_EM 0
@@ -62,6 +66,8 @@ typedef struct {
   double *wall_side;            /* absorbed charge per node, [nz+1]          */
   double t;                     /* t^n [s]                                   */
   int64_t step;                 /* n                                         */
+  double phi, phi_prev;         /* electrode potential at t^n, t^{n-1} [V]   */
+  double q_cap;                 /* blocking-capacitor charge at t^n [C]      */
 } og_state;
 
 typedef struct {
@@ -110,6 +116,9 @@ typedef struct {
                                    residual[] entries); iters counts every
                                    push pass of the iteration               */
   int32_t krylov_iters;         /* JFNK: GMRES iterations in all             */
+  double phi;                   /* electrode potential at t^{n+1} [V]        */
+  double q_cap;                 /* capacitor charge at t^{n+1} [C]           */
+  double w_gen;                 /* generator work dt V^{1/2} I_e [J]         */
 } og_stats;
 
 typedef struct og_ctx og_ctx;
