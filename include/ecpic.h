@@ -87,6 +87,26 @@ typedef struct {
   double drive_freq[32];
   double drive_phase[32];
   double drive_t_end;     /* > 0: V(t) = 0 from this time on (a burst)       */
+  double blocking_cap;    /* > 0: the generator V(t) reaches the powered
+                             electrode through a blocking capacitor of this
+                             capacitance [F] (Sec. 2.1, Eq. (6)).  The gap
+                             then carries the electrode potential phi, which
+                             the step iterates with the Picard iterates:
+                             phi^{(k+1)} = V^{n+1} - (q^n + dt I_e^{(k)}) / C,
+                             I_e the current the electrode sends into the
+                             domain (EM: 2 pi r h^{n+1/2} of the gap cell
+                             plus the gap edge's particle current; ES: the
+                             plate nodes' field flux change over dt plus the
+                             particle currents leaving them and the gap
+                             edge's), and q^{n+1} = q^n + dt I_e of the
+                             accepted iterate.  The residual is the larger of
+                             the field update and |phi^{(k+1)} - phi^{(k)}|
+                             over the sum of the drive amplitudes.  The plain
+                             iteration contracts by about C_e / C (C_e the
+                             electrode's capacitance to the domain, larger
+                             with plasma): meant for C well above C_e.  Not
+                             with the JFNK solver.  0 = the generator drives
+                             the gap directly. */
 } ecpic_grid_desc;
 
 typedef struct {
@@ -179,6 +199,12 @@ typedef struct {
   int32_t newton_iters;   /* JFNK: Newton residual evaluations (entries of
                              residual[]); 0 for Picard                       */
   int32_t krylov_iters;   /* JFNK: GMRES iterations over the step            */
+  double electrode_v;     /* blocking capacitor: electrode potential phi at
+                             t^{n+1} [V] (else the generator voltage)        */
+  double cap_charge;      /* blocking capacitor: its charge q^{n+1} [C]      */
+  double w_gen;           /* blocking capacitor: the generator's work
+                             dt V^{1/2} I_e [J] (= w_drive + the capacitor's
+                             energy change)                                  */
 } ecpic_step_stats;
 
 typedef struct ecpic_ctx ecpic_ctx;

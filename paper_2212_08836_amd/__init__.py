@@ -40,7 +40,8 @@ class GridDesc(C.Structure):
                 ("xi_axis", C.c_double), ("dt", C.c_double), ("eps", C.c_double),
                 ("mu", C.c_double), ("n_drive", C.c_int32), ("model", C.c_int32),
                 ("drive_amp", C.c_double * 32), ("drive_freq", C.c_double * 32),
-                ("drive_phase", C.c_double * 32), ("drive_t_end", C.c_double)]
+                ("drive_phase", C.c_double * 32), ("drive_t_end", C.c_double),
+                ("blocking_cap", C.c_double)]
 
 
 class SpeciesDesc(C.Structure):
@@ -76,7 +77,8 @@ class StepStats(C.Structure):
                 ("n_crossings", C.c_int64), ("n_errors", C.c_int64), ("n_over_range", C.c_int64),
                 ("t", C.c_double), ("step", C.c_int64), ("continuity_max", C.c_double),
                 ("gauss_max", C.c_double), ("q_max", C.c_double),
-                ("newton_iters", C.c_int32), ("krylov_iters", C.c_int32)]
+                ("newton_iters", C.c_int32), ("krylov_iters", C.c_int32),
+                ("electrode_v", C.c_double), ("cap_charge", C.c_double), ("w_gen", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -178,7 +180,7 @@ class Context:
 
     def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
                  drive_phase=(), drive_t_end=0.0, precision: str = "fp64", device: str = "cuda",
-                 model: str = "em"):
+                 model: str = "em", blocking_cap: float = 0.0):
         """The context allocates no device memory until its first device call;
         call :meth:`bind_workspace` after the last :meth:`add_species` to give
         it a torch-allocated region instead."""
@@ -196,6 +198,7 @@ class Context:
             g.drive_phase[k] = drive_phase[k] if k < len(drive_phase) else 0.0
         g.drive_t_end = drive_t_end
         g.model = {"em": ECPIC_MODEL_EM, "es": ECPIC_MODEL_ES}[model]
+        g.blocking_cap = blocking_cap
         self.desc = g
         stream = torch.cuda.current_stream(self.device).cuda_stream
         h = _vp()

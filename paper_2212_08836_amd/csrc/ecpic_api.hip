@@ -152,6 +152,7 @@ void carve_all(Ctx& c, Carver& k) {
   k.take(&c.q0, nn);
   k.take(&c.gq0, nn);
   k.take(&c.cons_dev, 4);
+  k.take(&c.circ, kCircLen);
   k.take(&c.nn_w, (size_t)ecpic_nn_param_count());
   char* gws = nullptr;
   k.take(&gws, nn_guess_ws_bytes(c));
@@ -618,6 +619,7 @@ ecpic_status materialise(Ctx& c) {
   int64_t zn[] = {nur, nuz, nh, nur, nuz, nur, nuz, nh, nur, nuz, nur, nuz, nur, nuz, nh, nur, nuz};
   for (int q = 0; q < 17; ++q) HIPCHK(launch_zero(zs[q], zn[q], c.stream));
   HIPCHK(launch_zero_i(c.stop, 2, c.stream));
+  HIPCHK(launch_zero(c.circ, kCircLen, c.stream));
   HIPCHK(launch_zero_i(c.qcount, 2 * kQCount, c.stream));
   HIPCHK(launch_zero(c.wall_bot, wall_len(c), c.stream));
   HIPCHK(launch_zero(c.wall_scr, 2 * wall_len(c), c.stream));
@@ -669,6 +671,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
       !(g->mu > 0) || !(g->xi_axis >= 0) || g->xi_axis > g->nr || g->n_drive < 0 ||
       g->n_drive > 32 || !(g->drive_t_end >= 0) || (prec != ECPIC_FP64 && prec != ECPIC_MIXED) ||
       (g->model != ECPIC_MODEL_EM && g->model != ECPIC_MODEL_ES) ||
+      !(g->blocking_cap >= 0.0) || !std::isfinite(g->blocking_cap) ||
       (g->model == ECPIC_MODEL_ES && g->nz < 2) ||
       (int64_t)g->nr * g->nz > (int64_t)1 << 28)
     return ECPIC_EINVAL;
@@ -1045,6 +1048,7 @@ static ecpic_status enqueue_solve(Ctx& c, int k, double tol, bool guarded, bool 
   a.ur1 = c.ur_nx;
   a.uz1 = c.uz_nx;
   a.h1 = c.h_nx;
+  a.gapv = c.g.blocking_cap > 0.0 ? c.circ + 3 : nullptr;
   a.ur_old = c.ur_it;
   a.uz_old = c.uz_it;
   a.part = c.sol.partial + kOffRes;
@@ -1066,7 +1070,7 @@ static ecpic_status enqueue_solve(Ctx& c, int k, double tol, bool guarded, bool 
   }
   static_assert(kOffRes == 0, "the residual kernel reads the partials at offset 0");
   std::memcpy(&c.res_host[k], &kResPending, sizeof(double));
-  HIPCHK(launch_converge(c, k, tol, c.stream));
+  HIPCHK(launch_converge(c, k, tol, c.stream, &a));
   std::swap(c.ur_it, c.ur_nx);
   std::swap(c.uz_it, c.uz_nx);
   std::swap(c.h_it, c.h_nx);
@@ -1492,6 +1496,8 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   if (kmax < 1 || kmax > 64) return fail(c, ECPIC_EINVAL, "iterations must be in 1..64");
   const bool jfnk = o->solver == ECPIC_SOLVER_JFNK;
   if (o->solver != ECPIC_SOLVER_PICARD && !jfnk) return fail(c, ECPIC_EINVAL, "unknown solver");
+  if (jfnk && c.g.blocking_cap > 0.0)
+    return fail(c, ECPIC_EINVAL, "JFNK with a blocking capacitor is not supported");
   if (jfnk && (c.jfnk_m < 1 || o->krylov < 1 || o->krylov > c.jfnk_m || !(o->eta >= 0.0)))
     return fail(c, ECPIC_EINVAL,
                 "JFNK: krylov must be in 1..the space reserved with ECPIC_OPT_JFNK_KRYLOV, "
@@ -1583,7 +1589,7 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
       spec_seq[k] = ++c.fin_seq;
       HIPCHK(launch_finalize(c, tally_set(c, k & 1), c.sol.partial + kOffEx, c.Ir_alt,
                              c.Iz_alt, wall_scratch(c, k & 1), spec_seq[k], tol_mode ? k : -1,
-                             c.stream));
+                             c.stream, k));
     }
     return ECPIC_OK;
   };
@@ -1706,7 +1712,7 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
                            c.stream));
     seq = ++c.fin_seq;
     HIPCHK(launch_finalize(c, tset, d + kOffEx, c.Ir_alt, c.Iz_alt, wall_scratch(c, cset), seq,
-                           -1, c.stream));
+                           -1, c.stream, ks));
   }
   // field shift u^{n-1} <- u^n <- u^{n+1}.  Library buffers: by pointer
   // roles, at once (the summary kernels above hold the pointers they read),
@@ -1745,8 +1751,14 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   std::memcpy(&fin, (const void*)c.fin_host, sizeof(fin));
   collect(c);
   const Tally& t = fin.t;
-  const double vh = 0.5 * (vnow + vnext);
+  const bool circ = c.g.blocking_cap > 0.0;
+  const double vgen = 0.5 * (vnow + vnext);
+  // the gap's half-step voltage: the electrode potential with a capacitor
+  const double vh = circ ? 0.5 * (fin.phi_n + fin.phi_1) : vgen;
   const double rgap = r_of_xi(c.m, c.g.nr - 0.5);
+  S->electrode_v = circ ? fin.phi_1 : vnext;
+  S->cap_charge = circ ? fin.q_1 : 0.0;
+  S->w_gen = circ ? c.g.dt * vgen * fin.ie : 0.0;
   S->w_field_io = c.g.dt * fin.xs;
   if (c.g.model == ECPIC_MODEL_ES)
     // the source's work: V^{1/2} times the charge it moves onto the powered

@@ -18,6 +18,8 @@
 //                  h^{n+1}, the next half-step field, per-block partial sums of
 //                  the Picard residual, and the reset of the consumed currents.
 // Grouping rows lets each load of the transform matrix feed several rows.
+#include <cmath>
+#include <cstring>
 #include <mutex>
 
 #include "ecpic_internal.h"
@@ -131,12 +133,16 @@ __global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restric
                                                  const double* __restrict__ h0,
                                                  const double* __restrict__ Ir,
                                                  const double* __restrict__ Iz, double vhalf,
+                                                 const double* __restrict__ gapv,
                                                  const double* __restrict__ Qt,
                                                  double* __restrict__ hat,
                                                  const int32_t* __restrict__ stop) {
   if (stop && *stop) return;
   extern __shared__ double sh[];  // kRB rows of the right-hand side, then the part sums
   const int nr = m.nr, nz = m.nz;
+  // blocking capacitor: the gap's half-step voltage from the electrode's
+  // potential at t^n (u0's gap edge) and the circuit's current iterate
+  if (gapv) vhalf = 0.5 * (ur0[(int64_t)(nr - 1) * (nz + 1)] + gapv[0]);
   const int i0 = blockIdx.x * kRB;
   const int rows = min(kRB, nr - i0);
   const int k0 = blockIdx.y * kCC;
@@ -319,6 +325,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
   __syncthreads();
   const double hdt = 0.5 * m.dt;
   const double two_pi = 2.0 * kPi;
+  const double vnext = a.gapv ? a.gapv[0] : a.vnext;
   double s0 = 0.0, s1 = 0.0;
   // r-edges j0 .. j0+nj-1 of the rows, and the top-wall edge nz in the last chunk
   const int ne = nj + (j0 + nj == nz ? 1 : 0);
@@ -328,7 +335,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
     const int64_t g = (int64_t)i * (nz + 1) + j;
     double v;
     if (j == 0) {
-      v = (i == nr - 1) ? a.vnext : 0.0;
+      v = (i == nr - 1) ? vnext : 0.0;
     } else if (j == nz) {
       v = 0.0;
     } else {
@@ -409,12 +416,15 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
 __global__ void __launch_bounds__(kFB) k_es_rhs_dst(MapP m, const double* __restrict__ wz,
                                                     const double* __restrict__ Ir,
                                                     const double* __restrict__ Iz, double dv,
+                                                    const double* __restrict__ gapv,
+                                                    const double* __restrict__ ur0,
                                                     const double* __restrict__ St,
                                                     double* __restrict__ hat,
                                                     const int32_t* __restrict__ stop) {
   if (stop && *stop) return;
   extern __shared__ double sh[];  // kRB rows of the right-hand side, then the part sums
   const int nr = m.nr, nz = m.nz, nf = nz - 1;
+  if (gapv) dv = gapv[0] - ur0[(int64_t)(nr - 1) * (nz + 1)];
   const int i0 = blockIdx.x * kRB;
   const int rows = min(kRB, nr - i0);
   const int k0 = blockIdx.y * kCC;
@@ -453,6 +463,8 @@ __global__ void __launch_bounds__(kFB) k_es_recover(SolveArgs a, MapP m,
   constexpr int XS = kCC + 1;  // node columns j0 .. j0 + nj
   extern __shared__ double sh[];
   const int nr = m.nr, nz = m.nz, nf = nz - 1;
+  const double vnext = a.gapv ? a.gapv[0] : a.vnext;
+  if (a.gapv) dv = a.gapv[0] - a.ur0[(int64_t)(nr - 1) * (nz + 1)];
   const int i0 = blockIdx.x * kRB;
   const int rows = min(kRB, nr - i0);
   const int j0 = blockIdx.y * kCC;
@@ -490,7 +502,7 @@ __global__ void __launch_bounds__(kFB) k_es_recover(SolveArgs a, MapP m,
     const int64_t g = (int64_t)i * (nz + 1) + j;
     double v;
     if (j == 0) {
-      v = (i == nr - 1) ? a.vnext : 0.0;
+      v = (i == nr - 1) ? vnext : 0.0;
     } else if (j == nz) {
       v = 0.0;
     } else {
@@ -566,7 +578,7 @@ __global__ void k_guess_half(MapP m, double* ur, double* uz, const double* ur_pr
                              const double* uz_prev, double* ur_it, double* uz_it, double* ur_h,
                              double* uz_h, float* ur_hf, float* uz_hf, double* Ir, double* Iz,
                              double vnow, double vnext, int32_t* stop, int32_t* qcount,
-                             Tally* tally, double* wscr, int64_t wlen) {
+                             Tally* tally, double* wscr, int64_t wlen, double* circ) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int nr = m.nr, nz = m.nz;
   const int64_t nur = (int64_t)nr * (nz + 1), nuz = (int64_t)(nr + 1) * nz;
@@ -578,7 +590,12 @@ __global__ void k_guess_half(MapP m, double* ur, double* uz, const double* ur_pr
   if (t < nur) {
     const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
     double u0 = ur[t], u1;
-    if (j == 0 || j == nz) {
+    if (j == 0 && i == nr - 1 && circ) {
+      // blocking capacitor: the gap carries the electrode potential; its
+      // first iterate is extrapolated like the interior edges
+      u1 = 2.0 * u0 - ur_prev[t];
+      circ[3] = u1;
+    } else if (j == 0 || j == nz) {
       const bool gap = (j == 0 && i == nr - 1);
       u0 = gap ? vnow : 0.0;
       ur[t] = u0;
@@ -720,10 +737,20 @@ __global__ void __launch_bounds__(kBlock) k_xsum(MapP m, const double* __restric
 // wavefront sums blocks l, l + 64, ... per lane and then combines the lanes in
 // a fixed butterfly order (deterministic).  The other threads clear the pass
 // scratch for the next push.
+// The blocking capacitor's part of a Picard iteration: the current the
+// electrode sent into the domain with this iterate, and the next electrode
+// potential from the capacitor charge (Sec. 2.1, Eq. (6)).
+struct CircArgs {
+  double* circ;  // null: no circuit
+  const double *h0, *h1, *Ir, *Iz, *uz0, *uz1, *wz, *rh;
+  double dt, cap, vnext_gen, scale;
+  int es, nr, nz;
+};
+
 __global__ void __launch_bounds__(256) k_converge(const double* __restrict__ part, int nparts, int k,
                                                   double tol, int32_t* stop, double* res,
                                                   int32_t* qcount, Tally* tally, double* wscr,
-                                                  int64_t wlen) {
+                                                  int64_t wlen, CircArgs ca) {
   if (*stop) return;
   const int t = threadIdx.x;
   if (t >= 64) {
@@ -739,8 +766,39 @@ __global__ void __launch_bounds__(256) k_converge(const double* __restrict__ par
     num += __shfl_xor(num, off, 64);
     den += __shfl_xor(den, off, 64);
   }
+  double ie = 0.0;
+  if (ca.circ) {
+    const double ir_gap = ca.Ir[(int64_t)(ca.nr - 1) * (ca.nz + 1)];
+    if (ca.es) {
+      double dq = 0.0, ip = 0.0;
+      for (int i = t; i < ca.nr; i += 64) {
+        const int64_t e = (int64_t)i * ca.nz;
+        dq += ca.wz[i] * (ca.uz1[e] - ca.uz0[e]);
+        ip += ca.Iz[e];
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        dq += __shfl_xor(dq, off, 64);
+        ip += __shfl_xor(ip, off, 64);
+      }
+      ie = dq / ca.dt + ip + ir_gap;
+    } else {
+      const int64_t gc = (int64_t)(ca.nr - 1) * ca.nz;
+      ie = 2.0 * kPi * ca.rh[ca.nr - 1] * (0.5 * (ca.h0[gc] + ca.h1[gc])) + ir_gap;
+    }
+  }
   if (t != 0) return;
   double r = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+  if (ca.circ) {
+    // the potential this iterate used, the next one, and the circuit's share
+    // of the residual (the change against the drive's amplitude)
+    const double used = ca.circ[3];
+    const double next = ca.vnext_gen - (ca.circ[2] + ca.dt * ie) / ca.cap;
+    const double rc = fabs(next - used) / ca.scale;
+    if (rc > r) r = rc;
+    ca.circ[6 + 2 * (k & 1)] = used;
+    ca.circ[7 + 2 * (k & 1)] = ie;
+    ca.circ[3] = next;
+  }
   if (r != r) r = __longlong_as_double(0x7ff8000000000000ll);  // one quiet NaN
   store_sys(res + k, r);
   if (r <= tol) {
@@ -776,7 +834,8 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
                                                  const double* __restrict__ wall_add,
                                                  double* __restrict__ wall_tot, uint64_t seq,
                                                  StepFinal* out, const int32_t* __restrict__ conv,
-                                                 int want_k) {
+                                                 int want_k, double* __restrict__ circ, int cpar,
+                                                 double dt) {
   static_assert(kSpread == 64, "64 tally copies");
   // enqueued ahead of the residual it depends on: only if iteration want_k
   // is the one that converged
@@ -829,6 +888,21 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
     out->ir_gap = Ir[(int64_t)(nr - 1) * (nz + 1)];
     out->qp_delta = qp;
     out->iz_plate = izp;
+    if (circ) {
+      // the accepted iterate's electrode potential and current; the circuit
+      // state moves to t^{n+1} only if the step is accepted
+      const double phi = circ[6 + 2 * cpar], ie = circ[7 + 2 * cpar];
+      const double q1 = circ[2] + dt * ie;
+      out->phi_n = circ[0];
+      out->phi_1 = phi;
+      out->q_1 = q1;
+      out->ie = ie;
+      if (!rejected) {
+        circ[1] = circ[0];
+        circ[0] = phi;
+        circ[2] = q1;
+      }
+    }
   }
   // every lane's stores are ordered before the sequence number
   __threadfence_system();
@@ -949,25 +1023,48 @@ __global__ void k_zero_tally(Tally* tally) {
 
 }  // namespace
 
-hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s) {
+hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s, const SolveArgs* a) {
   // the solve writes the residual row partials at the start of sol.partial
   if (k < 0 || k >= kMaxIter) return hipErrorInvalidValue;
   // the next iteration (parity k+1) gets a cleared tally set and wall scratch
   const int np = (k + 1) & 1;
+  CircArgs ca;
+  std::memset(&ca, 0, sizeof(ca));
+  if (a && a->gapv) {
+    double scale = 0.0;
+    for (int q = 0; q < c.g.n_drive && q < 32; ++q) scale += std::fabs(c.g.drive_amp[q]);
+    ca.circ = c.circ;
+    ca.h0 = a->h0;
+    ca.h1 = a->h1;
+    ca.Ir = a->Ir;
+    ca.Iz = a->Iz;
+    ca.uz0 = a->uz0;
+    ca.uz1 = a->uz1;
+    ca.wz = c.sol.wz;
+    ca.dt = c.g.dt;
+    ca.cap = c.g.blocking_cap;
+    ca.vnext_gen = a->vnext;
+    ca.scale = scale > 0.0 ? scale : 1.0;
+    ca.rh = c.sol.rh;
+    ca.es = c.g.model == ECPIC_MODEL_ES ? 1 : 0;
+    ca.nr = c.g.nr;
+    ca.nz = c.g.nz;
+  }
   hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, c.sol.partial,
                      row_blocks(c.g.nr) * col_blocks(c.g.nz),
                      k, tol, c.stop, c.res_dev, c.qcount, tally_set(c, np),
-                     wall_scratch(c, np), wall_len(c));
+                     wall_scratch(c, np), wall_len(c), ca);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart, const double* Ir,
                            const double* Iz, const double* wall_add, uint64_t seq, int guard_k,
-                           hipStream_t s) {
+                           hipStream_t s, int iter) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, tally, xpart, c.h, c.h_it, Ir,
                      c.g.nr, c.g.nz, c.uz, c.uz_it, Iz, c.sol.wz,
                      c.g.model == ECPIC_MODEL_ES ? 1 : 0, wall_add, c.wall_bot, seq, c.fin_dev,
-                     guard_k >= 0 ? (const int32_t*)c.stop : nullptr, guard_k);
+                     guard_k >= 0 ? (const int32_t*)c.stop : nullptr, guard_k,
+                     c.g.blocking_cap > 0.0 ? c.circ : nullptr, iter & 1, c.g.dt);
   return hipGetLastError();
 }
 
@@ -1042,7 +1139,7 @@ hipError_t launch_guess_half(const Ctx& c, double vnow, double vnext, hipStream_
   hipLaunchKernelGGL(k_guess_half, dim3(nblk(n)), dim3(kBlock), 0, s, c.m, c.ur, c.uz, c.ur_prev,
                      c.uz_prev, c.ur_it, c.uz_it, c.ur_half, c.uz_half, c.ur_half_f, c.uz_half_f,
                      c.Ir, c.Iz, vnow, vnext, c.stop, c.qcount, tally_set(c, 0),
-                     wall_scratch(c, 0), wall_len(c));
+                     wall_scratch(c, 0), wall_len(c), c.g.blocking_cap > 0.0 ? c.circ : nullptr);
   return hipGetLastError();
 }
 
@@ -1071,7 +1168,8 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s, double* 
     if (lds_es_rhs > 65536 || lds_es_rec > 65536) return hipErrorInvalidValue;
     const double dv = a.vnext - a.vnow;
     hipLaunchKernelGGL(k_es_rhs_dst, dim3(row_blocks(nr), col_blocks(nf)), dim3(kFB),
-                       lds_es_rhs, s, c.m, S.wz, a.Ir, a.Iz, dv, S.Qt, hat, a.stop);
+                       lds_es_rhs, s, c.m, S.wz, a.Ir, a.Iz, dv, a.gapv, a.ur0, S.Qt, hat,
+                       a.stop);
     hipLaunchKernelGGL(k_tri_scan, dim3(nf), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv, S.tri_up,
                        hat, a.stop);
     hipLaunchKernelGGL(k_es_recover, dim3(row_blocks(nr), cb), dim3(kFB), lds_es_rec, s, a, c.m,
@@ -1084,8 +1182,8 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s, double* 
                                            (size_t)kFB * (kRB + 1));
   if (lds_rhs > 65536 || lds_rec > 65536) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rhs_dct, dim3(row_blocks(nr), cb), dim3(kFB), lds_rhs, s, c.m, S.rh, S.wr,
-                     S.wz, S.area, c.g.mu, a.ur0, a.uz0, a.h0, a.Ir, a.Iz, a.vhalf, S.Qt, hat,
-                     a.stop);
+                     S.wz, S.area, c.g.mu, a.ur0, a.uz0, a.h0, a.Ir, a.Iz, a.vhalf, a.gapv, S.Qt,
+                     hat, a.stop);
   hipLaunchKernelGGL(k_tri_scan, dim3(nz), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv, S.tri_up,
                      hat, a.stop);
   hipLaunchKernelGGL(k_idct_recover, dim3(row_blocks(nr), cb), dim3(kFB), lds_rec, s, a, c.m,

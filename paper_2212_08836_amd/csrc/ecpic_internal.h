@@ -84,6 +84,9 @@ struct StepFinal {
   // leaving them, sum_i Iz[i][0] (the source's work)
   double qp_delta;
   double iz_plate;
+  // blocking capacitor: electrode potential at t^n and t^{n+1}, capacitor
+  // charge at t^{n+1}, and the electrode current of the accepted iterate
+  double phi_n, phi_1, q_1, ie;
   uint64_t seq;     // written last: the host polls it
 };
 
@@ -148,6 +151,10 @@ struct SolveArgs {
   double *Ir, *Iz;
   double vhalf, vnext;
   double vnow;          // drive at t^n (the electrostatic model's plate step)
+  // blocking capacitor: the gap voltage at t^{n+1} is read from here (the
+  // circuit's current iterate) and at t^n from ur0's gap edge; null: vnow,
+  // vnext
+  const double* gapv;
   double *ur1, *uz1, *h1;
   const double *ur_old, *uz_old;
   double* part;         // [2 * nr]: per row sum w (u1 - u_old)^2, sum w u1^2
@@ -260,6 +267,11 @@ struct Ctx {
   int32_t nn_force_fallback = 0;   // ECPIC_OPT_NN_FORCE_FALLBACK
   // Jacobian-free Newton-Krylov: ECPIC_OPT_JFNK_KRYLOV reserves jfnk_m + 1
   // Krylov vectors and six work vectors ([ur | uz] each) in the layout
+  // blocking capacitor (g.blocking_cap > 0), device state: [0] phi^n,
+  // [1] phi^{n-1}, [2] q^n, [3] the electrode potential the next solve uses,
+  // [6 + 2p], [7 + 2p] the potential and electrode current of the last
+  // Picard iteration of parity p
+  double* circ = nullptr;
   int32_t jfnk_m = 0;
   double* jf_vec = nullptr;
   double* jf_part = nullptr;       // dot partials [kMaxKrylov + 1][kJfBlocks]
@@ -355,7 +367,9 @@ double* static_scratch(int device);
 // (host memory, polled); sets *stop when it is <= tol (tol < 0: never) and
 // clears the queue counters and tallies for the next pass.  Does nothing
 // when *stop is already set.
-hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s);
+hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s,
+                           const SolveArgs* a = nullptr);
+constexpr int kCircLen = 16;
 // commit summary into fin_dev (host memory), seq written last
 // tally set (kSpread copies) and wall scratch of iterations of parity p
 inline Tally* tally_set(const Ctx& c, int p) { return c.tally + (int64_t)p * kSpread; }
@@ -367,7 +381,7 @@ inline double* wall_scratch(const Ctx& c, int p) { return c.wall_scr + p * wall_
 // kernel found converged (stop[1]), so it can be enqueued before that is known.
 hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart, const double* Ir,
                            const double* Iz, const double* wall_add, uint64_t seq, int guard_k,
-                           hipStream_t s);
+                           hipStream_t s, int iter = 0);
 hipError_t launch_zero_tally(const Ctx& c, hipStream_t s);
 // JFNK vector kernels.  A vector is [ur (nr (nz+1)) | uz ((nr+1) nz)]; the
 // inner product weights interior edges by eps A*/l (the residual's norm).

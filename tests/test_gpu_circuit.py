@@ -1,0 +1,96 @@
+"""The blocking-capacitor circuit on the HIP path (Sec. 2.1, Eq. (6)):
+whole steps against the oracle (EM and electrostatic, driven, collisional,
+with the electrode potential, capacitor charge and generator work compared
+each step), the vacuum capacitive divider, and the self-bias of a plasma
+over two RF periods with its energy balances."""
+import sys
+
+import numpy as np
+import pytest
+
+import ecpic_inputs as E
+
+from test_gpu_parity import _step_parity
+from test_oracle_circuit import _electrode_capacitance
+
+pytestmark = pytest.mark.gpu
+F = 50e6
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.parametrize("model", ["em", "es"])
+def test_circuit_step_parity(og, torch_cuda, model):
+    import paper_2212_08836_amd as P
+    _flush(f"step parity with a blocking capacitor, {model}, driven + MCC")
+    w = E.Workload("cap", 48, 24, 0.03, 0.012, n0=1e16, profile="j0sin", ppc=12,
+                   drive_amp=(200.0,), drive_freq=(100e6,), pressure_pa=60.0, seed=16,
+                   dt=1e-11, tol=1e-10)
+    cap = 10.0 * _electrode_capacitance(og, w)
+    parts = E.make_particles(w)
+    for k in ("vr", "vt", "vz"):
+        parts[0][k] = parts[0][k] * 3.0
+    worst = _step_parity(og, P, w, parts, 8, mcc=w.mcc_params(), sort_every=3, model=model,
+                         cap=cap)
+    _flush(f"  worst {worst:.2e}")
+
+
+@pytest.mark.parametrize("model", ["em", "es"])
+def test_vacuum_divider(og, torch_cuda, model):
+    import paper_2212_08836_amd as P
+    # a step of 97 ps keeps the steps off the drive's zeros (at 100 ps the
+    # drive reaches 1e-14 V at step 100): with no plasma the field there
+    # vanishes, and its relative update is undefined
+    w = E.Workload("v", 16, 16, 0.02, 0.02, dt=0.97e-10, drive_amp=(100.0,), drive_freq=(F,))
+    ce = _electrode_capacitance(og, w)
+    cap = 10.0 * ce
+    ctx = P.context_from_workload(w, model=model, blocking_cap=cap)
+    ctx.add_species(-E.QE, E.ME, 1.0, 16, True)
+    g = og.grid_from_workload(w, model=model, cap=cap)
+    st = og.State(g)
+    err = 0.0
+    # tol 1e-11: the field's norm passes near zero with the drive, where a
+    # relative update of 1e-12 is below the solves' rounding
+    for n in range(200):
+        d = ctx.step(tol=1e-11)
+        g.step(st, [], tol=1e-11)
+        v = g.drive(st.t)
+        err = max(err, abs(d["electrode_v"] - v * cap / (cap + ce)) / 100.0)
+        assert d["electrode_v"] == pytest.approx(st.phi, rel=1e-9, abs=1e-9)
+    _flush(f"  {model}: divider deviation {err:.2e} of the amplitude")
+    assert err < (1e-10 if model == "es" else 1e-3)
+
+
+@pytest.mark.parametrize("model", ["em", "es"])
+def test_self_bias(og, torch_cuda, model):
+    import paper_2212_08836_amd as P
+    w = E.Workload("p", 16, 16, 0.02, 0.02, n0=3e15, ppc=8, dt=5e-11, drive_amp=(100.0,),
+                   drive_freq=(F,), seed=3, tol=1e-11)
+    cap = 10.0 * _electrode_capacitance(og, w)
+    ctx = P.context_from_workload(w, model=model, blocking_cap=cap)
+    P.load_workload_species(ctx, E.make_particles(w), extra_cap=0.5)
+    per = int(round(1.0 / (F * w.dt)))
+    phis = []
+    q0 = 0.0
+    for n in range(2 * per):
+        d = ctx.step(tol=w.tol, conservation=(n % 50 == 0))
+        de = (d["cap_charge"] ** 2 - q0 ** 2) / (2.0 * cap)
+        q0 = d["cap_charge"]
+        assert abs(d["w_gen"] - d["w_drive"] - de) <= 1e-8 * abs(d["w_gen"]) + 1e-9 * abs(de) + 1e-30
+        if n % 50 == 0:
+            assert d["gauss_max"] < 1e-10 * d["q_max"]
+        phis.append(d["electrode_v"])
+    bias = float(np.mean(phis[per:]))
+    _flush(f"  {model}: self-bias {bias:.1f} V over the second period")
+    assert -60.0 < bias < -20.0

@@ -95,14 +95,14 @@ def _cmp_species(gpu, ora, what=""):
 
 
 def _make_pair(w, og, P, parts, precision="fp64", extra_cap=0.3, mobile=(True, True),
-               model="em"):
-    g = og.grid_from_workload(w, model=model)
+               model="em", cap=0.0):
+    g = og.grid_from_workload(w, model=model, cap=cap)
     sp = []
     for k, d in enumerate(parts):
         n = len(d["r"])
         sp.append(g.species(d, cap=int(n * (1 + extra_cap)) + 256, role=k + 1,
                             mobile=mobile[k]))
-    ctx = P.context_from_workload(w, precision=precision, model=model)
+    ctx = P.context_from_workload(w, precision=precision, model=model, blocking_cap=cap)
     P.load_workload_species(ctx, parts, extra_cap=extra_cap, mobile=mobile)
     return g, sp, ctx
 
@@ -353,13 +353,13 @@ def test_step_parity_edge_cases(og, torch_cuda):
 
 
 def _step_parity(og, P, w, parts, nsteps, mcc=None, sort_every=0, mobile=(True, True),
-                 running_scale=False, model="em"):
+                 running_scale=False, model="em", cap=0.0):
     """Steps on both sides with the oracle's iteration counts.  Fields are
     compared against their largest value in this step, or with running_scale
     in any step so far (for runs whose drive is switched off: the fields then
     fall to the plasma's response and keep the absolute rounding of the
     driven steps)."""
-    g, sp, ctx = _make_pair(w, og, P, parts, mobile=mobile, model=model)
+    g, sp, ctx = _make_pair(w, og, P, parts, mobile=mobile, model=model, cap=cap)
     st = og.State(g)
     if mcc:
         ctx.set_mcc(mcc)
@@ -393,6 +393,10 @@ def _step_parity(og, P, w, parts, nsteps, mcc=None, sort_every=0, mobile=(True, 
         for k in range(2):
             assert d_g["ke"][k] == pytest.approx(d_o["ke"][k], rel=1e-12), "ke"
         assert d_g["w_drive"] == pytest.approx(d_o["w_drive"], rel=1e-9, abs=1e-30)
+        if cap > 0.0:
+            assert d_g["electrode_v"] == pytest.approx(st.phi, rel=1e-10, abs=1e-12)
+            assert d_g["cap_charge"] == pytest.approx(st.q_cap, rel=1e-10, abs=1e-30)
+            assert d_g["w_gen"] == pytest.approx(d_o["w_gen"], rel=1e-9, abs=1e-30)
     return worst
 
 

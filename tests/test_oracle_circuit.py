@@ -24,11 +24,12 @@ def _electrode_capacitance(og, w):
     """C_e: the charge on the powered plate's nodes per volt of plate
     potential, from one electrostatic solve of a plate step with no current
     (its Gauss charge, from the mesh tables)."""
-    g = og.grid_from_workload(w, model="es", drive_amp=(1.0,), drive_freq=(w.drive_freq[0],))
+    g = og.grid_from_workload(w, model="es", drive_amp=(1.0,), drive_freq=(w.drive_freq[0],),
+                              drive_phase=(0.0,))
     t = g.tables()
     u1 = g.field_solve(g.zeros_r(), g.zeros_z(), g.zeros_h(), g.zeros_r(), g.zeros_z(), 0.0)
     uz = u1[1].reshape(w.nr + 1, w.nz)
-    return float(np.sum(t["wz"] * uz[: w.nr, 0])) / g.drive(w.dt)
+    return float(np.sum(t["wz"] * uz[: w.nr, 0])) / (g.drive(w.dt) - g.drive(0.0))
 
 
 def _divider_error(og, model, f=F, steps=200):
