@@ -57,6 +57,8 @@ class Workload:
     T_gas: float = 300.0
     eps_max_ev: float = 1000.0
     seed: int = 1
+    port_i: int = 0  # > 0: the drive enters through a TEM port over r-edges port_i.. of the bottom wall
+    port_eps: float = 1.0  # relative permittivity of the port's line
 
     @property
     def n_per_species(self) -> int:
@@ -72,7 +74,7 @@ class Workload:
                     drive_amp=tuple(self.drive_amp), drive_freq=tuple(self.drive_freq),
                     drive_phase=tuple(self.drive_phase) if self.drive_phase
                     else tuple(0.0 for _ in self.drive_amp),
-                    drive_t_end=self.drive_t_end)
+                    drive_t_end=self.drive_t_end, port_i=self.port_i, port_eps=self.port_eps)
 
     def mcc_params(self) -> Optional[dict]:
         if self.pressure_pa <= 0:

@@ -60,7 +60,7 @@ class OgGrid(C.Structure):
                 ("drive_phase", C.c_double * 32), ("drive_t_end", C.c_double),
                 ("bz_ext", C.c_double), ("er_ext", C.c_double),
                 ("sub_tol", C.c_double), ("push_only", C.c_int32), ("model", C.c_int32),
-                ("cap", C.c_double)]
+                ("cap", C.c_double), ("port_i", C.c_int32), ("port_eps", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -77,7 +77,7 @@ class OgState(C.Structure):
     _fields_ = [("ur", _dp), ("uz", _dp), ("h", _dp), ("ur_prev", _dp), ("uz_prev", _dp),
                 ("wall_bot", _dp), ("wall_top", _dp), ("wall_side", _dp),
                 ("t", C.c_double), ("step", C.c_int64), ("phi", C.c_double),
-                ("phi_prev", C.c_double), ("q_cap", C.c_double)]
+                ("phi_prev", C.c_double), ("q_cap", C.c_double), ("hb", _dp)]
 
 
 class OgOpts(C.Structure):
@@ -100,7 +100,8 @@ class OgStats(C.Structure):
                 ("n_substeps", C.c_int64), ("n_crossings", C.c_int64), ("n_halvings", C.c_int64),
                 ("n_errors", C.c_int64), ("n_capped", C.c_int64), ("n_over_range", C.c_int64),
                 ("newton_iters", C.c_int32), ("krylov_iters", C.c_int32),
-                ("phi", C.c_double), ("q_cap", C.c_double), ("w_gen", C.c_double)]
+                ("phi", C.c_double), ("q_cap", C.c_double), ("w_gen", C.c_double),
+                ("port_v", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -149,6 +150,9 @@ def _declare(L):
     L.og_child_uid.restype = C.c_uint64
     L.og_threads.argtypes = []
     L.og_threads.restype = C.c_int
+    L.og_set_port_h.argtypes = [vp, _dp]
+    L.og_get_port_h.argtypes = [vp, _dp]
+    L.og_port_tables.argtypes = [vp, _dp, _dp]
 
 
 def _p(a: Optional[np.ndarray]):
@@ -210,11 +214,12 @@ class State:
         self.phi = 0.0       # electrode potential (blocking capacitor)
         self.phi_prev = 0.0
         self.q_cap = 0.0     # capacitor charge
+        self.hb = np.zeros(nr)  # port: H_theta on the wall under the port edges
 
     def struct(self) -> OgState:
         return OgState(_p(self.ur), _p(self.uz), _p(self.h), _p(self.ur_prev), _p(self.uz_prev),
                        _p(self.wall_bot), _p(self.wall_top), _p(self.wall_side), self.t, self.step,
-                       self.phi, self.phi_prev, self.q_cap)
+                       self.phi, self.phi_prev, self.q_cap, _p(self.hb))
 
     def copy(self) -> "State":
         s = State.__new__(State)
@@ -228,7 +233,8 @@ class Grid:
 
     def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
                  drive_phase=(), drive_t_end=0.0, self_b=False, bz_ext=0.0, er_ext=0.0,
-                 sub_tol=0.0, omp=False, push_only=False, model="em", cap=0.0):
+                 sub_tol=0.0, omp=False, push_only=False, model="em", cap=0.0, port_i=0,
+                 port_eps=1.0):
         L_ = lib(omp)
         g = OgGrid()
         g.nr, g.nz, g.R, g.L, g.xi_a, g.dt, g.eps, g.mu = nr, nz, R, L, xi_a, dt, eps, mu
@@ -243,6 +249,8 @@ class Grid:
         g.push_only = int(push_only)
         g.model = {"em": 0, "es": 1}[model]
         g.cap = cap
+        g.port_i, g.port_eps = port_i, port_eps
+        self.port_i, self.port_eps = port_i, port_eps
         self.desc = g
         self.nr, self.nz, self.R, self.L, self.xi_a, self.dt = nr, nz, R, L, xi_a, dt
         self.eps, self.mu = eps, mu
@@ -322,6 +330,22 @@ class Grid:
 
     def energy_norm2(self, ur, uz) -> float:
         return self._lib.og_energy_norm2(self._h, _p(ur), _p(uz))
+
+    def set_port_h(self, hb):
+        """H_b at t of the port edges (used by the next field_solve)."""
+        self._lib.og_set_port_h(self._h, _p(np.ascontiguousarray(hb, dtype=np.float64)))
+
+    def get_port_h(self):
+        """H_b at t + dt left by the last field_solve."""
+        out = np.zeros(self.nr)
+        self._lib.og_get_port_h(self._h, _p(out))
+        return out
+
+    def port_tables(self):
+        """(kappa[nr], wall potential profile[nr+1]) of the port."""
+        k, p = np.zeros(self.nr), np.zeros(self.nr + 1)
+        self._lib.og_port_tables(self._h, _p(k), _p(p))
+        return k, p
 
     def field_solve(self, ur0, uz0, h0, Ir, Iz, t):
         ur1, uz1, h1 = self.zeros_r(), self.zeros_z(), self.zeros_h()

@@ -61,6 +61,13 @@ struct og_ctx {
   double *rhs, *x, *tr, *tz; /* work                                 */
   int gap_set;              /* 1: the solves take the gap voltages below */
   double gap_now, gap_next; /* gap voltage at t^n and t^{n+1}            */
+  /* TEM port (Sec. 2.1, Eqs. (5), (7)), edges (i, 0), ip <= i < nr */
+  int ip;                   /* first port edge, 0: no port                */
+  double eta_p;             /* wave impedance of the line sqrt(mu/eps_l)  */
+  double *pk;               /* kappa: TEM share of the mouth voltage, nr  */
+  double *pg;               /* 1 / (w_b/dt + M/(2 eta l)), nr             */
+  double *pprof;            /* ES wall potential profile, nr+1            */
+  double *hb0, *hb1;        /* H_b at t^n (input), t^{n+1} (last solve)   */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -206,6 +213,12 @@ static int factorize(og_ctx* c) {
         add_entry(c, HC(i - 1, j), HC(i, j), -mm * mi * dinv);
       }
     }
+  /* port edges: the eliminated half-face voltage couples the wall cell to
+   * itself only */
+  for (int i = c->ip; c->ip > 0 && i < nr; ++i) {
+    const double m = 2.0 * OG_PI * c->rh[i];
+    add_entry(c, HC(i, 0), HC(i, 0), 0.5 * m * m * c->pg[i]);
+  }
   return chol_factor(c);
 }
 
@@ -283,11 +296,64 @@ static void chol_solve(og_ctx* c, const double* rhs, double* x) {
 /* ------------------------------------------------------------------------ */
 /* Setup                                                                     */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* TEM port (Sec. 2.1, Eqs. (5), (7))                                        */
+/* ------------------------------------------------------------------------ */
+/* The drive enters through a coaxial line, filled with a dielectric of
+ * permittivity eps_l = port_eps * eps, that meets the bottom wall over
+ * r_p = r(ip) <= r <= R.  The powered electrode is the wall r <= r_p.  Each
+ * port edge (i, 0), ip <= i < nr, is a free edge whose dual face is the half
+ * cell above the wall (capacitance w_b = wr/2, the half face og_gauss
+ * already uses), closed on the wall by the line's field H_b.  Ampere's law
+ * on that half face reads
+ *   w_b (u^{n+1} - u^n) / dt = -M (h^{n+1/2}(i,0) - H_b^{n+1/2}) - I_r(i,0),
+ * with M = 2 pi r_{i+1/2}.  Eq. (5) is the Mur condition for the wave
+ * leaving through the line; with the line's own Ampere law
+ * (d_z H = -eps_l d_t E_r) it becomes d_t (E_r + eta H_b) = d_t (2 E_r^+),
+ * eta = sqrt(mu / eps_l), where E_r^+ is the incoming wave.  Eq. (7) gives
+ * that wave from the electrode potential: half of phi, with the TEM radial
+ * profile 1/r, so that on edge i it carries kappa_i phi / 2 with
+ * kappa_i = ln(r_{i+1} / r_i) / ln(R / r_p) (the kappa_i add up to one).
+ * Integrated over the edge and centred in time:
+ *   (u^{n+1} - u^n) + eta l_i (H_b^{n+1} - H_b^n) = kappa_i (phi^{n+1} - phi^n).
+ * Eliminating H_b^{n+1/2} between the two:
+ *   u^{n+1} - u^n = g_i (-M h^{n+1/2} + M H_b^n + a_i dphi - I_r(i,0)),
+ *   g_i = 1 / (w_b / dt + M / (2 eta l_i)),  a_i = M kappa_i / (2 eta l_i),
+ * so the cell (i, 0) of the H_theta system gains M^2 g_i / 2 on its
+ * diagonal and the rest joins the right-hand side.  The line delivers
+ * dt M H_b^{n+1/2} u^{n+1/2} per edge and step, and the discrete energy
+ * balance holds with it exactly.  The condition constrains only changes:
+ * a static voltage across the mouth (E_r with H_b = 0) is allowed, as in
+ * the paper's differential form, so a dc self-bias is not drained.
+ *
+ * The electrostatic model takes the port as a Dirichlet wall with the
+ * static coaxial potential: 1 on the electrode's nodes, ln(R/r)/ln(R/r_p)
+ * on the mouth's (Sec. 2.2), times the electrode potential. */
+static void port_tables(og_ctx* c) {
+  const og_grid* g = &c->g;
+  const int nr = g->nr, ip = g->port_i;
+  c->ip = ip;
+  /* the electrostatic wall profile of the gap model: the whole bottom wall
+   * but its corner node with the side wall is powered */
+  for (int i = 0; i <= nr; ++i) c->pprof[i] = (i < nr) ? 1.0 : 0.0;
+  if (ip == 0) return;
+  c->eta_p = sqrt(g->mu / (g->eps * g->port_eps));
+  const double lnr = log(g->R / c->rn[ip]);
+  for (int i = ip; i < nr; ++i) {
+    const double M = 2.0 * OG_PI * c->rh[i];
+    c->pk[i] = log(c->rn[i + 1] / c->rn[i]) / lnr;
+    c->pg[i] = 1.0 / (0.5 * c->wr[i] / g->dt + M / (2.0 * c->eta_p * c->ell[i]));
+  }
+  for (int i = 0; i <= nr; ++i) c->pprof[i] = (i <= ip) ? 1.0 : log(g->R / c->rn[i]) / lnr;
+  c->pprof[nr] = 0.0;
+}
+
 int og_create(const og_grid* g, og_ctx** out) {
   if (!g || !out || g->nr < 1 || g->nz < 1 || !(g->R > 0) || !(g->L > 0) ||
       !(g->dt > 0) || !(g->eps > 0) || !(g->mu > 0) || g->xi_a < 0 || g->xi_a > g->nr ||
       !(g->cap >= 0.0) ||
-      (g->model != OG_EM && g->model != OG_ES) || (g->model == OG_ES && g->nz < 2))
+      (g->model != OG_EM && g->model != OG_ES) || (g->model == OG_ES && g->nz < 2) ||
+      g->port_i < 0 || (g->port_i > 0 && (g->port_i >= g->nr || !(g->port_eps > 0.0))))
     return -1;
   og_ctx* c = (og_ctx*)calloc(1, sizeof(og_ctx));
   if (!c) return -2;
@@ -312,8 +378,14 @@ int og_create(const og_grid* g, og_ctx** out) {
   c->x = (double*)malloc(sizeof(double) * (size_t)c->ncell);
   c->tr = (double*)malloc(sizeof(double) * (size_t)nr * (nz + 1));
   c->tz = (double*)malloc(sizeof(double) * (size_t)(nr + 1) * nz);
+  c->pk = (double*)calloc(nr, sizeof(double));
+  c->pg = (double*)calloc(nr, sizeof(double));
+  c->pprof = (double*)calloc(nr + 1, sizeof(double));
+  c->hb0 = (double*)calloc(nr, sizeof(double));
+  c->hb1 = (double*)calloc(nr, sizeof(double));
   if (!c->rn || !c->rh || !c->ell || !c->area || !c->azs || !c->wr || !c->wz ||
-      !c->chol || !c->rhs || !c->x || !c->tr || !c->tz) {
+      !c->chol || !c->rhs || !c->x || !c->tr || !c->tz || !c->pk || !c->pg || !c->pprof ||
+      !c->hb0 || !c->hb1) {
     og_destroy(c);
     return -2;
   }
@@ -328,6 +400,7 @@ int og_create(const og_grid* g, og_ctx** out) {
     c->wr[i] = g->eps * 2.0 * OG_PI * c->rh[i] * c->dz / c->ell[i];
     c->wz[i] = g->eps * c->azs[i] / c->dz;
   }
+  port_tables(c);
   if (!g->push_only && (g->model == OG_ES ? factorize_es(c) : factorize(c)) != 0) {
     og_destroy(c);
     return -3;
@@ -341,7 +414,22 @@ void og_destroy(og_ctx* c) {
   free(c->rn); free(c->rh); free(c->ell); free(c->area); free(c->azs);
   free(c->wr); free(c->wz); free(c->chol); free(c->rhs); free(c->x);
   free(c->tr); free(c->tz);
+  free(c->pk); free(c->pg); free(c->pprof); free(c->hb0); free(c->hb1);
   free(c);
+}
+
+void og_set_port_h(og_ctx* c, const double* hb) {
+  for (int i = c->ip; c->ip > 0 && i < c->g.nr; ++i) c->hb0[i] = hb[i];
+}
+
+void og_get_port_h(const og_ctx* c, double* hb) {
+  for (int i = c->ip; c->ip > 0 && i < c->g.nr; ++i) hb[i] = c->hb1[i];
+}
+
+void og_port_tables(const og_ctx* c, double* kappa, double* prof) {
+  if (c->ip == 0) return;
+  for (int i = 0; i < c->g.nr; ++i) if (kappa) kappa[i] = c->pk[i];
+  for (int i = 0; i <= c->g.nr; ++i) if (prof) prof[i] = c->pprof[i];
 }
 
 void og_tables(const og_ctx* c, double* rn, double* rh, double* area_c,
@@ -362,9 +450,12 @@ void og_tables(const og_ctx* c, double* rn, double* rh, double* area_c,
 /* ------------------------------------------------------------------------ */
 static void set_boundary(const og_ctx* c, double* ur, double* uz, double vd) {
   const int nr = c->g.nr, nz = c->g.nz;
-  for (int i = 0; i < nr; ++i) { ur[UR(i, 0)] = 0.0; ur[UR(i, nz)] = 0.0; }
+  for (int i = 0; i < nr; ++i) {
+    if (c->ip == 0 || i < c->ip) ur[UR(i, 0)] = 0.0; /* port edges are unknowns */
+    ur[UR(i, nz)] = 0.0;
+  }
   for (int j = 0; j < nz; ++j) uz[UZ(nr, j)] = 0.0;
-  ur[UR(nr - 1, 0)] = vd; /* drive gap between powered bottom plate and wall */
+  if (c->ip == 0) ur[UR(nr - 1, 0)] = vd; /* drive gap between powered plate and wall */
 }
 
 /* Electrostatic update (Sec. 2.2, Eq. (8)).  The deposit conserves charge,
@@ -387,21 +478,23 @@ static void field_solve_es(og_ctx* c, const double* ur0, const double* uz0,
       double div = Ir[UR(i, j)] + Iz[UZ(i, j)] - Iz[UZ(i, j - 1)];
       if (i > 0) div -= Ir[UR(i - 1, j)];
       double v = -dt * div;
-      if (j == 1) v += c->wz[i] * dv; /* the powered plate below */
+      if (j == 1) v += c->wz[i] * dv * c->pprof[i]; /* the powered wall below */
       b[PN(i, j)] = v;
     }
   chol_solve(c, b, c->x);
   /* dphi on every node, Dirichlet values included */
+  const double* pw = c->pprof;
   for (int i = 0; i < nr; ++i)
     for (int j = 0; j <= nz; ++j) {
-      const double pa = (j == 0) ? dv : (j == nz ? 0.0 : c->x[PN(i, j)]);
-      const double pb = (i + 1 == nr) ? 0.0 : ((j == 0) ? dv : (j == nz ? 0.0 : c->x[PN(i + 1, j)]));
+      const double pa = (j == 0) ? dv * pw[i] : (j == nz ? 0.0 : c->x[PN(i, j)]);
+      const double pb = (i + 1 == nr) ? 0.0
+                                      : ((j == 0) ? dv * pw[i + 1] : (j == nz ? 0.0 : c->x[PN(i + 1, j)]));
       ur1[UR(i, j)] = ur0[UR(i, j)] + (pa - pb);
     }
   for (int i = 0; i <= nr; ++i)
     for (int j = 0; j < nz; ++j) {
       if (i == nr) { uz1[UZ(i, j)] = 0.0; continue; }
-      const double pa = (j == 0) ? dv : c->x[PN(i, j)];
+      const double pa = (j == 0) ? dv * pw[i] : c->x[PN(i, j)];
       const double pb = (j + 1 == nz) ? 0.0 : c->x[PN(i, j + 1)];
       uz1[UZ(i, j)] = uz0[UZ(i, j)] + (pa - pb);
     }
@@ -431,7 +524,18 @@ int og_field_solve(og_ctx* c, const double* ur0, const double* uz0, const double
   for (int i = 0; i <= nr; ++i)
     for (int j = 0; j < nz; ++j)
       tz[UZ(i, j)] = (i < nr) ? uz0[UZ(i, j)] - dt * Iz[UZ(i, j)] / (2.0 * c->wz[i]) : 0.0;
-  tr[UR(nr - 1, 0)] = vh;
+  const double dphi = vnext - vnow;
+  if (c->ip == 0) {
+    tr[UR(nr - 1, 0)] = vh;
+  } else {
+    /* port edges: u^n plus the h-free part of their half-step change */
+    for (int i = c->ip; i < nr; ++i) {
+      const double M = 2.0 * OG_PI * c->rh[i];
+      const double a = M * c->pk[i] / (2.0 * c->eta_p * c->ell[i]);
+      tr[UR(i, 0)] = ur0[UR(i, 0)] +
+                     0.5 * c->pg[i] * (M * c->hb0[i] + a * dphi - Ir[UR(i, 0)]);
+    }
+  }
   og_curl_e(c, tr, tz, c->rhs);
   for (int i = 0; i < nr; ++i)
     for (int j = 0; j < nz; ++j) {
@@ -452,6 +556,13 @@ int og_field_solve(og_ctx* c, const double* ur0, const double* uz0, const double
       const double uh = uz0[UZ(i, j)] + dt * (tz[UZ(i, j)] - Iz[UZ(i, j)]) / (2.0 * c->wz[i]);
       uz1[UZ(i, j)] = 2.0 * uh - uz0[UZ(i, j)];
     }
+  for (int i = c->ip; c->ip > 0 && i < nr; ++i) {
+    const double M = 2.0 * OG_PI * c->rh[i];
+    const double a = M * c->pk[i] / (2.0 * c->eta_p * c->ell[i]);
+    const double du = c->pg[i] * (-M * c->x[HC(i, 0)] + M * c->hb0[i] + a * dphi - Ir[UR(i, 0)]);
+    ur1[UR(i, 0)] = ur0[UR(i, 0)] + du;
+    c->hb1[i] = c->hb0[i] + (c->pk[i] * dphi - du) / (c->eta_p * c->ell[i]);
+  }
   set_boundary(c, ur1, uz1, vnext);
   for (int64_t k = 0; k < c->ncell; ++k) h1[k] = 2.0 * c->x[k] - h0[k];
   return 0;
@@ -467,6 +578,8 @@ double og_energy_norm2(const og_ctx* c, const double* ur, const double* uz) {
     for (int j = 1; j < nz; ++j) s += c->wr[i] * ur[UR(i, j)] * ur[UR(i, j)];
   for (int i = 0; i < nr; ++i)
     for (int j = 0; j < nz; ++j) s += c->wz[i] * uz[UZ(i, j)] * uz[UZ(i, j)];
+  /* port edges: the half cell above the wall */
+  for (int i = c->ip; c->ip > 0 && i < nr; ++i) s += 0.5 * c->wr[i] * ur[UR(i, 0)] * ur[UR(i, 0)];
   return s;
 }
 
@@ -1233,6 +1346,7 @@ static double wdot(const og_ctx* c, const double* a, const double* b) {
     for (int j = 1; j < nz; ++j) s += c->wr[i] * a[UR(i, j)] * b[UR(i, j)];
   for (int i = 0; i < nr; ++i)
     for (int j = 0; j < nz; ++j) s += c->wz[i] * a[nur + UZ(i, j)] * b[nur + UZ(i, j)];
+  for (int i = c->ip; c->ip > 0 && i < nr; ++i) s += 0.5 * c->wr[i] * a[UR(i, 0)] * b[UR(i, 0)];
   return s;
 }
 
@@ -1361,7 +1475,10 @@ out:
 /* balance of the drive takes (the drive's work is dt V_gap^{1/2} I_e):       */
 /*   EM: 2 pi r_{nr-1/2} h^{n+1/2} of the gap cell + I_r of the gap edge;     */
 /*   ES: the change of the field flux leaving the plate's nodes over dt, the  */
-/*       particle current leaving them, and I_r of the gap edge.              */
+/*       particle current leaving them, and I_r of the gap edge;              */
+/*   with a port (either model): the displacement plus conduction current     */
+/*       through the z-edges of the electrode's face r <= r_p, as Eq. (6)     */
+/*       writes it (in EM, 2 pi r h^{n+1/2} of the first port cell).          */
 /* The electrode potential then follows from the capacitor charge:            */
 /* phi^{n+1} = V^{n+1} - (q^n + dt I_e) / C, iterated with the Picard         */
 /* iterates, and q^{n+1} = q^n + dt I_e for the accepted one.  The iteration */
@@ -1380,6 +1497,14 @@ static double electrode_current(const og_ctx* c, const og_state* st, const doubl
                                 const double* h1, const double* Ir, const double* Iz) {
   const int nr = c->g.nr, nz = c->g.nz;
   const double dt = c->g.dt;
+  if (c->ip > 0) {
+    /* Eq. (6) over the electrode's face r <= r_p: displacement plus
+     * conduction current through the z-edges on its nodes */
+    double s = 0.0;
+    for (int i = 0; i <= c->ip; ++i)
+      s += c->wz[i] * (uz1[UZ(i, 0)] - st->uz[UZ(i, 0)]) / dt + Iz[UZ(i, 0)];
+    return s;
+  }
   if (c->g.model == OG_ES) {
     double dq = 0.0, ip = 0.0;
     for (int i = 0; i < nr; ++i) {
@@ -1435,6 +1560,7 @@ int og_step(og_ctx* c, og_state* st, og_species* sp, int32_t nsp, const og_mcc* 
   memcpy(h1, st->h, sizeof(double) * nh);
   c->gap_set = circ;
   c->gap_now = st->phi;
+  if (c->ip > 0) og_set_port_h(c, st->hb);
   int k;
   int kmax = o->fixed_iter > 0 ? o->fixed_iter : o->max_iter;
   if (kmax > 64) kmax = 64;
@@ -1515,12 +1641,42 @@ accepted:
     double wio = 0.0;
     for (int i = 0; i < nr; ++i)
       for (int j = 1; j < nz; ++j) wio += 0.5 * (st->ur[UR(i, j)] + ur1[UR(i, j)]) * Ir[UR(i, j)];
+    for (int i = c->ip; c->ip > 0 && i < nr; ++i)
+      wio += 0.5 * (st->ur[UR(i, 0)] + ur1[UR(i, 0)]) * Ir[UR(i, 0)];
     for (int i = 0; i < nr; ++i)
       for (int j = 0; j < nz; ++j) wio += 0.5 * (st->uz[UZ(i, j)] + uz1[UZ(i, j)]) * Iz[UZ(i, j)];
     S->w_field_io = dt * wio;
     const double vgen = 0.5 * (og_drive(c, t) + og_drive(c, t + dt));
     const double vh = circ ? 0.5 * (st->phi + phi_used) : vgen;
-    if (c->g.model == OG_ES) {
+    if (c->ip > 0 && c->g.model == OG_ES) {
+      /* the source's work on the powered wall nodes (profile p): phi^{1/2}
+       * times sum p (change of the node's Gauss charge, port edges with
+       * their half faces, plus dt times the current leaving it) */
+      double sq = 0.0;
+      for (int i = 0; i <= nr; ++i) {
+        double dg = 0.0, dv = 0.0;
+        if (i < nr) {
+          dg += c->wz[i] * (uz1[UZ(i, 0)] - st->uz[UZ(i, 0)]);
+          dv += Iz[UZ(i, 0)] + Ir[UR(i, 0)];
+          if (i >= c->ip) dg += 0.5 * c->wr[i] * (ur1[UR(i, 0)] - st->ur[UR(i, 0)]);
+        }
+        if (i > 0) {
+          dv -= Ir[UR(i - 1, 0)];
+          if (i - 1 >= c->ip) dg -= 0.5 * c->wr[i - 1] * (ur1[UR(i - 1, 0)] - st->ur[UR(i - 1, 0)]);
+        }
+        sq += c->pprof[i] * (dg + dt * dv);
+      }
+      S->w_drive = vh * sq;
+    } else if (c->ip > 0) {
+      /* the power the line delivers through the mouth: M H_b u per edge at
+       * the half step (H_b at t^{n+1} from the solve of the accepted
+       * iterate, the last one made) */
+      double pw = 0.0;
+      for (int i = c->ip; i < nr; ++i)
+        pw += 2.0 * OG_PI * c->rh[i] * 0.5 * (st->hb[i] + c->hb1[i]) * 0.5 *
+              (st->ur[UR(i, 0)] + ur1[UR(i, 0)]);
+      S->w_drive = dt * pw;
+    } else if (c->g.model == OG_ES) {
       /* the source's work: V^{1/2} times the charge it moves onto the
        * powered plate's nodes (the change of their field flux plus the
        * current leaving them into the domain), plus the gap edge's share */
@@ -1551,6 +1707,14 @@ accepted:
     st->phi_prev = st->phi;
     st->phi = phi_used;
     st->q_cap += dt * ie;
+  }
+  if (c->ip > 0) {
+    double v = 0.0;
+    for (int i = c->ip; i < nr; ++i) {
+      if (c->g.model == OG_EM) st->hb[i] = c->hb1[i];
+      v += st->ur[UR(i, 0)];
+    }
+    S->port_v = v;
   }
   S->phi = st->phi;
   S->q_cap = st->q_cap;

@@ -45,6 +45,12 @@ typedef struct {
                                    electrode through a blocking capacitor of
                                    this capacitance [F] (Eq. (6)); the gap
                                    voltage is then the electrode potential   */
+  int32_t port_i;               /* > 0: the drive enters through a coaxial
+                                   TEM port on the bottom wall, r-edges
+                                   (i, 0) with port_i <= i < nr (the powered
+                                   electrode is r <= r(port_i)); 0: the
+                                   delta gap on the r-edge (nr-1, 0)         */
+  double port_eps;              /* relative permittivity of the port's line */
 } og_grid;
 
 #define OG_EM 0
@@ -68,6 +74,8 @@ typedef struct {
   int64_t step;                 /* n                                         */
   double phi, phi_prev;         /* electrode potential at t^n, t^{n-1} [V]   */
   double q_cap;                 /* blocking-capacitor charge at t^n [C]      */
+  double *hb;                   /* port: H_theta on the wall under every port
+                                   edge at t^n, [nr] (entries i >= port_i)   */
 } og_state;
 
 typedef struct {
@@ -119,6 +127,8 @@ typedef struct {
   double phi;                   /* electrode potential at t^{n+1} [V]        */
   double q_cap;                 /* capacitor charge at t^{n+1} [C]           */
   double w_gen;                 /* generator work dt V^{1/2} I_e [J]         */
+  double port_v;                /* port: voltage across the port's mouth at
+                                   t^{n+1}, sum of its edge voltages [V]     */
 } og_stats;
 
 typedef struct og_ctx og_ctx;
@@ -154,10 +164,22 @@ void og_curl_e(const og_ctx* c, const double* ur, const double* uz, double* ce);
 void og_curl_h(const og_ctx* c, const double* h, double* kr, double* kz);
 void og_div(const og_ctx* c, const double* fr, const double* fz, double* dnode);
 
-/* Crank-Nicolson field update from t to t+dt with the given currents. */
+/* Crank-Nicolson field update from t to t+dt with the given currents.
+ * With a port, its wall field H_b at t comes from og_set_port_h (zero at
+ * create), and the solve leaves H_b at t+dt for og_get_port_h. */
 int og_field_solve(og_ctx* c, const double* ur0, const double* uz0,
                    const double* h0, const double* Ir, const double* Iz,
                    double t, double* ur1, double* uz1, double* h1);
+
+/* Port (Sec. 2.1, Eqs. (5), (7)): the wall field H_b of the port edges,
+ * [nr] with entries i >= port_i, in and out of og_field_solve; the TEM
+ * share kappa[i] of the mouth voltage carried by port edge i (ln of its end
+ * radii over ln(R / r_p)), and the electrostatic model's wall potential
+ * profile prof[nr+1] (1 on the electrode, ln(R/r)/ln(R/r_p) across the
+ * mouth).  Both do nothing without a port. */
+void og_set_port_h(og_ctx* c, const double* hb);
+void og_get_port_h(const og_ctx* c, double* hb);
+void og_port_tables(const og_ctx* c, double* kappa, double* prof);
 
 /* One pass of the implicit push + charge-conserving deposit of one species in
  * the frozen half-step field (ur_h, uz_h, h_h).  commit=0 leaves the state
