@@ -107,6 +107,36 @@ typedef struct {
                              with plasma): meant for C well above C_e.  Not
                              with the JFNK solver.  0 = the generator drives
                              the gap directly. */
+  int32_t port_i;         /* > 0: the drive enters through a coaxial TEM port
+                             (Sec. 2.1, Eqs. (5), (7)) instead of the gap:
+                             a line filled with a dielectric of relative
+                             permittivity port_eps meets the bottom wall over
+                             the r-edges (i, 0), port_i <= i < nr
+                             (1 <= port_i < nr); the powered electrode is the
+                             wall r <= r(port_i).  EM: each port edge is a
+                             free edge on the half cell above the wall, closed
+                             by the line's wall field H_b (library state, zero
+                             at create; ecpic_set_port_field), with the Mur
+                             condition for the outgoing wave integrated over
+                             the edge:
+                               (u^{n+1} - u^n) + eta l (H_b^{n+1} - H_b^n)
+                                 = kappa (phi^{n+1} - phi^n),
+                             eta = sqrt(mu / (port_eps eps)), l the edge
+                             length, kappa = ln(r_{i+1}/r_i) / ln(R/r_p) the
+                             edge's share of the incoming TEM wave, phi the
+                             electrode potential (the generator voltage, or
+                             the blocking capacitor's electrode potential);
+                             the power through the mouth is the drive's work
+                             (w_drive).  ES: the port is the Dirichlet wall
+                             with the static coaxial potential phi
+                             ln(R/r)/ln(R/r_p) across the mouth (Sec. 2.2).
+                             With the capacitor, I_e is Eq. (6)'s current
+                             through the electrode's face r <= r_p (EM: the
+                             Ampere loop 2 pi r h^{n+1/2} of the first port
+                             cell).  Particles reaching the mouth stick to it:
+                             they leave the plasma and their charge is
+                             tallied on the wall nodes.  0 = the delta gap. */
+  double port_eps;        /* relative permittivity of the port's line (> 0)  */
 } ecpic_grid_desc;
 
 typedef struct {
@@ -205,6 +235,8 @@ typedef struct {
   double w_gen;           /* blocking capacitor: the generator's work
                              dt V^{1/2} I_e [J] (= w_drive + the capacitor's
                              energy change)                                  */
+  double port_v;          /* port: voltage across its mouth at t^{n+1}, the
+                             sum of the port edges' voltages [V]             */
 } ecpic_step_stats;
 
 typedef struct ecpic_ctx ecpic_ctx;
@@ -275,6 +307,13 @@ ecpic_status ecpic_read_particles(ecpic_ctx* ctx, int32_t sid, double* xi, doubl
 ecpic_status ecpic_set_fields(ecpic_ctx* ctx, const double* ur, const double* uz, const double* h,
                               const double* ur_prev, const double* uz_prev, double t, int64_t step);
 ecpic_status ecpic_get_fields(ecpic_ctx* ctx, double* ur, double* uz, double* h);
+
+/* The TEM port's wall field H_b at t^n (Sec. 2.1, Eq. (5); see port_i):
+ * hb[nr] (host), entries i >= port_i used, the others ignored (set) or
+ * zero (get).  The field solves and steps read it; a committed EM step
+ * moves it to t^{n+1}.  EINVAL without a port.  (host, synchronises) */
+ecpic_status ecpic_set_port_field(ecpic_ctx* ctx, const double* hb);
+ecpic_status ecpic_get_port_field(ecpic_ctx* ctx, double* hb);
 
 /* Set the frozen half-step field u^{n+1/2} used by ecpic_push_deposit. (device) */
 ecpic_status ecpic_set_half_field(ecpic_ctx* ctx, const double* ur_half, const double* uz_half);

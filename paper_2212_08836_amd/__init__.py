@@ -41,7 +41,7 @@ class GridDesc(C.Structure):
                 ("mu", C.c_double), ("n_drive", C.c_int32), ("model", C.c_int32),
                 ("drive_amp", C.c_double * 32), ("drive_freq", C.c_double * 32),
                 ("drive_phase", C.c_double * 32), ("drive_t_end", C.c_double),
-                ("blocking_cap", C.c_double)]
+                ("blocking_cap", C.c_double), ("port_i", C.c_int32), ("port_eps", C.c_double)]
 
 
 class SpeciesDesc(C.Structure):
@@ -78,7 +78,8 @@ class StepStats(C.Structure):
                 ("t", C.c_double), ("step", C.c_int64), ("continuity_max", C.c_double),
                 ("gauss_max", C.c_double), ("q_max", C.c_double),
                 ("newton_iters", C.c_int32), ("krylov_iters", C.c_int32),
-                ("electrode_v", C.c_double), ("cap_charge", C.c_double), ("w_gen", C.c_double)]
+                ("electrode_v", C.c_double), ("cap_charge", C.c_double), ("w_gen", C.c_double),
+                ("port_v", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -128,6 +129,8 @@ def lib() -> C.CDLL:
                                                                       C.POINTER(C.c_int64)], st),
             "ecpic_set_fields": ([_vp] + [_dp] * 5 + [C.c_double, C.c_int64], st),
             "ecpic_get_fields": ([_vp, _dp, _dp, _dp], st),
+            "ecpic_set_port_field": ([_vp, _dp], st),
+            "ecpic_get_port_field": ([_vp, _dp], st),
             "ecpic_set_half_field": ([_vp, _dp, _dp], st),
             "ecpic_push_deposit": ([_vp, C.c_int32, _dp, _dp], st),
             "ecpic_field_solve": ([_vp] + [_dp] * 5 + [C.c_double] + [_dp] * 3, st),
@@ -180,7 +183,8 @@ class Context:
 
     def __init__(self, nr, nz, R, L, xi_a, dt, eps, mu, drive_amp=(), drive_freq=(),
                  drive_phase=(), drive_t_end=0.0, precision: str = "fp64", device: str = "cuda",
-                 model: str = "em", blocking_cap: float = 0.0):
+                 model: str = "em", blocking_cap: float = 0.0, port_i: int = 0,
+                 port_eps: float = 1.0):
         """The context allocates no device memory until its first device call;
         call :meth:`bind_workspace` after the last :meth:`add_species` to give
         it a torch-allocated region instead."""
@@ -199,6 +203,7 @@ class Context:
         g.drive_t_end = drive_t_end
         g.model = {"em": ECPIC_MODEL_EM, "es": ECPIC_MODEL_ES}[model]
         g.blocking_cap = blocking_cap
+        g.port_i, g.port_eps = port_i, port_eps
         self.desc = g
         stream = torch.cuda.current_stream(self.device).cuda_stream
         h = _vp()
@@ -324,6 +329,17 @@ class Context:
         self._check(self.L.ecpic_get_fields(self.h, _ptr(ur), _ptr(uz), _ptr(h)), self.h)
         self.torch.cuda.synchronize()
         return ur.cpu().numpy(), uz.cpu().numpy(), h.cpu().numpy()
+
+    def set_port_field(self, hb):
+        """The TEM port's wall field H_b at t^n, [nr] (entries from port_i on)."""
+        a = np.ascontiguousarray(hb, dtype=np.float64)
+        assert a.size == self.nr
+        self._check(self.L.ecpic_set_port_field(self.h, a.ctypes.data_as(_dp)), self.h)
+
+    def get_port_field(self):
+        out = np.zeros(self.nr)
+        self._check(self.L.ecpic_get_port_field(self.h, out.ctypes.data_as(_dp)), self.h)
+        return out
 
     def set_half_field(self, ur_h, uz_h):
         f = self.torch.float64

@@ -34,13 +34,7 @@ ecpic_status fail(Ctx& c, ecpic_status s, const std::string& msg) {
   return s;
 }
 
-double drive(const ecpic_grid_desc& g, double t) {
-  double v = 0.0;
-  if (g.drive_t_end > 0.0 && t >= g.drive_t_end) return 0.0;
-  for (int k = 0; k < g.n_drive && k < 32; ++k)
-    v += g.drive_amp[k] * std::sin(2.0 * kPi * g.drive_freq[k] * t + g.drive_phase[k]);
-  return v;
-}
+double drive(const ecpic_grid_desc& g, double t) { return drive_voltage(g, t); }
 
 double r_of_xi(const MapP& m, double xi) {
   if (xi < m.xi_a) return 2.0 * m.s * std::sqrt(xi * m.xi_a);
@@ -144,6 +138,17 @@ void carve_all(Ctx& c, Carver& k) {
   k.take(&S.tri_lo, (size_t)nz * nr);
   k.take(&S.tri_inv, (size_t)nz * nr);
   k.take(&S.tri_up, nr);
+  k.take(&S.prof, nr + 1);
+  if (c.g.port_i > 0) {
+    const size_t mp = (size_t)(nr - c.g.port_i);
+    k.take(&S.port_pc, 4 * (size_t)nr);
+    k.take(&c.port_hb, nr);
+    if (c.g.model == ECPIC_MODEL_EM) {
+      k.take(&S.port_F, mp * mp);
+      k.take(&S.port_q0, nz);
+      k.take(&S.port_z, mp);
+    }
+  }
   k.take(&S.work0, nh);
   k.take(&S.work1, nh);
   k.take(&S.partial, kPartLen);
@@ -295,12 +300,92 @@ hipError_t setup_solver(Ctx& c) {
       }
     }
   }
+  // TEM port (Sec. 2.1, Eqs. (5), (7)): the electrostatic wall profile, the
+  // per-edge tables, and for EM the Woodbury coupling of the port's diagonal
+  // d_i = M_i^2 g_i / 2 on the wall cells (i, 0), i >= ip:
+  // F = (D^-1 + U^T A0^-1 U)^-1, where the port block of A0^-1 is
+  // sum_k Q[k][0]^2 T_k^-1 restricted to the port rows.
+  const int ip = c.g.port_i;
+  std::vector<double> prof(nr + 1), pc, Fm, q0;
+  for (int i = 0; i <= nr; ++i) prof[i] = (i < nr) ? 1.0 : 0.0;
+  if (ip > 0) {
+    const int mp = nr - ip;
+    const double lnr = std::log(c.g.R / rn[ip]);
+    for (int i = 0; i <= nr; ++i) prof[i] = (i <= ip) ? 1.0 : std::log(c.g.R / rn[i]) / lnr;
+    prof[nr] = 0.0;
+    const double eta = std::sqrt(mu / (eps * c.g.port_eps));
+    pc.assign(4 * (size_t)nr, 0.0);
+    std::vector<double> dg(mp);
+    for (int i = ip; i < nr; ++i) {
+      const double M = 2.0 * kPi * rh[i];
+      const double kap = std::log(rn[i + 1] / rn[i]) / lnr;
+      const double g = 1.0 / (0.5 * wr[i] / dt + M / (2.0 * eta * ell[i]));
+      pc[kPortG * (size_t)nr + i] = g;
+      pc[kPortA * (size_t)nr + i] = M * kap / (2.0 * eta * ell[i]);
+      pc[kPortK * (size_t)nr + i] = kap;
+      pc[kPortIEL * (size_t)nr + i] = 1.0 / (eta * ell[i]);
+      dg[i - ip] = 0.5 * M * M * g;
+    }
+    if (c.g.model == ECPIC_MODEL_EM) {
+      std::vector<double> C((size_t)mp * mp, 0.0), y(nr), x(nr + 1);
+      q0.resize(nz);
+      for (int k = 0; k < nz; ++k) {
+        q0[k] = Q[(size_t)k * nz];
+        const double w = q0[k] * q0[k];
+        const double* L = lo.data() + (size_t)k * nr;
+        const double* Iv = inv.data() + (size_t)k * nr;
+        for (int p = 0; p < mp; ++p) {
+          // T_k x = e_{ip+p}: forward from row ip+p, backward down to row ip
+          for (int i = ip; i < ip + p; ++i) y[i] = 0.0;
+          y[ip + p] = 1.0;
+          for (int i = ip + p + 1; i < nr; ++i) y[i] = -L[i] * y[i - 1];
+          x[nr] = 0.0;
+          for (int i = nr - 1; i >= ip; --i)
+            x[i] = Iv[i] * (y[i] - (i + 1 < nr ? To[i + 1] : 0.0) * x[i + 1]);
+          for (int q = 0; q < mp; ++q) C[(size_t)q * mp + p] += w * x[ip + q];
+        }
+      }
+      for (int q = 0; q < mp; ++q) C[(size_t)q * mp + q] += 1.0 / dg[q];
+      // F = C^-1 by Cholesky (C is SPD), column by column
+      for (int j = 0; j < mp; ++j) {
+        for (int q = 0; q < j; ++q) {
+          double v = C[(size_t)j * mp + q];
+          for (int t = 0; t < q; ++t) v -= C[(size_t)j * mp + t] * C[(size_t)q * mp + t];
+          C[(size_t)j * mp + q] = v / C[(size_t)q * mp + q];
+        }
+        double d = C[(size_t)j * mp + j];
+        for (int t = 0; t < j; ++t) d -= C[(size_t)j * mp + t] * C[(size_t)j * mp + t];
+        if (!(d > 0.0)) return hipErrorInvalidValue;
+        C[(size_t)j * mp + j] = std::sqrt(d);
+      }
+      Fm.assign((size_t)mp * mp, 0.0);
+      std::vector<double> b(mp);
+      for (int col = 0; col < mp; ++col) {
+        for (int q = 0; q < mp; ++q) b[q] = (q == col) ? 1.0 : 0.0;
+        for (int q = 0; q < mp; ++q) {
+          double v = b[q];
+          for (int t = 0; t < q; ++t) v -= C[(size_t)q * mp + t] * b[t];
+          b[q] = v / C[(size_t)q * mp + q];
+        }
+        for (int q = mp - 1; q >= 0; --q) {
+          double v = b[q];
+          for (int t = q + 1; t < mp; ++t) v -= C[(size_t)t * mp + q] * b[t];
+          b[q] = v / C[(size_t)q * mp + q];
+        }
+        for (int q = 0; q < mp; ++q) Fm[(size_t)q * mp + col] = b[q];
+      }
+    }
+  }
   SolverDev& S = c.sol;
   hipError_t e;
   auto up = [&](double* d, const std::vector<double>& h) -> hipError_t {
     return hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
                           c.stream);
   };
+  if ((e = up(S.prof, prof)) != hipSuccess) return e;
+  if (ip > 0 && (e = up(S.port_pc, pc)) != hipSuccess) return e;
+  if (!Fm.empty() && (e = up(S.port_F, Fm)) != hipSuccess) return e;
+  if (!q0.empty() && (e = up(S.port_q0, q0)) != hipSuccess) return e;
   if ((e = up(S.rh, rh)) != hipSuccess) return e;
   if ((e = up(S.wr, wr)) != hipSuccess) return e;
   if ((e = up(S.wz, wz)) != hipSuccess) return e;
@@ -588,6 +673,14 @@ ecpic_status finish_tally(Ctx& c, Tally& t) {
 
 namespace ecpic {
 
+double drive_voltage(const ecpic_grid_desc& g, double t) {
+  double v = 0.0;
+  if (g.drive_t_end > 0.0 && t >= g.drive_t_end) return 0.0;
+  for (int k = 0; k < g.n_drive && k < 32; ++k)
+    v += g.drive_amp[k] * std::sin(2.0 * kPi * g.drive_freq[k] * t + g.drive_phase[k]);
+  return v;
+}
+
 // Assign every device array (from the bound workspace, or from one block of
 // the library's own), upload the solver tables and clear the state.  Done
 // once, at the first call that needs the device.
@@ -620,6 +713,7 @@ ecpic_status materialise(Ctx& c) {
   for (int q = 0; q < 17; ++q) HIPCHK(launch_zero(zs[q], zn[q], c.stream));
   HIPCHK(launch_zero_i(c.stop, 2, c.stream));
   HIPCHK(launch_zero(c.circ, kCircLen, c.stream));
+  if (c.port_hb) HIPCHK(launch_zero(c.port_hb, c.g.nr, c.stream));
   HIPCHK(launch_zero_i(c.qcount, 2 * kQCount, c.stream));
   HIPCHK(launch_zero(c.wall_bot, wall_len(c), c.stream));
   HIPCHK(launch_zero(c.wall_scr, 2 * wall_len(c), c.stream));
@@ -673,7 +767,9 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
       (g->model != ECPIC_MODEL_EM && g->model != ECPIC_MODEL_ES) ||
       !(g->blocking_cap >= 0.0) || !std::isfinite(g->blocking_cap) ||
       (g->model == ECPIC_MODEL_ES && g->nz < 2) ||
-      (int64_t)g->nr * g->nz > (int64_t)1 << 28)
+      (int64_t)g->nr * g->nz > (int64_t)1 << 28 || g->port_i < 0 ||
+      (g->port_i > 0 && (g->port_i >= g->nr || !(g->port_eps > 0.0) ||
+                         !std::isfinite(g->port_eps))))
     return ECPIC_EINVAL;
   ecpic_ctx* x = new (std::nothrow) ecpic_ctx();
   if (!x) return ECPIC_ENOMEM;
@@ -691,6 +787,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
   c.m.inv_dz = 1.0 / c.m.dz;
   c.m.dt = g->dt;
   c.m.i_lin = (int)std::ceil(g->xi_axis);
+  c.m.ip = g->port_i;
   // host memory the device writes or the host reads back (pinned); device
   // memory waits for the first use or a bound workspace
   bool ok = true;
@@ -948,6 +1045,30 @@ ecpic_status ecpic_get_fields(ecpic_ctx* x, double* ur, double* uz, double* h) {
   return ECPIC_OK;
 }
 
+ecpic_status ecpic_set_port_field(ecpic_ctx* x, const double* hb) {
+  if (!x || !hb) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  if (c.g.port_i <= 0) return fail(c, ECPIC_EINVAL, "no port");
+  ENSURE_DEVICE(c);
+  std::vector<double> h(hb, hb + c.g.nr);
+  for (int i = 0; i < c.g.port_i; ++i) h[i] = 0.0;
+  HIPCHK(hipMemcpyAsync(c.port_hb, h.data(), sizeof(double) * c.g.nr, hipMemcpyHostToDevice,
+                        c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_get_port_field(ecpic_ctx* x, double* hb) {
+  if (!x || !hb) return ECPIC_EINVAL;
+  Ctx& c = x->c;
+  if (c.g.port_i <= 0) return fail(c, ECPIC_EINVAL, "no port");
+  ENSURE_DEVICE(c);
+  HIPCHK(hipMemcpyAsync(hb, c.port_hb, sizeof(double) * c.g.nr, hipMemcpyDeviceToHost,
+                        c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  return ECPIC_OK;
+}
+
 ecpic_status ecpic_set_half_field(ecpic_ctx* x, const double* urh, const double* uzh) {
   if (!x || !urh || !uzh) return ECPIC_EINVAL;
   Ctx& c = x->c;
@@ -1049,6 +1170,7 @@ static ecpic_status enqueue_solve(Ctx& c, int k, double tol, bool guarded, bool 
   a.uz1 = c.uz_nx;
   a.h1 = c.h_nx;
   a.gapv = c.g.blocking_cap > 0.0 ? c.circ + 3 : nullptr;
+  a.phin = (c.g.blocking_cap > 0.0 && c.g.port_i > 0) ? c.circ : nullptr;
   a.ur_old = c.ur_it;
   a.uz_old = c.uz_it;
   a.part = c.sol.partial + kOffRes;
@@ -1760,7 +1882,14 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
   S->cap_charge = circ ? fin.q_1 : 0.0;
   S->w_gen = circ ? c.g.dt * vgen * fin.ie : 0.0;
   S->w_field_io = c.g.dt * fin.xs;
-  if (c.g.model == ECPIC_MODEL_ES)
+  S->port_v = fin.port_v;
+  if (c.g.port_i > 0 && c.g.model == ECPIC_MODEL_ES)
+    // the source's work on the powered wall nodes, weighted by the wall profile
+    S->w_drive = vh * (fin.qp_delta + c.g.dt * fin.iz_plate);
+  else if (c.g.port_i > 0)
+    // the power the line delivered through the mouth
+    S->w_drive = fin.port_w;
+  else if (c.g.model == ECPIC_MODEL_ES)
     // the source's work: V^{1/2} times the charge it moves onto the powered
     // plate (the change of the plate nodes' field flux and the current
     // leaving them), plus the gap edge's share

@@ -136,13 +136,14 @@ __global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restric
                                                  const double* __restrict__ gapv,
                                                  const double* __restrict__ Qt,
                                                  double* __restrict__ hat,
-                                                 const int32_t* __restrict__ stop) {
+                                                 const int32_t* __restrict__ stop, PortDev P) {
   if (stop && *stop) return;
   extern __shared__ double sh[];  // kRB rows of the right-hand side, then the part sums
   const int nr = m.nr, nz = m.nz;
   // blocking capacitor: the gap's half-step voltage from the electrode's
   // potential at t^n (u0's gap edge) and the circuit's current iterate
-  if (gapv) vhalf = 0.5 * (ur0[(int64_t)(nr - 1) * (nz + 1)] + gapv[0]);
+  if (gapv && P.ip == 0) vhalf = 0.5 * (ur0[(int64_t)(nr - 1) * (nz + 1)] + gapv[0]);
+  const double dphi = port_dphi(P);
   const int i0 = blockIdx.x * kRB;
   const int rows = min(kRB, nr - i0);
   const int k0 = blockIdx.y * kCC;
@@ -158,10 +159,19 @@ __global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restric
     const double* Irr = Ir + (int64_t)i * (nz + 1);
     // r-edges j (bottom) and j+1 (top) of cell (i, j)
     double rb, rt;
-    if (j == 0)
-      rb = (i == nr - 1) ? vhalf : 0.0;
-    else
+    if (j == 0) {
+      if (P.ip == 0) {
+        rb = (i == nr - 1) ? vhalf : 0.0;
+      } else if (i >= P.ip) {
+        // port edge: u^n plus the h-free part of its half-step change
+        const double g = P.pc[kPortG * nr + i], pa = P.pc[kPortA * nr + i];
+        rb = urr[0] + 0.5 * g * (mi * P.hb[i] + pa * dphi - Irr[0]);
+      } else {
+        rb = 0.0;
+      }
+    } else {
       rb = urr[j] - Irr[j] * iwr;
+    }
     if (j + 1 == nz)
       rt = 0.0;
     else
@@ -211,11 +221,17 @@ __device__ Aff block_exscan(Aff v, bool reverse, Aff* sA) {
 
 constexpr int kMaxE = 8;  // rows per thread: nr <= kFB * kMaxE
 
+// kCorr: the port's correction pass.  The right-hand side of mode k is
+// q0[k] z on the port rows (zero elsewhere) and the solution is subtracted
+// from hat (x = y - A0^-1 U z).
+template <bool kCorr>
 __global__ void __launch_bounds__(kFB) k_tri_scan(int nr, const double* __restrict__ lo,
                                                   const double* __restrict__ inv,
                                                   const double* __restrict__ up,
                                                   double* __restrict__ hat,
-                                                  const int32_t* __restrict__ stop) {
+                                                  const int32_t* __restrict__ stop, int ip,
+                                                  const double* __restrict__ q0,
+                                                  const double* __restrict__ zq) {
   if (stop && *stop) return;
   __shared__ Aff sA[kFB];
   const int k = blockIdx.x;
@@ -228,10 +244,11 @@ __global__ void __launch_bounds__(kFB) k_tri_scan(int nr, const double* __restri
   double y[kMaxE];
   // forward: y_i = -l_i y_{i-1} + d_i (l_0 = 0)
   Aff f{1.0, 0.0};
+  const double qk = kCorr ? q0[k] : 0.0;
   for (int q = 0; q < E; ++q) {
     const int i = i0 + q;
     if (i < i1) {
-      y[q] = x[i];
+      y[q] = kCorr ? (i >= ip ? qk * zq[i - ip] : 0.0) : x[i];
       const Aff g{i == 0 ? 0.0 : -L[i], y[q]};
       f = compose(g, f);
     }
@@ -263,8 +280,64 @@ __global__ void __launch_bounds__(kFB) k_tri_scan(int nr, const double* __restri
     if (i < i1) {
       const double c = (i + 1 < nr) ? -Iv[i] * up[i + 1] : 0.0;
       xn = fma(c, xn, Iv[i] * y[q]);
-      x[i] = xn;
+      x[i] = kCorr ? x[i] - xn : xn;
     }
+  }
+}
+
+// The port's coupling: p = U^T y (the wall cells (i, 0), i >= ip, of the
+// first solve, y(i, 0) = sum_k q0[k] yhat[k][i]) and z = F p, in one block
+// (m = nr - ip <= kFB kMaxE).  Each row's sum is split over P parts of the
+// block's threads and the parts are added in order (deterministic).
+constexpr int kPortThreads = 1024;
+__global__ void __launch_bounds__(kPortThreads) k_port_couple(int nr, int nz, int ip,
+                                                              const double* __restrict__ hat,
+                                                              const double* __restrict__ q0,
+                                                              const double* __restrict__ F,
+                                                              double* __restrict__ zq,
+                                                              const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  __shared__ double pv[kFB * kMaxE];
+  __shared__ double ps[kPortThreads];
+  const int m = nr - ip;
+  const int P = m >= kPortThreads ? 1 : kPortThreads / m;
+  for (int base = 0; base < m; base += kPortThreads) {
+    const int rows = min(m - base, kPortThreads);
+    const int parts = rows >= kPortThreads ? 1 : min(P, kPortThreads / rows);
+    const int t = threadIdx.x, r = t % rows, q = t / rows;
+    double acc = 0.0;
+    if (q < parts) {
+      const int k0 = q * nz / parts, k1 = (q + 1) * nz / parts;
+      const double* col = hat + ip + base + r;
+      for (int k = k0; k < k1; ++k) acc = fma(q0[k], col[(int64_t)k * nr], acc);
+      ps[q * rows + r] = acc;
+    }
+    __syncthreads();
+    if (t < rows) {
+      double v = ps[t];
+      for (int u = 1; u < parts; ++u) v += ps[u * rows + t];
+      pv[base + t] = v;
+    }
+    __syncthreads();
+  }
+  for (int base = 0; base < m; base += kPortThreads) {
+    const int rows = min(m - base, kPortThreads);
+    const int parts = rows >= kPortThreads ? 1 : min(P, kPortThreads / rows);
+    const int t = threadIdx.x, r = t % rows, q = t / rows;
+    if (q < parts) {
+      const int c0 = q * m / parts, c1 = (q + 1) * m / parts;
+      double acc = 0.0;
+      // F symmetric: column base + r read as a row, coalesced over r
+      for (int cc = c0; cc < c1; ++cc) acc = fma(F[(int64_t)cc * m + base + r], pv[cc], acc);
+      ps[q * rows + r] = acc;
+    }
+    __syncthreads();
+    if (t < rows) {
+      double v = ps[t];
+      for (int u = 1; u < parts; ++u) v += ps[u * rows + t];
+      zq[base + t] = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -295,7 +368,8 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
                                                       const double* __restrict__ wr,
                                                       const double* __restrict__ wz,
                                                       const double* __restrict__ Q,
-                                                      const double* __restrict__ hat) {
+                                                      const double* __restrict__ hat,
+                                                      PortDev P) {
   if (a.stop && *a.stop) return;
   constexpr int R1 = kRB + 1;  // rows i0 - 1 .. i0 + kRB - 1
   extern __shared__ double sh[];
@@ -326,6 +400,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
   const double hdt = 0.5 * m.dt;
   const double two_pi = 2.0 * kPi;
   const double vnext = a.gapv ? a.gapv[0] : a.vnext;
+  const double dphi = port_dphi(P);
   double s0 = 0.0, s1 = 0.0;
   // r-edges j0 .. j0+nj-1 of the rows, and the top-wall edge nz in the last chunk
   const int ne = nj + (j0 + nj == nz ? 1 : 0);
@@ -334,8 +409,20 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
     const double* xr = xs + (r + 1) * nx - jlo;  // xr[j] = x[i][j]
     const int64_t g = (int64_t)i * (nz + 1) + j;
     double v;
-    if (j == 0) {
-      v = (i == nr - 1) ? vnext : 0.0;
+    if (j == 0 && P.ip > 0 && i >= P.ip) {
+      // port edge: its change from h^{n+1/2} of the wall cell
+      const double M = two_pi * rh[i];
+      const double du = P.pc[kPortG * nr + i] *
+                        (-M * xr[0] + M * P.hb[i] + P.pc[kPortA * nr + i] * dphi - a.Ir[g]);
+      v = a.ur0[g] + du;
+      if (a.part) {
+        const double w = 0.5 * wr[i];
+        const double d = v - a.ur_old[g];
+        s0 += w * d * d;
+        s1 += w * v * v;
+      }
+    } else if (j == 0) {
+      v = (P.ip == 0 && i == nr - 1) ? vnext : 0.0;
     } else if (j == nz) {
       v = 0.0;
     } else {
@@ -420,11 +507,13 @@ __global__ void __launch_bounds__(kFB) k_es_rhs_dst(MapP m, const double* __rest
                                                     const double* __restrict__ ur0,
                                                     const double* __restrict__ St,
                                                     double* __restrict__ hat,
-                                                    const int32_t* __restrict__ stop) {
+                                                    const int32_t* __restrict__ stop,
+                                                    const double* __restrict__ prof,
+                                                    const double* __restrict__ phin) {
   if (stop && *stop) return;
   extern __shared__ double sh[];  // kRB rows of the right-hand side, then the part sums
   const int nr = m.nr, nz = m.nz, nf = nz - 1;
-  if (gapv) dv = gapv[0] - ur0[(int64_t)(nr - 1) * (nz + 1)];
+  if (gapv) dv = gapv[0] - (phin ? phin[0] : ur0[(int64_t)(nr - 1) * (nz + 1)]);
   const int i0 = blockIdx.x * kRB;
   const int rows = min(kRB, nr - i0);
   const int k0 = blockIdx.y * kCC;
@@ -436,7 +525,7 @@ __global__ void __launch_bounds__(kFB) k_es_rhs_dst(MapP m, const double* __rest
     double div = Irr[j] + Izr[j] - Izr[j - 1];
     if (i > 0) div -= Irr[j - (nz + 1)];
     double v = -m.dt * div;
-    if (j == 1) v += wz[i] * dv;
+    if (j == 1) v += wz[i] * dv * prof[i];  // the powered wall below
     sh[r * nf + jj] = v;
   }
   __syncthreads();
@@ -457,14 +546,15 @@ __global__ void __launch_bounds__(kFB) k_es_recover(SolveArgs a, MapP m,
                                                     const double* __restrict__ wr,
                                                     const double* __restrict__ wz,
                                                     const double* __restrict__ S,
-                                                    const double* __restrict__ hat, double dv) {
+                                                    const double* __restrict__ hat, double dv,
+                                                    const double* __restrict__ prof) {
   if (a.stop && *a.stop) return;
   constexpr int R1 = kRB + 1;  // rows i0 .. i0 + kRB
   constexpr int XS = kCC + 1;  // node columns j0 .. j0 + nj
   extern __shared__ double sh[];
   const int nr = m.nr, nz = m.nz, nf = nz - 1;
   const double vnext = a.gapv ? a.gapv[0] : a.vnext;
-  if (a.gapv) dv = a.gapv[0] - a.ur0[(int64_t)(nr - 1) * (nz + 1)];
+  if (a.gapv) dv = a.gapv[0] - (a.phin ? a.phin[0] : a.ur0[(int64_t)(nr - 1) * (nz + 1)]);
   const int i0 = blockIdx.x * kRB;
   const int rows = min(kRB, nr - i0);
   const int j0 = blockIdx.y * kCC;
@@ -489,7 +579,7 @@ __global__ void __launch_bounds__(kFB) k_es_recover(SolveArgs a, MapP m,
     if (i >= nr || j == nz)
       x = 0.0;  // grounded wall row, top plate (and the corners)
     else if (j == 0)
-      x = dv;   // the powered plate
+      x = dv * prof[i];  // the powered wall (electrode and port mouth)
     else
       x = chunk_total(psum, nc, r, j - jf_lo, R1);
     xs[r * XS + jn] = x;
@@ -501,8 +591,17 @@ __global__ void __launch_bounds__(kFB) k_es_recover(SolveArgs a, MapP m,
     const int r = e / ne, jn = e - r * ne, j = j0 + jn, i = i0 + r;
     const int64_t g = (int64_t)i * (nz + 1) + j;
     double v;
-    if (j == 0) {
-      v = (i == nr - 1) ? vnext : 0.0;
+    if (j == 0 && m.ip > 0 && i >= m.ip) {
+      // port edge: the profile's drop, on the half cell above the wall
+      v = a.ur0[g] + (xs[r * XS + jn] - xs[(r + 1) * XS + jn]);
+      if (a.part) {
+        const double w = 0.5 * wr[i];
+        const double d = v - a.ur_old[g];
+        s0 += w * d * d;
+        s1 += w * v * v;
+      }
+    } else if (j == 0) {
+      v = (m.ip == 0 && i == nr - 1) ? vnext : 0.0;
     } else if (j == nz) {
       v = 0.0;
     } else {
@@ -585,18 +684,24 @@ __global__ void k_guess_half(MapP m, double* ur, double* uz, const double* ur_pr
   if (t == 0) {
     stop[0] = 0;
     stop[1] = -1;
+    // blocking capacitor with a port: the first potential iterate is the
+    // extrapolation 2 phi^n - phi^{n-1}
+    if (circ && m.ip > 0) circ[3] = 2.0 * circ[0] - circ[1];
   }
   clear_pass_scratch(t, (int64_t)gridDim.x * blockDim.x, qcount, tally, wscr, wlen);
   if (t < nur) {
     const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
     double u0 = ur[t], u1;
-    if (j == 0 && i == nr - 1 && circ) {
+    if (j == 0 && m.ip > 0 && i >= m.ip) {
+      // port edge: an unknown, extrapolated like the interior edges
+      u1 = 2.0 * u0 - ur_prev[t];
+    } else if (j == 0 && i == nr - 1 && circ && m.ip == 0) {
       // blocking capacitor: the gap carries the electrode potential; its
       // first iterate is extrapolated like the interior edges
       u1 = 2.0 * u0 - ur_prev[t];
       circ[3] = u1;
     } else if (j == 0 || j == nz) {
-      const bool gap = (j == 0 && i == nr - 1);
+      const bool gap = (j == 0 && i == nr - 1 && m.ip == 0);
       u0 = gap ? vnow : 0.0;
       ur[t] = u0;
       u1 = gap ? vnext : 0.0;
@@ -658,8 +763,9 @@ __global__ void __launch_bounds__(kBlock) k_norm2(MapP m, const double* __restri
        t += (int64_t)gridDim.x * kBlock) {
     if (t < nur) {
       const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
-      if (j == 0 || j == nz) continue;
-      s += wr[i] * ar[t] * ar[t];
+      const bool port = j == 0 && m.ip > 0 && i >= m.ip;  // the half cell above the wall
+      if ((j == 0 && !port) || j == nz) continue;
+      s += (port ? 0.5 * wr[i] : wr[i]) * ar[t] * ar[t];
     } else {
       const int64_t e = t - nur;
       s += wz[e / nz] * az[e] * az[e];
@@ -713,8 +819,8 @@ __global__ void __launch_bounds__(kBlock) k_xsum(MapP m, const double* __restric
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nur + nuz;
        t += (int64_t)gridDim.x * kBlock) {
     if (t < nur) {
-      const int j = int(t % (nz + 1));
-      if (j == 0 || j == nz) continue;
+      const int i = int(t / (nz + 1)), j = int(t - (int64_t)i * (nz + 1));
+      if ((j == 0 && !(m.ip > 0 && i >= m.ip)) || j == nz) continue;
       s += 0.5 * (ar[t] + br[t]) * Ir[t];
     } else {
       const int64_t e = t - nur;
@@ -745,6 +851,7 @@ struct CircArgs {
   const double *h0, *h1, *Ir, *Iz, *uz0, *uz1, *wz, *rh;
   double dt, cap, vnext_gen, scale;
   int es, nr, nz;
+  int ip;  // TEM port: first port edge, 0: the delta gap
 };
 
 __global__ void __launch_bounds__(256) k_converge(const double* __restrict__ part, int nparts, int k,
@@ -767,7 +874,26 @@ __global__ void __launch_bounds__(256) k_converge(const double* __restrict__ par
     den += __shfl_xor(den, off, 64);
   }
   double ie = 0.0;
-  if (ca.circ) {
+  if (ca.circ && ca.ip > 0) {
+    if (ca.es) {
+      // Eq. (6) over the electrode's face r <= r_p: the z-edges of its nodes
+      double dq = 0.0, ip = 0.0;
+      for (int i = t; i <= ca.ip; i += 64) {
+        const int64_t e = (int64_t)i * ca.nz;
+        dq += ca.wz[i] * (ca.uz1[e] - ca.uz0[e]);
+        ip += ca.Iz[e];
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        dq += __shfl_xor(dq, off, 64);
+        ip += __shfl_xor(ip, off, 64);
+      }
+      ie = dq / ca.dt + ip;
+    } else {
+      // the same current by Ampere's law: the loop through the first port cell
+      const int64_t gc = (int64_t)ca.ip * ca.nz;
+      ie = 2.0 * kPi * ca.rh[ca.ip] * (0.5 * (ca.h0[gc] + ca.h1[gc]));
+    }
+  } else if (ca.circ) {
     const double ir_gap = ca.Ir[(int64_t)(ca.nr - 1) * (ca.nz + 1)];
     if (ca.es) {
       double dq = 0.0, ip = 0.0;
@@ -822,6 +948,17 @@ constexpr int kTallyDoubles = 4;  // w_absorbed, w_coll, w_particles, pad lead t
 static_assert(sizeof(Tally) % sizeof(uint64_t) == 0 && kTallyWords <= 64, "one word per lane");
 static_assert(offsetof(Tally, n_absorbed) == kTallyDoubles * sizeof(double), "doubles first");
 
+// The TEM port's part of the commit summary: its tables, the line's wall
+// field (moved to t^{n+1} when the step is accepted), the wall profile and
+// the fields at t^n and of the accepted iterate.
+struct PortFin {
+  int ip;  // 0: no port
+  const double* pc;
+  double* hb;
+  const double *prof, *ur0, *ur1, *rh, *wr;
+  double vnow, vnext;  // the generator at t^n, t^{n+1} (no capacitor)
+};
+
 __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally,
                                                  const double* __restrict__ xpart,
                                                  const double* __restrict__ hn,
@@ -835,7 +972,7 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
                                                  double* __restrict__ wall_tot, uint64_t seq,
                                                  StepFinal* out, const int32_t* __restrict__ conv,
                                                  int want_k, double* __restrict__ circ, int cpar,
-                                                 double dt) {
+                                                 double dt, PortFin pf) {
   static_assert(kSpread == 64, "64 tally copies");
   // enqueued ahead of the residual it depends on: only if iteration want_k
   // is the one that converged
@@ -875,6 +1012,51 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
     qp = wsum_d(qp);
     izp = wsum_d(izp);
   }
+  double port_w = 0.0, port_v = 0.0;
+  if (pf.ip > 0) {
+    // the electrode potential's step of the accepted iterate (read before
+    // the circuit state moves below)
+    const double dphi = circ ? circ[6 + 2 * cpar] - circ[0] : pf.vnext - pf.vnow;
+    for (int i = pf.ip + l; i < nr; i += 64) port_v += pf.ur1[(int64_t)i * (nz + 1)];
+    port_v = wsum_d(port_v);
+    if (!es) {
+      // H_b^{n+1} from the Mur condition and the accepted edge voltages, and
+      // the power through the mouth, M H_b^{n+1/2} u^{n+1/2} per edge; each
+      // lane owns its edges' H_b
+      for (int i = pf.ip + l; i < nr; i += 64) {
+        const int64_t e = (int64_t)i * (nz + 1);
+        const double u0 = pf.ur0[e], u1 = pf.ur1[e], h0 = pf.hb[i];
+        const double h1 = h0 + (pf.pc[kPortK * nr + i] * dphi - (u1 - u0)) * pf.pc[kPortIEL * nr + i];
+        port_w += 2.0 * kPi * pf.rh[i] * (0.5 * (h0 + h1)) * (0.5 * (u0 + u1));
+        if (!rejected) pf.hb[i] = h1;
+      }
+      port_w = dt * wsum_d(port_w);
+    } else {
+      // the source's charge on the powered wall nodes, weighted by the wall
+      // profile: the change of each node's Gauss charge (port edges on their
+      // half cells) and the current leaving it
+      qp = 0.0;
+      izp = 0.0;
+      for (int i = l; i <= nr; i += 64) {
+        double dg = 0.0, dv = 0.0;
+        if (i < nr) {
+          const int64_t e = (int64_t)i * nz, f = (int64_t)i * (nz + 1);
+          dg += wz[i] * (uz1[e] - uzn[e]);
+          dv += Iz[e] + Ir[f];
+          if (i >= pf.ip) dg += 0.5 * pf.wr[i] * (pf.ur1[f] - pf.ur0[f]);
+        }
+        if (i > 0) {
+          const int64_t f = (int64_t)(i - 1) * (nz + 1);
+          dv -= Ir[f];
+          if (i - 1 >= pf.ip) dg -= 0.5 * pf.wr[i - 1] * (pf.ur1[f] - pf.ur0[f]);
+        }
+        qp += pf.prof[i] * dg;
+        izp += pf.prof[i] * dv;
+      }
+      qp = wsum_d(qp);
+      izp = wsum_d(izp);
+    }
+  }
   if (wall_add && !rejected) {
     // the wall charge of a committing iteration joins the totals (the three
     // wall arrays are contiguous in both)
@@ -888,6 +1070,8 @@ __global__ void __launch_bounds__(64) k_finalize(const Tally* __restrict__ tally
     out->ir_gap = Ir[(int64_t)(nr - 1) * (nz + 1)];
     out->qp_delta = qp;
     out->iz_plate = izp;
+    out->port_w = port_w;
+    out->port_v = port_v;
     if (circ) {
       // the accepted iterate's electrode potential and current; the circuit
       // state moves to t^{n+1} only if the step is accepted
@@ -917,6 +1101,7 @@ __device__ __forceinline__ double jf_weight(const MapP& m, const double* __restr
   if (e < nur) {
     const int64_t i = e / (m.nz + 1);
     const int64_t j = e - i * (m.nz + 1);
+    if (j == 0 && m.ip > 0 && i >= m.ip) return 0.5 * wr[i];  // port edge
     return (j >= 1 && j < m.nz) ? wr[i] : 0.0;
   }
   const int64_t i = (e - nur) / m.nz;
@@ -1049,6 +1234,7 @@ hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s, const
     ca.es = c.g.model == ECPIC_MODEL_ES ? 1 : 0;
     ca.nr = c.g.nr;
     ca.nz = c.g.nz;
+    ca.ip = c.g.port_i;
   }
   hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, c.sol.partial,
                      row_blocks(c.g.nr) * col_blocks(c.g.nz),
@@ -1060,11 +1246,25 @@ hipError_t launch_converge(const Ctx& c, int k, double tol, hipStream_t s, const
 hipError_t launch_finalize(const Ctx& c, const Tally* tally, const double* xpart, const double* Ir,
                            const double* Iz, const double* wall_add, uint64_t seq, int guard_k,
                            hipStream_t s, int iter) {
+  PortFin pf;
+  std::memset(&pf, 0, sizeof(pf));
+  if (c.g.port_i > 0) {
+    pf.ip = c.g.port_i;
+    pf.pc = c.sol.port_pc;
+    pf.hb = c.port_hb;
+    pf.prof = c.sol.prof;
+    pf.ur0 = c.ur;
+    pf.ur1 = c.ur_it;
+    pf.rh = c.sol.rh;
+    pf.wr = c.sol.wr;
+    pf.vnow = drive_voltage(c.g, c.t);
+    pf.vnext = drive_voltage(c.g, c.t + c.g.dt);
+  }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, tally, xpart, c.h, c.h_it, Ir,
                      c.g.nr, c.g.nz, c.uz, c.uz_it, Iz, c.sol.wz,
                      c.g.model == ECPIC_MODEL_ES ? 1 : 0, wall_add, c.wall_bot, seq, c.fin_dev,
                      guard_k >= 0 ? (const int32_t*)c.stop : nullptr, guard_k,
-                     c.g.blocking_cap > 0.0 ? c.circ : nullptr, iter & 1, c.g.dt);
+                     c.g.blocking_cap > 0.0 ? c.circ : nullptr, iter & 1, c.g.dt, pf);
   return hipGetLastError();
 }
 
@@ -1169,12 +1369,23 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s, double* 
     const double dv = a.vnext - a.vnow;
     hipLaunchKernelGGL(k_es_rhs_dst, dim3(row_blocks(nr), col_blocks(nf)), dim3(kFB),
                        lds_es_rhs, s, c.m, S.wz, a.Ir, a.Iz, dv, a.gapv, a.ur0, S.Qt, hat,
-                       a.stop);
-    hipLaunchKernelGGL(k_tri_scan, dim3(nf), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv, S.tri_up,
-                       hat, a.stop);
+                       a.stop, S.prof, a.phin);
+    hipLaunchKernelGGL(k_tri_scan<false>, dim3(nf), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv,
+                       S.tri_up, hat, a.stop, 0, nullptr, nullptr);
     hipLaunchKernelGGL(k_es_recover, dim3(row_blocks(nr), cb), dim3(kFB), lds_es_rec, s, a, c.m,
-                       S.wr, S.wz, S.Q, hat, dv);
+                       S.wr, S.wz, S.Q, hat, dv, S.prof);
     return hipGetLastError();
+  }
+  PortDev P;
+  std::memset(&P, 0, sizeof(P));
+  if (c.g.port_i > 0) {
+    P.ip = c.g.port_i;
+    P.pc = S.port_pc;
+    P.hb = c.port_hb;
+    P.vnow = a.vnow;
+    P.vnext = a.vnext;
+    P.phin = a.phin;
+    P.phi1 = a.gapv;
   }
   // part sums: P * R * nc <= kFB * R for nc < kFB (chunks have at most kCC + 1 columns)
   const size_t lds_rhs = sizeof(double) * ((size_t)kRB * nz + (size_t)kFB * kRB);
@@ -1183,11 +1394,19 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s, double* 
   if (lds_rhs > 65536 || lds_rec > 65536) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rhs_dct, dim3(row_blocks(nr), cb), dim3(kFB), lds_rhs, s, c.m, S.rh, S.wr,
                      S.wz, S.area, c.g.mu, a.ur0, a.uz0, a.h0, a.Ir, a.Iz, a.vhalf, a.gapv, S.Qt,
-                     hat, a.stop);
-  hipLaunchKernelGGL(k_tri_scan, dim3(nz), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv, S.tri_up,
-                     hat, a.stop);
+                     hat, a.stop, P);
+  hipLaunchKernelGGL(k_tri_scan<false>, dim3(nz), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv,
+                     S.tri_up, hat, a.stop, 0, nullptr, nullptr);
+  if (P.ip > 0) {
+    // the port's diagonal on the wall cells, by the Woodbury identity:
+    // z = F U^T y, then hat -= A0^-1 U z (a second scan on q0[k] z)
+    hipLaunchKernelGGL(k_port_couple, dim3(1), dim3(kPortThreads), 0, s, nr, nz, P.ip, hat,
+                       S.port_q0, S.port_F, S.port_z, a.stop);
+    hipLaunchKernelGGL(k_tri_scan<true>, dim3(nz), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv,
+                       S.tri_up, hat, a.stop, P.ip, S.port_q0, S.port_z);
+  }
   hipLaunchKernelGGL(k_idct_recover, dim3(row_blocks(nr), cb), dim3(kFB), lds_rec, s, a, c.m,
-                     S.rh, S.wr, S.wz, S.Q, hat);
+                     S.rh, S.wr, S.wz, S.Q, hat, P);
   return hipGetLastError();
 }
 

@@ -36,7 +36,25 @@ struct MapP {
   int nr, nz;
   double xi_a, s, inv_s, rsqrt_xa, dz, inv_dz, dt;
   int i_lin;  // first radial cell entirely in the linear part of the map
+  int ip;     // TEM port: first port edge (i, 0) of the bottom wall, 0: none
 };
+
+// The TEM port's tables and state as the field kernels see them (Sec. 2.1,
+// Eqs. (5), (7)).  pc holds four rows of nr values, entries i >= ip used:
+// g_i = 1 / (w_b/dt + M/(2 eta l)), a_i = M kappa_i / (2 eta l), kappa_i, and
+// 1 / (eta l), with M = 2 pi r_{i+1/2}, w_b = wr/2, l the edge length.
+struct PortDev {
+  int ip;               // 0: no port
+  const double* pc;
+  const double* hb;     // H_b^n, [nr]
+  double vnow, vnext;   // the electrode potential at t^n, t^{n+1} (no capacitor)
+  const double* phin;   // with the capacitor: phi^n on the device, else null
+  const double* phi1;   // with the capacitor: the iterate's phi^{n+1}, else null
+};
+constexpr int kPortG = 0, kPortA = 1, kPortK = 2, kPortIEL = 3;
+__host__ __device__ inline double port_dphi(const PortDev& P) {
+  return (P.phi1 ? P.phi1[0] : P.vnext) - (P.phin ? P.phin[0] : P.vnow);
+}
 
 // One species as the kernels see it.  FP64 path: xi, eta, v*; mixed path:
 // cell (= i*nz + j), fa, fb (offsets in [0,1]) and fv*.  Dead particles have
@@ -87,6 +105,9 @@ struct StepFinal {
   // blocking capacitor: electrode potential at t^n and t^{n+1}, capacitor
   // charge at t^{n+1}, and the electrode current of the accepted iterate
   double phi_n, phi_1, q_1, ie;
+  // TEM port: EM, the power through the mouth times dt,
+  // dt sum M H_b^{n+1/2} u^{n+1/2}; either model, the mouth voltage at t^{n+1}
+  double port_w, port_v;
   uint64_t seq;     // written last: the host polls it
 };
 
@@ -155,6 +176,9 @@ struct SolveArgs {
   // circuit's current iterate) and at t^n from ur0's gap edge; null: vnow,
   // vnext
   const double* gapv;
+  // blocking capacitor with a port: the electrode potential at t^n (the
+  // circuit state), else null
+  const double* phin;
   double *ur1, *uz1, *h1;
   const double *ur_old, *uz_old;
   double* part;         // [2 * nr]: per row sum w (u1 - u_old)^2, sum w u1^2
@@ -186,6 +210,15 @@ struct SolverDev {
   double* tri_lo;   // Thomas: sub-diagonal multipliers, [nz][nr]
   double* tri_inv;  // Thomas: inverse pivots, [nz][nr]
   double* tri_up;   // super-diagonal of the system, [nr]
+  // TEM port (Woodbury form of the port's diagonal on the separable solve):
+  // pc [4][nr] (PortDev), F = (D^-1 + U^T A0^-1 U)^-1 over the m port cells
+  // [m][m] (symmetric), q0[k] = Q[k][0] [nz], z = F U^T y [m]; the
+  // electrostatic wall profile [nr+1] (always present)
+  double* port_pc;
+  double* port_F;
+  double* port_q0;
+  double* port_z;
+  double* prof;
   double* work0;    // [nr][nz]
   double* work1;    // [nr][nz]
   double* partial;  // reduction partials
@@ -272,6 +305,8 @@ struct Ctx {
   // [6 + 2p], [7 + 2p] the potential and electrode current of the last
   // Picard iteration of parity p
   double* circ = nullptr;
+  // TEM port: the line's wall field H_b at t^n under every port edge [nr]
+  double* port_hb = nullptr;
   int32_t jfnk_m = 0;
   double* jf_vec = nullptr;
   double* jf_part = nullptr;       // dot partials [kMaxKrylov + 1][kJfBlocks]
@@ -316,6 +351,10 @@ struct Ctx {
   std::vector<hipEvent_t> ev_pool;
   std::vector<hipEvent_t> ev_dropped;  // back to the pool at the next collect
 };
+
+// The generator voltage V(t): a sum of up to 32 harmonics, zero from
+// drive_t_end on when that is set (host).
+double drive_voltage(const ecpic_grid_desc& g, double t);
 
 // ---- launchers (stream-ordered, no synchronisation) ----
 // push

@@ -397,6 +397,12 @@ def _step_parity(og, P, w, parts, nsteps, mcc=None, sort_every=0, mobile=(True, 
             assert d_g["electrode_v"] == pytest.approx(st.phi, rel=1e-10, abs=1e-12)
             assert d_g["cap_charge"] == pytest.approx(st.q_cap, rel=1e-10, abs=1e-30)
             assert d_g["w_gen"] == pytest.approx(d_o["w_gen"], rel=1e-9, abs=1e-30)
+        if w.port_i > 0:
+            # the mouth voltage and the line's wall field at t^{n+1}
+            assert d_g["port_v"] == pytest.approx(d_o["port_v"], rel=1e-10, abs=1e-12)
+            hb = ctx.get_port_field()
+            hs = np.abs(st.hb).max()
+            assert np.abs(hb - st.hb).max() <= TOL * hs + 1e-300, "port H_b"
     return worst
 
 

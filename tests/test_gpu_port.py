@@ -1,0 +1,187 @@
+"""The TEM port on the HIP path (Sec. 2.1, Eqs. (5)-(7); Sec. 2.2 for the
+electrostatic model's port), against the oracle.
+
+1. Field solve with the port: the separable solve plus the Woodbury
+   correction of the port's diagonal (a coupling kernel and a second scan),
+   from one port cell to 800, ragged row blocks, up to 1100 radial rows,
+   random fields, currents and line field H_b, at the 1e-12 bar (scaled by
+   the system's conditioning where that is larger); the electrostatic
+   solve with the coaxial wall profile.
+2. Whole steps, driven and collisional, EM and ES, with and without the
+   blocking capacitor, and JFNK: fields, particles, energies (the drive's
+   work is the power through the mouth), the mouth voltage and H_b.
+3. The vacuum physics on the GPU: the energy balance with the power through
+   the mouth holds to rounding, and after a burst that ends at zero the field
+   energy never rises and drains away.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import ecpic_inputs as E
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    s = np.abs(b).max()
+    return np.abs(a - b).max() / s if s > 0 else np.abs(a).max()
+
+
+@pytest.mark.parametrize("shape", [(24, 8, 20, 2.0), (37, 29, 1, 2.0), (70, 130, 69, 0.0),
+                                   (256, 128, 190, 2.0), (300, 16, 150, 2.0),
+                                   (1100, 12, 300, 0.0)])
+def test_port_field_solve_parity(og, torch_cuda, shape):
+    import paper_2212_08836_amd as P
+    from test_gpu_parity import _cn_condition
+    nr, nz, ip, xa = shape
+    _flush(f"port field solve parity nr={nr} nz={nz} port_i={ip}")
+    w = E.Workload("f", nr, nz, 0.05, 0.03, xi_a=xa, dt=2e-11, drive_amp=(150.0,),
+                   drive_freq=(90e6,), drive_phase=(0.4,), port_i=ip, port_eps=3.8)
+    g = og.grid_from_workload(w)
+    ctx = P.context_from_workload(w)
+    rng = np.random.default_rng(nr * 1000 + nz + ip)
+    ur0 = rng.standard_normal(nr * (nz + 1)) * 20
+    uz0 = rng.standard_normal((nr + 1) * nz) * 20
+    u = ur0.reshape(nr, nz + 1)
+    u[:ip, 0] = 0
+    u[:, -1] = 0
+    uz0.reshape(nr + 1, nz)[-1] = 0
+    h0 = rng.standard_normal(nr * nz) * 0.1
+    hb = np.zeros(nr)
+    hb[ip:] = rng.standard_normal(nr - ip) * 0.1
+    Ir = rng.standard_normal(nr * (nz + 1)) * 1e-2
+    Iz = rng.standard_normal((nr + 1) * nz) * 1e-2
+    t = 3.3e-9
+    ctx.set_port_field(hb)
+    g.set_port_h(hb)
+    a = ctx.field_solve(ur0, uz0, h0, Ir, Iz, t)
+    b = g.field_solve(ur0, uz0, h0, Ir, Iz, t)
+    bar = max(TOL, _cn_condition(g, w) * 2.0 ** -53)
+    errs = [_rel(x, y) for x, y in zip(a, b)]
+    pe = _rel(a[0].reshape(nr, nz + 1)[ip:, 0], b[0].reshape(nr, nz + 1)[ip:, 0])
+    _flush(f"  errors {errs}, port edges {pe:.2e}, bar {bar:.2e}")
+    assert max(errs) < bar and pe < bar
+    assert np.array_equal(ctx.get_port_field(), hb)  # the solve leaves the state alone
+
+
+@pytest.mark.parametrize("shape", [(24, 8, 20), (300, 16, 150)])
+def test_port_electrostatic_solve_parity(og, torch_cuda, shape):
+    import paper_2212_08836_amd as P
+    nr, nz, ip = shape
+    w = E.Workload("f", nr, nz, 0.05, 0.03, dt=2e-11, drive_amp=(150.0,), drive_freq=(90e6,),
+                   drive_phase=(0.4,), port_i=ip, port_eps=3.8)
+    g = og.grid_from_workload(w, model="es")
+    ctx = P.context_from_workload(w, model="es")
+    rng = np.random.default_rng(nr + ip)
+    ur0 = rng.standard_normal(nr * (nz + 1)) * 20
+    uz0 = rng.standard_normal((nr + 1) * nz) * 20
+    Ir = rng.standard_normal(nr * (nz + 1)) * 1e-2
+    Iz = rng.standard_normal((nr + 1) * nz) * 1e-2
+    a = ctx.field_solve(ur0, uz0, g.zeros_h(), Ir, Iz, 3.3e-9)
+    b = g.field_solve(ur0, uz0, g.zeros_h(), Ir, Iz, 3.3e-9)
+    errs = [_rel(x, y) for x, y in zip(a[:2], b[:2])]
+    _flush(f"port ES solve {shape}: errors {errs}")
+    assert max(errs) < TOL and not np.any(a[2])
+
+
+def _port_workload(**over):
+    w = E.Workload("port", 48, 24, 0.03, 0.012, n0=1e16, profile="j0sin", ppc=12,
+                   drive_amp=(200.0,), drive_freq=(100e6,), pressure_pa=60.0, seed=15,
+                   dt=1e-11, tol=1e-10, port_i=36, port_eps=3.8)
+    for k, v in over.items():
+        setattr(w, k, v)
+    return w
+
+
+@pytest.mark.parametrize("model,cap", [("em", 0.0), ("em", 2e-10), ("es", 0.0), ("es", 2e-10)])
+def test_port_step_parity(og, torch_cuda, model, cap):
+    import paper_2212_08836_amd as P
+    from test_gpu_parity import _step_parity
+    _flush(f"port step parity, {model}, blocking capacitor {cap:g} F, driven + MCC")
+    w = _port_workload()
+    parts = E.make_particles(w)
+    for k in ("vr", "vt", "vz"):
+        parts[0][k] = parts[0][k] * 3.0
+    _step_parity(og, P, w, parts, 6, mcc=w.mcc_params(), sort_every=3, model=model, cap=cap)
+
+
+def test_port_jfnk_parity(og, torch_cuda):
+    """JFNK with the port (its edges are unknowns of the Newton vector, in the
+    energy inner product on their half cells): one Krylov direction per
+    Newton step against the oracle's."""
+    import paper_2212_08836_amd as P
+    w = _port_workload(pressure_pa=0.0)
+    ctx = P.context_from_workload(w)
+    ctx.set_option(P.ECPIC_OPT_JFNK_KRYLOV, 1)
+    parts = E.make_particles(w)
+    P.load_workload_species(ctx, parts, extra_cap=0.5)
+    g = og.grid_from_workload(w)
+    sp = og.species_from_workload(g, parts, extra_cap=0.5)
+    st = og.State(g)
+    for n in range(3):
+        d = ctx.step(fixed_iter=3, solver="jfnk", krylov=1)
+        do = g.step(st, sp, fixed_iter=3, solver="jfnk", krylov=1)
+        assert do["rc"] == 0 and d["iters"] == do["iters"]
+        assert abs(d["residual"][0] - do["residual"][0]) <= 1e-9 * do["residual"][0]
+        f = ctx.get_fields()
+        errs = [_rel(x, y) for x, y in zip(f, (st.ur, st.uz, st.h))]
+        eh = _rel(ctx.get_port_field(), st.hb)
+        _flush(f"  JFNK port step {n}: residuals {np.array(d['residual'][:3])}, field errors "
+               f"{errs}, H_b {eh:.1e}")
+        assert max(errs) < 1e-10 and eh < 1e-10
+
+
+def _vacuum_ctx(P, ip, f, t_end=0.0, eps_r=1.0):
+    w = E.Workload("v", 64, 16, 0.12, 0.005, dt=1e-10, drive_amp=(100.0,), drive_freq=(f,),
+                   drive_t_end=t_end, port_i=ip, port_eps=eps_r)
+    ctx = P.context_from_workload(w)
+    return w, ctx
+
+
+def test_port_energy_balance_on_the_gpu(torch_cuda):
+    import paper_2212_08836_amd as P
+    _, ctx = _vacuum_ctx(P, 52, 150e6, eps_r=3.8)
+    W0, worst, drive = 0.0, 0.0, 0.0
+    for n in range(400):
+        d = ctx.step(tol=1e-13, max_iter=30)
+        W = d["we"] + d["wb"]
+        worst = max(worst, abs(W - W0 - d["w_drive"]) / max(W, 1e-300))
+        drive += abs(d["w_drive"])
+        W0 = W
+    _flush(f"port vacuum energy balance: worst {worst:.2e}")
+    assert drive > 0 and worst < 1e-11
+
+
+def test_port_absorbs_after_a_burst_on_the_gpu(torch_cuda):
+    import paper_2212_08836_amd as P
+    f, dt = 200e6, 1e-10
+    _, ctx = _vacuum_ctx(P, 52, f, t_end=2 / f)
+    Wp, Wmax, rise, W_end, t = 0.0, 0.0, 0.0, None, 0.0
+    for n in range(400):
+        d = ctx.step(tol=1e-13, max_iter=30)
+        t += dt
+        W = d["we"] + d["wb"]
+        if t > 2 / f + dt / 2:
+            rise = max(rise, (W - Wp) / Wmax)
+            W_end = W_end or Wp
+        Wmax, Wp = max(Wmax, W), W
+    _flush(f"port absorption: largest rise {rise:.1e}, left {W / W_end:.1e}")
+    assert rise <= 1e-13 and W / W_end < 1e-4
