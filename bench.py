@@ -108,10 +108,11 @@ def particles(E, w, device_gen):
     return E.make_particles(w)
 
 
-def new_context(E, P, w, parts, precision, model="em", krylov=0):
+def new_context(E, P, w, parts, precision, model="em", krylov=0, **over):
     """A context whose device memory is one torch tensor (bound workspace);
-    krylov > 0 reserves that many JFNK Krylov vectors in it."""
-    ctx = P.context_from_workload(w, precision=precision, model=model)
+    krylov > 0 reserves that many JFNK Krylov vectors in it; over: grid
+    settings in place of the workload's (port, blocking capacitor)."""
+    ctx = P.context_from_workload(w, precision=precision, model=model, **over)
     if krylov:
         ctx.set_option(P.ECPIC_OPT_JFNK_KRYLOV, krylov)
     P.load_workload_species(ctx, parts, extra_cap=0.25, workspace=True)
@@ -235,6 +236,31 @@ def model_leg(E, P, w, parts_fn, steps, warmup, period, plain_ms):
             "vs_em_step": plain_ms / ms}
 
 
+# the paper's reactor feeds the drive through an annulus from 14 to 19 cm of
+# radius, filled with quartz, behind a blocking capacitor (Sec. 2.1)
+PORT_R_FRAC, PORT_EPS, PORT_CAP = 14.0 / 19.0, 3.8, 1e-9
+
+
+def port_leg(E, P, w, parts_fn, steps, warmup, period, plain_ms):
+    """The paper's drive on the same workload: the TEM port with its Mur
+    condition (Eqs. (5), (7)) over the outer quarter of the bottom wall and
+    the blocking capacitor (Eq. (6)); the field solve gains the port's
+    coupling kernel and second scan."""
+    ip = int(round(PORT_R_FRAC * (w.nr + w.xi_a) - w.xi_a))
+    ctx = new_context(E, P, w, parts_fn(), "fp64", port_i=ip, port_eps=PORT_EPS,
+                      blocking_cap=PORT_CAP)
+    el, prof = timed_run(ctx, w, steps, warmup, period, kinds=("push", "push_commit", "field"))
+    pushes, iters = pushes_and_iters(prof, steps)
+    ctx.close()
+    ms = 1e3 * el / steps
+    f = prof["field"]
+    return {"drive": "TEM port + blocking capacitor", "port_i": ip, "port_cells": w.nr - ip,
+            "port_eps": PORT_EPS, "blocking_cap_F": PORT_CAP, "ms_per_step": ms,
+            "particle_pushes_per_s": pushes / el, "picard_iterations_per_step": iters,
+            "field_solve_ms": f["ms"] / f["launches"] if f["launches"] else None,
+            "vs_gap_step": plain_ms / ms}
+
+
 def jfnk_leg(E, P, w, parts_fn, steps, warmup, period, plain_ms, krylov=10, eta=1e-3):
     """The JFNK solver on the same workload, and on a dense 32x32 plasma
     (omega_pe dt = 3.4) where Picard does not converge."""
@@ -349,6 +375,9 @@ def main():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the mixed-precision and learned-guess legs")
     ap.add_argument("--no-nn", action="store_true", help="skip the learned-guess legs")
+    ap.add_argument("--legs", default="es,port,jfnk,mixed,nn",
+                    help="comma-separated legs to run beside the headline (of es, port, jfnk, "
+                         "mixed, nn)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="the form of the headline leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -447,16 +476,24 @@ def main():
 
         def parts_fn():
             return particles(E, w, device_gen)
-        log("leg: electrostatic model")
-        legs["es"] = model_leg(E, P, w, parts_fn, args.steps, args.warmup, period, ms)
-        torch.cuda.empty_cache()
-        log("leg: JFNK solver")
-        legs["jfnk"] = jfnk_leg(E, P, w, parts_fn, args.steps, args.warmup, period, ms)
-        torch.cuda.empty_cache()
-        log("leg: mixed precision, extrapolated guess")
-        legs["mixed"] = leg(E, P, w, parts_fn, "mixed", False, args.steps, args.warmup,
-                            period, ms)
-        if not args.no_nn:
+        want = set(args.legs.split(","))
+        if "es" in want:
+            log("leg: electrostatic model")
+            legs["es"] = model_leg(E, P, w, parts_fn, args.steps, args.warmup, period, ms)
+            torch.cuda.empty_cache()
+        if "port" in want:
+            log("leg: TEM port and blocking capacitor")
+            legs["port"] = port_leg(E, P, w, parts_fn, args.steps, args.warmup, period, ms)
+            torch.cuda.empty_cache()
+        if "jfnk" in want:
+            log("leg: JFNK solver")
+            legs["jfnk"] = jfnk_leg(E, P, w, parts_fn, args.steps, args.warmup, period, ms)
+            torch.cuda.empty_cache()
+        if "mixed" in want:
+            log("leg: mixed precision, extrapolated guess")
+            legs["mixed"] = leg(E, P, w, parts_fn, "mixed", False, args.steps, args.warmup,
+                                period, ms)
+        if not args.no_nn and "nn" in want:
             log("training the learned guess on held-out runs")
             wts, norm, info = train_network(E, P, G, w, period, device_gen)
             torch.cuda.empty_cache()

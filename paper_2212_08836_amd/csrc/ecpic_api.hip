@@ -146,7 +146,8 @@ void carve_all(Ctx& c, Carver& k) {
     if (c.g.model == ECPIC_MODEL_EM) {
       k.take(&S.port_F, mp * mp);
       k.take(&S.port_q0, nz);
-      k.take(&S.port_z, mp);
+      // z, then the coupling's mode parts ([32][m] at most)
+      k.take(&S.port_z, mp * 33);
     }
   }
   k.take(&S.work0, nh);

@@ -285,59 +285,85 @@ __global__ void __launch_bounds__(kFB) k_tri_scan(int nr, const double* __restri
   }
 }
 
-// The port's coupling: p = U^T y (the wall cells (i, 0), i >= ip, of the
-// first solve, y(i, 0) = sum_k q0[k] yhat[k][i]) and z = F p, in one block
-// (m = nr - ip <= kFB kMaxE).  Each row's sum is split over P parts of the
-// block's threads and the parts are added in order (deterministic).
-constexpr int kPortThreads = 1024;
-__global__ void __launch_bounds__(kPortThreads) k_port_couple(int nr, int nz, int ip,
-                                                              const double* __restrict__ hat,
-                                                              const double* __restrict__ q0,
-                                                              const double* __restrict__ F,
-                                                              double* __restrict__ zq,
-                                                              const int32_t* __restrict__ stop) {
+// The port's coupling, in two launches with deterministic sums:
+//   k_port_gather  p = U^T y, the wall cells (i, 0), i >= ip, of the first
+//                  solve: y(i, 0) = sum_k q0[k] yhat[k][i].  Block (b, kp)
+//                  sums its mode range kp for 256 port rows (loads coalesced
+//                  over the rows), into part[kp][r];
+//   k_port_solve   z = F p: every block adds the mode parts in order, then
+//                  16 rows of z, each split over 16 column parts added in
+//                  order (F symmetric: its columns read as rows, coalesced).
+constexpr int kPortRows = 16;
+constexpr int kPortKParts = 32;  // mode parts at most
+inline int port_kparts(int nz) { return std::max(1, std::min(kPortKParts, nz / 16)); }
+
+__global__ void __launch_bounds__(kFB) k_port_gather(int nr, int nz, int ip, int kparts,
+                                                    const double* __restrict__ hat,
+                                                    const double* __restrict__ q0,
+                                                    double* __restrict__ part,
+                                                    const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int m = nr - ip;
+  const int r = blockIdx.x * kFB + threadIdx.x;
+  if (r >= m) return;
+  const int kp = blockIdx.y;
+  const int k0 = kp * nz / kparts, k1 = (kp + 1) * nz / kparts;
+  const double* col = hat + ip + r;
+  double acc = 0.0;
+  int k = k0;
+  for (; k + kUnroll <= k1; k += kUnroll) {
+    double v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v[u] = col[(int64_t)(k + u) * nr];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) acc = fma(q0[k + u], v[u], acc);
+  }
+  for (; k < k1; ++k) acc = fma(q0[k], col[(int64_t)k * nr], acc);
+  part[(int64_t)kp * m + r] = acc;
+}
+
+__global__ void __launch_bounds__(kFB) k_port_solve(int m, int kparts,
+                                                   const double* __restrict__ part,
+                                                   const double* __restrict__ F,
+                                                   double* __restrict__ zq,
+                                                   const int32_t* __restrict__ stop) {
   if (stop && *stop) return;
   __shared__ double pv[kFB * kMaxE];
-  __shared__ double ps[kPortThreads];
-  const int m = nr - ip;
-  const int P = m >= kPortThreads ? 1 : kPortThreads / m;
-  for (int base = 0; base < m; base += kPortThreads) {
-    const int rows = min(m - base, kPortThreads);
-    const int parts = rows >= kPortThreads ? 1 : min(P, kPortThreads / rows);
-    const int t = threadIdx.x, r = t % rows, q = t / rows;
-    double acc = 0.0;
-    if (q < parts) {
-      const int k0 = q * nz / parts, k1 = (q + 1) * nz / parts;
-      const double* col = hat + ip + base + r;
-      for (int k = k0; k < k1; ++k) acc = fma(q0[k], col[(int64_t)k * nr], acc);
-      ps[q * rows + r] = acc;
-    }
-    __syncthreads();
-    if (t < rows) {
-      double v = ps[t];
-      for (int u = 1; u < parts; ++u) v += ps[u * rows + t];
-      pv[base + t] = v;
-    }
-    __syncthreads();
+  __shared__ double ps[kFB];
+  for (int c = threadIdx.x; c < m; c += kFB) {
+    // the parts' loads issued together, then added in order
+    double t[kPortKParts];
+#pragma unroll
+    for (int kp = 0; kp < kPortKParts; ++kp) t[kp] = kp < kparts ? part[(int64_t)kp * m + c] : 0.0;
+    double v = t[0];
+#pragma unroll
+    for (int kp = 1; kp < kPortKParts; ++kp)
+      if (kp < kparts) v += t[kp];
+    pv[c] = v;
   }
-  for (int base = 0; base < m; base += kPortThreads) {
-    const int rows = min(m - base, kPortThreads);
-    const int parts = rows >= kPortThreads ? 1 : min(P, kPortThreads / rows);
-    const int t = threadIdx.x, r = t % rows, q = t / rows;
-    if (q < parts) {
-      const int c0 = q * m / parts, c1 = (q + 1) * m / parts;
-      double acc = 0.0;
-      // F symmetric: column base + r read as a row, coalesced over r
-      for (int cc = c0; cc < c1; ++cc) acc = fma(F[(int64_t)cc * m + base + r], pv[cc], acc);
-      ps[q * rows + r] = acc;
+  __syncthreads();
+  constexpr int kParts = kFB / kPortRows;
+  const int lr = threadIdx.x % kPortRows, q = threadIdx.x / kPortRows;
+  const int r = blockIdx.x * kPortRows + lr;
+  double acc = 0.0;
+  if (r < m) {
+    const int c0 = q * m / kParts, c1 = (q + 1) * m / kParts;
+    int c = c0;
+    for (; c + kUnroll <= c1; c += kUnroll) {
+      double f[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) f[u] = F[(int64_t)(c + u) * m + r];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) acc = fma(f[u], pv[c + u], acc);
     }
-    __syncthreads();
-    if (t < rows) {
-      double v = ps[t];
-      for (int u = 1; u < parts; ++u) v += ps[u * rows + t];
-      zq[base + t] = v;
-    }
-    __syncthreads();
+    for (; c < c1; ++c) acc = fma(F[(int64_t)c * m + r], pv[c], acc);
+  }
+  ps[threadIdx.x] = acc;
+  __syncthreads();
+  if (q == 0 && r < m) {
+    double v = ps[lr];
+    for (int u = 1; u < kParts; ++u) v += ps[u * kPortRows + lr];
+    zq[r] = v;
   }
 }
 
@@ -1400,8 +1426,12 @@ hipError_t field_solve(const Ctx& c, const SolveArgs& a, hipStream_t s, double* 
   if (P.ip > 0) {
     // the port's diagonal on the wall cells, by the Woodbury identity:
     // z = F U^T y, then hat -= A0^-1 U z (a second scan on q0[k] z)
-    hipLaunchKernelGGL(k_port_couple, dim3(1), dim3(kPortThreads), 0, s, nr, nz, P.ip, hat,
-                       S.port_q0, S.port_F, S.port_z, a.stop);
+    const int mp = nr - P.ip, kparts = port_kparts(nz);
+    double* part = S.port_z + mp;  // [kparts][m] after z
+    hipLaunchKernelGGL(k_port_gather, dim3((mp + kFB - 1) / kFB, kparts), dim3(kFB), 0, s, nr,
+                       nz, P.ip, kparts, hat, S.port_q0, part, a.stop);
+    hipLaunchKernelGGL(k_port_solve, dim3((mp + kPortRows - 1) / kPortRows), dim3(kFB), 0, s, mp,
+                       kparts, part, S.port_F, S.port_z, a.stop);
     hipLaunchKernelGGL(k_tri_scan<true>, dim3(nz), dim3(kFB), 0, s, nr, S.tri_lo, S.tri_inv,
                        S.tri_up, hat, a.stop, P.ip, S.port_q0, S.port_z);
   }

@@ -212,7 +212,8 @@ struct SolverDev {
   double* tri_up;   // super-diagonal of the system, [nr]
   // TEM port (Woodbury form of the port's diagonal on the separable solve):
   // pc [4][nr] (PortDev), F = (D^-1 + U^T A0^-1 U)^-1 over the m port cells
-  // [m][m] (symmetric), q0[k] = Q[k][0] [nz], z = F U^T y [m]; the
+  // [m][m] (symmetric), q0[k] = Q[k][0] [nz], z = F U^T y [m] followed by
+  // the coupling's partial sums [32][m]; the
   // electrostatic wall profile [nr+1] (always present)
   double* port_pc;
   double* port_F;

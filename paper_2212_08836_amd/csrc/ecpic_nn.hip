@@ -4,7 +4,7 @@
 // ReLU between layers, on the (nr+1) x (nz+1) canvas of the staggered field
 // arrays, predicting the correction of the extrapolated guess 2u^n - u^{n-1}
 // of u^{n+1}.  BF16 weights and activations on the matrix cores
-// (v_mfma_f32_32x32x8bf16_1k), FP32 accumulation.
+// (v_mfma_f32_32x32x16_bf16), FP32 accumulation.
 //
 // Layout: activations channels-last, [image][i][j][channel], 32 channels
 // (8 for the 6-channel input).  Each wavefront computes a 32 (output
@@ -14,6 +14,12 @@
 // product with the taps flipped and the channel roles swapped; the weight
 // gradient is a product over positions, reduced per wavefront and then over
 // wavefronts in a fixed order.
+//
+// The products use gfx950's double-K BF16 instruction
+// (v_mfma_f32_32x32x16_bf16): lane l holds A[l % 32][8 (l / 32) + 0..7] and
+// B[8 (l / 32) + 0..7][l % 32], and D in the layout of the 32x32x8 form.  A
+// 32-channel tap takes two of them; the 8-channel input layer puts two taps
+// in one (each half of the wavefront takes one tap's 8 channels).
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -31,8 +37,22 @@ constexpr int kCH = 32;          // channels of a hidden activation / MFMA M
 constexpr int kWaves = 4;        // wavefronts per block
 constexpr int kGradWaves = 256;  // wavefronts of the weight-gradient pass
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+
+// 8 BF16 values (16 bytes, 16-byte aligned) as an MFMA operand
+__device__ __forceinline__ v8bf ld8(const uint16_t* p) {
+  return __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(p));
+}
+__device__ __forceinline__ v8bf zero8() { return __builtin_bit_cast(v8bf, make_uint4(0u, 0u, 0u, 0u)); }
+__device__ __forceinline__ v8bf pack8(const uint16_t (&v)[8]) {
+  uint4 u;
+  u.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+  u.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+  u.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+  u.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+  return __builtin_bit_cast(v8bf, u);
+}
 
 __host__ __device__ inline int64_t layer_w_off(int l) {
   int64_t o = 0;
@@ -65,23 +85,35 @@ __global__ void __launch_bounds__(64 * kWaves)
   const int64_t ni = tile / tw;
   const int i = (int)(ni % H);
   const int n = (int)(ni / H);
-  const int col = lane & 31, kq = (lane >> 5) * 4;
+  const int col = lane & 31, kh = lane >> 5, kq = kh * 4;
   const int j = jt * 32 + col;
   v16f acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  if (CINP == 32) {
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ii = i + tap / 3 - 1, jj = j + tap % 3 - 1;
-    const bool ok = j < W && ii >= 0 && ii < H && jj >= 0 && jj < W;
-    const uint16_t* src = in + (((int64_t)n * H + ii) * W + jj) * CINP + kq;
-    const uint16_t* wa = A + ((int64_t)tap * kCH + col) * CINP + kq;
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ii = i + tap / 3 - 1, jj = j + tap % 3 - 1;
+      const bool ok = j < W && ii >= 0 && ii < H && jj >= 0 && jj < W;
+      const uint16_t* src = in + (((int64_t)n * H + ii) * W + jj) * CINP + 8 * kh;
+      const uint16_t* wa = A + ((int64_t)tap * kCH + col) * CINP + 8 * kh;
 #pragma unroll
-    for (int c8 = 0; c8 < CINP / 8; ++c8) {
-      const v4s a = *reinterpret_cast<const v4s*>(wa + c8 * 8);
-      v4s b = {0, 0, 0, 0};
-      if (ok) b = *reinterpret_cast<const v4s*>(src + c8 * 8);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+      for (int c16 = 0; c16 < 2; ++c16) {
+        const v8bf a = ld8(wa + 16 * c16);
+        const v8bf b = ok ? ld8(src + 16 * c16) : zero8();
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+    }
+  } else {
+    // 8 channels: taps 2p (lanes 0-31) and 2p + 1 (lanes 32-63) per product
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      const int tap = 2 * p + kh;
+      const int ii = i + tap / 3 - 1, jj = j + tap % 3 - 1;
+      const bool ok = tap < 9 && j < W && ii >= 0 && ii < H && jj >= 0 && jj < W;
+      const v8bf a = tap < 9 ? ld8(A + ((int64_t)tap * kCH + col) * CINP) : zero8();
+      const v8bf b = ok ? ld8(in + (((int64_t)n * H + ii) * W + jj) * CINP) : zero8();
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
   }
   if (j >= W) return;
@@ -128,7 +160,7 @@ __global__ void __launch_bounds__(64 * kWaves)
   const int wv = blockIdx.x * kWaves + (threadIdx.x >> 6);
   const int64_t tw = (W + 31) / 32;
   const int64_t ntile = (int64_t)nimg * H * tw;
-  const int row = lane & 31, kq = (lane >> 5) * 4;
+  const int row = lane & 31, kh = lane >> 5, kq = kh * 4;
   v16f acc[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t)
@@ -141,31 +173,32 @@ __global__ void __launch_bounds__(64 * kWaves)
     const int i = (int)(ni % H);
     const int n = (int)(ni / H);
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      // the 4 positions of this lane's K slice: j = jt*32 + ks*8 + kq + 0..3
-      v4s a;
+    for (int ks = 0; ks < 2; ++ks) {
+      // the 8 positions of this lane's K slice: j = jt*32 + ks*16 + 8*kh + 0..7
+      uint16_t av[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = jt * 32 + ks * 8 + kq + q;
+      for (int q = 0; q < 8; ++q) {
+        const int j = jt * 32 + ks * 16 + 8 * kh + q;
         uint16_t gv = 0;
         if (j < W) gv = g[(((int64_t)n * H + i) * W + j) * kCH + row];
-        a[q] = (short)gv;
+        av[q] = gv;
         db += bf2f(gv);
       }
+      const v8bf a = pack8(av);
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
         const int ii = i + tap / 3 - 1;
-        v4s b;
+        uint16_t bv[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int j = jt * 32 + ks * 8 + kq + q;
+        for (int q = 0; q < 8; ++q) {
+          const int j = jt * 32 + ks * 16 + 8 * kh + q;
           const int jj = j + tap % 3 - 1;
           uint16_t xv = 0;
           if (row < CINP && j < W && ii >= 0 && ii < H && jj >= 0 && jj < W)
             xv = x[(((int64_t)n * H + ii) * W + jj) * CINP + row];
-          b[q] = (short)xv;
+          bv[q] = xv;
         }
-        acc[tap] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[tap], 0, 0, 0);
+        acc[tap] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack8(bv), acc[tap], 0, 0, 0);
       }
     }
   }
