@@ -94,6 +94,11 @@ def committed_traffic(workload, precision):
         return None
 
 
+# steps between counting sorts, measured per workload (the sorted order
+# decays faster where the cells are small against a step's travel)
+SORT_EVERY = {"c5": 16}
+
+
 def sort_period(steps, cap=32):
     """The largest divisor of `steps` not above cap."""
     for p in range(min(cap, steps), 0, -1):
@@ -375,6 +380,9 @@ def main():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the mixed-precision and learned-guess legs")
     ap.add_argument("--no-nn", action="store_true", help="skip the learned-guess legs")
+    ap.add_argument("--sort-every", type=int, default=0,
+                    help="steps between counting sorts (0: the workload's own cadence); "
+                         "rounded down to a divisor of --steps")
     ap.add_argument("--legs", default="es,port,jfnk,mixed,nn",
                     help="comma-separated legs to run beside the headline (of es, port, jfnk, "
                          "mixed, nn)")
@@ -401,7 +409,7 @@ def main():
     torch.cuda.set_device(0)
     w = E.workload(args.workload)
     device_gen = args.workload in ("c3", "c5")
-    period = sort_period(args.steps)
+    period = sort_period(args.steps, args.sort_every or SORT_EVERY.get(args.workload, 32))
     log(f"generating the {args.workload} particles ({'GPU' if device_gen else 'host'})")
     parts = particles(E, w, device_gen)
     n0 = sum(int(len(p["r"])) for p in parts)
