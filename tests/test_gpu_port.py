@@ -185,3 +185,51 @@ def test_port_absorbs_after_a_burst_on_the_gpu(torch_cuda):
         Wmax, Wp = max(Wmax, W), W
     _flush(f"port absorption: largest rise {rise:.1e}, left {W / W_end:.1e}")
     assert rise <= 1e-13 and W / W_end < 1e-4
+
+
+def _face_capacitance(og, w):
+    """The electrode's face charge per volt with the port: one static
+    solve of the electrostatic model (the same reading of Eq. (6)'s face)."""
+    g = og.Grid(w.nr, w.nz, w.R, w.L, w.xi_a, w.dt, E.EPS0, E.MU0, drive_amp=(1.0,),
+                drive_freq=(1e3,), model="es", port_i=w.port_i, port_eps=w.port_eps)
+    t = g.tables()
+    _, uz1, _ = g.field_solve(g.zeros_r(), g.zeros_z(), g.zeros_h(), g.zeros_r(), g.zeros_z(), 0.0)
+    uz = uz1.reshape(w.nr + 1, w.nz)
+    return sum(t["wz"][i] * uz[i, 0] for i in range(w.port_i + 1)) / g.drive(w.dt)
+
+
+def test_em_port_reproduces_the_electrostatic_electrode_voltage(og, torch_cuda):
+    """Sec. 3.3 with the paper's drive: a 3e15 m^-3 plasma driven at 50 MHz
+    through the port and a blocking capacitor (100 x the face capacitance)
+    for three periods.  The EM model's electrode potential over the third
+    period (dc self-bias, first-harmonic amplitude and phase) matches the
+    electrostatic model's at c* = c (the cavity is small against the
+    wavelength) and more closely at c* = 10 c; runs of one configuration
+    differ by about 0.05 V (the order of the FP64 atomics).  Tolerance
+    1e-8: in runs of thousands of steps a particle whose wall or face event
+    flips between iterates can hold the Picard residual in a cycle (seen at
+    8e-11 .. 1.6e-6 on the GPU, whose runs differ in their last bits); the
+    electrode voltage does not depend on the last digits."""
+    import paper_2212_08836_amd as P
+    f = 50e6
+    w = E.Workload("p", 32, 32, 0.02, 0.02, n0=3e15, ppc=32, dt=5e-11, drive_amp=(100.0,),
+                   drive_freq=(f,), seed=3, tol=1e-8, port_i=24, port_eps=3.8)
+    cap = 100.0 * _face_capacitance(og, w)
+    per = int(round(1.0 / (f * w.dt)))
+    t = w.dt * np.arange(2 * per + 1, 3 * per + 1)
+    A = np.stack([np.sin(2 * math.pi * f * t), np.cos(2 * math.pi * f * t), np.ones(per)], 1)
+    out = {}
+    for model, cf in (("es", 1.0), ("em", 1.0), ("em", 10.0)):
+        ctx = P.context_from_workload(w, model=model, blocking_cap=cap, mu=E.MU0 / cf ** 2)
+        P.load_workload_species(ctx, E.make_particles(w), extra_cap=0.5)
+        phi = [ctx.step(tol=w.tol, max_iter=50)["electrode_v"] for _ in range(3 * per)]
+        ctx.close()
+        (s, c, bias), *_ = np.linalg.lstsq(A, np.array(phi[2 * per:]), rcond=None)
+        out[(model, cf)] = (bias, math.hypot(s, c), math.atan2(c, s))
+        _flush(f"  {model} c* = {cf:g} c: self-bias {bias:.2f} V, amplitude {math.hypot(s, c):.2f} V, "
+               f"phase {math.atan2(c, s):.4f}")
+    b0, a0, p0 = out[("es", 1.0)]
+    assert b0 < -10.0  # the smaller powered electrode charges negative
+    for cf, db, da, dp in ((1.0, 0.05, 0.005, 0.01), (10.0, 0.01, 0.002, 0.005)):
+        b, a, p = out[("em", cf)]
+        assert abs(b / b0 - 1.0) < db and abs(a / a0 - 1.0) < da and abs(p - p0) < dp, (cf, out)
