@@ -875,7 +875,7 @@ static int push_one(const pctx* P, pst* p, double qw, double* Ir, double* Iz,
   const double dt = c->g.dt;
   const double qw_dt = qw / dt;
   double tau = dt;
-  int nsub = 0;
+  int nsub = 0, ncut = 0; /* ncut: halvings after crossing solves that found no face */
   hit->wall = 0;
   while (tau > 0.0) {
     if (nsub >= OG_MAX_SUB) { if (S) S->n_errors++; return P_ERROR; }
@@ -883,6 +883,7 @@ static int push_one(const pctx* P, pst* p, double qw, double* Ir, double* Iz,
     const int i = cell_of(p->xi, p->vr, nr);
     const int j = cell_of(p->eta, p->vz, nz);
     double dtry = tau, xb = 0, eb = 0, vb[3];
+    for (int k = 0; k < ncut; ++k) dtry *= 0.5;
     int ok = 0, nh = 0;
     for (nh = 0; nh <= OG_MAX_HALVE; ++nh) {
       ok = solve_free(P, i, j, p, dtry, &xb, &eb, vb);
@@ -890,7 +891,6 @@ static int push_one(const pctx* P, pst* p, double qw, double* Ir, double* Iz,
       dtry *= 0.5;
     }
     if (!ok) { if (S) S->n_errors++; return P_ERROR; }
-    if (S) { S->n_substeps++; S->n_halvings += nh; }
     pst e;
     e.xi = 2.0 * xb - p->xi;
     e.eta = 2.0 * eb - p->eta;
@@ -900,6 +900,8 @@ static int push_one(const pctx* P, pst* p, double qw, double* Ir, double* Iz,
     const int in_x = (e.xi >= i && e.xi <= i + 1);
     const int in_e = (e.eta >= j && e.eta <= j + 1);
     if (in_x && in_e) {
+      if (S) { S->n_substeps++; S->n_halvings += nh + ncut; }
+      ncut = 0;
       deposit(c, i, j, p->xi, p->eta, e.xi, e.eta, qw_dt, Ir, Iz);
       if (work) *work += substep_work(c, P, i, j, p->xi, p->eta, e.xi, e.eta, qw);
       *p = e;
@@ -931,7 +933,17 @@ static int push_one(const pctx* P, pst* p, double qw, double* Ir, double* Iz,
         bv[0] = cv[0]; bv[1] = cv[1]; bv[2] = cv[2]; best_cap = cap;
       }
     }
-    if (best_d < 0) { if (S) S->n_errors++; return P_ERROR; }
+    if (best_d < 0) {
+      /* the free orbit leaves the cell but no face can be reached
+       * consistently (an orbit that turns at the face: the crossing solve
+       * jumps between a root and none): take the sub-step again at half
+       * the length (a new pass of the loop, counted like a sub-step) */
+      if (ncut >= OG_MAX_HALVE) { if (S) S->n_errors++; return P_ERROR; }
+      ncut++;
+      continue;
+    }
+    if (S) { S->n_substeps++; S->n_halvings += nh + ncut; }
+    ncut = 0;
     if (S) { S->n_crossings++; if (best_cap) S->n_capped++; }
     pst q;
     q.vr = 2.0 * bv[0] - p->vr;

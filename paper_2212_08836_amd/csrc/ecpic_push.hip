@@ -507,6 +507,8 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
   // the crossing is solved (pf_i < 0: none)
   T Fn[4];
   int pf_i = -1, pf_j = -1;
+  // halvings of the sub-step after crossing solves that found no face
+  int cut = 0;
   while (tau > T(0)) {
     if (out.nsub >= kMaxSub) {
       out.status = kError;
@@ -559,6 +561,7 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
       }
     }
     T dtry = tau;
+    for (int k = 0; k < cut; ++k) dtry *= T(0.5);
     Mid<T> M;
     // linear-map cells: the closed-form solve (the same mid point as the
     // fixed point, to its tolerance); otherwise the fixed point, halving
@@ -630,8 +633,16 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
         }
       }
       if (cd < 0) {
-        out.status = kError;
-        return;
+        // the free orbit leaves the cell but no face can be reached
+        // consistently (it turns at the face: the crossing solve jumps
+        // between a root and none): the sub-step is taken again at half
+        // the length
+        if (cut >= kMaxHalve) {
+          out.status = kError;
+          return;
+        }
+        ++cut;
+        continue;
       }
       out.ncross++;
       q.vr = T(2) * BM.vr - p.vr;
@@ -654,6 +665,7 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
     tile_or_global(tl, Ir, Iz, nz, p.i, p.j, dp);
     p = q;
     tau -= used;
+    cut = 0;
     if (cd == 0 && cf == T(1) && p.i == nr - 1) {
       out.status = kAbsorbed;
       out.wall = 3;

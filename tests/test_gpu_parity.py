@@ -834,3 +834,33 @@ def test_run_driven_collisional_matches_oracle(og, torch_cuda):
     _flush(f"  after 8 steps ({ion} ionisations): worst rel {max(errs):.2e}")
     assert ion > 0
     assert max(errs) < TOL
+
+
+@pytest.mark.parametrize("waves", [2, 3])
+def test_orbit_that_turns_at_a_face(og, torch_cuda, waves):
+    """The electron of tests/golden/grazing_particle.npz (from the oracle's
+    own run): its free sub-step leaves the cell across the eta face, its orbit
+    turns there and no face can be reached consistently, so the sub-step is
+    taken again at half the length on both sides.  Both builds of the slow
+    pass, uncommitted and committed, against the oracle."""
+    import os
+    import paper_2212_08836_amd as P
+    d = np.load(os.path.join(os.path.dirname(__file__), "golden", "grazing_particle.npz"))
+    w = E.Workload("p", 32, 32, 0.02, 0.02, dt=5e-11, port_i=24, port_eps=3.8)
+    g0 = og.grid_from_workload(w)
+    e = dict(q=float(d["q"]), m=float(d["m"]), w=float(d["w"]), r=g0.r_of_xi(d["xi"]),
+             z=d["eta"] * (w.L / w.nz), vr=d["vr"].copy(), vt=d["vt"].copy(), vz=d["vz"].copy(),
+             uid=d["uid"].copy())
+    empty = {k: (v[:0] if isinstance(v, np.ndarray) else v) for k, v in e.items()}
+    g, sp, ctx = _make_pair(w, og, P, [e, empty])
+    ctx.set_option(P.ECPIC_OPT_QUEUE_WAVES, waves)
+    ctx.set_half_field(d["ur_h"], d["uz_h"])
+    Ir_g, Iz_g = ctx.push_deposit(commit=False)
+    Ir_o, Iz_o, rc, st = g.push_deposit(sp[0], d["ur_h"], d["uz_h"], commit=False)
+    assert rc == 0 and st["n_halvings"] >= 1 and st["n_errors"] == 0
+    # the electron moves 7e-4 of a cell in eta near eta = 23: its z current
+    # is at the floor of the oracle's global positions
+    assert _currents_ok((Ir_g, Iz_g), (Ir_o, Iz_o), w, [e], "turning electron")
+    ctx.push_deposit(commit=True)
+    g.push_deposit(sp[0], d["ur_h"], d["uz_h"], commit=True, state=og.State(g))
+    assert _cmp_species(ctx.read_particles(0), sp[0].view(), "turning electron") < TOL

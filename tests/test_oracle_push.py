@@ -247,3 +247,28 @@ def test_exb_epicyclic_frequency_is_second_order(og):
         errs.append(abs(_sinusoid_frequency(r * r, dt) / W - 1))
     assert errs[0] < 1e-2
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+def test_orbit_that_turns_at_a_face_takes_a_halved_substep(og):
+    """tests/golden/grazing_particle.npz (written by make_grazing_fixture.py
+    from the oracle's own run): the electron's free sub-step leaves its cell
+    across the eta face, but its orbit turns there, so no face can be
+    reached consistently.  The sub-step is taken again at half the length:
+    the push succeeds, charge is conserved to round-off and the work done
+    equals the deposited power (the identities every sub-step keeps)."""
+    import os
+    d = np.load(os.path.join(os.path.dirname(__file__), "golden", "grazing_particle.npz"))
+    g = og.Grid(32, 32, 0.02, 0.02, 2.0, 5e-11, EPS0, MU0, port_i=24, port_eps=3.8)
+    q, m, w = float(d["q"]), float(d["m"]), float(d["w"])
+    sp = og.Species(q, m, w, d["xi"], d["eta"], d["vr"], d["vt"], d["vz"], d["uid"], cap=2)
+    qw = q * w
+    Q0 = _bilinear_charge(32, 32, sp.xi[:1], sp.eta[:1], qw)
+    e0 = 0.5 * m * w * (sp.vr[0] ** 2 + sp.vt[0] ** 2 + sp.vz[0] ** 2)
+    Ir, Iz, rc, st = g.push_deposit(sp, d["ur_h"], d["uz_h"], commit=True, state=og.State(g))
+    assert rc == 0 and st["n_errors"] == 0 and st["n_halvings"] >= 1 and sp.n == 1
+    Q1 = _bilinear_charge(32, 32, sp.xi[:1], sp.eta[:1], qw)
+    res = Q1 - Q0 + g.dt * g.div(Ir, Iz).reshape(33, 33)
+    assert np.abs(res).max() <= 1e-13 * abs(qw)
+    e1 = 0.5 * m * w * (sp.vr[0] ** 2 + sp.vt[0] ** 2 + sp.vz[0] ** 2)
+    pw = g.dt * (np.dot(d["ur_h"], Ir) + np.dot(d["uz_h"], Iz))
+    assert abs((e1 - e0) - pw) <= 1e-10 * e0
