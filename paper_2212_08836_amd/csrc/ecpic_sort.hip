@@ -119,10 +119,30 @@ __global__ void k_hist(MapP m, SpecDev s, int64_t n, int mixed, int32_t* hist) {
 }
 
 // scatter to the cell's slots: one atomic per run, which keeps the order of
-// the run's particles
+// the run's particles.  The record is loaded before the slot is claimed, so
+// its loads are in flight while the atomic returns.
 __global__ void k_scatter(MapP m, SpecDev src, SpecDev dst, int64_t n, int mixed, int32_t* offs) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int c = (k < n) ? cell_key(m, src, k, mixed != 0) : -1;
+  double x[5] = {0, 0, 0, 0, 0};
+  float f[5] = {0, 0, 0, 0, 0};
+  uint64_t id = 0;
+  if (c >= 0) {
+    if (!mixed) {
+      x[0] = src.xi[k];
+      x[1] = src.eta[k];
+      x[2] = src.vr[k];
+      x[3] = src.vt[k];
+      x[4] = src.vz[k];
+    } else {
+      f[0] = src.fa[k];
+      f[1] = src.fb[k];
+      f[2] = src.fvr[k];
+      f[3] = src.fvt[k];
+      f[4] = src.fvz[k];
+    }
+    id = src.uid[k];
+  }
   const Run r = wave_run(c);
   int base = 0;
   if (c >= 0 && r.rank == 0) base = atomicAdd(&offs[c], r.len);
@@ -130,20 +150,20 @@ __global__ void k_scatter(MapP m, SpecDev src, SpecDev dst, int64_t n, int mixed
   if (c < 0) return;
   const int64_t d = (int64_t)base + r.rank;
   if (!mixed) {
-    dst.xi[d] = src.xi[k];
-    dst.eta[d] = src.eta[k];
-    dst.vr[d] = src.vr[k];
-    dst.vt[d] = src.vt[k];
-    dst.vz[d] = src.vz[k];
+    dst.xi[d] = x[0];
+    dst.eta[d] = x[1];
+    dst.vr[d] = x[2];
+    dst.vt[d] = x[3];
+    dst.vz[d] = x[4];
   } else {
     dst.cell[d] = c;
-    dst.fa[d] = src.fa[k];
-    dst.fb[d] = src.fb[k];
-    dst.fvr[d] = src.fvr[k];
-    dst.fvt[d] = src.fvt[k];
-    dst.fvz[d] = src.fvz[k];
+    dst.fa[d] = f[0];
+    dst.fb[d] = f[1];
+    dst.fvr[d] = f[2];
+    dst.fvt[d] = f[3];
+    dst.fvz[d] = f[4];
   }
-  dst.uid[d] = src.uid[k];
+  dst.uid[d] = id;
 }
 
 // Kinetic energy of a species: a fixed grid (kKineticBlocks) strides over
