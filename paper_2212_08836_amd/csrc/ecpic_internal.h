@@ -140,7 +140,6 @@ struct PushArgs {
   double* wall_side;
   Tally* tally;
   MccDev mcc;
-  int32_t* hist;     // per-cell counts of the survivors (commit), or null
   const int32_t* stop;  // when set and nonzero the pass does nothing (or null)
 };
 
