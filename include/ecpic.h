@@ -244,7 +244,10 @@ typedef struct ecpic_ctx ecpic_ctx;
 /* Create a context for the grid (Sec. 2.1 mesh and TM field model) and
  * factorise the H_theta system.  hip_stream: a hipStream_t (NULL = default
  * stream).  Fields start at zero, t = 0, step = 0.  EINVAL on bad shapes or
- * non-positive constants, ENOMEM/EHIP on device failures. */
+ * non-positive constants, ENOMEM/EHIP on device failures.  Shapes: nr <=
+ * 2048, nz <= 1024 and ceil(nr/4) * ceil(nz/32) <= 8192 (1024 x 1024 and
+ * 2048 x 512 fit), the limits of the field solve's blocking and of the
+ * kernels' per-row LDS arrays; EINVAL beyond. */
 ecpic_status ecpic_create(const ecpic_grid_desc* grid, ecpic_precision prec, void* hip_stream,
                           ecpic_ctx** out);
 ecpic_status ecpic_destroy(ecpic_ctx* ctx);

@@ -768,7 +768,7 @@ ecpic_status ecpic_create(const ecpic_grid_desc* g, ecpic_precision prec, void* 
       (g->model != ECPIC_MODEL_EM && g->model != ECPIC_MODEL_ES) ||
       !(g->blocking_cap >= 0.0) || !std::isfinite(g->blocking_cap) ||
       (g->model == ECPIC_MODEL_ES && g->nz < 2) ||
-      (int64_t)g->nr * g->nz > (int64_t)1 << 28 || g->port_i < 0 ||
+      !grid_fits(g->nr, g->nz) || g->port_i < 0 ||
       (g->port_i > 0 && (g->port_i >= g->nr || !(g->port_eps > 0.0) ||
                          !std::isfinite(g->port_eps))))
     return ECPIC_EINVAL;

@@ -220,6 +220,7 @@ __device__ Aff block_exscan(Aff v, bool reverse, Aff* sA) {
 }
 
 constexpr int kMaxE = 8;  // rows per thread: nr <= kFB * kMaxE
+static_assert(kFB * kMaxE == kMaxNr && kRB == 4 && kCC == 32, "grid_fits() limits");
 
 // kCorr: the port's correction pass.  The right-hand side of mode k is
 // q0[k] z on the port rows (zero elsewhere) and the solution is subtracted

@@ -189,6 +189,16 @@ struct SolveArgs {
 
 constexpr int kRedBlocks = 256;  // partial-sum blocks of the field reductions
 constexpr int kResParts = 8192;  // blocks of the field solve that write residual partials
+// Grid limits checked at creation: the field solve's per-mode scan holds at
+// most 2048 rows (256 threads x 8), its transform blocks (4 rows x 32
+// columns) write at most kResParts residual partials, and the row-sized
+// LDS arrays of the transform and push kernels fit 64 KB with nz <= 1024.
+constexpr int kMaxNr = 2048;
+constexpr int kMaxNz = 1024;
+inline bool grid_fits(int nr, int nz) {
+  return nr <= kMaxNr && nz <= kMaxNz &&
+         (int64_t)((nr + 3) / 4) * ((nz + 31) / 32) <= kResParts;
+}
 
 struct Species {
   ecpic_species_desc desc;

@@ -1,6 +1,8 @@
 // ecpic_sort.hip -- counting sort of particles by cell (the fine sorting the
 // paper's GPU parallelisation builds on, Sec. 2.1) with compaction of
 // absorbed particles, an exclusive scan, and particle-side reductions.
+#include <climits>
+
 #include "ecpic_internal.h"
 
 namespace ecpic {
@@ -92,78 +94,238 @@ __device__ __forceinline__ int cell_key(const MapP& m, const SpecDev& s, int64_t
   return i * m.nz + j;
 }
 
-// Runs of equal consecutive keys in a wavefront (particles are nearly sorted
-// by cell, so a wavefront holds a few long runs): the first lane of a run and
-// the run's length, and my rank in it.
-struct Run {
-  int start, len, rank;
+// Block-local counting (histogram and scatter).  A block takes kSortChunk
+// consecutive slots; between sorts they hold the particles of a few
+// neighbouring cells that have drifted a few cells in z or a row in r, so
+// their cells fall in a window of sort_window(nz) = 2 nz + 256 cells from
+// lo = max(lowest cell, first slot's cell - nz - 32): counts and ranks are
+// taken with LDS atomics there and the global counters see one atomic per
+// occupied window cell and block.  Slots of cells outside the window (born
+// elsewhere and appended, or before the first sort) use global atomics of
+// their own.  Dead slots (cell < 0) are dropped.
+constexpr int kSortThreads = 256;
+constexpr int kSortPer = 8;
+constexpr int kSortChunk = kSortThreads * kSortPer;  // 2048 slots per block
+__host__ __device__ inline int sort_window(int nz) { return 2 * nz + 256; }
+static_assert(2 * kMaxNz + 256 <= 4096, "window counters within 16 KB of LDS");
+
+// the cells of a thread's slots (k = block start + q * kSortThreads + tid)
+// and the window's first cell; every thread of the block calls it
+__device__ __forceinline__ int sort_keys(const MapP& m, const SpecDev& s, int64_t n, bool mixed,
+                                         int64_t k0, int key[kSortPer]) {
+  __shared__ int wmin[kSortThreads / 64];
+  __shared__ int cref;
+  int mn = INT_MAX;
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int64_t k = k0 + (int64_t)q * kSortThreads + threadIdx.x;
+    key[q] = (k < n) ? cell_key(m, s, k, mixed) : -1;
+    if (key[q] >= 0) mn = min(mn, key[q]);
+  }
+  if (threadIdx.x == 0) cref = key[0];
+  for (int off = 32; off > 0; off >>= 1) mn = min(mn, __shfl_xor(mn, off, 64));
+  if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = mn;
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < kSortThreads / 64; ++w) mn = min(mn, wmin[w]);
+  int lo = mn == INT_MAX ? 0 : mn;
+  if (cref >= 0) lo = max(lo, cref - m.nz - 32);
+  return lo;
+}
+
+// per-cell counts of one species (hist zeroed beforehand)
+__global__ void __launch_bounds__(kSortThreads)
+    k_hist(MapP m, SpecDev s, int64_t n, int mixed, int32_t* hist) {
+  extern __shared__ int32_t cnt[];
+  const int W = sort_window(m.nz);
+  for (int e = threadIdx.x; e < W; e += kSortThreads) cnt[e] = 0;
+  int key[kSortPer];
+  const int lo = sort_keys(m, s, n, mixed != 0, (int64_t)blockIdx.x * kSortChunk, key);
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int c = key[q], e = c - lo;
+    if (c < 0) continue;
+    if (e >= 0 && e < W)
+      atomicAdd(&cnt[e], 1);
+    else
+      atomicAdd(&hist[c], 1);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < W; e += kSortThreads) {
+    const int v = cnt[e];
+    if (v) atomicAdd(&hist[lo + e], v);
+  }
+}
+
+// Where a block's slots go: for a window slot, its place lp in the block's
+// cell-ordered stage (its cell's offset in the block + its rank) and, for
+// the writer of stage place t, the destination dest[t]; for the others the
+// global slot claimed on their own.
+struct SortPlan {
+  int key[kSortPer];   // cell, -1 for a dead slot
+  int pos[kSortPer];   // lp (>= 0), or -(global slot) - 1
+  int dest[kSortPer];  // destination of stage place q * kSortThreads + tid
+  int lo, W, ns;       // window and number of staged slots
 };
-__device__ __forceinline__ Run wave_run(int key) {
-  const int lane = threadIdx.x & 63;
-  const int prev = __shfl_up(key, 1, 64);
-  const bool head = (lane == 0) || (prev != key);
-  const uint64_t heads = __ballot(head);
-  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-  const int start = 63 - __clzll(heads & upto);
-  const uint64_t after = heads & ~upto;
-  const int end = after ? (__ffsll((unsigned long long)after) - 1) : 64;
-  return Run{start, end - start, lane - start};
+
+// One column moved through the stage: loads of the block's slots (one per
+// thread and round, coalesced), staged in cell order, then stored by the
+// writers to consecutive destinations of each cell.  CELL: the mixed
+// layout's cell column, whose values are the keys themselves.
+template <typename E, bool CELL = false>
+__device__ __forceinline__ void scatter_col(const SortPlan& P, int64_t k0, const E* __restrict__ src,
+                                            E* __restrict__ dst, E* stage) {
+  E v[kSortPer];
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int64_t k = k0 + (int64_t)q * kSortThreads + threadIdx.x;
+    if constexpr (CELL)
+      v[q] = (E)P.key[q];
+    else
+      v[q] = P.key[q] >= 0 ? src[k] : E(0);
+  }
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    if (P.key[q] < 0) continue;
+    if (P.pos[q] >= 0)
+      stage[P.pos[q]] = v[q];
+    else
+      dst[-(int64_t)P.pos[q] - 1] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int t = q * kSortThreads + threadIdx.x;
+    if (t < P.ns) dst[P.dest[q]] = stage[t];
+  }
+  __syncthreads();
 }
 
-// per-cell counts, one atomic per run of equal cells in a wavefront
-__global__ void k_hist(MapP m, SpecDev s, int64_t n, int mixed, int32_t* hist) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int c = (k < n) ? cell_key(m, s, k, mixed != 0) : -1;
-  const Run r = wave_run(c);
-  if (c >= 0 && r.rank == 0) atomicAdd(&hist[c], r.len);
-}
-
-// scatter to the cell's slots: one atomic per run, which keeps the order of
-// the run's particles.  The record is loaded before the slot is claimed, so
-// its loads are in flight while the atomic returns.
-__global__ void k_scatter(MapP m, SpecDev src, SpecDev dst, int64_t n, int mixed, int32_t* offs) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int c = (k < n) ? cell_key(m, src, k, mixed != 0) : -1;
-  double x[5] = {0, 0, 0, 0, 0};
-  float f[5] = {0, 0, 0, 0, 0};
-  uint64_t id = 0;
-  if (c >= 0) {
-    if (!mixed) {
-      x[0] = src.xi[k];
-      x[1] = src.eta[k];
-      x[2] = src.vr[k];
-      x[3] = src.vt[k];
-      x[4] = src.vz[k];
-    } else {
-      f[0] = src.fa[k];
-      f[1] = src.fb[k];
-      f[2] = src.fvr[k];
-      f[3] = src.fvt[k];
-      f[4] = src.fvz[k];
+// Scatter to the cells' slots (offs: the exclusive scan of the counts, each
+// entry advanced by what is claimed from it).  The block's window slots are
+// ranked per cell by LDS atomics and laid out in cell order in LDS; one
+// global atomic per occupied cell claims the cell's range, and the columns
+// go out one at a time through the LDS stage, consecutive threads writing
+// consecutive slots of a cell.  Order within a cell is not kept.
+template <bool MIXED>
+__global__ void __launch_bounds__(kSortThreads)
+    k_scatter(MapP m, SpecDev src, SpecDev dst, int64_t n, int32_t* offs) {
+  extern __shared__ int32_t cnt[];                      // [W], then offset << 16 | list index
+  __shared__ uint64_t stage[kSortChunk];                // lists, then slot lists, then columns
+  __shared__ int nocc, nstaged;
+  int32_t* occ_e = reinterpret_cast<int32_t*>(stage);   // occupied cells [nocc]
+  int32_t* occ_v = occ_e + kSortChunk;                  // their counts, then dest - lp
+  SortPlan P;
+  P.W = sort_window(m.nz);
+  const int W = P.W;
+  for (int e = threadIdx.x; e < W; e += kSortThreads) cnt[e] = 0;
+  const int64_t k0 = (int64_t)blockIdx.x * kSortChunk;
+  P.lo = sort_keys(m, src, n, MIXED, k0, P.key);
+  const int lo = P.lo;
+  // ranks within the block's cells, or global slots for the others
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int c = P.key[q], e = c - lo;
+    P.pos[q] = 0;
+    if (c < 0) continue;
+    if (e >= 0 && e < W)
+      P.pos[q] = atomicAdd(&cnt[e], 1);
+    else
+      P.pos[q] = -atomicAdd(&offs[c], 1) - 1;
+  }
+  __syncthreads();
+  // exclusive scan of the counts over the window (consecutive entries per
+  // thread) with the occupied cells listed in order
+  {
+    const int per = (W + kSortThreads - 1) / kSortThreads;
+    const int e0 = threadIdx.x * per, e1 = min(e0 + per, W);
+    int tot = 0, nnz = 0;
+    for (int e = e0; e < e1; ++e) {
+      const int v = cnt[e];
+      tot += v;
+      nnz += v ? 1 : 0;
     }
-    id = src.uid[k];
+    // counts and occupied cells packed (each at most kSortChunk) and scanned together
+    const int x = (tot << 16) | nnz;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += o;
+    }
+    __shared__ int wsum[kSortThreads / 64];
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int base = 0, all = 0;
+#pragma unroll
+    for (int u = 0; u < kSortThreads / 64; ++u) {
+      base += u < w ? wsum[u] : 0;
+      all += wsum[u];
+    }
+    const int run = base + inc - x;
+    int off = run >> 16, li = run & 0xffff;
+    for (int e = e0; e < e1; ++e) {
+      const int v = cnt[e];
+      if (v) {
+        occ_e[li] = e;
+        occ_v[li] = v;
+        cnt[e] = (off << 16) | li;
+        off += v;
+        ++li;
+      }
+    }
+    if (threadIdx.x == 0) {
+      nocc = all & 0xffff;
+      nstaged = all >> 16;
+    }
   }
-  const Run r = wave_run(c);
-  int base = 0;
-  if (c >= 0 && r.rank == 0) base = atomicAdd(&offs[c], r.len);
-  base = __shfl(base, r.start, 64);
-  if (c < 0) return;
-  const int64_t d = (int64_t)base + r.rank;
-  if (!mixed) {
-    dst.xi[d] = x[0];
-    dst.eta[d] = x[1];
-    dst.vr[d] = x[2];
-    dst.vt[d] = x[3];
-    dst.vz[d] = x[4];
+  __syncthreads();
+  // one global atomic per occupied cell: dest = lp + (claimed slot - offset)
+  for (int li = threadIdx.x; li < nocc; li += kSortThreads) {
+    const int e = occ_e[li];
+    const int g = atomicAdd(&offs[lo + e], occ_v[li]);
+    occ_v[li] = g - (cnt[e] >> 16);
+  }
+  // places in the stage
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int c = P.key[q], e = c - lo;
+    if (c >= 0 && e >= 0 && e < W) P.pos[q] += cnt[e] >> 16;
+  }
+  __syncthreads();
+  // the list index of each staged slot, then each writer's destinations
+  int32_t* slot_li = occ_e;  // occ_e is no longer read
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int c = P.key[q], e = c - lo;
+    if (c >= 0 && e >= 0 && e < W) slot_li[P.pos[q]] = cnt[e] & 0xffff;
+  }
+  __syncthreads();
+  P.ns = nstaged;
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int t = q * kSortThreads + threadIdx.x;
+    P.dest[q] = t < P.ns ? t + occ_v[slot_li[t]] : 0;
+  }
+  __syncthreads();
+  if constexpr (!MIXED) {
+    double* sd = reinterpret_cast<double*>(stage);
+    scatter_col<double>(P, k0, src.xi, dst.xi, sd);
+    scatter_col<double>(P, k0, src.eta, dst.eta, sd);
+    scatter_col<double>(P, k0, src.vr, dst.vr, sd);
+    scatter_col<double>(P, k0, src.vt, dst.vt, sd);
+    scatter_col<double>(P, k0, src.vz, dst.vz, sd);
   } else {
-    dst.cell[d] = c;
-    dst.fa[d] = f[0];
-    dst.fb[d] = f[1];
-    dst.fvr[d] = f[2];
-    dst.fvt[d] = f[3];
-    dst.fvz[d] = f[4];
+    float* sf = reinterpret_cast<float*>(stage);
+    scatter_col<int32_t, true>(P, k0, src.cell, dst.cell, reinterpret_cast<int32_t*>(stage));
+    scatter_col<float>(P, k0, src.fa, dst.fa, sf);
+    scatter_col<float>(P, k0, src.fb, dst.fb, sf);
+    scatter_col<float>(P, k0, src.fvr, dst.fvr, sf);
+    scatter_col<float>(P, k0, src.fvt, dst.fvt, sf);
+    scatter_col<float>(P, k0, src.fvz, dst.fvz, sf);
   }
-  dst.uid[d] = id;
+  scatter_col<uint64_t>(P, k0, src.uid, dst.uid, stage);
 }
 
 // Kinetic energy of a species: a fixed grid (kKineticBlocks) strides over
@@ -290,16 +452,18 @@ hipError_t launch_sort_async(Ctx& c, Species& sp, int32_t* total_pinned, hipStre
   SpecDev& src = sp.d[sp.cur];
   SpecDev& dst = sp.d[1 - sp.cur];
   hipLaunchKernelGGL(k_zero_i, dim3(nblk(ncell + 1)), dim3(kBlock), 0, st, c.hist, ncell + 1);
+  const int64_t nsb = (sp.n + kSortChunk - 1) / kSortChunk;
+  const size_t win = (size_t)sort_window(c.g.nz) * sizeof(int32_t);
   if (sp.n > 0)
-    hipLaunchKernelGGL(k_hist, dim3(nblk(sp.n)), dim3(kBlock), 0, st, c.m, src, sp.n, mixed,
+    hipLaunchKernelGGL(k_hist, dim3(nsb), dim3(kSortThreads), win, st, c.m, src, sp.n, mixed,
                        c.hist);
   hipError_t e = scan_exclusive(c.hist, ncell, c.scan_part, st);
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(total_pinned, c.hist + ncell, sizeof(int32_t), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return e;
   if (sp.n > 0)
-    hipLaunchKernelGGL(k_scatter, dim3(nblk(sp.n)), dim3(kBlock), 0, st, c.m, src, dst, sp.n,
-                       mixed, c.hist);
+    hipLaunchKernelGGL(mixed ? k_scatter<true> : k_scatter<false>, dim3(nsb), dim3(kSortThreads),
+                       win, st, c.m, src, dst, sp.n, c.hist);
   return hipGetLastError();
 }
 

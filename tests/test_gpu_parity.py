@@ -117,10 +117,11 @@ def test_load_read_roundtrip(og, torch_cuda):
         assert _cmp_species(d, sp[k].view(), "load") < 1e-14
 
 
-# nr > 256 gives the per-mode scan 2, 4 and 5 rows per thread
+# nr > 256 gives the per-mode scan 2, 4, 5 and (at the largest nr, 2048) 8
+# rows per thread; 40 x 1024 has the longest rows a grid may have
 @pytest.mark.parametrize("shape", [(32, 32, 2.0), (37, 29, 2.0), (70, 130, 0.0), (300, 16, 2.0),
                                    (512, 8, 2.0), (1024, 8, 2.0), (1100, 12, 0.0),
-                                   (1024, 512, 2.0)])
+                                   (1024, 512, 2.0), (2048, 8, 2.0), (40, 1024, 2.0)])
 def test_field_solve_parity(og, torch_cuda, shape):
     import paper_2212_08836_amd as P
     nr, nz, xa = shape
@@ -473,6 +474,49 @@ def test_sort_keeps_particles_and_orders_cells(og, torch_cuda):
             np.minimum(np.floor(d["eta"]).astype(int), w.nz - 1)
         assert np.all(np.diff(cell) >= 0)
         assert _cmp_species(d, before[k], "sort") == 0.0
+
+
+def _order_ok(d, nr, nz):
+    """Slots in cell order: the cell of each slot lies between the cells its
+    position allows (a particle on a face reads as either neighbour)."""
+    xi, eta = d["xi"], d["eta"]
+    ilo = np.clip(np.ceil(xi).astype(np.int64) - 1, 0, nr - 1)
+    ihi = np.clip(np.floor(xi).astype(np.int64), 0, nr - 1)
+    jlo = np.clip(np.ceil(eta).astype(np.int64) - 1, 0, nz - 1)
+    jhi = np.clip(np.floor(eta).astype(np.int64), 0, nz - 1)
+    lo, hi = ilo * nz + jlo, ihi * nz + jhi
+    return len(lo) < 2 or bool(np.all(np.maximum.accumulate(lo)[:-1] <= hi[1:]))
+
+
+@pytest.mark.parametrize("name,precision", [("c2", "fp64"), ("c2", "mixed"), ("rows", "fp64"),
+                                            ("rows", "mixed")])
+def test_sort_after_drift(og, torch_cuda, name, precision):
+    """The sort on the order a run leaves: sorted, then twelve steps without
+    a sort, so that most particles are still near their block's cells and
+    some have left for other rows (c2), and on the longest rows a grid may
+    have (4 x 1024, hot electrons), where a block's cells and window span
+    rows and drift across rows leaves the window.  Every particle is kept
+    unchanged and the slots come out in cell order."""
+    import paper_2212_08836_amd as P
+    _flush(f"sort after drift, {name}, {precision}")
+    if name == "c2":
+        w = E.workload("c2")
+    else:
+        w = E.Workload("rows", 4, 1024, 0.004, 0.128, ppc=4, Te_eV=50.0, tol=1e-9)
+    ctx = P.context_from_workload(w, precision=precision)
+    P.load_workload_species(ctx, E.make_particles(w), extra_cap=0.3)
+    ctx.sort()
+    for k in range(2):
+        assert _order_ok(ctx.read_particles(k), w.nr, w.nz)
+    for _ in range(12):
+        ctx.step(tol=w.tol, sort_every=0)
+    before = [ctx.read_particles(k) for k in range(2)]
+    assert not all(_order_ok(d, w.nr, w.nz) for d in before)
+    ctx.sort()
+    for k in range(2):
+        d = ctx.read_particles(k)
+        assert _order_ok(d, w.nr, w.nz), k
+        assert _cmp_species(d, before[k], f"sort sp {k}") == 0.0
 
 
 def test_c2_full_size_sampled(og, torch_cuda):
