@@ -45,9 +45,10 @@ def _rel(a, b):
     return np.abs(a - b).max() / s if s > 0 else np.abs(a).max()
 
 
+# 1024 x 512: the c5 grid with its port leg
 @pytest.mark.parametrize("shape", [(24, 8, 20, 2.0), (37, 29, 1, 2.0), (70, 130, 69, 0.0),
                                    (256, 128, 190, 2.0), (300, 16, 150, 2.0),
-                                   (1100, 12, 300, 0.0)])
+                                   (1100, 12, 300, 0.0), (1024, 512, 754, 2.0)])
 def test_port_field_solve_parity(og, torch_cuda, shape):
     import paper_2212_08836_amd as P
     from test_gpu_parity import _cn_condition
@@ -82,7 +83,7 @@ def test_port_field_solve_parity(og, torch_cuda, shape):
     assert np.array_equal(ctx.get_port_field(), hb)  # the solve leaves the state alone
 
 
-@pytest.mark.parametrize("shape", [(24, 8, 20), (300, 16, 150)])
+@pytest.mark.parametrize("shape", [(24, 8, 20), (300, 16, 150), (1024, 512, 754)])
 def test_port_electrostatic_solve_parity(og, torch_cuda, shape):
     import paper_2212_08836_amd as P
     nr, nz, ip = shape
