@@ -80,20 +80,49 @@ inline int col_blocks(int nz) { return (nz + kCC - 1) / kCC; }
 constexpr int kUnroll = 8;
 __host__ __device__ __forceinline__ int chunk_parts(int nc) { return nc >= kFB ? 1 : kFB / nc; }
 
-template <int R>
-__device__ __forceinline__ void dense_chunk(const double* __restrict__ M, int ldm,
-                                            const double* __restrict__ in, int ns, int c0, int nc,
-                                            double* __restrict__ psum) {
+// The thread's task of a chunk (at most one: nc * P <= kFB) with the first
+// kUnroll entries of its column of M, loaded by dense_pre so that a kernel
+// can issue them before it fills `in`.
+struct DenseTask {
+  bool on;
+  int p, c, s0, s1;
+  double q0[kUnroll];
+};
+
+__device__ __forceinline__ void dense_pre(const double* __restrict__ M, int ldm, int ns, int c0,
+                                          int nc, DenseTask& d) {
   const int P = chunk_parts(nc);
-  for (int t = threadIdx.x; t < nc * P; t += blockDim.x) {
-    const int p = t / nc, c = t - p * nc;
-    const int s0 = p * ns / P, s1 = (p + 1) * ns / P;
+  const int t = threadIdx.x;
+  d.on = t < nc * P;
+  d.p = d.on ? t / nc : 0;
+  d.c = t - d.p * nc;
+  d.s0 = d.p * ns / P;
+  d.s1 = d.on ? (d.p + 1) * ns / P : d.s0;
+  if (d.s0 + kUnroll <= d.s1) {
+    const double* q = M + c0 + d.c;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) d.q0[u] = q[(int64_t)(d.s0 + u) * ldm];
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void dense_run(const double* __restrict__ M, int ldm,
+                                          const double* __restrict__ in, int ns, int c0, int nc,
+                                          double* __restrict__ psum, const DenseTask& d) {
+  if (d.on) {
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    const double* q = M + c0 + c;
-    int j = s0;
-    for (; j + kUnroll <= s1; j += kUnroll) {
+    const double* q = M + c0 + d.c;
+    int j = d.s0;
+    if (j + kUnroll <= d.s1) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = fma(in[r * ns + j + u], d.q0[u], acc[r]);
+      j += kUnroll;
+    }
+    for (; j + kUnroll <= d.s1; j += kUnroll) {
       double qv[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) qv[u] = q[(int64_t)(j + u) * ldm];
@@ -102,15 +131,24 @@ __device__ __forceinline__ void dense_chunk(const double* __restrict__ M, int ld
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = fma(in[r * ns + j + u], qv[u], acc[r]);
     }
-    for (; j < s1; ++j) {
+    for (; j < d.s1; ++j) {
       const double qv = q[(int64_t)j * ldm];
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[r] = fma(in[r * ns + j], qv, acc[r]);
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) psum[(p * R + r) * nc + c] = acc[r];
+    for (int r = 0; r < R; ++r) psum[(d.p * R + r) * nc + d.c] = acc[r];
   }
   __syncthreads();
+}
+
+template <int R>
+__device__ __forceinline__ void dense_chunk(const double* __restrict__ M, int ldm,
+                                            const double* __restrict__ in, int ns, int c0, int nc,
+                                            double* __restrict__ psum) {
+  DenseTask d;
+  dense_pre(M, ldm, ns, c0, nc, d);
+  dense_run<R>(M, ldm, in, ns, c0, nc, psum, d);
 }
 
 __device__ __forceinline__ double chunk_total(const double* __restrict__ psum, int nc, int r, int c,
@@ -148,6 +186,8 @@ __global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restric
   const int rows = min(kRB, nr - i0);
   const int k0 = blockIdx.y * kCC;
   const int nk = min(kCC, nz - k0);
+  DenseTask dt;  // the transform's first loads, in flight while the rows are formed
+  dense_pre(Qt, nz, nz, k0, nk, dt);
   const double hdt = 0.5 * m.dt;
   for (int e = threadIdx.x; e < rows * nz; e += blockDim.x) {
     const int r = e / nz, j = e - r * nz, i = i0 + r;
@@ -185,7 +225,7 @@ __global__ void __launch_bounds__(kFB) k_rhs_dct(MapP m, const double* __restric
   __syncthreads();
   // hat[k][i] = sum_j Qt[j][k] rhs[i][j] for the block's modes k0 .. k0+nk-1
   double* psum = sh + kRB * nz;
-  dense_chunk<kRB>(Qt, nz, sh, nz, k0, nk, psum);
+  dense_run<kRB>(Qt, nz, sh, nz, k0, nk, psum, dt);
   for (int e = threadIdx.x; e < nk * kRB; e += blockDim.x) {
     const int kl = e / kRB, r = e - kl * kRB;
     if (r < rows) hat[(int64_t)(k0 + kl) * nr + i0 + r] = chunk_total(psum, nk, r, kl, kRB);
@@ -399,6 +439,8 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
                                                       PortDev P) {
   if (a.stop && *a.stop) return;
   constexpr int R1 = kRB + 1;  // rows i0 - 1 .. i0 + kRB - 1
+  // one r-edge and one z-edge per thread at most
+  static_assert(kRB * (kCC + 1) <= kFB, "edges per block");
   extern __shared__ double sh[];
   const int nr = m.nr, nz = m.nz;
   const int i0 = blockIdx.x * kRB;
@@ -409,6 +451,30 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
   const int nj = min(kCC, nz - j0);
   const int jlo = j0 > 0 ? j0 - 1 : 0;
   const int nx = j0 + nj - jlo;
+  // this thread's edges: r-edges j0 .. j0+nj-1 of the rows (and the
+  // top-wall edge nz in the last chunk), z-edges j0 .. j0+nj-1 of the rows;
+  // their inputs are loaded first, so that the loads are in flight during
+  // the transform
+  const int ne = nj + (j0 + nj == nz ? 1 : 0);
+  const int t = threadIdx.x;
+  const bool has_r = t < rows * ne, has_z = t < rows * nj;
+  const int rr = has_r ? t / ne : 0, jr = j0 + (t - rr * ne), ir = i0 + rr;
+  const int rz = has_z ? t / nj : 0, jz = j0 + (t - rz * nj), iz = i0 + rz;
+  const int64_t gr = (int64_t)ir * (nz + 1) + jr, gz = (int64_t)iz * nz + jz;
+  double r_u0 = 0.0, r_I = 0.0, r_old = 0.0, z_u0 = 0.0, z_I = 0.0, z_old = 0.0, z_h0 = 0.0;
+  if (has_r) {
+    r_u0 = a.ur0[gr];
+    r_I = a.Ir[gr];
+    if (a.part) r_old = a.ur_old[gr];
+  }
+  if (has_z) {
+    z_u0 = a.uz0[gz];
+    z_I = a.Iz[gz];
+    z_h0 = a.h0[gz];
+    if (a.part) z_old = a.uz_old[gz];
+  }
+  DenseTask dt;
+  dense_pre(Q, nz, nz, jlo, nx, dt);
   double* hs = sh;                 // hat of the R1 rows, [r][k]
   double* xs = sh + R1 * nz;       // x of the R1 rows, [r][j - jlo]; row r is i0 - 1 + r
   double* psum = xs + R1 * (kCC + 1);
@@ -418,7 +484,7 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
     hs[r * nz + k] = (i >= 0 && i < nr) ? hat[(int64_t)k * nr + i] : 0.0;
   }
   __syncthreads();
-  dense_chunk<R1>(Q, nz, hs, nz, jlo, nx, psum);
+  dense_run<R1>(Q, nz, hs, nz, jlo, nx, psum, dt);
   for (int e = threadIdx.x; e < R1 * nx; e += blockDim.x) {
     const int r = e / nx, c = e - r * nx;
     xs[e] = chunk_total(psum, nx, r, c, R1);
@@ -429,22 +495,20 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
   const double vnext = a.gapv ? a.gapv[0] : a.vnext;
   const double dphi = port_dphi(P);
   double s0 = 0.0, s1 = 0.0;
-  // r-edges j0 .. j0+nj-1 of the rows, and the top-wall edge nz in the last chunk
-  const int ne = nj + (j0 + nj == nz ? 1 : 0);
-  for (int e = threadIdx.x; e < rows * ne; e += blockDim.x) {
-    const int r = e / ne, j = j0 + (e - r * ne), i = i0 + r;
-    const double* xr = xs + (r + 1) * nx - jlo;  // xr[j] = x[i][j]
-    const int64_t g = (int64_t)i * (nz + 1) + j;
+  if (has_r) {
+    const int i = ir, j = jr;
+    const int64_t g = gr;
+    const double* xr = xs + (rr + 1) * nx - jlo;  // xr[j] = x[i][j]
     double v;
     if (j == 0 && P.ip > 0 && i >= P.ip) {
       // port edge: its change from h^{n+1/2} of the wall cell
       const double M = two_pi * rh[i];
       const double du = P.pc[kPortG * nr + i] *
-                        (-M * xr[0] + M * P.hb[i] + P.pc[kPortA * nr + i] * dphi - a.Ir[g]);
-      v = a.ur0[g] + du;
+                        (-M * xr[0] + M * P.hb[i] + P.pc[kPortA * nr + i] * dphi - r_I);
+      v = r_u0 + du;
       if (a.part) {
         const double w = 0.5 * wr[i];
-        const double d = v - a.ur_old[g];
+        const double d = v - r_old;
         s0 += w * d * d;
         s1 += w * v * v;
       }
@@ -455,47 +519,47 @@ __global__ void __launch_bounds__(kFB) k_idct_recover(SolveArgs a, MapP m,
     } else {
       const double w = wr[i];
       const double K = -two_pi * rh[i] * (xr[j] - xr[j - 1]);
-      const double uh = a.ur0[g] + (K - a.Ir[g]) * (hdt / w);
-      v = 2.0 * uh - a.ur0[g];
+      const double uh = r_u0 + (K - r_I) * (hdt / w);
+      v = 2.0 * uh - r_u0;
       if (a.part) {
-        const double d = v - a.ur_old[g];
+        const double d = v - r_old;
         s0 += w * d * d;
         s1 += w * v * v;
       }
     }
     a.ur1[g] = v;
     if (a.ur_h) {
-      const double hv = 0.5 * (a.ur0[g] + v);
+      const double hv = 0.5 * (r_u0 + v);
       a.ur_h[g] = hv;
       if (a.ur_hf) a.ur_hf[g] = float(hv);
     }
     if (a.Ir_clr) a.Ir_clr[g] = 0.0;
   }
   // z-edges of the rows (and the PEC row nr, owned by the blocks of row nr - 1)
-  for (int e = threadIdx.x; e < rows * nj; e += blockDim.x) {
-    const int r = e / nj, j = j0 + (e - r * nj), i = i0 + r;
-    const double* xr = xs + (r + 1) * nx - jlo;
-    const double* xm = xs + r * nx - jlo;
+  if (has_z) {
+    const int i = iz, j = jz;
+    const int64_t g = gz;
+    const double* xr = xs + (rz + 1) * nx - jlo;
+    const double* xm = xs + rz * nx - jlo;
     const double w = wz[i];
     const double ri = two_pi * rh[i];
     const double rm = (i > 0) ? two_pi * rh[i - 1] : 0.0;
-    const int64_t g = (int64_t)i * nz + j;
     const double K = ri * xr[j] - rm * xm[j];
-    const double uh = a.uz0[g] + (K - a.Iz[g]) * (hdt / w);
-    const double v = 2.0 * uh - a.uz0[g];
+    const double uh = z_u0 + (K - z_I) * (hdt / w);
+    const double v = 2.0 * uh - z_u0;
     if (a.part) {
-      const double d = v - a.uz_old[g];
+      const double d = v - z_old;
       s0 += w * d * d;
       s1 += w * v * v;
     }
     a.uz1[g] = v;
     if (a.uz_h) {
-      const double hv = 0.5 * (a.uz0[g] + v);
+      const double hv = 0.5 * (z_u0 + v);
       a.uz_h[g] = hv;
       if (a.uz_hf) a.uz_hf[g] = float(hv);
     }
     if (a.Iz_clr) a.Iz_clr[g] = 0.0;
-    a.h1[g] = 2.0 * xr[j] - a.h0[g];
+    a.h1[g] = 2.0 * xr[j] - z_h0;
     if (i == nr - 1) {
       const int64_t ew = (int64_t)nr * nz + j;
       a.uz1[ew] = 0.0;
