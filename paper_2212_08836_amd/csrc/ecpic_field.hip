@@ -240,23 +240,41 @@ __device__ __forceinline__ Aff compose(Aff later, Aff earlier) {
   return Aff{later.A * earlier.A, fma(later.A, earlier.B, later.B)};
 }
 
-// exclusive scan of per-thread affine maps in thread order (reverse = false)
-// or in reverse thread order; returns the composition of all maps before me
-__device__ Aff block_exscan(Aff v, bool reverse, Aff* sA) {
-  const int n = blockDim.x;
-  const int t = reverse ? (n - 1 - (int)threadIdx.x) : (int)threadIdx.x;
-  sA[t] = v;
-  __syncthreads();
-  for (int off = 1; off < n; off <<= 1) {
-    Aff mine = sA[t];
-    Aff other = (t >= off) ? sA[t - off] : Aff{1.0, 0.0};
-    __syncthreads();
-    if (t >= off) sA[t] = compose(mine, other);
-    __syncthreads();
+__device__ __forceinline__ Aff shfl_aff(Aff v, int src) {
+  return Aff{__shfl(v.A, src, 64), __shfl(v.B, src, 64)};
+}
+
+// Exclusive scan of per-thread affine maps in thread order (reverse = false)
+// or in reverse thread order; returns the composition of all maps before
+// me.  Within a wavefront by shuffles, then across the block's wavefronts
+// through LDS (one barrier); sW holds one map per wavefront.  The
+// association differs from a sequential composition by rounding only.
+__device__ Aff block_exscan(Aff v, bool reverse, Aff* sW) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const Aff id{1.0, 0.0};
+  // inclusive scan in the wavefront: lanes below (forward) or above (reverse)
+  // come first
+  Aff inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int src = reverse ? lane + off : lane - off;
+    const Aff o = shfl_aff(inc, src & 63);
+    if (reverse ? (lane + off < 64) : (lane >= off)) inc = compose(inc, o);
   }
-  const Aff r = (t > 0) ? sA[t - 1] : Aff{1.0, 0.0};
+  const int prev = reverse ? lane + 1 : lane - 1;
+  Aff ex = shfl_aff(inc, prev & 63);
+  if (reverse ? lane == 63 : lane == 0) ex = id;
+  if (lane == (reverse ? 0 : 63)) sW[w] = inc;
   __syncthreads();
-  return r;
+  // the wavefronts before this one, the farthest first
+  Aff acc = id;
+  if (!reverse) {
+    for (int u = 0; u < w; ++u) acc = compose(sW[u], acc);
+  } else {
+    for (int u = nw - 1; u > w; --u) acc = compose(sW[u], acc);
+  }
+  __syncthreads();  // sW is reused by the next scan
+  return compose(ex, acc);
 }
 
 constexpr int kMaxE = 8;  // rows per thread: nr <= kFB * kMaxE
@@ -274,7 +292,7 @@ __global__ void __launch_bounds__(kFB) k_tri_scan(int nr, const double* __restri
                                                   const double* __restrict__ q0,
                                                   const double* __restrict__ zq) {
   if (stop && *stop) return;
-  __shared__ Aff sA[kFB];
+  __shared__ Aff sA[kFB / 64];
   const int k = blockIdx.x;
   double* x = hat + (int64_t)k * nr;
   const double* L = lo + (int64_t)k * nr;
