@@ -354,13 +354,15 @@ def test_step_parity_edge_cases(og, torch_cuda):
 
 
 def _step_parity(og, P, w, parts, nsteps, mcc=None, sort_every=0, mobile=(True, True),
-                 running_scale=False, model="em", cap=0.0):
+                 running_scale=False, model="em", cap=0.0, waves=0):
     """Steps on both sides with the oracle's iteration counts.  Fields are
     compared against their largest value in this step, or with running_scale
     in any step so far (for runs whose drive is switched off: the fields then
     fall to the plasma's response and keep the absolute rounding of the
     driven steps)."""
     g, sp, ctx = _make_pair(w, og, P, parts, mobile=mobile, model=model, cap=cap)
+    if waves:
+        ctx.set_option(P.ECPIC_OPT_QUEUE_WAVES, waves)
     st = og.State(g)
     if mcc:
         ctx.set_mcc(mcc)
@@ -414,11 +416,14 @@ def test_step_parity_c1(og, torch_cuda):
     _step_parity(og, P, w, E.make_particles(w), w.steps)
 
 
-def test_step_parity_driven_collisional(og, torch_cuda):
+@pytest.mark.parametrize("waves", [0, 3])
+def test_step_parity_driven_collisional(og, torch_cuda, waves):
     # the c2 physics (drive, J0 sin profile, MCC) on a reduced grid; high
-    # pressure so that every process occurs, with a sort every 3 steps
+    # pressure so that every process occurs, with a sort every 3 steps; both
+    # builds of the plain slow pass (two wavefronts per SIMD, and the three
+    # the large workloads take)
     import paper_2212_08836_amd as P
-    _flush("step parity driven + MCC")
+    _flush(f"step parity driven + MCC, slow-pass build {waves}")
     w = E.Workload("c2s", 48, 24, 0.03, 0.012, n0=1e16, profile="j0sin", ppc=12,
                    drive_amp=(200.0,), drive_freq=(100e6,), pressure_pa=60.0, seed=12,
                    dt=1e-11, tol=1e-10)
@@ -427,10 +432,11 @@ def test_step_parity_driven_collisional(og, torch_cuda):
     parts[0]["vt"] *= 3.0
     parts[0]["vz"] *= 3.0
     mcc = w.mcc_params()
-    _step_parity(og, P, w, parts, 8, mcc=mcc, sort_every=3)
+    _step_parity(og, P, w, parts, 8, mcc=mcc, sort_every=3, waves=waves)
 
 
-def test_step_parity_immobile_ions_collisional(og, torch_cuda):
+@pytest.mark.parametrize("waves", [0, 3])
+def test_step_parity_immobile_ions_collisional(og, torch_cuda, waves):
     # one mobile species: the passes run one slot, the commit is never fused
     # (an immobile species' buffer would not flip), so every step ends with
     # the separate commit pass and its collision list
@@ -442,7 +448,8 @@ def test_step_parity_immobile_ions_collisional(og, torch_cuda):
     parts = E.make_particles(w)
     for k in ("vr", "vt", "vz"):
         parts[0][k] = parts[0][k] * 3.0
-    _step_parity(og, P, w, parts, 4, mcc=w.mcc_params(), sort_every=2, mobile=(True, False))
+    _step_parity(og, P, w, parts, 4, mcc=w.mcc_params(), sort_every=2, mobile=(True, False),
+                 waves=waves)
 
 
 def test_collide_parity(og, torch_cuda):
