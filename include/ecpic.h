@@ -345,7 +345,8 @@ ecpic_status ecpic_field_solve(ecpic_ctx* ctx, const double* ur0, const double* 
  * the library (2^20 doubles, 8 MiB, on each GPU it runs on, held until the
  * process ends) instead of the context's region; the call allocates nothing
  * and needs nothing cleared (the solve writes every element it reads).
- * Limit: nr * nz <= 2^20 cells (EINVAL beyond).  The context's device
+ * Limit: nr * nz <= 2^20 cells (EINVAL beyond), which every grid
+ * ecpic_create accepts meets.  The context's device
  * memory must already be in place (after ecpic_bind_workspace or any
  * earlier call that touches the device): EINVAL otherwise.  Every call on
  * one GPU shares the array: calls that overlap on one GPU (different
