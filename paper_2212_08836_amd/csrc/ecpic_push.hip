@@ -1352,12 +1352,15 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
   // wavefront's first kStageW slow particles, kept when they are queued
   // (later ones are fetched again at the end)
   constexpr int kWaves = kBlock / 64, kPerWave = kPerBlock / kWaves, kStageW = 16;
-  // entries are offsets in the block (k - k_first < kPerBlock): 16 bits keep
-  // the block's LDS small enough for one more block per CU at c5
+  static_assert(kPerWave == kPerThread * 64, "a list place per particle of the wavefront");
+  // entries are offsets in the block (k - k_first < kPerBlock), 16 bits; a
+  // wavefront's region holds its slow entries from the front and its
+  // collision entries from the back (a particle is at most one of the two,
+  // and the region has a place per particle), which keeps the block's LDS
+  // small enough for six blocks per CU at c5
   static_assert(kPerBlock <= 65536, "16-bit list offsets");
-  __shared__ uint16_t slow_list[kPerBlock];
+  __shared__ uint16_t plist[kPerBlock];
   __shared__ Raw<T> slow_rec[kWaves * kStageW];
-  __shared__ uint16_t coll_list[COMMIT ? kPerBlock : 1];
   __shared__ int wslow[kWaves], wcoll[kWaves], gbase, cbase;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // the species slot indexes the arguments directly (a select between the
@@ -1474,7 +1477,7 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
     const uint64_t mask = __ballot(slow);
     if (slow) {
       const int qi = wn_slow + lanes_below(mask);
-      slow_list[wv * kPerWave + qi] = (uint16_t)(k - k_first);
+      plist[wv * kPerWave + qi] = (uint16_t)(k - k_first);
       if (qi < kStageW) slow_rec[wv * kStageW + qi] = raw_of(p, nz);
     }
     wn_slow = __builtin_amdgcn_readfirstlane(wn_slow + (int)__popcll(mask));
@@ -1486,7 +1489,8 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
       // into the other buffer: dead slots stay dead there
       if (k < s.n && !alive && !same_buffer(A.out, A.s)) kill_slot<T>(A.out, k);
       const uint64_t cm = __ballot(coll);
-      if (coll) coll_list[wv * kPerWave + wn_coll + lanes_below(cm)] = (uint16_t)(k - k_first);
+      if (coll)
+        plist[wv * kPerWave + kPerWave - 1 - (wn_coll + lanes_below(cm))] = (uint16_t)(k - k_first);
       wn_coll = __builtin_amdgcn_readfirstlane(wn_coll + (int)__popcll(cm));
     }
     cur = nxt;
@@ -1532,7 +1536,7 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
 #pragma unroll
       for (int u = 1; u < kWaves; ++u) w += q >= spre[u] ? 1 : 0;
       const int o = q - spre[w];
-      const int32_t kq = (int32_t)(k_first + slow_list[w * kPerWave + o]);
+      const int32_t kq = (int32_t)(k_first + plist[w * kPerWave + o]);
       const int64_t pos = seg * qseg + gbase + q;
       queue[pos] = kq;
       Raw<T> r;
@@ -1552,7 +1556,8 @@ __global__ void __launch_bounds__(kBlock) k_push_fast(PassArgs P) {
       int w = 0;
 #pragma unroll
       for (int u = 1; u < kWaves; ++u) w += q >= cpre[u] ? 1 : 0;
-      cqueue[seg * qseg + cbase + q] = (int32_t)(k_first + coll_list[w * kPerWave + q - cpre[w]]);
+      cqueue[seg * qseg + cbase + q] =
+          (int32_t)(k_first + plist[w * kPerWave + kPerWave - 1 - (q - cpre[w])]);
     }
   }
   tl_flush(t, A.tally + (blockIdx.x % kSpread), s.sid);
