@@ -199,6 +199,18 @@ def _face_capacitance(og, w):
     return sum(t["wz"][i] * uz[i, 0] for i in range(w.port_i + 1)) / g.drive(w.dt)
 
 
+def _step_or_fixed(P, ctx, tol, fixed=12):
+    """A step to the tolerance; where Picard cycles instead (ENOTCONV, the
+    step left uncommitted), the same step again with a fixed count of
+    iterations.  Returns the step's statistics and whether it was retried."""
+    try:
+        return ctx.step(tol=tol, max_iter=50), False
+    except P.EcpicError as e:
+        if e.status != P.ECPIC_ENOTCONV:
+            raise
+        return ctx.step(fixed_iter=fixed), True
+
+
 def test_em_port_reproduces_the_electrostatic_electrode_voltage(og, torch_cuda):
     """Sec. 3.3 with the paper's drive: a 3e15 m^-3 plasma driven at 50 MHz
     through the port and a blocking capacitor (100 x the face capacitance)
@@ -209,8 +221,10 @@ def test_em_port_reproduces_the_electrostatic_electrode_voltage(og, torch_cuda):
     differ by about 0.05 V (the order of the FP64 atomics).  Tolerance
     1e-8: in runs of thousands of steps a particle whose wall or face event
     flips between iterates can hold the Picard residual in a cycle (seen at
-    8e-11 .. 1.6e-6 on the GPU, whose runs differ in their last bits); the
-    electrode voltage does not depend on the last digits."""
+    8e-11 .. 1.6e-6 on the GPU, whose runs differ in their last bits); such
+    a step is taken again with a fixed count of 12 iterations (the library
+    leaves it uncommitted), and the electrode voltage does not depend on the
+    last digits."""
     import paper_2212_08836_amd as P
     f = 50e6
     w = E.Workload("p", 32, 32, 0.02, 0.02, n0=3e15, ppc=32, dt=5e-11, drive_amp=(100.0,),
@@ -223,12 +237,17 @@ def test_em_port_reproduces_the_electrostatic_electrode_voltage(og, torch_cuda):
     for model, cf in (("es", 1.0), ("em", 1.0), ("em", 10.0)):
         ctx = P.context_from_workload(w, model=model, blocking_cap=cap, mu=E.MU0 / cf ** 2)
         P.load_workload_species(ctx, E.make_particles(w), extra_cap=0.5)
-        phi = [ctx.step(tol=w.tol, max_iter=50)["electrode_v"] for _ in range(3 * per)]
+        phi, retried = [], 0
+        for _ in range(3 * per):
+            d, again = _step_or_fixed(P, ctx, w.tol)
+            phi.append(d["electrode_v"])
+            retried += again
         ctx.close()
+        assert retried <= per // 10, retried  # cycles are rare events
         (s, c, bias), *_ = np.linalg.lstsq(A, np.array(phi[2 * per:]), rcond=None)
         out[(model, cf)] = (bias, math.hypot(s, c), math.atan2(c, s))
         _flush(f"  {model} c* = {cf:g} c: self-bias {bias:.2f} V, amplitude {math.hypot(s, c):.2f} V, "
-               f"phase {math.atan2(c, s):.4f}")
+               f"phase {math.atan2(c, s):.4f}; steps retried with a fixed count {retried}")
     b0, a0, p0 = out[("es", 1.0)]
     assert b0 < -10.0  # the smaller powered electrode charges negative
     for cf, db, da, dp in ((1.0, 0.05, 0.005, 0.01), (10.0, 0.01, 0.002, 0.005)):
