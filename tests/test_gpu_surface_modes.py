@@ -86,15 +86,24 @@ def _gpu_ring(torch, P, w, c_factor, model="em"):
     first = int(math.ceil(w.drive_t_end / w.dt))
     rec = torch.zeros((w.steps, 2, nr + 1), dtype=f64, device=dev)
     uz2 = uz.view(nr + 1, nz)
-    iters = 0
+    iters = retried = 0
     for k in range(w.steps):
-        d = ctx.step(tol=w.tol, max_iter=50)
+        try:
+            d = ctx.step(tol=w.tol, max_iter=50)
+        except P.EcpicError as e:
+            # a Picard cycle held up by a flipping particle event (the step
+            # is left uncommitted): the same step with a fixed count
+            if e.status != P.ECPIC_ENOTCONV:
+                raise
+            retried += 1
+            d = ctx.step(fixed_iter=12)
         iters += d["iters"]
         rec[k, 0] = uz2[:, jb]
         rec[k, 1] = uz2[:, nz - 1 - jb]
         if k % 5000 == 4999:
             _flush(f"  c* = {c_factor:g} c: step {k + 1}, mean iterations {iters / (k + 1):.2f}")
     torch.cuda.synchronize()
+    assert retried <= w.steps // 1000, retried
     out = rec.cpu().numpy()
     ctx.bind_fields(None, None, None, None, None, None)
     return out[first:, 0], out[first:, 1]
