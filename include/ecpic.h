@@ -394,7 +394,11 @@ ecpic_status ecpic_step(ecpic_ctx* ctx, const ecpic_step_opts* opts, ecpic_step_
 ecpic_status ecpic_run(ecpic_ctx* ctx, const ecpic_step_opts* opts, int32_t n_steps, int32_t* done,
                        ecpic_step_stats* last);
 
-/* Counting sort of every species by cell, dropping absorbed particles. */
+/* Counting sort of every species by cell (the order the fast pass's
+ * per-block current tiles rely on), dropping absorbed particles.  Slots come
+ * out in nondecreasing cell order; the order of the particles within a cell
+ * is not specified (it depends on the order of device atomics).  Device
+ * work on the context's stream; synchronises to read the new counts. */
 ecpic_status ecpic_sort(ecpic_ctx* ctx);
 
 /* Node charge of all species with logical bilinear weights into q (device,
