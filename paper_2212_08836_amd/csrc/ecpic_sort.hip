@@ -356,62 +356,99 @@ __global__ void k_kinetic(SpecDev s, int64_t n, int mixed, double* out) {
   }
 }
 
-// Bilinear node charge.  The lanes of a wavefront that share a cell (most
-// of them, between sorts) are summed by a butterfly first, and one lane adds
-// the four sums: one round per distinct cell in the wavefront, four atomics
-// each, instead of four per particle.
+// Bilinear node charge, block-local as the sort: a block's slots add their
+// four corner charges in LDS over the nodes of its cell window (node
+// i (nz + 1) + j of cell i nz + j, and the corners +1, +nz+1, +nz+2), then
+// one global atomic per touched node; slots outside the window add theirs
+// globally.  In a wavefront the lanes of the most common cells (up to
+// kNodeGroups cells of at least kNodeMinGroup lanes: between sorts a
+// wavefront holds a few cells) are summed by a butterfly first, so that
+// one lane adds their charge; LDS atomics from many lanes on one address
+// would serialise.
+__host__ __device__ inline int node_window(int nz) {
+  const int W = sort_window(nz);
+  return W + W / nz + nz + 4;
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-__global__ void k_node_charge(MapP m, SpecDev s, int64_t n, int mixed, double* q) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  int key = -1;  // cell of a live particle
-  int i = 0, j = 0;
-  double a = 0.0, b = 0.0;
-  if (k < n) {
-    if (!mixed) {
-      const double xi = s.xi[k];
-      if (xi >= 0.0) {
-        i = int(floor(xi));
-        j = int(floor(s.eta[k]));
-        i = i < 0 ? 0 : (i > m.nr - 1 ? m.nr - 1 : i);
-        j = j < 0 ? 0 : (j > m.nz - 1 ? m.nz - 1 : j);
-        a = xi - i;
+constexpr int kNodeGroups = 2, kNodeMinGroup = 16;
+
+__global__ void __launch_bounds__(kSortThreads)
+    k_node_charge(MapP m, SpecDev s, int64_t n, int mixed, double* q) {
+  extern __shared__ double qn[];
+  const int nz = m.nz, nz1 = nz + 1;
+  const int W = sort_window(nz), NW = node_window(nz);
+  for (int e = threadIdx.x; e < NW; e += kSortThreads) qn[e] = 0.0;
+  const int64_t k0 = (int64_t)blockIdx.x * kSortChunk;
+  int key[kSortPer];
+  const int lo = sort_keys(m, s, n, mixed != 0, k0, key);
+  const int n0 = lo + lo / nz;  // node of cell lo's lower corner
+  const double qw = s.q * s.w;
+  const uint64_t me = 1ull << (threadIdx.x & 63);
+#pragma unroll 1
+  for (int r = 0; r < kSortPer; ++r) {
+    const int c = key[r];
+    const int64_t k = k0 + (int64_t)r * kSortThreads + threadIdx.x;
+    double w00 = 0.0, w10 = 0.0, w01 = 0.0, w11 = 0.0;
+    int nd = 0;
+    if (c >= 0) {
+      const int i = c / nz, j = c - i * nz;
+      double a, b;
+      if (!mixed) {
+        a = s.xi[k] - i;
         b = s.eta[k] - j;
-        key = i * m.nz + j;
-      }
-    } else {
-      const int c = s.cell[k];
-      if (c >= 0) {
-        i = c / m.nz;
-        j = c - i * m.nz;
+      } else {
         a = s.fa[k];
         b = s.fb[k];
-        key = c;
       }
+      w00 = qw * (1 - a) * (1 - b);
+      w10 = qw * a * (1 - b);
+      w01 = qw * (1 - a) * b;
+      w11 = qw * a * b;
+      nd = c + i;  // i (nz + 1) + j
+    }
+    const bool in = c >= lo && c < lo + W;
+    if (c >= 0 && !in) {
+      unsafeAtomicAdd(&q[nd], w00);
+      unsafeAtomicAdd(&q[nd + nz1], w10);
+      unsafeAtomicAdd(&q[nd + 1], w01);
+      unsafeAtomicAdd(&q[nd + nz1 + 1], w11);
+    }
+    uint64_t pending = __ballot(in);
+    for (int g = 0; g < kNodeGroups && pending; ++g) {
+      const int lead = __ffsll((unsigned long long)pending) - 1;
+      const int lk = __shfl(c, lead, 64);
+      const bool mem = (pending & me) && c == lk;
+      const uint64_t mm = __ballot(mem);
+      if (__popcll(mm) < kNodeMinGroup) break;
+      const double s00 = wave_sum_d(mem ? w00 : 0.0), s10 = wave_sum_d(mem ? w10 : 0.0);
+      const double s01 = wave_sum_d(mem ? w01 : 0.0), s11 = wave_sum_d(mem ? w11 : 0.0);
+      if ((int)(threadIdx.x & 63) == lead) {
+        const int e = nd - n0;
+        atomicAdd(&qn[e], s00);
+        atomicAdd(&qn[e + nz1], s10);
+        atomicAdd(&qn[e + 1], s01);
+        atomicAdd(&qn[e + nz1 + 1], s11);
+      }
+      pending &= ~mm;
+    }
+    if (pending & me) {
+      const int e = nd - n0;
+      atomicAdd(&qn[e], w00);
+      atomicAdd(&qn[e + nz1], w10);
+      atomicAdd(&qn[e + 1], w01);
+      atomicAdd(&qn[e + nz1 + 1], w11);
     }
   }
-  const double qw = s.q * s.w;
-  const double w00 = qw * (1 - a) * (1 - b), w10 = qw * a * (1 - b);
-  const double w01 = qw * (1 - a) * b, w11 = qw * a * b;
-  const int lane = (int)(threadIdx.x & 63);
-  const int nz1 = m.nz + 1;
-  unsigned long long todo = __ballot(key >= 0);
-  while (todo) {
-    const int leader = __ffsll((long long)todo) - 1;
-    const int lk = __shfl(key, leader, 64);
-    const bool mine = key == lk;
-    const double s00 = wave_sum_d(mine ? w00 : 0.0), s10 = wave_sum_d(mine ? w10 : 0.0);
-    const double s01 = wave_sum_d(mine ? w01 : 0.0), s11 = wave_sum_d(mine ? w11 : 0.0);
-    if (lane == leader) {
-      unsafeAtomicAdd(&q[(size_t)i * nz1 + j], s00);
-      unsafeAtomicAdd(&q[(size_t)(i + 1) * nz1 + j], s10);
-      unsafeAtomicAdd(&q[(size_t)i * nz1 + j + 1], s01);
-      unsafeAtomicAdd(&q[(size_t)(i + 1) * nz1 + j + 1], s11);
-    }
-    todo &= ~__ballot(mine);
+  __syncthreads();
+  const int64_t nn = (int64_t)(m.nr + 1) * nz1;
+  for (int e = threadIdx.x; e < NW; e += kSortThreads) {
+    const double v = qn[e];
+    if (v != 0.0 && n0 + e < nn) unsafeAtomicAdd(&q[n0 + e], v);
   }
 }
 
@@ -497,8 +534,10 @@ hipError_t launch_node_charge(const Ctx& c, double* q, hipStream_t st) {
   const int mixed = c.prec == ECPIC_MIXED;
   for (const Species& sp : c.sp) {
     if (sp.n <= 0) continue;
-    hipLaunchKernelGGL(k_node_charge, dim3(nblk(sp.n)), dim3(kBlock), 0, st, c.m, sp.d[sp.cur],
-                       sp.n, mixed, q);
+    const int64_t nsb = (sp.n + kSortChunk - 1) / kSortChunk;
+    hipLaunchKernelGGL(k_node_charge, dim3(nsb), dim3(kSortThreads),
+                       (size_t)node_window(c.g.nz) * sizeof(double), st, c.m, sp.d[sp.cur], sp.n,
+                       mixed, q);
   }
   return hipGetLastError();
 }

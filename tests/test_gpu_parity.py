@@ -526,6 +526,50 @@ def test_sort_after_drift(og, torch_cuda, name, precision):
         assert _cmp_species(d, before[k], f"sort sp {k}") == 0.0
 
 
+def _host_node_charge(ds, qs, ws, nr, nz):
+    """Bilinear node charge of read-back particles (the plain definition)."""
+    Q = np.zeros((nr + 1, nz + 1))
+    for d, q, w in zip(ds, qs, ws):
+        i = np.clip(np.floor(d["xi"]).astype(int), 0, nr - 1)
+        j = np.clip(np.floor(d["eta"]).astype(int), 0, nz - 1)
+        a, b = d["xi"] - i, d["eta"] - j
+        np.add.at(Q, (i, j), q * w * (1 - a) * (1 - b))
+        np.add.at(Q, (i + 1, j), q * w * a * (1 - b))
+        np.add.at(Q, (i, j + 1), q * w * (1 - a) * b)
+        np.add.at(Q, (i + 1, j + 1), q * w * a * b)
+    return Q
+
+
+@pytest.mark.parametrize("name,precision", [("c1", "fp64"), ("c1", "mixed"), ("rows", "fp64")])
+def test_node_charge_matches_bilinear_weights(og, torch_cuda, name, precision):
+    """The device's node charge (block-local sums in LDS over a block's cell
+    window, global adds for slots outside it) against the bilinear
+    definition on the host, on particles in load order (most slots outside
+    their block's window), after a sort, and after steps without one."""
+    import paper_2212_08836_amd as P
+    _flush(f"node charge, {name}, {precision}")
+    if name == "c1":
+        w = E.workload("c1")
+    else:
+        w = E.Workload("rows", 4, 1024, 0.004, 0.128, ppc=4, Te_eV=50.0, tol=1e-9)
+    parts = E.make_particles(w)
+    ctx = P.context_from_workload(w, precision=precision)
+    P.load_workload_species(ctx, parts, extra_cap=0.3)
+    qs = [d["q"] for d in parts]
+    ws = [d["w"] for d in parts]
+    scale = abs(qs[0] * ws[0]) * w.ppc
+    for stage in ("loaded", "sorted", "stepped"):
+        if stage == "sorted":
+            ctx.sort()
+        elif stage == "stepped":
+            for _ in range(6):
+                ctx.step(tol=w.tol, sort_every=0)
+        q, _, _, _ = ctx.node_charge()
+        want = _host_node_charge([ctx.read_particles(k) for k in range(2)], qs, ws, w.nr, w.nz)
+        err = np.abs(np.asarray(q).reshape(w.nr + 1, w.nz + 1) - want).max()
+        assert err <= 1e-12 * scale, (stage, err, scale)
+
+
 def test_c2_full_size_sampled(og, torch_cuda):
     # c2 at full size (256 x 128, 4.2M particles) in the configuration the
     # bench times: one committed pass in a strong half-step field; sampled
