@@ -688,6 +688,19 @@ __device__ void push_particle(const MapP& m, const T* __restrict__ ur, const T* 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC'11) and the null-collision step
 // ---------------------------------------------------------------------------
+// The full 128-bit product of a and the constant m from four 32 x 32 -> 64
+// products, each with a 64-bit addend (one multiply-add instruction each),
+// so that the low and high halves share their partial products.
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t m, uint64_t& hi, uint64_t& lo) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t m0 = (uint32_t)m, m1 = (uint32_t)(m >> 32);
+  const uint64_t t = (uint64_t)a0 * m0;
+  const uint64_t u = (uint64_t)a1 * m0 + (t >> 32);
+  const uint64_t v = (uint64_t)a0 * m1 + (uint32_t)u;
+  hi = (uint64_t)a1 * m1 + ((u >> 32) + (v >> 32));
+  lo = (v << 32) | (uint32_t)t;
+}
+
 __device__ __forceinline__ void philox(uint64_t c[4], uint64_t k0, uint64_t k1) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
 #pragma unroll
@@ -696,8 +709,9 @@ __device__ __forceinline__ void philox(uint64_t c[4], uint64_t k0, uint64_t k1) 
       k0 += 0x9E3779B97F4A7C15ull;
       k1 += 0xBB67AE8584CAA73Bull;
     }
-    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(c[0], M0, hi0, lo0);
+    mulhilo64(c[2], M1, hi1, lo1);
     const uint64_t y0 = hi1 ^ c[1] ^ k0, y2 = hi0 ^ c[3] ^ k1;
     c[0] = y0;
     c[1] = lo1;
