@@ -97,6 +97,10 @@ def committed_traffic(workload, precision):
 # steps between counting sorts, measured per workload (the sorted order
 # decays faster where the cells are small against a step's travel)
 SORT_EVERY = {"c5": 16}
+# the ions (0.026 eV) hardly move between sorts: the steps' sorts include
+# them at every ION_SORT_STRIDE-th one
+ION_SORT_STRIDE = {"c5": 4}
+SORT_STRIDES = (1, 1)
 
 
 def sort_period(steps, cap=32):
@@ -120,7 +124,7 @@ def new_context(E, P, w, parts, precision, model="em", krylov=0, **over):
     ctx = P.context_from_workload(w, precision=precision, model=model, **over)
     if krylov:
         ctx.set_option(P.ECPIC_OPT_JFNK_KRYLOV, krylov)
-    P.load_workload_species(ctx, parts, extra_cap=0.25, workspace=True)
+    P.load_workload_species(ctx, parts, extra_cap=0.25, workspace=True, sort_strides=SORT_STRIDES)
     ctx.sort()
     ctx.set_mcc(w.mcc_params())
     return ctx
@@ -383,6 +387,9 @@ def main():
     ap.add_argument("--sort-every", type=int, default=0,
                     help="steps between counting sorts (0: the workload's own cadence); "
                          "rounded down to a divisor of --steps")
+    ap.add_argument("--ion-sort-stride", type=int, default=0,
+                    help="the ions are sorted at every k-th of those sorts (0: the workload's "
+                         "own choice)")
     ap.add_argument("--legs", default="es,port,jfnk,mixed,nn",
                     help="comma-separated legs to run beside the headline (of es, port, jfnk, "
                          "mixed, nn)")
@@ -410,6 +417,9 @@ def main():
     w = E.workload(args.workload)
     device_gen = args.workload in ("c3", "c5")
     period = sort_period(args.steps, args.sort_every or SORT_EVERY.get(args.workload, 32))
+    global SORT_STRIDES
+    ion_stride = args.ion_sort_stride or ION_SORT_STRIDE.get(args.workload, 1)
+    SORT_STRIDES = (1, ion_stride)
     log(f"generating the {args.workload} particles ({'GPU' if device_gen else 'host'})")
     parts = particles(E, w, device_gen)
     n0 = sum(int(len(p["r"])) for p in parts)
@@ -460,7 +470,8 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "particles": n0,
                    "grid": [w.nr, w.nz], "dt": w.dt, "tol": w.tol,
                    "precision": args.precision, "sort_every": period,
-                   "sorts_in_window": args.steps // period, "parallelism": "single GPU",
+                   "sorts_in_window": args.steps // period, "ion_sort_stride": ion_stride,
+                   "parallelism": "single GPU",
                    "device_memory": "one torch tensor bound as the library's workspace"},
         "picard_iterations_per_step": iters,
         "particles_alive_end": diag["n_alive"][:2],

@@ -144,7 +144,13 @@ typedef struct {
   double weight;          /* physical particles per macro-particle           */
   int64_t capacity;       /* maximum macro-particles held                    */
   int32_t mobile;         /* 0: frozen (not pushed, no current)              */
-  int32_t reserved;
+  int32_t sort_stride;    /* the sorts a step makes (ecpic_step_opts
+                             sort_every) include this species at every
+                             sort_stride-th of them, counted from step 0
+                             (0 or 1: at every one): for a species that
+                             hardly moves between sorts (cold ions), whose
+                             order keeps.  ecpic_sort sorts every species.
+                             Negative: EINVAL.                             */
 } ecpic_species_desc;
 
 /* Null-collision Monte Carlo (Sec. 2.1) with synthetic argon cross-sections:

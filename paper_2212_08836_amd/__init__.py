@@ -46,7 +46,7 @@ class GridDesc(C.Structure):
 
 class SpeciesDesc(C.Structure):
     _fields_ = [("q", C.c_double), ("m", C.c_double), ("weight", C.c_double),
-                ("capacity", C.c_int64), ("mobile", C.c_int32), ("reserved", C.c_int32)]
+                ("capacity", C.c_int64), ("mobile", C.c_int32), ("sort_stride", C.c_int32)]
 
 
 class MccDesc(C.Structure):
@@ -286,8 +286,8 @@ class Context:
         return self.torch.zeros(self.nr * self.nz, dtype=self.torch.float64, device=self.device)
 
     # -- species --
-    def add_species(self, q, m, weight, capacity, mobile=True) -> int:
-        d = SpeciesDesc(q, m, weight, int(capacity), int(bool(mobile)), 0)
+    def add_species(self, q, m, weight, capacity, mobile=True, sort_stride=0) -> int:
+        d = SpeciesDesc(q, m, weight, int(capacity), int(bool(mobile)), int(sort_stride))
         sid = C.c_int32()
         self._check(self.L.ecpic_add_species(self.h, C.byref(d), C.byref(sid)), self.h)
         self.caps[sid.value] = int(capacity)
@@ -528,14 +528,17 @@ def context_from_workload(w, precision="fp64", device="cuda", **over) -> Context
 
 
 def load_workload_species(ctx: Context, parts, extra_cap: float = 0.0, mobile=(True, True),
-                          workspace: bool = False):
+                          workspace: bool = False, sort_strides=()):
     """Add the species of `parts` and load them; with workspace, the
-    context's device region is one torch tensor bound before the load."""
+    context's device region is one torch tensor bound before the load.
+    sort_strides: per species, at which of the steps' sorts it is sorted
+    (ecpic_species_desc.sort_stride; missing entries 0, every sort)."""
     sids = []
     for k, d in enumerate(parts):
         n = len(d["r"])
         cap = int(n * (1.0 + extra_cap)) + 256
-        sid = ctx.add_species(d["q"], d["m"], d["w"], cap, mobile[k] if k < len(mobile) else True)
+        sid = ctx.add_species(d["q"], d["m"], d["w"], cap, mobile[k] if k < len(mobile) else True,
+                              sort_strides[k] if k < len(sort_strides) else 0)
         sids.append(sid)
     if workspace:
         ctx.bind_workspace()

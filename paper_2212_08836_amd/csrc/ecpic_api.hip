@@ -912,7 +912,8 @@ ecpic_status ecpic_add_species(ecpic_ctx* x, const ecpic_species_desc* d, int32_
   if ((int)c.sp.size() >= kMaxSpecies) return fail(c, ECPIC_EINVAL, "at most 4 species");
   // the kernels address particle arrays by 32-bit byte offsets: at most
   // 2^29 slots of 8 bytes
-  if (d->capacity < 0 || d->capacity > ((int64_t)1 << 29) || !(d->m > 0) || !(d->weight > 0))
+  if (d->capacity < 0 || d->capacity > ((int64_t)1 << 29) || !(d->m > 0) || !(d->weight > 0) ||
+      d->sort_stride < 0)
     return fail(c, ECPIC_EINVAL, "bad species descriptor");
   if (c.materialised && c.ws)
     return fail(c, ECPIC_EINVAL, "add every species before binding the workspace");
@@ -1972,14 +1973,21 @@ static ecpic_status step_impl(Ctx& c, const ecpic_step_opts* o, ecpic_step_stats
     c.cons_valid = false;
   }
   if (o->sort_every > 0 && c.step % o->sort_every == 0) {
+    // the species whose stride this sort reaches
+    const int64_t nth = c.step / o->sort_every;
+    bool due[kMaxSpecies] = {false, false, false, false};
     for (size_t s = 0; s < c.sp.size(); ++s) {
+      const int32_t k = c.sp[s].desc.sort_stride;
+      due[s] = k <= 1 || nth % k == 0;
+      if (!due[s]) continue;
       const int64_t n0 = c.sp[s].n;
       Timed tm(c, ECPIC_K_SORT, (2.0 * (state_bytes(c) + 8.0) + 16.0) * (double)n0, n0);
       HIPCHK(launch_sort_async(c, c.sp[s], c.sort_total_host + s, c.stream));
     }
     HIPCHK(hipStreamSynchronize(c.stream));
     collect(c);
-    for (size_t s = 0; s < c.sp.size(); ++s) finish_sort(c.sp[s], c.sort_total_host[s]);
+    for (size_t s = 0; s < c.sp.size(); ++s)
+      if (due[s]) finish_sort(c.sp[s], c.sort_total_host[s]);
   }
   if (st) {
     ecpic_status r2 = diag_into(c, S);

@@ -526,6 +526,30 @@ def test_sort_after_drift(og, torch_cuda, name, precision):
         assert _cmp_species(d, before[k], f"sort sp {k}") == 0.0
 
 
+def test_sort_stride_sorts_a_species_at_every_kth_sort(og, torch_cuda):
+    """ecpic_species_desc.sort_stride: with a sort every 2 steps and the ions
+    at every 3rd of those sorts, the electrons come out in cell order after
+    every sort, the ions only after steps 6, 12, ... (counted from step 0);
+    both keep every particle."""
+    import paper_2212_08836_amd as P
+    _flush("sort stride")
+    w = E.workload("c1")
+    ctx = P.context_from_workload(w)
+    P.load_workload_species(ctx, E.make_particles(w), extra_cap=0.3, sort_strides=(0, 3))
+    n0 = [len(ctx.read_particles(k)["uid"]) for k in range(2)]
+    assert not _order_ok(ctx.read_particles(1), w.nr, w.nz)  # load order
+    for step in range(1, 7):
+        ctx.step(tol=w.tol, sort_every=2)
+        d = [ctx.read_particles(k) for k in range(2)]
+        if step % 2 == 0:
+            assert _order_ok(d[0], w.nr, w.nz), step
+        assert _order_ok(d[1], w.nr, w.nz) == (step == 6), step
+    assert len(d[1]["uid"]) <= n0[1]
+    with pytest.raises(P.EcpicError) as e:
+        ctx.add_species(E.QE, E.M_AR, 1.0, 100, True, -1)
+    assert e.value.status == P.ECPIC_EINVAL
+
+
 def _host_node_charge(ds, qs, ws, nr, nz):
     """Bilinear node charge of read-back particles (the plain definition)."""
     Q = np.zeros((nr + 1, nz + 1))
